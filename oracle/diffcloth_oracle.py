@@ -1,0 +1,612 @@
+"""FP64 CPU oracle of the DiffCloth hot path (Projective Dynamics with dry
+frictional contact, forward and adjoint).
+
+TEST INFRASTRUCTURE ONLY.  This module is the plain, slow, obviously correct
+reference that the GPU library is checked against.  Only the test suite, the
+smoke check and the CPU-baseline leg of the benchmark may import it; the
+product path never calls it.  It shares no code with the GPU library: it
+reads the seeded inputs of ``scenes`` and implements every step itself with
+NumPy / SciPy in float64.
+
+Layout: positions, velocities and gradients are (m, 3) arrays (node-major);
+3m-vectors, where needed for sparse algebra, interleave xyz per node.
+
+Readings of the paper taken here (the paper is silent or ambiguous on them):
+  * Contact iteration (Sec. 3.2, the per-node decoupled iteration of Ly et al.):
+    one global solve with the prefactored P per PD iteration, with the current
+    contact impulses on the right-hand side, followed by one per-node contact
+    update that uses the decoupled node response h/m_j (the same fixed point).
+  * Contact detection on the inertial predictor y, contact frame and gap taken
+    at x_n; Signorini applies to the gap-corrected normal velocity u_N + phi/h.
+  * Tie-breaks: take off iff a > 0, stick iff |u_T| <= mu(-a); obstacle is
+    argmin phi with ties to the lowest index; phi(y) = 0 counts as contact.
+  * Contact adjoint: differentiate the converged state through the per-node
+    closed-form contact map (blocks T_j); this is the block-diagonal, per-node
+    contact Jacobian of Sec. 4.2 and reduces to the DiffPD adjoint without contact.
+  * Springs: p = L0 q/|q| with the given stiffness as weight; quadratic bending:
+    one constraint per interior vertex with a cotangent-Laplacian stencil l,
+    p = rho0 l(x)/|l(x)|, rho0 = |l(X)|, p = 0 when rho0 = 0; attachments
+    p = target(t).
+  * Degenerate |q| < 1e-12 rho: use the rest direction and a zero projection Jacobian.
+  * Initial guess per step: v^0 = v_n + h g, contact impulses 0.
+  * Backward projections re-evaluated at x_{n+1} = x_n + h v_{n+1}.
+Every function cites the passage it follows.  Parity is pinned by the
+``-m "not gpu"`` tests in ``tests/test_oracle_pins.py``.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+FREE, TAKEOFF, STICK, SLIP = 0, 1, 2, 3
+PLANE, SPHERE = 0, 1
+DEGENERATE_REL = 1e-12
+
+
+# =========================================================================== constraints
+
+def triangle_edges(tris: np.ndarray) -> np.ndarray:
+    """Unique undirected triangle edges (a < b), sorted lexicographically."""
+    t = np.asarray(tris, dtype=np.int64)
+    e = np.concatenate([t[:, [0, 1]], t[:, [1, 2]], t[:, [2, 0]]])
+    e = np.sort(e, axis=1)
+    return np.unique(e, axis=0).astype(np.int64)
+
+
+def cotangent_bending_stencils(X: np.ndarray, tris: np.ndarray):
+    """Quadratic bending constraints (Bouaziz et al. material, Sec. 3.1): one
+    per interior vertex b, with A_b x = sum_k c_bk (x_k - x_b) and c_bk the
+    cotangent weight (cot alpha + cot beta) / 2 of edge (b, k).
+    Returns (centers, stencil matrix L (nb x m))."""
+    m = X.shape[0]
+    t = np.asarray(tris, dtype=np.int64)
+    W = {}
+    count = {}
+    for tri in t:
+        for r in range(3):
+            i, j, k = tri[r], tri[(r + 1) % 3], tri[(r + 2) % 3]
+            # angle at k, opposite edge (i, j)
+            u = X[i] - X[k]
+            v = X[j] - X[k]
+            cot = float(np.dot(u, v) / np.linalg.norm(np.cross(u, v)))
+            key = (min(i, j), max(i, j))
+            W[key] = W.get(key, 0.0) + 0.5 * cot
+            count[key] = count.get(key, 0) + 1
+    boundary = np.zeros(m, bool)
+    for (a, b), c in count.items():
+        if c == 1:
+            boundary[a] = True
+            boundary[b] = True
+    centers = [b for b in range(m) if not boundary[b]]
+    nbrs = {b: {} for b in centers}
+    for (a, b), w in W.items():
+        if a in nbrs:
+            nbrs[a][b] = w
+        if b in nbrs:
+            nbrs[b][a] = w
+    rows, cols, vals = [], [], []
+    for r, b in enumerate(centers):
+        tot = 0.0
+        for k, w in nbrs[b].items():
+            rows.append(r); cols.append(k); vals.append(w)
+            tot += w
+        rows.append(r); cols.append(b); vals.append(-tot)
+    L = sp.csr_matrix((vals, (rows, cols)), shape=(len(centers), m))
+    return np.array(centers, dtype=np.int64), L
+
+
+def rotation(axis, angle: float) -> np.ndarray:
+    a = np.asarray(axis, float)
+    a = a / np.linalg.norm(a)
+    K = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+    return np.eye(3) + math.sin(angle) * K + (1 - math.cos(angle)) * (K @ K)
+
+
+@dataclasses.dataclass
+class Contact:
+    """Per-step contact record (Sec. 3.2: contact set, local frames, modes)."""
+    nodes: np.ndarray       # (C,) node ids in the contact set
+    obstacle: np.ndarray    # (C,) obstacle index
+    normal: np.ndarray      # (C, 3) contact normal at x_n
+    gap: np.ndarray         # (C,) signed distance at x_n
+    mu: np.ndarray          # (C,)
+    ubar: np.ndarray        # (C, 3) free velocity of the last contact update
+    impulse: np.ndarray     # (C, 3) h J^T r, world frame
+    mode: np.ndarray        # (C,) TAKEOFF / STICK / SLIP
+
+
+@dataclasses.dataclass
+class StepRecord:
+    x0: np.ndarray          # x_n
+    v0: np.ndarray          # v_n
+    x1: np.ndarray          # x_{n+1}
+    v1: np.ndarray          # v_{n+1}
+    contact: Contact
+    iters: int
+
+
+class Model:
+    """Constraint set, masses and the prefactored global matrix (Sec. 3.1,
+    eqn pd_global): P = M + h^2 sum_i w_i A_i^T A_i, with A_i = a_i^T (x) I_3 for
+    springs and bending, and the node selector for attachments, so that
+    P = P_s (x) I_3 with the scalar m x m matrix P_s."""
+
+    def __init__(self, scene, edge_stiffness=None, bend_weight=None, region_scale=None,
+                 mu=None, h=None):
+        self.scene = scene
+        self.X = np.asarray(scene.X, float)
+        self.m = self.X.shape[0]
+        self.h = float(scene.h if h is None else h)
+        self.g = np.asarray(scene.gravity, float)
+        self.mass = np.asarray(scene.node_mass, float)
+        edges = np.asarray(scene.edges if scene.edges is not None else triangle_edges(scene.tris),
+                           np.int64)
+        self.edges = edges
+        E = edges.shape[0]
+        k = np.asarray(scene.edge_stiffness if edge_stiffness is None else edge_stiffness, float)
+        wb = float(scene.bend_weight if bend_weight is None else bend_weight)
+        rs = scene.region_scale if region_scale is None else region_scale
+        self.region_scale = None if rs is None else np.asarray(rs, float)
+        # springs: a_e = e_a - e_b
+        S = sp.csr_matrix((np.concatenate([np.ones(E), -np.ones(E)]),
+                           (np.concatenate([np.arange(E), np.arange(E)]),
+                            np.concatenate([edges[:, 0], edges[:, 1]]))), shape=(E, self.m))
+        centers, Lb = cotangent_bending_stencils(self.X, scene.tris)
+        self.bend_centers = centers
+        nb = centers.shape[0]
+        self.A = sp.vstack([S, Lb]).tocsr()                      # (nc, m)
+        self.n_spring, self.n_bend = E, nb
+        self.nc = E + nb
+        base_w = np.concatenate([k, np.full(nb, wb)])
+        self.base_w = base_w
+        if self.region_scale is not None:
+            reg = np.concatenate([np.asarray(scene.edge_region, np.int64),
+                                  np.asarray(scene.bend_region, np.int64)[centers]])
+            self.region = reg
+            self.w = base_w * self.region_scale[reg]
+        else:
+            self.region = None
+            self.w = base_w.copy()
+        q_rest = self.A @ self.X
+        self.rho = np.linalg.norm(q_rest, axis=1)
+        # flat bending: a rest Laplacian below 1e-10 of sum_k |c_bk||X_k - X_b| has no target
+        Lc = Lb.tocoo()
+        terms = np.abs(Lc.data) * np.linalg.norm(self.X[Lc.col] - self.X[centers[Lc.row]], axis=1)
+        mag = np.zeros(nb)
+        np.add.at(mag, Lc.row, terms)
+        flat = self.rho[E:] <= 1e-10 * mag
+        self.rho[E:][flat] = 0.0
+        rd = np.zeros_like(q_rest)
+        ok = self.rho > 0
+        rd[ok] = q_rest[ok] / self.rho[ok, None]
+        self.rest_dir = rd
+        self.attach = np.asarray(scene.attach, np.int64)
+        self.w_att = float(scene.attach_weight)
+        self.obstacles = list(scene.obstacles)
+        if mu is not None:
+            self.obstacles = [dataclasses.replace(o, mu=float(mu_o))
+                              for o, mu_o in zip(self.obstacles, np.atleast_1d(mu))]
+        h2 = self.h * self.h
+        Patt = sp.csr_matrix((np.full(len(self.attach), self.w_att),
+                              (self.attach, self.attach)), shape=(self.m, self.m))
+        self.K_s = (self.A.T @ sp.diags(self.w) @ self.A + Patt).tocsr()   # sum w A^T A (scalar)
+        self.P_s = (sp.diags(self.mass) + h2 * self.K_s).tocsc()
+        self.lu = spla.splu(self.P_s)                            # "prefactorized" P
+
+    # ----------------------------------------------------------------- helpers
+    def attach_targets(self, t: float) -> np.ndarray:
+        sc = self.scene
+        R = rotation(sc.attach_axis, sc.attach_omega * t)
+        c = np.asarray(sc.attach_center, float)
+        return (self.X[self.attach] - c) @ R.T + c
+
+    def solve_P(self, rhs: np.ndarray) -> np.ndarray:
+        """Global step: back-substitution with the prefactored P (eqn pd_global)."""
+        return self.lu.solve(rhs)
+
+    # ----------------------------------------------------------------- obstacles
+    def signed_distance(self, o, x: np.ndarray) -> np.ndarray:
+        if o.kind == PLANE:
+            return (x - np.asarray(o.point)) @ np.asarray(o.normal, float)
+        d = x - np.asarray(o.point, float)
+        return np.linalg.norm(d, axis=1) - o.radius
+
+    def normal_at(self, o, x: np.ndarray) -> np.ndarray:
+        if o.kind == PLANE:
+            return np.tile(np.asarray(o.normal, float), (x.shape[0], 1))
+        d = x - np.asarray(o.point, float)
+        return d / np.linalg.norm(d, axis=1)[:, None]
+
+
+# =========================================================================== forward
+
+def inertial_predictor(model: Model, x: np.ndarray, v: np.ndarray) -> np.ndarray:
+    """y = x_n + h v_n + h^2 M^{-1} f_ext with f_ext = M g (eqn implicit_energy)."""
+    return x + model.h * v + model.h ** 2 * model.g
+
+
+def detect_contacts(model: Model, x: np.ndarray, y: np.ndarray):
+    """Contact set on the predictor y; explicit frame and gap at x_n (Sec. 3.2:
+    J_n depends on the state entering the step; Sec. 4.2 Extensions: the normal
+    of a curved obstacle is taken where the contact occurs)."""
+    if not model.obstacles:
+        z = np.zeros(0, np.int64)
+        return z, z, np.zeros((0, 3)), np.zeros(0), np.zeros(0)
+    phis = np.stack([model.signed_distance(o, y) for o in model.obstacles], axis=1)
+    ostar = np.argmin(phis, axis=1)                 # ties -> lowest index
+    phimin = phis[np.arange(model.m), ostar]
+    nodes = np.nonzero(phimin <= 0.0)[0]
+    obst = ostar[nodes]
+    normal = np.zeros((nodes.size, 3))
+    gap = np.zeros(nodes.size)
+    mu = np.zeros(nodes.size)
+    for oi, o in enumerate(model.obstacles):
+        sel = obst == oi
+        if np.any(sel):
+            xs = x[nodes[sel]]
+            normal[sel] = model.normal_at(o, xs)
+            gap[sel] = model.signed_distance(o, xs)
+            mu[sel] = o.mu
+    return nodes, obst, normal, gap, mu
+
+
+def local_projection(model: Model, x: np.ndarray):
+    """Local step (eqn pd_project): p_i = argmin over M_i of |A_i x - p|.
+    Springs/bending: the sphere of radius rho_i; returns (p, q = A x)."""
+    q = model.A @ x
+    nq = np.linalg.norm(q, axis=1)
+    p = np.zeros_like(q)
+    act = model.rho > 0
+    deg = act & (nq < DEGENERATE_REL * np.maximum(model.rho, 1e-300))
+    ok = act & ~deg
+    p[ok] = model.rho[ok, None] * q[ok] / nq[ok, None]
+    p[deg] = model.rho[deg, None] * model.rest_dir[deg]
+    return p, q
+
+
+def constant_rhs(model: Model, x: np.ndarray, v: np.ndarray, t1: float) -> np.ndarray:
+    """b_hat minus the parts that change inside the step (eqn pd_velocity):
+    (b(p) - P x_n)/h = M v_n + h M g - (P - M) x_n / h + h sum_att w t_j(t_{n+1})
+    + h sum_i w_i A_i^T p_i, of which the last sum is added per iteration."""
+    h = model.h
+    r = model.mass[:, None] * v + h * model.mass[:, None] * model.g
+    r -= h * (model.K_s @ x)
+    if model.attach.size:
+        np.add.at(r, model.attach, h * model.w_att * model.attach_targets(t1))
+    return r
+
+
+def signorini_coulomb(ubar, n, phi, mu, h, mass):
+    """Per-node Signorini-Coulomb update (eqn contact_all) for nodes whose
+    velocity responds to their impulse f as v = ubar + f/m (decoupled nodes, the
+    mass-splitting of eqn ly_et_al_govrningEq).  With an isotropic node
+    response the law has a closed form; the normal uses the gap-corrected
+    velocity u_N + phi/h.  Vectorised over nodes: ubar, n (C, 3); phi, mu,
+    mass (C,).  Returns v, f (C, 3) and the mode (TAKEOFF/STICK/SLIP)."""
+    ubar = np.atleast_2d(np.asarray(ubar, float))
+    n = np.atleast_2d(np.asarray(n, float))
+    phi = np.atleast_1d(np.asarray(phi, float))
+    mu = np.atleast_1d(np.asarray(mu, float))
+    mass = np.atleast_1d(np.asarray(mass, float))
+    un = np.sum(n * ubar, axis=1)
+    a = un + phi / h
+    ut = ubar - un[:, None] * n
+    tau = np.linalg.norm(ut, axis=1)
+    takeoff = a > 0.0
+    stick = ~takeoff & (tau <= mu * (-a))
+    slip = ~takeoff & ~stick
+    v = ubar.copy()
+    vn = -(phi / h)[:, None] * n
+    v[stick] = vn[stick]
+    that = np.zeros_like(ut)
+    that[slip] = ut[slip] / tau[slip, None]
+    v[slip] = vn[slip] + ut[slip] + (mu * a)[slip, None] * that[slip]
+    f = mass[:, None] * (v - ubar)
+    f[takeoff] = 0.0
+    mode = np.where(takeoff, TAKEOFF, np.where(stick, STICK, SLIP)).astype(np.int8)
+    return v, f, mode
+
+
+def forward_step(model: Model, x: np.ndarray, v: np.ndarray, n: int, iters: Optional[int] = None,
+                 tol: Optional[float] = None, max_iters: int = 100000, energy_log=None):
+    """One implicit-Euler step with dry frictional contact (eqn
+    implicit_with_contact) solved by PD local/global iterations (Sec. 3.1) with
+    contact impulses on the right-hand side (eqn pd_velocity_with_contact) and a
+    per-node Signorini-Coulomb update after each global step."""
+    h = model.h
+    t1 = (n + 1) * h
+    y = inertial_predictor(model, x, v)
+    nodes, obst, normal, gap, mu = detect_contacts(model, x, y)
+    C = nodes.size
+    bhat0 = constant_rhs(model, x, v, t1)
+    vk = v + h * model.g                                      # v^0: x^0 = y
+    f = np.zeros((C, 3))
+    ubar = np.zeros((C, 3))
+    mode = np.full(C, TAKEOFF, np.int8)
+    K = model.scene.pd_iters if iters is None else iters
+    k = 0
+    while True:
+        xk = x + h * vk
+        p, _ = local_projection(model, xk)                    # local step
+        rhs = bhat0 + h * (model.A.T @ (model.w[:, None] * p))
+        if C:
+            np.add.at(rhs, nodes, f)                          # h J^T r
+        vnew = model.solve_P(rhs)                             # global step
+        if C:                                                 # contact update per node
+            ubar = vnew[nodes] - f / model.mass[nodes, None]
+            vc, f, mode = signorini_coulomb(ubar, normal, gap, mu, h, model.mass[nodes])
+            vnew[nodes] = vc
+        k += 1
+        dv = np.max(np.abs(vnew - vk)) if vk.size else 0.0
+        vk = vnew
+        if energy_log is not None:
+            energy_log.append(implicit_energy(model, x + h * vk, y, t1))
+        if tol is None:
+            if k >= K:
+                break
+        elif dv <= tol or k >= max_iters:
+            break
+    x1 = x + h * vk
+    return StepRecord(x.copy(), v.copy(), x1, vk.copy(),
+                      Contact(nodes, obst, normal, gap, mu, ubar, f, mode), k)
+
+
+def rollout(model: Model, x0=None, v0=None, steps: Optional[int] = None, iters=None, tol=None):
+    """Forward simulation over T steps; returns the list of step records."""
+    x = np.asarray(model.X if x0 is None else x0, float).copy()
+    v = np.asarray(model.scene.v0 if v0 is None else v0, float).copy()
+    T = model.scene.steps if steps is None else steps
+    recs = []
+    for n in range(T):
+        r = forward_step(model, x, v, n, iters=iters, tol=tol)
+        recs.append(r)
+        x, v = r.x1, r.v1
+    return recs
+
+
+def elastic_energy(model: Model, x: np.ndarray, t: float) -> float:
+    """W(x) = sum_i min_p w_i/2 |A_i x - p|^2 (eqn pd_energy)."""
+    p, q = local_projection(model, x)
+    W = 0.5 * float(np.sum(model.w * np.sum((q - p) ** 2, axis=1)))
+    if model.attach.size:
+        d = x[model.attach] - model.attach_targets(t)
+        W += 0.5 * model.w_att * float(np.sum(d * d))
+    return W
+
+
+def implicit_energy(model: Model, x: np.ndarray, y: np.ndarray, t: Optional[float] = None) -> float:
+    """g(x) = (1/2h^2)(x-y)^T M (x-y) + W(x) (eqn implicit_energy)."""
+    if t is None:
+        t = 0.0
+    d = x - y
+    return 0.5 / model.h ** 2 * float(np.sum(model.mass[:, None] * d * d)) + elastic_energy(model, x, t)
+
+
+# =========================================================================== backward
+
+def projection_jacobian_blocks(model: Model, x: np.ndarray):
+    """dp_i/d(A_i x) for the sphere projections: (rho/|q|)(I - qhat qhat^T), zero for
+    rho = 0 and for degenerate q (Sec. 4.1, the DiffPD Hessian term)."""
+    q = model.A @ x
+    nq = np.linalg.norm(q, axis=1)
+    act = model.rho > 0
+    ok = act & (nq >= DEGENERATE_REL * np.maximum(model.rho, 1e-300))
+    J = np.zeros((model.nc, 3, 3))
+    qh = np.zeros_like(q)
+    qh[ok] = q[ok] / nq[ok, None]
+    s = np.zeros(model.nc)
+    s[ok] = model.rho[ok] / nq[ok]
+    J[ok] = s[ok, None, None] * (np.eye(3)[None] - qh[ok, :, None] * qh[ok, None, :])
+    return J
+
+
+def _kron3(Ms: sp.spmatrix) -> sp.csr_matrix:
+    return sp.kron(Ms, sp.eye(3), format="csr")
+
+
+def _blockdiag3(blocks: np.ndarray) -> sp.csr_matrix:
+    nb = blocks.shape[0]
+    r = (3 * np.arange(nb)[:, None, None] + np.arange(3)[None, :, None]) * np.ones((1, 1, 3), int)
+    c = (3 * np.arange(nb)[:, None, None] + np.arange(3)[None, None, :]) * np.ones((1, 3, 1), int)
+    return sp.csr_matrix((blocks.ravel(), (r.ravel(), c.ravel())), shape=(3 * nb, 3 * nb))
+
+
+def delta_P(model: Model, x: np.ndarray) -> sp.csr_matrix:
+    """Delta P = h^2 sum_i w_i A_i^T dp_i*/dx at x (eqn adjoint_pd), 3m x 3m."""
+    J = projection_jacobian_blocks(model, x)
+    At = _kron3(model.A)                                      # (3nc, 3m)
+    D = _blockdiag3(model.h ** 2 * model.w[:, None, None] * J)
+    return (At.T @ D @ At).tocsr()
+
+
+def contact_jacobian_blocks(contact: Contact, h: float):
+    """T_j = d v_j / d ubar_j of the closed-form contact update: identity for
+    take-off, zero for stick, (1-s)Pi + s t t^T + mu t n^T for slip, with
+    Pi = I - n n^T, t the unit free tangential velocity and s = mu(-a)/|u_T|."""
+    C = contact.nodes.size
+    T = np.zeros((C, 3, 3))
+    T[contact.mode == TAKEOFF] = np.eye(3)
+    sl = contact.mode == SLIP
+    if np.any(sl):
+        n = contact.normal[sl]
+        ub = contact.ubar[sl]
+        un = np.sum(n * ub, axis=1)
+        ut = ub - un[:, None] * n
+        tau = np.linalg.norm(ut, axis=1)
+        t = ut / tau[:, None]
+        a = un + contact.gap[sl] / h
+        mu = contact.mu[sl]
+        s = mu * (-a) / tau
+        Pi = np.eye(3)[None] - n[:, :, None] * n[:, None, :]
+        T[sl] = ((1 - s)[:, None, None] * Pi + s[:, None, None] * t[:, :, None] * t[:, None, :]
+                 + mu[:, None, None] * t[:, :, None] * n[:, None, :])
+    return T
+
+
+def backward_step(model: Model, rec: StepRecord, gx: np.ndarray, gv: np.ndarray,
+                  n: int, direct: bool = True, iter_tol: float = 1e-12, iter_max: int = 100000):
+    """Adjoint of one step (Sec. 4.2, eqns adjoint_vv, adjoint_v, ppr_adjoint):
+    given dL/dx_{n+1} and dL/dv_{n+1}, solve (M + H T^T) zeta = gbar with
+    H = h^2 Hess W(x_{n+1}) = P - M - Delta P and return dL/dx_n, dL/dv_n and the
+    parameter gradients of this step.  The plain definition of the adjoint is
+    the direct solve (the paper's ground truth); ``direct=False`` runs the
+    paper's iteration P zeta^{k+1} = (Delta P + Delta R) zeta^k + gbar instead."""
+    h = model.h
+    m = model.m
+    x1 = rec.x1
+    gbar = gv + h * gx                                        # x_{n+1} = x_n + h v_{n+1}
+    dP = delta_P(model, x1)
+    PmM = _kron3(h * h * model.K_s)
+    Hm = (PmM - dP).tocsr()                                   # h^2 Hess W(x_{n+1})
+    C = rec.contact.nodes.size
+    Tb = np.tile(np.eye(3), (m, 1, 1))
+    if C:
+        Tb[rec.contact.nodes] = contact_jacobian_blocks(rec.contact, h)
+    TT = _blockdiag3(np.transpose(Tb, (0, 2, 1)))             # T^T
+    Mk = sp.diags(np.repeat(model.mass, 3))
+    Aadj = (Mk + Hm @ TT).tocsc()
+    gb = gbar.reshape(-1)
+    if direct:
+        zeta = spla.splu(Aadj).solve(gb)
+        iters = 0
+    else:
+        zeta, iters = adjoint_fixed_point(model, Hm, dP, TT, gb, iter_tol, iter_max)
+    z = TT @ zeta
+    dv = (Mk @ z).reshape(m, 3)
+    dx = gx - (Hm @ z).reshape(m, 3) / h
+    zeta3 = zeta.reshape(m, 3)
+    z3 = z.reshape(m, 3)
+    # parameter gradients: dc/dw_i = h A_i^T (p_i - q_i) at x_{n+1}
+    p, q = local_projection(model, x1)
+    Az = model.A @ z3
+    dw = h * np.sum(Az * (p - q), axis=1)
+    dmu = np.zeros(len(model.obstacles))
+    ct = rec.contact
+    act = ct.mode != TAKEOFF
+    if np.any(act):
+        j = ct.nodes[act]
+        nrm = ct.normal[act]
+        phi = ct.gap[act]
+        ub = ct.ubar[act]
+        mu = ct.mu[act]
+        lam = model.mass[j, None] * zeta3[j]                  # lambda = M zeta
+        I3 = np.eye(3)[None]
+        un = np.sum(nrm * ub, axis=1)
+        a = un + phi / h
+        ut = ub - un[:, None] * nrm
+        tau = np.linalg.norm(ut, axis=1)
+        sl = ct.mode[act] == SLIP
+        t = np.zeros_like(ut)
+        t[sl] = ut[sl] / tau[sl, None]
+        # d v / d phi: stick -n/h, slip (-n + mu t)/h
+        dv_dphi = (-nrm + (mu * sl)[:, None] * t) / h
+        # d v / d n (ubar, phi held fixed)
+        dv_dn = -(phi / h)[:, None, None] * I3 * np.ones((j.size, 1, 1))
+        if np.any(sl):
+            nn, ubs, ts, taus, As, mus = nrm[sl], ub[sl], t[sl], tau[sl], a[sl], mu[sl]
+            dut_dn = -un[sl][:, None, None] * I3 - nn[:, :, None] * ubs[:, None, :]
+            dt_dut = (I3 - ts[:, :, None] * ts[:, None, :]) / taus[:, None, None]
+            dv_dn[sl] += (dut_dn + mus[:, None, None] * ts[:, :, None] * ubs[:, None, :]
+                          + (mus * As)[:, None, None] * np.einsum('cij,cjk->cik', dt_dut, dut_dn))
+            np.add.at(dmu, ct.obstacle[act][sl], np.sum(lam[sl] * ts, axis=1) * As)
+        dphi = np.sum(lam * dv_dphi, axis=1)
+        np.add.at(dx, j, dphi[:, None] * nrm)                 # grad phi = n (plane, sphere)
+        dn = np.einsum('cji,cj->ci', dv_dn, lam)              # (dv/dn)^T lambda
+        for oi, o in enumerate(model.obstacles):
+            if o.kind != SPHERE:
+                continue
+            so = ct.obstacle[act] == oi
+            if not np.any(so):
+                continue
+            r = np.linalg.norm(rec.x0[j[so]] - np.asarray(o.point, float), axis=1)
+            ns = nrm[so]
+            dns = dn[so]
+            proj = dns - np.sum(ns * dns, axis=1)[:, None] * ns   # (I - n n^T) dn
+            np.add.at(dx, j[so], proj / r[:, None])
+    return dx, dv, dw, dmu, iters
+
+
+def adjoint_fixed_point(model: Model, Hm, dP, TT, gbar, tol, max_iters):
+    """Paper's iteration for the contact adjoint (eqn ppr_adjoint): with the
+    prefactored P, zeta^{k+1} = P^{-1}[gbar + Delta P z^k + (P - M)(zeta^k - z^k)],
+    z^k = T^T zeta^k, which at its fixed point solves (M + H T^T) zeta = gbar."""
+    m = model.m
+    PmM = _kron3(model.h ** 2 * model.K_s)
+    zeta = np.zeros_like(gbar)
+    for k in range(1, max_iters + 1):
+        z = TT @ zeta
+        r = gbar + dP @ z + PmM @ (zeta - z)
+        zn = model.solve_P(r.reshape(m, 3)).reshape(-1)
+        d = np.max(np.abs(zn - zeta))
+        zeta = zn
+        if d <= tol * max(np.max(np.abs(zeta)), 1e-300):
+            return zeta, k
+    return zeta, max_iters
+
+
+@dataclasses.dataclass
+class Gradients:
+    dx0: np.ndarray
+    dv0: np.ndarray
+    dw: np.ndarray          # per constraint: springs first, then bending
+    dmu: np.ndarray         # per obstacle
+    dregion: Optional[np.ndarray] = None
+
+    @property
+    def dk_spring(self):
+        return self.dw
+
+
+def backward(model: Model, recs: List[StepRecord], dL_dxT: np.ndarray, dL_dvT=None,
+             dL_dx_steps=None, direct: bool = True) -> Gradients:
+    """Backpropagation through the whole rollout (Sec. 4.1, eqn adjoint): the
+    per-step adjoints chained from the last step to the first."""
+    gx = np.asarray(dL_dxT, float).copy()
+    gv = np.zeros_like(gx) if dL_dvT is None else np.asarray(dL_dvT, float).copy()
+    dw = np.zeros(model.nc)
+    dmu = np.zeros(len(model.obstacles))
+    T = len(recs)
+    for n in range(T - 1, -1, -1):
+        dx, dv, dwn, dmun, _ = backward_step(model, recs[n], gx, gv, n, direct=direct)
+        dw += dwn
+        dmu += dmun
+        gx, gv = dx, dv
+        if dL_dx_steps is not None:
+            gx = gx + dL_dx_steps[n]
+    dregion = None
+    if model.region is not None:
+        dregion = np.zeros(model.region_scale.size)
+        np.add.at(dregion, model.region, dw * model.base_w)
+    return Gradients(gx, gv, dw, dmu, dregion)
+
+
+# =========================================================================== losses
+
+def centroid_loss(model: Model, x: np.ndarray, target: np.ndarray):
+    """Squared distance of the centroid to a target; returns (L, dL/dx)."""
+    c = x.mean(axis=0)
+    d = c - target
+    return float(d @ d), np.tile(2.0 * d / x.shape[0], (x.shape[0], 1))
+
+
+def apex_angle_loss(x: np.ndarray, waist: np.ndarray, hem: np.ndarray):
+    """Apex angle 2 atan(mean hem radius / (mean waist y - mean hem y)) of a
+    skirt about the vertical axis; returns (angle, d angle / dx)."""
+    rh = np.sqrt(x[hem, 0] ** 2 + x[hem, 2] ** 2)
+    R = rh.mean()
+    Hh = x[waist, 1].mean() - x[hem, 1].mean()
+    ang = 2.0 * math.atan2(R, Hh)
+    den = R * R + Hh * Hh
+    dR = 2.0 * Hh / den
+    dH = -2.0 * R / den
+    g = np.zeros_like(x)
+    g[hem, 0] += dR * x[hem, 0] / rh / hem.size
+    g[hem, 2] += dR * x[hem, 2] / rh / hem.size
+    g[waist, 1] += dH / waist.size
+    g[hem, 1] -= dH / hem.size
+    return ang, g

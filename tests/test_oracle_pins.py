@@ -1,0 +1,459 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: closed
+forms (free fall, rest state, rigid motions, textbook friction cases, the
+sliding-particle trajectory), invariants (monotone PD energy, the
+Signorini-Coulomb conditions, continuity in mu), brute-force assemblies and
+central finite differences on tiny meshes, so that a dropped term, a wrong
+sign or index, or a transposed operand fails at least one of them.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import scenes
+from oracle import diffcloth_oracle as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------------ helpers
+
+def particle_scene(points, obstacles, v0, steps=1, h=1.0 / 120.0, mass=1e-3):
+    """Independent particles: a grid mesh with zero spring and bending weights."""
+    pts = np.asarray(points, float)
+    n = int(round(math.sqrt(pts.shape[0])))
+    assert n * n == pts.shape[0]
+    _, tris, edges = scenes.grid_mesh(n)
+    return scenes.Scene(
+        name="particles", X=pts, tris=tris, edges=edges,
+        edge_stiffness=np.zeros(edges.shape[0]), node_mass=np.full(pts.shape[0], mass),
+        v0=np.asarray(v0, float) * np.ones_like(pts), h=h, steps=steps, bend_weight=0.0,
+        obstacles=obstacles)
+
+
+def dense_constraint_rows(model):
+    """Explicit A_i (3 x 3m) of every spring/bending constraint, built from the
+    edge list and the stencil coefficients (eqn pd_project)."""
+    rows = []
+    A = model.A.tocsr()
+    for i in range(model.nc):
+        Ai = np.zeros((3, 3 * model.m))
+        for p in range(A.indptr[i], A.indptr[i + 1]):
+            k = A.indices[p]
+            Ai[:, 3 * k:3 * k + 3] += A.data[p] * np.eye(3)
+        rows.append(Ai)
+    return rows
+
+
+def converged_loss(scene, tol=1e-13, **kw):
+    """Converged rollout and L = centroid loss + a seeded linear functional of x_T
+    (the latter makes L sensitive to the cloth's deformation)."""
+    x0 = kw.pop("x0", None)
+    v0 = kw.pop("v0", None)
+    model = O.Model(scene, **kw)
+    recs = O.rollout(model, x0=x0, v0=v0, tol=tol)
+    L, g = O.centroid_loss(model, recs[-1].x1, scene.target)
+    c = np.random.default_rng(1234).normal(size=g.shape)
+    return model, recs, L + float(np.sum(c * recs[-1].x1)), g + c
+
+
+def modes_of(recs):
+    return [tuple(r.contact.nodes.tolist()) + tuple(r.contact.mode.tolist()) for r in recs]
+
+
+# ------------------------------------------------------------------ constraint set
+
+def test_edges_match_triangle_edges():
+    for sc in (scenes.c1_napkin(0), scenes.tiny_scene(4), scenes.c3_skirt(0, 8, 6)):
+        e = O.triangle_edges(sc.tris)
+        assert np.array_equal(e, sc.edges.astype(np.int64))
+
+
+def test_cotangent_stencil_on_regular_grid_is_five_point():
+    # cot 45 deg = 1 on the axis edges, cot 90 deg = 0 on the diagonals
+    X, tris, _ = scenes.grid_mesh(5, 0.4)
+    centers, L = O.cotangent_bending_stencils(X, tris)
+    assert sorted(centers.tolist()) == [i * 5 + j for i in range(1, 4) for j in range(1, 4)]
+    L = L.toarray()
+    for r, b in enumerate(centers):
+        i, j = divmod(int(b), 5)
+        expect = np.zeros(25)
+        for di, dj in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+            expect[(i + di) * 5 + (j + dj)] = 1.0
+        expect[b] = -4.0
+        assert np.allclose(L[r], expect, atol=1e-12)
+
+
+def test_global_matrix_matches_bruteforce_assembly():
+    sc = scenes.tiny_scene(4, pins=True, seed=3)
+    model = O.Model(sc)
+    h = model.h
+    P = np.diag(np.repeat(model.mass, 3))
+    for w, Ai in zip(model.w, dense_constraint_rows(model)):
+        P += h * h * w * Ai.T @ Ai
+    for j in model.attach:
+        Aj = np.zeros((3, 3 * model.m))
+        Aj[:, 3 * j:3 * j + 3] = np.eye(3)
+        P += h * h * model.w_att * Aj.T @ Aj
+    P_or = np.kron(model.P_s.toarray(), np.eye(3))
+    assert np.allclose(P_or, P, rtol=1e-13, atol=1e-15)
+    # global solve: residual and agreement with a dense solve of the brute-force P
+    rng = np.random.default_rng(0)
+    rhs = rng.normal(size=(model.m, 3))
+    v = model.solve_P(rhs)
+    assert np.linalg.norm(P @ v.ravel() - rhs.ravel()) <= 1e-13 * np.linalg.norm(rhs)
+    assert np.allclose(v.ravel(), np.linalg.solve(P, rhs.ravel()), rtol=1e-12, atol=1e-14)
+
+
+def test_projection_of_rigid_motion_is_identity():
+    sc = scenes.tiny_scene(4, seed=5)     # noisy rest shape: curved bending active
+    model = O.Model(sc)
+    R = O.rotation((0.3, 1.0, -0.2), 0.7)
+    x = sc.X @ R.T + np.array([0.4, -1.0, 2.0])
+    p, q = O.local_projection(model, x)
+    act = model.rho > 0
+    assert act.sum() > model.n_spring          # bending constraints are curved here
+    assert np.allclose(p[act], q[act], rtol=0, atol=1e-14)
+    assert np.allclose(np.linalg.norm(p[act], axis=1), model.rho[act], rtol=1e-14)
+
+
+# ------------------------------------------------------------------ forward closed forms
+
+def test_free_fall_is_exact():
+    sc = scenes.tiny_scene(4, steps=12, obstacle=None, seed=2)
+    vel = np.array([0.3, 0.5, -0.2])
+    sc.v0 = np.tile(vel, (sc.n_nodes, 1))
+    model = O.Model(sc)
+    recs = O.rollout(model)
+    T, h, g = sc.steps, sc.h, np.asarray(sc.gravity)
+    expect = sc.X + T * h * vel + h * h * g * T * (T + 1) / 2
+    assert np.allclose(recs[-1].x1, expect, rtol=0, atol=1e-12)
+    # per step: x_{n+1} = x_n + h v_n + h^2 g
+    for r in recs:
+        assert np.allclose(r.x1, r.x0 + h * r.v0 + h * h * g, rtol=0, atol=1e-13)
+
+
+def test_rest_state_stays_still():
+    sc = scenes.tiny_scene(4, steps=10, obstacle=None, pins=True, seed=4)
+    sc.gravity = (0.0, 0.0, 0.0)
+    model = O.Model(sc)
+    recs = O.rollout(model)
+    assert np.max(np.abs(recs[-1].x1 - sc.X)) <= 1e-12
+
+
+def test_pd_energy_decreases_monotonically():
+    sc = scenes.c1_napkin(0, steps=6)
+    sc.obstacles = []
+    model = O.Model(sc)
+    x, v = sc.X.copy(), sc.v0.copy()
+    checked = 0
+    for n in range(sc.steps):
+        log = []
+        r = O.forward_step(model, x, v, n, iters=40, energy_log=log)
+        e = np.array(log)
+        assert np.all(e[1:] <= e[:-1] * (1 + 1e-12) + 1e-15), (n, np.max(np.diff(e)))
+        checked += e.size
+        x, v = r.x1, r.v1
+    assert checked == 6 * 40
+
+
+def test_converged_step_satisfies_implicit_euler():
+    sc = scenes.tiny_scene(4, steps=3, obstacle=None, pins=True, seed=7)
+    model = O.Model(sc)
+    recs = O.rollout(model, tol=1e-14, steps=3)
+    rows = dense_constraint_rows(model)
+    for n, r in enumerate(recs):
+        x = r.x1
+        y = O.inertial_predictor(model, r.x0, r.v0)
+        p, _ = O.local_projection(model, x)
+        grad = np.zeros(3 * model.m)
+        for i, Ai in enumerate(rows):
+            grad += model.w[i] * Ai.T @ (Ai @ x.ravel() - p[i])
+        tgt = model.attach_targets((n + 1) * model.h)
+        for c, j in enumerate(model.attach):
+            grad[3 * j:3 * j + 3] += model.w_att * (x[j] - tgt[c])
+        res = (model.mass[:, None] * (x - y)).ravel() / model.h ** 2 + grad
+        scale = np.abs(grad).max()
+        assert np.abs(res).max() <= 1e-8 * scale
+
+
+# ------------------------------------------------------------------ contact law
+
+def test_signorini_coulomb_conditions_hold():
+    rng = np.random.default_rng(11)
+    C = 4000
+    n = rng.normal(size=(C, 3))
+    n /= np.linalg.norm(n, axis=1)[:, None]
+    ub = rng.normal(size=(C, 3))
+    phi = rng.uniform(-0.01, 0.01, C)
+    mu = rng.uniform(0.0, 1.5, C)
+    mass = rng.uniform(1e-4, 1e-2, C)
+    h = 1.0 / 120.0
+    v, f, mode = O.signorini_coulomb(ub, n, phi, mu, h, mass)
+    assert set(np.unique(mode)) == {O.TAKEOFF, O.STICK, O.SLIP}
+    assert np.allclose(v, ub + f / mass[:, None], rtol=0, atol=1e-14)   # v = ubar + W f
+    r = f / h
+    rN = np.sum(r * n, axis=1)
+    rT = r - rN[:, None] * n
+    vN = np.sum(v * n, axis=1)
+    vT = v - vN[:, None] * n
+    uN = vN + phi / h                                           # gap-corrected normal velocity
+    assert np.all(rN >= -1e-12 * np.abs(r).max(axis=1))
+    assert np.all(np.linalg.norm(rT, axis=1) <= mu * rN * (1 + 1e-12) + 1e-13)
+    to, st, sl = mode == O.TAKEOFF, mode == O.STICK, mode == O.SLIP
+    assert np.all(r[to] == 0.0) and np.all(uN[to] > 0)
+    assert np.allclose(vT[st], 0.0, atol=1e-14) and np.allclose(uN[st], 0.0, atol=1e-12)
+    assert np.allclose(uN[sl], 0.0, atol=1e-12)
+    assert np.allclose(np.linalg.norm(rT[sl], axis=1), mu[sl] * rN[sl], rtol=1e-12)
+    assert np.all(np.sum(rT[sl] * vT[sl], axis=1) <= 1e-15)
+    cross = np.cross(rT[sl], vT[sl])
+    assert np.allclose(cross, 0.0, atol=1e-12 * np.abs(rT[sl]).max() * np.abs(vT[sl]).max())
+
+
+def test_friction_special_cases():
+    rng = np.random.default_rng(12)
+    C = 2000
+    n = np.tile([0.0, 1.0, 0.0], (C, 1))
+    ub = rng.normal(size=(C, 3))
+    ub[:, 1] = -np.abs(ub[:, 1])
+    phi = np.zeros(C)
+    mass = np.ones(C)
+    _, _, mode0 = O.signorini_coulomb(ub, n, phi, np.zeros(C), 0.01, mass)
+    assert np.all(mode0 == O.SLIP)                   # mu = 0: no stick unless u_T = 0
+    ub2 = ub.copy()
+    ub2[:10, [0, 2]] = 0.0
+    _, _, m2 = O.signorini_coulomb(ub2, n, phi, np.zeros(C), 0.01, mass)
+    assert np.all(m2[:10] == O.STICK)
+    _, _, mbig = O.signorini_coulomb(ub, n, phi, np.full(C, 1e6), 0.01, mass)
+    assert np.all(mbig == O.STICK)                   # huge mu: every pressed node sticks
+
+
+def _inclined(theta, mu, steps=1, v0=(0.0, 0.0, 0.0)):
+    nrm = np.array([-math.sin(theta), math.cos(theta), 0.0])
+    tang = np.array([math.cos(theta), math.sin(theta), 0.0])
+    pts = np.array([a * tang + b * np.array([0.0, 0.0, 1.0]) for a in (0.0, 0.3) for b in (0.0, 0.3)])
+    sc = particle_scene(pts, [scenes.Obstacle(scenes.PLANE, (0, 0, 0), tuple(nrm), 0.0, mu)],
+                        v0, steps=steps)
+    return sc, nrm, tang
+
+
+def test_inclined_plane_textbook_cases():
+    rows = np.loadtxt(os.path.join(GOLDEN, "inclined_plane.txt"))
+    for theta_deg, mu, expect in rows:
+        sc, nrm, tang = _inclined(math.radians(theta_deg), mu)
+        recs = O.rollout(O.Model(sc))
+        assert np.all(recs[0].contact.mode == int(expect)), (theta_deg, mu)
+        if int(expect) == O.STICK:
+            assert np.allclose(recs[0].x1, sc.X, atol=1e-15)
+        else:
+            # slides along the slope with a = g (sin - mu cos), stays on the plane
+            g = 9.8
+            acc = g * (math.sin(math.radians(theta_deg)) - mu * math.cos(math.radians(theta_deg)))
+            h = sc.h
+            assert np.allclose((recs[0].x1 - sc.X) @ nrm, 0.0, atol=1e-15)
+            assert np.allclose((recs[0].x1 - sc.X) @ tang, -h * h * acc, rtol=1e-12)
+
+
+def test_sliding_particle_decelerates_then_sticks():
+    mu, h, g = 0.3, 1.0 / 120.0, 9.8
+    vx = 0.05
+    pts = np.array([[a, 0.0, b] for a in (0.0, 0.5) for b in (0.0, 0.5)])
+    sc = particle_scene(pts, [scenes.Obstacle(scenes.PLANE, (0, 0, 0), (0, 1, 0), 0.0, mu)],
+                        (vx, 0.0, 0.0), steps=30, h=h)
+    recs = O.rollout(O.Model(sc))
+    v = vx
+    for r in recs:
+        if v > mu * g * h:
+            v = v - mu * g * h
+            md = O.SLIP
+        else:
+            v = 0.0
+            md = O.STICK
+        assert np.all(r.contact.mode == md)
+        assert np.allclose(r.v1[:, 0], v, atol=1e-14)
+        assert np.allclose(r.v1[:, 1], 0.0, atol=1e-15)
+
+
+def test_landing_stops_on_the_surface():
+    # falls from 1 cm, lands exactly on the linearised surface on the contact step
+    pts = np.array([[a, 0.01, b] for a in (0.0, 0.5) for b in (0.0, 0.5)])
+    sc = particle_scene(pts, [scenes.Obstacle(scenes.PLANE, (0, 0, 0), (0, 1, 0), 0.0, 0.5)],
+                        (0.0, -0.9, 0.0), steps=3)
+    recs = O.rollout(O.Model(sc))
+    first = next(i for i, r in enumerate(recs) if r.contact.nodes.size)
+    r = recs[first]
+    assert np.all(r.contact.mode == O.STICK)
+    assert np.allclose(r.x1[:, 1], 0.0, atol=1e-15)
+
+
+def test_sphere_polar_angle_stick_criterion():
+    # a particle resting on a sphere at polar angle theta sticks iff tan(theta) <= mu
+    for theta, mu, expect in ((0.4, 0.5, O.STICK), (0.4, 0.4, O.SLIP), (0.9, 1.3, O.STICK),
+                              (0.9, 1.2, O.SLIP)):
+        R = 0.5
+        pts = np.array([[R * math.sin(theta + d) * math.cos(psi), R * math.cos(theta + d),
+                         R * math.sin(theta + d) * math.sin(psi)]
+                        for d in (0.0, 1e-3) for psi in (0.0, 1e-2)])
+        sc = particle_scene(pts, [scenes.Obstacle(scenes.SPHERE, (0, 0, 0), (0, 1, 0), R, mu)],
+                            (0.0, 0.0, 0.0))
+        recs = O.rollout(O.Model(sc))
+        assert np.all(recs[0].contact.mode == expect), (theta, mu)
+
+
+def test_velocities_continuous_in_mu():
+    # branch switches stick <-> slip <-> take-off do not create jumps (Sec. 5.1)
+    sc = scenes.tiny_scene(4, steps=12, obstacle="sphere", seed=8, height=0.002, v0_scale=0.3)
+    mus = np.linspace(0.0, 0.6, 121)
+    finals = []
+    for mu in mus:
+        recs = O.rollout(O.Model(sc, mu=[mu]))
+        finals.append(recs[-1].v1.ravel())
+    finals = np.array(finals)
+    d = np.abs(np.diff(finals, axis=0)).max(axis=1)
+    assert d.max() <= 12 * np.median(d) + 1e-12
+
+
+# ------------------------------------------------------------------ adjoint
+
+def test_adjoint_fixed_point_equals_direct_solve():
+    # the paper's iteration converges to the direct solve (its ground truth)
+    rng = np.random.default_rng(21)
+    for obst in ("plane", "sphere", None):
+        sc = scenes.tiny_scene(4, steps=6, obstacle=obst, seed=9, height=0.003, v0_scale=0.05)
+        model, recs, L, g = converged_loss(sc, tol=1e-13)
+        for n in range(len(recs)):
+            gx = rng.normal(size=g.shape)
+            gv = rng.normal(size=g.shape)
+            d = O.backward_step(model, recs[n], gx, gv, n, direct=True)
+            it = O.backward_step(model, recs[n], gx, gv, n, direct=False, iter_tol=1e-14)
+            for a, b in zip(d[:4], it[:4]):
+                if a.size:
+                    assert np.allclose(a, b, rtol=1e-9, atol=1e-10 * np.abs(a).max())
+
+
+def test_no_contact_step_jacobian_matches_finite_differences():
+    sc = scenes.tiny_scene(3, steps=1, obstacle=None, seed=10, v0_scale=0.2)
+    model = O.Model(sc)
+    r = O.forward_step(model, sc.X, sc.v0, 0, tol=1e-14, max_iters=5000)
+    m3 = 3 * model.m
+    Jx = np.zeros((m3, m3))
+    for i in range(m3):
+        e = np.zeros(m3)
+        e[i] = 1.0
+        dx, dv, *_ = O.backward_step(model, r, e.reshape(-1, 3), np.zeros((model.m, 3)), 0)
+        Jx[i] = dx.ravel()                       # row i: d x1_i / d x0
+    eps = 1e-6
+    for j in range(0, m3, 4):
+        xp = sc.X.copy().ravel(); xp[j] += eps
+        xm = sc.X.copy().ravel(); xm[j] -= eps
+        rp = O.forward_step(model, xp.reshape(-1, 3), sc.v0, 0, tol=1e-14, max_iters=5000)
+        rm = O.forward_step(model, xm.reshape(-1, 3), sc.v0, 0, tol=1e-14, max_iters=5000)
+        fd = (rp.x1 - rm.x1).ravel() / (2 * eps)
+        assert np.allclose(Jx[:, j], fd, rtol=1e-6, atol=1e-7)
+
+
+def test_linear_system_whole_trajectory_jacobian():
+    # attachments + flat bending, no springs: the step is affine, so dL/dv0 is a
+    # product of the per-step matrices v_{n+1} = P^-1 (M v_n + ... - (P-M) x_n / h)
+    X, tris, edges = scenes.grid_mesh(4, 0.3, (0.0, 0.5, 0.0))
+    sc = scenes.Scene(name="lin", X=X, tris=tris, edges=edges,
+                      edge_stiffness=np.zeros(edges.shape[0]), node_mass=np.full(16, 2e-3),
+                      v0=np.zeros((16, 3)), steps=8, bend_weight=0.5,
+                      attach=np.array([0, 3], np.int32), obstacles=[],
+                      target=np.array([0.1, 0.2, 0.3]))
+    model = O.Model(sc)
+    recs = O.rollout(model)
+    L, g = O.centroid_loss(model, recs[-1].x1, sc.target)
+    G = O.backward(model, recs, g)
+    P = np.kron(model.P_s.toarray(), np.eye(3))
+    Mk = np.diag(np.repeat(model.mass, 3))
+    h = model.h
+    Pinv = np.linalg.inv(P)
+    A_v = Pinv @ Mk                          # d v_{n+1} / d v_n
+    A_x = -Pinv @ (P - Mk) / h               # d v_{n+1} / d x_n
+    # state s = (x, v): x' = x + h v', v' = A_x x + A_v v + c
+    Ms = np.block([[np.eye(len(Mk)) + h * A_x, h * A_v], [A_x, A_v]])
+    J = np.linalg.matrix_power(Ms, sc.steps)
+    gs = np.concatenate([g.ravel(), np.zeros(g.size)])
+    back = J.T @ gs
+    assert np.allclose(G.dx0.ravel(), back[:g.size], rtol=1e-10, atol=1e-13)
+    assert np.allclose(G.dv0.ravel(), back[g.size:], rtol=1e-10, atol=1e-13)
+
+
+def test_sliding_particle_gradients_closed_form():
+    mu, h, g, T = 0.2, 1.0 / 120.0, 9.8, 10
+    vx = 1.0                                  # keeps sliding for all T steps
+    pts = np.array([[a, 0.0, b] for a in (0.0, 0.5) for b in (0.0, 0.5)])
+    sc = particle_scene(pts, [scenes.Obstacle(scenes.PLANE, (0, 0, 0), (0, 1, 0), 0.0, mu)],
+                        (vx, 0.0, 0.0), steps=T, h=h)
+    model = O.Model(sc)
+    recs = O.rollout(model)
+    assert all(np.all(r.contact.mode == O.SLIP) for r in recs)
+    x_T = recs[-1].x1
+    assert np.allclose(x_T[:, 0], pts[:, 0] + T * h * vx - mu * g * h * h * T * (T + 1) / 2, rtol=1e-13)
+    # L = sum of final x coordinates
+    gl = np.zeros_like(x_T)
+    gl[:, 0] = 1.0
+    G = O.backward(model, recs, gl)
+    npart = pts.shape[0]
+    assert np.isclose(G.dmu[0], -npart * g * h * h * T * (T + 1) / 2, rtol=1e-10)
+    assert np.allclose(G.dv0[:, 0], T * h, rtol=1e-10)
+    assert np.allclose(G.dx0[:, 0], 1.0, rtol=1e-10)
+    # gap at the first step: x_1 = x_0 + h(v0 - mu(g h - delta/h)) along x
+    assert np.allclose(G.dx0[:, 1], mu, rtol=1e-10)
+
+
+@pytest.mark.parametrize("obst", ["plane", "sphere", None])
+def test_gradients_match_central_finite_differences(obst):
+    sc = scenes.tiny_scene(3, steps=8, obstacle=obst, k=50.0, mu=0.4, seed=1, height=0.005,
+                           v0_scale=0.05, bend=0.02)
+    model, recs, L, g = converged_loss(sc)
+    G = O.backward(model, recs, g)
+    base_modes = modes_of(recs)
+    rng = np.random.default_rng(0)
+    checks = 0
+
+    def fd(eps, **kw):
+        _, rp, Lp, _ = converged_loss(sc, **{k: v[0] for k, v in kw.items()})
+        _, rm, Lm, _ = converged_loss(sc, **{k: v[1] for k, v in kw.items()})
+        if modes_of(rp) != base_modes or modes_of(rm) != base_modes:
+            return None
+        return (Lp - Lm) / (2 * eps)
+
+    d = rng.normal(size=sc.X.shape)
+    e = 1e-6
+    val = fd(e, x0=(sc.X + e * d, sc.X - e * d))
+    if val is not None:
+        assert abs(val - np.sum(G.dx0 * d)) <= 1e-5 * abs(val) + 1e-12
+        checks += 1
+    d = rng.normal(size=sc.X.shape)
+    val = fd(e, v0=(sc.v0 + e * d, sc.v0 - e * d))
+    if val is not None:
+        assert abs(val - np.sum(G.dv0 * d)) <= 1e-5 * abs(val) + 1e-12
+        checks += 1
+    # per-spring stiffness and the bending weight (a relative step of 1e-4)
+    k = sc.edge_stiffness
+    d = rng.normal(size=k.shape) * k
+    e = 1e-4
+    val = fd(e, edge_stiffness=(k + e * d, k - e * d))
+    if val is not None:
+        ad = np.sum(G.dw[:model.n_spring] * d)
+        assert abs(val - ad) <= 1e-4 * abs(val) + 1e-14, (val, ad)
+        checks += 1
+    wb = sc.bend_weight
+    val = fd(e * wb, bend_weight=(wb * (1 + e), wb * (1 - e)))
+    if val is not None:
+        ad = np.sum(G.dw[model.n_spring:])
+        assert abs(val - ad) <= 1e-4 * abs(val) + 1e-14, (val, ad)
+        checks += 1
+    if obst is not None:
+        mu = sc.obstacles[0].mu
+        e = 1e-5
+        val = fd(e, mu=([mu + e], [mu - e]))
+        if val is not None:
+            assert abs(val - G.dmu[0]) <= 1e-5 * abs(val) + 1e-10, (val, G.dmu[0])
+            checks += 1
+    assert checks >= 3
