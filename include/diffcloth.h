@@ -1,0 +1,232 @@
+/*
+ * diffcloth.h -- C ABI of the MI355X (gfx950) DiffCloth hot path.
+ *
+ * The library simulates cloth with Projective Dynamics (PD) and dry frictional
+ * contact, and back-propagates a loss through the rollout with the adjoint
+ * method of DiffCloth (Li et al., "DiffCloth: Differentiable Cloth Simulation
+ * with Dry Frictional Contact", ACM TOG 2022):
+ *   forward  -- per time step the PD local/global loop (Sec. 3.1, eqns
+ *               pd_project, pd_global) in velocity form with contact impulses
+ *               on the right-hand side (Sec. 3.2, eqns pd_velocity,
+ *               pd_velocity_with_contact) and a per-node Signorini-Coulomb
+ *               update (eqn contact_all);
+ *   backward -- per time step the adjoint solve with the prefactored PD matrix
+ *               and the per-node contact Jacobians (Sec. 4.2, eqns adjoint_v,
+ *               ppr_adjoint), then the gradients with respect to the initial
+ *               state, the constraint weights and the friction coefficients.
+ *
+ * Conventions
+ *   - Every call returns an int: 0 = success, < 0 = error (SIM_E*), > 0 =
+ *     success with a warning (SIM_W*).  No C++ exception crosses this ABI.
+ *   - Host arrays passed to sim_create are copied; the caller keeps ownership.
+ *   - "_dev" pointers are device (HBM) pointers owned by the caller; they must
+ *     be valid for the sizes stated and stay valid until the call's work on
+ *     the handle's stream has finished.  Positions, velocities and gradients
+ *     are node-major float64 arrays [n_nodes][3] in the caller's node order.
+ *   - All device memory the handle needs comes from the caller's allocator
+ *     callback (e.g. the PyTorch caching allocator) or, when it is NULL, from
+ *     hipMalloc; it is returned in sim_destroy.
+ *   - All device work is enqueued on the stream given to sim_create (NULL =
+ *     the default stream).  Calls that return data to the host synchronise
+ *     that stream.
+ *   - A handle is not thread-safe; use one handle per thread or lock.
+ */
+#ifndef DIFFCLOTH_H
+#define DIFFCLOTH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- codes */
+#define SIM_OK               0
+#define SIM_EINVAL          -1   /* bad mesh or parameters                              */
+#define SIM_ENOTSPD         -2   /* a Cholesky pivot of the PD matrix is not positive   */
+#define SIM_ENOMEM          -3   /* allocation failed                                   */
+#define SIM_ENONFINITE      -4   /* NaN / Inf in inputs or state                        */
+#define SIM_ESTATE          -5   /* call out of order (backward before forward, ...)    */
+#define SIM_EHIP            -6   /* a HIP runtime call failed                           */
+#define SIM_WADJ_FALLBACK    1   /* >= 1 adjoint step needed the fallback solver        */
+#define SIM_WADJ_NOCONV      2   /* >= 1 adjoint step did not reach its tolerance       */
+
+#define SIM_PLANE            0
+#define SIM_SPHERE           1
+
+#define SIM_FP64             0   /* every step in float64                               */
+#define SIM_MIXED            1   /* float32 local projections, projection Jacobians and
+                                    residual SpMV; float64 solves, contact, accumulation */
+
+#define SIM_MODE_FREE        0   /* node not in the contact set                          */
+#define SIM_MODE_TAKEOFF     1
+#define SIM_MODE_STICK       2
+#define SIM_MODE_SLIP        3
+
+/* ---------------------------------------------------------------- types */
+typedef struct sim sim_t;
+
+/* Static analytic obstacle.  Plane: {x : n.(x - p) = 0}, signed distance
+ * n.(x - p) with unit normal n.  Sphere: centre p, radius r, signed distance
+ * |x - p| - r.  mu is its Coulomb friction coefficient. */
+typedef struct {
+    int32_t type;          /* SIM_PLANE or SIM_SPHERE */
+    double  p[3];
+    double  n[3];
+    double  radius;
+    double  mu;
+} sim_obstacle_t;
+
+/* Triangle mesh.  X is the rest shape, also the default initial state.
+ * Springs are the unique triangle edges (a < b, sorted lexicographically)
+ * unless an explicit edge list is given.  Attachment targets are the rest
+ * positions rotated by attach_omega * t about attach_axis through
+ * attach_center (omega = 0: fixed pins). */
+typedef struct {
+    int32_t        n_nodes;
+    const double  *X;              /* [n_nodes*3] */
+    int32_t        n_tris;
+    const int32_t *tris;           /* [n_tris*3]  */
+    int32_t        n_edges;        /* 0: extract from tris */
+    const int32_t *edges;          /* [n_edges*2] or NULL  */
+    int32_t        n_attach;
+    const int32_t *attach;         /* [n_attach] node ids  */
+    double         attach_omega;
+    double         attach_axis[3];
+    double         attach_center[3];
+} sim_mesh_t;
+
+/* Physical and solver parameters.
+ *  h, pd_iters     time step (s) and PD local/global iterations per step;
+ *  fwd_tol         > 0: iterate each step until max|v^{k+1} - v^k| <= fwd_tol
+ *                  (m/s) or fwd_max_iters; <= 0: exactly pd_iters iterations;
+ *  node_mass       [n_nodes] lumped masses (kg), all > 0;
+ *  edge_stiffness  [n_edges] spring weights (N/m) in the spring order above;
+ *  bend_weight     quadratic-bending weight (cotangent Laplacian, one
+ *                  constraint per interior vertex);
+ *  attach_weight   attachment constraint weight (N/m);
+ *  edge_region / bend_region / region_scale: optional; spring e uses
+ *                  edge_stiffness[e] * region_scale[edge_region[e]], the
+ *                  bending constraint at node j bend_weight *
+ *                  region_scale[bend_region[j]] (NULL: scale 1);
+ *  adj_tol         adjoint stop rule max|zeta^{k+1}-zeta^k| <= adj_tol*max|zeta^{k+1}|;
+ *  adj_max_iters   fixed-point iterations before the GMRES fallback;
+ *  checkpoint_every  0: keep every step's record for the backward pass;
+ *                  k > 0: keep the state every k steps and recompute segments. */
+typedef struct {
+    double                h;
+    int32_t               pd_iters;
+    double                fwd_tol;
+    int32_t               fwd_max_iters;
+    double                gravity[3];
+    const double         *node_mass;
+    const double         *edge_stiffness;
+    double                bend_weight;
+    double                attach_weight;
+    const int32_t        *edge_region;
+    const int32_t        *bend_region;
+    const double         *region_scale;
+    int32_t               n_regions;
+    int32_t               n_obstacles;      /* <= 8 */
+    const sim_obstacle_t *obstacles;
+    int32_t               precision;        /* SIM_FP64 or SIM_MIXED */
+    double                adj_tol;
+    int32_t               adj_max_iters;
+    int32_t               checkpoint_every;
+} sim_params_t;
+
+/* Gradient outputs (caller-allocated device arrays; any may be NULL). */
+typedef struct {
+    double *dx0;      /* [n_nodes*3] dL/dx_0                                   */
+    double *dv0;      /* [n_nodes*3] dL/dv_0                                   */
+    double *dw_edge;  /* [n_edges]   dL/d(spring weight)                       */
+    double *dw_bend;  /* [n_nodes]   dL/d(bending weight of the constraint at
+                                     node j); 0 for boundary nodes            */
+    double *dregion;  /* [n_regions] dL/d(region_scale)                        */
+    double *dmu;      /* [n_obstacles] dL/d(mu)                                */
+} sim_grads_t;
+
+typedef struct {
+    int32_t n_nodes, n_edges, n_bend, n_constraints_active;
+    int64_t nnz_P, nnz_L;           /* scalar PD matrix and its Cholesky factor  */
+    int32_t n_supernodes, n_levels; /* supernodal elimination tree              */
+    int32_t steps_recorded;
+    int64_t fwd_iters_total;        /* PD iterations of the last forward        */
+    int64_t adj_iters_total;        /* fixed-point iterations of the last backward */
+    int32_t adj_fallbacks;          /* steps solved by the fallback             */
+    int32_t adj_noconv;             /* steps that missed the tolerance          */
+    int64_t device_bytes;           /* device memory held by the handle         */
+    int64_t adj_krylov_total;       /* GMRES iterations of the fallback         */
+} sim_stats_t;
+
+typedef void *(*sim_alloc_fn)(size_t bytes, void *ctx);
+typedef void  (*sim_free_fn)(void *ptr, void *ctx);
+
+/* ---------------------------------------------------------------- calls */
+
+/* Builds the constraint set (springs, bending, attachments; eqn pd_project),
+ * assembles the scalar PD matrix P_s with P = P_s (x) I_3 (eqn pd_global),
+ * orders it by nested dissection, factors it (supernodal Cholesky, float64,
+ * "prefactorized at the beginning of the simulation", Sec. 3.1) and uploads
+ * everything.  Returns SIM_EINVAL on bad inputs, SIM_ENOTSPD on a
+ * non-positive pivot, SIM_ENOMEM / SIM_EHIP on device failures. */
+int sim_create(const sim_mesh_t *mesh, const sim_params_t *params, void *hip_stream,
+               sim_alloc_fn alloc, sim_free_fn free_fn, void *alloc_ctx, sim_t **out);
+
+/* Sets the initial state (device arrays [n_nodes*3], caller order).  NULL x0
+ * = rest shape; NULL v0 = zero.  Invalidates any recorded rollout. */
+int sim_set_state(sim_t *sim, const double *x0_dev, const double *v0_dev);
+
+/* Runs n_steps implicit-Euler steps with dry frictional contact from the
+ * initial state and records what the backward pass needs.  Optional outputs:
+ * x_traj_dev [(n_steps+1)*n_nodes*3] (x_0 .. x_T), xT_dev, vT_dev [n_nodes*3]. */
+int sim_forward(sim_t *sim, int32_t n_steps, double *x_traj_dev, double *xT_dev, double *vT_dev);
+
+/* Back-propagates dL/dx_T (and optionally dL/dv_T and per-step dL/dx_n,
+ * [(T+1)*n_nodes*3], entry n is added when the pass reaches x_n) through the
+ * recorded rollout.  Returns SIM_ESTATE if no rollout is recorded; a warning
+ * if an adjoint step fell back or missed its tolerance. */
+int sim_backward(sim_t *sim, const double *dL_dxT_dev, const double *dL_dvT_dev,
+                 const double *dL_dx_steps_dev, const sim_grads_t *out);
+
+/* One adjoint step at recorded step n (0 <= n < T): given dL/dx_{n+1} and
+ * dL/dv_{n+1}, writes dL/dx_n, dL/dv_n and this step's weight / friction
+ * gradients (dw_edge, dw_bend, dmu of `out`; the others are ignored). */
+int sim_adjoint_step(sim_t *sim, int32_t n, const double *gx_dev, const double *gv_dev,
+                     double *dx_dev, double *dv_dev, const sim_grads_t *out);
+
+/* Recorded state (x_n, v_n) of the last forward pass, 0 <= n <= T, written
+ * to caller device arrays [n_nodes*3] (either may be NULL). */
+int sim_state(const sim_t *sim, int32_t n, double *x_dev, double *v_dev);
+
+/* Contact modes (SIM_MODE_*) of recorded step n, caller node order, host array [n_nodes]. */
+int sim_modes(const sim_t *sim, int32_t n, uint8_t *modes_host);
+
+int sim_stats(const sim_t *sim, sim_stats_t *out);
+
+/* Batched forward / backward of independent handles in one persistent launch
+ * (one workgroup per handle; handles may differ in size and step count).  All
+ * handles must share the first handle's stream.  Per-handle arguments are
+ * arrays of length n (entries may be NULL where the single call allows it). */
+int sim_batch_forward(sim_t *const *sims, int32_t n, const int32_t *n_steps,
+                      double *const *xT_dev, double *const *vT_dev);
+int sim_batch_backward(sim_t *const *sims, int32_t n, const double *const *dL_dxT_dev,
+                       const sim_grads_t *out);
+
+/* Host-only analysis (no GPU needed): builds the constraint set, the PD
+ * matrix, the ordering and the Cholesky factor exactly as sim_create does and
+ * reports their sizes.  perm_out [n_nodes] (may be NULL) receives the
+ * elimination order (new -> caller node id); dense_L_out [n_nodes^2]
+ * (row-major, may be NULL) the factor L with P_s[perm][:, perm] = L L^T when
+ * n_nodes <= max_dense. */
+int sim_analyze(const sim_mesh_t *mesh, const sim_params_t *params, int32_t leaf_size, sim_stats_t *stats,
+                int32_t *perm_out, double *dense_L_out, int32_t max_dense);
+
+void        sim_destroy(sim_t *sim);
+const char *sim_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DIFFCLOTH_H */

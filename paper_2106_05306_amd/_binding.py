@@ -1,0 +1,109 @@
+"""ctypes binding of libdiffcloth.so (argument marshalling only).
+
+Every function of include/diffcloth.h is exposed under the same name.  The
+library is loaded from the package directory; a missing library raises
+immediately -- there is no fallback implementation.
+"""
+import ctypes
+import os
+from ctypes import (CFUNCTYPE, POINTER, Structure, c_double, c_int32, c_int64, c_size_t, c_uint8,
+                    c_void_p, c_char_p)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdiffcloth.so")
+
+SIM_OK, SIM_EINVAL, SIM_ENOTSPD, SIM_ENOMEM, SIM_ENONFINITE, SIM_ESTATE, SIM_EHIP = 0, -1, -2, -3, -4, -5, -6
+SIM_WADJ_FALLBACK, SIM_WADJ_NOCONV = 1, 2
+SIM_PLANE, SIM_SPHERE = 0, 1
+SIM_FP64, SIM_MIXED = 0, 1
+MODE_FREE, MODE_TAKEOFF, MODE_STICK, MODE_SLIP = 0, 1, 2, 3
+
+c_double_p = POINTER(c_double)
+c_int32_p = POINTER(c_int32)
+
+
+class SimObstacle(Structure):
+    _fields_ = [("type", c_int32), ("p", c_double * 3), ("n", c_double * 3), ("radius", c_double),
+                ("mu", c_double)]
+
+
+class SimMesh(Structure):
+    _fields_ = [("n_nodes", c_int32), ("X", c_double_p), ("n_tris", c_int32), ("tris", c_int32_p),
+                ("n_edges", c_int32), ("edges", c_int32_p), ("n_attach", c_int32), ("attach", c_int32_p),
+                ("attach_omega", c_double), ("attach_axis", c_double * 3), ("attach_center", c_double * 3)]
+
+
+class SimParams(Structure):
+    _fields_ = [("h", c_double), ("pd_iters", c_int32), ("fwd_tol", c_double), ("fwd_max_iters", c_int32),
+                ("gravity", c_double * 3), ("node_mass", c_double_p), ("edge_stiffness", c_double_p),
+                ("bend_weight", c_double), ("attach_weight", c_double), ("edge_region", c_int32_p),
+                ("bend_region", c_int32_p), ("region_scale", c_double_p), ("n_regions", c_int32),
+                ("n_obstacles", c_int32), ("obstacles", POINTER(SimObstacle)), ("precision", c_int32),
+                ("adj_tol", c_double), ("adj_max_iters", c_int32), ("checkpoint_every", c_int32)]
+
+
+class SimGrads(Structure):
+    _fields_ = [("dx0", c_void_p), ("dv0", c_void_p), ("dw_edge", c_void_p), ("dw_bend", c_void_p),
+                ("dregion", c_void_p), ("dmu", c_void_p)]
+
+
+class SimStats(Structure):
+    _fields_ = [("n_nodes", c_int32), ("n_edges", c_int32), ("n_bend", c_int32),
+                ("n_constraints_active", c_int32), ("nnz_P", c_int64), ("nnz_L", c_int64),
+                ("n_supernodes", c_int32), ("n_levels", c_int32), ("steps_recorded", c_int32),
+                ("fwd_iters_total", c_int64), ("adj_iters_total", c_int64), ("adj_fallbacks", c_int32),
+                ("adj_noconv", c_int32), ("device_bytes", c_int64), ("adj_krylov_total", c_int64)]
+
+
+ALLOC_FN = CFUNCTYPE(c_void_p, c_size_t, c_void_p)
+FREE_FN = CFUNCTYPE(None, c_void_p, c_void_p)
+
+_lib = None
+
+
+def lib():
+    """Load libdiffcloth.so once; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2106_05306_amd.build_lib` (no CPU fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        sig = {
+            "sim_create": (c_int32, [POINTER(SimMesh), POINTER(SimParams), c_void_p, ALLOC_FN, FREE_FN, c_void_p,
+                                     POINTER(c_void_p)]),
+            "sim_set_state": (c_int32, [c_void_p, c_void_p, c_void_p]),
+            "sim_forward": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
+            "sim_backward": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, POINTER(SimGrads)]),
+            "sim_adjoint_step": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
+                                           POINTER(SimGrads)]),
+            "sim_state": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
+            "sim_modes": (c_int32, [c_void_p, c_int32, POINTER(c_uint8)]),
+            "sim_stats": (c_int32, [c_void_p, POINTER(SimStats)]),
+            "sim_batch_forward": (c_int32, [POINTER(c_void_p), c_int32, c_int32_p, POINTER(c_void_p),
+                                            POINTER(c_void_p)]),
+            "sim_batch_backward": (c_int32, [POINTER(c_void_p), c_int32, POINTER(c_void_p), POINTER(SimGrads)]),
+            "sim_analyze": (c_int32, [POINTER(SimMesh), POINTER(SimParams), c_int32, POINTER(SimStats), c_int32_p,
+                                      c_double_p, c_int32]),
+            "sim_destroy": (None, [c_void_p]),
+            "sim_strerror": (c_char_p, [c_int32]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class SimError(RuntimeError):
+    def __init__(self, code, what=""):
+        msg = lib().sim_strerror(code).decode()
+        super().__init__(f"{what}: {msg} (code {code})" if what else f"{msg} (code {code})")
+        self.code = code
+
+
+def check(code, what=""):
+    if code < 0:
+        raise SimError(code, what)
+    return code

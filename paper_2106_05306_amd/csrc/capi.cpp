@@ -1,0 +1,827 @@
+// C ABI of the DiffCloth hot path: handle lifetime, device tables, launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <new>
+#include <vector>
+
+#include "diffcloth.h"
+#include "host_model.h"
+#include "sim_dev.h"
+
+namespace dc {
+hipError_t launch_forward(const SimDev *d_sims, int n, bool mixed, hipStream_t st);
+hipError_t launch_backward(const SimDev *d_sims, int n, bool mixed, hipStream_t st);
+hipError_t launch_permute3(const double *in, double *out, const int32_t *perm, int m, bool to_caller, hipStream_t st);
+hipError_t launch_modes(const uint8_t *in, uint8_t *out, const int32_t *perm, int m, hipStream_t st);
+hipError_t launch_region_grad(const double *dw, const double *base_w, const int32_t *region, int nc, int nreg,
+                              double *out, hipStream_t st);
+hipError_t launch_scatter_bend(const double *dw, const int32_t *centers, int n_edges, int n_bend, double *out,
+                               hipStream_t st);
+hipError_t launch_fill(double *p, double v, int64_t n, hipStream_t st);
+}  // namespace dc
+
+using namespace dc;
+
+struct sim {
+    HostModel hm;
+    hipStream_t stream = nullptr;
+    sim_alloc_fn alloc = nullptr;
+    sim_free_fn free_fn = nullptr;
+    void *ctx = nullptr;
+    std::vector<void *> owned;          // every device allocation of the handle
+    int64_t bytes = 0;
+
+    SimDev hd{};                        // host copy of the descriptor
+    SimDev *dd = nullptr;               // device copy (one element)
+    int32_t *d_perm = nullptr;          // new -> caller
+    double *rest_x = nullptr;           // rest shape, new order
+    double *start_x = nullptr, *start_v = nullptr;  // state a forward pass starts from
+    double *ckpt = nullptr;             // checkpoints: [n_seg][2][m*3]
+    int ckpt_cap = 0;
+    double *gsteps = nullptr;           // per-step loss gradients, new order
+    int gsteps_cap = 0;
+    const double *d_basew = nullptr;
+    const int32_t *d_region = nullptr;
+    const int32_t *d_bend_centers = nullptr;
+    uint8_t *d_modes_tmp = nullptr;
+    int T = -1;                         // steps of the recorded rollout (-1: none)
+    int64_t counters_host[8] = {0};
+    int nca = 0;
+};
+
+namespace {
+
+int hip_err(hipError_t e) { return e == hipSuccess ? SIM_OK : SIM_EHIP; }
+
+void *dev_alloc(sim *s, size_t bytes) {
+    if (bytes == 0) bytes = 8;
+    bytes = (bytes + 255) & ~size_t(255);
+    void *p = nullptr;
+    if (s->alloc) {
+        p = s->alloc(bytes, s->ctx);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        p = nullptr;
+    }
+    if (!p) throw std::bad_alloc();
+    s->owned.push_back(p);
+    s->bytes += (int64_t)bytes;
+    return p;
+}
+
+void dev_release(sim *s, void *p) {
+    if (!p) return;
+    auto it = std::find(s->owned.begin(), s->owned.end(), p);
+    if (it != s->owned.end()) s->owned.erase(it);
+    if (s->free_fn) s->free_fn(p, s->ctx);
+    else (void)hipFree(p);
+}
+
+template <class T>
+T *upload(sim *s, const std::vector<T> &v) {
+    T *d = (T *)dev_alloc(s, v.size() * sizeof(T));
+    if (!v.empty() && hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s->stream) != hipSuccess)
+        throw std::runtime_error("hip copy");
+    return d;
+}
+
+template <class T>
+T *zeros(sim *s, size_t n) {
+    T *d = (T *)dev_alloc(s, n * sizeof(T));
+    if (hipMemsetAsync(d, 0, std::max<size_t>(n, 1) * sizeof(T), s->stream) != hipSuccess)
+        throw std::runtime_error("hip memset");
+    return d;
+}
+
+// Build every device table from the host model and upload it.
+void build_device(sim *s) {
+    HostModel &hm = s->hm;
+    const int m = hm.m;
+    SimDev &D = s->hd;
+    D = SimDev{};
+    D.m = m;
+    D.nc_total = hm.nc;
+    D.n_obst = (int)hm.obstacles.size();
+    D.na = (int)hm.attach.size();
+    D.K = hm.pd_iters;
+    D.fwd_max_iters = hm.fwd_max_iters;
+    D.adj_max_iters = hm.adj_max_iters;
+    D.mixed = hm.precision == SIM_MIXED;
+    D.h = hm.h;
+    D.fwd_tol = hm.fwd_tol;
+    D.adj_tol = hm.adj_tol;
+    for (int d = 0; d < 3; ++d) {
+        D.g[d] = hm.g[d];
+        D.att_axis[d] = hm.att_axis[d];
+        D.att_center[d] = hm.att_center[d];
+    }
+    D.w_att = hm.w_att;
+    D.att_omega = hm.att_omega;
+    for (int o = 0; o < D.n_obst; ++o) {
+        const sim_obstacle_t &ob = hm.obstacles[o];
+        D.obst[o].type = ob.type;
+        for (int d = 0; d < 3; ++d) { D.obst[o].p[d] = ob.p[d]; D.obst[o].n[d] = ob.n[d]; }
+        D.obst[o].radius = ob.radius;
+        D.obst[o].mu = ob.mu;
+    }
+    const auto &perm = hm.perm, &iperm = hm.iperm;
+    // masses
+    std::vector<double> mass(m);
+    for (int i = 0; i < m; ++i) mass[i] = hm.mass[perm[i]];
+    D.mass = upload(s, mass);
+    // K_s in the new order
+    std::vector<int32_t> kp(1, 0), kc;
+    std::vector<double> kv;
+    std::vector<float> kvf;
+    for (int i = 0; i < m; ++i) {
+        const int o = perm[i];
+        std::vector<std::pair<int, double>> row;
+        for (int k = hm.ks_ptr[o]; k < hm.ks_ptr[o + 1]; ++k) row.push_back({iperm[hm.ks_col[k]], hm.ks_val[k]});
+        std::sort(row.begin(), row.end());
+        for (auto &pr : row) { kc.push_back(pr.first); kv.push_back(pr.second); kvf.push_back((float)pr.second); }
+        kp.push_back((int32_t)kc.size());
+    }
+    D.ks_ptr = upload(s, kp);
+    D.ks_col = upload(s, kc);
+    D.ks_val = upload(s, kv);
+    D.ks_valf = upload(s, kvf);
+    // constraints: active (rho > 0) first, then the rest; canonical ids kept
+    std::vector<int32_t> order;
+    for (int c = 0; c < hm.nc; ++c)
+        if (hm.rho[c] > 0) order.push_back(c);
+    const int nca = (int)order.size();
+    for (int c = 0; c < hm.nc; ++c)
+        if (!(hm.rho[c] > 0)) order.push_back(c);
+    D.nca = nca;
+    s->nca = nca;
+    std::vector<int32_t> cp(1, 0), cn, cid;
+    std::vector<double> cc, crho, cw, crd;
+    std::vector<float> crhof, cwf;
+    for (int c : order) {
+        for (int k = hm.c_ptr[c]; k < hm.c_ptr[c + 1]; ++k) {
+            cn.push_back(iperm[hm.c_node[k]]);
+            cc.push_back(hm.c_coef[k]);
+        }
+        cp.push_back((int32_t)cn.size());
+        cid.push_back(c);
+        crho.push_back(hm.rho[c]);
+        cw.push_back(hm.w[c]);
+        crhof.push_back((float)hm.rho[c]);
+        cwf.push_back((float)hm.w[c]);
+        for (int d = 0; d < 3; ++d) crd.push_back(hm.restdir[3 * c + d]);
+    }
+    D.c_ptr = upload(s, cp);
+    D.c_node = upload(s, cn);
+    D.c_coef = upload(s, cc);
+    D.c_rho = upload(s, crho);
+    D.c_w = upload(s, cw);
+    D.c_rhof = upload(s, crhof);
+    D.c_wf = upload(s, cwf);
+    D.c_restdir = upload(s, crd);
+    D.c_id = upload(s, cid);
+    // node -> active constraint incidence
+    std::vector<std::vector<std::pair<int, double>>> inc(m);
+    for (int c = 0; c < nca; ++c)
+        for (int k = cp[c]; k < cp[c + 1]; ++k) inc[cn[k]].push_back({c, cc[k]});
+    std::vector<int32_t> ip(1, 0), ic;
+    std::vector<double> icf;
+    for (int i = 0; i < m; ++i) {
+        for (auto &pr : inc[i]) { ic.push_back(pr.first); icf.push_back(pr.second); }
+        ip.push_back((int32_t)ic.size());
+    }
+    D.inc_ptr = upload(s, ip);
+    D.inc_con = upload(s, ic);
+    D.inc_coef = upload(s, icf);
+    // attachments
+    std::vector<int32_t> an, aof(m, -1);
+    std::vector<double> arest;
+    for (size_t a = 0; a < hm.attach.size(); ++a) {
+        const int o = hm.attach[a];
+        an.push_back(iperm[o]);
+        aof[iperm[o]] = (int32_t)a;
+        for (int d = 0; d < 3; ++d) arest.push_back(hm.X[3 * o + d]);
+    }
+    D.att_node = upload(s, an);
+    D.att_of = upload(s, aof);
+    D.att_rest = upload(s, arest);
+    // supernodal factor: inverse diagonal blocks, off-diagonal blocks, row gathers, levels
+    const int ns = hm.ns;
+    std::vector<int32_t> sc0(ns), sns(ns), rptr(ns + 1, 0), rows;
+    std::vector<int64_t> slinv(ns), sboff(ns);
+    std::vector<double> linv, bval;
+    std::vector<std::vector<std::pair<int, double>>> lrow(m);
+    for (int sn = 0; sn < ns; ++sn) {
+        const int c0 = hm.sup_c0[sn], nsz = hm.sup_c0[sn + 1] - c0;
+        const int nR = hm.R_ptr[sn + 1] - hm.R_ptr[sn], nrow = nsz + nR;
+        const std::vector<double> &F = hm.Lblk[sn];
+        sc0[sn] = c0;
+        sns[sn] = nsz;
+        // inverse of the lower-triangular diagonal block, row-major
+        slinv[sn] = (int64_t)linv.size();
+        std::vector<double> inv((size_t)nsz * nsz, 0.0);
+        for (int j = 0; j < nsz; ++j) {
+            for (int i = j; i < nsz; ++i) {
+                double acc = i == j ? 1.0 : 0.0;
+                for (int k = j; k < i; ++k) acc -= F[(size_t)k * nrow + i] * inv[(size_t)k * nsz + j];
+                inv[(size_t)i * nsz + j] = acc / F[(size_t)i * nrow + i];
+            }
+        }
+        linv.insert(linv.end(), inv.begin(), inv.end());
+        sboff[sn] = (int64_t)bval.size();
+        for (int q = 0; q < nR; ++q) {
+            const int r = hm.R_rows[hm.R_ptr[sn] + q];
+            rows.push_back(r);
+            for (int k = 0; k < nsz; ++k) {
+                const double val = F[(size_t)k * nrow + nsz + q];
+                bval.push_back(val);
+                lrow[r].push_back({c0 + k, val});
+            }
+        }
+        rptr[sn + 1] = (int32_t)rows.size();
+    }
+    std::vector<int32_t> lp(1, 0), lc;
+    std::vector<double> lv;
+    for (int i = 0; i < m; ++i) {
+        std::sort(lrow[i].begin(), lrow[i].end());
+        for (auto &pr : lrow[i]) { lc.push_back(pr.first); lv.push_back(pr.second); }
+        lp.push_back((int32_t)lc.size());
+    }
+    std::vector<int32_t> lvl(hm.n_levels + 1, 0), tcol, tsup;
+    for (int l = 0; l < hm.n_levels; ++l) {
+        for (int sn = 0; sn < ns; ++sn)
+            if (hm.sup_level[sn] == l)
+                for (int c = hm.sup_c0[sn]; c < hm.sup_c0[sn + 1]; ++c) { tcol.push_back(c); tsup.push_back(sn); }
+        lvl[l + 1] = (int32_t)tcol.size();
+    }
+    D.n_levels = hm.n_levels;
+    D.lvl_ptr = upload(s, lvl);
+    D.task_col = upload(s, tcol);
+    D.task_sup = upload(s, tsup);
+    D.sup_c0 = upload(s, sc0);
+    D.sup_ns = upload(s, sns);
+    D.sup_linv = upload(s, slinv);
+    D.sup_boff = upload(s, sboff);
+    D.sup_rptr = upload(s, rptr);
+    D.sup_rows = upload(s, rows);
+    D.linv = upload(s, linv);
+    D.bval = upload(s, bval);
+    D.lrow_ptr = upload(s, lp);
+    D.lrow_col = upload(s, lc);
+    D.lrow_val = upload(s, lv);
+    // state and work buffers
+    const size_t v3 = 3 * (size_t)m;
+    D.x = zeros<double>(s, v3);
+    D.v = zeros<double>(s, v3);
+    D.vk = zeros<double>(s, v3);
+    D.vk1 = zeros<double>(s, v3);
+    D.b0 = zeros<double>(s, v3);
+    D.rhs = zeros<double>(s, v3);
+    D.ysol = zeros<double>(s, v3);
+    D.f = zeros<double>(s, v3);
+    D.wp = zeros<double>(s, 3 * (size_t)std::max(nca, 1));
+    D.mode = zeros<uint8_t>(s, m);
+    D.cobst = zeros<int8_t>(s, m);
+    D.ubar = zeros<double>(s, v3);
+    D.red = zeros<double>(s, 64);
+    D.gx = zeros<double>(s, v3);
+    D.gv = zeros<double>(s, v3);
+    D.zeta = zeros<double>(s, v3);
+    D.zeta1 = zeros<double>(s, v3);
+    D.zt = zeros<double>(s, v3);
+    D.adj_s = zeros<double>(s, std::max(nca, 1));
+    D.adj_q = zeros<double>(s, 3 * (size_t)std::max(nca, 1));
+    D.adj_pq = zeros<double>(s, 3 * (size_t)std::max(nca, 1));
+    D.tblk = zeros<double>(s, 9 * (size_t)m);
+    D.dw = zeros<double>(s, std::max(hm.nc, 1));
+    D.dmu = zeros<double>(s, kMaxObstacles);
+    D.counters = zeros<int64_t>(s, 8);
+    D.kry = zeros<double>(s, (size_t)(kKryM + 1) * v3);
+    // caller-order helpers
+    s->d_perm = upload(s, perm);
+    std::vector<double> xr(v3);
+    for (int i = 0; i < m; ++i)
+        for (int d = 0; d < 3; ++d) xr[3 * i + d] = hm.X[3 * perm[i] + d];
+    s->rest_x = upload(s, xr);
+    s->start_x = zeros<double>(s, v3);
+    s->start_v = zeros<double>(s, v3);
+    s->d_basew = upload(s, hm.base_w);
+    if (!hm.region.empty()) s->d_region = upload(s, hm.region);
+    s->d_bend_centers = upload(s, hm.bend_center);
+    s->d_modes_tmp = zeros<uint8_t>(s, m);
+    s->dd = (SimDev *)dev_alloc(s, sizeof(SimDev));
+}
+
+int push_desc(sim *s) {
+    return hip_err(hipMemcpyAsync(s->dd, &s->hd, sizeof(SimDev), hipMemcpyHostToDevice, s->stream));
+}
+
+// make room for `cap` step records
+void ensure_records(sim *s, int cap) {
+    if (s->hd.rec_cap >= cap && s->hd.rec_x) return;
+    dev_release(s, s->hd.rec_x);
+    dev_release(s, s->hd.rec_v);
+    dev_release(s, s->hd.rec_ubar);
+    dev_release(s, s->hd.rec_mode);
+    dev_release(s, s->hd.rec_obst);
+    const size_t v3 = 3 * (size_t)s->hd.m;
+    s->hd.rec_x = (double *)dev_alloc(s, (cap + 1) * v3 * sizeof(double));
+    s->hd.rec_v = (double *)dev_alloc(s, (cap + 1) * v3 * sizeof(double));
+    s->hd.rec_ubar = (double *)dev_alloc(s, cap * v3 * sizeof(double));
+    s->hd.rec_mode = (uint8_t *)dev_alloc(s, (size_t)cap * s->hd.m);
+    s->hd.rec_obst = (int8_t *)dev_alloc(s, (size_t)cap * s->hd.m);
+    s->hd.rec_cap = cap;
+}
+
+int copy_d2d(sim *s, void *dst, const void *src, size_t bytes) {
+    return hip_err(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s->stream));
+}
+
+int seg_len(const sim *s) { return s->hm.checkpoint_every > 0 ? s->hm.checkpoint_every : 0; }
+
+// Forward over [a, b) from the handle's current state into the record buffer.
+int run_forward_range(sim *s, int a, int b) {
+    s->hd.step_begin = a;
+    s->hd.step_end = b;
+    s->hd.rec_step0 = a;
+    int rc = push_desc(s);
+    if (rc) return rc;
+    return hip_err(launch_forward(s->dd, 1, s->hd.mixed != 0, s->stream));
+}
+
+int read_counters(sim *s) {
+    int rc = hip_err(hipMemcpyAsync(s->counters_host, s->hd.counters, sizeof(s->counters_host), hipMemcpyDeviceToHost,
+                                    s->stream));
+    if (rc) return rc;
+    return hip_err(hipStreamSynchronize(s->stream));
+}
+
+template <class F>
+int guarded(F &&f) {
+    try {
+        return f();
+    } catch (const std::bad_alloc &) {
+        return SIM_ENOMEM;
+    } catch (...) {
+        return SIM_EHIP;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int sim_create(const sim_mesh_t *mesh, const sim_params_t *params, void *hip_stream, sim_alloc_fn alloc,
+               sim_free_fn free_fn, void *alloc_ctx, sim_t **out) {
+    if (!out) return SIM_EINVAL;
+    *out = nullptr;
+    sim *s = new (std::nothrow) sim();
+    if (!s) return SIM_ENOMEM;
+    s->stream = (hipStream_t)hip_stream;
+    s->alloc = alloc;
+    s->free_fn = free_fn;
+    s->ctx = alloc_ctx;
+    int rc = s->hm.build(mesh, params);
+    if (rc == SIM_OK) rc = s->hm.order_and_factor(32);
+    if (rc == SIM_OK) {
+        rc = guarded([&] {
+            build_device(s);
+            int r = push_desc(s);
+            if (r) return r;
+            r = sim_set_state(s, nullptr, nullptr);
+            if (r) return r;
+            return hip_err(hipStreamSynchronize(s->stream));
+        });
+    }
+    if (rc != SIM_OK) {
+        sim_destroy(s);
+        return rc;
+    }
+    *out = s;
+    return SIM_OK;
+}
+
+int sim_set_state(sim_t *s, const double *x0_dev, const double *v0_dev) {
+    if (!s) return SIM_EINVAL;
+    const int m = s->hd.m;
+    const size_t v3b = 3 * (size_t)m * sizeof(double);
+    int rc;
+    if (x0_dev) rc = hip_err(launch_permute3(x0_dev, s->start_x, s->d_perm, m, false, s->stream));
+    else rc = copy_d2d(s, s->start_x, s->rest_x, v3b);
+    if (rc) return rc;
+    if (v0_dev) rc = hip_err(launch_permute3(v0_dev, s->start_v, s->d_perm, m, false, s->stream));
+    else rc = hip_err(launch_fill(s->start_v, 0.0, 3 * (int64_t)m, s->stream));
+    if (rc) return rc;
+    s->T = -1;
+    return SIM_OK;
+}
+
+namespace {
+
+// Prepare a handle for a forward pass of n_steps (records / checkpoints) and reset its state.
+int prepare_forward(sim *s, int n_steps) {
+    const int k = seg_len(s);
+    const int cap = k > 0 ? std::min(k, n_steps) : n_steps;
+    ensure_records(s, std::max(cap, 1));
+    const size_t v3b = 3 * (size_t)s->hd.m * sizeof(double);
+    if (k > 0) {
+        const int nseg = (n_steps + k - 1) / k;
+        if (s->ckpt_cap < nseg) {
+            dev_release(s, s->ckpt);
+            s->ckpt = (double *)dev_alloc(s, (size_t)nseg * 2 * v3b);
+            s->ckpt_cap = nseg;
+        }
+    }
+    int rc = copy_d2d(s, s->hd.x, s->start_x, v3b);
+    if (!rc) rc = copy_d2d(s, s->hd.v, s->start_v, v3b);
+    if (!rc) rc = hip_err(hipMemsetAsync(s->hd.counters, 0, 8 * sizeof(int64_t), s->stream));
+    return rc;
+}
+
+// Forward pass; with checkpointing, segment by segment (state saved at each segment start).
+int forward_all(sim *s, int n_steps, double *x_traj_dev) {
+    const int m = s->hd.m;
+    const size_t v3 = 3 * (size_t)m;
+    const int k = seg_len(s);
+    int rc = SIM_OK;
+    if (k <= 0) {
+        rc = run_forward_range(s, 0, n_steps);
+        if (!rc && x_traj_dev)
+            for (int n = 0; n <= n_steps && !rc; ++n)
+                rc = hip_err(launch_permute3(s->hd.rec_x + n * v3, x_traj_dev + n * v3, s->d_perm, m, true, s->stream));
+        return rc;
+    }
+    for (int a = 0, seg = 0; a < n_steps && !rc; a += k, ++seg) {
+        const int b = std::min(n_steps, a + k);
+        rc = copy_d2d(s, s->ckpt + (size_t)seg * 2 * v3, s->hd.x, v3 * sizeof(double));
+        if (!rc) rc = copy_d2d(s, s->ckpt + ((size_t)seg * 2 + 1) * v3, s->hd.v, v3 * sizeof(double));
+        if (!rc) rc = run_forward_range(s, a, b);
+        if (!rc && x_traj_dev)
+            for (int n = a; n <= b && !rc; ++n)
+                rc = hip_err(launch_permute3(s->hd.rec_x + (n - a) * v3, x_traj_dev + n * v3, s->d_perm, m, true,
+                                             s->stream));
+    }
+    return rc;
+}
+
+int finish_forward(sim *s, int n_steps, double *xT_dev, double *vT_dev) {
+    const int m = s->hd.m;
+    int rc = SIM_OK;
+    if (xT_dev) rc = hip_err(launch_permute3(s->hd.x, xT_dev, s->d_perm, m, true, s->stream));
+    if (!rc && vT_dev) rc = hip_err(launch_permute3(s->hd.v, vT_dev, s->d_perm, m, true, s->stream));
+    if (!rc) rc = read_counters(s);
+    if (!rc) s->T = n_steps;
+    return rc;
+}
+
+// Seed the adjoint: gx = dL/dx_T (+ per-step term at T), gv = dL/dv_T; zero the accumulators.
+int prepare_backward(sim *s, const double *dL_dxT, const double *dL_dvT, const double *dL_dx_steps) {
+    const int m = s->hd.m, T = s->T;
+    const size_t v3 = 3 * (size_t)m;
+    int rc = SIM_OK;
+    if (dL_dx_steps) {
+        if (s->gsteps_cap < T + 1) {
+            dev_release(s, s->gsteps);
+            s->gsteps = (double *)dev_alloc(s, (T + 1) * v3 * sizeof(double));
+            s->gsteps_cap = T + 1;
+        }
+        for (int n = 0; n <= T && !rc; ++n)
+            rc = hip_err(launch_permute3(dL_dx_steps + n * v3, s->gsteps + n * v3, s->d_perm, m, false, s->stream));
+        s->hd.gx_steps = s->gsteps;
+    } else {
+        s->hd.gx_steps = nullptr;
+    }
+    if (rc) return rc;
+    if (dL_dxT) rc = hip_err(launch_permute3(dL_dxT, s->hd.gx, s->d_perm, m, false, s->stream));
+    else rc = hip_err(launch_fill(s->hd.gx, 0.0, (int64_t)v3, s->stream));
+    if (!rc && dL_dx_steps) {
+        // gx += per-step term at T (done on the host side of the stream: tiny)
+        std::vector<double> a(v3), b(v3);
+        rc = hip_err(hipMemcpyAsync(a.data(), s->hd.gx, v3 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        if (!rc) rc = hip_err(hipMemcpyAsync(b.data(), s->gsteps + T * v3, v3 * sizeof(double), hipMemcpyDeviceToHost,
+                                             s->stream));
+        if (!rc) rc = hip_err(hipStreamSynchronize(s->stream));
+        for (size_t i = 0; i < v3 && !rc; ++i) a[i] += b[i];
+        if (!rc) rc = hip_err(hipMemcpyAsync(s->hd.gx, a.data(), v3 * sizeof(double), hipMemcpyHostToDevice, s->stream));
+        if (!rc) rc = hip_err(hipStreamSynchronize(s->stream));
+    }
+    if (!rc) {
+        if (dL_dvT) rc = hip_err(launch_permute3(dL_dvT, s->hd.gv, s->d_perm, m, false, s->stream));
+        else rc = hip_err(launch_fill(s->hd.gv, 0.0, (int64_t)v3, s->stream));
+    }
+    if (!rc) rc = hip_err(launch_fill(s->hd.dw, 0.0, std::max(s->hm.nc, 1), s->stream));
+    if (!rc) rc = hip_err(launch_fill(s->hd.dmu, 0.0, kMaxObstacles, s->stream));
+    if (!rc) rc = hip_err(hipMemsetAsync(s->hd.counters, 0, 8 * sizeof(int64_t), s->stream));
+    return rc;
+}
+
+int backward_all(sim *s) {
+    const int T = s->T, k = seg_len(s);
+    const size_t v3 = 3 * (size_t)s->hd.m;
+    if (k <= 0) {
+        s->hd.step_begin = 0;
+        s->hd.step_end = T;
+        s->hd.rec_step0 = 0;
+        int rc = push_desc(s);
+        if (rc) return rc;
+        return hip_err(launch_backward(s->dd, 1, s->hd.mixed != 0, s->stream));
+    }
+    const int nseg = (T + k - 1) / k;
+    for (int seg = nseg - 1; seg >= 0; --seg) {
+        const int a = seg * k, b = std::min(T, a + k);
+        int rc = copy_d2d(s, s->hd.x, s->ckpt + (size_t)seg * 2 * v3, v3 * sizeof(double));
+        if (!rc) rc = copy_d2d(s, s->hd.v, s->ckpt + ((size_t)seg * 2 + 1) * v3, v3 * sizeof(double));
+        if (!rc) rc = run_forward_range(s, a, b);             // recompute the segment's records
+        if (rc) return rc;
+        s->hd.step_begin = a;
+        s->hd.step_end = b;
+        s->hd.rec_step0 = a;
+        rc = push_desc(s);
+        if (!rc) rc = hip_err(launch_backward(s->dd, 1, s->hd.mixed != 0, s->stream));
+        if (rc) return rc;
+    }
+    return SIM_OK;
+}
+
+int write_grads(sim *s, const sim_grads_t *out) {
+    const int m = s->hd.m;
+    int rc = SIM_OK;
+    if (!out) return rc;
+    if (out->dx0) rc = hip_err(launch_permute3(s->hd.gx, out->dx0, s->d_perm, m, true, s->stream));
+    if (!rc && out->dv0) rc = hip_err(launch_permute3(s->hd.gv, out->dv0, s->d_perm, m, true, s->stream));
+    if (!rc && out->dw_edge && s->hm.n_edges)
+        rc = copy_d2d(s, out->dw_edge, s->hd.dw, s->hm.n_edges * sizeof(double));
+    if (!rc && out->dw_bend) {
+        rc = hip_err(launch_fill(out->dw_bend, 0.0, m, s->stream));
+        if (!rc)
+            rc = hip_err(launch_scatter_bend(s->hd.dw, s->d_bend_centers, s->hm.n_edges, s->hm.n_bend, out->dw_bend,
+                                             s->stream));
+    }
+    if (!rc && out->dregion && s->d_region)
+        rc = hip_err(launch_region_grad(s->hd.dw, s->d_basew, s->d_region, s->hm.nc,
+                                        (int)s->hm.region_scale.size(), out->dregion, s->stream));
+    if (!rc && out->dmu && s->hd.n_obst)
+        rc = copy_d2d(s, out->dmu, s->hd.dmu, s->hd.n_obst * sizeof(double));
+    return rc;
+}
+
+int backward_status(sim *s) {
+    int rc = read_counters(s);
+    if (rc) return rc;
+    if (s->counters_host[3] > 0) return SIM_WADJ_NOCONV;
+    if (s->counters_host[2] > 0) return SIM_WADJ_FALLBACK;
+    return SIM_OK;
+}
+
+}  // namespace
+
+int sim_forward(sim_t *s, int32_t n_steps, double *x_traj_dev, double *xT_dev, double *vT_dev) {
+    if (!s || n_steps < 1) return SIM_EINVAL;
+    return guarded([&] {
+        int rc = prepare_forward(s, n_steps);
+        if (!rc) rc = forward_all(s, n_steps, x_traj_dev);
+        if (!rc) rc = finish_forward(s, n_steps, xT_dev, vT_dev);
+        return rc;
+    });
+}
+
+int sim_backward(sim_t *s, const double *dL_dxT_dev, const double *dL_dvT_dev, const double *dL_dx_steps_dev,
+                 const sim_grads_t *out) {
+    if (!s) return SIM_EINVAL;
+    if (s->T < 1) return SIM_ESTATE;
+    return guarded([&] {
+        int rc = prepare_backward(s, dL_dxT_dev, dL_dvT_dev, dL_dx_steps_dev);
+        if (!rc) rc = backward_all(s);
+        if (!rc) rc = write_grads(s, out);
+        if (!rc) rc = backward_status(s);
+        return rc;
+    });
+}
+
+int sim_adjoint_step(sim_t *s, int32_t n, const double *gx_dev, const double *gv_dev, double *dx_dev, double *dv_dev,
+                     const sim_grads_t *out) {
+    if (!s || !gx_dev || !gv_dev) return SIM_EINVAL;
+    if (s->T < 1 || n < 0 || n >= s->T) return SIM_ESTATE;
+    if (seg_len(s) > 0) return SIM_ESTATE;      // needs every step's record
+    return guarded([&] {
+        const int m = s->hd.m;
+        int rc = hip_err(launch_permute3(gx_dev, s->hd.gx, s->d_perm, m, false, s->stream));
+        if (!rc) rc = hip_err(launch_permute3(gv_dev, s->hd.gv, s->d_perm, m, false, s->stream));
+        if (!rc) rc = hip_err(launch_fill(s->hd.dw, 0.0, std::max(s->hm.nc, 1), s->stream));
+        if (!rc) rc = hip_err(launch_fill(s->hd.dmu, 0.0, kMaxObstacles, s->stream));
+        if (!rc) rc = hip_err(hipMemsetAsync(s->hd.counters, 0, 8 * sizeof(int64_t), s->stream));
+        s->hd.gx_steps = nullptr;
+        s->hd.step_begin = n;
+        s->hd.step_end = n + 1;
+        s->hd.rec_step0 = 0;
+        if (!rc) rc = push_desc(s);
+        if (!rc) rc = hip_err(launch_backward(s->dd, 1, s->hd.mixed != 0, s->stream));
+        if (!rc && dx_dev) rc = hip_err(launch_permute3(s->hd.gx, dx_dev, s->d_perm, m, true, s->stream));
+        if (!rc && dv_dev) rc = hip_err(launch_permute3(s->hd.gv, dv_dev, s->d_perm, m, true, s->stream));
+        if (!rc && out) {
+            sim_grads_t o2 = *out;
+            o2.dx0 = nullptr;
+            o2.dv0 = nullptr;
+            rc = write_grads(s, &o2);
+        }
+        if (!rc) rc = backward_status(s);
+        return rc;
+    });
+}
+
+int sim_state(const sim_t *cs, int32_t n, double *x_dev, double *v_dev) {
+    sim *s = const_cast<sim *>(cs);
+    if (!s) return SIM_EINVAL;
+    if (s->T < 1 || n < 0 || n > s->T) return SIM_ESTATE;
+    const int k = seg_len(s);
+    return guarded([&] {
+        const int m = s->hd.m;
+        const size_t v3 = 3 * (size_t)m;
+        int rc = SIM_OK;
+        int slot = n;
+        if (k > 0) {
+            const int seg = std::min(n / k, (s->T - 1) / k), a = seg * k, b = std::min(s->T, a + k);
+            rc = copy_d2d(s, s->hd.x, s->ckpt + (size_t)seg * 2 * v3, v3 * sizeof(double));
+            if (!rc) rc = copy_d2d(s, s->hd.v, s->ckpt + ((size_t)seg * 2 + 1) * v3, v3 * sizeof(double));
+            if (!rc) rc = run_forward_range(s, a, b);
+            slot = n - a;
+        }
+        if (!rc && x_dev) rc = hip_err(launch_permute3(s->hd.rec_x + slot * v3, x_dev, s->d_perm, m, true, s->stream));
+        if (!rc && v_dev) rc = hip_err(launch_permute3(s->hd.rec_v + slot * v3, v_dev, s->d_perm, m, true, s->stream));
+        if (!rc) rc = hip_err(hipStreamSynchronize(s->stream));
+        return rc;
+    });
+}
+
+int sim_modes(const sim_t *cs, int32_t n, uint8_t *modes_host) {
+    sim *s = const_cast<sim *>(cs);
+    if (!s || !modes_host) return SIM_EINVAL;
+    if (s->T < 1 || n < 0 || n >= s->T) return SIM_ESTATE;
+    const int k = seg_len(s);
+    return guarded([&] {
+        const int m = s->hd.m;
+        int rc = SIM_OK;
+        int slot = n;
+        if (k > 0) {                        // recompute the segment holding step n
+            const int seg = n / k, a = seg * k, b = std::min(s->T, a + k);
+            const size_t v3 = 3 * (size_t)m;
+            rc = copy_d2d(s, s->hd.x, s->ckpt + (size_t)seg * 2 * v3, v3 * sizeof(double));
+            if (!rc) rc = copy_d2d(s, s->hd.v, s->ckpt + ((size_t)seg * 2 + 1) * v3, v3 * sizeof(double));
+            if (!rc) rc = run_forward_range(s, a, b);
+            slot = n - a;
+        }
+        if (!rc) rc = hip_err(launch_modes(s->hd.rec_mode + (size_t)slot * m, s->d_modes_tmp, s->d_perm, m, s->stream));
+        if (!rc) rc = hip_err(hipMemcpyAsync(modes_host, s->d_modes_tmp, m, hipMemcpyDeviceToHost, s->stream));
+        if (!rc) rc = hip_err(hipStreamSynchronize(s->stream));
+        return rc;
+    });
+}
+
+int sim_stats(const sim_t *cs, sim_stats_t *out) {
+    if (!cs || !out) return SIM_EINVAL;
+    const sim *s = cs;
+    std::memset(out, 0, sizeof(*out));
+    out->n_nodes = s->hm.m;
+    out->n_edges = s->hm.n_edges;
+    out->n_bend = s->hm.n_bend;
+    out->n_constraints_active = s->nca;
+    out->nnz_P = (int64_t)s->hm.ks_col.size();
+    out->nnz_L = s->hm.nnz_L;
+    out->n_supernodes = s->hm.ns;
+    out->n_levels = s->hm.n_levels;
+    out->steps_recorded = s->T;
+    out->fwd_iters_total = s->counters_host[0];
+    out->adj_iters_total = s->counters_host[1];
+    out->adj_fallbacks = (int32_t)s->counters_host[2];
+    out->adj_noconv = (int32_t)s->counters_host[3];
+    out->device_bytes = s->bytes;
+    out->adj_krylov_total = s->counters_host[4];
+    return SIM_OK;
+}
+
+int sim_batch_forward(sim_t *const *sims, int32_t n, const int32_t *n_steps, double *const *xT_dev,
+                      double *const *vT_dev) {
+    if (!sims || n < 1 || !n_steps) return SIM_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        if (!sims[i] || n_steps[i] < 1) return SIM_EINVAL;
+        if (seg_len(sims[i]) > 0) return SIM_EINVAL;   // batched passes keep every record
+        if (sims[i]->stream != sims[0]->stream || sims[i]->hd.mixed != sims[0]->hd.mixed) return SIM_EINVAL;
+    }
+    sim *s0 = sims[0];
+    return guarded([&] {
+        std::vector<SimDev> descs(n);
+        int rc = SIM_OK;
+        for (int i = 0; i < n && !rc; ++i) {
+            rc = prepare_forward(sims[i], n_steps[i]);
+            sims[i]->hd.step_begin = 0;
+            sims[i]->hd.step_end = n_steps[i];
+            sims[i]->hd.rec_step0 = 0;
+            descs[i] = sims[i]->hd;
+            if (!rc) rc = push_desc(sims[i]);
+        }
+        if (rc) return rc;
+        SimDev *d = (SimDev *)dev_alloc(s0, n * sizeof(SimDev));
+        rc = hip_err(hipMemcpyAsync(d, descs.data(), n * sizeof(SimDev), hipMemcpyHostToDevice, s0->stream));
+        if (!rc) rc = hip_err(launch_forward(d, n, s0->hd.mixed != 0, s0->stream));
+        for (int i = 0; i < n && !rc; ++i)
+            rc = finish_forward(sims[i], n_steps[i], xT_dev ? xT_dev[i] : nullptr, vT_dev ? vT_dev[i] : nullptr);
+        (void)hipStreamSynchronize(s0->stream);
+        dev_release(s0, d);
+        return rc;
+    });
+}
+
+int sim_batch_backward(sim_t *const *sims, int32_t n, const double *const *dL_dxT_dev, const sim_grads_t *out) {
+    if (!sims || n < 1) return SIM_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        if (!sims[i]) return SIM_EINVAL;
+        if (sims[i]->T < 1) return SIM_ESTATE;
+        if (seg_len(sims[i]) > 0 || sims[i]->stream != sims[0]->stream || sims[i]->hd.mixed != sims[0]->hd.mixed)
+            return SIM_EINVAL;
+    }
+    sim *s0 = sims[0];
+    return guarded([&] {
+        std::vector<SimDev> descs(n);
+        int rc = SIM_OK;
+        for (int i = 0; i < n && !rc; ++i) {
+            rc = prepare_backward(sims[i], dL_dxT_dev ? dL_dxT_dev[i] : nullptr, nullptr, nullptr);
+            sims[i]->hd.step_begin = 0;
+            sims[i]->hd.step_end = sims[i]->T;
+            sims[i]->hd.rec_step0 = 0;
+            descs[i] = sims[i]->hd;
+            if (!rc) rc = push_desc(sims[i]);
+        }
+        if (rc) return rc;
+        SimDev *d = (SimDev *)dev_alloc(s0, n * sizeof(SimDev));
+        rc = hip_err(hipMemcpyAsync(d, descs.data(), n * sizeof(SimDev), hipMemcpyHostToDevice, s0->stream));
+        if (!rc) rc = hip_err(launch_backward(d, n, s0->hd.mixed != 0, s0->stream));
+        int warn = SIM_OK;
+        for (int i = 0; i < n && !rc; ++i) {
+            if (out) rc = write_grads(sims[i], &out[i]);
+            if (!rc) {
+                int st = backward_status(sims[i]);
+                if (st < 0) rc = st;
+                else if (st > warn) warn = st;
+            }
+        }
+        (void)hipStreamSynchronize(s0->stream);
+        dev_release(s0, d);
+        return rc ? rc : warn;
+    });
+}
+
+void sim_destroy(sim_t *s) {
+    if (!s) return;
+    if (s->stream || !s->owned.empty()) (void)hipStreamSynchronize(s->stream);
+    for (void *p : s->owned) {
+        if (s->free_fn) s->free_fn(p, s->ctx);
+        else (void)hipFree(p);
+    }
+    s->owned.clear();
+    delete s;
+}
+
+const char *sim_strerror(int code) {
+    switch (code) {
+        case SIM_OK: return "ok";
+        case SIM_EINVAL: return "invalid mesh or parameters";
+        case SIM_ENOTSPD: return "PD matrix is not positive definite";
+        case SIM_ENOMEM: return "out of memory";
+        case SIM_ENONFINITE: return "non-finite input or state";
+        case SIM_ESTATE: return "call out of order (no recorded rollout or bad step)";
+        case SIM_EHIP: return "HIP runtime error";
+        case SIM_WADJ_FALLBACK: return "warning: an adjoint step used the fallback solver";
+        case SIM_WADJ_NOCONV: return "warning: an adjoint step missed its tolerance";
+        default: return "unknown code";
+    }
+}
+
+int sim_analyze(const sim_mesh_t *mesh, const sim_params_t *params, int32_t leaf_size, sim_stats_t *stats,
+                int32_t *perm_out, double *dense_L_out, int32_t max_dense) {
+    HostModel hm;
+    int rc = hm.build(mesh, params);
+    if (rc) return rc;
+    rc = hm.order_and_factor(leaf_size > 0 ? leaf_size : 32);
+    if (rc) return rc;
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->n_nodes = hm.m;
+        stats->n_edges = hm.n_edges;
+        stats->n_bend = hm.n_bend;
+        int nca = 0;
+        for (double r : hm.rho) nca += r > 0;
+        stats->n_constraints_active = nca;
+        stats->nnz_P = (int64_t)hm.ks_col.size();
+        stats->nnz_L = hm.nnz_L;
+        stats->n_supernodes = hm.ns;
+        stats->n_levels = hm.n_levels;
+        stats->steps_recorded = -1;
+    }
+    if (perm_out) std::memcpy(perm_out, hm.perm.data(), hm.m * sizeof(int32_t));
+    if (dense_L_out && hm.m <= max_dense) hm.dense_L(dense_L_out);
+    return SIM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,464 @@
+// Host setup of one cloth: constraint tables (springs, cotangent bending,
+// attachments), the scalar PD matrix P_s (P = P_s (x) I_3), a nested-dissection
+// ordering, and a supernodal float64 Cholesky factor of P_s.
+#include "host_model.h"
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <numeric>
+#include <utility>
+
+namespace dc {
+
+namespace {
+
+inline void sub3(const double *a, const double *b, double *o) {
+    o[0] = a[0] - b[0]; o[1] = a[1] - b[1]; o[2] = a[2] - b[2];
+}
+inline double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+inline double norm3(const double *a) { return std::sqrt(dot3(a, a)); }
+
+bool finite_all(const double *p, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+int HostModel::build(const sim_mesh_t *mesh, const sim_params_t *p) {
+    if (!mesh || !p || mesh->n_nodes < 1 || !mesh->X || mesh->n_tris < 1 || !mesh->tris) {
+        error = "mesh needs nodes and triangles";
+        return SIM_EINVAL;
+    }
+    m = mesh->n_nodes;
+    X.assign(mesh->X, mesh->X + 3 * (size_t)m);
+    if (!finite_all(X.data(), X.size())) { error = "non-finite rest positions"; return SIM_ENONFINITE; }
+    if (!p->node_mass) { error = "node_mass is required"; return SIM_EINVAL; }
+    mass.assign(p->node_mass, p->node_mass + m);
+    for (double v : mass)
+        if (!(v > 0) || !std::isfinite(v)) { error = "masses must be positive and finite"; return SIM_ENOTSPD; }
+    if (!(p->h > 0) || !std::isfinite(p->h)) { error = "time step must be positive"; return SIM_EINVAL; }
+    h = p->h;
+    for (int d = 0; d < 3; ++d) g[d] = p->gravity[d];
+    pd_iters = p->pd_iters;
+    fwd_tol = p->fwd_tol;
+    fwd_max_iters = p->fwd_max_iters > 0 ? p->fwd_max_iters : 100000;
+    if (fwd_tol <= 0 && pd_iters < 1) { error = "pd_iters must be >= 1"; return SIM_EINVAL; }
+    adj_tol = p->adj_tol > 0 ? p->adj_tol : 1e-10;
+    adj_max_iters = p->adj_max_iters > 0 ? p->adj_max_iters : 500;
+    precision = p->precision;
+    if (precision != SIM_FP64 && precision != SIM_MIXED) { error = "bad precision"; return SIM_EINVAL; }
+    checkpoint_every = std::max(0, p->checkpoint_every);
+    if (p->n_obstacles < 0 || p->n_obstacles > 8 || (p->n_obstacles > 0 && !p->obstacles)) {
+        error = "0..8 obstacles";
+        return SIM_EINVAL;
+    }
+    obstacles.assign(p->obstacles, p->obstacles + p->n_obstacles);
+    for (auto &o : obstacles) {
+        if (o.type == SIM_PLANE) {
+            double nn = norm3(o.n);
+            if (!(nn > 0)) { error = "plane normal is zero"; return SIM_EINVAL; }
+            for (int d = 0; d < 3; ++d) o.n[d] /= nn;
+        } else if (o.type == SIM_SPHERE) {
+            if (!(o.radius > 0)) { error = "sphere radius must be positive"; return SIM_EINVAL; }
+        } else {
+            error = "unknown obstacle type";
+            return SIM_EINVAL;
+        }
+        if (!(o.mu >= 0) || !std::isfinite(o.mu)) { error = "friction must be >= 0"; return SIM_EINVAL; }
+    }
+
+    // ---------------------------------------------------------------- triangles
+    const int nt = mesh->n_tris;
+    for (int t = 0; t < 3 * nt; ++t)
+        if (mesh->tris[t] < 0 || mesh->tris[t] >= m) { error = "triangle index out of range"; return SIM_EINVAL; }
+    // edge -> (count, cotangent weight sum); keyed by (min, max)
+    std::map<std::pair<int, int>, std::pair<int, double>> ew;
+    for (int t = 0; t < nt; ++t) {
+        const int32_t *tri = mesh->tris + 3 * t;
+        for (int r = 0; r < 3; ++r) {
+            int i = tri[r], j = tri[(r + 1) % 3], k = tri[(r + 2) % 3];
+            double u[3], v[3], c[3];
+            sub3(&X[3 * i], &X[3 * k], u);
+            sub3(&X[3 * j], &X[3 * k], v);
+            c[0] = u[1] * v[2] - u[2] * v[1];
+            c[1] = u[2] * v[0] - u[0] * v[2];
+            c[2] = u[0] * v[1] - u[1] * v[0];
+            double cn = norm3(c);
+            if (!(cn > 0)) { error = "degenerate triangle"; return SIM_EINVAL; }
+            auto key = std::make_pair(std::min(i, j), std::max(i, j));
+            auto &e = ew[key];
+            e.first += 1;
+            e.second += 0.5 * dot3(u, v) / cn;       // half the cotangent of the angle at k
+        }
+    }
+    // springs
+    if (mesh->n_edges > 0) {
+        if (!mesh->edges) { error = "n_edges > 0 needs an edge list"; return SIM_EINVAL; }
+        n_edges = mesh->n_edges;
+        edges.assign(mesh->edges, mesh->edges + 2 * (size_t)n_edges);
+        for (int e = 0; e < n_edges; ++e) {
+            int a = edges[2 * e], b = edges[2 * e + 1];
+            if (a < 0 || b < 0 || a >= m || b >= m || a == b) { error = "bad edge"; return SIM_EINVAL; }
+        }
+    } else {
+        n_edges = (int)ew.size();
+        edges.resize(2 * (size_t)n_edges);
+        int e = 0;
+        for (auto &kv : ew) { edges[2 * e] = kv.first.first; edges[2 * e + 1] = kv.first.second; ++e; }
+    }
+    if (!p->edge_stiffness) { error = "edge_stiffness is required"; return SIM_EINVAL; }
+    // bending: interior vertices (every incident edge shared by two triangles)
+    std::vector<char> boundary(m, 0), touched(m, 0);
+    for (auto &kv : ew) {
+        touched[kv.first.first] = touched[kv.first.second] = 1;
+        if (kv.second.first == 1) boundary[kv.first.first] = boundary[kv.first.second] = 1;
+    }
+    std::vector<std::vector<std::pair<int, double>>> nbr(m);
+    for (auto &kv : ew) {
+        int a = kv.first.first, b = kv.first.second;
+        nbr[a].push_back({b, kv.second.second});
+        nbr[b].push_back({a, kv.second.second});
+    }
+    bend_center.clear();
+    for (int j = 0; j < m; ++j)
+        if (touched[j] && !boundary[j]) bend_center.push_back(j);
+    n_bend = (int)bend_center.size();
+    nc = n_edges + n_bend;
+
+    // stencils (caller ids)
+    c_ptr.assign(1, 0);
+    c_node.clear();
+    c_coef.clear();
+    for (int e = 0; e < n_edges; ++e) {
+        c_node.push_back(edges[2 * e]);     c_coef.push_back(1.0);
+        c_node.push_back(edges[2 * e + 1]); c_coef.push_back(-1.0);
+        c_ptr.push_back((int32_t)c_node.size());
+    }
+    for (int b = 0; b < n_bend; ++b) {
+        int j = bend_center[b];
+        auto nb = nbr[j];
+        std::sort(nb.begin(), nb.end());
+        double tot = 0;
+        for (auto &pr : nb) {
+            if (pr.second == 0.0) continue;          // e.g. right angles opposite grid diagonals
+            c_node.push_back(pr.first);
+            c_coef.push_back(pr.second);
+            tot += pr.second;
+        }
+        c_node.push_back(j);
+        c_coef.push_back(-tot);
+        c_ptr.push_back((int32_t)c_node.size());
+    }
+    // weights, regions
+    base_w.resize(nc);
+    for (int e = 0; e < n_edges; ++e) base_w[e] = p->edge_stiffness[e];
+    for (int b = 0; b < n_bend; ++b) base_w[n_edges + b] = p->bend_weight;
+    if (!finite_all(base_w.data(), nc)) { error = "non-finite weights"; return SIM_ENONFINITE; }
+    for (double v : base_w)
+        if (v < 0) { error = "weights must be >= 0"; return SIM_EINVAL; }
+    w = base_w;
+    region.clear();
+    region_scale.clear();
+    if (p->region_scale && p->n_regions > 0) {
+        if (!p->edge_region || !p->bend_region) { error = "regions need edge_region and bend_region"; return SIM_EINVAL; }
+        region_scale.assign(p->region_scale, p->region_scale + p->n_regions);
+        region.resize(nc);
+        for (int e = 0; e < n_edges; ++e) region[e] = p->edge_region[e];
+        for (int b = 0; b < n_bend; ++b) region[n_edges + b] = p->bend_region[bend_center[b]];
+        for (int c = 0; c < nc; ++c) {
+            if (region[c] < 0 || region[c] >= p->n_regions) { error = "region index out of range"; return SIM_EINVAL; }
+            w[c] = base_w[c] * region_scale[region[c]];
+        }
+    }
+    // rest norms and directions; flat bending (|l(X)| <= 1e-10 sum_k |c_k||X_k - X_b|) has no target
+    rho.assign(nc, 0.0);
+    restdir.assign(3 * (size_t)nc, 0.0);
+    for (int c = 0; c < nc; ++c) {
+        double q[3] = {0, 0, 0}, mag = 0;
+        int ctr = c >= n_edges ? bend_center[c - n_edges] : -1;
+        for (int k = c_ptr[c]; k < c_ptr[c + 1]; ++k) {
+            const double *xk = &X[3 * c_node[k]];
+            for (int d = 0; d < 3; ++d) q[d] += c_coef[k] * xk[d];
+            if (ctr >= 0) {
+                double dd[3];
+                sub3(xk, &X[3 * ctr], dd);
+                mag += std::fabs(c_coef[k]) * norm3(dd);
+            }
+        }
+        double nq = norm3(q);
+        if (ctr >= 0 && nq <= 1e-10 * mag) nq = 0.0;
+        rho[c] = nq;
+        if (nq > 0)
+            for (int d = 0; d < 3; ++d) restdir[3 * c + d] = q[d] / nq;
+    }
+    // attachments
+    attach.assign(mesh->attach, mesh->attach + mesh->n_attach);
+    for (int a : attach)
+        if (a < 0 || a >= m) { error = "attachment index out of range"; return SIM_EINVAL; }
+    w_att = p->attach_weight;
+    att_omega = mesh->attach_omega;
+    for (int d = 0; d < 3; ++d) { att_axis[d] = mesh->attach_axis[d]; att_center[d] = mesh->attach_center[d]; }
+    if (!attach.empty()) {
+        double an = norm3(att_axis);
+        if (!(an > 0)) { error = "attachment axis is zero"; return SIM_EINVAL; }
+        for (int d = 0; d < 3; ++d) att_axis[d] /= an;
+    }
+
+    // ---------------------------------------------------------------- K_s
+    std::vector<std::map<int, double>> rows(m);
+    for (int c = 0; c < nc; ++c) {
+        for (int k = c_ptr[c]; k < c_ptr[c + 1]; ++k)
+            for (int l = c_ptr[c]; l < c_ptr[c + 1]; ++l)
+                rows[c_node[k]][c_node[l]] += w[c] * c_coef[k] * c_coef[l];
+    }
+    for (int a : attach) rows[a][a] += w_att;
+    for (int i = 0; i < m; ++i) rows[i][i] += 0.0;   // keep the diagonal in the pattern
+    ks_ptr.assign(1, 0);
+    ks_col.clear();
+    ks_val.clear();
+    for (int i = 0; i < m; ++i) {
+        for (auto &kv : rows[i]) {
+            if (kv.second == 0.0 && kv.first != i) continue;
+            ks_col.push_back(kv.first);
+            ks_val.push_back(kv.second);
+        }
+        ks_ptr.push_back((int32_t)ks_col.size());
+    }
+    return SIM_OK;
+}
+
+// --------------------------------------------------------------------------
+// Nested dissection: split a node set at the median of its longest rest-shape
+// extent, take the smaller one-sided boundary of the cut as the separator
+// (this also separates the bending 2-ring couplings), recurse on both sides,
+// and number the separator last.  Leaves of <= leaf_size nodes and the
+// separators become the (relaxed, dense) supernodes.
+// --------------------------------------------------------------------------
+namespace {
+
+struct NDCtx {
+    const std::vector<int32_t> *ptr, *col;
+    const std::vector<double> *X;
+    int leaf;
+    std::vector<int32_t> order;        // new -> old
+    std::vector<int32_t> sup_sizes;    // supernode sizes in elimination order
+    std::vector<int32_t> mark;         // scratch: 0 outside, 1 side A, 2 side B
+};
+
+void nd_rec(NDCtx &c, std::vector<int32_t> nodes) {
+    const int n = (int)nodes.size();
+    if (n == 0) return;
+    if (n <= c.leaf) {
+        std::sort(nodes.begin(), nodes.end());
+        for (int v : nodes) c.order.push_back(v);
+        c.sup_sizes.push_back(n);
+        return;
+    }
+    const auto &X = *c.X;
+    std::vector<int32_t> best_sep, best_A, best_B;
+    bool found = false;
+    for (int ax = 0; ax < 3; ++ax) {
+        std::vector<int32_t> sorted = nodes;
+        std::stable_sort(sorted.begin(), sorted.end(), [&](int a, int b) {
+            if (X[3 * a + ax] != X[3 * b + ax]) return X[3 * a + ax] < X[3 * b + ax];
+            return a < b;
+        });
+        const int half = n / 2;
+        for (int i = 0; i < n; ++i) c.mark[sorted[i]] = i < half ? 1 : 2;
+        std::vector<int32_t> bA, bB;
+        for (int v : nodes) {
+            bool cross = false;
+            for (int k = (*c.ptr)[v]; k < (*c.ptr)[v + 1]; ++k) {
+                int u = (*c.col)[k];
+                if (c.mark[u] != 0 && c.mark[u] != c.mark[v]) { cross = true; break; }
+            }
+            if (cross) (c.mark[v] == 1 ? bA : bB).push_back(v);
+        }
+        std::vector<int32_t> &sep = bA.size() <= bB.size() ? bA : bB;
+        for (int v : sep) c.mark[v] = 3;
+        std::vector<int32_t> A, B;
+        for (int v : nodes) {
+            if (c.mark[v] == 1) A.push_back(v);
+            else if (c.mark[v] == 2) B.push_back(v);
+        }
+        for (int v : nodes) c.mark[v] = 0;
+        if (A.empty() || B.empty() || sep.size() * 2 >= (size_t)n) continue;
+        if (!found || sep.size() < best_sep.size()) {
+            found = true;
+            best_sep = sep;
+            best_A = std::move(A);
+            best_B = std::move(B);
+        }
+    }
+    if (!found) {                                   // no useful cut
+        std::sort(nodes.begin(), nodes.end());
+        for (int v : nodes) c.order.push_back(v);
+        c.sup_sizes.push_back(n);
+        return;
+    }
+    std::vector<int32_t> &sep = best_sep, &A = best_A, &B = best_B;
+    nd_rec(c, A);
+    nd_rec(c, B);
+    std::sort(sep.begin(), sep.end());
+    for (int v : sep) c.order.push_back(v);
+    c.sup_sizes.push_back((int)sep.size());
+}
+
+}  // namespace
+
+int HostModel::order_and_factor(int leaf_size) {
+    // ---------------------------------------------------------------- ordering
+    NDCtx ctx;
+    ctx.ptr = &ks_ptr;
+    ctx.col = &ks_col;
+    ctx.X = &X;
+    ctx.leaf = std::max(4, leaf_size);
+    ctx.mark.assign(m, 0);
+    std::vector<int32_t> all(m);
+    std::iota(all.begin(), all.end(), 0);
+    nd_rec(ctx, all);
+    perm = ctx.order;
+    iperm.assign(m, -1);
+    for (int i = 0; i < m; ++i) iperm[perm[i]] = i;
+    ns = (int)ctx.sup_sizes.size();
+    sup_c0.assign(ns + 1, 0);
+    for (int s = 0; s < ns; ++s) sup_c0[s + 1] = sup_c0[s] + ctx.sup_sizes[s];
+    sup_of.assign(m, 0);
+    for (int s = 0; s < ns; ++s)
+        for (int c = sup_c0[s]; c < sup_c0[s + 1]; ++c) sup_of[c] = s;
+
+    // permuted lower pattern: for new column c, rows r > c adjacent to it
+    std::vector<std::vector<int32_t>> adj(m);
+    for (int oi = 0; oi < m; ++oi) {
+        int ci = iperm[oi];
+        for (int k = ks_ptr[oi]; k < ks_ptr[oi + 1]; ++k) {
+            int rj = iperm[ks_col[k]];
+            if (rj > ci) adj[ci].push_back(rj);
+        }
+    }
+
+    // ---------------------------------------------------------------- symbolic
+    std::vector<std::vector<int32_t>> pend(ns), R(ns);
+    std::vector<int32_t> parent(ns, -1);
+    std::vector<char> seen(m, 0);
+    for (int s = 0; s < ns; ++s) {
+        const int c0 = sup_c0[s], c1 = sup_c0[s + 1];
+        std::vector<int32_t> rs;
+        auto add = [&](int r) {
+            if (r >= c1 && !seen[r]) { seen[r] = 1; rs.push_back(r); }
+        };
+        for (int c = c0; c < c1; ++c)
+            for (int r : adj[c]) add(r);
+        for (int r : pend[s]) add(r);
+        for (int r : rs) seen[r] = 0;
+        std::sort(rs.begin(), rs.end());
+        R[s] = rs;
+        if (!rs.empty()) {
+            int p = sup_of[rs[0]];
+            parent[s] = p;
+            pend[p].insert(pend[p].end(), rs.begin(), rs.end());
+        }
+        pend[s].clear();
+        pend[s].shrink_to_fit();
+    }
+    R_ptr.assign(ns + 1, 0);
+    R_rows.clear();
+    for (int s = 0; s < ns; ++s) {
+        R_rows.insert(R_rows.end(), R[s].begin(), R[s].end());
+        R_ptr[s + 1] = (int32_t)R_rows.size();
+    }
+    sup_level.assign(ns, 0);
+    n_levels = 0;
+    for (int s = 0; s < ns; ++s) {                       // children precede parents
+        if (parent[s] >= 0) sup_level[parent[s]] = std::max(sup_level[parent[s]], sup_level[s] + 1);
+        n_levels = std::max(n_levels, sup_level[s] + 1);
+    }
+
+    // ---------------------------------------------------------------- numeric (left-looking, dense blocks)
+    Lblk.assign(ns, {});
+    std::vector<std::vector<int32_t>> updaters(ns);
+    std::vector<int32_t> rowpos(m, -1);
+    nnz_L = 0;
+    const double hh = h * h;
+    for (int s = 0; s < ns; ++s) {
+        const int c0 = sup_c0[s], c1 = sup_c0[s + 1], nsc = c1 - c0;
+        const int nR = (int)R[s].size(), nrow = nsc + nR;
+        std::vector<double> &F = Lblk[s];
+        F.assign((size_t)nrow * nsc, 0.0);
+        for (int c = c0; c < c1; ++c) rowpos[c] = c - c0;
+        for (int i = 0; i < nR; ++i) rowpos[R[s][i]] = nsc + i;
+        // assemble P_s columns c0..c1-1 (lower part)
+        for (int c = c0; c < c1; ++c) {
+            int oc = perm[c];
+            for (int k = ks_ptr[oc]; k < ks_ptr[oc + 1]; ++k) {
+                int r = iperm[ks_col[k]];
+                if (r < c) continue;
+                double v = hh * ks_val[k] + (r == c ? mass[oc] : 0.0);
+                F[(size_t)(c - c0) * nrow + rowpos[r]] += v;
+            }
+        }
+        // updates from descendants
+        for (int d : updaters[s]) {
+            const auto &Rd = R[d];
+            const int nsd = sup_c0[d + 1] - sup_c0[d], nrd = nsd + (int)Rd.size();
+            const auto &Ld = Lblk[d];
+            int i0 = (int)(std::lower_bound(Rd.begin(), Rd.end(), c0) - Rd.begin());
+            int i1 = (int)(std::lower_bound(Rd.begin(), Rd.end(), c1) - Rd.begin());
+            for (int j = i0; j < i1; ++j) {
+                const int colloc = Rd[j] - c0;
+                for (int i = j; i < (int)Rd.size(); ++i) {
+                    double acc = 0;
+                    for (int k = 0; k < nsd; ++k)
+                        acc += Ld[(size_t)k * nrd + nsd + i] * Ld[(size_t)k * nrd + nsd + j];
+                    F[(size_t)colloc * nrow + rowpos[Rd[i]]] -= acc;
+                }
+            }
+        }
+        // dense Cholesky of the diagonal block, then the off-diagonal rows
+        for (int k = 0; k < nsc; ++k) {
+            double dkk = F[(size_t)k * nrow + k];
+            for (int l = 0; l < k; ++l) dkk -= F[(size_t)l * nrow + k] * F[(size_t)l * nrow + k];
+            if (!(dkk > 0) || !std::isfinite(dkk)) {
+                error = "P is not positive definite";
+                return SIM_ENOTSPD;
+            }
+            const double lkk = std::sqrt(dkk);
+            F[(size_t)k * nrow + k] = lkk;
+            for (int i = k + 1; i < nrow; ++i) {
+                double v = F[(size_t)k * nrow + i];
+                for (int l = 0; l < k; ++l) v -= F[(size_t)l * nrow + i] * F[(size_t)l * nrow + k];
+                F[(size_t)k * nrow + i] = v / lkk;
+            }
+        }
+        for (int k = 0; k < nsc; ++k)
+            for (int i = 0; i < k; ++i) F[(size_t)k * nrow + i] = 0.0;
+        nnz_L += (int64_t)nsc * (nsc + 1) / 2 + (int64_t)nR * nsc;
+        for (int c = c0; c < c1; ++c) rowpos[c] = -1;
+        for (int i = 0; i < nR; ++i) rowpos[R[s][i]] = -1;
+        // register s as an updater of the supernodes its rows fall in
+        int last = -1;
+        for (int r : R[s]) {
+            int t = sup_of[r];
+            if (t != last) { updaters[t].push_back(s); last = t; }
+        }
+    }
+    return SIM_OK;
+}
+
+void HostModel::dense_L(double *out) const {
+    std::fill(out, out + (size_t)m * m, 0.0);
+    for (int s = 0; s < ns; ++s) {
+        const int c0 = sup_c0[s], nsc = sup_c0[s + 1] - c0;
+        const int nR = R_ptr[s + 1] - R_ptr[s], nrow = nsc + nR;
+        for (int k = 0; k < nsc; ++k) {
+            for (int i = k; i < nsc; ++i) out[(size_t)(c0 + i) * m + c0 + k] = Lblk[s][(size_t)k * nrow + i];
+            for (int i = 0; i < nR; ++i)
+                out[(size_t)R_rows[R_ptr[s] + i] * m + c0 + k] = Lblk[s][(size_t)k * nrow + nsc + i];
+        }
+    }
+}
+
+}  // namespace dc

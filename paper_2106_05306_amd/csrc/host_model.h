@@ -1,0 +1,69 @@
+// Host-side model of one cloth: constraint tables, the scalar PD matrix, its
+// nested-dissection ordering and supernodal Cholesky factor, and the level
+// schedule of the triangular solves.  Pure C++ (no HIP); built once per
+// handle and uploaded by the C ABI layer.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "diffcloth.h"
+
+namespace dc {
+
+struct HostModel {
+    // ------------------------------------------------------------ inputs
+    int m = 0;                              // nodes
+    std::vector<double> X;                  // [m*3] rest shape, caller order
+    std::vector<double> mass;               // [m]   caller order
+    double h = 0, g[3] = {0, 0, 0};
+    int pd_iters = 20, fwd_max_iters = 0, adj_max_iters = 500, precision = SIM_FP64;
+    double fwd_tol = 0, adj_tol = 1e-10;
+    int checkpoint_every = 0;
+    std::vector<sim_obstacle_t> obstacles;
+
+    // ------------------------------------------------------------ constraints
+    // All "norm" constraints (springs, then bending): A_c x = sum_k a_ck x_k,
+    // projection onto |p| = rho_c.  Canonical order: springs in edge order,
+    // then bending constraints by ascending centre node (caller ids).
+    int n_edges = 0, n_bend = 0, nc = 0;
+    std::vector<int32_t> edges;             // [n_edges*2]
+    std::vector<int32_t> bend_center;       // [n_bend] caller ids
+    std::vector<int32_t> c_ptr, c_node;     // stencil CSR, caller ids
+    std::vector<double> c_coef;
+    std::vector<double> rho, w, base_w, restdir;   // [nc], [nc], [nc], [nc*3]
+    std::vector<int32_t> region;            // [nc] or empty
+    std::vector<double> region_scale;
+    std::vector<int32_t> attach;            // caller ids
+    double w_att = 0, att_omega = 0, att_axis[3] = {0, 1, 0}, att_center[3] = {0, 0, 0};
+
+    // ------------------------------------------------------------ matrices (caller order)
+    // K_s = sum_c w_c a_c a_c^T + w_att sum_att e_j e_j^T ; P_s = diag(m) + h^2 K_s
+    std::vector<int32_t> ks_ptr, ks_col;    // CSR, full symmetric pattern
+    std::vector<double> ks_val;
+
+    // ------------------------------------------------------------ ordering
+    std::vector<int32_t> perm;              // perm[new] = old
+    std::vector<int32_t> iperm;             // iperm[old] = new
+
+    // ------------------------------------------------------------ supernodal factor (new order)
+    int ns = 0;                             // supernodes
+    std::vector<int32_t> sup_c0;            // [ns+1] column ranges
+    std::vector<int32_t> sup_of;            // [m] supernode of each column
+    std::vector<int32_t> R_ptr, R_rows;     // off-diagonal row structure of each supernode
+    std::vector<int32_t> sup_level;         // [ns]
+    int n_levels = 0;
+    std::vector<std::vector<double>> Lblk;  // per supernode, column-major (ns_s + nR_s) x ns_s
+    int64_t nnz_L = 0;
+
+    std::string error;
+
+    int build(const sim_mesh_t *mesh, const sim_params_t *p);   // SIM_OK or SIM_E*
+    int order_and_factor(int leaf_size);
+
+    // dense copy of L in the new order (tests; m small)
+    void dense_L(double *out) const;
+};
+
+}  // namespace dc

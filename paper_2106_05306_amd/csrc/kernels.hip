@@ -1,0 +1,901 @@
+// gfx950 kernels of the DiffCloth hot path.
+//
+// One workgroup of 1024 threads (16 wavefronts) owns one cloth handle for a
+// whole launch: it runs every time step of a forward segment (PD local/global
+// iterations with the contact update) or every adjoint step of a backward
+// segment without returning to the host.  A batched launch gives each handle
+// its own workgroup.  All vectors stay in HBM / L2; workgroup barriers order
+// the phases, so results do not depend on scheduling (no floating-point
+// atomics anywhere: every sum has a fixed order).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "sim_dev.h"
+
+namespace dc {
+
+constexpr uint8_t FREE = 0, TAKEOFF = 1, STICK = 2, SLIP = 3;
+
+// ------------------------------------------------------------------ reductions
+
+__device__ inline double team_sum(double v) {
+#pragma unroll
+    for (int o = kTeam / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kTeam);
+    return v;
+}
+
+// Block-wide max of a non-negative value; every thread gets the result.
+__device__ inline double block_max(double v, double *red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    const int wave = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[wave] = v;
+    __syncthreads();
+    double r = red[0];
+#pragma unroll
+    for (int w = 1; w < kBlock / 64; ++w) r = fmax(r, red[w]);
+    return r;
+}
+
+// Block-wide sum in a fixed order (wave butterflies, then waves 0..15).
+__device__ inline double block_sum(double v, double *red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int wave = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[wave] = v;
+    __syncthreads();
+    double r = red[0];
+#pragma unroll
+    for (int w = 1; w < kBlock / 64; ++w) r += red[w];
+    return r;
+}
+
+// ------------------------------------------------------------------ global solve
+// P v = b with P = P_s (x) I_3 = (L L^T) (x) I_3, three right-hand sides held
+// node-major.  Supernodes of one elimination-tree level are independent; each
+// level is two phases: a gather of the already-solved unknowns into the
+// level's rows, then the dense inverse diagonal block.  b is overwritten;
+// y is the forward-solve scratch; x receives the solution.
+__device__ void solve_P(const SimDev &S, double *__restrict__ b, double *__restrict__ y,
+                        double *__restrict__ x) {
+    const int team = threadIdx.x / kTeam, lane = threadIdx.x % kTeam;
+    constexpr int nteams = kBlock / kTeam;
+    for (int l = 0; l < S.n_levels; ++l) {
+        const int t0 = S.lvl_ptr[l], t1 = S.lvl_ptr[l + 1];
+        for (int t = t0 + team; t < t1; t += nteams) {
+            const int i = S.task_col[t];
+            double a0 = 0, a1 = 0, a2 = 0;
+            for (int p = S.lrow_ptr[i] + lane; p < S.lrow_ptr[i + 1]; p += kTeam) {
+                const int j = S.lrow_col[p];
+                const double L = S.lrow_val[p];
+                a0 += L * y[3 * j];
+                a1 += L * y[3 * j + 1];
+                a2 += L * y[3 * j + 2];
+            }
+            a0 = team_sum(a0); a1 = team_sum(a1); a2 = team_sum(a2);
+            if (lane == 0) { b[3 * i] -= a0; b[3 * i + 1] -= a1; b[3 * i + 2] -= a2; }
+        }
+        __syncthreads();
+        for (int t = t0 + team; t < t1; t += nteams) {
+            const int i = S.task_col[t], s = S.task_sup[t];
+            const int c0 = S.sup_c0[s], nsz = S.sup_ns[s], r = i - c0;
+            const double *Li = S.linv + S.sup_linv[s] + (int64_t)r * nsz;
+            double a0 = 0, a1 = 0, a2 = 0;
+            for (int k = lane; k <= r; k += kTeam) {
+                const double L = Li[k];
+                const int c = c0 + k;
+                a0 += L * b[3 * c];
+                a1 += L * b[3 * c + 1];
+                a2 += L * b[3 * c + 2];
+            }
+            a0 = team_sum(a0); a1 = team_sum(a1); a2 = team_sum(a2);
+            if (lane == 0) { y[3 * i] = a0; y[3 * i + 1] = a1; y[3 * i + 2] = a2; }
+        }
+        __syncthreads();
+    }
+    for (int l = S.n_levels - 1; l >= 0; --l) {
+        const int t0 = S.lvl_ptr[l], t1 = S.lvl_ptr[l + 1];
+        for (int t = t0 + team; t < t1; t += nteams) {
+            const int c = S.task_col[t], s = S.task_sup[t];
+            const int c0 = S.sup_c0[s], nsz = S.sup_ns[s];
+            const int r0 = S.sup_rptr[s], nR = S.sup_rptr[s + 1] - r0;
+            const double *B = S.bval + S.sup_boff[s] + (c - c0);
+            double a0 = 0, a1 = 0, a2 = 0;
+            for (int q = lane; q < nR; q += kTeam) {
+                const int r = S.sup_rows[r0 + q];
+                const double L = B[(int64_t)q * nsz];
+                a0 += L * x[3 * r];
+                a1 += L * x[3 * r + 1];
+                a2 += L * x[3 * r + 2];
+            }
+            a0 = team_sum(a0); a1 = team_sum(a1); a2 = team_sum(a2);
+            if (lane == 0) { y[3 * c] -= a0; y[3 * c + 1] -= a1; y[3 * c + 2] -= a2; }
+        }
+        __syncthreads();
+        for (int t = t0 + team; t < t1; t += nteams) {
+            const int c = S.task_col[t], s = S.task_sup[t];
+            const int c0 = S.sup_c0[s], nsz = S.sup_ns[s], r = c - c0;
+            const double *Lc = S.linv + S.sup_linv[s] + r;
+            double a0 = 0, a1 = 0, a2 = 0;
+            for (int k = r + lane; k < nsz; k += kTeam) {
+                const double L = Lc[(int64_t)k * nsz];
+                const int cc = c0 + k;
+                a0 += L * y[3 * cc];
+                a1 += L * y[3 * cc + 1];
+                a2 += L * y[3 * cc + 2];
+            }
+            a0 = team_sum(a0); a1 = team_sum(a1); a2 = team_sum(a2);
+            if (lane == 0) { x[3 * c] = a0; x[3 * c + 1] = a1; x[3 * c + 2] = a2; }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ geometry
+
+__device__ inline void contact_frame(const SimDev &S, int o, const double *xi, double *n, double &phi) {
+    const ObstacleDev &ob = S.obst[o];
+    if (ob.type == 0) {
+        n[0] = ob.n[0]; n[1] = ob.n[1]; n[2] = ob.n[2];
+        phi = (xi[0] - ob.p[0]) * n[0] + (xi[1] - ob.p[1]) * n[1] + (xi[2] - ob.p[2]) * n[2];
+    } else {
+        const double d0 = xi[0] - ob.p[0], d1 = xi[1] - ob.p[1], d2 = xi[2] - ob.p[2];
+        const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        n[0] = d0 / r; n[1] = d1 / r; n[2] = d2 / r;
+        phi = r - ob.radius;
+    }
+}
+
+__device__ inline double signed_distance(const ObstacleDev &ob, const double *y) {
+    if (ob.type == 0)
+        return (y[0] - ob.p[0]) * ob.n[0] + (y[1] - ob.p[1]) * ob.n[1] + (y[2] - ob.p[2]) * ob.n[2];
+    const double d0 = y[0] - ob.p[0], d1 = y[1] - ob.p[1], d2 = y[2] - ob.p[2];
+    return sqrt(d0 * d0 + d1 * d1 + d2 * d2) - ob.radius;
+}
+
+// attachment target of rest point X at time t: c + R(axis, omega t)(X - c)
+__device__ inline void attach_target(const SimDev &S, const double *X, double t, double *out) {
+    const double ang = S.att_omega * t, cs = cos(ang), sn = sin(ang);
+    const double *a = S.att_axis;
+    const double d0 = X[0] - S.att_center[0], d1 = X[1] - S.att_center[1], d2 = X[2] - S.att_center[2];
+    const double ad = a[0] * d0 + a[1] * d1 + a[2] * d2;
+    const double c0 = a[1] * d2 - a[2] * d1, c1 = a[2] * d0 - a[0] * d2, c2 = a[0] * d1 - a[1] * d0;
+    out[0] = S.att_center[0] + d0 * cs + c0 * sn + a[0] * ad * (1 - cs);
+    out[1] = S.att_center[1] + d1 * cs + c1 * sn + a[1] * ad * (1 - cs);
+    out[2] = S.att_center[2] + d2 * cs + c2 * sn + a[2] * ad * (1 - cs);
+}
+
+// Closed-form Signorini-Coulomb update of one node with isotropic response
+// v = ub + f/m; gap-corrected normal velocity.  Decisions in float64.
+__device__ inline uint8_t signorini_coulomb(const double *ub, const double *n, double phi, double mu,
+                                            double h, double mass, double *v, double *f) {
+    const double un = n[0] * ub[0] + n[1] * ub[1] + n[2] * ub[2];
+    const double a = un + phi / h;
+    if (a > 0.0) {
+        v[0] = ub[0]; v[1] = ub[1]; v[2] = ub[2];
+        f[0] = f[1] = f[2] = 0.0;
+        return TAKEOFF;
+    }
+    const double ut0 = ub[0] - un * n[0], ut1 = ub[1] - un * n[1], ut2 = ub[2] - un * n[2];
+    const double tau = sqrt(ut0 * ut0 + ut1 * ut1 + ut2 * ut2);
+    const double vn = -phi / h;
+    uint8_t md;
+    if (tau <= mu * (-a)) {
+        v[0] = vn * n[0]; v[1] = vn * n[1]; v[2] = vn * n[2];
+        md = STICK;
+    } else {
+        const double k = mu * a / tau;
+        v[0] = vn * n[0] + ut0 + k * ut0;
+        v[1] = vn * n[1] + ut1 + k * ut1;
+        v[2] = vn * n[2] + ut2 + k * ut2;
+        md = SLIP;
+    }
+    f[0] = mass * (v[0] - ub[0]);
+    f[1] = mass * (v[1] - ub[1]);
+    f[2] = mass * (v[2] - ub[2]);
+    return md;
+}
+
+// ------------------------------------------------------------------ forward
+
+// w_c p_c for every active constraint at x^k = x_n + h v^k (local step).
+template <bool MIXED>
+__device__ void local_projection(const SimDev &S, const double *__restrict__ vk) {
+    const double h = S.h;
+    for (int c = threadIdx.x; c < S.nca; c += kBlock) {
+        double q0 = 0, q1 = 0, q2 = 0;
+        for (int p = S.c_ptr[c]; p < S.c_ptr[c + 1]; ++p) {
+            const int j = S.c_node[p];
+            const double a = S.c_coef[p];
+            q0 += a * (S.x[3 * j] + h * vk[3 * j]);
+            q1 += a * (S.x[3 * j + 1] + h * vk[3 * j + 1]);
+            q2 += a * (S.x[3 * j + 2] + h * vk[3 * j + 2]);
+        }
+        double p0, p1, p2;
+        if (MIXED) {
+            const float f0 = (float)q0, f1 = (float)q1, f2 = (float)q2;
+            const float nq = sqrtf(f0 * f0 + f1 * f1 + f2 * f2);
+            const float rho = S.c_rhof[c], w = S.c_wf[c];
+            float r0, r1, r2;
+            if (nq < 1e-12f * rho) {
+                r0 = rho * (float)S.c_restdir[3 * c]; r1 = rho * (float)S.c_restdir[3 * c + 1];
+                r2 = rho * (float)S.c_restdir[3 * c + 2];
+            } else {
+                const float sc = rho / nq;
+                r0 = sc * f0; r1 = sc * f1; r2 = sc * f2;
+            }
+            p0 = (double)(w * r0); p1 = (double)(w * r1); p2 = (double)(w * r2);
+        } else {
+            const double nq = sqrt(q0 * q0 + q1 * q1 + q2 * q2);
+            const double rho = S.c_rho[c], w = S.c_w[c];
+            if (nq < 1e-12 * rho) {
+                p0 = w * rho * S.c_restdir[3 * c]; p1 = w * rho * S.c_restdir[3 * c + 1];
+                p2 = w * rho * S.c_restdir[3 * c + 2];
+            } else {
+                const double sc = w * rho / nq;
+                p0 = sc * q0; p1 = sc * q1; p2 = sc * q2;
+            }
+        }
+        S.wp[3 * c] = p0; S.wp[3 * c + 1] = p1; S.wp[3 * c + 2] = p2;
+    }
+}
+
+// Forward steps [step_begin, step_end) of one handle per workgroup.
+template <bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_forward(const SimDev *__restrict__ sims) {
+    const SimDev &S = sims[blockIdx.x];
+    __shared__ double red[kBlock / 64];
+    const int m = S.m;
+    const double h = S.h;
+    const bool converge = S.fwd_tol > 0;
+    int64_t iters_total = 0;
+    for (int n = S.step_begin; n < S.step_end; ++n) {
+        const int slot = n - S.rec_step0;
+        const double t1 = (n + 1) * h;
+        double *xrec = S.rec_x + (int64_t)slot * 3 * m;
+        double *vrec = S.rec_v + (int64_t)slot * 3 * m;
+        // predictor, detection on y, constant right-hand side, initial guess
+        for (int i = threadIdx.x; i < m; i += kBlock) {
+            const double xi[3] = {S.x[3 * i], S.x[3 * i + 1], S.x[3 * i + 2]};
+            const double vi[3] = {S.v[3 * i], S.v[3 * i + 1], S.v[3 * i + 2]};
+            if (n == S.step_begin) {
+                for (int d = 0; d < 3; ++d) { xrec[3 * i + d] = xi[d]; vrec[3 * i + d] = vi[d]; }
+            }
+            double y[3];
+            for (int d = 0; d < 3; ++d) y[d] = xi[d] + h * vi[d] + h * h * S.g[d];
+            double best = 0.0;
+            int ob = -1;
+            for (int o = 0; o < S.n_obst; ++o) {
+                const double phi = signed_distance(S.obst[o], y);
+                if (ob < 0 || phi < best) { best = phi; ob = o; }
+            }
+            const bool contact = ob >= 0 && best <= 0.0;
+            S.mode[i] = contact ? TAKEOFF : FREE;
+            S.cobst[i] = contact ? (int8_t)ob : (int8_t)-1;
+            double kx0 = 0, kx1 = 0, kx2 = 0;
+            for (int p = S.ks_ptr[i]; p < S.ks_ptr[i + 1]; ++p) {
+                const int j = S.ks_col[p];
+                const double kv = S.ks_val[p];
+                kx0 += kv * S.x[3 * j];
+                kx1 += kv * S.x[3 * j + 1];
+                kx2 += kv * S.x[3 * j + 2];
+            }
+            const double mi = S.mass[i];
+            double b[3] = {mi * vi[0] + h * mi * S.g[0] - h * kx0, mi * vi[1] + h * mi * S.g[1] - h * kx1,
+                           mi * vi[2] + h * mi * S.g[2] - h * kx2};
+            const int as = S.att_of[i];
+            if (as >= 0) {
+                double tg[3];
+                attach_target(S, S.att_rest + 3 * as, t1, tg);
+                for (int d = 0; d < 3; ++d) b[d] += h * S.w_att * tg[d];
+            }
+            for (int d = 0; d < 3; ++d) {
+                S.b0[3 * i + d] = b[d];
+                S.f[3 * i + d] = 0.0;
+                S.vk[3 * i + d] = vi[d] + h * S.g[d];
+            }
+        }
+        __syncthreads();
+        double *vk = S.vk, *vk1 = S.vk1;
+        int k = 0;
+        while (true) {
+            local_projection<MIXED>(S, vk);
+            __syncthreads();
+            for (int i = threadIdx.x; i < m; i += kBlock) {
+                double r0 = 0, r1 = 0, r2 = 0;
+                for (int p = S.inc_ptr[i]; p < S.inc_ptr[i + 1]; ++p) {
+                    const int c = S.inc_con[p];
+                    const double a = S.inc_coef[p];
+                    r0 += a * S.wp[3 * c];
+                    r1 += a * S.wp[3 * c + 1];
+                    r2 += a * S.wp[3 * c + 2];
+                }
+                S.rhs[3 * i] = S.b0[3 * i] + h * r0 + S.f[3 * i];
+                S.rhs[3 * i + 1] = S.b0[3 * i + 1] + h * r1 + S.f[3 * i + 1];
+                S.rhs[3 * i + 2] = S.b0[3 * i + 2] + h * r2 + S.f[3 * i + 2];
+            }
+            __syncthreads();
+            solve_P(S, S.rhs, S.ysol, vk1);
+            double dmax = 0.0;
+            for (int i = threadIdx.x; i < m; i += kBlock) {
+                if (S.mode[i] != FREE) {
+                    const double mi = S.mass[i];
+                    const double ub[3] = {vk1[3 * i] - S.f[3 * i] / mi, vk1[3 * i + 1] - S.f[3 * i + 1] / mi,
+                                          vk1[3 * i + 2] - S.f[3 * i + 2] / mi};
+                    double nrm[3], phi, vv[3], ff[3];
+                    contact_frame(S, S.cobst[i], S.x + 3 * i, nrm, phi);
+                    S.mode[i] = signorini_coulomb(ub, nrm, phi, S.obst[S.cobst[i]].mu, h, mi, vv, ff);
+                    for (int d = 0; d < 3; ++d) {
+                        vk1[3 * i + d] = vv[d];
+                        S.f[3 * i + d] = ff[d];
+                        S.ubar[3 * i + d] = ub[d];
+                    }
+                }
+                if (converge)
+                    for (int d = 0; d < 3; ++d) dmax = fmax(dmax, fabs(vk1[3 * i + d] - vk[3 * i + d]));
+            }
+            ++k;
+            double *tmp = vk; vk = vk1; vk1 = tmp;
+            if (converge) {
+                dmax = block_max(dmax, red);          // includes the barrier
+                if (!(dmax > S.fwd_tol) || k >= S.fwd_max_iters) break;
+            } else {
+                __syncthreads();
+                if (k >= S.K) break;
+            }
+        }
+        iters_total += k;
+        // advance and record
+        double *xn = xrec + 3 * m, *vn = vrec + 3 * m;
+        double *ubrec = S.rec_ubar + (int64_t)slot * 3 * m;
+        for (int i = threadIdx.x; i < m; i += kBlock) {
+            for (int d = 0; d < 3; ++d) {
+                const double vv = vk[3 * i + d];
+                const double xx = S.x[3 * i + d] + h * vv;
+                S.x[3 * i + d] = xx;
+                S.v[3 * i + d] = vv;
+                xn[3 * i + d] = xx;
+                vn[3 * i + d] = vv;
+                ubrec[3 * i + d] = S.ubar[3 * i + d];
+            }
+            S.rec_mode[(int64_t)slot * m + i] = S.mode[i];
+            S.rec_obst[(int64_t)slot * m + i] = S.cobst[i];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) S.counters[0] += iters_total;
+}
+
+// ------------------------------------------------------------------ adjoint
+
+// z = T^T zeta per node (T = I off contact / take-off, 0 for stick, the slip
+// block otherwise); also keeps zeta - z for the (P - M) term.
+__device__ inline void apply_TT(const SimDev &S, const uint8_t *mode, const double *zeta, double *z) {
+    for (int i = threadIdx.x; i < S.m; i += kBlock) {
+        const uint8_t md = mode[i];
+        const double a0 = zeta[3 * i], a1 = zeta[3 * i + 1], a2 = zeta[3 * i + 2];
+        if (md == FREE || md == TAKEOFF) {
+            z[3 * i] = a0; z[3 * i + 1] = a1; z[3 * i + 2] = a2;
+        } else if (md == STICK) {
+            z[3 * i] = 0.0; z[3 * i + 1] = 0.0; z[3 * i + 2] = 0.0;
+        } else {
+            const double *T = S.tblk + 9 * (int64_t)i;     // row-major T
+            z[3 * i] = T[0] * a0 + T[3] * a1 + T[6] * a2;
+            z[3 * i + 1] = T[1] * a0 + T[4] * a1 + T[7] * a2;
+            z[3 * i + 2] = T[2] * a0 + T[5] * a1 + T[8] * a2;
+        }
+    }
+}
+
+// u_c = G_c (A_c z) with G_c = s_c (I - qhat qhat^T) (the Delta P blocks)
+template <bool MIXED>
+__device__ inline void projection_jacobian_apply(const SimDev &S, const double *z, double *u, bool accumulate_dw,
+                                                 double h) {
+    for (int c = threadIdx.x; c < S.nca; c += kBlock) {
+        double a0 = 0, a1 = 0, a2 = 0;
+        for (int p = S.c_ptr[c]; p < S.c_ptr[c + 1]; ++p) {
+            const int j = S.c_node[p];
+            const double a = S.c_coef[p];
+            a0 += a * z[3 * j];
+            a1 += a * z[3 * j + 1];
+            a2 += a * z[3 * j + 2];
+        }
+        const double *qh = S.adj_q + 3 * c;
+        if (MIXED) {
+            const float sc = (float)S.adj_s[c];
+            const float q0 = (float)qh[0], q1 = (float)qh[1], q2 = (float)qh[2];
+            const float b0 = (float)a0, b1 = (float)a1, b2 = (float)a2;
+            const float qd = q0 * b0 + q1 * b1 + q2 * b2;
+            u[3 * c] = (double)(sc * (b0 - qd * q0));
+            u[3 * c + 1] = (double)(sc * (b1 - qd * q1));
+            u[3 * c + 2] = (double)(sc * (b2 - qd * q2));
+        } else {
+            const double sc = S.adj_s[c];
+            const double qd = qh[0] * a0 + qh[1] * a1 + qh[2] * a2;
+            u[3 * c] = sc * (a0 - qd * qh[0]);
+            u[3 * c + 1] = sc * (a1 - qd * qh[1]);
+            u[3 * c + 2] = sc * (a2 - qd * qh[2]);
+        }
+        if (accumulate_dw) {
+            const double *pq = S.adj_pq + 3 * c;
+            S.dw[S.c_id[c]] += h * (a0 * pq[0] + a1 * pq[1] + a2 * pq[2]);
+        }
+    }
+}
+
+// dL/dw for constraints without a local projection (flat bending): p = 0.
+__device__ inline void inactive_dw(const SimDev &S, const double *z, const double *x1, double h) {
+    for (int c = S.nca + threadIdx.x; c < S.nc_total; c += kBlock) {
+        double a0 = 0, a1 = 0, a2 = 0, q0 = 0, q1 = 0, q2 = 0;
+        for (int p = S.c_ptr[c]; p < S.c_ptr[c + 1]; ++p) {
+            const int j = S.c_node[p];
+            const double a = S.c_coef[p];
+            a0 += a * z[3 * j]; a1 += a * z[3 * j + 1]; a2 += a * z[3 * j + 2];
+            q0 += a * x1[3 * j]; q1 += a * x1[3 * j + 1]; q2 += a * x1[3 * j + 2];
+        }
+        S.dw[S.c_id[c]] -= h * (a0 * q0 + a1 * q1 + a2 * q2);
+    }
+}
+
+// r_i = g_i + sum_c a_ci u_c + h^2 (K_s d)_i, d = zeta - z (FP32 matrix values in mixed mode)
+template <bool MIXED>
+__device__ inline void adjoint_rhs(const SimDev &S, const double *gbar, const double *u, const double *zeta,
+                                   const double *z, double *r) {
+    const double hh = S.h * S.h;
+    for (int i = threadIdx.x; i < S.m; i += kBlock) {
+        double r0 = 0, r1 = 0, r2 = 0;
+        for (int p = S.inc_ptr[i]; p < S.inc_ptr[i + 1]; ++p) {
+            const int c = S.inc_con[p];
+            const double a = S.inc_coef[p];
+            r0 += a * u[3 * c]; r1 += a * u[3 * c + 1]; r2 += a * u[3 * c + 2];
+        }
+        double k0 = 0, k1 = 0, k2 = 0;
+        for (int p = S.ks_ptr[i]; p < S.ks_ptr[i + 1]; ++p) {
+            const int j = S.ks_col[p];
+            const double kv = MIXED ? (double)S.ks_valf[p] : S.ks_val[p];
+            k0 += kv * (zeta[3 * j] - z[3 * j]);
+            k1 += kv * (zeta[3 * j + 1] - z[3 * j + 1]);
+            k2 += kv * (zeta[3 * j + 2] - z[3 * j + 2]);
+        }
+        r[3 * i] = gbar[3 * i] + r0 + hh * k0;
+        r[3 * i + 1] = gbar[3 * i + 1] + r1 + hh * k1;
+        r[3 * i + 2] = gbar[3 * i + 2] + r2 + hh * k2;
+    }
+}
+
+// out = A v = M v + H T^T v with H = h^2 K_s - Delta P (the contact adjoint operator)
+template <bool MIXED>
+__device__ void apply_adjoint_operator(const SimDev &S, const uint8_t *mode, const double *vin, double *out) {
+    apply_TT(S, mode, vin, S.zt);
+    __syncthreads();
+    projection_jacobian_apply<MIXED>(S, S.zt, S.wp, false, S.h);
+    __syncthreads();
+    const double hh = S.h * S.h;
+    for (int i = threadIdx.x; i < S.m; i += kBlock) {
+        double r0 = 0, r1 = 0, r2 = 0;
+        for (int p = S.inc_ptr[i]; p < S.inc_ptr[i + 1]; ++p) {
+            const int c = S.inc_con[p];
+            const double a = S.inc_coef[p];
+            r0 += a * S.wp[3 * c]; r1 += a * S.wp[3 * c + 1]; r2 += a * S.wp[3 * c + 2];
+        }
+        double k0 = 0, k1 = 0, k2 = 0;
+        for (int p = S.ks_ptr[i]; p < S.ks_ptr[i + 1]; ++p) {
+            const int j = S.ks_col[p];
+            const double kv = MIXED ? (double)S.ks_valf[p] : S.ks_val[p];
+            k0 += kv * S.zt[3 * j]; k1 += kv * S.zt[3 * j + 1]; k2 += kv * S.zt[3 * j + 2];
+        }
+        const double mi = S.mass[i];
+        out[3 * i] = mi * vin[3 * i] + hh * k0 - r0;
+        out[3 * i + 1] = mi * vin[3 * i + 1] + hh * k1 - r1;
+        out[3 * i + 2] = mi * vin[3 * i + 2] + hh * k2 - r2;
+    }
+    __syncthreads();
+}
+
+// Block-wide dot products <V_k, w> for k = 0..nk-1 (fixed order); results in hk[0..nk).
+__device__ void block_dots(const double *V, int64_t ld, int nk, const double *w, int n3, double *red2, double *hk) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int k = 0; k < nk; ++k) {
+        const double *Vk = V + k * ld;
+        double p = 0.0;
+        for (int i = threadIdx.x; i < n3; i += kBlock) p += Vk[i] * w[i];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o, 64);
+        if (lane == 0) red2[wave * (kKryM + 1) + k] = p;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < nk; k += kBlock) {
+        double s = 0.0;
+        for (int wv = 0; wv < kBlock / 64; ++wv) s += red2[wv * (kKryM + 1) + k];
+        hk[k] = s;
+    }
+    __syncthreads();
+}
+
+// Restarted GMRES(kKryM), left-preconditioned by the prefactored P, for
+// (M + H T^T) zeta = gbar; fallback when the paper's fixed point stalls or
+// diverges.  Stops when |P^{-1}(gbar - A zeta)| <= tol |P^{-1} gbar|.
+// Returns the number of Krylov iterations, negative if the tolerance was missed.
+template <bool MIXED>
+__device__ int gmres_solve(const SimDev &S, const uint8_t *mode, const double *gbar, double *zeta, double tol,
+                           int max_iters, double *red) {
+    __shared__ double Hs[(kKryM + 1) * kKryM];
+    __shared__ double cs[kKryM], sn[kKryM], gv[kKryM + 1], yk[kKryM + 1];
+    __shared__ double red2[(kBlock / 64) * (kKryM + 1)];
+    __shared__ int flag[2];
+    const int n3 = 3 * S.m;
+    const int64_t ld = n3;
+    double *V = S.kry;
+    double beta0 = -1.0;
+    int total = 0;
+    for (int i = threadIdx.x; i < n3; i += kBlock) zeta[i] = 0.0;
+    __syncthreads();
+    while (true) {
+        // r = P^{-1}(gbar - A zeta)
+        apply_adjoint_operator<MIXED>(S, mode, zeta, S.rhs);
+        for (int i = threadIdx.x; i < n3; i += kBlock) S.rhs[i] = gbar[i] - S.rhs[i];
+        __syncthreads();
+        solve_P(S, S.rhs, S.ysol, V);
+        double ss = 0.0;
+        for (int i = threadIdx.x; i < n3; i += kBlock) ss += V[i] * V[i];
+        const double beta = sqrt(block_sum(ss, red));
+        if (beta0 < 0) beta0 = beta;
+        if (!(beta > tol * beta0) || !(beta == beta)) return (beta == beta) ? total : -total - 1;
+        if (total >= max_iters) return -total - 1;
+        for (int i = threadIdx.x; i < n3; i += kBlock) V[i] /= beta;
+        if (threadIdx.x == 0) {
+            gv[0] = beta;
+            for (int k = 1; k <= kKryM; ++k) gv[k] = 0.0;
+        }
+        __syncthreads();
+        int jdone = 0;
+        for (int j = 0; j < kKryM; ++j) {
+            double *w = V + (j + 1) * ld;
+            apply_adjoint_operator<MIXED>(S, mode, V + j * ld, S.rhs);
+            solve_P(S, S.rhs, S.ysol, w);
+            // classical Gram-Schmidt, twice
+            for (int pass = 0; pass < 2; ++pass) {
+                block_dots(V, ld, j + 1, w, n3, red2, yk);
+                for (int i = threadIdx.x; i < n3; i += kBlock) {
+                    double acc = w[i];
+                    for (int k = 0; k <= j; ++k) acc -= yk[k] * V[k * ld + i];
+                    w[i] = acc;
+                }
+                if (threadIdx.x == 0)
+                    for (int k = 0; k <= j; ++k) Hs[k * kKryM + j] = (pass ? Hs[k * kKryM + j] : 0.0) + yk[k];
+                __syncthreads();
+            }
+            double ws = 0.0;
+            for (int i = threadIdx.x; i < n3; i += kBlock) ws += w[i] * w[i];
+            const double hn = sqrt(block_sum(ws, red));
+            if (hn > 0)
+                for (int i = threadIdx.x; i < n3; i += kBlock) w[i] /= hn;
+            if (threadIdx.x == 0) {
+                // apply previous rotations to column j, then a new one
+                for (int k = 0; k < j; ++k) {
+                    const double a = Hs[k * kKryM + j], b = Hs[(k + 1) * kKryM + j];
+                    Hs[k * kKryM + j] = cs[k] * a + sn[k] * b;
+                    Hs[(k + 1) * kKryM + j] = -sn[k] * a + cs[k] * b;
+                }
+                const double a = Hs[j * kKryM + j], b = hn;
+                const double r = sqrt(a * a + b * b);
+                cs[j] = r > 0 ? a / r : 1.0;
+                sn[j] = r > 0 ? b / r : 0.0;
+                Hs[j * kKryM + j] = r;
+                Hs[(j + 1) * kKryM + j] = 0.0;
+                gv[j + 1] = -sn[j] * gv[j];
+                gv[j] = cs[j] * gv[j];
+                flag[0] = (fabs(gv[j + 1]) <= tol * beta0 || !(hn > 0)) ? 1 : 0;
+            }
+            __syncthreads();
+            ++total;
+            jdone = j + 1;
+            if (flag[0] || total >= max_iters) break;
+        }
+        // y = R^{-1} g, zeta += V y
+        if (threadIdx.x == 0) {
+            for (int k = jdone - 1; k >= 0; --k) {
+                double acc = gv[k];
+                for (int l = k + 1; l < jdone; ++l) acc -= Hs[k * kKryM + l] * yk[l];
+                yk[k] = acc / Hs[k * kKryM + k];
+            }
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < n3; i += kBlock) {
+            double acc = zeta[i];
+            for (int k = 0; k < jdone; ++k) acc += yk[k] * V[k * ld + i];
+            zeta[i] = acc;
+        }
+        __syncthreads();
+    }
+}
+
+// Backward over steps [step_begin, step_end) in reverse, one handle per workgroup.
+template <bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_backward(const SimDev *__restrict__ sims) {
+    const SimDev &S = sims[blockIdx.x];
+    __shared__ double red[kBlock / 64];
+    const int m = S.m;
+    const double h = S.h, hh = h * h;
+    int64_t iters_total = 0, gm_total = 0;
+    int noconv = 0;
+    double dmu_acc[kMaxObstacles];
+    for (int o = 0; o < kMaxObstacles; ++o) dmu_acc[o] = 0.0;
+    for (int n = S.step_end - 1; n >= S.step_begin; --n) {
+        const int slot = n - S.rec_step0;
+        const double *x0 = S.rec_x + (int64_t)slot * 3 * m;
+        const double *x1 = x0 + 3 * m;
+        const uint8_t *mode = S.rec_mode + (int64_t)slot * m;
+        const int8_t *obst = S.rec_obst + (int64_t)slot * m;
+        const double *ubr = S.rec_ubar + (int64_t)slot * 3 * m;
+        double *gbar = S.b0;
+        // projections and their Jacobians at x_{n+1}
+        for (int c = threadIdx.x; c < S.nca; c += kBlock) {
+            double q0 = 0, q1 = 0, q2 = 0;
+            for (int p = S.c_ptr[c]; p < S.c_ptr[c + 1]; ++p) {
+                const int j = S.c_node[p];
+                const double a = S.c_coef[p];
+                q0 += a * x1[3 * j]; q1 += a * x1[3 * j + 1]; q2 += a * x1[3 * j + 2];
+            }
+            const double nq = sqrt(q0 * q0 + q1 * q1 + q2 * q2);
+            const double rho = S.c_rho[c];
+            double p0, p1, p2, sc, qh0, qh1, qh2;
+            if (nq < 1e-12 * rho) {
+                p0 = rho * S.c_restdir[3 * c]; p1 = rho * S.c_restdir[3 * c + 1]; p2 = rho * S.c_restdir[3 * c + 2];
+                sc = 0.0; qh0 = qh1 = qh2 = 0.0;
+            } else {
+                qh0 = q0 / nq; qh1 = q1 / nq; qh2 = q2 / nq;
+                p0 = rho * qh0; p1 = rho * qh1; p2 = rho * qh2;
+                sc = hh * S.c_w[c] * rho / nq;
+            }
+            S.adj_s[c] = sc;
+            S.adj_q[3 * c] = qh0; S.adj_q[3 * c + 1] = qh1; S.adj_q[3 * c + 2] = qh2;
+            S.adj_pq[3 * c] = p0 - q0; S.adj_pq[3 * c + 1] = p1 - q1; S.adj_pq[3 * c + 2] = p2 - q2;
+        }
+        // gbar and the contact blocks T_j (slip)
+        for (int i = threadIdx.x; i < m; i += kBlock) {
+            for (int d = 0; d < 3; ++d) {
+                gbar[3 * i + d] = S.gv[3 * i + d] + h * S.gx[3 * i + d];
+                S.zeta[3 * i + d] = 0.0;
+            }
+            if (mode[i] == SLIP) {
+                double nrm[3], phi;
+                contact_frame(S, obst[i], x0 + 3 * i, nrm, phi);
+                const double *ub = ubr + 3 * i;
+                const double mu = S.obst[obst[i]].mu;
+                const double un = nrm[0] * ub[0] + nrm[1] * ub[1] + nrm[2] * ub[2];
+                const double a = un + phi / h;
+                double t[3] = {ub[0] - un * nrm[0], ub[1] - un * nrm[1], ub[2] - un * nrm[2]};
+                const double tau = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+                t[0] /= tau; t[1] /= tau; t[2] /= tau;
+                const double s = mu * (-a) / tau;
+                double *T = S.tblk + 9 * (int64_t)i;
+                for (int r = 0; r < 3; ++r)
+                    for (int c = 0; c < 3; ++c)
+                        T[3 * r + c] = (1 - s) * ((r == c ? 1.0 : 0.0) - nrm[r] * nrm[c]) + s * t[r] * t[c] +
+                                       mu * t[r] * nrm[c];
+            }
+        }
+        __syncthreads();
+        // fixed point zeta <- P^{-1}[gbar + dP z + (P - M)(zeta - z)], z = T^T zeta
+        double *zeta = S.zeta, *zeta1 = S.zeta1;
+        int k = 0;
+        bool ok = false, stalled = false;
+        double dprev = 0.0, d5 = 0.0;
+        int rising = 0;
+        while (k < S.adj_max_iters) {
+            apply_TT(S, mode, zeta, S.zt);
+            __syncthreads();
+            projection_jacobian_apply<MIXED>(S, S.zt, S.wp, false, h);
+            __syncthreads();
+            adjoint_rhs<MIXED>(S, gbar, S.wp, zeta, S.zt, S.rhs);
+            __syncthreads();
+            solve_P(S, S.rhs, S.ysol, zeta1);
+            double dmax = 0.0, zmax = 0.0;
+            for (int i = threadIdx.x; i < 3 * m; i += kBlock) {
+                dmax = fmax(dmax, fabs(zeta1[i] - zeta[i]));
+                zmax = fmax(zmax, fabs(zeta1[i]));
+            }
+            dmax = block_max(dmax, red);
+            zmax = block_max(zmax, red);
+            ++k;
+            double *tmp = zeta; zeta = zeta1; zeta1 = tmp;
+            if (!(dmax > S.adj_tol * zmax)) { ok = true; break; }
+            // divergence (3 rises in a row / non-finite) or a contraction too slow
+            // to reach the tolerance within the remaining budget -> fallback
+            rising = (dmax > dprev && k > 1) ? rising + 1 : 0;
+            dprev = dmax;
+            if (!(dmax == dmax) || dmax > 1e300 || rising >= 3) { stalled = true; break; }
+            if (k % 10 == 5) d5 = dmax;
+            if (k % 10 == 0 && k >= 20) {
+                const double rate = pow(dmax / d5, 0.2);
+                const double need = log(S.adj_tol * zmax / dmax) / log(rate);
+                if (!(rate < 1.0) || need > (double)(S.adj_max_iters - k)) { stalled = true; break; }
+            }
+        }
+        iters_total += k;
+        if (!ok) {
+            if (threadIdx.x == 0) S.counters[2] += 1;
+            const int it = gmres_solve<MIXED>(S, mode, gbar, S.zeta, S.adj_tol, S.adj_max_iters, red);
+            zeta = S.zeta;
+            if (it < 0) ++noconv;
+            gm_total += it < 0 ? -it - 1 : it;
+            (void)stalled;
+        }
+        // gradients of this step
+        apply_TT(S, mode, zeta, S.zt);
+        __syncthreads();
+        projection_jacobian_apply<MIXED>(S, S.zt, S.wp, true, h);
+        inactive_dw(S, S.zt, x1, h);
+        __syncthreads();
+        double dmu_local[kMaxObstacles];
+        for (int o = 0; o < kMaxObstacles; ++o) dmu_local[o] = 0.0;
+        const double *gstep = S.gx_steps ? S.gx_steps + (int64_t)n * 3 * m : nullptr;
+        for (int i = threadIdx.x; i < m; i += kBlock) {
+            const double *z = S.zt + 3 * i;
+            double r0 = 0, r1 = 0, r2 = 0;      // Delta P z
+            for (int p = S.inc_ptr[i]; p < S.inc_ptr[i + 1]; ++p) {
+                const int c = S.inc_con[p];
+                const double a = S.inc_coef[p];
+                r0 += a * S.wp[3 * c]; r1 += a * S.wp[3 * c + 1]; r2 += a * S.wp[3 * c + 2];
+            }
+            double k0 = 0, k1 = 0, k2 = 0;      // K_s z
+            for (int p = S.ks_ptr[i]; p < S.ks_ptr[i + 1]; ++p) {
+                const int j = S.ks_col[p];
+                const double kv = MIXED ? (double)S.ks_valf[p] : S.ks_val[p];
+                k0 += kv * S.zt[3 * j]; k1 += kv * S.zt[3 * j + 1]; k2 += kv * S.zt[3 * j + 2];
+            }
+            const double Hz[3] = {hh * k0 - r0, hh * k1 - r1, hh * k2 - r2};
+            const double mi = S.mass[i];
+            double dx[3];
+            for (int d = 0; d < 3; ++d) dx[d] = S.gx[3 * i + d] - Hz[d] / h;
+            const uint8_t md = mode[i];
+            if (md == STICK || md == SLIP) {
+                const int o = obst[i];
+                double nrm[3], phi;
+                contact_frame(S, o, x0 + 3 * i, nrm, phi);
+                const double lam[3] = {mi * zeta[3 * i], mi * zeta[3 * i + 1], mi * zeta[3 * i + 2]};
+                const double nl = nrm[0] * lam[0] + nrm[1] * lam[1] + nrm[2] * lam[2];
+                double dphi, dn[3];
+                if (md == STICK) {
+                    dphi = -nl / h;
+                    for (int d = 0; d < 3; ++d) dn[d] = -(phi / h) * lam[d];
+                } else {
+                    const double *ub = ubr + 3 * i;
+                    const double mu = S.obst[o].mu;
+                    const double un = nrm[0] * ub[0] + nrm[1] * ub[1] + nrm[2] * ub[2];
+                    const double a = un + phi / h;
+                    double t[3] = {ub[0] - un * nrm[0], ub[1] - un * nrm[1], ub[2] - un * nrm[2]};
+                    const double tau = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+                    t[0] /= tau; t[1] /= tau; t[2] /= tau;
+                    const double tl = t[0] * lam[0] + t[1] * lam[1] + t[2] * lam[2];
+                    dphi = (-nl + mu * tl) / h;
+                    dmu_local[o] += a * tl;
+                    // (dv/dn)^T lambda for v = -(phi/h) n + u_T + mu a t
+                    double El[3];
+                    for (int d = 0; d < 3; ++d) El[d] = (lam[d] - t[d] * tl) / tau;
+                    const double nE = nrm[0] * El[0] + nrm[1] * El[1] + nrm[2] * El[2];
+                    for (int d = 0; d < 3; ++d)
+                        dn[d] = -(phi / h) * lam[d] + (-un * lam[d] - ub[d] * nl) + mu * tl * ub[d] +
+                                mu * a * (-un * El[d] - ub[d] * nE);
+                }
+                for (int d = 0; d < 3; ++d) dx[d] += dphi * nrm[d];
+                if (S.obst[o].type == 1) {
+                    const double e0 = x0[3 * i] - S.obst[o].p[0], e1 = x0[3 * i + 1] - S.obst[o].p[1],
+                                 e2 = x0[3 * i + 2] - S.obst[o].p[2];
+                    const double r = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+                    const double ndn = nrm[0] * dn[0] + nrm[1] * dn[1] + nrm[2] * dn[2];
+                    for (int d = 0; d < 3; ++d) dx[d] += (dn[d] - ndn * nrm[d]) / r;
+                }
+            }
+            for (int d = 0; d < 3; ++d) {
+                S.gx[3 * i + d] = dx[d] + (gstep ? gstep[3 * i + d] : 0.0);
+                S.gv[3 * i + d] = mi * z[d];
+            }
+        }
+        for (int o = 0; o < S.n_obst; ++o) dmu_acc[o] += block_sum(dmu_local[o], red);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        for (int o = 0; o < S.n_obst; ++o) S.dmu[o] += dmu_acc[o];
+        S.counters[1] += iters_total;
+        S.counters[3] += noconv;
+        S.counters[4] += gm_total;
+    }
+}
+
+// ------------------------------------------------------------------ small helper kernels
+
+// out[perm[i]] = in[i] (new -> caller order) or out[i] = in[perm[i]] (caller -> new), 3 per node
+__global__ void k_permute3(const double *__restrict__ in, double *__restrict__ out, const int32_t *__restrict__ perm,
+                           int m, int to_caller) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const int o = perm[i];
+    if (to_caller) {
+        out[3 * o] = in[3 * i]; out[3 * o + 1] = in[3 * i + 1]; out[3 * o + 2] = in[3 * i + 2];
+    } else {
+        out[3 * i] = in[3 * o]; out[3 * i + 1] = in[3 * o + 1]; out[3 * i + 2] = in[3 * o + 2];
+    }
+}
+
+__global__ void k_modes_to_caller(const uint8_t *__restrict__ in, uint8_t *__restrict__ out,
+                                  const int32_t *__restrict__ perm, int m) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) out[perm[i]] = in[i];
+}
+
+// dregion[r] = sum_c base_w[c] dw[c] over constraints of region r (one workgroup)
+__global__ __launch_bounds__(kBlock) void k_region_grad(const double *__restrict__ dw, const double *__restrict__ base_w,
+                                                        const int32_t *__restrict__ region, int nc, int nreg,
+                                                        double *__restrict__ out) {
+    __shared__ double red[kBlock / 64];
+    for (int r = 0; r < nreg; ++r) {
+        double acc = 0.0;
+        for (int c = threadIdx.x; c < nc; c += kBlock)
+            if (region[c] == r) acc += base_w[c] * dw[c];
+        acc = block_sum(acc, red);
+        if (threadIdx.x == 0) out[r] = acc;
+    }
+}
+
+// bending gradients: dw_bend[center] = dw[n_edges + b]
+__global__ void k_scatter_bend(const double *__restrict__ dw, const int32_t *__restrict__ centers, int n_edges,
+                               int n_bend, double *__restrict__ out) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < n_bend) out[centers[b]] = dw[n_edges + b];
+}
+
+__global__ void k_fill(double *p, double v, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ------------------------------------------------------------------ launchers
+
+hipError_t launch_forward(const SimDev *d_sims, int n, bool mixed, hipStream_t st) {
+    if (mixed) hipLaunchKernelGGL(k_forward<true>, dim3(n), dim3(kBlock), 0, st, d_sims);
+    else hipLaunchKernelGGL(k_forward<false>, dim3(n), dim3(kBlock), 0, st, d_sims);
+    return hipGetLastError();
+}
+
+hipError_t launch_backward(const SimDev *d_sims, int n, bool mixed, hipStream_t st) {
+    if (mixed) hipLaunchKernelGGL(k_backward<true>, dim3(n), dim3(kBlock), 0, st, d_sims);
+    else hipLaunchKernelGGL(k_backward<false>, dim3(n), dim3(kBlock), 0, st, d_sims);
+    return hipGetLastError();
+}
+
+hipError_t launch_permute3(const double *in, double *out, const int32_t *perm, int m, bool to_caller, hipStream_t st) {
+    hipLaunchKernelGGL(k_permute3, dim3((m + 255) / 256), dim3(256), 0, st, in, out, perm, m, to_caller ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_modes(const uint8_t *in, uint8_t *out, const int32_t *perm, int m, hipStream_t st) {
+    hipLaunchKernelGGL(k_modes_to_caller, dim3((m + 255) / 256), dim3(256), 0, st, in, out, perm, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_region_grad(const double *dw, const double *base_w, const int32_t *region, int nc, int nreg,
+                              double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_region_grad, dim3(1), dim3(kBlock), 0, st, dw, base_w, region, nc, nreg, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_bend(const double *dw, const int32_t *centers, int n_edges, int n_bend, double *out,
+                               hipStream_t st) {
+    if (n_bend <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter_bend, dim3((n_bend + 255) / 256), dim3(256), 0, st, dw, centers, n_edges, n_bend, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(double *p, double v, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+}  // namespace dc

@@ -1,0 +1,102 @@
+// Device-side descriptor of one cloth handle.  Every array lives in HBM and
+// uses the nested-dissection node order ("new" order); vectors of 3D
+// quantities are node-major [node][xyz].  One workgroup owns one handle for
+// the duration of a launch, so work buffers are private to it.
+#pragma once
+
+#include <cstdint>
+
+namespace dc {
+
+constexpr int kMaxObstacles = 8;
+constexpr int kBlock = 1024;         // threads per workgroup (16 wavefronts)
+constexpr int kTeam = 8;             // lanes cooperating on one solve row / column
+constexpr int kKryM = 60;            // GMRES restart length of the adjoint fallback
+
+struct ObstacleDev {
+    int type;                         // 0 plane, 1 sphere
+    double p[3], n[3], radius, mu;
+};
+
+struct SimDev {
+    // ---------------------------------------------------------------- sizes, parameters
+    int m;                            // nodes
+    int nca;                          // active norm constraints (springs + curved bending)
+    int nc_total;                     // all norm constraints (canonical numbering)
+    int n_obst, na;
+    int K, fwd_max_iters, adj_max_iters, mixed;
+    double h, fwd_tol, adj_tol;
+    double g[3];
+    double w_att, att_omega, att_axis[3], att_center[3];
+    ObstacleDev obst[kMaxObstacles];
+
+    // ---------------------------------------------------------------- static tables
+    const double *mass;               // [m]
+    const int32_t *ks_ptr, *ks_col;   // K_s CSR (new order)
+    const double *ks_val;             // float64 values
+    const float *ks_valf;             // float32 copy (residual SpMV in mixed precision)
+    const int32_t *c_ptr, *c_node;    // active-constraint stencils (new node ids)
+    const double *c_coef;
+    const double *c_rho, *c_w, *c_restdir;   // [nca], [nca], [nca*3]
+    const float *c_rhof, *c_wf;
+    const int32_t *c_id;              // canonical index of each active constraint
+    const int32_t *inc_ptr, *inc_con; // node -> active constraint incidence
+    const double *inc_coef;
+    const int32_t *att_node;          // [na] new ids
+    const int32_t *att_of;            // [m] attachment slot or -1
+    const double *att_rest;           // [na*3] rest positions (caller coordinates)
+
+    // supernodal factor of P_s (new order)
+    int n_levels;
+    const int32_t *lvl_ptr;           // [n_levels+1] ranges into the task arrays
+    const int32_t *task_col;          // column handled by a task
+    const int32_t *task_sup;          // its supernode
+    const int32_t *sup_c0, *sup_ns;   // [n_sup]
+    const int64_t *sup_linv;          // offset of the dense inverse diagonal block (ns x ns, row-major)
+    const int64_t *sup_boff;          // offset of the off-diagonal block (nR x ns, row-major)
+    const int32_t *sup_rptr;          // [n_sup+1] into sup_rows
+    const int32_t *sup_rows;          // off-diagonal row structure
+    const double *linv;
+    const double *bval;
+    const int32_t *lrow_ptr, *lrow_col;   // strictly-lower off-supernode rows (forward gather)
+    const double *lrow_val;
+
+    // ---------------------------------------------------------------- state and work
+    double *x, *v;                    // state x_n, v_n
+    double *vk, *vk1;                 // PD iterates
+    double *b0, *rhs, *ysol;          // constant rhs, rhs / gather scratch, forward-solve result
+    double *f;                        // contact impulse h J^T r per node
+    double *wp;                       // [nca*3] w_c p_c (forward) / projection-Jacobian products (adjoint)
+    uint8_t *mode;                    // [m] contact mode of the current step
+    int8_t *cobst;                    // [m] obstacle of contact nodes
+    double *ubar;                     // [m*3] free velocity of the last contact update
+    double *red;                      // [64] reduction scratch (per workgroup)
+
+    // step records: slot s holds step (rec_step0 + s)
+    double *rec_x;                    // [(cap+1) * m*3]: x at step rec_step0 + s
+    double *rec_v;                    // [(cap+1) * m*3]
+    double *rec_ubar;                 // [cap * m*3]
+    uint8_t *rec_mode;                // [cap * m]
+    int8_t *rec_obst;                 // [cap * m]
+    int rec_cap;
+
+    // adjoint buffers
+    double *gx, *gv;                  // dL/dx_{n+1}, dL/dv_{n+1} -> dL/dx_n, dL/dv_n
+    double *zeta, *zeta1, *zt;        // iterate, next iterate, T^T zeta
+    double *adj_s, *adj_q;            // [nca], [nca*3] projection-Jacobian scale and direction at x_{n+1}
+    double *adj_pq;                   // [nca*3] p - q at x_{n+1}
+    double *tblk;                     // [m*9] T_j blocks (contact nodes)
+    double *dw;                       // [nc_total] accumulated weight gradients (canonical)
+    double *dmu;                      // [kMaxObstacles]
+    const double *gx_steps;           // optional per-step dL/dx_n [(T+1)*m*3], new order
+
+    // Krylov fallback workspace (GMRES)
+    double *kry;                      // [(kKryM+1) * m*3] Krylov basis
+
+    // run control for one launch
+    int step_begin, step_end;         // forward: steps [begin, end); backward: reverse
+    int rec_step0;                    // step number of record slot 0
+    int64_t *counters;                // [8]: fwd iters, adj iters, fallbacks, noconv, Krylov iters
+};
+
+}  // namespace dc
