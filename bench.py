@@ -1,0 +1,230 @@
+#!/usr/bin/env python3
+"""Forward+adjoint cloth steps/s on the 40x40-node sphere-drop workload (4800 DoF).
+
+One benchmark step is one whole rollout of the hot path: 200 implicit-Euler
+steps forward (PD local/global iterations with the dry-friction contact
+update, K = 20 per step) followed by the 200 adjoint steps back to the
+initial state.  ``value`` counts cloth time steps (forward + adjoint pairs)
+per second of wall clock with inputs resident in HBM.
+
+Prints one JSON line.  Extra objects:
+  roofline      -- the dominant kernel's algorithmic bytes per launch / its
+                   average launch time (HIP events on the kernel's stream),
+                   against MI355X HBM3E peak 8 TB/s; traffic from the
+                   committed rocprofv3 counter summary when it matches the
+                   current kernel source, else null;
+  cpu_baseline  -- the FP64 CPU oracle timed on a bounded sample of the same
+                   workload (sampled steps of the rollout redone from the GPU's
+                   recorded states, forward + direct-solve adjoint), one thread;
+  error_vs_oracle -- max one-step position error of the GPU path (bench
+                   precision) against the oracle over that sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_2106_05306_amd", "csrc", "kernels.hip")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "sphere_drop40_pmc.txt")
+
+
+def source_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_from_profile(kernel_name):
+    """HBM bytes per launch from the committed PMC summary, if it was taken on
+    the current kernel source (else None)."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    txt = open(PMC_SUMMARY).read()
+    m = re.search(r"kernel_source_sha256_16:\s*(\w+)", txt)
+    if not m or m.group(1) != source_hash():
+        return None
+    m = re.search(kernel_name + r"_hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    return float(m.group(1)) if m else None
+
+
+def algorithmic_bytes(st, m, E, C_steps, K, T, adj_iters):
+    """Bytes the method must move (per launch), from the per-unit figures:
+    per PD iteration 2 nnz(L) 12 + 4 (3m 8) + E 16 + m 12 + C 48;
+    per forward step K x that + nnz(P) 12 + m 24;
+    per adjoint iteration 2 nnz(L) 12 + nnz(P) 12 + E 16 + 6 (3m 8) + C 72."""
+    nnzL, nnzP = st["nnz_L"], st["nnz_P"]
+    C_tot = float(sum(C_steps))
+    per_iter = 2 * nnzL * 12 + 4 * 3 * m * 8 + E * 16 + m * 12
+    fwd = T * (K * per_iter + nnzP * 12 + m * 24) + K * C_tot * 48
+    per_adj = 2 * nnzL * 12 + nnzP * 12 + E * 16 + 6 * 3 * m * 8
+    C_avg = C_tot / max(T, 1)
+    bwd = adj_iters * (per_adj + C_avg * 72)
+    return fwd, bwd
+
+
+def cpu_baseline(sim, sc, sample_at):
+    """Oracle (FP64, one thread) on a bounded sample of the same rollout: for
+    each sampled step n it redoes the forward step from the GPU's recorded
+    state (K=20 PD iterations with contact) and its adjoint step (direct
+    solve).  Returns steps/s and the max position error of the GPU step."""
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except Exception:                                   # pragma: no cover
+        pass
+    import numpy as np
+
+    from oracle import diffcloth_oracle as O
+    model = O.Model(sc)
+    rng = np.random.default_rng(0)
+    err, dt = 0.0, 0.0
+    for n in sample_at:
+        x, v = sim.state(n)
+        x1g, _ = sim.state(n + 1)
+        x, v, x1g = x.cpu().numpy(), v.cpu().numpy(), x1g.cpu().numpy()
+        gx, gv = rng.normal(size=(2,) + x.shape)
+        t0 = time.perf_counter()
+        rec = O.forward_step(model, x, v, n)
+        O.backward_step(model, rec, gx, gv, n)
+        dt += time.perf_counter() - t0
+        err = max(err, float(np.abs(rec.x1 - x1g).max()))
+    return len(sample_at) / dt, dt, err
+
+
+def copy_probe(nbytes):
+    """A plain device copy of known size (calibrates the HBM byte counters)."""
+    import torch
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": nbytes}))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3, help="timed rollouts")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed rollouts")
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--adj-tol", type=float, default=1e-4)
+    ap.add_argument("--adj-max-iters", type=int, default=100)
+    ap.add_argument("--cpu-sample", default="10,40,70,100,130,160,190",
+                    help="steps of the rollout the CPU oracle redoes (forward + adjoint)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, help="only run a device copy of this many bytes")
+    args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU: one rollout per workgroup, "
+                                   "no collectives; run with --gpus 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import scenes
+    from paper_2106_05306_amd.sim import Sim
+
+    dev = torch.device("cuda:0")
+    sc = scenes.c2_sphere_drop(0)
+    T, K = sc.steps, sc.pd_iters
+    sim = Sim.from_scene(sc, device=dev, precision=args.precision, adj_tol=args.adj_tol,
+                         adj_max_iters=args.adj_max_iters)
+    st = sim.stats()
+    target = torch.tensor(sc.target, device=dev)
+    stream = sim.stream
+    fwd_stats = {}
+
+    def rollout(events=None):
+        if events:
+            events[0].record(stream)
+        xT, vT, _ = sim.forward(T)
+        fwd_stats.update(sim.stats())
+        if events:
+            events[1].record(stream)
+        g = (2.0 / sc.n_nodes) * (xT.mean(dim=0) - target).expand_as(xT).contiguous()  # centroid loss
+        if events:
+            events[2].record(stream)
+        out = sim.backward(g)
+        if events:
+            events[3].record(stream)
+        return out
+
+    for _ in range(args.warmup):
+        rollout()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for e in evs:
+        out = rollout(e)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    fwd_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    bwd_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
+    st = sim.stats()
+    fwd_iters = fwd_stats["fwd_iters_total"]
+    C_steps = [int(np.count_nonzero(sim.modes(n))) for n in range(T)]
+    adj_iters = st["adj_iters_total"] + st["adj_krylov_total"]
+    fwd_b, bwd_b = algorithmic_bytes(st, sc.n_nodes, st["n_edges"], C_steps, K, T, adj_iters)
+    if bwd_ms > fwd_ms:
+        kname, nbytes, ms = "k_backward", bwd_b, bwd_ms
+    else:
+        kname, nbytes, ms = "k_forward", fwd_b, fwd_ms
+    achieved = nbytes / (ms * 1e-3) / 1e9
+    traffic = traffic_from_profile(kname)
+    value = args.steps * T / elapsed
+
+    result = {
+        "metric": "forward+adjoint cloth steps/sec at 4800 DoF",
+        "value": value,
+        "unit": "cloth steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": "sphere_drop 40x40 nodes (4800 DoF), 1 m cloth onto a 0.25 m sphere, "
+                               "200 steps h=1/120, K=20 PD iterations/step, forward + adjoint "
+                               "(one benchmark step = one rollout)",
+                   "precision": args.precision, "adj_tol": args.adj_tol, "adj_max_iters": args.adj_max_iters,
+                   "seed": 0},
+        "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "algorithmic_bytes_per_launch": nbytes, "launch_ms": ms},
+        "timing_ms": {"forward_launch": fwd_ms, "backward_launch": bwd_ms},
+        "solver": {"pd_iters_per_rollout": fwd_iters, "adj_fixed_point_iters": st["adj_iters_total"],
+                   "adj_krylov_iters": st["adj_krylov_total"], "adj_fallback_steps": st["adj_fallbacks"],
+                   "adj_unconverged_steps": st["adj_noconv"], "nnz_L": st["nnz_L"], "nnz_P": st["nnz_P"],
+                   "levels": st["n_levels"], "lds_forward": st["lds_forward"],
+                   "contact_nodes_mean": float(np.mean(C_steps))},
+    }
+    if not args.no_cpu_baseline:
+        sample = [int(v) for v in args.cpu_sample.split(",")]
+        rate, dt, err = cpu_baseline(sim, sc, sample)
+        result["cpu_baseline"] = {"value": rate, "unit": "cloth steps/s", "cores": 1, "kind": "oracle",
+                                  "sample": f"forward (K=20, contact) + direct-solve adjoint of steps {sample} "
+                                            f"of the same rollout, redone from the GPU's recorded states, "
+                                            f"FP64 NumPy/SciPy, {dt:.1f} s"}
+        result["error_vs_oracle"] = {"step_positions_max_abs_m": err, "steps_compared": sample,
+                                     "precision": args.precision,
+                                     "note": "one step from the same state; the 20-iteration forward is "
+                                             "chaotic over whole rollouts"}
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -158,6 +158,8 @@ typedef struct {
     int32_t adj_noconv;             /* steps that missed the tolerance          */
     int64_t device_bytes;           /* device memory held by the handle         */
     int64_t adj_krylov_total;       /* GMRES iterations of the fallback         */
+    int64_t factor_bytes;           /* bytes of the stacked factor blocks       */
+    int64_t lds_forward, lds_backward; /* dynamic LDS per workgroup (0: vectors in HBM) */
 } sim_stats_t;
 
 typedef void *(*sim_alloc_fn)(size_t bytes, void *ctx);

@@ -10,7 +10,7 @@ from ctypes import (CFUNCTYPE, POINTER, Structure, c_double, c_int32, c_int64, c
                     c_void_p, c_char_p)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libdiffcloth.so")
+LIB_PATH = os.environ.get("DIFFCLOTH_LIB", os.path.join(HERE, "libdiffcloth.so"))
 
 SIM_OK, SIM_EINVAL, SIM_ENOTSPD, SIM_ENOMEM, SIM_ENONFINITE, SIM_ESTATE, SIM_EHIP = 0, -1, -2, -3, -4, -5, -6
 SIM_WADJ_FALLBACK, SIM_WADJ_NOCONV = 1, 2
@@ -52,7 +52,8 @@ class SimStats(Structure):
                 ("n_constraints_active", c_int32), ("nnz_P", c_int64), ("nnz_L", c_int64),
                 ("n_supernodes", c_int32), ("n_levels", c_int32), ("steps_recorded", c_int32),
                 ("fwd_iters_total", c_int64), ("adj_iters_total", c_int64), ("adj_fallbacks", c_int32),
-                ("adj_noconv", c_int32), ("device_bytes", c_int64), ("adj_krylov_total", c_int64)]
+                ("adj_noconv", c_int32), ("device_bytes", c_int64), ("adj_krylov_total", c_int64),
+                ("factor_bytes", c_int64), ("lds_forward", c_int64), ("lds_backward", c_int64)]
 
 
 ALLOC_FN = CFUNCTYPE(c_void_p, c_size_t, c_void_p)

@@ -13,8 +13,10 @@
 #include "sim_dev.h"
 
 namespace dc {
-hipError_t launch_forward(const SimDev *d_sims, int n, bool mixed, hipStream_t st);
-hipError_t launch_backward(const SimDev *d_sims, int n, bool mixed, hipStream_t st);
+hipError_t launch_forward(const SimDev *d_sims, int n, bool mixed, size_t lds, hipStream_t st);
+hipError_t launch_backward(const SimDev *d_sims, int n, bool mixed, size_t lds, hipStream_t st);
+hipError_t configure_lds(size_t fwd_bytes, size_t bwd_bytes);
+hipError_t kernel_static_lds(size_t *fwd, size_t *bwd);
 hipError_t launch_permute3(const double *in, double *out, const int32_t *perm, int m, bool to_caller, hipStream_t st);
 hipError_t launch_modes(const uint8_t *in, uint8_t *out, const int32_t *perm, int m, hipStream_t st);
 hipError_t launch_region_grad(const double *dw, const double *base_w, const int32_t *region, int nc, int nreg,
@@ -51,6 +53,8 @@ struct sim {
     int T = -1;                         // steps of the recorded rollout (-1: none)
     int64_t counters_host[8] = {0};
     int nca = 0;
+    int64_t factor_bytes = 0;
+    size_t lds_fwd = 0, lds_bwd = 0;   // dynamic LDS of the two kernels
 };
 
 namespace {
@@ -207,21 +211,22 @@ void build_device(sim *s) {
     D.att_node = upload(s, an);
     D.att_of = upload(s, aof);
     D.att_rest = upload(s, arest);
-    // supernodal factor: inverse diagonal blocks, off-diagonal blocks, row gathers, levels
+    // supernodal factor, stacked per supernode as G_s = [L_ss^{-1}; B_s L_ss^{-1}]
+    // (column-major (ns + nR) x ns), with B_s = L(R_s, s) the off-diagonal block:
+    //   forward  y_s = L_ss^{-1} t_s and u_s = B_s y_s = (B_s L_ss^{-1}) t_s in one product,
+    //   backward x_s = L_ss^{-T} y_s - (B_s L_ss^{-1})^T x_{R_s}.
     const int ns = hm.ns;
-    std::vector<int32_t> sc0(ns), sns(ns), rptr(ns + 1, 0), rows;
-    std::vector<int64_t> slinv(ns), sboff(ns);
-    std::vector<double> linv, bval;
-    std::vector<std::vector<std::pair<int, double>>> lrow(m);
+    std::vector<int32_t> sc0(ns), sns(ns), snr(ns), rptr(ns + 1, 0), rows, uoff(ns + 1, 0);
+    std::vector<int64_t> goff(ns);
+    std::vector<double> gval;
     for (int sn = 0; sn < ns; ++sn) {
         const int c0 = hm.sup_c0[sn], nsz = hm.sup_c0[sn + 1] - c0;
         const int nR = hm.R_ptr[sn + 1] - hm.R_ptr[sn], nrow = nsz + nR;
-        const std::vector<double> &F = hm.Lblk[sn];
+        const std::vector<double> &F = hm.Lblk[sn];       // column-major nrow x nsz, L_ss on top
         sc0[sn] = c0;
         sns[sn] = nsz;
-        // inverse of the lower-triangular diagonal block, row-major
-        slinv[sn] = (int64_t)linv.size();
-        std::vector<double> inv((size_t)nsz * nsz, 0.0);
+        snr[sn] = nR;
+        std::vector<double> inv((size_t)nsz * nsz, 0.0);   // row-major L_ss^{-1}
         for (int j = 0; j < nsz; ++j) {
             for (int i = j; i < nsz; ++i) {
                 double acc = i == j ? 1.0 : 0.0;
@@ -229,48 +234,60 @@ void build_device(sim *s) {
                 inv[(size_t)i * nsz + j] = acc / F[(size_t)i * nrow + i];
             }
         }
-        linv.insert(linv.end(), inv.begin(), inv.end());
-        sboff[sn] = (int64_t)bval.size();
-        for (int q = 0; q < nR; ++q) {
-            const int r = hm.R_rows[hm.R_ptr[sn] + q];
-            rows.push_back(r);
-            for (int k = 0; k < nsz; ++k) {
-                const double val = F[(size_t)k * nrow + nsz + q];
-                bval.push_back(val);
-                lrow[r].push_back({c0 + k, val});
+        goff[sn] = (int64_t)gval.size();
+        gval.resize(gval.size() + (size_t)nrow * nsz, 0.0);
+        double *G = gval.data() + goff[sn];
+        for (int k = 0; k < nsz; ++k) {
+            for (int r = k; r < nsz; ++r) G[(size_t)k * nrow + r] = inv[(size_t)r * nsz + k];
+            for (int q = 0; q < nR; ++q) {
+                double acc = 0.0;
+                for (int j = k; j < nsz; ++j) acc += F[(size_t)j * nrow + nsz + q] * inv[(size_t)j * nsz + k];
+                G[(size_t)k * nrow + nsz + q] = acc;
             }
         }
+        for (int q = 0; q < nR; ++q) rows.push_back(hm.R_rows[hm.R_ptr[sn] + q]);
         rptr[sn + 1] = (int32_t)rows.size();
+        uoff[sn + 1] = uoff[sn] + 3 * nR;
     }
-    std::vector<int32_t> lp(1, 0), lc;
-    std::vector<double> lv;
+    // per column: the update-vector entries it gathers in the forward solve (ascending supernode)
+    std::vector<std::vector<int32_t>> upd(m);
+    for (int sn = 0; sn < ns; ++sn)
+        for (int q = 0; q < snr[sn]; ++q) upd[rows[rptr[sn] + q]].push_back(uoff[sn] + 3 * q);
+    std::vector<int32_t> up(1, 0), uo;
     for (int i = 0; i < m; ++i) {
-        std::sort(lrow[i].begin(), lrow[i].end());
-        for (auto &pr : lrow[i]) { lc.push_back(pr.first); lv.push_back(pr.second); }
-        lp.push_back((int32_t)lc.size());
+        uo.insert(uo.end(), upd[i].begin(), upd[i].end());
+        up.push_back((int32_t)uo.size());
     }
-    std::vector<int32_t> lvl(hm.n_levels + 1, 0), tcol, tsup;
+    // level lists: the columns of each level, and the (supernode, stacked row) items
+    std::vector<int32_t> lrp(hm.n_levels + 1, 0), lrows, lip(hm.n_levels + 1, 0), isup, irow;
     for (int l = 0; l < hm.n_levels; ++l) {
-        for (int sn = 0; sn < ns; ++sn)
-            if (hm.sup_level[sn] == l)
-                for (int c = hm.sup_c0[sn]; c < hm.sup_c0[sn + 1]; ++c) { tcol.push_back(c); tsup.push_back(sn); }
-        lvl[l + 1] = (int32_t)tcol.size();
+        for (int sn = 0; sn < ns; ++sn) {
+            if (hm.sup_level[sn] != l) continue;
+            for (int c = sc0[sn]; c < sc0[sn] + sns[sn]; ++c) lrows.push_back(c);
+            for (int r = 0; r < sns[sn] + snr[sn]; ++r) { isup.push_back(sn); irow.push_back(r); }
+        }
+        lrp[l + 1] = (int32_t)lrows.size();
+        lip[l + 1] = (int32_t)isup.size();
     }
     D.n_levels = hm.n_levels;
-    D.lvl_ptr = upload(s, lvl);
-    D.task_col = upload(s, tcol);
-    D.task_sup = upload(s, tsup);
+    D.lvl_rows_ptr = upload(s, lrp);
+    D.lvl_rows = upload(s, lrows);
+    D.lvl_items_ptr = upload(s, lip);
+    D.item_sup = upload(s, isup);
+    D.item_row = upload(s, irow);
+    D.sup_of = upload(s, hm.sup_of);
     D.sup_c0 = upload(s, sc0);
     D.sup_ns = upload(s, sns);
-    D.sup_linv = upload(s, slinv);
-    D.sup_boff = upload(s, sboff);
+    D.sup_nr = upload(s, snr);
+    D.sup_goff = upload(s, goff);
     D.sup_rptr = upload(s, rptr);
     D.sup_rows = upload(s, rows);
-    D.linv = upload(s, linv);
-    D.bval = upload(s, bval);
-    D.lrow_ptr = upload(s, lp);
-    D.lrow_col = upload(s, lc);
-    D.lrow_val = upload(s, lv);
+    D.sup_uoff = upload(s, uoff);
+    D.gval = upload(s, gval);
+    D.upd_ptr = upload(s, up);
+    D.upd_off = upload(s, uo);
+    D.ubuf = zeros<double>(s, std::max<size_t>(uoff[ns], 3));
+    s->factor_bytes = (int64_t)gval.size() * 8;
     // state and work buffers
     const size_t v3 = 3 * (size_t)m;
     D.x = zeros<double>(s, v3);
@@ -312,6 +329,31 @@ void build_device(sim *s) {
     s->d_bend_centers = upload(s, hm.bend_center);
     s->d_modes_tmp = zeros<uint8_t>(s, m);
     s->dd = (SimDev *)dev_alloc(s, sizeof(SimDev));
+    // solve vectors in LDS when they fit beside the kernels' static LDS
+    int dev = 0, maxlds = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        throw std::runtime_error("hip attribute");
+    size_t sf = 0, sb = 0;
+    if (kernel_static_lds(&sf, &sb) != hipSuccess) throw std::runtime_error("hip attribute");
+    const size_t vb = 3 * (size_t)m * sizeof(double);
+    s->lds_fwd = sf + 3 * vb <= (size_t)maxlds ? 3 * vb : 0;
+    s->lds_bwd = sb + 2 * vb <= (size_t)maxlds ? 2 * vb : 0;
+    if ((s->lds_fwd || s->lds_bwd) && configure_lds(maxlds - sf, maxlds - sb) != hipSuccess) {
+        s->lds_fwd = 0;
+        s->lds_bwd = 0;
+    }
+}
+
+// A batched launch uses LDS vectors only if every handle's fit.
+size_t batch_lds(sim *const *sims, int n, bool fwd) {
+    size_t mx = 0;
+    for (int i = 0; i < n; ++i) {
+        const size_t b = fwd ? sims[i]->lds_fwd : sims[i]->lds_bwd;
+        if (b == 0) return 0;
+        mx = std::max(mx, b);
+    }
+    return mx;
 }
 
 int push_desc(sim *s) {
@@ -348,7 +390,7 @@ int run_forward_range(sim *s, int a, int b) {
     s->hd.rec_step0 = a;
     int rc = push_desc(s);
     if (rc) return rc;
-    return hip_err(launch_forward(s->dd, 1, s->hd.mixed != 0, s->stream));
+    return hip_err(launch_forward(s->dd, 1, s->hd.mixed != 0, s->lds_fwd, s->stream));
 }
 
 int read_counters(sim *s) {
@@ -526,7 +568,7 @@ int backward_all(sim *s) {
         s->hd.rec_step0 = 0;
         int rc = push_desc(s);
         if (rc) return rc;
-        return hip_err(launch_backward(s->dd, 1, s->hd.mixed != 0, s->stream));
+        return hip_err(launch_backward(s->dd, 1, s->hd.mixed != 0, s->lds_bwd, s->stream));
     }
     const int nseg = (T + k - 1) / k;
     for (int seg = nseg - 1; seg >= 0; --seg) {
@@ -539,7 +581,7 @@ int backward_all(sim *s) {
         s->hd.step_end = b;
         s->hd.rec_step0 = a;
         rc = push_desc(s);
-        if (!rc) rc = hip_err(launch_backward(s->dd, 1, s->hd.mixed != 0, s->stream));
+        if (!rc) rc = hip_err(launch_backward(s->dd, 1, s->hd.mixed != 0, s->lds_bwd, s->stream));
         if (rc) return rc;
     }
     return SIM_OK;
@@ -617,7 +659,7 @@ int sim_adjoint_step(sim_t *s, int32_t n, const double *gx_dev, const double *gv
         s->hd.step_end = n + 1;
         s->hd.rec_step0 = 0;
         if (!rc) rc = push_desc(s);
-        if (!rc) rc = hip_err(launch_backward(s->dd, 1, s->hd.mixed != 0, s->stream));
+        if (!rc) rc = hip_err(launch_backward(s->dd, 1, s->hd.mixed != 0, s->lds_bwd, s->stream));
         if (!rc && dx_dev) rc = hip_err(launch_permute3(s->hd.gx, dx_dev, s->d_perm, m, true, s->stream));
         if (!rc && dv_dev) rc = hip_err(launch_permute3(s->hd.gv, dv_dev, s->d_perm, m, true, s->stream));
         if (!rc && out) {
@@ -698,6 +740,9 @@ int sim_stats(const sim_t *cs, sim_stats_t *out) {
     out->adj_noconv = (int32_t)s->counters_host[3];
     out->device_bytes = s->bytes;
     out->adj_krylov_total = s->counters_host[4];
+    out->factor_bytes = s->factor_bytes;
+    out->lds_forward = (int64_t)s->lds_fwd;
+    out->lds_backward = (int64_t)s->lds_bwd;
     return SIM_OK;
 }
 
@@ -724,7 +769,7 @@ int sim_batch_forward(sim_t *const *sims, int32_t n, const int32_t *n_steps, dou
         if (rc) return rc;
         SimDev *d = (SimDev *)dev_alloc(s0, n * sizeof(SimDev));
         rc = hip_err(hipMemcpyAsync(d, descs.data(), n * sizeof(SimDev), hipMemcpyHostToDevice, s0->stream));
-        if (!rc) rc = hip_err(launch_forward(d, n, s0->hd.mixed != 0, s0->stream));
+        if (!rc) rc = hip_err(launch_forward(d, n, s0->hd.mixed != 0, batch_lds(sims, n, true), s0->stream));
         for (int i = 0; i < n && !rc; ++i)
             rc = finish_forward(sims[i], n_steps[i], xT_dev ? xT_dev[i] : nullptr, vT_dev ? vT_dev[i] : nullptr);
         (void)hipStreamSynchronize(s0->stream);
@@ -756,7 +801,7 @@ int sim_batch_backward(sim_t *const *sims, int32_t n, const double *const *dL_dx
         if (rc) return rc;
         SimDev *d = (SimDev *)dev_alloc(s0, n * sizeof(SimDev));
         rc = hip_err(hipMemcpyAsync(d, descs.data(), n * sizeof(SimDev), hipMemcpyHostToDevice, s0->stream));
-        if (!rc) rc = hip_err(launch_backward(d, n, s0->hd.mixed != 0, s0->stream));
+        if (!rc) rc = hip_err(launch_backward(d, n, s0->hd.mixed != 0, batch_lds(sims, n, false), s0->stream));
         int warn = SIM_OK;
         for (int i = 0; i < n && !rc; ++i) {
             if (out) rc = write_grads(sims[i], &out[i]);

@@ -56,77 +56,68 @@ __device__ inline double block_sum(double v, double *red) {
 
 // ------------------------------------------------------------------ global solve
 // P v = b with P = P_s (x) I_3 = (L L^T) (x) I_3, three right-hand sides held
-// node-major.  Supernodes of one elimination-tree level are independent; each
-// level is two phases: a gather of the already-solved unknowns into the
-// level's rows, then the dense inverse diagonal block.  b is overwritten;
-// y is the forward-solve scratch; x receives the solution.
-__device__ void solve_P(const SimDev &S, double *__restrict__ b, double *__restrict__ y,
-                        double *__restrict__ x) {
+// node-major.  Supernodes of one level of the elimination tree are independent.
+// Each supernode s stores G_s = [L_ss^{-1}; B_s L_ss^{-1}] (column-major), so
+//   forward,  per level: (1) t_i = b_i - sum of the update entries of descendant
+//             supernodes that reach row i; (2) [y_s; u_s] = G_s t_s;
+//   backward, per level: x_s = L_ss^{-T} y_s - (B_s L_ss^{-1})^T x_{R_s}.
+// T and Y are scratch vectors (LDS when they fit); b may alias T; x receives v.
+__device__ void solve_P(const SimDev &S, const double *b, double *T, double *Y, double *x) {
     const int team = threadIdx.x / kTeam, lane = threadIdx.x % kTeam;
     constexpr int nteams = kBlock / kTeam;
+    const double *__restrict__ gval = S.gval;
+    double *__restrict__ ubuf = S.ubuf;
     for (int l = 0; l < S.n_levels; ++l) {
-        const int t0 = S.lvl_ptr[l], t1 = S.lvl_ptr[l + 1];
-        for (int t = t0 + team; t < t1; t += nteams) {
-            const int i = S.task_col[t];
-            double a0 = 0, a1 = 0, a2 = 0;
-            for (int p = S.lrow_ptr[i] + lane; p < S.lrow_ptr[i + 1]; p += kTeam) {
-                const int j = S.lrow_col[p];
-                const double L = S.lrow_val[p];
-                a0 += L * y[3 * j];
-                a1 += L * y[3 * j + 1];
-                a2 += L * y[3 * j + 2];
+        const int r0 = S.lvl_rows_ptr[l], r1 = S.lvl_rows_ptr[l + 1];
+        for (int t = r0 + threadIdx.x; t < r1; t += kBlock) {
+            const int i = S.lvl_rows[t];
+            double a0 = b[3 * i], a1 = b[3 * i + 1], a2 = b[3 * i + 2];
+            for (int p = S.upd_ptr[i]; p < S.upd_ptr[i + 1]; ++p) {
+                const int o = S.upd_off[p];
+                a0 -= ubuf[o]; a1 -= ubuf[o + 1]; a2 -= ubuf[o + 2];
             }
-            a0 = team_sum(a0); a1 = team_sum(a1); a2 = team_sum(a2);
-            if (lane == 0) { b[3 * i] -= a0; b[3 * i + 1] -= a1; b[3 * i + 2] -= a2; }
+            T[3 * i] = a0; T[3 * i + 1] = a1; T[3 * i + 2] = a2;
         }
         __syncthreads();
-        for (int t = t0 + team; t < t1; t += nteams) {
-            const int i = S.task_col[t], s = S.task_sup[t];
-            const int c0 = S.sup_c0[s], nsz = S.sup_ns[s], r = i - c0;
-            const double *Li = S.linv + S.sup_linv[s] + (int64_t)r * nsz;
+        const int i0 = S.lvl_items_ptr[l], i1 = S.lvl_items_ptr[l + 1];
+        for (int t = i0 + team; t < i1; t += nteams) {
+            const int sn = S.item_sup[t], r = S.item_row[t];
+            const int c0 = S.sup_c0[sn], nsz = S.sup_ns[sn], ld = nsz + S.sup_nr[sn];
+            const double *G = gval + S.sup_goff[sn] + r;
+            const int kmax = r < nsz ? r + 1 : nsz;
             double a0 = 0, a1 = 0, a2 = 0;
-            for (int k = lane; k <= r; k += kTeam) {
-                const double L = Li[k];
-                const int c = c0 + k;
-                a0 += L * b[3 * c];
-                a1 += L * b[3 * c + 1];
-                a2 += L * b[3 * c + 2];
+#pragma unroll 4
+            for (int k = lane; k < kmax; k += kTeam) {
+                const double g = G[(int64_t)k * ld];
+                const double *tk = T + 3 * (c0 + k);
+                a0 += g * tk[0]; a1 += g * tk[1]; a2 += g * tk[2];
             }
             a0 = team_sum(a0); a1 = team_sum(a1); a2 = team_sum(a2);
-            if (lane == 0) { y[3 * i] = a0; y[3 * i + 1] = a1; y[3 * i + 2] = a2; }
+            if (lane == 0) {
+                double *o = r < nsz ? Y + 3 * (c0 + r) : ubuf + S.sup_uoff[sn] + 3 * (r - nsz);
+                o[0] = a0; o[1] = a1; o[2] = a2;
+            }
         }
         __syncthreads();
     }
     for (int l = S.n_levels - 1; l >= 0; --l) {
-        const int t0 = S.lvl_ptr[l], t1 = S.lvl_ptr[l + 1];
-        for (int t = t0 + team; t < t1; t += nteams) {
-            const int c = S.task_col[t], s = S.task_sup[t];
-            const int c0 = S.sup_c0[s], nsz = S.sup_ns[s];
-            const int r0 = S.sup_rptr[s], nR = S.sup_rptr[s + 1] - r0;
-            const double *B = S.bval + S.sup_boff[s] + (c - c0);
+        const int r0 = S.lvl_rows_ptr[l], r1 = S.lvl_rows_ptr[l + 1];
+        for (int t = r0 + team; t < r1; t += nteams) {
+            const int c = S.lvl_rows[t], sn = S.sup_of[c];
+            const int c0 = S.sup_c0[sn], nsz = S.sup_ns[sn], ld = nsz + S.sup_nr[sn], k = c - c0;
+            const double *G = gval + S.sup_goff[sn] + (int64_t)k * ld;
+            const int32_t *R = S.sup_rows + S.sup_rptr[sn] - nsz;
             double a0 = 0, a1 = 0, a2 = 0;
-            for (int q = lane; q < nR; q += kTeam) {
-                const int r = S.sup_rows[r0 + q];
-                const double L = B[(int64_t)q * nsz];
-                a0 += L * x[3 * r];
-                a1 += L * x[3 * r + 1];
-                a2 += L * x[3 * r + 2];
-            }
-            a0 = team_sum(a0); a1 = team_sum(a1); a2 = team_sum(a2);
-            if (lane == 0) { y[3 * c] -= a0; y[3 * c + 1] -= a1; y[3 * c + 2] -= a2; }
-        }
-        __syncthreads();
-        for (int t = t0 + team; t < t1; t += nteams) {
-            const int c = S.task_col[t], s = S.task_sup[t];
-            const int c0 = S.sup_c0[s], nsz = S.sup_ns[s], r = c - c0;
-            const double *Lc = S.linv + S.sup_linv[s] + r;
-            double a0 = 0, a1 = 0, a2 = 0;
-            for (int k = r + lane; k < nsz; k += kTeam) {
-                const double L = Lc[(int64_t)k * nsz];
-                const int cc = c0 + k;
-                a0 += L * y[3 * cc];
-                a1 += L * y[3 * cc + 1];
-                a2 += L * y[3 * cc + 2];
+#pragma unroll 4
+            for (int r = k + lane; r < ld; r += kTeam) {
+                const double g = G[r];
+                if (r < nsz) {
+                    const double *yr = Y + 3 * (c0 + r);
+                    a0 += g * yr[0]; a1 += g * yr[1]; a2 += g * yr[2];
+                } else {
+                    const double *xr = x + 3 * R[r];
+                    a0 -= g * xr[0]; a1 -= g * xr[1]; a2 -= g * xr[2];
+                }
             }
             a0 = team_sum(a0); a1 = team_sum(a1); a2 = team_sum(a2);
             if (lane == 0) { x[3 * c] = a0; x[3 * c + 1] = a1; x[3 * c + 2] = a2; }
@@ -244,14 +235,21 @@ __device__ void local_projection(const SimDev &S, const double *__restrict__ vk)
     }
 }
 
-// Forward steps [step_begin, step_end) of one handle per workgroup.
+// Forward steps [step_begin, step_end) of one handle per workgroup.  The
+// solve vectors (T, Y) and the PD iterate V live in LDS when 9m doubles fit
+// (dynamic shared memory sized by the host), else in the handle's buffers.
 template <bool MIXED>
-__global__ __launch_bounds__(kBlock) void k_forward(const SimDev *__restrict__ sims) {
+__global__ __launch_bounds__(kBlock) void k_forward(const SimDev *__restrict__ sims, int lds_vectors) {
     const SimDev &S = sims[blockIdx.x];
+    extern __shared__ double dyn[];
     __shared__ double red[kBlock / 64];
     const int m = S.m;
     const double h = S.h;
     const bool converge = S.fwd_tol > 0;
+    double *T = lds_vectors ? dyn : S.rhs;
+    double *Y = lds_vectors ? dyn + 3 * m : S.ysol;
+    double *V = lds_vectors ? dyn + 6 * m : S.vk;
+    double *Vprev = S.vk1;
     int64_t iters_total = 0;
     for (int n = S.step_begin; n < S.step_end; ++n) {
         const int slot = n - S.rec_step0;
@@ -296,14 +294,15 @@ __global__ __launch_bounds__(kBlock) void k_forward(const SimDev *__restrict__ s
             for (int d = 0; d < 3; ++d) {
                 S.b0[3 * i + d] = b[d];
                 S.f[3 * i + d] = 0.0;
-                S.vk[3 * i + d] = vi[d] + h * S.g[d];
+                V[3 * i + d] = vi[d] + h * S.g[d];
             }
         }
         __syncthreads();
-        double *vk = S.vk, *vk1 = S.vk1;
         int k = 0;
         while (true) {
-            local_projection<MIXED>(S, vk);
+            local_projection<MIXED>(S, V);
+            if (converge)
+                for (int i = threadIdx.x; i < 3 * m; i += kBlock) Vprev[i] = V[i];
             __syncthreads();
             for (int i = threadIdx.x; i < m; i += kBlock) {
                 double r0 = 0, r1 = 0, r2 = 0;
@@ -314,32 +313,31 @@ __global__ __launch_bounds__(kBlock) void k_forward(const SimDev *__restrict__ s
                     r1 += a * S.wp[3 * c + 1];
                     r2 += a * S.wp[3 * c + 2];
                 }
-                S.rhs[3 * i] = S.b0[3 * i] + h * r0 + S.f[3 * i];
-                S.rhs[3 * i + 1] = S.b0[3 * i + 1] + h * r1 + S.f[3 * i + 1];
-                S.rhs[3 * i + 2] = S.b0[3 * i + 2] + h * r2 + S.f[3 * i + 2];
+                T[3 * i] = S.b0[3 * i] + h * r0 + S.f[3 * i];
+                T[3 * i + 1] = S.b0[3 * i + 1] + h * r1 + S.f[3 * i + 1];
+                T[3 * i + 2] = S.b0[3 * i + 2] + h * r2 + S.f[3 * i + 2];
             }
             __syncthreads();
-            solve_P(S, S.rhs, S.ysol, vk1);
+            solve_P(S, T, T, Y, V);
             double dmax = 0.0;
             for (int i = threadIdx.x; i < m; i += kBlock) {
                 if (S.mode[i] != FREE) {
                     const double mi = S.mass[i];
-                    const double ub[3] = {vk1[3 * i] - S.f[3 * i] / mi, vk1[3 * i + 1] - S.f[3 * i + 1] / mi,
-                                          vk1[3 * i + 2] - S.f[3 * i + 2] / mi};
+                    const double ub[3] = {V[3 * i] - S.f[3 * i] / mi, V[3 * i + 1] - S.f[3 * i + 1] / mi,
+                                          V[3 * i + 2] - S.f[3 * i + 2] / mi};
                     double nrm[3], phi, vv[3], ff[3];
                     contact_frame(S, S.cobst[i], S.x + 3 * i, nrm, phi);
                     S.mode[i] = signorini_coulomb(ub, nrm, phi, S.obst[S.cobst[i]].mu, h, mi, vv, ff);
                     for (int d = 0; d < 3; ++d) {
-                        vk1[3 * i + d] = vv[d];
+                        V[3 * i + d] = vv[d];
                         S.f[3 * i + d] = ff[d];
                         S.ubar[3 * i + d] = ub[d];
                     }
                 }
                 if (converge)
-                    for (int d = 0; d < 3; ++d) dmax = fmax(dmax, fabs(vk1[3 * i + d] - vk[3 * i + d]));
+                    for (int d = 0; d < 3; ++d) dmax = fmax(dmax, fabs(V[3 * i + d] - Vprev[3 * i + d]));
             }
             ++k;
-            double *tmp = vk; vk = vk1; vk1 = tmp;
             if (converge) {
                 dmax = block_max(dmax, red);          // includes the barrier
                 if (!(dmax > S.fwd_tol) || k >= S.fwd_max_iters) break;
@@ -354,7 +352,7 @@ __global__ __launch_bounds__(kBlock) void k_forward(const SimDev *__restrict__ s
         double *ubrec = S.rec_ubar + (int64_t)slot * 3 * m;
         for (int i = threadIdx.x; i < m; i += kBlock) {
             for (int d = 0; d < 3; ++d) {
-                const double vv = vk[3 * i + d];
+                const double vv = V[3 * i + d];
                 const double xx = S.x[3 * i + d] + h * vv;
                 S.x[3 * i + d] = xx;
                 S.v[3 * i + d] = vv;
@@ -496,16 +494,26 @@ __device__ void apply_adjoint_operator(const SimDev &S, const uint8_t *mode, con
     __syncthreads();
 }
 
-// Block-wide dot products <V_k, w> for k = 0..nk-1 (fixed order); results in hk[0..nk).
+// Block-wide dot products <V_k, w> for k = 0..nk-1 (fixed order); results in
+// hk[0..nk).  Eight basis vectors per pass over w.
 __device__ void block_dots(const double *V, int64_t ld, int nk, const double *w, int n3, double *red2, double *hk) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int k = 0; k < nk; ++k) {
-        const double *Vk = V + k * ld;
-        double p = 0.0;
-        for (int i = threadIdx.x; i < n3; i += kBlock) p += Vk[i] * w[i];
+    for (int k0 = 0; k0 < nk; k0 += 8) {
+        double p[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        const int kn = min(8, nk - k0);
+        for (int i = threadIdx.x; i < n3; i += kBlock) {
+            const double wi = w[i];
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o, 64);
-        if (lane == 0) red2[wave * (kKryM + 1) + k] = p;
+            for (int q = 0; q < 8; ++q)
+                if (q < kn) p[q] += V[(k0 + q) * ld + i] * wi;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            double v = p[q];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+            if (lane == 0 && q < kn) red2[wave * (kKryM + 1) + k0 + q] = v;
+        }
     }
     __syncthreads();
     for (int k = threadIdx.x; k < nk; k += kBlock) {
@@ -522,7 +530,7 @@ __device__ void block_dots(const double *V, int64_t ld, int nk, const double *w,
 // Returns the number of Krylov iterations, negative if the tolerance was missed.
 template <bool MIXED>
 __device__ int gmres_solve(const SimDev &S, const uint8_t *mode, const double *gbar, double *zeta, double tol,
-                           int max_iters, double *red) {
+                           int max_iters, double *red, double *T, double *Y) {
     __shared__ double Hs[(kKryM + 1) * kKryM];
     __shared__ double cs[kKryM], sn[kKryM], gv[kKryM + 1], yk[kKryM + 1];
     __shared__ double red2[(kBlock / 64) * (kKryM + 1)];
@@ -539,7 +547,7 @@ __device__ int gmres_solve(const SimDev &S, const uint8_t *mode, const double *g
         apply_adjoint_operator<MIXED>(S, mode, zeta, S.rhs);
         for (int i = threadIdx.x; i < n3; i += kBlock) S.rhs[i] = gbar[i] - S.rhs[i];
         __syncthreads();
-        solve_P(S, S.rhs, S.ysol, V);
+        solve_P(S, S.rhs, T, Y, V);
         double ss = 0.0;
         for (int i = threadIdx.x; i < n3; i += kBlock) ss += V[i] * V[i];
         const double beta = sqrt(block_sum(ss, red));
@@ -556,7 +564,7 @@ __device__ int gmres_solve(const SimDev &S, const uint8_t *mode, const double *g
         for (int j = 0; j < kKryM; ++j) {
             double *w = V + (j + 1) * ld;
             apply_adjoint_operator<MIXED>(S, mode, V + j * ld, S.rhs);
-            solve_P(S, S.rhs, S.ysol, w);
+            solve_P(S, S.rhs, T, Y, w);
             // classical Gram-Schmidt, twice
             for (int pass = 0; pass < 2; ++pass) {
                 block_dots(V, ld, j + 1, w, n3, red2, yk);
@@ -616,9 +624,12 @@ __device__ int gmres_solve(const SimDev &S, const uint8_t *mode, const double *g
 
 // Backward over steps [step_begin, step_end) in reverse, one handle per workgroup.
 template <bool MIXED>
-__global__ __launch_bounds__(kBlock) void k_backward(const SimDev *__restrict__ sims) {
+__global__ __launch_bounds__(kBlock) void k_backward(const SimDev *__restrict__ sims, int lds_vectors) {
     const SimDev &S = sims[blockIdx.x];
+    extern __shared__ double dyn[];
     __shared__ double red[kBlock / 64];
+    double *T = lds_vectors ? dyn : S.rhs;
+    double *Y = lds_vectors ? dyn + 3 * S.m : S.ysol;
     const int m = S.m;
     const double h = S.h, hh = h * h;
     int64_t iters_total = 0, gm_total = 0;
@@ -692,9 +703,9 @@ __global__ __launch_bounds__(kBlock) void k_backward(const SimDev *__restrict__ 
             __syncthreads();
             projection_jacobian_apply<MIXED>(S, S.zt, S.wp, false, h);
             __syncthreads();
-            adjoint_rhs<MIXED>(S, gbar, S.wp, zeta, S.zt, S.rhs);
+            adjoint_rhs<MIXED>(S, gbar, S.wp, zeta, S.zt, T);
             __syncthreads();
-            solve_P(S, S.rhs, S.ysol, zeta1);
+            solve_P(S, T, T, Y, zeta1);
             double dmax = 0.0, zmax = 0.0;
             for (int i = threadIdx.x; i < 3 * m; i += kBlock) {
                 dmax = fmax(dmax, fabs(zeta1[i] - zeta[i]));
@@ -720,7 +731,7 @@ __global__ __launch_bounds__(kBlock) void k_backward(const SimDev *__restrict__ 
         iters_total += k;
         if (!ok) {
             if (threadIdx.x == 0) S.counters[2] += 1;
-            const int it = gmres_solve<MIXED>(S, mode, gbar, S.zeta, S.adj_tol, S.adj_max_iters, red);
+            const int it = gmres_solve<MIXED>(S, mode, gbar, S.zeta, S.adj_tol, S.adj_max_iters, red, T, Y);
             zeta = S.zeta;
             if (it < 0) ++noconv;
             gm_total += it < 0 ? -it - 1 : it;
@@ -857,16 +868,44 @@ __global__ void k_fill(double *p, double v, int64_t n) {
 
 // ------------------------------------------------------------------ launchers
 
-hipError_t launch_forward(const SimDev *d_sims, int n, bool mixed, hipStream_t st) {
-    if (mixed) hipLaunchKernelGGL(k_forward<true>, dim3(n), dim3(kBlock), 0, st, d_sims);
-    else hipLaunchKernelGGL(k_forward<false>, dim3(n), dim3(kBlock), 0, st, d_sims);
+hipError_t launch_forward(const SimDev *d_sims, int n, bool mixed, size_t lds, hipStream_t st) {
+    const int lv = lds > 0 ? 1 : 0;
+    if (mixed) hipLaunchKernelGGL(k_forward<true>, dim3(n), dim3(kBlock), lds, st, d_sims, lv);
+    else hipLaunchKernelGGL(k_forward<false>, dim3(n), dim3(kBlock), lds, st, d_sims, lv);
     return hipGetLastError();
 }
 
-hipError_t launch_backward(const SimDev *d_sims, int n, bool mixed, hipStream_t st) {
-    if (mixed) hipLaunchKernelGGL(k_backward<true>, dim3(n), dim3(kBlock), 0, st, d_sims);
-    else hipLaunchKernelGGL(k_backward<false>, dim3(n), dim3(kBlock), 0, st, d_sims);
+hipError_t launch_backward(const SimDev *d_sims, int n, bool mixed, size_t lds, hipStream_t st) {
+    const int lv = lds > 0 ? 1 : 0;
+    if (mixed) hipLaunchKernelGGL(k_backward<true>, dim3(n), dim3(kBlock), lds, st, d_sims, lv);
+    else hipLaunchKernelGGL(k_backward<false>, dim3(n), dim3(kBlock), lds, st, d_sims, lv);
     return hipGetLastError();
+}
+
+// Allow the dynamic LDS the kernels may request (solve vectors resident in LDS).
+hipError_t configure_lds(size_t fwd_bytes, size_t bwd_bytes) {
+    hipError_t e = hipSuccess;
+    for (auto f : {(const void *)k_forward<true>, (const void *)k_forward<false>}) {
+        hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fwd_bytes);
+        if (r != hipSuccess) e = r;
+    }
+    for (auto f : {(const void *)k_backward<true>, (const void *)k_backward<false>}) {
+        hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bwd_bytes);
+        if (r != hipSuccess) e = r;
+    }
+    return e;
+}
+
+// Static LDS of the kernels (reductions, GMRES workspace).
+hipError_t kernel_static_lds(size_t *fwd, size_t *bwd) {
+    hipFuncAttributes a;
+    hipError_t e = hipFuncGetAttributes(&a, (const void *)k_forward<false>);
+    if (e != hipSuccess) return e;
+    *fwd = a.sharedSizeBytes;
+    e = hipFuncGetAttributes(&a, (const void *)k_backward<false>);
+    if (e != hipSuccess) return e;
+    *bwd = a.sharedSizeBytes;
+    return hipSuccess;
 }
 
 hipError_t launch_permute3(const double *in, double *out, const int32_t *perm, int m, bool to_caller, hipStream_t st) {

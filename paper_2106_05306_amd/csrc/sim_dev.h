@@ -46,20 +46,21 @@ struct SimDev {
     const int32_t *att_of;            // [m] attachment slot or -1
     const double *att_rest;           // [na*3] rest positions (caller coordinates)
 
-    // supernodal factor of P_s (new order)
+    // supernodal factor of P_s (new order): per supernode the stacked dense block
+    // G_s = [L_ss^{-1}; B_s L_ss^{-1}], column-major (ns + nR) x ns
     int n_levels;
-    const int32_t *lvl_ptr;           // [n_levels+1] ranges into the task arrays
-    const int32_t *task_col;          // column handled by a task
-    const int32_t *task_sup;          // its supernode
-    const int32_t *sup_c0, *sup_ns;   // [n_sup]
-    const int64_t *sup_linv;          // offset of the dense inverse diagonal block (ns x ns, row-major)
-    const int64_t *sup_boff;          // offset of the off-diagonal block (nR x ns, row-major)
-    const int32_t *sup_rptr;          // [n_sup+1] into sup_rows
-    const int32_t *sup_rows;          // off-diagonal row structure
-    const double *linv;
-    const double *bval;
-    const int32_t *lrow_ptr, *lrow_col;   // strictly-lower off-supernode rows (forward gather)
-    const double *lrow_val;
+    const int32_t *lvl_rows_ptr;      // [n_levels+1] into lvl_rows
+    const int32_t *lvl_rows;          // columns of each level's supernodes
+    const int32_t *lvl_items_ptr;     // [n_levels+1] into item_sup / item_row
+    const int32_t *item_sup, *item_row;   // forward items: (supernode, row of G_s)
+    const int32_t *sup_of;            // [m] supernode of each column
+    const int32_t *sup_c0, *sup_ns, *sup_nr;
+    const int64_t *sup_goff;          // offset of G_s in gval
+    const int32_t *sup_rptr, *sup_rows;   // off-diagonal row structure R_s
+    const int32_t *sup_uoff;          // offset of u_s = B_s y_s in ubuf
+    const double *gval;
+    const int32_t *upd_ptr, *upd_off; // per column: ubuf offsets gathered by the forward solve
+    double *ubuf;                     // update vectors u_s (3 per row of R_s)
 
     // ---------------------------------------------------------------- state and work
     double *x, *v;                    // state x_n, v_n
