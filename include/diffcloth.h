@@ -111,7 +111,9 @@ typedef struct {
  *                  bending constraint at node j bend_weight *
  *                  region_scale[bend_region[j]] (NULL: scale 1);
  *  adj_tol         adjoint stop rule max|zeta^{k+1}-zeta^k| <= adj_tol*max|zeta^{k+1}|;
- *  adj_max_iters   fixed-point iterations before the GMRES fallback;
+ *  adj_max_iters   fixed-point iterations before the GMRES fallback, and the
+ *                  GMRES iteration budget;
+ *  adj_restart     GMRES restart length, 1..60 (0: 60);
  *  checkpoint_every  0: keep every step's record for the backward pass;
  *                  k > 0: keep the state every k steps and recompute segments. */
 typedef struct {
@@ -134,6 +136,7 @@ typedef struct {
     double                adj_tol;
     int32_t               adj_max_iters;
     int32_t               checkpoint_every;
+    int32_t               adj_restart;
 } sim_params_t;
 
 /* Gradient outputs (caller-allocated device arrays; any may be NULL). */

@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <exception>
 #include <new>
@@ -13,8 +14,9 @@
 #include "sim_dev.h"
 
 namespace dc {
-hipError_t launch_forward(const SimDev *d_sims, int n, bool mixed, size_t lds, hipStream_t st);
-hipError_t launch_backward(const SimDev *d_sims, int n, bool mixed, size_t lds, hipStream_t st);
+hipError_t launch_forward(const SimDev *d_sims, int n, bool mixed, size_t lds, int flags, hipStream_t st);
+hipError_t launch_backward(const SimDev *d_sims, int n, bool mixed, size_t lds, int flags, hipStream_t st);
+constexpr int kLdsVectors = 1, kLdsUpdates = 2, kLdsPositions = 4;
 hipError_t configure_lds(size_t fwd_bytes, size_t bwd_bytes);
 hipError_t kernel_static_lds(size_t *fwd, size_t *bwd);
 hipError_t launch_permute3(const double *in, double *out, const int32_t *perm, int m, bool to_caller, hipStream_t st);
@@ -55,11 +57,21 @@ struct sim {
     int nca = 0;
     int64_t factor_bytes = 0;
     size_t lds_fwd = 0, lds_bwd = 0;   // dynamic LDS of the two kernels
+    int flags_fwd = 0, flags_bwd = 0;  // what lives in LDS (kLds* bits)
+    size_t static_fwd = 0, static_bwd = 0, max_lds = 0;
 };
 
 namespace {
 
 int hip_err(hipError_t e) { return e == hipSuccess ? SIM_OK : SIM_EHIP; }
+
+// Nested-dissection leaf size (nodes per leaf supernode).  DIFFCLOTH_LEAF
+// overrides it for experiments.
+int leaf_size_default() {
+    const char *e = std::getenv("DIFFCLOTH_LEAF");
+    const int v = e ? std::atoi(e) : 0;
+    return v >= 4 && v <= 256 ? v : 32;
+}
 
 void *dev_alloc(sim *s, size_t bytes) {
     if (bytes == 0) bytes = 8;
@@ -98,6 +110,27 @@ T *zeros(sim *s, size_t n) {
     if (hipMemsetAsync(d, 0, std::max<size_t>(n, 1) * sizeof(T), s->stream) != hipSuccess)
         throw std::runtime_error("hip memset");
     return d;
+}
+
+size_t lds_bytes(const sim *s, int flags, bool fwd) {
+    const size_t m3 = 3 * (size_t)s->hd.m;
+    size_t b = 0;
+    if (flags & kLdsVectors) b += 2 * m3;
+    if (flags & kLdsUpdates) b += (size_t)s->hd.n_ubuf;
+    if (fwd && (flags & kLdsPositions)) b += m3;
+    return b * sizeof(double);
+}
+
+// Greedy placement: add each kind of data to LDS while it still fits.
+void plan_lds(sim *s, int &flags, size_t &bytes, bool fwd) {
+    const size_t avail = s->max_lds > (fwd ? s->static_fwd : s->static_bwd)
+                             ? s->max_lds - (fwd ? s->static_fwd : s->static_bwd) : 0;
+    flags = 0;
+    for (int bit : {kLdsVectors, kLdsUpdates, kLdsPositions}) {
+        if (!fwd && bit == kLdsPositions) continue;
+        if (lds_bytes(s, flags | bit, fwd) <= avail) flags |= bit;
+    }
+    bytes = lds_bytes(s, flags, fwd);
 }
 
 // Build every device table from the host model and upload it.
@@ -258,36 +291,115 @@ void build_device(sim *s) {
         uo.insert(uo.end(), upd[i].begin(), upd[i].end());
         up.push_back((int32_t)uo.size());
     }
-    // level lists: the columns of each level, and the (supernode, stacked row) items
-    std::vector<int32_t> lrp(hm.n_levels + 1, 0), lrows, lip(hm.n_levels + 1, 0), isup, irow;
+    if (gval.size() >= (size_t)INT32_MAX || uoff[ns] >= INT32_MAX / 2) throw std::runtime_error("factor too large");
+    // level work lists (packed) and lanes per item
+    std::vector<int32_t> lrp(hm.n_levels + 1, 0), lip(hm.n_levels + 1, 0), team(2 * hm.n_levels, 1);
+    std::vector<RowItem> ritems;
+    std::vector<BwdItem> bitems;
+    std::vector<FwdItem> fitems;
+    auto pick_team = [](int items, int maxlen) {
+        int best = 1;
+        double best_cost = 1e300;
+        for (int tl = 1; tl <= 32; tl *= 2) {
+            const int passes = (items * tl + kBlock - 1) / kBlock;
+            const double cost = passes * ((maxlen + tl - 1) / tl + 0.5 * __builtin_ctz(tl) + 1.0);
+            if (cost < best_cost) { best_cost = cost; best = tl; }
+        }
+        return best;
+    };
     for (int l = 0; l < hm.n_levels; ++l) {
+        int fmax = 1, bmax = 1;
         for (int sn = 0; sn < ns; ++sn) {
             if (hm.sup_level[sn] != l) continue;
-            for (int c = sc0[sn]; c < sc0[sn] + sns[sn]; ++c) lrows.push_back(c);
-            for (int r = 0; r < sns[sn] + snr[sn]; ++r) { isup.push_back(sn); irow.push_back(r); }
+            const int c0 = sc0[sn], nsz = sns[sn], ld = nsz + snr[sn];
+            if (ld >= 32768) throw std::runtime_error("supernode too large");
+            for (int k = 0; k < nsz; ++k) {
+                const int c = c0 + k;
+                ritems.push_back(RowItem{3 * c, up[c], up[c + 1], 0});
+                BwdItem b{};
+                b.g = (int32_t)(goff[sn] + k);
+                b.k = (int16_t)k;
+                b.ld = (int16_t)ld;
+                b.nsz = (int16_t)nsz;
+                b.ybase = 3 * c0;
+                b.rbase = rptr[sn] - nsz;
+                b.out = 3 * c;
+                bitems.push_back(b);
+                bmax = std::max(bmax, ld - k);
+            }
+            for (int r = 0; r < ld; ++r) {
+                FwdItem f{};
+                f.g = (int32_t)(goff[sn] + r);
+                f.ld = (int16_t)ld;
+                f.kmax = (int16_t)(r < nsz ? r + 1 : nsz);
+                f.tbase = 3 * c0;
+                f.out = r < nsz ? 3 * (c0 + r) : -(uoff[sn] + 3 * (r - nsz)) - 1;
+                fitems.push_back(f);
+                fmax = std::max(fmax, (int)f.kmax);
+            }
         }
-        lrp[l + 1] = (int32_t)lrows.size();
-        lip[l + 1] = (int32_t)isup.size();
+        lrp[l + 1] = (int32_t)ritems.size();
+        lip[l + 1] = (int32_t)fitems.size();
+        team[2 * l] = pick_team(lip[l + 1] - lip[l], fmax);
+        team[2 * l + 1] = pick_team(lrp[l + 1] - lrp[l], bmax);
     }
     D.n_levels = hm.n_levels;
     D.lvl_rows_ptr = upload(s, lrp);
-    D.lvl_rows = upload(s, lrows);
     D.lvl_items_ptr = upload(s, lip);
-    D.item_sup = upload(s, isup);
-    D.item_row = upload(s, irow);
-    D.sup_of = upload(s, hm.sup_of);
-    D.sup_c0 = upload(s, sc0);
-    D.sup_ns = upload(s, sns);
-    D.sup_nr = upload(s, snr);
-    D.sup_goff = upload(s, goff);
-    D.sup_rptr = upload(s, rptr);
+    D.lvl_team = upload(s, team);
+    D.rows = upload(s, ritems);
+    D.fitems = upload(s, fitems);
+    D.bitems = upload(s, bitems);
     D.sup_rows = upload(s, rows);
-    D.sup_uoff = upload(s, uoff);
     D.gval = upload(s, gval);
-    D.upd_ptr = upload(s, up);
+    {   // row-major copy of every block for the backward solve (coalesced across columns)
+        std::vector<double> gt(gval.size());
+        for (int sn = 0; sn < ns; ++sn) {
+            const int nsz = sns[sn], ld = nsz + snr[sn];
+            const double *G = gval.data() + goff[sn];
+            double *Gt = gt.data() + goff[sn];
+            for (int k = 0; k < nsz; ++k)
+                for (int r = 0; r < ld; ++r) Gt[(size_t)r * nsz + k] = G[(size_t)k * ld + r];
+        }
+        D.gvalt = upload(s, gt);
+    }
     D.upd_off = upload(s, uo);
-    D.ubuf = zeros<double>(s, std::max<size_t>(uoff[ns], 3));
-    s->factor_bytes = (int64_t)gval.size() * 8;
+    D.n_ubuf = std::max(uoff[ns], 3);
+    D.ubuf = zeros<double>(s, D.n_ubuf);
+    // node-centred springs (active springs only) and active curved-bending incidence
+    std::vector<std::vector<SpringInc>> sl(m);
+    int nca_bend = 0;
+    for (int c = 0; c < nca; ++c) {
+        const int canon = order[c];
+        if (canon < hm.n_edges) {
+            const int a = cn[cp[c]], b = cn[cp[c] + 1];
+            const double w0 = cw[c], r0 = crho[c];
+            sl[a].push_back(SpringInc{a, b, +1, c, r0, w0});
+            sl[b].push_back(SpringInc{a, b, -1, c, r0, w0});
+        } else {
+            ++nca_bend;
+        }
+    }
+    std::vector<int32_t> sp(1, 0);
+    std::vector<SpringInc> sv;
+    for (int i = 0; i < m; ++i) {
+        sv.insert(sv.end(), sl[i].begin(), sl[i].end());
+        sp.push_back((int32_t)sv.size());
+    }
+    D.sinc_ptr = upload(s, sp);
+    D.sinc = upload(s, sv);
+    D.nca_bend = nca_bend;
+    std::vector<int32_t> bp(1, 0), bc;
+    std::vector<double> bcf;
+    for (int i = 0; i < m; ++i) {
+        for (auto &pr : inc[i])
+            if (pr.first >= nca - nca_bend) { bc.push_back(pr.first); bcf.push_back(pr.second); }
+        bp.push_back((int32_t)bc.size());
+    }
+    D.binc_ptr = upload(s, bp);
+    D.binc_con = upload(s, bc);
+    D.binc_coef = upload(s, bcf);
+    s->factor_bytes = (int64_t)gval.size() * 8;   // per copy (forward and backward each hold one)
     // state and work buffers
     const size_t v3 = 3 * (size_t)m;
     D.x = zeros<double>(s, v3);
@@ -315,7 +427,8 @@ void build_device(sim *s) {
     D.dw = zeros<double>(s, std::max(hm.nc, 1));
     D.dmu = zeros<double>(s, kMaxObstacles);
     D.counters = zeros<int64_t>(s, 8);
-    D.kry = zeros<double>(s, (size_t)(kKryM + 1) * v3);
+    D.kry_m = std::min(hm.adj_restart, kKryM);
+    D.kry = zeros<double>(s, (size_t)(D.kry_m + 1) * v3);
     // caller-order helpers
     s->d_perm = upload(s, perm);
     std::vector<double> xr(v3);
@@ -329,31 +442,37 @@ void build_device(sim *s) {
     s->d_bend_centers = upload(s, hm.bend_center);
     s->d_modes_tmp = zeros<uint8_t>(s, m);
     s->dd = (SimDev *)dev_alloc(s, sizeof(SimDev));
-    // solve vectors in LDS when they fit beside the kernels' static LDS
+    // LDS placement: the solve vectors first, then the update buffer, then x_n
     int dev = 0, maxlds = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
         throw std::runtime_error("hip attribute");
-    size_t sf = 0, sb = 0;
-    if (kernel_static_lds(&sf, &sb) != hipSuccess) throw std::runtime_error("hip attribute");
-    const size_t vb = 3 * (size_t)m * sizeof(double);
-    s->lds_fwd = sf + 3 * vb <= (size_t)maxlds ? 3 * vb : 0;
-    s->lds_bwd = sb + 2 * vb <= (size_t)maxlds ? 2 * vb : 0;
-    if ((s->lds_fwd || s->lds_bwd) && configure_lds(maxlds - sf, maxlds - sb) != hipSuccess) {
-        s->lds_fwd = 0;
-        s->lds_bwd = 0;
-    }
+    if (kernel_static_lds(&s->static_fwd, &s->static_bwd) != hipSuccess) throw std::runtime_error("hip attribute");
+    s->max_lds = (size_t)maxlds;
+    if (configure_lds(s->max_lds - s->static_fwd, s->max_lds - s->static_bwd) != hipSuccess) s->max_lds = 0;
+    plan_lds(s, s->flags_fwd, s->lds_fwd, true);
+    plan_lds(s, s->flags_bwd, s->lds_bwd, false);
 }
 
-// A batched launch uses LDS vectors only if every handle's fit.
-size_t batch_lds(sim *const *sims, int n, bool fwd) {
-    size_t mx = 0;
-    for (int i = 0; i < n; ++i) {
-        const size_t b = fwd ? sims[i]->lds_fwd : sims[i]->lds_bwd;
-        if (b == 0) return 0;
-        mx = std::max(mx, b);
+// A batched launch shares one placement: the bits every handle has, trimmed
+// until the largest handle fits.
+size_t batch_lds(sim *const *sims, int n, bool fwd, int &flags) {
+    flags = kLdsVectors | kLdsUpdates | kLdsPositions;
+    for (int i = 0; i < n; ++i) flags &= fwd ? sims[i]->flags_fwd : sims[i]->flags_bwd;
+    for (int bit : {kLdsPositions, kLdsUpdates, kLdsVectors}) {
+        size_t mx = 0;
+        bool ok = true;
+        for (int i = 0; i < n; ++i) {
+            const size_t avail = sims[i]->max_lds - (fwd ? sims[i]->static_fwd : sims[i]->static_bwd);
+            const size_t b = lds_bytes(sims[i], flags, fwd);
+            mx = std::max(mx, b);
+            if (b > avail) ok = false;
+        }
+        if (ok) return mx;
+        flags &= ~bit;
     }
-    return mx;
+    flags = 0;
+    return 0;
 }
 
 int push_desc(sim *s) {
@@ -390,7 +509,7 @@ int run_forward_range(sim *s, int a, int b) {
     s->hd.rec_step0 = a;
     int rc = push_desc(s);
     if (rc) return rc;
-    return hip_err(launch_forward(s->dd, 1, s->hd.mixed != 0, s->lds_fwd, s->stream));
+    return hip_err(launch_forward(s->dd, 1, s->hd.mixed != 0, s->lds_fwd, s->flags_fwd, s->stream));
 }
 
 int read_counters(sim *s) {
@@ -426,7 +545,7 @@ int sim_create(const sim_mesh_t *mesh, const sim_params_t *params, void *hip_str
     s->free_fn = free_fn;
     s->ctx = alloc_ctx;
     int rc = s->hm.build(mesh, params);
-    if (rc == SIM_OK) rc = s->hm.order_and_factor(32);
+    if (rc == SIM_OK) rc = s->hm.order_and_factor(leaf_size_default());
     if (rc == SIM_OK) {
         rc = guarded([&] {
             build_device(s);
@@ -568,7 +687,7 @@ int backward_all(sim *s) {
         s->hd.rec_step0 = 0;
         int rc = push_desc(s);
         if (rc) return rc;
-        return hip_err(launch_backward(s->dd, 1, s->hd.mixed != 0, s->lds_bwd, s->stream));
+        return hip_err(launch_backward(s->dd, 1, s->hd.mixed != 0, s->lds_bwd, s->flags_bwd, s->stream));
     }
     const int nseg = (T + k - 1) / k;
     for (int seg = nseg - 1; seg >= 0; --seg) {
@@ -581,7 +700,7 @@ int backward_all(sim *s) {
         s->hd.step_end = b;
         s->hd.rec_step0 = a;
         rc = push_desc(s);
-        if (!rc) rc = hip_err(launch_backward(s->dd, 1, s->hd.mixed != 0, s->lds_bwd, s->stream));
+        if (!rc) rc = hip_err(launch_backward(s->dd, 1, s->hd.mixed != 0, s->lds_bwd, s->flags_bwd, s->stream));
         if (rc) return rc;
     }
     return SIM_OK;
@@ -659,7 +778,7 @@ int sim_adjoint_step(sim_t *s, int32_t n, const double *gx_dev, const double *gv
         s->hd.step_end = n + 1;
         s->hd.rec_step0 = 0;
         if (!rc) rc = push_desc(s);
-        if (!rc) rc = hip_err(launch_backward(s->dd, 1, s->hd.mixed != 0, s->lds_bwd, s->stream));
+        if (!rc) rc = hip_err(launch_backward(s->dd, 1, s->hd.mixed != 0, s->lds_bwd, s->flags_bwd, s->stream));
         if (!rc && dx_dev) rc = hip_err(launch_permute3(s->hd.gx, dx_dev, s->d_perm, m, true, s->stream));
         if (!rc && dv_dev) rc = hip_err(launch_permute3(s->hd.gv, dv_dev, s->d_perm, m, true, s->stream));
         if (!rc && out) {
@@ -769,7 +888,9 @@ int sim_batch_forward(sim_t *const *sims, int32_t n, const int32_t *n_steps, dou
         if (rc) return rc;
         SimDev *d = (SimDev *)dev_alloc(s0, n * sizeof(SimDev));
         rc = hip_err(hipMemcpyAsync(d, descs.data(), n * sizeof(SimDev), hipMemcpyHostToDevice, s0->stream));
-        if (!rc) rc = hip_err(launch_forward(d, n, s0->hd.mixed != 0, batch_lds(sims, n, true), s0->stream));
+        int fl = 0;
+        const size_t lb = batch_lds(sims, n, true, fl);
+        if (!rc) rc = hip_err(launch_forward(d, n, s0->hd.mixed != 0, lb, fl, s0->stream));
         for (int i = 0; i < n && !rc; ++i)
             rc = finish_forward(sims[i], n_steps[i], xT_dev ? xT_dev[i] : nullptr, vT_dev ? vT_dev[i] : nullptr);
         (void)hipStreamSynchronize(s0->stream);
@@ -801,7 +922,9 @@ int sim_batch_backward(sim_t *const *sims, int32_t n, const double *const *dL_dx
         if (rc) return rc;
         SimDev *d = (SimDev *)dev_alloc(s0, n * sizeof(SimDev));
         rc = hip_err(hipMemcpyAsync(d, descs.data(), n * sizeof(SimDev), hipMemcpyHostToDevice, s0->stream));
-        if (!rc) rc = hip_err(launch_backward(d, n, s0->hd.mixed != 0, batch_lds(sims, n, false), s0->stream));
+        int fl = 0;
+        const size_t lb = batch_lds(sims, n, false, fl);
+        if (!rc) rc = hip_err(launch_backward(d, n, s0->hd.mixed != 0, lb, fl, s0->stream));
         int warn = SIM_OK;
         for (int i = 0; i < n && !rc; ++i) {
             if (out) rc = write_grads(sims[i], &out[i]);

@@ -16,13 +16,25 @@
 
 namespace dc {
 
+// Pointers read from the descriptor are HBM (global) pointers; saying so lets
+// the compiler emit global (not flat) memory instructions, so loads to HBM and
+// LDS are tracked by separate counters and overlap.
+#define GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ GLOBAL T *G(T *p) { return (GLOBAL T *)p; }
+// compile-time choice between an LDS and an HBM pointer (their types differ)
+template <bool C, class P, class Q>
+__device__ __forceinline__ auto pick(P a, Q b) {
+    if constexpr (C) return a;
+    else return b;
+}
+
 constexpr uint8_t FREE = 0, TAKEOFF = 1, STICK = 2, SLIP = 3;
 
 // ------------------------------------------------------------------ reductions
 
-__device__ inline double team_sum(double v) {
-#pragma unroll
-    for (int o = kTeam / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kTeam);
+__device__ inline double team_sum(double v, int tl) {
+    for (int o = tl >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, tl);
     return v;
 }
 
@@ -36,7 +48,7 @@ __device__ inline double block_max(double v, double *red) {
     __syncthreads();
     double r = red[0];
 #pragma unroll
-    for (int w = 1; w < kBlock / 64; ++w) r = fmax(r, red[w]);
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = fmax(r, red[w]);
     return r;
 }
 
@@ -50,7 +62,7 @@ __device__ inline double block_sum(double v, double *red) {
     __syncthreads();
     double r = red[0];
 #pragma unroll
-    for (int w = 1; w < kBlock / 64; ++w) r += red[w];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r += red[w];
     return r;
 }
 
@@ -61,66 +73,88 @@ __device__ inline double block_sum(double v, double *red) {
 //   forward,  per level: (1) t_i = b_i - sum of the update entries of descendant
 //             supernodes that reach row i; (2) [y_s; u_s] = G_s t_s;
 //   backward, per level: x_s = L_ss^{-T} y_s - (B_s L_ss^{-1})^T x_{R_s}.
-// T and Y are scratch vectors (LDS when they fit); b may alias T; x receives v.
-__device__ void solve_P(const SimDev &S, const double *b, double *T, double *Y, double *x) {
-    const int team = threadIdx.x / kTeam, lane = threadIdx.x % kTeam;
-    constexpr int nteams = kBlock / kTeam;
-    const double *__restrict__ gval = S.gval;
-    double *__restrict__ ubuf = S.ubuf;
+// Work items are packed descriptors; the host picks the lanes per item of each
+// level.  T, Y and the update buffer U live in LDS when they fit.  b may alias
+// T; x may alias T (T is dead once a level's products are formed).
+__device__ __forceinline__ void solve_P(const SimDev &S, auto b, auto T, auto Y, auto x, auto U) {
+    const auto gval = G(S.gval);
     for (int l = 0; l < S.n_levels; ++l) {
-        const int r0 = S.lvl_rows_ptr[l], r1 = S.lvl_rows_ptr[l + 1];
-        for (int t = r0 + threadIdx.x; t < r1; t += kBlock) {
-            const int i = S.lvl_rows[t];
-            double a0 = b[3 * i], a1 = b[3 * i + 1], a2 = b[3 * i + 2];
-            for (int p = S.upd_ptr[i]; p < S.upd_ptr[i + 1]; ++p) {
-                const int o = S.upd_off[p];
-                a0 -= ubuf[o]; a1 -= ubuf[o + 1]; a2 -= ubuf[o + 2];
+        const int r0 = G(S.lvl_rows_ptr)[l], r1 = G(S.lvl_rows_ptr)[l + 1];
+        for (int t = r0 + threadIdx.x; t < r1; t += (int)blockDim.x) {
+            const auto &it = G(S.rows)[t];
+            double a0 = b[it.i3], a1 = b[it.i3 + 1], a2 = b[it.i3 + 2];
+            for (int p = it.p0; p < it.p1; ++p) {
+                const int o = G(S.upd_off)[p];
+                a0 -= U[o]; a1 -= U[o + 1]; a2 -= U[o + 2];
             }
-            T[3 * i] = a0; T[3 * i + 1] = a1; T[3 * i + 2] = a2;
+            T[it.i3] = a0; T[it.i3 + 1] = a1; T[it.i3 + 2] = a2;
         }
         __syncthreads();
-        const int i0 = S.lvl_items_ptr[l], i1 = S.lvl_items_ptr[l + 1];
+        const int tl = G(S.lvl_team)[2 * l];
+        const int team = threadIdx.x / tl, lane = threadIdx.x % tl, nteams = (int)blockDim.x / tl;
+        const int i0 = G(S.lvl_items_ptr)[l], i1 = G(S.lvl_items_ptr)[l + 1];
         for (int t = i0 + team; t < i1; t += nteams) {
-            const int sn = S.item_sup[t], r = S.item_row[t];
-            const int c0 = S.sup_c0[sn], nsz = S.sup_ns[sn], ld = nsz + S.sup_nr[sn];
-            const double *G = gval + S.sup_goff[sn] + r;
-            const int kmax = r < nsz ? r + 1 : nsz;
+            const auto &it = G(S.fitems)[t];
+            const auto Gb = gval + it.g;
+            const auto Tb = T + it.tbase;
+            const int ld = it.ld, kmax = it.kmax;
             double a0 = 0, a1 = 0, a2 = 0;
-#pragma unroll 4
-            for (int k = lane; k < kmax; k += kTeam) {
-                const double g = G[(int64_t)k * ld];
-                const double *tk = T + 3 * (c0 + k);
-                a0 += g * tk[0]; a1 += g * tk[1]; a2 += g * tk[2];
+            for (int k0 = lane; k0 < kmax; k0 += 8 * tl) {
+                double g[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {            // eight independent loads in flight
+                    const int k = k0 + j * tl;
+                    g[j] = k < kmax ? Gb[k * ld] : 0.0;
+                }
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int k = k0 + j * tl;
+                    if (k < kmax) { a0 += g[j] * Tb[3 * k]; a1 += g[j] * Tb[3 * k + 1]; a2 += g[j] * Tb[3 * k + 2]; }
+                }
             }
-            a0 = team_sum(a0); a1 = team_sum(a1); a2 = team_sum(a2);
+            a0 = team_sum(a0, tl); a1 = team_sum(a1, tl); a2 = team_sum(a2, tl);
             if (lane == 0) {
-                double *o = r < nsz ? Y + 3 * (c0 + r) : ubuf + S.sup_uoff[sn] + 3 * (r - nsz);
-                o[0] = a0; o[1] = a1; o[2] = a2;
+                if (it.out >= 0) {
+                    Y[it.out] = a0; Y[it.out + 1] = a1; Y[it.out + 2] = a2;
+                } else {
+                    const int o = -it.out - 1;
+                    U[o] = a0; U[o + 1] = a1; U[o + 2] = a2;
+                }
             }
         }
         __syncthreads();
     }
     for (int l = S.n_levels - 1; l >= 0; --l) {
-        const int r0 = S.lvl_rows_ptr[l], r1 = S.lvl_rows_ptr[l + 1];
+        const int tl = G(S.lvl_team)[2 * l + 1];
+        const int team = threadIdx.x / tl, lane = threadIdx.x % tl, nteams = (int)blockDim.x / tl;
+        const int r0 = G(S.lvl_rows_ptr)[l], r1 = G(S.lvl_rows_ptr)[l + 1];
         for (int t = r0 + team; t < r1; t += nteams) {
-            const int c = S.lvl_rows[t], sn = S.sup_of[c];
-            const int c0 = S.sup_c0[sn], nsz = S.sup_ns[sn], ld = nsz + S.sup_nr[sn], k = c - c0;
-            const double *G = gval + S.sup_goff[sn] + (int64_t)k * ld;
-            const int32_t *R = S.sup_rows + S.sup_rptr[sn] - nsz;
+            const auto &it = G(S.bitems)[t];
+            const auto Gb = G(S.gvalt) + it.g;           // row-major: element (r, k) at r * nsz
+            const auto Yb = Y + it.ybase;
+            const auto R = G(S.sup_rows) + it.rbase;
+            const int ld = it.ld, nsz = it.nsz;
             double a0 = 0, a1 = 0, a2 = 0;
-#pragma unroll 4
-            for (int r = k + lane; r < ld; r += kTeam) {
-                const double g = G[r];
-                if (r < nsz) {
-                    const double *yr = Y + 3 * (c0 + r);
-                    a0 += g * yr[0]; a1 += g * yr[1]; a2 += g * yr[2];
-                } else {
-                    const double *xr = x + 3 * R[r];
-                    a0 -= g * xr[0]; a1 -= g * xr[1]; a2 -= g * xr[2];
+            for (int r0i = it.k + lane; r0i < ld; r0i += 8 * tl) {
+                double g[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int r = r0i + j * tl;
+                    g[j] = r < ld ? Gb[r * nsz] : 0.0;
+                }
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int r = r0i + j * tl;
+                    if (r < nsz) {
+                        a0 += g[j] * Yb[3 * r]; a1 += g[j] * Yb[3 * r + 1]; a2 += g[j] * Yb[3 * r + 2];
+                    } else if (r < ld) {
+                        const auto xr = x + 3 * R[r];
+                        a0 -= g[j] * xr[0]; a1 -= g[j] * xr[1]; a2 -= g[j] * xr[2];
+                    }
                 }
             }
-            a0 = team_sum(a0); a1 = team_sum(a1); a2 = team_sum(a2);
-            if (lane == 0) { x[3 * c] = a0; x[3 * c + 1] = a1; x[3 * c + 2] = a2; }
+            a0 = team_sum(a0, tl); a1 = team_sum(a1, tl); a2 = team_sum(a2, tl);
+            if (lane == 0) { x[it.out] = a0; x[it.out + 1] = a1; x[it.out + 2] = a2; }
         }
         __syncthreads();
     }
@@ -128,7 +162,7 @@ __device__ void solve_P(const SimDev &S, const double *b, double *T, double *Y, 
 
 // ------------------------------------------------------------------ geometry
 
-__device__ inline void contact_frame(const SimDev &S, int o, const double *xi, double *n, double &phi) {
+__device__ __forceinline__ void contact_frame(const SimDev &S, int o, auto xi, double *n, double &phi) {
     const ObstacleDev &ob = S.obst[o];
     if (ob.type == 0) {
         n[0] = ob.n[0]; n[1] = ob.n[1]; n[2] = ob.n[2];
@@ -141,7 +175,7 @@ __device__ inline void contact_frame(const SimDev &S, int o, const double *xi, d
     }
 }
 
-__device__ inline double signed_distance(const ObstacleDev &ob, const double *y) {
+__device__ __forceinline__ double signed_distance(const ObstacleDev &ob, const double *y) {
     if (ob.type == 0)
         return (y[0] - ob.p[0]) * ob.n[0] + (y[1] - ob.p[1]) * ob.n[1] + (y[2] - ob.p[2]) * ob.n[2];
     const double d0 = y[0] - ob.p[0], d1 = y[1] - ob.p[1], d2 = y[2] - ob.p[2];
@@ -149,7 +183,7 @@ __device__ inline double signed_distance(const ObstacleDev &ob, const double *y)
 }
 
 // attachment target of rest point X at time t: c + R(axis, omega t)(X - c)
-__device__ inline void attach_target(const SimDev &S, const double *X, double t, double *out) {
+__device__ __forceinline__ void attach_target(const SimDev &S, auto X, double t, double *out) {
     const double ang = S.att_omega * t, cs = cos(ang), sn = sin(ang);
     const double *a = S.att_axis;
     const double d0 = X[0] - S.att_center[0], d1 = X[1] - S.att_center[1], d2 = X[2] - S.att_center[2];
@@ -162,7 +196,7 @@ __device__ inline void attach_target(const SimDev &S, const double *X, double t,
 
 // Closed-form Signorini-Coulomb update of one node with isotropic response
 // v = ub + f/m; gap-corrected normal velocity.  Decisions in float64.
-__device__ inline uint8_t signorini_coulomb(const double *ub, const double *n, double phi, double mu,
+__device__ __forceinline__ uint8_t signorini_coulomb(const double *ub, const double *n, double phi, double mu,
                                             double h, double mass, double *v, double *f) {
     const double un = n[0] * ub[0] + n[1] * ub[1] + n[2] * ub[2];
     const double a = un + phi / h;
@@ -193,28 +227,29 @@ __device__ inline uint8_t signorini_coulomb(const double *ub, const double *n, d
 
 // ------------------------------------------------------------------ forward
 
-// w_c p_c for every active constraint at x^k = x_n + h v^k (local step).
+// w_c p_c for active constraints [c0, c1) at x^k = x_n + h v^k (local step,
+// constraint-centred; used for curved bending stencils).
 template <bool MIXED>
-__device__ void local_projection(const SimDev &S, const double *__restrict__ vk) {
+__device__ __forceinline__ void local_projection(const SimDev &S, auto XN, auto vk, int c0, int c1) {
     const double h = S.h;
-    for (int c = threadIdx.x; c < S.nca; c += kBlock) {
+    for (int c = c0 + threadIdx.x; c < c1; c += (int)blockDim.x) {
         double q0 = 0, q1 = 0, q2 = 0;
-        for (int p = S.c_ptr[c]; p < S.c_ptr[c + 1]; ++p) {
-            const int j = S.c_node[p];
-            const double a = S.c_coef[p];
-            q0 += a * (S.x[3 * j] + h * vk[3 * j]);
-            q1 += a * (S.x[3 * j + 1] + h * vk[3 * j + 1]);
-            q2 += a * (S.x[3 * j + 2] + h * vk[3 * j + 2]);
+        for (int p = G(S.c_ptr)[c]; p < G(S.c_ptr)[c + 1]; ++p) {
+            const int j = G(S.c_node)[p];
+            const double a = G(S.c_coef)[p];
+            q0 += a * (XN[3 * j] + h * vk[3 * j]);
+            q1 += a * (XN[3 * j + 1] + h * vk[3 * j + 1]);
+            q2 += a * (XN[3 * j + 2] + h * vk[3 * j + 2]);
         }
         double p0, p1, p2;
         if (MIXED) {
             const float f0 = (float)q0, f1 = (float)q1, f2 = (float)q2;
             const float nq = sqrtf(f0 * f0 + f1 * f1 + f2 * f2);
-            const float rho = S.c_rhof[c], w = S.c_wf[c];
+            const float rho = G(S.c_rhof)[c], w = G(S.c_wf)[c];
             float r0, r1, r2;
             if (nq < 1e-12f * rho) {
-                r0 = rho * (float)S.c_restdir[3 * c]; r1 = rho * (float)S.c_restdir[3 * c + 1];
-                r2 = rho * (float)S.c_restdir[3 * c + 2];
+                r0 = rho * (float)G(S.c_restdir)[3 * c]; r1 = rho * (float)G(S.c_restdir)[3 * c + 1];
+                r2 = rho * (float)G(S.c_restdir)[3 * c + 2];
             } else {
                 const float sc = rho / nq;
                 r0 = sc * f0; r1 = sc * f1; r2 = sc * f2;
@@ -222,44 +257,121 @@ __device__ void local_projection(const SimDev &S, const double *__restrict__ vk)
             p0 = (double)(w * r0); p1 = (double)(w * r1); p2 = (double)(w * r2);
         } else {
             const double nq = sqrt(q0 * q0 + q1 * q1 + q2 * q2);
-            const double rho = S.c_rho[c], w = S.c_w[c];
+            const double rho = G(S.c_rho)[c], w = G(S.c_w)[c];
             if (nq < 1e-12 * rho) {
-                p0 = w * rho * S.c_restdir[3 * c]; p1 = w * rho * S.c_restdir[3 * c + 1];
-                p2 = w * rho * S.c_restdir[3 * c + 2];
+                p0 = w * rho * G(S.c_restdir)[3 * c]; p1 = w * rho * G(S.c_restdir)[3 * c + 1];
+                p2 = w * rho * G(S.c_restdir)[3 * c + 2];
             } else {
                 const double sc = w * rho / nq;
                 p0 = sc * q0; p1 = sc * q1; p2 = sc * q2;
             }
         }
-        S.wp[3 * c] = p0; S.wp[3 * c + 1] = p1; S.wp[3 * c + 2] = p2;
+        G(S.wp)[3 * c] = p0; G(S.wp)[3 * c + 1] = p1; G(S.wp)[3 * c + 2] = p2;
     }
 }
 
-// Forward steps [step_begin, step_end) of one handle per workgroup.  The
-// solve vectors (T, Y) and the PD iterate V live in LDS when 9m doubles fit
-// (dynamic shared memory sized by the host), else in the handle's buffers.
+// Right-hand side of the global step (eqn pd_velocity_with_contact):
+// out_i = b0_i + h sum_c a_ci w_c p_c + f_i.  Springs are projected here,
+// node-centred (each spring on both of its nodes, with the same arithmetic, so
+// the two contributions are exact negatives); curved-bending projections come
+// from wp.
 template <bool MIXED>
-__global__ __launch_bounds__(kBlock) void k_forward(const SimDev *__restrict__ sims, int lds_vectors) {
+__device__ __forceinline__ void spring_rhs(const SimDev &S, auto XN, auto V, auto out) {
+    const double h = S.h;
+    const bool bend = S.nca_bend > 0;
+    for (int i = threadIdx.x; i < S.m; i += (int)blockDim.x) {
+        double r0 = 0, r1 = 0, r2 = 0;
+        const int p0 = G(S.sinc_ptr)[i], p1 = G(S.sinc_ptr)[i + 1];
+        for (int pb = p0; pb < p1; pb += 8) {
+            SpringInc spv[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {                // independent record loads in flight
+                if (pb + j < p1) {
+                    const auto &g = G(S.sinc)[pb + j];
+                    spv[j].a = g.a; spv[j].b = g.b; spv[j].sign = g.sign; spv[j].pad = g.pad;
+                    spv[j].rho = g.rho; spv[j].w = g.w;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if (pb + j >= p1) break;
+                const SpringInc &sp = spv[j];
+                const double q0 = (XN[3 * sp.a] + h * V[3 * sp.a]) - (XN[3 * sp.b] + h * V[3 * sp.b]);
+                const double q1 = (XN[3 * sp.a + 1] + h * V[3 * sp.a + 1]) - (XN[3 * sp.b + 1] + h * V[3 * sp.b + 1]);
+                const double q2 = (XN[3 * sp.a + 2] + h * V[3 * sp.a + 2]) - (XN[3 * sp.b + 2] + h * V[3 * sp.b + 2]);
+                double p0v, p1v, p2v;
+                if (MIXED) {
+                    const float f0 = (float)q0, f1 = (float)q1, f2 = (float)q2;
+                    const float nq = sqrtf(f0 * f0 + f1 * f1 + f2 * f2);
+                    const float rho = (float)sp.rho, w = (float)sp.w;
+                    float g0, g1, g2;
+                    if (nq < 1e-12f * rho) {
+                        const auto rd = G(S.c_restdir) + 3 * sp.pad;
+                        g0 = rho * (float)rd[0]; g1 = rho * (float)rd[1]; g2 = rho * (float)rd[2];
+                    } else {
+                        const float sc = rho / nq;
+                        g0 = sc * f0; g1 = sc * f1; g2 = sc * f2;
+                    }
+                    p0v = (double)(w * g0); p1v = (double)(w * g1); p2v = (double)(w * g2);
+                } else {
+                    const double nq = sqrt(q0 * q0 + q1 * q1 + q2 * q2);
+                    if (nq < 1e-12 * sp.rho) {
+                        const auto rd = G(S.c_restdir) + 3 * sp.pad;
+                        p0v = sp.w * sp.rho * rd[0]; p1v = sp.w * sp.rho * rd[1]; p2v = sp.w * sp.rho * rd[2];
+                    } else {
+                        const double sc = sp.w * sp.rho / nq;
+                        p0v = sc * q0; p1v = sc * q1; p2v = sc * q2;
+                    }
+                }
+                if (sp.sign > 0) { r0 += p0v; r1 += p1v; r2 += p2v; }
+                else { r0 -= p0v; r1 -= p1v; r2 -= p2v; }
+            }
+        }
+        if (bend) {
+            for (int p = G(S.binc_ptr)[i]; p < G(S.binc_ptr)[i + 1]; ++p) {
+                const int c = G(S.binc_con)[p];
+                const double a = G(S.binc_coef)[p];
+                r0 += a * G(S.wp)[3 * c]; r1 += a * G(S.wp)[3 * c + 1]; r2 += a * G(S.wp)[3 * c + 2];
+            }
+        }
+        out[3 * i] = G(S.b0)[3 * i] + h * r0 + G(S.f)[3 * i];
+        out[3 * i + 1] = G(S.b0)[3 * i + 1] + h * r1 + G(S.f)[3 * i + 1];
+        out[3 * i + 2] = G(S.b0)[3 * i + 2] + h * r2 + G(S.f)[3 * i + 2];
+    }
+}
+
+// LDS placement bits chosen by the host for a launch.
+constexpr int kLdsVectors = 1, kLdsUpdates = 2, kLdsPositions = 4;
+
+// Forward steps [step_begin, step_end) of one handle per workgroup.  The PD
+// iterate ping-pongs between two vectors A and B (LDS when they fit): B gets
+// the right-hand side, the forward solve writes into A, the backward solve
+// writes the new iterate into B.
+template <bool MIXED, int FL>
+__global__ __launch_bounds__(kBlock) void k_forward(const SimDev *__restrict__ sims) {
     const SimDev &S = sims[blockIdx.x];
     extern __shared__ double dyn[];
     __shared__ double red[kBlock / 64];
     const int m = S.m;
     const double h = S.h;
     const bool converge = S.fwd_tol > 0;
-    double *T = lds_vectors ? dyn : S.rhs;
-    double *Y = lds_vectors ? dyn + 3 * m : S.ysol;
-    double *V = lds_vectors ? dyn + 6 * m : S.vk;
-    double *Vprev = S.vk1;
+    constexpr bool kv = (FL & kLdsVectors) != 0, ku = (FL & kLdsUpdates) != 0, kx = (FL & kLdsPositions) != 0;
+    const int off_u = kv ? 6 * m : 0, off_x = off_u + (ku ? S.n_ubuf : 0);
+    auto A = pick<kv>(dyn, G(S.vk));
+    auto B = pick<kv>(dyn + 3 * m, G(S.rhs));
+    auto U = pick<ku>(dyn + off_u, G(S.ubuf));
+    auto XN = pick<kx>(dyn + off_x, G(S.x));
+    auto Vprev = G(S.vk1);
     int64_t iters_total = 0;
     for (int n = S.step_begin; n < S.step_end; ++n) {
         const int slot = n - S.rec_step0;
         const double t1 = (n + 1) * h;
-        double *xrec = S.rec_x + (int64_t)slot * 3 * m;
-        double *vrec = S.rec_v + (int64_t)slot * 3 * m;
+        auto xrec = G(S.rec_x) + (int64_t)slot * 3 * m;
+        auto vrec = G(S.rec_v) + (int64_t)slot * 3 * m;
         // predictor, detection on y, constant right-hand side, initial guess
-        for (int i = threadIdx.x; i < m; i += kBlock) {
-            const double xi[3] = {S.x[3 * i], S.x[3 * i + 1], S.x[3 * i + 2]};
-            const double vi[3] = {S.v[3 * i], S.v[3 * i + 1], S.v[3 * i + 2]};
+        for (int i = threadIdx.x; i < m; i += (int)blockDim.x) {
+            const double xi[3] = {G(S.x)[3 * i], G(S.x)[3 * i + 1], G(S.x)[3 * i + 2]};
+            const double vi[3] = {G(S.v)[3 * i], G(S.v)[3 * i + 1], G(S.v)[3 * i + 2]};
             if (n == S.step_begin) {
                 for (int d = 0; d < 3; ++d) { xrec[3 * i + d] = xi[d]; vrec[3 * i + d] = vi[d]; }
             }
@@ -272,72 +384,65 @@ __global__ __launch_bounds__(kBlock) void k_forward(const SimDev *__restrict__ s
                 if (ob < 0 || phi < best) { best = phi; ob = o; }
             }
             const bool contact = ob >= 0 && best <= 0.0;
-            S.mode[i] = contact ? TAKEOFF : FREE;
-            S.cobst[i] = contact ? (int8_t)ob : (int8_t)-1;
+            G(S.mode)[i] = contact ? TAKEOFF : FREE;
+            G(S.cobst)[i] = contact ? (int8_t)ob : (int8_t)-1;
             double kx0 = 0, kx1 = 0, kx2 = 0;
-            for (int p = S.ks_ptr[i]; p < S.ks_ptr[i + 1]; ++p) {
-                const int j = S.ks_col[p];
-                const double kv = S.ks_val[p];
-                kx0 += kv * S.x[3 * j];
-                kx1 += kv * S.x[3 * j + 1];
-                kx2 += kv * S.x[3 * j + 2];
+            for (int p = G(S.ks_ptr)[i]; p < G(S.ks_ptr)[i + 1]; ++p) {
+                const int j = G(S.ks_col)[p];
+                const double kv = G(S.ks_val)[p];
+                kx0 += kv * G(S.x)[3 * j];
+                kx1 += kv * G(S.x)[3 * j + 1];
+                kx2 += kv * G(S.x)[3 * j + 2];
             }
-            const double mi = S.mass[i];
+            const double mi = G(S.mass)[i];
             double b[3] = {mi * vi[0] + h * mi * S.g[0] - h * kx0, mi * vi[1] + h * mi * S.g[1] - h * kx1,
                            mi * vi[2] + h * mi * S.g[2] - h * kx2};
-            const int as = S.att_of[i];
+            const int as = G(S.att_of)[i];
             if (as >= 0) {
                 double tg[3];
-                attach_target(S, S.att_rest + 3 * as, t1, tg);
+                attach_target(S, G(S.att_rest) + 3 * as, t1, tg);
                 for (int d = 0; d < 3; ++d) b[d] += h * S.w_att * tg[d];
             }
             for (int d = 0; d < 3; ++d) {
-                S.b0[3 * i + d] = b[d];
-                S.f[3 * i + d] = 0.0;
-                V[3 * i + d] = vi[d] + h * S.g[d];
+                G(S.b0)[3 * i + d] = b[d];
+                G(S.f)[3 * i + d] = 0.0;
+                A[3 * i + d] = vi[d] + h * S.g[d];
             }
+            if constexpr ((FL & kLdsPositions) != 0)
+                for (int d = 0; d < 3; ++d) XN[3 * i + d] = xi[d];
         }
         __syncthreads();
         int k = 0;
         while (true) {
-            local_projection<MIXED>(S, V);
-            if (converge)
-                for (int i = threadIdx.x; i < 3 * m; i += kBlock) Vprev[i] = V[i];
-            __syncthreads();
-            for (int i = threadIdx.x; i < m; i += kBlock) {
-                double r0 = 0, r1 = 0, r2 = 0;
-                for (int p = S.inc_ptr[i]; p < S.inc_ptr[i + 1]; ++p) {
-                    const int c = S.inc_con[p];
-                    const double a = S.inc_coef[p];
-                    r0 += a * S.wp[3 * c];
-                    r1 += a * S.wp[3 * c + 1];
-                    r2 += a * S.wp[3 * c + 2];
-                }
-                T[3 * i] = S.b0[3 * i] + h * r0 + S.f[3 * i];
-                T[3 * i + 1] = S.b0[3 * i + 1] + h * r1 + S.f[3 * i + 1];
-                T[3 * i + 2] = S.b0[3 * i + 2] + h * r2 + S.f[3 * i + 2];
+            if (S.nca_bend > 0) {
+                local_projection<MIXED>(S, XN, A, S.nca - S.nca_bend, S.nca);
+                __syncthreads();
             }
+            spring_rhs<MIXED>(S, XN, A, B);
+            if (converge)
+                for (int i = threadIdx.x; i < 3 * m; i += (int)blockDim.x) Vprev[i] = A[i];
             __syncthreads();
-            solve_P(S, T, T, Y, V);
+            solve_P(S, B, B, A, B, U);
             double dmax = 0.0;
-            for (int i = threadIdx.x; i < m; i += kBlock) {
-                if (S.mode[i] != FREE) {
-                    const double mi = S.mass[i];
-                    const double ub[3] = {V[3 * i] - S.f[3 * i] / mi, V[3 * i + 1] - S.f[3 * i + 1] / mi,
-                                          V[3 * i + 2] - S.f[3 * i + 2] / mi};
+            for (int i = threadIdx.x; i < m; i += (int)blockDim.x) {
+                if (G(S.mode)[i] != FREE) {
+                    const double mi = G(S.mass)[i];
+                    const double ub[3] = {B[3 * i] - G(S.f)[3 * i] / mi, B[3 * i + 1] - G(S.f)[3 * i + 1] / mi,
+                                          B[3 * i + 2] - G(S.f)[3 * i + 2] / mi};
                     double nrm[3], phi, vv[3], ff[3];
-                    contact_frame(S, S.cobst[i], S.x + 3 * i, nrm, phi);
-                    S.mode[i] = signorini_coulomb(ub, nrm, phi, S.obst[S.cobst[i]].mu, h, mi, vv, ff);
+                    contact_frame(S, G(S.cobst)[i], XN + 3 * i, nrm, phi);
+                    G(S.mode)[i] = signorini_coulomb(ub, nrm, phi, S.obst[G(S.cobst)[i]].mu, h, mi, vv, ff);
                     for (int d = 0; d < 3; ++d) {
-                        V[3 * i + d] = vv[d];
-                        S.f[3 * i + d] = ff[d];
-                        S.ubar[3 * i + d] = ub[d];
+                        B[3 * i + d] = vv[d];
+                        G(S.f)[3 * i + d] = ff[d];
+                        G(S.ubar)[3 * i + d] = ub[d];
                     }
                 }
                 if (converge)
-                    for (int d = 0; d < 3; ++d) dmax = fmax(dmax, fabs(V[3 * i + d] - Vprev[3 * i + d]));
+                    for (int d = 0; d < 3; ++d) dmax = fmax(dmax, fabs(B[3 * i + d] - Vprev[3 * i + d]));
             }
             ++k;
+            auto tmp = A; A = B; B = tmp;
             if (converge) {
                 dmax = block_max(dmax, red);          // includes the barrier
                 if (!(dmax > S.fwd_tol) || k >= S.fwd_max_iters) break;
@@ -347,33 +452,34 @@ __global__ __launch_bounds__(kBlock) void k_forward(const SimDev *__restrict__ s
             }
         }
         iters_total += k;
-        // advance and record
-        double *xn = xrec + 3 * m, *vn = vrec + 3 * m;
-        double *ubrec = S.rec_ubar + (int64_t)slot * 3 * m;
-        for (int i = threadIdx.x; i < m; i += kBlock) {
+        // advance and record (the iterate is in A)
+        auto xn = xrec + 3 * m;
+        auto vn = vrec + 3 * m;
+        auto ubrec = G(S.rec_ubar) + (int64_t)slot * 3 * m;
+        for (int i = threadIdx.x; i < m; i += (int)blockDim.x) {
             for (int d = 0; d < 3; ++d) {
-                const double vv = V[3 * i + d];
-                const double xx = S.x[3 * i + d] + h * vv;
-                S.x[3 * i + d] = xx;
-                S.v[3 * i + d] = vv;
+                const double vv = A[3 * i + d];
+                const double xx = XN[3 * i + d] + h * vv;
+                G(S.x)[3 * i + d] = xx;
+                G(S.v)[3 * i + d] = vv;
                 xn[3 * i + d] = xx;
                 vn[3 * i + d] = vv;
-                ubrec[3 * i + d] = S.ubar[3 * i + d];
+                ubrec[3 * i + d] = G(S.ubar)[3 * i + d];
             }
-            S.rec_mode[(int64_t)slot * m + i] = S.mode[i];
-            S.rec_obst[(int64_t)slot * m + i] = S.cobst[i];
+            G(S.rec_mode)[(int64_t)slot * m + i] = G(S.mode)[i];
+            G(S.rec_obst)[(int64_t)slot * m + i] = G(S.cobst)[i];
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) S.counters[0] += iters_total;
+    if (threadIdx.x == 0) G(S.counters)[0] += iters_total;
 }
 
 // ------------------------------------------------------------------ adjoint
 
 // z = T^T zeta per node (T = I off contact / take-off, 0 for stick, the slip
 // block otherwise); also keeps zeta - z for the (P - M) term.
-__device__ inline void apply_TT(const SimDev &S, const uint8_t *mode, const double *zeta, double *z) {
-    for (int i = threadIdx.x; i < S.m; i += kBlock) {
+__device__ __forceinline__ void apply_TT(const SimDev &S, auto mode, auto zeta, auto z) {
+    for (int i = threadIdx.x; i < S.m; i += (int)blockDim.x) {
         const uint8_t md = mode[i];
         const double a0 = zeta[3 * i], a1 = zeta[3 * i + 1], a2 = zeta[3 * i + 2];
         if (md == FREE || md == TAKEOFF) {
@@ -381,7 +487,7 @@ __device__ inline void apply_TT(const SimDev &S, const uint8_t *mode, const doub
         } else if (md == STICK) {
             z[3 * i] = 0.0; z[3 * i + 1] = 0.0; z[3 * i + 2] = 0.0;
         } else {
-            const double *T = S.tblk + 9 * (int64_t)i;     // row-major T
+            const auto T = G(S.tblk) + 9 * (int64_t)i;       // row-major T
             z[3 * i] = T[0] * a0 + T[3] * a1 + T[6] * a2;
             z[3 * i + 1] = T[1] * a0 + T[4] * a1 + T[7] * a2;
             z[3 * i + 2] = T[2] * a0 + T[5] * a1 + T[8] * a2;
@@ -391,20 +497,20 @@ __device__ inline void apply_TT(const SimDev &S, const uint8_t *mode, const doub
 
 // u_c = G_c (A_c z) with G_c = s_c (I - qhat qhat^T) (the Delta P blocks)
 template <bool MIXED>
-__device__ inline void projection_jacobian_apply(const SimDev &S, const double *z, double *u, bool accumulate_dw,
+__device__ __forceinline__ void projection_jacobian_apply(const SimDev &S, auto z, auto u, bool accumulate_dw,
                                                  double h) {
-    for (int c = threadIdx.x; c < S.nca; c += kBlock) {
+    for (int c = threadIdx.x; c < S.nca; c += (int)blockDim.x) {
         double a0 = 0, a1 = 0, a2 = 0;
-        for (int p = S.c_ptr[c]; p < S.c_ptr[c + 1]; ++p) {
-            const int j = S.c_node[p];
-            const double a = S.c_coef[p];
+        for (int p = G(S.c_ptr)[c]; p < G(S.c_ptr)[c + 1]; ++p) {
+            const int j = G(S.c_node)[p];
+            const double a = G(S.c_coef)[p];
             a0 += a * z[3 * j];
             a1 += a * z[3 * j + 1];
             a2 += a * z[3 * j + 2];
         }
-        const double *qh = S.adj_q + 3 * c;
+        const auto qh = G(S.adj_q) + 3 * c;
         if (MIXED) {
-            const float sc = (float)S.adj_s[c];
+            const float sc = (float)G(S.adj_s)[c];
             const float q0 = (float)qh[0], q1 = (float)qh[1], q2 = (float)qh[2];
             const float b0 = (float)a0, b1 = (float)a1, b2 = (float)a2;
             const float qd = q0 * b0 + q1 * b1 + q2 * b2;
@@ -412,49 +518,48 @@ __device__ inline void projection_jacobian_apply(const SimDev &S, const double *
             u[3 * c + 1] = (double)(sc * (b1 - qd * q1));
             u[3 * c + 2] = (double)(sc * (b2 - qd * q2));
         } else {
-            const double sc = S.adj_s[c];
+            const double sc = G(S.adj_s)[c];
             const double qd = qh[0] * a0 + qh[1] * a1 + qh[2] * a2;
             u[3 * c] = sc * (a0 - qd * qh[0]);
             u[3 * c + 1] = sc * (a1 - qd * qh[1]);
             u[3 * c + 2] = sc * (a2 - qd * qh[2]);
         }
         if (accumulate_dw) {
-            const double *pq = S.adj_pq + 3 * c;
-            S.dw[S.c_id[c]] += h * (a0 * pq[0] + a1 * pq[1] + a2 * pq[2]);
+            const auto pq = G(S.adj_pq) + 3 * c;
+            G(S.dw)[G(S.c_id)[c]] += h * (a0 * pq[0] + a1 * pq[1] + a2 * pq[2]);
         }
     }
 }
 
 // dL/dw for constraints without a local projection (flat bending): p = 0.
-__device__ inline void inactive_dw(const SimDev &S, const double *z, const double *x1, double h) {
-    for (int c = S.nca + threadIdx.x; c < S.nc_total; c += kBlock) {
+__device__ __forceinline__ void inactive_dw(const SimDev &S, auto z, auto x1, double h) {
+    for (int c = S.nca + threadIdx.x; c < S.nc_total; c += (int)blockDim.x) {
         double a0 = 0, a1 = 0, a2 = 0, q0 = 0, q1 = 0, q2 = 0;
-        for (int p = S.c_ptr[c]; p < S.c_ptr[c + 1]; ++p) {
-            const int j = S.c_node[p];
-            const double a = S.c_coef[p];
+        for (int p = G(S.c_ptr)[c]; p < G(S.c_ptr)[c + 1]; ++p) {
+            const int j = G(S.c_node)[p];
+            const double a = G(S.c_coef)[p];
             a0 += a * z[3 * j]; a1 += a * z[3 * j + 1]; a2 += a * z[3 * j + 2];
             q0 += a * x1[3 * j]; q1 += a * x1[3 * j + 1]; q2 += a * x1[3 * j + 2];
         }
-        S.dw[S.c_id[c]] -= h * (a0 * q0 + a1 * q1 + a2 * q2);
+        G(S.dw)[G(S.c_id)[c]] -= h * (a0 * q0 + a1 * q1 + a2 * q2);
     }
 }
 
 // r_i = g_i + sum_c a_ci u_c + h^2 (K_s d)_i, d = zeta - z (FP32 matrix values in mixed mode)
 template <bool MIXED>
-__device__ inline void adjoint_rhs(const SimDev &S, const double *gbar, const double *u, const double *zeta,
-                                   const double *z, double *r) {
+__device__ __forceinline__ void adjoint_rhs(const SimDev &S, auto gbar, auto u, auto zeta, auto z, auto r) {
     const double hh = S.h * S.h;
-    for (int i = threadIdx.x; i < S.m; i += kBlock) {
+    for (int i = threadIdx.x; i < S.m; i += (int)blockDim.x) {
         double r0 = 0, r1 = 0, r2 = 0;
-        for (int p = S.inc_ptr[i]; p < S.inc_ptr[i + 1]; ++p) {
-            const int c = S.inc_con[p];
-            const double a = S.inc_coef[p];
+        for (int p = G(S.inc_ptr)[i]; p < G(S.inc_ptr)[i + 1]; ++p) {
+            const int c = G(S.inc_con)[p];
+            const double a = G(S.inc_coef)[p];
             r0 += a * u[3 * c]; r1 += a * u[3 * c + 1]; r2 += a * u[3 * c + 2];
         }
         double k0 = 0, k1 = 0, k2 = 0;
-        for (int p = S.ks_ptr[i]; p < S.ks_ptr[i + 1]; ++p) {
-            const int j = S.ks_col[p];
-            const double kv = MIXED ? (double)S.ks_valf[p] : S.ks_val[p];
+        for (int p = G(S.ks_ptr)[i]; p < G(S.ks_ptr)[i + 1]; ++p) {
+            const int j = G(S.ks_col)[p];
+            const double kv = MIXED ? (double)G(S.ks_valf)[p] : G(S.ks_val)[p];
             k0 += kv * (zeta[3 * j] - z[3 * j]);
             k1 += kv * (zeta[3 * j + 1] - z[3 * j + 1]);
             k2 += kv * (zeta[3 * j + 2] - z[3 * j + 2]);
@@ -467,26 +572,26 @@ __device__ inline void adjoint_rhs(const SimDev &S, const double *gbar, const do
 
 // out = A v = M v + H T^T v with H = h^2 K_s - Delta P (the contact adjoint operator)
 template <bool MIXED>
-__device__ void apply_adjoint_operator(const SimDev &S, const uint8_t *mode, const double *vin, double *out) {
-    apply_TT(S, mode, vin, S.zt);
+__device__ __forceinline__ void apply_adjoint_operator(const SimDev &S, auto mode, auto vin, auto out) {
+    apply_TT(S, mode, vin, G(S.zt));
     __syncthreads();
-    projection_jacobian_apply<MIXED>(S, S.zt, S.wp, false, S.h);
+    projection_jacobian_apply<MIXED>(S, G(S.zt), G(S.wp), false, S.h);
     __syncthreads();
     const double hh = S.h * S.h;
-    for (int i = threadIdx.x; i < S.m; i += kBlock) {
+    for (int i = threadIdx.x; i < S.m; i += (int)blockDim.x) {
         double r0 = 0, r1 = 0, r2 = 0;
-        for (int p = S.inc_ptr[i]; p < S.inc_ptr[i + 1]; ++p) {
-            const int c = S.inc_con[p];
-            const double a = S.inc_coef[p];
-            r0 += a * S.wp[3 * c]; r1 += a * S.wp[3 * c + 1]; r2 += a * S.wp[3 * c + 2];
+        for (int p = G(S.inc_ptr)[i]; p < G(S.inc_ptr)[i + 1]; ++p) {
+            const int c = G(S.inc_con)[p];
+            const double a = G(S.inc_coef)[p];
+            r0 += a * G(S.wp)[3 * c]; r1 += a * G(S.wp)[3 * c + 1]; r2 += a * G(S.wp)[3 * c + 2];
         }
         double k0 = 0, k1 = 0, k2 = 0;
-        for (int p = S.ks_ptr[i]; p < S.ks_ptr[i + 1]; ++p) {
-            const int j = S.ks_col[p];
-            const double kv = MIXED ? (double)S.ks_valf[p] : S.ks_val[p];
-            k0 += kv * S.zt[3 * j]; k1 += kv * S.zt[3 * j + 1]; k2 += kv * S.zt[3 * j + 2];
+        for (int p = G(S.ks_ptr)[i]; p < G(S.ks_ptr)[i + 1]; ++p) {
+            const int j = G(S.ks_col)[p];
+            const double kv = MIXED ? (double)G(S.ks_valf)[p] : G(S.ks_val)[p];
+            k0 += kv * G(S.zt)[3 * j]; k1 += kv * G(S.zt)[3 * j + 1]; k2 += kv * G(S.zt)[3 * j + 2];
         }
-        const double mi = S.mass[i];
+        const double mi = G(S.mass)[i];
         out[3 * i] = mi * vin[3 * i] + hh * k0 - r0;
         out[3 * i + 1] = mi * vin[3 * i + 1] + hh * k1 - r1;
         out[3 * i + 2] = mi * vin[3 * i + 2] + hh * k2 - r2;
@@ -496,12 +601,12 @@ __device__ void apply_adjoint_operator(const SimDev &S, const uint8_t *mode, con
 
 // Block-wide dot products <V_k, w> for k = 0..nk-1 (fixed order); results in
 // hk[0..nk).  Eight basis vectors per pass over w.
-__device__ void block_dots(const double *V, int64_t ld, int nk, const double *w, int n3, double *red2, double *hk) {
+__device__ __forceinline__ void block_dots(auto V, int64_t ld, int nk, auto w, int n3, double *red2, double *hk) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int k0 = 0; k0 < nk; k0 += 8) {
         double p[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         const int kn = min(8, nk - k0);
-        for (int i = threadIdx.x; i < n3; i += kBlock) {
+        for (int i = threadIdx.x; i < n3; i += (int)blockDim.x) {
             const double wi = w[i];
 #pragma unroll
             for (int q = 0; q < 8; ++q)
@@ -516,9 +621,9 @@ __device__ void block_dots(const double *V, int64_t ld, int nk, const double *w,
         }
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < nk; k += kBlock) {
+    for (int k = threadIdx.x; k < nk; k += (int)blockDim.x) {
         double s = 0.0;
-        for (int wv = 0; wv < kBlock / 64; ++wv) s += red2[wv * (kKryM + 1) + k];
+        for (int wv = 0; wv < (int)(blockDim.x >> 6); ++wv) s += red2[wv * (kKryM + 1) + k];
         hk[k] = s;
     }
     __syncthreads();
@@ -529,46 +634,50 @@ __device__ void block_dots(const double *V, int64_t ld, int nk, const double *w,
 // diverges.  Stops when |P^{-1}(gbar - A zeta)| <= tol |P^{-1} gbar|.
 // Returns the number of Krylov iterations, negative if the tolerance was missed.
 template <bool MIXED>
-__device__ int gmres_solve(const SimDev &S, const uint8_t *mode, const double *gbar, double *zeta, double tol,
-                           int max_iters, double *red, double *T, double *Y) {
+__device__ __forceinline__ int gmres_solve(const SimDev &S, auto mode, auto gbar, auto zeta, double tol, int max_iters,
+                           double *red, auto T, auto Y, auto U) {
     __shared__ double Hs[(kKryM + 1) * kKryM];
     __shared__ double cs[kKryM], sn[kKryM], gv[kKryM + 1], yk[kKryM + 1];
     __shared__ double red2[(kBlock / 64) * (kKryM + 1)];
     __shared__ int flag[2];
     const int n3 = 3 * S.m;
     const int64_t ld = n3;
-    double *V = S.kry;
+    auto V = G(S.kry);
     double beta0 = -1.0;
     int total = 0;
-    for (int i = threadIdx.x; i < n3; i += kBlock) zeta[i] = 0.0;
+    for (int i = threadIdx.x; i < n3; i += (int)blockDim.x) zeta[i] = 0.0;
     __syncthreads();
     while (true) {
         // r = P^{-1}(gbar - A zeta)
-        apply_adjoint_operator<MIXED>(S, mode, zeta, S.rhs);
-        for (int i = threadIdx.x; i < n3; i += kBlock) S.rhs[i] = gbar[i] - S.rhs[i];
+        apply_adjoint_operator<MIXED>(S, mode, zeta, G(S.rhs));
+        for (int i = threadIdx.x; i < n3; i += (int)blockDim.x) G(S.rhs)[i] = gbar[i] - G(S.rhs)[i];
         __syncthreads();
-        solve_P(S, S.rhs, T, Y, V);
+        solve_P(S, G(S.rhs), T, Y, V, U);
         double ss = 0.0;
-        for (int i = threadIdx.x; i < n3; i += kBlock) ss += V[i] * V[i];
+        for (int i = threadIdx.x; i < n3; i += (int)blockDim.x) ss += V[i] * V[i];
         const double beta = sqrt(block_sum(ss, red));
         if (beta0 < 0) beta0 = beta;
         if (!(beta > tol * beta0) || !(beta == beta)) return (beta == beta) ? total : -total - 1;
         if (total >= max_iters) return -total - 1;
-        for (int i = threadIdx.x; i < n3; i += kBlock) V[i] /= beta;
+        for (int i = threadIdx.x; i < n3; i += (int)blockDim.x) V[i] /= beta;
         if (threadIdx.x == 0) {
             gv[0] = beta;
-            for (int k = 1; k <= kKryM; ++k) gv[k] = 0.0;
+            for (int k = 1; k <= S.kry_m; ++k) gv[k] = 0.0;
         }
         __syncthreads();
         int jdone = 0;
-        for (int j = 0; j < kKryM; ++j) {
-            double *w = V + (j + 1) * ld;
-            apply_adjoint_operator<MIXED>(S, mode, V + j * ld, S.rhs);
-            solve_P(S, S.rhs, T, Y, w);
-            // classical Gram-Schmidt, twice
+        for (int j = 0; j < S.kry_m; ++j) {
+            auto w = V + (j + 1) * ld;
+            apply_adjoint_operator<MIXED>(S, mode, V + j * ld, G(S.rhs));
+            solve_P(S, G(S.rhs), T, Y, w, U);
+            // classical Gram-Schmidt; a second pass only when the first one
+            // cancelled most of w (|w| dropped below 0.7 of its norm)
+            double ws = 0.0;
+            for (int i = threadIdx.x; i < n3; i += (int)blockDim.x) ws += w[i] * w[i];
+            double wn = sqrt(block_sum(ws, red));
             for (int pass = 0; pass < 2; ++pass) {
                 block_dots(V, ld, j + 1, w, n3, red2, yk);
-                for (int i = threadIdx.x; i < n3; i += kBlock) {
+                for (int i = threadIdx.x; i < n3; i += (int)blockDim.x) {
                     double acc = w[i];
                     for (int k = 0; k <= j; ++k) acc -= yk[k] * V[k * ld + i];
                     w[i] = acc;
@@ -576,12 +685,16 @@ __device__ int gmres_solve(const SimDev &S, const uint8_t *mode, const double *g
                 if (threadIdx.x == 0)
                     for (int k = 0; k <= j; ++k) Hs[k * kKryM + j] = (pass ? Hs[k * kKryM + j] : 0.0) + yk[k];
                 __syncthreads();
+                ws = 0.0;
+                for (int i = threadIdx.x; i < n3; i += (int)blockDim.x) ws += w[i] * w[i];
+                const double wa = sqrt(block_sum(ws, red));
+                const bool again = wa < 0.7 * wn;
+                wn = wa;
+                if (!again) break;
             }
-            double ws = 0.0;
-            for (int i = threadIdx.x; i < n3; i += kBlock) ws += w[i] * w[i];
-            const double hn = sqrt(block_sum(ws, red));
+            const double hn = wn;
             if (hn > 0)
-                for (int i = threadIdx.x; i < n3; i += kBlock) w[i] /= hn;
+                for (int i = threadIdx.x; i < n3; i += (int)blockDim.x) w[i] /= hn;
             if (threadIdx.x == 0) {
                 // apply previous rotations to column j, then a new one
                 for (int k = 0; k < j; ++k) {
@@ -613,7 +726,7 @@ __device__ int gmres_solve(const SimDev &S, const uint8_t *mode, const double *g
             }
         }
         __syncthreads();
-        for (int i = threadIdx.x; i < n3; i += kBlock) {
+        for (int i = threadIdx.x; i < n3; i += (int)blockDim.x) {
             double acc = zeta[i];
             for (int k = 0; k < jdone; ++k) acc += yk[k] * V[k * ld + i];
             zeta[i] = acc;
@@ -623,60 +736,60 @@ __device__ int gmres_solve(const SimDev &S, const uint8_t *mode, const double *g
 }
 
 // Backward over steps [step_begin, step_end) in reverse, one handle per workgroup.
-template <bool MIXED>
-__global__ __launch_bounds__(kBlock) void k_backward(const SimDev *__restrict__ sims, int lds_vectors) {
+template <bool MIXED, int FL>
+__global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict__ sims) {
     const SimDev &S = sims[blockIdx.x];
     extern __shared__ double dyn[];
     __shared__ double red[kBlock / 64];
-    double *T = lds_vectors ? dyn : S.rhs;
-    double *Y = lds_vectors ? dyn + 3 * S.m : S.ysol;
+    constexpr bool kv = (FL & kLdsVectors) != 0, ku = (FL & kLdsUpdates) != 0;
+    auto T = pick<kv>(dyn, G(S.rhs));
+    auto Y = pick<kv>(dyn + 3 * S.m, G(S.ysol));
+    auto U = pick<ku>(dyn + (kv ? 6 * S.m : 0), G(S.ubuf));
     const int m = S.m;
     const double h = S.h, hh = h * h;
     int64_t iters_total = 0, gm_total = 0;
     int noconv = 0;
-    double dmu_acc[kMaxObstacles];
-    for (int o = 0; o < kMaxObstacles; ++o) dmu_acc[o] = 0.0;
     for (int n = S.step_end - 1; n >= S.step_begin; --n) {
         const int slot = n - S.rec_step0;
-        const double *x0 = S.rec_x + (int64_t)slot * 3 * m;
-        const double *x1 = x0 + 3 * m;
-        const uint8_t *mode = S.rec_mode + (int64_t)slot * m;
-        const int8_t *obst = S.rec_obst + (int64_t)slot * m;
-        const double *ubr = S.rec_ubar + (int64_t)slot * 3 * m;
-        double *gbar = S.b0;
+        const auto x0 = G(S.rec_x) + (int64_t)slot * 3 * m;
+        const auto x1 = x0 + 3 * m;
+        const auto mode = G(S.rec_mode) + (int64_t)slot * m;
+        const auto obst = G(S.rec_obst) + (int64_t)slot * m;
+        const auto ubr = G(S.rec_ubar) + (int64_t)slot * 3 * m;
+        auto gbar = G(S.b0);
         // projections and their Jacobians at x_{n+1}
-        for (int c = threadIdx.x; c < S.nca; c += kBlock) {
+        for (int c = threadIdx.x; c < S.nca; c += (int)blockDim.x) {
             double q0 = 0, q1 = 0, q2 = 0;
-            for (int p = S.c_ptr[c]; p < S.c_ptr[c + 1]; ++p) {
-                const int j = S.c_node[p];
-                const double a = S.c_coef[p];
+            for (int p = G(S.c_ptr)[c]; p < G(S.c_ptr)[c + 1]; ++p) {
+                const int j = G(S.c_node)[p];
+                const double a = G(S.c_coef)[p];
                 q0 += a * x1[3 * j]; q1 += a * x1[3 * j + 1]; q2 += a * x1[3 * j + 2];
             }
             const double nq = sqrt(q0 * q0 + q1 * q1 + q2 * q2);
-            const double rho = S.c_rho[c];
+            const double rho = G(S.c_rho)[c];
             double p0, p1, p2, sc, qh0, qh1, qh2;
             if (nq < 1e-12 * rho) {
-                p0 = rho * S.c_restdir[3 * c]; p1 = rho * S.c_restdir[3 * c + 1]; p2 = rho * S.c_restdir[3 * c + 2];
+                p0 = rho * G(S.c_restdir)[3 * c]; p1 = rho * G(S.c_restdir)[3 * c + 1]; p2 = rho * G(S.c_restdir)[3 * c + 2];
                 sc = 0.0; qh0 = qh1 = qh2 = 0.0;
             } else {
                 qh0 = q0 / nq; qh1 = q1 / nq; qh2 = q2 / nq;
                 p0 = rho * qh0; p1 = rho * qh1; p2 = rho * qh2;
-                sc = hh * S.c_w[c] * rho / nq;
+                sc = hh * G(S.c_w)[c] * rho / nq;
             }
-            S.adj_s[c] = sc;
-            S.adj_q[3 * c] = qh0; S.adj_q[3 * c + 1] = qh1; S.adj_q[3 * c + 2] = qh2;
-            S.adj_pq[3 * c] = p0 - q0; S.adj_pq[3 * c + 1] = p1 - q1; S.adj_pq[3 * c + 2] = p2 - q2;
+            G(S.adj_s)[c] = sc;
+            G(S.adj_q)[3 * c] = qh0; G(S.adj_q)[3 * c + 1] = qh1; G(S.adj_q)[3 * c + 2] = qh2;
+            G(S.adj_pq)[3 * c] = p0 - q0; G(S.adj_pq)[3 * c + 1] = p1 - q1; G(S.adj_pq)[3 * c + 2] = p2 - q2;
         }
         // gbar and the contact blocks T_j (slip)
-        for (int i = threadIdx.x; i < m; i += kBlock) {
+        for (int i = threadIdx.x; i < m; i += (int)blockDim.x) {
             for (int d = 0; d < 3; ++d) {
-                gbar[3 * i + d] = S.gv[3 * i + d] + h * S.gx[3 * i + d];
-                S.zeta[3 * i + d] = 0.0;
+                gbar[3 * i + d] = G(S.gv)[3 * i + d] + h * G(S.gx)[3 * i + d];
+                G(S.zeta)[3 * i + d] = 0.0;
             }
             if (mode[i] == SLIP) {
                 double nrm[3], phi;
                 contact_frame(S, obst[i], x0 + 3 * i, nrm, phi);
-                const double *ub = ubr + 3 * i;
+                const auto ub = ubr + 3 * i;
                 const double mu = S.obst[obst[i]].mu;
                 const double un = nrm[0] * ub[0] + nrm[1] * ub[1] + nrm[2] * ub[2];
                 const double a = un + phi / h;
@@ -684,7 +797,7 @@ __global__ __launch_bounds__(kBlock) void k_backward(const SimDev *__restrict__ 
                 const double tau = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
                 t[0] /= tau; t[1] /= tau; t[2] /= tau;
                 const double s = mu * (-a) / tau;
-                double *T = S.tblk + 9 * (int64_t)i;
+                auto T = G(S.tblk) + 9 * (int64_t)i;
                 for (int r = 0; r < 3; ++r)
                     for (int c = 0; c < 3; ++c)
                         T[3 * r + c] = (1 - s) * ((r == c ? 1.0 : 0.0) - nrm[r] * nrm[c]) + s * t[r] * t[c] +
@@ -693,28 +806,29 @@ __global__ __launch_bounds__(kBlock) void k_backward(const SimDev *__restrict__ 
         }
         __syncthreads();
         // fixed point zeta <- P^{-1}[gbar + dP z + (P - M)(zeta - z)], z = T^T zeta
-        double *zeta = S.zeta, *zeta1 = S.zeta1;
+        auto zeta = G(S.zeta);
+        auto zeta1 = G(S.zeta1);
         int k = 0;
         bool ok = false, stalled = false;
         double dprev = 0.0, d5 = 0.0;
         int rising = 0;
         while (k < S.adj_max_iters) {
-            apply_TT(S, mode, zeta, S.zt);
+            apply_TT(S, mode, zeta, G(S.zt));
             __syncthreads();
-            projection_jacobian_apply<MIXED>(S, S.zt, S.wp, false, h);
+            projection_jacobian_apply<MIXED>(S, G(S.zt), G(S.wp), false, h);
             __syncthreads();
-            adjoint_rhs<MIXED>(S, gbar, S.wp, zeta, S.zt, T);
+            adjoint_rhs<MIXED>(S, gbar, G(S.wp), zeta, G(S.zt), T);
             __syncthreads();
-            solve_P(S, T, T, Y, zeta1);
+            solve_P(S, T, T, Y, zeta1, U);
             double dmax = 0.0, zmax = 0.0;
-            for (int i = threadIdx.x; i < 3 * m; i += kBlock) {
+            for (int i = threadIdx.x; i < 3 * m; i += (int)blockDim.x) {
                 dmax = fmax(dmax, fabs(zeta1[i] - zeta[i]));
                 zmax = fmax(zmax, fabs(zeta1[i]));
             }
             dmax = block_max(dmax, red);
             zmax = block_max(zmax, red);
             ++k;
-            double *tmp = zeta; zeta = zeta1; zeta1 = tmp;
+            auto tmp = zeta; zeta = zeta1; zeta1 = tmp;
             if (!(dmax > S.adj_tol * zmax)) { ok = true; break; }
             // divergence (3 rises in a row / non-finite) or a contraction too slow
             // to reach the tolerance within the remaining budget -> fallback
@@ -730,40 +844,41 @@ __global__ __launch_bounds__(kBlock) void k_backward(const SimDev *__restrict__ 
         }
         iters_total += k;
         if (!ok) {
-            if (threadIdx.x == 0) S.counters[2] += 1;
-            const int it = gmres_solve<MIXED>(S, mode, gbar, S.zeta, S.adj_tol, S.adj_max_iters, red, T, Y);
-            zeta = S.zeta;
+            if (threadIdx.x == 0) G(S.counters)[2] += 1;
+            const int it = gmres_solve<MIXED>(S, mode, gbar, G(S.zeta), S.adj_tol, S.adj_max_iters, red, T, Y, U);
+            zeta = G(S.zeta);
             if (it < 0) ++noconv;
             gm_total += it < 0 ? -it - 1 : it;
             (void)stalled;
         }
         // gradients of this step
-        apply_TT(S, mode, zeta, S.zt);
+        apply_TT(S, mode, zeta, G(S.zt));
         __syncthreads();
-        projection_jacobian_apply<MIXED>(S, S.zt, S.wp, true, h);
-        inactive_dw(S, S.zt, x1, h);
+        projection_jacobian_apply<MIXED>(S, G(S.zt), G(S.wp), true, h);
+        inactive_dw(S, G(S.zt), x1, h);
         __syncthreads();
         double dmu_local[kMaxObstacles];
         for (int o = 0; o < kMaxObstacles; ++o) dmu_local[o] = 0.0;
-        const double *gstep = S.gx_steps ? S.gx_steps + (int64_t)n * 3 * m : nullptr;
-        for (int i = threadIdx.x; i < m; i += kBlock) {
-            const double *z = S.zt + 3 * i;
+        const bool has_gstep = S.gx_steps != nullptr;
+        const auto gstep = G(S.gx_steps) + (has_gstep ? (int64_t)n * 3 * m : 0);
+        for (int i = threadIdx.x; i < m; i += (int)blockDim.x) {
+            const auto z = G(S.zt) + 3 * i;
             double r0 = 0, r1 = 0, r2 = 0;      // Delta P z
-            for (int p = S.inc_ptr[i]; p < S.inc_ptr[i + 1]; ++p) {
-                const int c = S.inc_con[p];
-                const double a = S.inc_coef[p];
-                r0 += a * S.wp[3 * c]; r1 += a * S.wp[3 * c + 1]; r2 += a * S.wp[3 * c + 2];
+            for (int p = G(S.inc_ptr)[i]; p < G(S.inc_ptr)[i + 1]; ++p) {
+                const int c = G(S.inc_con)[p];
+                const double a = G(S.inc_coef)[p];
+                r0 += a * G(S.wp)[3 * c]; r1 += a * G(S.wp)[3 * c + 1]; r2 += a * G(S.wp)[3 * c + 2];
             }
             double k0 = 0, k1 = 0, k2 = 0;      // K_s z
-            for (int p = S.ks_ptr[i]; p < S.ks_ptr[i + 1]; ++p) {
-                const int j = S.ks_col[p];
-                const double kv = MIXED ? (double)S.ks_valf[p] : S.ks_val[p];
-                k0 += kv * S.zt[3 * j]; k1 += kv * S.zt[3 * j + 1]; k2 += kv * S.zt[3 * j + 2];
+            for (int p = G(S.ks_ptr)[i]; p < G(S.ks_ptr)[i + 1]; ++p) {
+                const int j = G(S.ks_col)[p];
+                const double kv = MIXED ? (double)G(S.ks_valf)[p] : G(S.ks_val)[p];
+                k0 += kv * G(S.zt)[3 * j]; k1 += kv * G(S.zt)[3 * j + 1]; k2 += kv * G(S.zt)[3 * j + 2];
             }
             const double Hz[3] = {hh * k0 - r0, hh * k1 - r1, hh * k2 - r2};
-            const double mi = S.mass[i];
+            const double mi = G(S.mass)[i];
             double dx[3];
-            for (int d = 0; d < 3; ++d) dx[d] = S.gx[3 * i + d] - Hz[d] / h;
+            for (int d = 0; d < 3; ++d) dx[d] = G(S.gx)[3 * i + d] - Hz[d] / h;
             const uint8_t md = mode[i];
             if (md == STICK || md == SLIP) {
                 const int o = obst[i];
@@ -776,7 +891,7 @@ __global__ __launch_bounds__(kBlock) void k_backward(const SimDev *__restrict__ 
                     dphi = -nl / h;
                     for (int d = 0; d < 3; ++d) dn[d] = -(phi / h) * lam[d];
                 } else {
-                    const double *ub = ubr + 3 * i;
+                    const auto ub = ubr + 3 * i;
                     const double mu = S.obst[o].mu;
                     const double un = nrm[0] * ub[0] + nrm[1] * ub[1] + nrm[2] * ub[2];
                     const double a = un + phi / h;
@@ -804,18 +919,20 @@ __global__ __launch_bounds__(kBlock) void k_backward(const SimDev *__restrict__ 
                 }
             }
             for (int d = 0; d < 3; ++d) {
-                S.gx[3 * i + d] = dx[d] + (gstep ? gstep[3 * i + d] : 0.0);
-                S.gv[3 * i + d] = mi * z[d];
+                G(S.gx)[3 * i + d] = dx[d] + (has_gstep ? gstep[3 * i + d] : 0.0);
+                G(S.gv)[3 * i + d] = mi * z[d];
             }
         }
-        for (int o = 0; o < S.n_obst; ++o) dmu_acc[o] += block_sum(dmu_local[o], red);
+        for (int o = 0; o < S.n_obst; ++o) {
+            const double v = block_sum(dmu_local[o], red);   // one fixed-order sum per step
+            if (threadIdx.x == 0) G(S.dmu)[o] += v;
+        }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        for (int o = 0; o < S.n_obst; ++o) S.dmu[o] += dmu_acc[o];
-        S.counters[1] += iters_total;
-        S.counters[3] += noconv;
-        S.counters[4] += gm_total;
+        G(S.counters)[1] += iters_total;
+        G(S.counters)[3] += noconv;
+        G(S.counters)[4] += gm_total;
     }
 }
 
@@ -847,7 +964,7 @@ __global__ __launch_bounds__(kBlock) void k_region_grad(const double *__restrict
     __shared__ double red[kBlock / 64];
     for (int r = 0; r < nreg; ++r) {
         double acc = 0.0;
-        for (int c = threadIdx.x; c < nc; c += kBlock)
+        for (int c = threadIdx.x; c < nc; c += (int)blockDim.x)
             if (region[c] == r) acc += base_w[c] * dw[c];
         acc = block_sum(acc, red);
         if (threadIdx.x == 0) out[r] = acc;
@@ -868,43 +985,78 @@ __global__ void k_fill(double *p, double v, int64_t n) {
 
 // ------------------------------------------------------------------ launchers
 
-hipError_t launch_forward(const SimDev *d_sims, int n, bool mixed, size_t lds, hipStream_t st) {
-    const int lv = lds > 0 ? 1 : 0;
-    if (mixed) hipLaunchKernelGGL(k_forward<true>, dim3(n), dim3(kBlock), lds, st, d_sims, lv);
-    else hipLaunchKernelGGL(k_forward<false>, dim3(n), dim3(kBlock), lds, st, d_sims, lv);
+template <bool MIXED, int FL>
+static void fwd_one(const SimDev *d, int n, size_t lds, hipStream_t st) {
+    hipLaunchKernelGGL((k_forward<MIXED, FL>), dim3(n), dim3(kBlock), lds, st, d);
+}
+template <bool MIXED, int FL>
+static void bwd_one(const SimDev *d, int n, size_t lds, hipStream_t st) {
+    hipLaunchKernelGGL((k_backward<MIXED, FL>), dim3(n), dim3(kBlockAdj), lds, st, d);
+}
+
+hipError_t launch_forward(const SimDev *d_sims, int n, bool mixed, size_t lds, int flags, hipStream_t st) {
+    using F = void (*)(const SimDev *, int, size_t, hipStream_t);
+    static const F tab[2][8] = {
+        {fwd_one<false, 0>, fwd_one<false, 1>, fwd_one<false, 2>, fwd_one<false, 3>, fwd_one<false, 4>,
+         fwd_one<false, 5>, fwd_one<false, 6>, fwd_one<false, 7>},
+        {fwd_one<true, 0>, fwd_one<true, 1>, fwd_one<true, 2>, fwd_one<true, 3>, fwd_one<true, 4>,
+         fwd_one<true, 5>, fwd_one<true, 6>, fwd_one<true, 7>}};
+    tab[mixed ? 1 : 0][flags & 7](d_sims, n, lds, st);
     return hipGetLastError();
 }
 
-hipError_t launch_backward(const SimDev *d_sims, int n, bool mixed, size_t lds, hipStream_t st) {
-    const int lv = lds > 0 ? 1 : 0;
-    if (mixed) hipLaunchKernelGGL(k_backward<true>, dim3(n), dim3(kBlock), lds, st, d_sims, lv);
-    else hipLaunchKernelGGL(k_backward<false>, dim3(n), dim3(kBlock), lds, st, d_sims, lv);
+hipError_t launch_backward(const SimDev *d_sims, int n, bool mixed, size_t lds, int flags, hipStream_t st) {
+    using F = void (*)(const SimDev *, int, size_t, hipStream_t);
+    static const F tab[2][4] = {{bwd_one<false, 0>, bwd_one<false, 1>, bwd_one<false, 2>, bwd_one<false, 3>},
+                                {bwd_one<true, 0>, bwd_one<true, 1>, bwd_one<true, 2>, bwd_one<true, 3>}};
+    tab[mixed ? 1 : 0][flags & 3](d_sims, n, lds, st);
     return hipGetLastError();
 }
 
-// Allow the dynamic LDS the kernels may request (solve vectors resident in LDS).
+// Allow the dynamic LDS the kernels may request (data resident in LDS).
+template <bool MIXED, int FL>
+static hipError_t set_fwd(size_t bytes) {
+    return hipFuncSetAttribute((const void *)k_forward<MIXED, FL>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+template <bool MIXED, int FL>
+static hipError_t set_bwd(size_t bytes) {
+    return hipFuncSetAttribute((const void *)k_backward<MIXED, FL>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
 hipError_t configure_lds(size_t fwd_bytes, size_t bwd_bytes) {
-    hipError_t e = hipSuccess;
-    for (auto f : {(const void *)k_forward<true>, (const void *)k_forward<false>}) {
-        hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fwd_bytes);
-        if (r != hipSuccess) e = r;
-    }
-    for (auto f : {(const void *)k_backward<true>, (const void *)k_backward<false>}) {
-        hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bwd_bytes);
-        if (r != hipSuccess) e = r;
-    }
+    hipError_t e = hipSuccess, r;
+#define DC_SETF(M, F) if ((r = set_fwd<M, F>(fwd_bytes)) != hipSuccess) e = r;
+#define DC_SETB(M, F) if ((r = set_bwd<M, F>(bwd_bytes)) != hipSuccess) e = r;
+    DC_SETF(false, 0) DC_SETF(false, 1) DC_SETF(false, 2) DC_SETF(false, 3)
+    DC_SETF(false, 4) DC_SETF(false, 5) DC_SETF(false, 6) DC_SETF(false, 7)
+    DC_SETF(true, 0) DC_SETF(true, 1) DC_SETF(true, 2) DC_SETF(true, 3)
+    DC_SETF(true, 4) DC_SETF(true, 5) DC_SETF(true, 6) DC_SETF(true, 7)
+    DC_SETB(false, 0) DC_SETB(false, 1) DC_SETB(false, 2) DC_SETB(false, 3)
+    DC_SETB(true, 0) DC_SETB(true, 1) DC_SETB(true, 2) DC_SETB(true, 3)
+#undef DC_SETF
+#undef DC_SETB
     return e;
 }
 
-// Static LDS of the kernels (reductions, GMRES workspace).
+// Largest static LDS over the kernel variants (reductions, GMRES workspace).
 hipError_t kernel_static_lds(size_t *fwd, size_t *bwd) {
     hipFuncAttributes a;
-    hipError_t e = hipFuncGetAttributes(&a, (const void *)k_forward<false>);
-    if (e != hipSuccess) return e;
-    *fwd = a.sharedSizeBytes;
-    e = hipFuncGetAttributes(&a, (const void *)k_backward<false>);
-    if (e != hipSuccess) return e;
-    *bwd = a.sharedSizeBytes;
+    *fwd = 0;
+    *bwd = 0;
+    const void *fk[] = {(const void *)k_forward<false, 0>, (const void *)k_forward<false, 7>,
+                        (const void *)k_forward<true, 0>, (const void *)k_forward<true, 7>};
+    const void *bk[] = {(const void *)k_backward<false, 0>, (const void *)k_backward<false, 3>,
+                        (const void *)k_backward<true, 0>, (const void *)k_backward<true, 3>};
+    for (const void *f : fk) {
+        hipError_t e = hipFuncGetAttributes(&a, f);
+        if (e != hipSuccess) return e;
+        *fwd = a.sharedSizeBytes > *fwd ? a.sharedSizeBytes : *fwd;
+    }
+    for (const void *f : bk) {
+        hipError_t e = hipFuncGetAttributes(&a, f);
+        if (e != hipSuccess) return e;
+        *bwd = a.sharedSizeBytes > *bwd ? a.sharedSizeBytes : *bwd;
+    }
     return hipSuccess;
 }
 

@@ -9,9 +9,38 @@
 namespace dc {
 
 constexpr int kMaxObstacles = 8;
-constexpr int kBlock = 1024;         // threads per workgroup (16 wavefronts)
+constexpr int kBlock = 1024;         // threads per workgroup of the forward kernel (16 wavefronts)
+constexpr int kBlockAdj = 1024;      // threads per workgroup of the adjoint kernel
 constexpr int kTeam = 8;             // lanes cooperating on one solve row / column
 constexpr int kKryM = 60;            // GMRES restart length of the adjoint fallback
+
+// Packed solve work items (shared host/device layout).
+struct FwdItem {            // forward: one row r of a stacked block G_s
+    int32_t g;              // offset of G_s[r, 0] in gval (column stride ld)
+    int16_t ld, kmax;       // column stride (ns + nR) and number of columns used
+    int32_t tbase;          // 3 * c0: first right-hand-side entry of the supernode
+    int32_t out;            // >= 0: 3 * (c0 + r) in the forward result; < 0: -(ubuf offset) - 1
+};
+struct BwdItem {            // backward: one column k of a stacked block G_s
+    int32_t g;              // offset of G_s[0, k] in gvalt (row-major copy, row stride nsz)
+    int16_t k, ld;          // first row used and column length
+    int16_t nsz, pad;       // diagonal-block size = row stride of the row-major copy
+    int32_t ybase;          // 3 * c0
+    int32_t rbase;          // offset into sup_rows of row nsz of this block (= rptr - nsz)
+    int32_t out;            // 3 * (c0 + k)
+    int32_t pad2;
+};
+struct RowItem {            // forward gather: t_i = b_i - sum of update entries
+    int32_t i3;             // 3 * i
+    int32_t p0, p1;         // range in upd_off
+    int32_t pad;
+};
+struct SpringInc {          // node-centred spring projection: one incident spring
+    int32_t a, b;           // endpoints (new ids), q = x_a - x_b
+    int32_t sign;           // +1 if this node is a, -1 if b
+    int32_t pad;
+    double rho, w;          // rest length and weight
+};
 
 struct ObstacleDev {
     int type;                         // 0 plane, 1 sphere
@@ -49,18 +78,24 @@ struct SimDev {
     // supernodal factor of P_s (new order): per supernode the stacked dense block
     // G_s = [L_ss^{-1}; B_s L_ss^{-1}], column-major (ns + nR) x ns
     int n_levels;
-    const int32_t *lvl_rows_ptr;      // [n_levels+1] into lvl_rows
-    const int32_t *lvl_rows;          // columns of each level's supernodes
-    const int32_t *lvl_items_ptr;     // [n_levels+1] into item_sup / item_row
-    const int32_t *item_sup, *item_row;   // forward items: (supernode, row of G_s)
-    const int32_t *sup_of;            // [m] supernode of each column
-    const int32_t *sup_c0, *sup_ns, *sup_nr;
-    const int64_t *sup_goff;          // offset of G_s in gval
-    const int32_t *sup_rptr, *sup_rows;   // off-diagonal row structure R_s
-    const int32_t *sup_uoff;          // offset of u_s = B_s y_s in ubuf
-    const double *gval;
-    const int32_t *upd_ptr, *upd_off; // per column: ubuf offsets gathered by the forward solve
-    double *ubuf;                     // update vectors u_s (3 per row of R_s)
+    const int32_t *lvl_rows_ptr;      // [n_levels+1] into rows / bwd items (columns of each level)
+    const int32_t *lvl_items_ptr;     // [n_levels+1] into fwd items
+    const int32_t *lvl_team;          // [2*n_levels] lanes per item: forward, backward
+    const RowItem *rows;
+    const FwdItem *fitems;
+    const BwdItem *bitems;
+    const int32_t *sup_rows;          // off-diagonal row structure R_s (concatenated)
+    const double *gval;               // stacked blocks, column-major (forward)
+    const double *gvalt;              // the same blocks, row-major (backward)
+    const int32_t *upd_off;           // ubuf offsets gathered by the forward solve
+    double *ubuf;                     // update vectors u_s (3 per row of R_s), HBM copy
+    int n_ubuf;                       // doubles in ubuf
+    // springs, node-centred (forward local step + RHS gather in one pass)
+    const int32_t *sinc_ptr;          // [m+1]
+    const SpringInc *sinc;
+    int nca_bend;                     // active (curved) bending constraints: device indices [nca - nca_bend, nca)
+    const int32_t *binc_ptr, *binc_con;   // node -> active bending constraint incidence
+    const double *binc_coef;
 
     // ---------------------------------------------------------------- state and work
     double *x, *v;                    // state x_n, v_n
@@ -92,7 +127,8 @@ struct SimDev {
     const double *gx_steps;           // optional per-step dL/dx_n [(T+1)*m*3], new order
 
     // Krylov fallback workspace (GMRES)
-    double *kry;                      // [(kKryM+1) * m*3] Krylov basis
+    double *kry;                      // [(kry_m+1) * m*3] Krylov basis
+    int kry_m;                        // GMRES restart length (<= kKryM)
 
     // run control for one launch
     int step_begin, step_end;         // forward: steps [begin, end); backward: reverse
