@@ -183,6 +183,21 @@ int sim_create(const sim_mesh_t *mesh, const sim_params_t *params, void *hip_str
  * = rest shape; NULL v0 = zero.  Invalidates any recorded rollout. */
 int sim_set_state(sim_t *sim, const double *x0_dev, const double *v0_dev);
 
+/* Changes the material of a handle and refactors P (Sec. 3.1: P depends on
+ * the constraint weights only, so a weight change is a numeric refactor on
+ * the handle's ordering and symbolic structure; the mesh, masses and
+ * obstacles' geometry stay).  Host arrays, each NULL = keep:
+ *   edge_stiffness [n_edges], bend_weight (one scalar), region_scale
+ *   [n_regions] (SIM_EINVAL if the handle has no regions), obstacle_mu
+ *   [n_obstacles] (friction only; no refactor).
+ * Weights must be finite and >= 0 (SIM_ENONFINITE / SIM_EINVAL); a weight
+ * that was exactly 0 at sim_create and becomes nonzero changes the sparsity
+ * pattern of P and is rejected with SIM_EINVAL; a non-positive pivot returns
+ * SIM_ENOTSPD.  On any error the handle keeps its previous material.
+ * Invalidates any recorded rollout; synchronises the handle's stream. */
+int sim_set_material(sim_t *sim, const double *edge_stiffness, const double *bend_weight,
+                     const double *region_scale, const double *obstacle_mu);
+
 /* Runs n_steps implicit-Euler steps with dry frictional contact from the
  * initial state and records what the backward pass needs.  Optional outputs:
  * x_traj_dev [(n_steps+1)*n_nodes*3] (x_0 .. x_T), xT_dev, vT_dev [n_nodes*3]. */

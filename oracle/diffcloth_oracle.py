@@ -567,6 +567,8 @@ def backward(model: Model, recs: List[StepRecord], dL_dxT: np.ndarray, dL_dvT=No
     """Backpropagation through the whole rollout (Sec. 4.1, eqn adjoint): the
     per-step adjoints chained from the last step to the first."""
     gx = np.asarray(dL_dxT, float).copy()
+    if dL_dx_steps is not None:                               # a per-step loss term on x_T as well
+        gx = gx + dL_dx_steps[len(recs)]
     gv = np.zeros_like(gx) if dL_dvT is None else np.asarray(dL_dvT, float).copy()
     dw = np.zeros(model.nc)
     dmu = np.zeros(len(model.obstacles))

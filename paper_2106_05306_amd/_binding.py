@@ -75,6 +75,7 @@ def lib():
             "sim_create": (c_int32, [POINTER(SimMesh), POINTER(SimParams), c_void_p, ALLOC_FN, FREE_FN, c_void_p,
                                      POINTER(c_void_p)]),
             "sim_set_state": (c_int32, [c_void_p, c_void_p, c_void_p]),
+            "sim_set_material": (c_int32, [c_void_p, c_double_p, c_double_p, c_double_p, c_double_p]),
             "sim_forward": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
             "sim_backward": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, POINTER(SimGrads)]),
             "sim_adjoint_step": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,

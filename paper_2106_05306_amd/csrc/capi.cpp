@@ -55,6 +55,7 @@ struct sim {
     int T = -1;                         // steps of the recorded rollout (-1: none)
     int64_t counters_host[8] = {0};
     int nca = 0;
+    std::vector<int32_t> corder;        // device constraint slot -> canonical constraint id
     int64_t factor_bytes = 0;
     size_t lds_fwd = 0, lds_bwd = 0;   // dynamic LDS of the two kernels
     int flags_fwd = 0, flags_bwd = 0;  // what lives in LDS (kLds* bits)
@@ -133,6 +134,106 @@ void plan_lds(sim *s, int &flags, size_t &bytes, bool fwd) {
     bytes = lds_bytes(s, flags, fwd);
 }
 
+// K_s in the new order: pattern (kp, kc) and values in both precisions.
+void ks_new_order(const HostModel &hm, std::vector<int32_t> &kp, std::vector<int32_t> &kc, std::vector<double> &kv,
+                  std::vector<float> &kvf) {
+    const int m = hm.m;
+    kp.assign(1, 0);
+    kc.clear();
+    kv.clear();
+    kvf.clear();
+    for (int i = 0; i < m; ++i) {
+        const int o = hm.perm[i];
+        std::vector<std::pair<int, double>> row;
+        for (int k = hm.ks_ptr[o]; k < hm.ks_ptr[o + 1]; ++k) row.push_back({hm.iperm[hm.ks_col[k]], hm.ks_val[k]});
+        std::sort(row.begin(), row.end());
+        for (auto &pr : row) { kc.push_back(pr.first); kv.push_back(pr.second); kvf.push_back((float)pr.second); }
+        kp.push_back((int32_t)kc.size());
+    }
+}
+
+// Supernodal factor stacked per supernode as G_s = [L_ss^{-1}; B_s L_ss^{-1}]
+// (column-major (ns + nR) x ns, offset goff[s]) with B_s = L(R_s, s) the
+// off-diagonal block:
+//   forward  y_s = L_ss^{-1} t_s and u_s = B_s y_s = (B_s L_ss^{-1}) t_s in one product,
+//   backward x_s = L_ss^{-T} y_s - (B_s L_ss^{-1})^T x_{R_s}.
+// gvalt holds every block again, row-major, for the backward solve.
+void stacked_factor(const HostModel &hm, std::vector<double> &gval, std::vector<double> &gvalt,
+                    std::vector<int64_t> &goff) {
+    const int ns = hm.ns;
+    goff.assign(ns, 0);
+    gval.clear();
+    for (int sn = 0; sn < ns; ++sn) {
+        const int nsz = hm.sup_c0[sn + 1] - hm.sup_c0[sn];
+        const int nR = hm.R_ptr[sn + 1] - hm.R_ptr[sn], nrow = nsz + nR;
+        const std::vector<double> &F = hm.Lblk[sn];       // column-major nrow x nsz, L_ss on top
+        std::vector<double> inv((size_t)nsz * nsz, 0.0);   // row-major L_ss^{-1}
+        for (int j = 0; j < nsz; ++j) {
+            for (int i = j; i < nsz; ++i) {
+                double acc = i == j ? 1.0 : 0.0;
+                for (int k = j; k < i; ++k) acc -= F[(size_t)k * nrow + i] * inv[(size_t)k * nsz + j];
+                inv[(size_t)i * nsz + j] = acc / F[(size_t)i * nrow + i];
+            }
+        }
+        goff[sn] = (int64_t)gval.size();
+        gval.resize(gval.size() + (size_t)nrow * nsz, 0.0);
+        double *G = gval.data() + goff[sn];
+        for (int k = 0; k < nsz; ++k) {
+            for (int r = k; r < nsz; ++r) G[(size_t)k * nrow + r] = inv[(size_t)r * nsz + k];
+            for (int q = 0; q < nR; ++q) {
+                double acc = 0.0;
+                for (int j = k; j < nsz; ++j) acc += F[(size_t)j * nrow + nsz + q] * inv[(size_t)j * nsz + k];
+                G[(size_t)k * nrow + nsz + q] = acc;
+            }
+        }
+    }
+    gvalt.assign(gval.size(), 0.0);
+    for (int sn = 0; sn < ns; ++sn) {
+        const int nsz = hm.sup_c0[sn + 1] - hm.sup_c0[sn], ld = nsz + hm.R_ptr[sn + 1] - hm.R_ptr[sn];
+        const double *G = gval.data() + goff[sn];
+        double *Gt = gvalt.data() + goff[sn];
+        for (int k = 0; k < nsz; ++k)
+            for (int r = 0; r < ld; ++r) Gt[(size_t)r * nsz + k] = G[(size_t)k * ld + r];
+    }
+}
+
+// Weights of the device constraint slots (canonical ids in corder).
+void slot_weights(const HostModel &hm, const std::vector<int32_t> &corder, std::vector<double> &cw,
+                  std::vector<float> &cwf) {
+    cw.clear();
+    cwf.clear();
+    for (int c : corder) {
+        cw.push_back(hm.w[c]);
+        cwf.push_back((float)hm.w[c]);
+    }
+}
+
+// Node-centred springs (active springs only): every node lists the springs
+// it ends, with the spring's other data inlined.
+void spring_incidence(const HostModel &hm, const std::vector<int32_t> &corder, int nca, std::vector<int32_t> &sp,
+                      std::vector<SpringInc> &sv, int &nca_bend) {
+    const int m = hm.m;
+    std::vector<std::vector<SpringInc>> sl(m);
+    nca_bend = 0;
+    for (int c = 0; c < nca; ++c) {
+        const int canon = corder[c];
+        if (canon < hm.n_edges) {
+            const int a = hm.iperm[hm.c_node[hm.c_ptr[canon]]], b = hm.iperm[hm.c_node[hm.c_ptr[canon] + 1]];
+            const double w0 = hm.w[canon], r0 = hm.rho[canon];
+            sl[a].push_back(SpringInc{a, b, +1, c, r0, w0});
+            sl[b].push_back(SpringInc{a, b, -1, c, r0, w0});
+        } else {
+            ++nca_bend;
+        }
+    }
+    sp.assign(1, 0);
+    sv.clear();
+    for (int i = 0; i < m; ++i) {
+        sv.insert(sv.end(), sl[i].begin(), sl[i].end());
+        sp.push_back((int32_t)sv.size());
+    }
+}
+
 // Build every device table from the host model and upload it.
 void build_device(sim *s) {
     HostModel &hm = s->hm;
@@ -170,17 +271,10 @@ void build_device(sim *s) {
     for (int i = 0; i < m; ++i) mass[i] = hm.mass[perm[i]];
     D.mass = upload(s, mass);
     // K_s in the new order
-    std::vector<int32_t> kp(1, 0), kc;
+    std::vector<int32_t> kp, kc;
     std::vector<double> kv;
     std::vector<float> kvf;
-    for (int i = 0; i < m; ++i) {
-        const int o = perm[i];
-        std::vector<std::pair<int, double>> row;
-        for (int k = hm.ks_ptr[o]; k < hm.ks_ptr[o + 1]; ++k) row.push_back({iperm[hm.ks_col[k]], hm.ks_val[k]});
-        std::sort(row.begin(), row.end());
-        for (auto &pr : row) { kc.push_back(pr.first); kv.push_back(pr.second); kvf.push_back((float)pr.second); }
-        kp.push_back((int32_t)kc.size());
-    }
+    ks_new_order(hm, kp, kc, kv, kvf);
     D.ks_ptr = upload(s, kp);
     D.ks_col = upload(s, kc);
     D.ks_val = upload(s, kv);
@@ -194,9 +288,11 @@ void build_device(sim *s) {
         if (!(hm.rho[c] > 0)) order.push_back(c);
     D.nca = nca;
     s->nca = nca;
+    s->corder = order;
     std::vector<int32_t> cp(1, 0), cn, cid;
     std::vector<double> cc, crho, cw, crd;
     std::vector<float> crhof, cwf;
+    slot_weights(hm, order, cw, cwf);
     for (int c : order) {
         for (int k = hm.c_ptr[c]; k < hm.c_ptr[c + 1]; ++k) {
             cn.push_back(iperm[hm.c_node[k]]);
@@ -205,9 +301,7 @@ void build_device(sim *s) {
         cp.push_back((int32_t)cn.size());
         cid.push_back(c);
         crho.push_back(hm.rho[c]);
-        cw.push_back(hm.w[c]);
         crhof.push_back((float)hm.rho[c]);
-        cwf.push_back((float)hm.w[c]);
         for (int d = 0; d < 3; ++d) crd.push_back(hm.restdir[3 * c + d]);
     }
     D.c_ptr = upload(s, cp);
@@ -244,43 +338,19 @@ void build_device(sim *s) {
     D.att_node = upload(s, an);
     D.att_of = upload(s, aof);
     D.att_rest = upload(s, arest);
-    // supernodal factor, stacked per supernode as G_s = [L_ss^{-1}; B_s L_ss^{-1}]
-    // (column-major (ns + nR) x ns), with B_s = L(R_s, s) the off-diagonal block:
-    //   forward  y_s = L_ss^{-1} t_s and u_s = B_s y_s = (B_s L_ss^{-1}) t_s in one product,
-    //   backward x_s = L_ss^{-T} y_s - (B_s L_ss^{-1})^T x_{R_s}.
+    // supernodal factor (stacked blocks) and the solve's update-vector layout
     const int ns = hm.ns;
+    std::vector<double> gval, gvalt;
+    std::vector<int64_t> goff;
+    stacked_factor(hm, gval, gvalt, goff);
     std::vector<int32_t> sc0(ns), sns(ns), snr(ns), rptr(ns + 1, 0), rows, uoff(ns + 1, 0);
-    std::vector<int64_t> goff(ns);
-    std::vector<double> gval;
     for (int sn = 0; sn < ns; ++sn) {
-        const int c0 = hm.sup_c0[sn], nsz = hm.sup_c0[sn + 1] - c0;
-        const int nR = hm.R_ptr[sn + 1] - hm.R_ptr[sn], nrow = nsz + nR;
-        const std::vector<double> &F = hm.Lblk[sn];       // column-major nrow x nsz, L_ss on top
-        sc0[sn] = c0;
-        sns[sn] = nsz;
-        snr[sn] = nR;
-        std::vector<double> inv((size_t)nsz * nsz, 0.0);   // row-major L_ss^{-1}
-        for (int j = 0; j < nsz; ++j) {
-            for (int i = j; i < nsz; ++i) {
-                double acc = i == j ? 1.0 : 0.0;
-                for (int k = j; k < i; ++k) acc -= F[(size_t)k * nrow + i] * inv[(size_t)k * nsz + j];
-                inv[(size_t)i * nsz + j] = acc / F[(size_t)i * nrow + i];
-            }
-        }
-        goff[sn] = (int64_t)gval.size();
-        gval.resize(gval.size() + (size_t)nrow * nsz, 0.0);
-        double *G = gval.data() + goff[sn];
-        for (int k = 0; k < nsz; ++k) {
-            for (int r = k; r < nsz; ++r) G[(size_t)k * nrow + r] = inv[(size_t)r * nsz + k];
-            for (int q = 0; q < nR; ++q) {
-                double acc = 0.0;
-                for (int j = k; j < nsz; ++j) acc += F[(size_t)j * nrow + nsz + q] * inv[(size_t)j * nsz + k];
-                G[(size_t)k * nrow + nsz + q] = acc;
-            }
-        }
-        for (int q = 0; q < nR; ++q) rows.push_back(hm.R_rows[hm.R_ptr[sn] + q]);
+        sc0[sn] = hm.sup_c0[sn];
+        sns[sn] = hm.sup_c0[sn + 1] - hm.sup_c0[sn];
+        snr[sn] = hm.R_ptr[sn + 1] - hm.R_ptr[sn];
+        for (int q = 0; q < snr[sn]; ++q) rows.push_back(hm.R_rows[hm.R_ptr[sn] + q]);
         rptr[sn + 1] = (int32_t)rows.size();
-        uoff[sn + 1] = uoff[sn] + 3 * nR;
+        uoff[sn + 1] = uoff[sn] + 3 * snr[sn];
     }
     // per column: the update-vector entries it gathers in the forward solve (ascending supernode)
     std::vector<std::vector<int32_t>> upd(m);
@@ -352,40 +422,15 @@ void build_device(sim *s) {
     D.bitems = upload(s, bitems);
     D.sup_rows = upload(s, rows);
     D.gval = upload(s, gval);
-    {   // row-major copy of every block for the backward solve (coalesced across columns)
-        std::vector<double> gt(gval.size());
-        for (int sn = 0; sn < ns; ++sn) {
-            const int nsz = sns[sn], ld = nsz + snr[sn];
-            const double *G = gval.data() + goff[sn];
-            double *Gt = gt.data() + goff[sn];
-            for (int k = 0; k < nsz; ++k)
-                for (int r = 0; r < ld; ++r) Gt[(size_t)r * nsz + k] = G[(size_t)k * ld + r];
-        }
-        D.gvalt = upload(s, gt);
-    }
+    D.gvalt = upload(s, gvalt);
     D.upd_off = upload(s, uo);
     D.n_ubuf = std::max(uoff[ns], 3);
     D.ubuf = zeros<double>(s, D.n_ubuf);
-    // node-centred springs (active springs only) and active curved-bending incidence
-    std::vector<std::vector<SpringInc>> sl(m);
-    int nca_bend = 0;
-    for (int c = 0; c < nca; ++c) {
-        const int canon = order[c];
-        if (canon < hm.n_edges) {
-            const int a = cn[cp[c]], b = cn[cp[c] + 1];
-            const double w0 = cw[c], r0 = crho[c];
-            sl[a].push_back(SpringInc{a, b, +1, c, r0, w0});
-            sl[b].push_back(SpringInc{a, b, -1, c, r0, w0});
-        } else {
-            ++nca_bend;
-        }
-    }
-    std::vector<int32_t> sp(1, 0);
+    // node-centred springs and active curved-bending incidence
+    std::vector<int32_t> sp;
     std::vector<SpringInc> sv;
-    for (int i = 0; i < m; ++i) {
-        sv.insert(sv.end(), sl[i].begin(), sl[i].end());
-        sp.push_back((int32_t)sv.size());
-    }
+    int nca_bend = 0;
+    spring_incidence(hm, order, nca, sp, sv, nca_bend);
     D.sinc_ptr = upload(s, sp);
     D.sinc = upload(s, sv);
     D.nca_bend = nca_bend;
@@ -577,6 +622,86 @@ int sim_set_state(sim_t *s, const double *x0_dev, const double *v0_dev) {
     if (rc) return rc;
     s->T = -1;
     return SIM_OK;
+}
+
+
+int sim_set_material(sim_t *s, const double *edge_stiffness, const double *bend_weight, const double *region_scale,
+                     const double *obstacle_mu) {
+    if (!s) return SIM_EINVAL;
+    const HostModel &hm = s->hm;
+    auto bad = [](double v) { return !std::isfinite(v); };
+    if (edge_stiffness)
+        for (int e = 0; e < hm.n_edges; ++e) {
+            if (bad(edge_stiffness[e])) return SIM_ENONFINITE;
+            if (edge_stiffness[e] < 0) return SIM_EINVAL;
+        }
+    if (bend_weight) {
+        if (bad(*bend_weight)) return SIM_ENONFINITE;
+        if (*bend_weight < 0) return SIM_EINVAL;
+    }
+    if (region_scale) {
+        if (hm.region_scale.empty()) return SIM_EINVAL;
+        for (size_t r = 0; r < hm.region_scale.size(); ++r) {
+            if (bad(region_scale[r])) return SIM_ENONFINITE;
+            if (region_scale[r] < 0) return SIM_EINVAL;
+        }
+    }
+    if (obstacle_mu)
+        for (size_t o = 0; o < hm.obstacles.size(); ++o) {
+            if (bad(obstacle_mu[o])) return SIM_ENONFINITE;
+            if (obstacle_mu[o] < 0) return SIM_EINVAL;
+        }
+    return guarded([&] {
+        HostModel nm = hm;                        // the handle keeps its material until all succeeded
+        if (edge_stiffness)
+            for (int e = 0; e < nm.n_edges; ++e) nm.base_w[e] = edge_stiffness[e];
+        if (bend_weight)
+            for (int b = 0; b < nm.n_bend; ++b) nm.base_w[nm.n_edges + b] = *bend_weight;
+        if (region_scale) nm.region_scale.assign(region_scale, region_scale + nm.region_scale.size());
+        if (obstacle_mu)
+            for (size_t o = 0; o < nm.obstacles.size(); ++o) nm.obstacles[o].mu = obstacle_mu[o];
+        const bool refactor = edge_stiffness || bend_weight || region_scale;
+        SimDev &D = s->hd;
+        std::vector<int32_t> kp, kc, sp;
+        std::vector<double> kv, cw, gval, gvalt;
+        std::vector<float> kvf, cwf;
+        std::vector<int64_t> goff;
+        std::vector<SpringInc> sv;
+        int rc = SIM_OK;
+        if (refactor) {
+            nm.apply_regions();
+            rc = nm.assemble_ks(true);
+            if (!rc) rc = nm.factor();
+            if (rc) return rc;
+            ks_new_order(nm, kp, kc, kv, kvf);
+            slot_weights(nm, s->corder, cw, cwf);
+            int nca_bend = 0;
+            spring_incidence(nm, s->corder, s->nca, sp, sv, nca_bend);
+            stacked_factor(nm, gval, gvalt, goff);
+            auto put = [&](const void *dst, const void *src, size_t bytes) {
+                if (!rc && bytes)
+                    rc = hip_err(hipMemcpyAsync(const_cast<void *>(dst), src, bytes, hipMemcpyHostToDevice, s->stream));
+            };
+            put(D.ks_val, kv.data(), kv.size() * sizeof(double));
+            put(D.ks_valf, kvf.data(), kvf.size() * sizeof(float));
+            put(D.c_w, cw.data(), cw.size() * sizeof(double));
+            put(D.c_wf, cwf.data(), cwf.size() * sizeof(float));
+            put(D.sinc, sv.data(), sv.size() * sizeof(SpringInc));
+            put(D.gval, gval.data(), gval.size() * sizeof(double));
+            put(D.gvalt, gvalt.data(), gvalt.size() * sizeof(double));
+            put(s->d_basew, nm.base_w.data(), nm.base_w.size() * sizeof(double));
+        }
+        if (!rc) {
+            for (size_t o = 0; o < nm.obstacles.size(); ++o) D.obst[o].mu = nm.obstacles[o].mu;
+            rc = push_desc(s);
+        }
+        const int rs = hip_err(hipStreamSynchronize(s->stream));    // host staging buffers end here
+        if (!rc) rc = rs;
+        if (rc) return rc;
+        s->hm = std::move(nm);
+        s->T = -1;
+        return SIM_OK;
+    });
 }
 
 namespace {

@@ -160,20 +160,21 @@ int HostModel::build(const sim_mesh_t *mesh, const sim_params_t *p) {
     if (!finite_all(base_w.data(), nc)) { error = "non-finite weights"; return SIM_ENONFINITE; }
     for (double v : base_w)
         if (v < 0) { error = "weights must be >= 0"; return SIM_EINVAL; }
-    w = base_w;
     region.clear();
     region_scale.clear();
     if (p->region_scale && p->n_regions > 0) {
         if (!p->edge_region || !p->bend_region) { error = "regions need edge_region and bend_region"; return SIM_EINVAL; }
         region_scale.assign(p->region_scale, p->region_scale + p->n_regions);
+        if (!finite_all(region_scale.data(), region_scale.size())) { error = "non-finite region scale"; return SIM_ENONFINITE; }
+        for (double v : region_scale)
+            if (v < 0) { error = "region scales must be >= 0"; return SIM_EINVAL; }
         region.resize(nc);
         for (int e = 0; e < n_edges; ++e) region[e] = p->edge_region[e];
         for (int b = 0; b < n_bend; ++b) region[n_edges + b] = p->bend_region[bend_center[b]];
-        for (int c = 0; c < nc; ++c) {
+        for (int c = 0; c < nc; ++c)
             if (region[c] < 0 || region[c] >= p->n_regions) { error = "region index out of range"; return SIM_EINVAL; }
-            w[c] = base_w[c] * region_scale[region[c]];
-        }
     }
+    apply_regions();
     // rest norms and directions; flat bending (|l(X)| <= 1e-10 sum_k |c_k||X_k - X_b|) has no target
     rho.assign(nc, 0.0);
     restdir.assign(3 * (size_t)nc, 0.0);
@@ -208,7 +209,21 @@ int HostModel::build(const sim_mesh_t *mesh, const sim_params_t *p) {
         for (int d = 0; d < 3; ++d) att_axis[d] /= an;
     }
 
-    // ---------------------------------------------------------------- K_s
+    return assemble_ks(false);
+}
+
+// Effective constraint weights: base weight times its region scale (if any).
+void HostModel::apply_regions() {
+    w = base_w;
+    if (!region.empty())
+        for (int c = 0; c < nc; ++c) w[c] = base_w[c] * region_scale[region[c]];
+}
+
+// K_s = sum_c w_c a_c a_c^T + w_att sum_att e_j e_j^T.  The first call fixes
+// the sparsity pattern (exact zeros off the diagonal dropped); later calls
+// (keep_pattern) refill the values on that pattern and fail if a nonzero
+// falls outside it.
+int HostModel::assemble_ks(bool keep_pattern) {
     std::vector<std::map<int, double>> rows(m);
     for (int c = 0; c < nc; ++c) {
         for (int k = c_ptr[c]; k < c_ptr[c + 1]; ++k)
@@ -217,6 +232,23 @@ int HostModel::build(const sim_mesh_t *mesh, const sim_params_t *p) {
     }
     for (int a : attach) rows[a][a] += w_att;
     for (int i = 0; i < m; ++i) rows[i][i] += 0.0;   // keep the diagonal in the pattern
+    if (keep_pattern) {
+        std::vector<double> val(ks_col.size(), 0.0);
+        for (int i = 0; i < m; ++i) {
+            for (auto &kv : rows[i]) {
+                const auto b = ks_col.begin() + ks_ptr[i], e = ks_col.begin() + ks_ptr[i + 1];
+                const auto it = std::lower_bound(b, e, kv.first);
+                if (it == e || *it != kv.first) {
+                    if (kv.second == 0.0) continue;
+                    error = "the new weights change the sparsity pattern of K";
+                    return SIM_EINVAL;
+                }
+                val[it - ks_col.begin()] = kv.second;
+            }
+        }
+        ks_val.swap(val);
+        return SIM_OK;
+    }
     ks_ptr.assign(1, 0);
     ks_col.clear();
     ks_val.clear();
@@ -311,6 +343,11 @@ void nd_rec(NDCtx &c, std::vector<int32_t> nodes) {
 }  // namespace
 
 int HostModel::order_and_factor(int leaf_size) {
+    order(leaf_size);
+    return factor();
+}
+
+void HostModel::order(int leaf_size) {
     // ---------------------------------------------------------------- ordering
     NDCtx ctx;
     ctx.ptr = &ks_ptr;
@@ -377,8 +414,13 @@ int HostModel::order_and_factor(int leaf_size) {
         if (parent[s] >= 0) sup_level[parent[s]] = std::max(sup_level[parent[s]], sup_level[s] + 1);
         n_levels = std::max(n_levels, sup_level[s] + 1);
     }
+}
 
-    // ---------------------------------------------------------------- numeric (left-looking, dense blocks)
+// Numeric factorisation on the symbolic structure of order() (left-looking,
+// dense blocks); refactoring after a weight change reuses the structure.
+int HostModel::factor() {
+    std::vector<std::vector<int32_t>> R(ns);
+    for (int s = 0; s < ns; ++s) R[s].assign(R_rows.begin() + R_ptr[s], R_rows.begin() + R_ptr[s + 1]);
     Lblk.assign(ns, {});
     std::vector<std::vector<int32_t>> updaters(ns);
     std::vector<int32_t> rowpos(m, -1);

@@ -61,6 +61,10 @@ struct HostModel {
 
     int build(const sim_mesh_t *mesh, const sim_params_t *p);   // SIM_OK or SIM_E*
     int order_and_factor(int leaf_size);
+    void order(int leaf_size);               // ordering + symbolic structure
+    int factor();                            // numeric factor on that structure
+    void apply_regions();                    // w = base_w * region scale
+    int assemble_ks(bool keep_pattern);      // K_s values (pattern fixed after the first call)
 
     // dense copy of L in the new order (tests; m small)
     void dense_L(double *out) const;

@@ -149,6 +149,10 @@ class Sim:
         mesh, p, self._keep = build_structs(X, tris, node_mass, edge_stiffness, **kw)
         self.m = mesh.n_nodes
         self.n_regions = int(p.n_regions)
+        self._gen = 0                       # bumped by every call that replaces the recorded rollout
+        self.edge_region = None if kw.get("edge_region") is None else np.asarray(kw["edge_region"], np.int64)
+        self.bend_region = None if kw.get("bend_region") is None else np.asarray(kw["bend_region"], np.int64)
+        self.region_scale = None if kw.get("region_scale") is None else np.asarray(kw["region_scale"], np.float64)
         self.n_obstacles = int(p.n_obstacles)
         self.precision = kw.get("precision", "fp64")
         self._mesh, self._params = mesh, p
@@ -183,12 +187,34 @@ class Sim:
         self._keep["x0"], self._keep["v0"] = x0, v0
         B.check(B.lib().sim_set_state(self.h, _dptr(x0), _dptr(v0)), "sim_set_state")
         self.T = -1
+        self._gen += 1
+
+    def set_material(self, edge_stiffness=None, bend_weight=None, region_scale=None, mu=None):
+        """New constraint weights / friction (host values; None = keep); refactors P."""
+        def host(a, n):
+            if a is None:
+                return None, None
+            a = np.ascontiguousarray(np.asarray(a.detach().cpu() if torch.is_tensor(a) else a,
+                                                dtype=np.float64).reshape(-1))
+            if n > 0 and a.size != n:          # (n = 0: the library rejects the argument)
+                raise ValueError(f"expected {n} values, got {a.size}")
+            return a, a.ctypes.data_as(B.c_double_p)
+        k, kp = host(edge_stiffness, self.n_edges)
+        b, bp = host(bend_weight, 1)
+        r, rp = host(region_scale, self.n_regions)
+        u, up = host(mu, self.n_obstacles)
+        B.check(B.lib().sim_set_material(self.h, kp, bp, rp, up), "sim_set_material")
+        if r is not None:
+            self.region_scale = r.copy()
+        self.T = -1
+        self._gen += 1
 
     def forward(self, n_steps: int, trajectory: bool = False):
         xT, vT = self._vec(), self._vec()
         traj = torch.empty((n_steps + 1, self.m, 3), dtype=torch.float64, device=self.device) if trajectory else None
         B.check(B.lib().sim_forward(self.h, n_steps, _dptr(traj), _dptr(xT), _dptr(vT)), "sim_forward")
         self.T = n_steps
+        self._gen += 1
         return xT, vT, traj
 
     def _grads(self):
@@ -265,6 +291,7 @@ def batch_forward(sims: Sequence[Sim], n_steps: Sequence[int]):
     B.check(B.lib().sim_batch_forward(hs, n, st, xs, vs), "sim_batch_forward")
     for s, T in zip(sims, n_steps):
         s.T = T
+        s._gen += 1
     return outs
 
 

@@ -457,3 +457,71 @@ def test_gradients_match_central_finite_differences(obst):
             assert abs(val - G.dmu[0]) <= 1e-5 * abs(val) + 1e-10, (val, G.dmu[0])
             checks += 1
     assert checks >= 3
+
+
+# ------------------------------------------------------------------ losses, regions, per-step terms
+
+def test_apex_angle_of_a_cone_and_its_gradient():
+    # rest skirt: a frustum whose hem nodes lie on a circle of radius 0.30 m
+    sc = scenes.c3_skirt(0, n_around=10, n_rings=5, steps=1)
+    x = sc.X
+    r_hem = np.sqrt(x[sc.hem_nodes, 0] ** 2 + x[sc.hem_nodes, 2] ** 2).mean()
+    height = x[sc.waist_nodes, 1].mean() - x[sc.hem_nodes, 1].mean()
+    ang, g = O.apex_angle_loss(x, sc.waist_nodes, sc.hem_nodes)
+    assert np.isclose(ang, 2 * np.arctan(r_hem / height), rtol=1e-14)
+    assert np.isclose(np.tan(ang / 2), 0.30 / height, rtol=1e-12)      # hem nodes on the 0.30 m circle
+    rng = np.random.default_rng(3)
+    xp = x + rng.normal(0, 0.01, x.shape)
+    _, g = O.apex_angle_loss(xp, sc.waist_nodes, sc.hem_nodes)
+    for _ in range(5):
+        d = rng.normal(size=x.shape)
+        e = 1e-6
+        fd = (O.apex_angle_loss(xp + e * d, sc.waist_nodes, sc.hem_nodes)[0]
+              - O.apex_angle_loss(xp - e * d, sc.waist_nodes, sc.hem_nodes)[0]) / (2 * e)
+        assert abs(fd - np.sum(g * d)) <= 1e-8 * abs(fd) + 1e-12
+
+
+def test_region_gradients_match_finite_differences():
+    # skirt with rotating waist attachments (no contact), converged steps
+    sc = scenes.c3_skirt(0, n_around=6, n_rings=4, steps=4, omega=4.0)
+    sc.edge_stiffness = np.full(sc.edges.shape[0], 20.0)
+    sc.node_mass = sc.node_mass * 50.0
+
+    def run(rs):
+        model = O.Model(sc, region_scale=np.asarray(rs, float))
+        recs = O.rollout(model, tol=1e-14)
+        ang, g = O.apex_angle_loss(recs[-1].x1, sc.waist_nodes, sc.hem_nodes)
+        return model, recs, ang, g
+
+    rs0 = np.array([1.0, 0.8, 1.2, 0.9])
+    model, recs, ang, g = run(rs0)
+    G = O.backward(model, recs, g)
+    assert G.dregion.shape == (4,)
+    for r in range(4):
+        e = 1e-5 * rs0[r]
+        up, dn = rs0.copy(), rs0.copy()
+        up[r] += e
+        dn[r] -= e
+        fd = (run(up)[2] - run(dn)[2]) / (2 * e)
+        assert abs(fd - G.dregion[r]) <= 1e-5 * abs(fd) + 1e-9, (r, fd, G.dregion[r])
+
+
+def test_per_step_loss_terms_match_finite_differences():
+    # L = sum_n c_n . x_n over n = 0..T, including the final state
+    sc = scenes.tiny_scene(3, steps=5, obstacle=None, k=50.0, seed=4, v0_scale=0.05)
+    cs = np.random.default_rng(5).normal(size=(sc.steps + 1,) + sc.X.shape)
+
+    def loss(v0):
+        model = O.Model(sc)
+        recs = O.rollout(model, v0=v0, tol=1e-14)
+        traj = np.stack([recs[0].x0] + [r.x1 for r in recs])
+        return model, recs, float(np.sum(cs * traj))
+
+    model, recs, _ = loss(sc.v0)
+    G = O.backward(model, recs, np.zeros_like(sc.X), dL_dx_steps=cs)
+    assert np.allclose(G.dx0, cs[0] + O.backward(model, recs, np.zeros_like(sc.X),
+                                                 dL_dx_steps=np.concatenate([0 * cs[:1], cs[1:]])).dx0)
+    d = np.random.default_rng(6).normal(size=sc.X.shape)
+    e = 1e-6
+    fd = (loss(sc.v0 + e * d)[2] - loss(sc.v0 - e * d)[2]) / (2 * e)
+    assert abs(fd - np.sum(G.dv0 * d)) <= 1e-6 * abs(fd) + 1e-12
