@@ -117,6 +117,7 @@ def main():
     ap.add_argument("--adj-tol", type=float, default=1e-4)
     ap.add_argument("--adj-max-iters", type=int, default=50)
     ap.add_argument("--adj-restart", type=int, default=30)
+    ap.add_argument("--adj-solver", default="direct", choices=["direct", "iterative"])
     ap.add_argument("--cpu-sample", default="10,40,70,100,130,160,190",
                     help="steps of the rollout the CPU oracle redoes (forward + adjoint)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -140,7 +141,8 @@ def main():
     sc = scenes.c2_sphere_drop(0)
     T, K = sc.steps, sc.pd_iters
     sim = Sim.from_scene(sc, device=dev, precision=args.precision, adj_tol=args.adj_tol,
-                         adj_max_iters=args.adj_max_iters, adj_restart=args.adj_restart)
+                         adj_max_iters=args.adj_max_iters, adj_restart=args.adj_restart,
+                         adj_solver=args.adj_solver)
     st = sim.stats()
     target = torch.tensor(sc.target, device=dev)
     stream = sim.stream
@@ -202,7 +204,7 @@ def main():
                                "200 steps h=1/120, K=20 PD iterations/step, forward + adjoint "
                                "(one benchmark step = one rollout)",
                    "precision": args.precision, "adj_tol": args.adj_tol, "adj_max_iters": args.adj_max_iters,
-                   "adj_restart": args.adj_restart,
+                   "adj_restart": args.adj_restart, "adj_solver": args.adj_solver,
                    "seed": 0},
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,

@@ -59,6 +59,11 @@ extern "C" {
 #define SIM_MIXED            1   /* float32 local projections, projection Jacobians and
                                     residual SpMV; float64 solves, contact, accumulation */
 
+#define SIM_ADJ_ITERATIVE    0   /* adjoint steps by the paper's fixed point (Sec. 4.2)
+                                    with the prefactored P; GMRES when it stalls      */
+#define SIM_ADJ_DIRECT       1   /* adjoint steps by a direct factorisation of each
+                                    step's matrix (all steps factored in parallel)    */
+
 #define SIM_MODE_FREE        0   /* node not in the contact set                          */
 #define SIM_MODE_TAKEOFF     1
 #define SIM_MODE_STICK       2
@@ -114,6 +119,15 @@ typedef struct {
  *  adj_max_iters   fixed-point iterations before the GMRES fallback, and the
  *                  GMRES iteration budget;
  *  adj_restart     GMRES restart length, 1..60 (0: 60);
+ *  adj_solver      SIM_ADJ_ITERATIVE or SIM_ADJ_DIRECT.  Direct: every step's
+ *                  adjoint matrix M + H T^T is factored (supernodes of P,
+ *                  pivoting inside each diagonal block), all steps of a
+ *                  rollout (or checkpoint segment) at once, one workgroup per
+ *                  step; each step is then solved with its factor and refined
+ *                  against the matrix until the normwise backward error
+ *                  |gbar - A zeta| / (|A| |zeta| + |gbar|) (max norms) is at
+ *                  most adj_tol (at most adj_max_iters solves).  Device memory: one factor
+ *                  per step of the segment (sim_stats_t.adj_factor_bytes each);
  *  checkpoint_every  0: keep every step's record for the backward pass;
  *                  k > 0: keep the state every k steps and recompute segments. */
 typedef struct {
@@ -137,6 +151,7 @@ typedef struct {
     int32_t               adj_max_iters;
     int32_t               checkpoint_every;
     int32_t               adj_restart;
+    int32_t               adj_solver;
 } sim_params_t;
 
 /* Gradient outputs (caller-allocated device arrays; any may be NULL). */
@@ -163,6 +178,8 @@ typedef struct {
     int64_t adj_krylov_total;       /* GMRES iterations of the fallback         */
     int64_t factor_bytes;           /* bytes of the stacked factor blocks       */
     int64_t lds_forward, lds_backward; /* dynamic LDS per workgroup (0: vectors in HBM) */
+    int64_t adj_factor_bytes;       /* direct adjoint: bytes of one step's factor */
+    int64_t adj_pivot_perturbed;    /* direct adjoint: pivots raised to the floor in the last backward */
 } sim_stats_t;
 
 typedef void *(*sim_alloc_fn)(size_t bytes, void *ctx);

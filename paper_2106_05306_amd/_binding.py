@@ -16,6 +16,7 @@ SIM_OK, SIM_EINVAL, SIM_ENOTSPD, SIM_ENOMEM, SIM_ENONFINITE, SIM_ESTATE, SIM_EHI
 SIM_WADJ_FALLBACK, SIM_WADJ_NOCONV = 1, 2
 SIM_PLANE, SIM_SPHERE = 0, 1
 SIM_FP64, SIM_MIXED = 0, 1
+SIM_ADJ_ITERATIVE, SIM_ADJ_DIRECT = 0, 1
 MODE_FREE, MODE_TAKEOFF, MODE_STICK, MODE_SLIP = 0, 1, 2, 3
 
 c_double_p = POINTER(c_double)
@@ -40,7 +41,7 @@ class SimParams(Structure):
                 ("bend_region", c_int32_p), ("region_scale", c_double_p), ("n_regions", c_int32),
                 ("n_obstacles", c_int32), ("obstacles", POINTER(SimObstacle)), ("precision", c_int32),
                 ("adj_tol", c_double), ("adj_max_iters", c_int32), ("checkpoint_every", c_int32),
-                ("adj_restart", c_int32)]
+                ("adj_restart", c_int32), ("adj_solver", c_int32)]
 
 
 class SimGrads(Structure):
@@ -54,7 +55,8 @@ class SimStats(Structure):
                 ("n_supernodes", c_int32), ("n_levels", c_int32), ("steps_recorded", c_int32),
                 ("fwd_iters_total", c_int64), ("adj_iters_total", c_int64), ("adj_fallbacks", c_int32),
                 ("adj_noconv", c_int32), ("device_bytes", c_int64), ("adj_krylov_total", c_int64),
-                ("factor_bytes", c_int64), ("lds_forward", c_int64), ("lds_backward", c_int64)]
+                ("factor_bytes", c_int64), ("lds_forward", c_int64), ("lds_backward", c_int64),
+                ("adj_factor_bytes", c_int64), ("adj_pivot_perturbed", c_int64)]
 
 
 ALLOC_FN = CFUNCTYPE(c_void_p, c_size_t, c_void_p)

@@ -26,6 +26,8 @@ hipError_t launch_region_grad(const double *dw, const double *base_w, const int3
 hipError_t launch_scatter_bend(const double *dw, const int32_t *centers, int n_edges, int n_bend, double *out,
                                hipStream_t st);
 hipError_t launch_fill(double *p, double v, int64_t n, hipStream_t st);
+size_t adj_factor_lds(int nmax);
+hipError_t launch_adj_factor(const SimDev *d_sims, const int32_t *work, int nblocks, int nmax, hipStream_t st);
 }  // namespace dc
 
 using namespace dc;
@@ -55,6 +57,7 @@ struct sim {
     int T = -1;                         // steps of the recorded rollout (-1: none)
     int64_t counters_host[8] = {0};
     int nca = 0;
+    int af_cap = 0;                     // step factors allocated (direct adjoint)
     std::vector<int32_t> corder;        // device constraint slot -> canonical constraint id
     int64_t factor_bytes = 0;
     size_t lds_fwd = 0, lds_bwd = 0;   // dynamic LDS of the two kernels
@@ -445,6 +448,145 @@ void build_device(sim *s) {
     D.binc_con = upload(s, bc);
     D.binc_coef = upload(s, bcf);
     s->factor_bytes = (int64_t)gval.size() * 8;   // per copy (forward and backward each hold one)
+    // direct adjoint: supernode table, update lists, scatter targets of A's blocks, solve items
+    {
+        std::vector<LuSup> ls(ns);
+        int64_t off = 0;
+        int nmax = 3;
+        for (int sn = 0; sn < ns; ++sn) {
+            LuSup &q = ls[sn];
+            q.c0 = sc0[sn];
+            q.n = sns[sn];
+            q.r = snr[sn];
+            q.rptr = rptr[sn];
+            q.uoff = uoff[sn];
+            q.off = off;
+            const int64_t N = 3 * (int64_t)q.n, R = 3 * (int64_t)q.r;
+            off += N * N + 2 * N * R;
+            nmax = std::max(nmax, (int)N);
+        }
+        // updaters: descendant d reaches supernode t through a run of rows of R_d
+        std::vector<std::vector<LuUpd>> ul(ns);
+        for (int d = 0; d < ns; ++d) {
+            const int r0 = rptr[d], nr = snr[d];
+            for (int i = 0; i < nr;) {
+                const int t = hm.sup_of[rows[r0 + i]];
+                int j = i;
+                while (j < nr && hm.sup_of[rows[r0 + j]] == t) ++j;
+                ul[t].push_back(LuUpd{d, i, j, 0});
+                i = j;
+            }
+        }
+        std::vector<int32_t> up_ptr(1, 0);
+        std::vector<LuUpd> upl;
+        for (int t = 0; t < ns; ++t) {
+            upl.insert(upl.end(), ul[t].begin(), ul[t].end());
+            up_ptr.push_back((int32_t)upl.size());
+        }
+        auto pos_in_R = [&](int sn, int node) {
+            const int *b = rows.data() + rptr[sn], *e = b + snr[sn];
+            const int *it = std::lower_bound(b, e, node);
+            if (it == e || *it != node) throw std::runtime_error("factor structure misses an entry of A");
+            return (int)(it - b);
+        };
+        // scatter target of every block (i, j) of the pattern of K_s (new order)
+        std::vector<int64_t> kdst(kc.size());
+        std::vector<int32_t> kld(kc.size());
+        for (int i = 0; i < m; ++i) {
+            for (int e = kp[i]; e < kp[i + 1]; ++e) {
+                const int j = kc[e], si = hm.sup_of[i], sj = hm.sup_of[j];
+                if (si == sj) {
+                    const LuSup &q = ls[si];
+                    kdst[e] = q.off + (int64_t)3 * (i - q.c0) * 3 * q.n + 3 * (j - q.c0);
+                    kld[e] = 3 * q.n;
+                } else if (sj < si) {                   // lower: i in R_sj
+                    const LuSup &q = ls[sj];
+                    const int64_t N = 3 * (int64_t)q.n;
+                    kdst[e] = q.off + N * N + (int64_t)3 * pos_in_R(sj, i) * N + 3 * (j - q.c0);
+                    kld[e] = (int32_t)N;
+                } else {                                // upper: j in R_si
+                    const LuSup &q = ls[si];
+                    const int64_t N = 3 * (int64_t)q.n, R = 3 * (int64_t)q.r;
+                    kdst[e] = q.off + N * N + R * N + (int64_t)3 * (i - q.c0) * R + 3 * pos_in_R(si, j);
+                    kld[e] = (int32_t)R;
+                }
+            }
+        }
+        // Delta P blocks: incidence entry (i, c) adds a_ci a_cl G_c to block (i, l)
+        std::vector<int32_t> dptr(1, 0), dks;
+        for (int i = 0; i < m; ++i) {
+            for (int p = ip[i]; p < ip[i + 1]; ++p) {
+                const int c = ic[p];
+                for (int q = cp[c]; q < cp[c + 1]; ++q) {
+                    const int l = cn[q];
+                    const int *b = kc.data() + kp[i], *e = kc.data() + kp[i + 1];
+                    const int *it = std::lower_bound(b, e, l);
+                    if (it == e || *it != l) throw std::runtime_error("K_s pattern misses a constraint coupling");
+                    dks.push_back((int32_t)(it - kc.data()));
+                }
+                dptr.push_back((int32_t)dks.size());
+            }
+        }
+        // solve items grouped by level
+        const int L = hm.n_levels;
+        std::vector<int32_t> lvl(3 * (L + 1), 0), lsn, lteam(3 * L, 1);
+        std::vector<LuItem> zi, ui;
+        auto pick = [](int items, int maxlen) {
+            int best = 1;
+            double best_cost = 1e300;
+            for (int tl = 1; tl <= 32; tl *= 2) {
+                const int passes = (items * tl + kBlockAdj - 1) / kBlockAdj;
+                const double cost = passes * ((maxlen + tl - 1) / tl + 0.5 * __builtin_ctz(tl) + 1.0);
+                if (cost < best_cost) { best_cost = cost; best = tl; }
+            }
+            return best;
+        };
+        for (int l = 0; l < L; ++l) {
+            int zmax = 1, rmax = 1;
+            const int z0 = (int)zi.size(), u0 = (int)ui.size();
+            for (int sn = 0; sn < ns; ++sn) {
+                if (hm.sup_level[sn] != l) continue;
+                lsn.push_back(sn);
+                for (int a = 0; a < 3 * sns[sn]; ++a) zi.push_back(LuItem{sn, a});
+                for (int a = 0; a < 3 * snr[sn]; ++a) ui.push_back(LuItem{sn, a});
+                zmax = std::max(zmax, 3 * sns[sn]);
+                rmax = std::max(rmax, 3 * snr[sn]);
+            }
+            lvl[3 * (l + 1)] = (int32_t)zi.size();
+            lvl[3 * (l + 1) + 1] = (int32_t)ui.size();
+            lvl[3 * (l + 1) + 2] = (int32_t)lsn.size();
+            lteam[3 * l] = pick((int)zi.size() - z0, zmax);
+            lteam[3 * l + 1] = pick((int)ui.size() - u0, zmax);
+            lteam[3 * l + 2] = pick((int)zi.size() - z0, rmax);
+        }
+        D.ns = ns;
+        D.lu_sup = upload(s, ls);
+        D.lu_upd_ptr = upload(s, up_ptr);
+        D.lu_upd = upload(s, upl);
+        D.ks_dst = upload(s, kdst);
+        D.ks_ld = upload(s, kld);
+        D.dp_ptr = upload(s, dptr);
+        D.dp_ks = upload(s, dks);
+        D.lu_lvl = upload(s, lvl);
+        D.lu_zitems = upload(s, zi);
+        D.lu_uitems = upload(s, ui);
+        D.lu_sn = upload(s, lsn);
+        D.lu_team = upload(s, lteam);
+        // every row of R_d past the rows in s must be a row of R_s (the factor
+        // kernel maps them through s's row table); panels must fit the LDS panel
+        for (int t = 0; t < ns; ++t)
+            for (int u = up_ptr[t]; u < up_ptr[t + 1]; ++u) {
+                const LuUpd &ud = upl[u];
+                for (int i = ud.i1; i < snr[ud.d]; ++i) (void)pos_in_R(t, rows[rptr[ud.d] + i]);
+            }
+        if (nmax > 8192) throw std::runtime_error("supernode too large for the direct adjoint");
+        D.af_size = off;
+        D.af_nmax = nmax;
+        // workspace: T blocks (9 m), projection scale + direction (4 nca), pivot
+        // perturbation count and |A|_inf (2), node -> panel row map (m int32)
+        D.af_ws_size = 9 * (int64_t)m + 4 * (int64_t)std::max(nca, 1) + 2 + (m + 1) / 2;
+        D.adj_direct = hm.adj_solver == SIM_ADJ_DIRECT;
+    }
     // state and work buffers
     const size_t v3 = 3 * (size_t)m;
     D.x = zeros<double>(s, v3);
@@ -539,6 +681,19 @@ void ensure_records(sim *s, int cap) {
     s->hd.rec_mode = (uint8_t *)dev_alloc(s, (size_t)cap * s->hd.m);
     s->hd.rec_obst = (int8_t *)dev_alloc(s, (size_t)cap * s->hd.m);
     s->hd.rec_cap = cap;
+}
+
+// room for `cap` step factors of the direct adjoint
+void ensure_af(sim *s, int cap) {
+    if (s->af_cap >= cap && s->hd.af) return;
+    dev_release(s, s->hd.af);
+    dev_release(s, s->hd.af_ws);
+    s->hd.af = nullptr;
+    s->hd.af_ws = nullptr;
+    s->af_cap = 0;
+    s->hd.af = (double *)dev_alloc(s, (size_t)cap * s->hd.af_size * sizeof(double));
+    s->hd.af_ws = (double *)dev_alloc(s, (size_t)cap * s->hd.af_ws_size * sizeof(double));
+    s->af_cap = cap;
 }
 
 int copy_d2d(sim *s, void *dst, const void *src, size_t bytes) {
@@ -803,6 +958,16 @@ int prepare_backward(sim *s, const double *dL_dxT, const double *dL_dvT, const d
     return rc;
 }
 
+// Direct adjoint: factor steps [a, b) (records in place, rec_step0 set), one workgroup per step.
+int factor_steps(sim *s, int a, int b) {
+    if (!s->hd.adj_direct) return SIM_OK;
+    ensure_af(s, b - a);
+    s->hd.af_step0 = a;
+    int rc = push_desc(s);
+    if (rc) return rc;
+    return hip_err(launch_adj_factor(s->dd, nullptr, b - a, s->hd.af_nmax, s->stream));
+}
+
 int backward_all(sim *s) {
     const int T = s->T, k = seg_len(s);
     const size_t v3 = 3 * (size_t)s->hd.m;
@@ -810,7 +975,8 @@ int backward_all(sim *s) {
         s->hd.step_begin = 0;
         s->hd.step_end = T;
         s->hd.rec_step0 = 0;
-        int rc = push_desc(s);
+        int rc = factor_steps(s, 0, T);
+        if (!rc) rc = push_desc(s);
         if (rc) return rc;
         return hip_err(launch_backward(s->dd, 1, s->hd.mixed != 0, s->lds_bwd, s->flags_bwd, s->stream));
     }
@@ -824,7 +990,8 @@ int backward_all(sim *s) {
         s->hd.step_begin = a;
         s->hd.step_end = b;
         s->hd.rec_step0 = a;
-        rc = push_desc(s);
+        rc = factor_steps(s, a, b);
+        if (!rc) rc = push_desc(s);
         if (!rc) rc = hip_err(launch_backward(s->dd, 1, s->hd.mixed != 0, s->lds_bwd, s->flags_bwd, s->stream));
         if (rc) return rc;
     }
@@ -902,6 +1069,7 @@ int sim_adjoint_step(sim_t *s, int32_t n, const double *gx_dev, const double *gv
         s->hd.step_begin = n;
         s->hd.step_end = n + 1;
         s->hd.rec_step0 = 0;
+        if (!rc) rc = factor_steps(s, n, n + 1);
         if (!rc) rc = push_desc(s);
         if (!rc) rc = hip_err(launch_backward(s->dd, 1, s->hd.mixed != 0, s->lds_bwd, s->flags_bwd, s->stream));
         if (!rc && dx_dev) rc = hip_err(launch_permute3(s->hd.gx, dx_dev, s->d_perm, m, true, s->stream));
@@ -987,6 +1155,8 @@ int sim_stats(const sim_t *cs, sim_stats_t *out) {
     out->factor_bytes = s->factor_bytes;
     out->lds_forward = (int64_t)s->lds_fwd;
     out->lds_backward = (int64_t)s->lds_bwd;
+    out->adj_factor_bytes = s->hd.af_size * (int64_t)sizeof(double);
+    out->adj_pivot_perturbed = s->counters_host[5];
     return SIM_OK;
 }
 
@@ -1035,18 +1205,27 @@ int sim_batch_backward(sim_t *const *sims, int32_t n, const double *const *dL_dx
     sim *s0 = sims[0];
     return guarded([&] {
         std::vector<SimDev> descs(n);
-        int rc = SIM_OK;
+        std::vector<int32_t> work;           // (handle, slot) of every step factor (direct adjoint)
+        int rc = SIM_OK, nmax = 3;
         for (int i = 0; i < n && !rc; ++i) {
             rc = prepare_backward(sims[i], dL_dxT_dev ? dL_dxT_dev[i] : nullptr, nullptr, nullptr);
             sims[i]->hd.step_begin = 0;
             sims[i]->hd.step_end = sims[i]->T;
             sims[i]->hd.rec_step0 = 0;
+            if (sims[i]->hd.adj_direct) {
+                ensure_af(sims[i], sims[i]->T);
+                sims[i]->hd.af_step0 = 0;
+                nmax = std::max(nmax, sims[i]->hd.af_nmax);
+                for (int k = 0; k < sims[i]->T; ++k) { work.push_back(i); work.push_back(k); }
+            }
             descs[i] = sims[i]->hd;
             if (!rc) rc = push_desc(sims[i]);
         }
         if (rc) return rc;
         SimDev *d = (SimDev *)dev_alloc(s0, n * sizeof(SimDev));
+        int32_t *dwork = work.empty() ? nullptr : upload(s0, work);
         rc = hip_err(hipMemcpyAsync(d, descs.data(), n * sizeof(SimDev), hipMemcpyHostToDevice, s0->stream));
+        if (!rc && dwork) rc = hip_err(launch_adj_factor(d, dwork, (int)work.size() / 2, nmax, s0->stream));
         int fl = 0;
         const size_t lb = batch_lds(sims, n, false, fl);
         if (!rc) rc = hip_err(launch_backward(d, n, s0->hd.mixed != 0, lb, fl, s0->stream));
@@ -1061,6 +1240,7 @@ int sim_batch_backward(sim_t *const *sims, int32_t n, const double *const *dL_dx
         }
         (void)hipStreamSynchronize(s0->stream);
         dev_release(s0, d);
+        dev_release(s0, dwork);
         return rc ? rc : warn;
     });
 }

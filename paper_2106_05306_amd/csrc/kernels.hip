@@ -736,6 +736,343 @@ __device__ __forceinline__ int gmres_solve(const SimDev &S, auto mode, auto gbar
 }
 
 // Backward over steps [step_begin, step_end) in reverse, one handle per workgroup.
+
+// ------------------------------------------------------------------ direct adjoint
+// Each adjoint step solves A zeta = gbar with A = M + H T^T (H = h^2 K_s (x) I_3
+// - Delta P at x_{n+1}, T the contact Jacobian blocks; Sec. 4.2).  The paper
+// solves it by a fixed point with the prefactored P and falls back to a direct
+// solve; here every step's A is factored up front, all steps at once (one
+// workgroup each), on the supernodes of P at the level of degrees of freedom
+// (left-looking, children first).  Supernode s keeps D_s^{-1} (its diagonal
+// block after the Schur updates, inverted by Gauss-Jordan with row pivoting
+// inside the block), B_s = A(R_s, s) and V_s = D_s^{-1} A(s, R_s); the Schur
+// update of descendant d onto the blocks it reaches is B_d V_d.
+
+constexpr int kLuPanel = 8192;        // doubles of LDS for one column panel of A(s, R_s)
+
+__device__ __forceinline__ void contact_T(const SimDev &S, uint8_t md, int o, auto xi, auto ub, double *T) {
+    // T = d v / d ubar of the contact update, row-major (identity off contact)
+    for (int e = 0; e < 9; ++e) T[e] = (md == STICK) ? 0.0 : ((e % 4 == 0) ? 1.0 : 0.0);
+    if (md != SLIP) return;
+    double nrm[3], phi;
+    contact_frame(S, o, xi, nrm, phi);
+    const double mu = S.obst[o].mu, h = S.h;
+    const double un = nrm[0] * ub[0] + nrm[1] * ub[1] + nrm[2] * ub[2];
+    const double a = un + phi / h;
+    double t[3] = {ub[0] - un * nrm[0], ub[1] - un * nrm[1], ub[2] - un * nrm[2]};
+    const double tau = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+    t[0] /= tau; t[1] /= tau; t[2] /= tau;
+    const double sl = mu * (-a) / tau;
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+            T[3 * r + c] = (1 - sl) * ((r == c ? 1.0 : 0.0) - nrm[r] * nrm[c]) + sl * t[r] * t[c] + mu * t[r] * nrm[c];
+}
+
+// One workgroup factors one step: work[2b] = handle, work[2b+1] = factor slot
+// (NULL: handle 0, slot = block index).  Slot k holds step af_step0 + k.
+__global__ __launch_bounds__(kBlockAdj) void k_adj_factor(const SimDev *__restrict__ sims,
+                                                          const int32_t *__restrict__ work) {
+    const int hidx = work ? work[2 * blockIdx.x] : 0;
+    const int slot = work ? work[2 * blockIdx.x + 1] : (int)blockIdx.x;
+    const SimDev &S = sims[hidx];
+    const int tid = threadIdx.x, bd = blockDim.x;
+    const int m = S.m;
+    const double hh = S.h * S.h;
+    const int rs = S.af_step0 + slot - S.rec_step0;
+    const auto x0 = G(S.rec_x) + (int64_t)rs * 3 * m;
+    const auto x1 = x0 + 3 * m;
+    const auto mode = G(S.rec_mode) + (int64_t)rs * m;
+    const auto obst = G(S.rec_obst) + (int64_t)rs * m;
+    const auto ubr = G(S.rec_ubar) + (int64_t)rs * 3 * m;
+    const auto F = G(S.af) + (int64_t)slot * S.af_size;
+    const auto ws = G(S.af_ws) + (int64_t)slot * S.af_ws_size;
+    const auto Tb = ws;
+    const auto Gc = ws + 9 * (int64_t)m;
+    const auto npert = Gc + 4 * (int64_t)max(S.nca, 1);     // [0] perturbed pivots, [1] |A|_inf
+    const auto rowpos = (GLOBAL int32_t *)(npert + 2);
+    extern __shared__ double lds[];
+    double *fcol = lds;
+    double *panel = lds + S.af_nmax;
+    int *ipiv = (int *)(panel + kLuPanel);
+    __shared__ int piv_sh;
+    __shared__ double red[kBlockAdj / 64];
+
+    for (int64_t e = tid; e < S.af_size; e += bd) F[e] = 0.0;
+    // projection Jacobian scale and direction at x_{n+1}
+    for (int c = tid; c < S.nca; c += bd) {
+        double q0 = 0, q1 = 0, q2 = 0;
+        for (int p = G(S.c_ptr)[c]; p < G(S.c_ptr)[c + 1]; ++p) {
+            const int j = G(S.c_node)[p];
+            const double a = G(S.c_coef)[p];
+            q0 += a * x1[3 * j]; q1 += a * x1[3 * j + 1]; q2 += a * x1[3 * j + 2];
+        }
+        const double nq = sqrt(q0 * q0 + q1 * q1 + q2 * q2);
+        const double rho = G(S.c_rho)[c];
+        if (nq < 1e-12 * rho) {
+            Gc[4 * c] = 0.0; Gc[4 * c + 1] = 0.0; Gc[4 * c + 2] = 0.0; Gc[4 * c + 3] = 0.0;
+        } else {
+            Gc[4 * c] = hh * G(S.c_w)[c] * rho / nq;
+            Gc[4 * c + 1] = q0 / nq; Gc[4 * c + 2] = q1 / nq; Gc[4 * c + 3] = q2 / nq;
+        }
+    }
+    for (int i = tid; i < m; i += bd) {
+        double T[9];
+        contact_T(S, mode[i], obst[i], x0 + 3 * i, ubr + 3 * i, T);
+        for (int e = 0; e < 9; ++e) Tb[9 * (int64_t)i + e] = T[e];
+    }
+    __syncthreads();
+    // assembly: the thread of row i owns every block (i, j)
+    double anorm = 0.0;
+    for (int i = tid; i < m; i += bd) {
+        double rsum[3] = {0.0, 0.0, 0.0};
+        for (int e = G(S.ks_ptr)[i]; e < G(S.ks_ptr)[i + 1]; ++e) {
+            const auto d = F + G(S.ks_dst)[e];
+            const int ld = G(S.ks_ld)[e];
+            const double k = hh * G(S.ks_val)[e];
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) d[r * ld + c] = r == c ? k : 0.0;
+        }
+        for (int p = G(S.inc_ptr)[i]; p < G(S.inc_ptr)[i + 1]; ++p) {
+            const int c = G(S.inc_con)[p];
+            const double sc = Gc[4 * c];
+            if (sc == 0.0) continue;
+            const double qh[3] = {Gc[4 * c + 1], Gc[4 * c + 2], Gc[4 * c + 3]};
+            const double ai = G(S.inc_coef)[p] * sc;
+            const int q0 = G(S.c_ptr)[c], q1 = G(S.c_ptr)[c + 1], e0 = G(S.dp_ptr)[p];
+            for (int q = q0; q < q1; ++q) {
+                const double f = ai * G(S.c_coef)[q];
+                const int e = G(S.dp_ks)[e0 + q - q0];
+                const auto d = F + G(S.ks_dst)[e];
+                const int ld = G(S.ks_ld)[e];
+                for (int r = 0; r < 3; ++r)
+                    for (int cc = 0; cc < 3; ++cc) d[r * ld + cc] -= f * ((r == cc ? 1.0 : 0.0) - qh[r] * qh[cc]);
+            }
+        }
+        for (int e = G(S.ks_ptr)[i]; e < G(S.ks_ptr)[i + 1]; ++e) {
+            const int j = G(S.ks_col)[e];
+            const uint8_t md = mode[j];
+            const auto d = F + G(S.ks_dst)[e];
+            const int ld = G(S.ks_ld)[e];
+            double b[9];
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) b[3 * r + c] = d[r * ld + c];
+            if (md == STICK) {
+                for (int q = 0; q < 9; ++q) b[q] = 0.0;
+            } else if (md == SLIP) {                      // H_ij T_j^T
+                const auto T = Tb + 9 * (int64_t)j;
+                double o[9];
+                for (int r = 0; r < 3; ++r)
+                    for (int c = 0; c < 3; ++c)
+                        o[3 * r + c] = b[3 * r] * T[3 * c] + b[3 * r + 1] * T[3 * c + 1] + b[3 * r + 2] * T[3 * c + 2];
+                for (int q = 0; q < 9; ++q) b[q] = o[q];
+            }
+            if (i == j) {
+                const double mi = G(S.mass)[i];
+                b[0] += mi; b[4] += mi; b[8] += mi;
+            }
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) {
+                    d[r * ld + c] = b[3 * r + c];
+                    rsum[r] += fabs(b[3 * r + c]);
+                }
+        }
+        anorm = fmax(anorm, fmax(rsum[0], fmax(rsum[1], rsum[2])));
+    }
+    anorm = block_max(anorm, red);
+    if (tid == 0) npert[1] = anorm;
+    __syncthreads();
+    int pert = 0;
+    for (int sn = 0; sn < S.ns; ++sn) {
+        const auto &q = G(S.lu_sup)[sn];
+        const int N = 3 * q.n, R = 3 * q.r;
+        const auto D = F + q.off;
+        const auto Bp = D + (int64_t)N * N;
+        const auto C = Bp + (int64_t)R * N;
+        for (int t = tid; t < q.n; t += bd) rowpos[q.c0 + t] = t;
+        for (int t = tid; t < q.r; t += bd) rowpos[G(S.sup_rows)[q.rptr + t]] = q.n + t;
+        __syncthreads();
+        // Schur updates B_d V_d of the descendants reaching s
+        for (int u = G(S.lu_upd_ptr)[sn]; u < G(S.lu_upd_ptr)[sn + 1]; ++u) {
+            const auto &ud = G(S.lu_upd)[u];
+            const auto &qd = G(S.lu_sup)[ud.d];
+            const int Nd = 3 * qd.n, Rd = 3 * qd.r;
+            const auto Bd = F + qd.off + (int64_t)Nd * Nd;
+            const auto Vd = Bd + (int64_t)Rd * Nd;
+            const auto Rrows = G(S.sup_rows) + qd.rptr;
+            const int a0 = 3 * ud.i0, a1 = 3 * ud.i1, wc = a1 - a0;
+            const int nlow = (Rd - a0) * wc, nup = wc * (Rd - a1);
+            for (int idx = tid; idx < nlow + nup; idx += bd) {
+                int a, b;
+                if (idx < nlow) {
+                    a = a0 + idx / wc;
+                    b = a0 + idx % wc;
+                } else {
+                    const int k = idx - nlow;
+                    a = a0 + k / (Rd - a1);
+                    b = a1 + k % (Rd - a1);
+                }
+                const auto br = Bd + (int64_t)a * Nd;
+                double acc = 0.0;
+                for (int k = 0; k < Nd; ++k) acc += br[k] * Vd[(int64_t)k * Rd + b];
+                const int ra = rowpos[Rrows[a / 3]], rb = rowpos[Rrows[b / 3]];
+                const int ca = a % 3, cb = b % 3;
+                if (idx < nlow) {
+                    if (ra < q.n) D[(int64_t)(3 * ra + ca) * N + 3 * rb + cb] -= acc;
+                    else Bp[(int64_t)(3 * (ra - q.n) + ca) * N + 3 * rb + cb] -= acc;
+                } else {
+                    C[(int64_t)(3 * ra + ca) * R + 3 * (rb - q.n) + cb] -= acc;
+                }
+            }
+            __syncthreads();
+        }
+        // pivot floor: 1e-13 of the largest entry of the diagonal block
+        double dm = 0.0;
+        for (int e = tid; e < N * N; e += bd) dm = fmax(dm, fabs(D[e]));
+        const double floor_ = 1e-13 * block_max(dm, red);
+        // Gauss-Jordan inversion of D in place, row pivoting inside the block
+        for (int k = 0; k < N; ++k) {
+            if (tid < 64) {
+                double best = -1.0;
+                int bi = k;
+                for (int i = k + tid; i < N; i += 64) {
+                    const double v = fabs(D[(int64_t)i * N + k]);
+                    if (v > best) { best = v; bi = i; }
+                }
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) {
+                    const double ob = __shfl_xor(best, o, 64);
+                    const int oi = __shfl_xor(bi, o, 64);
+                    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+                }
+                if (tid == 0) { piv_sh = bi; ipiv[k] = bi; }
+            }
+            __syncthreads();
+            const int p = piv_sh;
+            if (p != k)
+                for (int j = tid; j < N; j += bd) {
+                    const double t = D[(int64_t)k * N + j];
+                    D[(int64_t)k * N + j] = D[(int64_t)p * N + j];
+                    D[(int64_t)p * N + j] = t;
+                }
+            __syncthreads();
+            double pv = D[(int64_t)k * N + k];
+            if (!(fabs(pv) >= floor_)) {
+                pv = pv < 0.0 ? -floor_ : floor_;
+                if (!(pv != 0.0)) pv = 1e-300;
+                ++pert;
+            }
+            for (int i = tid; i < N; i += bd) fcol[i] = D[(int64_t)i * N + k];
+            __syncthreads();
+            const double pinv = 1.0 / pv;
+            for (int j = tid; j < N; j += bd) D[(int64_t)k * N + j] = j == k ? pinv : D[(int64_t)k * N + j] * pinv;
+            __syncthreads();
+            for (int idx = tid; idx < N * N; idx += bd) {
+                const int i = idx / N, j = idx - i * N;
+                if (i == k) continue;
+                const double f = fcol[i];
+                if (j == k) D[idx] = -f * pinv;
+                else D[idx] -= f * D[(int64_t)k * N + j];
+            }
+            __syncthreads();
+        }
+        for (int k = N - 1; k >= 0; --k) {
+            const int p = ipiv[k];
+            if (p != k)
+                for (int i = tid; i < N; i += bd) {
+                    const double t = D[(int64_t)i * N + k];
+                    D[(int64_t)i * N + k] = D[(int64_t)i * N + p];
+                    D[(int64_t)i * N + p] = t;
+                }
+            __syncthreads();
+        }
+        // V_s = D_s^{-1} A(s, R_s), one LDS panel of columns at a time
+        if (R > 0) {
+            const int cw = max(1, min(R, kLuPanel / N));
+            for (int c0 = 0; c0 < R; c0 += cw) {
+                const int w = min(cw, R - c0);
+                for (int idx = tid; idx < N * w; idx += bd) {
+                    const int k = idx / w, j = idx - k * w;
+                    panel[idx] = C[(int64_t)k * R + c0 + j];
+                }
+                __syncthreads();
+                for (int idx = tid; idx < N * w; idx += bd) {
+                    const int i = idx / w, j = idx - i * w;
+                    const auto dr = D + (int64_t)i * N;
+                    double acc = 0.0;
+                    for (int k = 0; k < N; ++k) acc += dr[k] * panel[k * w + j];
+                    C[(int64_t)i * R + c0 + j] = acc;
+                }
+                __syncthreads();
+            }
+        }
+    }
+    if (tid == 0) npert[0] = (double)pert;
+}
+
+// A z = b with a step factor F: forward over the levels (children first)
+//   t_s = b_s - (update entries reaching s), z_s = D_s^{-1} t_s, u_s = B_s z_s;
+// backward (parents first) x_s = z_s - V_s x_{R_s}.  Same level schedule and
+// update-buffer layout as solve_P; x must not alias b, T or Z.
+__device__ __forceinline__ void solve_A(const SimDev &S, auto F, auto b, auto T, auto Z, auto x, auto U) {
+    const int tid = threadIdx.x, bd = blockDim.x;
+    const auto lvl = G(S.lu_lvl);
+    for (int l = 0; l < S.n_levels; ++l) {
+        for (int it = G(S.lvl_rows_ptr)[l] + tid; it < G(S.lvl_rows_ptr)[l + 1]; it += bd) {
+            const auto &ri = G(S.rows)[it];
+            double t0 = b[ri.i3], t1 = b[ri.i3 + 1], t2 = b[ri.i3 + 2];
+            for (int p = ri.p0; p < ri.p1; ++p) {
+                const int o = G(S.upd_off)[p];
+                t0 -= U[o]; t1 -= U[o + 1]; t2 -= U[o + 2];
+            }
+            T[ri.i3] = t0; T[ri.i3 + 1] = t1; T[ri.i3 + 2] = t2;
+        }
+        __syncthreads();
+        {
+            const int tl = G(S.lu_team)[3 * l], lane = tid & (tl - 1);
+            for (int it = lvl[3 * l] + tid / tl; it < lvl[3 * (l + 1)]; it += bd / tl) {
+                const auto &li = G(S.lu_zitems)[it];
+                const auto &q = G(S.lu_sup)[li.s];
+                const int N = 3 * q.n, t0 = 3 * q.c0;
+                const auto row = F + q.off + (int64_t)li.a * N;
+                double acc = 0.0;
+                for (int k = lane; k < N; k += tl) acc += row[k] * T[t0 + k];
+                acc = team_sum(acc, tl);
+                if (lane == 0) Z[t0 + li.a] = acc;
+            }
+        }
+        __syncthreads();
+        {
+            const int tl = G(S.lu_team)[3 * l + 1], lane = tid & (tl - 1);
+            for (int it = lvl[3 * l + 1] + tid / tl; it < lvl[3 * (l + 1) + 1]; it += bd / tl) {
+                const auto &li = G(S.lu_uitems)[it];
+                const auto &q = G(S.lu_sup)[li.s];
+                const int N = 3 * q.n, t0 = 3 * q.c0;
+                const auto row = F + q.off + (int64_t)N * N + (int64_t)li.a * N;
+                double acc = 0.0;
+                for (int k = lane; k < N; k += tl) acc += row[k] * Z[t0 + k];
+                acc = team_sum(acc, tl);
+                if (lane == 0) U[q.uoff + li.a] = acc;
+            }
+        }
+        __syncthreads();
+    }
+    for (int l = S.n_levels - 1; l >= 0; --l) {
+        const int tl = G(S.lu_team)[3 * l + 2], lane = tid & (tl - 1);
+        for (int it = lvl[3 * l] + tid / tl; it < lvl[3 * (l + 1)]; it += bd / tl) {
+            const auto &li = G(S.lu_zitems)[it];
+            const auto &q = G(S.lu_sup)[li.s];
+            const int N = 3 * q.n, R = 3 * q.r, t0 = 3 * q.c0;
+            const auto row = F + q.off + (int64_t)N * N + (int64_t)R * N + (int64_t)li.a * R;
+            const auto rr = G(S.sup_rows) + q.rptr;
+            double acc = 0.0;
+            for (int k = lane; k < R; k += tl) acc += row[k] * x[3 * rr[k / 3] + k % 3];
+            acc = team_sum(acc, tl);
+            if (lane == 0) x[t0 + li.a] = Z[t0 + li.a] - acc;
+        }
+        __syncthreads();
+    }
+}
+
 template <bool MIXED, int FL>
 __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict__ sims) {
     const SimDev &S = sims[blockIdx.x];
@@ -747,7 +1084,7 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
     auto U = pick<ku>(dyn + (kv ? 6 * S.m : 0), G(S.ubuf));
     const int m = S.m;
     const double h = S.h, hh = h * h;
-    int64_t iters_total = 0, gm_total = 0;
+    int64_t iters_total = 0, gm_total = 0, pert_total = 0;
     int noconv = 0;
     for (int n = S.step_end - 1; n >= S.step_begin; --n) {
         const int slot = n - S.rec_step0;
@@ -805,9 +1142,44 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
             }
         }
         __syncthreads();
-        // fixed point zeta <- P^{-1}[gbar + dP z + (P - M)(zeta - z)], z = T^T zeta
         auto zeta = G(S.zeta);
         auto zeta1 = G(S.zeta1);
+        if (S.adj_direct) {
+            // zeta = A^{-1} gbar with the step's factor, refined against A until the
+            // normwise backward error |gbar - A zeta| / (|A| |zeta| + |gbar|) (max
+            // norms) is at most adj_tol
+            const auto F = G(S.af) + (int64_t)(n - S.af_step0) * S.af_size;
+            const auto wsn = G(S.af_ws) + (int64_t)(n - S.af_step0) * S.af_ws_size + 9 * (int64_t)m +
+                             4 * (int64_t)max(S.nca, 1);
+            const double anorm = wsn[1];
+            solve_A(S, F, gbar, T, Y, zeta, U);
+            double gmax = 0.0;
+            for (int i = threadIdx.x; i < 3 * m; i += (int)blockDim.x) gmax = fmax(gmax, fabs(gbar[i]));
+            gmax = block_max(gmax, red);
+            int k = 1;
+            bool ok = false;
+            while (true) {
+                apply_adjoint_operator<MIXED>(S, mode, zeta, zeta1);
+                double rmax = 0.0, zmax = 0.0;
+                for (int i = threadIdx.x; i < 3 * m; i += (int)blockDim.x) {
+                    zeta1[i] = gbar[i] - zeta1[i];
+                    rmax = fmax(rmax, fabs(zeta1[i]));
+                    zmax = fmax(zmax, fabs(zeta[i]));
+                }
+                rmax = block_max(rmax, red);
+                zmax = block_max(zmax, red);
+                if (!(rmax > S.adj_tol * (anorm * zmax + gmax))) { ok = true; break; }
+                if (k >= S.adj_max_iters || !(rmax == rmax)) break;
+                solve_A(S, F, zeta1, T, Y, G(S.zt), U);
+                for (int i = threadIdx.x; i < 3 * m; i += (int)blockDim.x) zeta[i] += G(S.zt)[i];
+                __syncthreads();
+                ++k;
+            }
+            iters_total += k;
+            if (!ok) ++noconv;
+            if (threadIdx.x == 0) pert_total += (int64_t)wsn[0];
+        } else {
+        // fixed point zeta <- P^{-1}[gbar + dP z + (P - M)(zeta - z)], z = T^T zeta
         int k = 0;
         bool ok = false, stalled = false;
         double dprev = 0.0, d5 = 0.0;
@@ -850,6 +1222,7 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
             if (it < 0) ++noconv;
             gm_total += it < 0 ? -it - 1 : it;
             (void)stalled;
+        }
         }
         // gradients of this step
         apply_TT(S, mode, zeta, G(S.zt));
@@ -933,6 +1306,7 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
         G(S.counters)[1] += iters_total;
         G(S.counters)[3] += noconv;
         G(S.counters)[4] += gm_total;
+        G(S.counters)[5] += pert_total;
     }
 }
 
@@ -1058,6 +1432,18 @@ hipError_t kernel_static_lds(size_t *fwd, size_t *bwd) {
         *bwd = a.sharedSizeBytes > *bwd ? a.sharedSizeBytes : *bwd;
     }
     return hipSuccess;
+}
+
+// Dynamic LDS of the step factorisation: pivot column, V panel, pivot rows.
+size_t adj_factor_lds(int nmax) { return (size_t)(nmax + kLuPanel) * sizeof(double) + (size_t)nmax * sizeof(int); }
+
+hipError_t launch_adj_factor(const SimDev *d_sims, const int32_t *work, int nblocks, int nmax, hipStream_t st) {
+    if (nblocks <= 0) return hipSuccess;
+    const size_t lds = adj_factor_lds(nmax);
+    hipError_t e = hipFuncSetAttribute((const void *)k_adj_factor, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_adj_factor, dim3(nblocks), dim3(kBlockAdj), lds, st, d_sims, work);
+    return hipGetLastError();
 }
 
 hipError_t launch_permute3(const double *in, double *out, const int32_t *perm, int m, bool to_caller, hipStream_t st) {

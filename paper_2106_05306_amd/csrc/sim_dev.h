@@ -42,6 +42,20 @@ struct SpringInc {          // node-centred spring projection: one incident spri
     double rho, w;          // rest length and weight
 };
 
+struct LuItem {             // direct adjoint solve: row a of supernode s
+    int32_t s, a;
+};
+struct LuUpd {              // supernode s is updated by descendant d: rows [i0, i1) of R_d lie in s
+    int32_t d, i0, i1, pad;
+};
+struct LuSup {              // supernode data of the direct adjoint factor
+    int32_t c0, n, r;       // first node, nodes, rows of R_s
+    int32_t rptr;           // offset of R_s in sup_rows
+    int32_t uoff;           // offset of u_s in the update buffer
+    int32_t pad;
+    int64_t off;            // offset of [D_s^{-1}; B_s; V_s] in a step factor (doubles)
+};
+
 struct ObstacleDev {
     int type;                         // 0 plane, 1 sphere
     double p[3], n[3], radius, mu;
@@ -129,6 +143,31 @@ struct SimDev {
     // Krylov fallback workspace (GMRES)
     double *kry;                      // [(kry_m+1) * m*3] Krylov basis
     int kry_m;                        // GMRES restart length (<= kKryM)
+
+    // direct adjoint: per step an LU-type factor of A = M + H T^T on the
+    // supernodes of P (degrees of freedom, not nodes): per supernode s with
+    // N = 3 n_s, R = 3 r_s, row-major blocks D_s^{-1} (N x N), B_s = A(R_s, s)
+    // after the Schur updates (R x N) and V_s = D_s^{-1} A(s, R_s) (N x R)
+    int adj_direct;                   // 1: adjoint steps solved with their factors
+    int ns;                           // supernodes
+    const LuSup *lu_sup;              // [ns]
+    const int32_t *lu_upd_ptr;        // [ns+1] updaters of each supernode
+    const LuUpd *lu_upd;
+    const int64_t *ks_dst;            // [nnz K_s] offset of block (i, j) in a step factor
+    const int32_t *ks_ld;             // [nnz K_s] row stride there
+    const int32_t *dp_ptr;            // [n_inc+1] per incidence entry (node i, constraint c):
+    const int32_t *dp_ks;             //   K_s entry of (i, l) for each stencil node l of c
+    const int32_t *lu_lvl;            // [3*(n_levels+1)]: per level start of z items, u items, supernodes
+    const LuItem *lu_zitems;          // rows of D_s^{-1} / V_s, grouped by level
+    const LuItem *lu_uitems;          // rows of B_s, grouped by level
+    const int32_t *lu_sn;             // supernodes grouped by level
+    const int32_t *lu_team;           // [3*n_levels] lanes per item: z, u, backward
+    int64_t af_size;                  // doubles per step factor
+    int64_t af_ws_size;               // doubles of factorisation workspace per step
+    int af_nmax;                      // largest N
+    double *af;                       // step factors: slot k holds step af_step0 + k
+    double *af_ws;                    // workspace per slot
+    int af_step0;
 
     // run control for one launch
     int step_begin, step_end;         // forward: steps [begin, end); backward: reverse

@@ -49,7 +49,8 @@ def build_structs(X, tris, node_mass, edge_stiffness, *, edges=None, h=1.0 / 120
                   fwd_max_iters=0, gravity=(0.0, -9.8, 0.0), bend_weight=1e-2, attach=(), attach_weight=1e5,
                   attach_omega=0.0, attach_axis=(0.0, 1.0, 0.0), attach_center=(0.0, 0.0, 0.0),
                   obstacles: Sequence[dict] = (), edge_region=None, bend_region=None, region_scale=None,
-                  precision="fp64", adj_tol=1e-10, adj_max_iters=500, checkpoint_every=0, adj_restart=0):
+                  precision="fp64", adj_tol=1e-10, adj_max_iters=500, checkpoint_every=0, adj_restart=0,
+                  adj_solver="iterative"):
     """Marshal a mesh and its parameters into the C structs; returns
     (SimMesh, SimParams, keep-alive dict of the numpy arrays they point to)."""
     k = {}
@@ -106,6 +107,7 @@ def build_structs(X, tris, node_mass, edge_stiffness, *, edges=None, h=1.0 / 120
     p.adj_max_iters = adj_max_iters
     p.checkpoint_every = checkpoint_every
     p.adj_restart = adj_restart
+    p.adj_solver = {"iterative": B.SIM_ADJ_ITERATIVE, "direct": B.SIM_ADJ_DIRECT}[adj_solver]
     return mesh, p, k
 
 

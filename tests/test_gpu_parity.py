@@ -206,3 +206,80 @@ def test_sphere_drop_adjoint_steps_from_gpu_state():
         assert ddw <= 1e-5 * np.linalg.norm(dw[:model.n_spring]) + 1e-12, n
         checked += 1
     assert checked >= 3
+
+
+# ------------------------------------------------------------------ direct adjoint (per-step factorisation)
+
+def test_direct_adjoint_napkin_fp64():
+    sc = scenes.c1_napkin(0)
+    model, recs, traj = _oracle(sc)
+    sim = _sim(sc, precision="fp64", adj_solver="direct")
+    _check_forward(sim, model, recs, traj)
+    errs, out, _ = _check_grads(sim, model, recs, tol=1e-6)
+    assert out["status"] == 0
+    print("napkin direct adjoint: grad errs", errs, "solves", sim.stats()["adj_iters_total"])
+
+
+@pytest.mark.parametrize("obst,pins,seed", [("plane", False, 1), ("sphere", False, 2), (None, True, 3)])
+def test_direct_adjoint_tiny_scenes(obst, pins, seed):
+    sc = scenes.tiny_scene(5, steps=15, obstacle=obst, pins=pins, seed=seed, height=0.01, v0_scale=0.1, k=200.0)
+    model, recs, traj = _oracle(sc)
+    sim = _sim(sc, precision="fp64", adj_solver="direct")
+    _check_forward(sim, model, recs, traj, tol=1e-9)
+    _check_grads(sim, model, recs, tol=1e-8, seed_gv=True)
+
+
+def test_direct_adjoint_skirt_regions_with_checkpoints():
+    sc = scenes.c3_skirt(0, n_around=12, n_rings=14, steps=10)
+    model, recs, traj = _oracle(sc)
+    sim = _sim(sc, precision="fp64", adj_solver="direct", checkpoint_every=4)
+    sim.forward(sc.steps)
+    ang, g = O.apex_angle_loss(recs[-1].x1, sc.waist_nodes, sc.hem_nodes)
+    G = O.backward(model, recs, g)
+    out = sim.backward(torch.tensor(g, device=DEV))
+    assert _rel(out["dregion"].cpu().numpy(), G.dregion) <= 1e-6
+    assert _rel(out["dx0"].cpu().numpy(), G.dx0) <= 1e-6
+
+
+def test_direct_adjoint_sphere_drop_every_step_converges():
+    # at 40x40 the iterative adjoint misses its tolerance on most steps; the
+    # direct solve matches the oracle's direct solve on every sampled step
+    sc = scenes.c2_sphere_drop(0, steps=200)
+    model = O.Model(sc)
+    sim = _sim(sc, precision="fp64", adj_solver="direct", adj_max_iters=10)
+    sim.forward(sc.steps)
+    rng = np.random.default_rng(0)
+    for n in (5, 28, 35, 60, 120, 199):
+        x, v = sim.state(n)
+        rec = O.forward_step(model, x.cpu().numpy(), v.cpu().numpy(), n)
+        gx, gv = rng.normal(size=(2, sc.n_nodes, 3))
+        out = sim.adjoint_step(n, torch.tensor(gx, device=DEV), torch.tensor(gv, device=DEV))
+        assert out["status"] == 0, n
+        dx, dv, dw, dmu, _ = O.backward_step(model, rec, gx, gv, n)
+        e = (_rel(out["dx0"].cpu().numpy(), dx), _rel(out["dv0"].cpu().numpy(), dv))
+        print(f"step {n}: direct adjoint rel err dx {e[0]:.2e} dv {e[1]:.2e}", flush=True)
+        assert max(e) <= 1e-6, n
+        ddw = np.linalg.norm(out["dw_edge"].cpu().numpy() - dw[:model.n_spring])
+        assert ddw <= 1e-5 * np.linalg.norm(dw[:model.n_spring]) + 1e-12, n
+
+
+def test_direct_adjoint_batch_and_checkpoint_are_bitwise():
+    from paper_2106_05306_amd.sim import batch_backward, batch_forward
+    batch = scenes.c4_batch(seed=2, count=3, steps=10, n_lo=6, n_hi=12)
+    singles, sims = [], []
+    for sc in batch:
+        s = _sim(sc, precision="fp64", adj_solver="direct", adj_tol=1e-10, adj_max_iters=10)
+        s.forward(sc.steps)
+        gseed = torch.ones(sc.n_nodes, 3, dtype=torch.float64, device=DEV)
+        singles.append(s.backward(gseed))
+        c = _sim(sc, precision="fp64", adj_solver="direct", adj_tol=1e-10, adj_max_iters=10, checkpoint_every=3)
+        c.forward(sc.steps)
+        gc = c.backward(gseed)
+        for key in ("dx0", "dv0", "dw_edge", "dmu"):
+            assert torch.equal(singles[-1][key], gc[key]), key
+        sims.append(_sim(sc, precision="fp64", adj_solver="direct", adj_tol=1e-10, adj_max_iters=10))
+    batch_forward(sims, [sc.steps for sc in batch])
+    grads = batch_backward(sims, [torch.ones(sc.n_nodes, 3, dtype=torch.float64, device=DEV) for sc in batch])
+    for g1, g2 in zip(singles, grads):
+        for key in ("dx0", "dv0", "dw_edge", "dmu"):
+            assert torch.equal(g1[key], g2[key]), key
