@@ -489,7 +489,10 @@ void build_device(sim *s) {
             if (it == e || *it != node) throw std::runtime_error("factor structure misses an entry of A");
             return (int)(it - b);
         };
-        // scatter target of every block (i, j) of the pattern of K_s (new order)
+        // scatter target of every block (i, j) of the pattern of K_s (new order).
+        // Blocks are stored transposed (column-major): D_s^T (N x N), B_s^T
+        // (N x R) and A(s, R_s)^T (R x N), row-major; entry (r, c) of the 3 x 3
+        // block (i, j) of A is at kdst + c * kld + r.
         std::vector<int64_t> kdst(kc.size());
         std::vector<int32_t> kld(kc.size());
         for (int i = 0; i < m; ++i) {
@@ -497,18 +500,18 @@ void build_device(sim *s) {
                 const int j = kc[e], si = hm.sup_of[i], sj = hm.sup_of[j];
                 if (si == sj) {
                     const LuSup &q = ls[si];
-                    kdst[e] = q.off + (int64_t)3 * (i - q.c0) * 3 * q.n + 3 * (j - q.c0);
+                    kdst[e] = q.off + (int64_t)3 * (j - q.c0) * 3 * q.n + 3 * (i - q.c0);
                     kld[e] = 3 * q.n;
                 } else if (sj < si) {                   // lower: i in R_sj
                     const LuSup &q = ls[sj];
-                    const int64_t N = 3 * (int64_t)q.n;
-                    kdst[e] = q.off + N * N + (int64_t)3 * pos_in_R(sj, i) * N + 3 * (j - q.c0);
-                    kld[e] = (int32_t)N;
+                    const int64_t N = 3 * (int64_t)q.n, R = 3 * (int64_t)q.r;
+                    kdst[e] = q.off + N * N + (int64_t)3 * (j - q.c0) * R + 3 * pos_in_R(sj, i);
+                    kld[e] = (int32_t)R;
                 } else {                                // upper: j in R_si
                     const LuSup &q = ls[si];
                     const int64_t N = 3 * (int64_t)q.n, R = 3 * (int64_t)q.r;
-                    kdst[e] = q.off + N * N + R * N + (int64_t)3 * (i - q.c0) * R + 3 * pos_in_R(si, j);
-                    kld[e] = (int32_t)R;
+                    kdst[e] = q.off + N * N + R * N + (int64_t)3 * pos_in_R(si, j) * N + 3 * (i - q.c0);
+                    kld[e] = (int32_t)N;
                 }
             }
         }
@@ -527,37 +530,21 @@ void build_device(sim *s) {
                 dptr.push_back((int32_t)dks.size());
             }
         }
-        // solve items grouped by level
+        // solve items grouped by level: 64-row chunks of D_s^{-1} (z and
+        // backward products) and of B_s (update products), one wavefront each
         const int L = hm.n_levels;
-        std::vector<int32_t> lvl(3 * (L + 1), 0), lsn, lteam(3 * L, 1);
+        std::vector<int32_t> lvl(3 * (L + 1), 0), lsn;
         std::vector<LuItem> zi, ui;
-        auto pick = [](int items, int maxlen) {
-            int best = 1;
-            double best_cost = 1e300;
-            for (int tl = 1; tl <= 32; tl *= 2) {
-                const int passes = (items * tl + kBlockAdj - 1) / kBlockAdj;
-                const double cost = passes * ((maxlen + tl - 1) / tl + 0.5 * __builtin_ctz(tl) + 1.0);
-                if (cost < best_cost) { best_cost = cost; best = tl; }
-            }
-            return best;
-        };
         for (int l = 0; l < L; ++l) {
-            int zmax = 1, rmax = 1;
-            const int z0 = (int)zi.size(), u0 = (int)ui.size();
             for (int sn = 0; sn < ns; ++sn) {
                 if (hm.sup_level[sn] != l) continue;
                 lsn.push_back(sn);
-                for (int a = 0; a < 3 * sns[sn]; ++a) zi.push_back(LuItem{sn, a});
-                for (int a = 0; a < 3 * snr[sn]; ++a) ui.push_back(LuItem{sn, a});
-                zmax = std::max(zmax, 3 * sns[sn]);
-                rmax = std::max(rmax, 3 * snr[sn]);
+                for (int a = 0; a < 3 * sns[sn]; a += 64) zi.push_back(LuItem{sn, a});
+                for (int a = 0; a < 3 * snr[sn]; a += 64) ui.push_back(LuItem{sn, a});
             }
             lvl[3 * (l + 1)] = (int32_t)zi.size();
             lvl[3 * (l + 1) + 1] = (int32_t)ui.size();
             lvl[3 * (l + 1) + 2] = (int32_t)lsn.size();
-            lteam[3 * l] = pick((int)zi.size() - z0, zmax);
-            lteam[3 * l + 1] = pick((int)ui.size() - u0, zmax);
-            lteam[3 * l + 2] = pick((int)zi.size() - z0, rmax);
         }
         D.ns = ns;
         D.lu_sup = upload(s, ls);
@@ -571,7 +558,6 @@ void build_device(sim *s) {
         D.lu_zitems = upload(s, zi);
         D.lu_uitems = upload(s, ui);
         D.lu_sn = upload(s, lsn);
-        D.lu_team = upload(s, lteam);
         // every row of R_d past the rows in s must be a row of R_s (the factor
         // kernel maps them through s's row table); panels must fit the LDS panel
         for (int t = 0; t < ns; ++t)

@@ -830,7 +830,7 @@ __global__ __launch_bounds__(kBlockAdj) void k_adj_factor(const SimDev *__restri
             const int ld = G(S.ks_ld)[e];
             const double k = hh * G(S.ks_val)[e];
             for (int r = 0; r < 3; ++r)
-                for (int c = 0; c < 3; ++c) d[r * ld + c] = r == c ? k : 0.0;
+                for (int c = 0; c < 3; ++c) d[c * ld + r] = r == c ? k : 0.0;
         }
         for (int p = G(S.inc_ptr)[i]; p < G(S.inc_ptr)[i + 1]; ++p) {
             const int c = G(S.inc_con)[p];
@@ -845,7 +845,7 @@ __global__ __launch_bounds__(kBlockAdj) void k_adj_factor(const SimDev *__restri
                 const auto d = F + G(S.ks_dst)[e];
                 const int ld = G(S.ks_ld)[e];
                 for (int r = 0; r < 3; ++r)
-                    for (int cc = 0; cc < 3; ++cc) d[r * ld + cc] -= f * ((r == cc ? 1.0 : 0.0) - qh[r] * qh[cc]);
+                    for (int cc = 0; cc < 3; ++cc) d[cc * ld + r] -= f * ((r == cc ? 1.0 : 0.0) - qh[r] * qh[cc]);
             }
         }
         for (int e = G(S.ks_ptr)[i]; e < G(S.ks_ptr)[i + 1]; ++e) {
@@ -855,7 +855,7 @@ __global__ __launch_bounds__(kBlockAdj) void k_adj_factor(const SimDev *__restri
             const int ld = G(S.ks_ld)[e];
             double b[9];
             for (int r = 0; r < 3; ++r)
-                for (int c = 0; c < 3; ++c) b[3 * r + c] = d[r * ld + c];
+                for (int c = 0; c < 3; ++c) b[3 * r + c] = d[c * ld + r];
             if (md == STICK) {
                 for (int q = 0; q < 9; ++q) b[q] = 0.0;
             } else if (md == SLIP) {                      // H_ij T_j^T
@@ -872,7 +872,7 @@ __global__ __launch_bounds__(kBlockAdj) void k_adj_factor(const SimDev *__restri
             }
             for (int r = 0; r < 3; ++r)
                 for (int c = 0; c < 3; ++c) {
-                    d[r * ld + c] = b[3 * r + c];
+                    d[c * ld + r] = b[3 * r + c];
                     rsum[r] += fabs(b[3 * r + c]);
                 }
         }
@@ -891,7 +891,9 @@ __global__ __launch_bounds__(kBlockAdj) void k_adj_factor(const SimDev *__restri
         for (int t = tid; t < q.n; t += bd) rowpos[q.c0 + t] = t;
         for (int t = tid; t < q.r; t += bd) rowpos[G(S.sup_rows)[q.rptr + t]] = q.n + t;
         __syncthreads();
-        // Schur updates B_d V_d of the descendants reaching s
+        // Schur updates B_d V_d of the descendants reaching s (blocks stored
+        // transposed: Bt_d[k][a] = B_d[a][k], Vt_d[b][k] = V_d[k][b]); threads run
+        // along a, so loads and stores are contiguous
         for (int u = G(S.lu_upd_ptr)[sn]; u < G(S.lu_upd_ptr)[sn + 1]; ++u) {
             const auto &ud = G(S.lu_upd)[u];
             const auto &qd = G(S.lu_sup)[ud.d];
@@ -904,23 +906,24 @@ __global__ __launch_bounds__(kBlockAdj) void k_adj_factor(const SimDev *__restri
             for (int idx = tid; idx < nlow + nup; idx += bd) {
                 int a, b;
                 if (idx < nlow) {
-                    a = a0 + idx / wc;
-                    b = a0 + idx % wc;
+                    b = a0 + idx / (Rd - a0);
+                    a = a0 + idx % (Rd - a0);
                 } else {
                     const int k = idx - nlow;
-                    a = a0 + k / (Rd - a1);
-                    b = a1 + k % (Rd - a1);
+                    b = a1 + k / wc;
+                    a = a0 + k % wc;
                 }
-                const auto br = Bd + (int64_t)a * Nd;
+                const auto vb = Vd + (int64_t)b * Nd;
                 double acc = 0.0;
-                for (int k = 0; k < Nd; ++k) acc += br[k] * Vd[(int64_t)k * Rd + b];
+#pragma unroll 4
+                for (int k = 0; k < Nd; ++k) acc += Bd[(int64_t)k * Rd + a] * vb[k];
                 const int ra = rowpos[Rrows[a / 3]], rb = rowpos[Rrows[b / 3]];
                 const int ca = a % 3, cb = b % 3;
                 if (idx < nlow) {
-                    if (ra < q.n) D[(int64_t)(3 * ra + ca) * N + 3 * rb + cb] -= acc;
-                    else Bp[(int64_t)(3 * (ra - q.n) + ca) * N + 3 * rb + cb] -= acc;
+                    if (ra < q.n) D[(int64_t)(3 * rb + cb) * N + 3 * ra + ca] -= acc;
+                    else Bp[(int64_t)(3 * rb + cb) * R + 3 * (ra - q.n) + ca] -= acc;
                 } else {
-                    C[(int64_t)(3 * ra + ca) * R + 3 * (rb - q.n) + cb] -= acc;
+                    C[(int64_t)(3 * (rb - q.n) + cb) * N + 3 * ra + ca] -= acc;
                 }
             }
             __syncthreads();
@@ -985,22 +988,21 @@ __global__ __launch_bounds__(kBlockAdj) void k_adj_factor(const SimDev *__restri
                 }
             __syncthreads();
         }
-        // V_s = D_s^{-1} A(s, R_s), one LDS panel of columns at a time
+        // V_s = D_s^{-1} A(s, R_s); transposed: Vt = Ct (D^{-1})^T, i.e. every row
+        // of Ct times the stored inverse, a panel of rows at a time through LDS
         if (R > 0) {
-            const int cw = max(1, min(R, kLuPanel / N));
-            for (int c0 = 0; c0 < R; c0 += cw) {
-                const int w = min(cw, R - c0);
-                for (int idx = tid; idx < N * w; idx += bd) {
-                    const int k = idx / w, j = idx - k * w;
-                    panel[idx] = C[(int64_t)k * R + c0 + j];
-                }
+            const int rw = max(1, min(R, kLuPanel / N));
+            for (int j0 = 0; j0 < R; j0 += rw) {
+                const int w = min(rw, R - j0);
+                for (int idx = tid; idx < w * N; idx += bd) panel[idx] = C[(int64_t)j0 * N + idx];
                 __syncthreads();
-                for (int idx = tid; idx < N * w; idx += bd) {
-                    const int i = idx / w, j = idx - i * w;
-                    const auto dr = D + (int64_t)i * N;
+                for (int idx = tid; idx < w * N; idx += bd) {
+                    const int jj = idx / N, i = idx - jj * N;
+                    const double *cr = panel + jj * N;
                     double acc = 0.0;
-                    for (int k = 0; k < N; ++k) acc += dr[k] * panel[k * w + j];
-                    C[(int64_t)i * R + c0 + j] = acc;
+#pragma unroll 4
+                    for (int k = 0; k < N; ++k) acc += cr[k] * D[(int64_t)k * N + i];
+                    C[(int64_t)(j0 + jj) * N + i] = acc;
                 }
                 __syncthreads();
             }
@@ -1012,9 +1014,29 @@ __global__ __launch_bounds__(kBlockAdj) void k_adj_factor(const SimDev *__restri
 // A z = b with a step factor F: forward over the levels (children first)
 //   t_s = b_s - (update entries reaching s), z_s = D_s^{-1} t_s, u_s = B_s z_s;
 // backward (parents first) x_s = z_s - V_s x_{R_s}.  Same level schedule and
-// update-buffer layout as solve_P; x must not alias b, T or Z.
+// update-buffer layout as solve_P.  One wavefront per 64-row chunk of a block,
+// one lane per row, a loop over the columns of the column-major block: every
+// factor load is one contiguous 512-byte wavefront load.  x must not alias b,
+// T or Z.
+// sum over k < n of col[k ld] v[k] in order; sixteen independent loads are
+// issued before their products (the step factors stream from HBM)
+__device__ __forceinline__ double col_dot(auto col, int64_t ld, auto v, int n) {
+    double acc = 0.0;
+    int k = 0;
+    for (; k + 16 <= n; k += 16) {
+        double c[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) c[j] = col[(int64_t)(k + j) * ld];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc += c[j] * v[k + j];
+    }
+    for (; k < n; ++k) acc += col[(int64_t)k * ld] * v[k];
+    return acc;
+}
+
 __device__ __forceinline__ void solve_A(const SimDev &S, auto F, auto b, auto T, auto Z, auto x, auto U) {
     const int tid = threadIdx.x, bd = blockDim.x;
+    const int wave = tid >> 6, lane = tid & 63, nw = bd >> 6;
     const auto lvl = G(S.lu_lvl);
     for (int l = 0; l < S.n_levels; ++l) {
         for (int it = G(S.lvl_rows_ptr)[l] + tid; it < G(S.lvl_rows_ptr)[l + 1]; it += bd) {
@@ -1027,47 +1049,35 @@ __device__ __forceinline__ void solve_A(const SimDev &S, auto F, auto b, auto T,
             T[ri.i3] = t0; T[ri.i3 + 1] = t1; T[ri.i3 + 2] = t2;
         }
         __syncthreads();
-        {
-            const int tl = G(S.lu_team)[3 * l], lane = tid & (tl - 1);
-            for (int it = lvl[3 * l] + tid / tl; it < lvl[3 * (l + 1)]; it += bd / tl) {
-                const auto &li = G(S.lu_zitems)[it];
-                const auto &q = G(S.lu_sup)[li.s];
-                const int N = 3 * q.n, t0 = 3 * q.c0;
-                const auto row = F + q.off + (int64_t)li.a * N;
-                double acc = 0.0;
-                for (int k = lane; k < N; k += tl) acc += row[k] * T[t0 + k];
-                acc = team_sum(acc, tl);
-                if (lane == 0) Z[t0 + li.a] = acc;
-            }
+        for (int it = lvl[3 * l] + wave; it < lvl[3 * (l + 1)]; it += nw) {
+            const auto &li = G(S.lu_zitems)[it];
+            const auto &q = G(S.lu_sup)[li.s];
+            const int N = 3 * q.n, t0 = 3 * q.c0, r = li.a + lane;
+            if (r < N) Z[t0 + r] = col_dot(F + q.off + r, N, T + t0, N);
         }
         __syncthreads();
-        {
-            const int tl = G(S.lu_team)[3 * l + 1], lane = tid & (tl - 1);
-            for (int it = lvl[3 * l + 1] + tid / tl; it < lvl[3 * (l + 1) + 1]; it += bd / tl) {
-                const auto &li = G(S.lu_uitems)[it];
-                const auto &q = G(S.lu_sup)[li.s];
-                const int N = 3 * q.n, t0 = 3 * q.c0;
-                const auto row = F + q.off + (int64_t)N * N + (int64_t)li.a * N;
-                double acc = 0.0;
-                for (int k = lane; k < N; k += tl) acc += row[k] * Z[t0 + k];
-                acc = team_sum(acc, tl);
-                if (lane == 0) U[q.uoff + li.a] = acc;
-            }
+        for (int it = lvl[3 * l + 1] + wave; it < lvl[3 * (l + 1) + 1]; it += nw) {
+            const auto &li = G(S.lu_uitems)[it];
+            const auto &q = G(S.lu_sup)[li.s];
+            const int N = 3 * q.n, R = 3 * q.r, t0 = 3 * q.c0, r = li.a + lane;
+            if (r < R) U[q.uoff + r] = col_dot(F + q.off + (int64_t)N * N + r, R, Z + t0, N);
         }
         __syncthreads();
     }
     for (int l = S.n_levels - 1; l >= 0; --l) {
-        const int tl = G(S.lu_team)[3 * l + 2], lane = tid & (tl - 1);
-        for (int it = lvl[3 * l] + tid / tl; it < lvl[3 * (l + 1)]; it += bd / tl) {
+        // x_{R_s} of every supernode of the level, gathered into the (now free)
+        // update buffer in the layout of u_s
+        for (int it = lvl[3 * l + 2] + wave; it < lvl[3 * (l + 1) + 2]; it += nw) {
+            const auto &q = G(S.lu_sup)[G(S.lu_sn)[it]];
+            const auto rr = G(S.sup_rows) + q.rptr;
+            for (int k = lane; k < 3 * q.r; k += 64) U[q.uoff + k] = x[3 * rr[k / 3] + k % 3];
+        }
+        __syncthreads();
+        for (int it = lvl[3 * l] + wave; it < lvl[3 * (l + 1)]; it += nw) {
             const auto &li = G(S.lu_zitems)[it];
             const auto &q = G(S.lu_sup)[li.s];
-            const int N = 3 * q.n, R = 3 * q.r, t0 = 3 * q.c0;
-            const auto row = F + q.off + (int64_t)N * N + (int64_t)R * N + (int64_t)li.a * R;
-            const auto rr = G(S.sup_rows) + q.rptr;
-            double acc = 0.0;
-            for (int k = lane; k < R; k += tl) acc += row[k] * x[3 * rr[k / 3] + k % 3];
-            acc = team_sum(acc, tl);
-            if (lane == 0) x[t0 + li.a] = Z[t0 + li.a] - acc;
+            const int N = 3 * q.n, R = 3 * q.r, t0 = 3 * q.c0, r = li.a + lane;
+            if (r < N) x[t0 + r] = Z[t0 + r] - col_dot(F + q.off + (int64_t)N * N + (int64_t)R * N + r, N, U + q.uoff, R);
         }
         __syncthreads();
     }

@@ -42,7 +42,7 @@ struct SpringInc {          // node-centred spring projection: one incident spri
     double rho, w;          // rest length and weight
 };
 
-struct LuItem {             // direct adjoint solve: row a of supernode s
+struct LuItem {             // direct adjoint solve: rows [a, a + 64) of a block of supernode s
     int32_t s, a;
 };
 struct LuUpd {              // supernode s is updated by descendant d: rows [i0, i1) of R_d lie in s
@@ -146,7 +146,7 @@ struct SimDev {
 
     // direct adjoint: per step an LU-type factor of A = M + H T^T on the
     // supernodes of P (degrees of freedom, not nodes): per supernode s with
-    // N = 3 n_s, R = 3 r_s, row-major blocks D_s^{-1} (N x N), B_s = A(R_s, s)
+    // N = 3 n_s, R = 3 r_s, column-major blocks D_s^{-1} (N x N), B_s = A(R_s, s)
     // after the Schur updates (R x N) and V_s = D_s^{-1} A(s, R_s) (N x R)
     int adj_direct;                   // 1: adjoint steps solved with their factors
     int ns;                           // supernodes
@@ -158,10 +158,9 @@ struct SimDev {
     const int32_t *dp_ptr;            // [n_inc+1] per incidence entry (node i, constraint c):
     const int32_t *dp_ks;             //   K_s entry of (i, l) for each stencil node l of c
     const int32_t *lu_lvl;            // [3*(n_levels+1)]: per level start of z items, u items, supernodes
-    const LuItem *lu_zitems;          // rows of D_s^{-1} / V_s, grouped by level
-    const LuItem *lu_uitems;          // rows of B_s, grouped by level
+    const LuItem *lu_zitems;          // row chunks of D_s^{-1} / V_s, grouped by level
+    const LuItem *lu_uitems;          // row chunks of B_s, grouped by level
     const int32_t *lu_sn;             // supernodes grouped by level
-    const int32_t *lu_team;           // [3*n_levels] lanes per item: z, u, backward
     int64_t af_size;                  // doubles per step factor
     int64_t af_ws_size;               // doubles of factorisation workspace per step
     int af_nmax;                      // largest N
