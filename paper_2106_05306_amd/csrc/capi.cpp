@@ -27,7 +27,8 @@ hipError_t launch_scatter_bend(const double *dw, const int32_t *centers, int n_e
                                hipStream_t st);
 hipError_t launch_fill(double *p, double v, int64_t n, hipStream_t st);
 size_t adj_factor_lds(int nmax);
-hipError_t launch_adj_factor(const SimDev *d_sims, const int32_t *work, int nblocks, int nmax, hipStream_t st);
+hipError_t launch_adj_assemble(const SimDev *d_sims, const int32_t *work, int nblocks, hipStream_t st);
+hipError_t launch_adj_factor_level(const SimDev *d_sims, const int32_t *work, int nblocks, int nmax, hipStream_t st);
 }  // namespace dc
 
 using namespace dc;
@@ -58,6 +59,11 @@ struct sim {
     int64_t counters_host[8] = {0};
     int nca = 0;
     int af_cap = 0;                     // step factors allocated (direct adjoint)
+    int n_ubuf_bwd = 0;                 // update-buffer doubles the backward kernel needs
+    std::vector<std::vector<int32_t>> lvl_sn;   // supernodes of each elimination level
+    std::vector<int32_t> h_work;        // factorisation work lists (host copy)
+    int32_t *d_work = nullptr;          // and their device copy
+    size_t work_cap = 0;
     std::vector<int32_t> corder;        // device constraint slot -> canonical constraint id
     int64_t factor_bytes = 0;
     size_t lds_fwd = 0, lds_bwd = 0;   // dynamic LDS of the two kernels
@@ -120,7 +126,7 @@ size_t lds_bytes(const sim *s, int flags, bool fwd) {
     const size_t m3 = 3 * (size_t)s->hd.m;
     size_t b = 0;
     if (flags & kLdsVectors) b += 2 * m3;
-    if (flags & kLdsUpdates) b += (size_t)s->hd.n_ubuf;
+    if (flags & kLdsUpdates) b += (size_t)(fwd ? s->hd.n_ubuf : s->n_ubuf_bwd);
     if (fwd && (flags & kLdsPositions)) b += m3;
     return b * sizeof(double);
 }
@@ -448,69 +454,103 @@ void build_device(sim *s) {
     D.binc_con = upload(s, bc);
     D.binc_coef = upload(s, bcf);
     s->factor_bytes = (int64_t)gval.size() * 8;   // per copy (forward and backward each hold one)
-    // direct adjoint: supernode table, update lists, scatter targets of A's blocks, solve items
+    // direct adjoint: its own supernode partition (the supernodes of P cut into
+    // chunks of at most kLuChunk nodes, so every diagonal block fits the
+    // register inversion), update lists, scatter targets of A's blocks, solve
+    // schedule
     {
-        std::vector<LuSup> ls(ns);
-        int64_t off = 0;
-        int nmax = 3;
+        const int kLuChunk = 42;
+        std::vector<int32_t> ac0, an, arptr(1, 0), arows, chunk_of(m);
         for (int sn = 0; sn < ns; ++sn) {
-            LuSup &q = ls[sn];
-            q.c0 = sc0[sn];
-            q.n = sns[sn];
-            q.r = snr[sn];
-            q.rptr = rptr[sn];
-            q.uoff = uoff[sn];
+            const int nck = (sns[sn] + kLuChunk - 1) / kLuChunk, s_end = sc0[sn] + sns[sn];
+            for (int j = 0; j < nck; ++j) {
+                const int c0 = sc0[sn] + (int)((int64_t)sns[sn] * j / nck);
+                const int c1 = sc0[sn] + (int)((int64_t)sns[sn] * (j + 1) / nck);
+                for (int c = c0; c < c1; ++c) chunk_of[c] = (int32_t)ac0.size();
+                ac0.push_back(c0);
+                an.push_back(c1 - c0);
+                for (int c = c1; c < s_end; ++c) arows.push_back(c);      // later chunks of the same supernode
+                for (int q = 0; q < snr[sn]; ++q) arows.push_back(rows[rptr[sn] + q]);
+                arptr.push_back((int32_t)arows.size());
+            }
+        }
+        const int na = (int)ac0.size();
+        std::vector<LuSup> ls(na);
+        int64_t off = 0;
+        int nmax = 3, ubuf_a = 0;
+        for (int t = 0; t < na; ++t) {
+            LuSup &q = ls[t];
+            q.c0 = ac0[t];
+            q.n = an[t];
+            q.r = arptr[t + 1] - arptr[t];
+            q.rptr = arptr[t];
+            q.uoff = ubuf_a;
+            ubuf_a += 3 * q.r;
             q.off = off;
             const int64_t N = 3 * (int64_t)q.n, R = 3 * (int64_t)q.r;
             off += N * N + 2 * N * R;
             nmax = std::max(nmax, (int)N);
         }
-        // updaters: descendant d reaches supernode t through a run of rows of R_d
-        std::vector<std::vector<LuUpd>> ul(ns);
-        for (int d = 0; d < ns; ++d) {
-            const int r0 = rptr[d], nr = snr[d];
+        if (nmax > 384) throw std::runtime_error("supernode chunk too large for the direct adjoint");
+        // updaters: chunk d reaches chunk t through a run of rows of R_d
+        std::vector<std::vector<LuUpd>> ul(na);
+        for (int d = 0; d < na; ++d) {
+            const int r0 = arptr[d], nr = arptr[d + 1] - arptr[d];
             for (int i = 0; i < nr;) {
-                const int t = hm.sup_of[rows[r0 + i]];
+                const int t = chunk_of[arows[r0 + i]];
                 int j = i;
-                while (j < nr && hm.sup_of[rows[r0 + j]] == t) ++j;
+                while (j < nr && chunk_of[arows[r0 + j]] == t) ++j;
                 ul[t].push_back(LuUpd{d, i, j, 0});
                 i = j;
             }
         }
-        std::vector<int32_t> up_ptr(1, 0);
-        std::vector<LuUpd> upl;
-        for (int t = 0; t < ns; ++t) {
-            upl.insert(upl.end(), ul[t].begin(), ul[t].end());
-            up_ptr.push_back((int32_t)upl.size());
-        }
-        auto pos_in_R = [&](int sn, int node) {
-            const int *b = rows.data() + rptr[sn], *e = b + snr[sn];
+        auto pos_in_R = [&](int t, int node) {
+            const int *b = arows.data() + arptr[t], *e = arows.data() + arptr[t + 1];
             const int *it = std::lower_bound(b, e, node);
             if (it == e || *it != node) throw std::runtime_error("factor structure misses an entry of A");
             return (int)(it - b);
         };
+        // panel rows in t of the rows of R_d from i0 on: nodes of t first, then
+        // R_t (every later row of R_d must be a row of R_t); levels: one more
+        // than the highest updater
+        std::vector<int32_t> up_ptr(1, 0), relmap, alevel(na, 0);
+        std::vector<LuUpd> upl;
+        for (int t = 0; t < na; ++t) {
+            for (LuUpd ud : ul[t]) {
+                ud.map = (int32_t)relmap.size();
+                for (int i = ud.i0; i < arptr[ud.d + 1] - arptr[ud.d]; ++i) {
+                    const int node = arows[arptr[ud.d] + i];
+                    relmap.push_back(i < ud.i1 ? node - ac0[t] : an[t] + pos_in_R(t, node));
+                }
+                upl.push_back(ud);
+                alevel[t] = std::max(alevel[t], alevel[ud.d] + 1);
+            }
+            up_ptr.push_back((int32_t)upl.size());
+        }
+        int L = 0;
+        for (int t = 0; t < na; ++t) L = std::max(L, alevel[t] + 1);
         // scatter target of every block (i, j) of the pattern of K_s (new order).
-        // Blocks are stored transposed (column-major): D_s^T (N x N), B_s^T
-        // (N x R) and A(s, R_s)^T (R x N), row-major; entry (r, c) of the 3 x 3
+        // Blocks are stored transposed (column-major): D_t^T (N x N), B_t^T
+        // (N x R) and A(t, R_t)^T (R x N), row-major; entry (r, c) of the 3 x 3
         // block (i, j) of A is at kdst + c * kld + r.
         std::vector<int64_t> kdst(kc.size());
         std::vector<int32_t> kld(kc.size());
         for (int i = 0; i < m; ++i) {
             for (int e = kp[i]; e < kp[i + 1]; ++e) {
-                const int j = kc[e], si = hm.sup_of[i], sj = hm.sup_of[j];
-                if (si == sj) {
-                    const LuSup &q = ls[si];
+                const int j = kc[e], ti = chunk_of[i], tj = chunk_of[j];
+                if (ti == tj) {
+                    const LuSup &q = ls[ti];
                     kdst[e] = q.off + (int64_t)3 * (j - q.c0) * 3 * q.n + 3 * (i - q.c0);
                     kld[e] = 3 * q.n;
-                } else if (sj < si) {                   // lower: i in R_sj
-                    const LuSup &q = ls[sj];
+                } else if (tj < ti) {                   // lower: i in R_tj
+                    const LuSup &q = ls[tj];
                     const int64_t N = 3 * (int64_t)q.n, R = 3 * (int64_t)q.r;
-                    kdst[e] = q.off + N * N + (int64_t)3 * (j - q.c0) * R + 3 * pos_in_R(sj, i);
+                    kdst[e] = q.off + N * N + (int64_t)3 * (j - q.c0) * R + 3 * pos_in_R(tj, i);
                     kld[e] = (int32_t)R;
-                } else {                                // upper: j in R_si
-                    const LuSup &q = ls[si];
+                } else {                                // upper: j in R_ti
+                    const LuSup &q = ls[ti];
                     const int64_t N = 3 * (int64_t)q.n, R = 3 * (int64_t)q.r;
-                    kdst[e] = q.off + N * N + R * N + (int64_t)3 * pos_in_R(si, j) * N + 3 * (i - q.c0);
+                    kdst[e] = q.off + N * N + R * N + (int64_t)3 * pos_in_R(ti, j) * N + 3 * (i - q.c0);
                     kld[e] = (int32_t)N;
                 }
             }
@@ -530,26 +570,42 @@ void build_device(sim *s) {
                 dptr.push_back((int32_t)dks.size());
             }
         }
-        // solve items grouped by level: 64-row chunks of D_s^{-1} (z and
-        // backward products) and of B_s (update products), one wavefront each
-        const int L = hm.n_levels;
-        std::vector<int32_t> lvl(3 * (L + 1), 0), lsn;
-        std::vector<LuItem> zi, ui;
-        for (int l = 0; l < L; ++l) {
-            for (int sn = 0; sn < ns; ++sn) {
-                if (hm.sup_level[sn] != l) continue;
-                lsn.push_back(sn);
-                for (int a = 0; a < 3 * sns[sn]; a += 64) zi.push_back(LuItem{sn, a});
-                for (int a = 0; a < 3 * snr[sn]; a += 64) ui.push_back(LuItem{sn, a});
-            }
-            lvl[3 * (l + 1)] = (int32_t)zi.size();
-            lvl[3 * (l + 1) + 1] = (int32_t)ui.size();
-            lvl[3 * (l + 1) + 2] = (int32_t)lsn.size();
+        // solve schedule by level: forward gathers (per node: the update-buffer
+        // entries reaching it), 64-row chunks of D^{-1} (z and backward products)
+        // and of B (update products), one wavefront each
+        std::vector<std::vector<int32_t>> aupd(m);
+        for (int d = 0; d < na; ++d)
+            for (int q = 0; q < ls[d].r; ++q) aupd[arows[arptr[d] + q]].push_back(ls[d].uoff + 3 * q);
+        std::vector<int32_t> aup(1, 0), auo;
+        for (int i = 0; i < m; ++i) {
+            auo.insert(auo.end(), aupd[i].begin(), aupd[i].end());
+            aup.push_back((int32_t)auo.size());
         }
-        D.ns = ns;
+        std::vector<int32_t> lvl(4 * (L + 1), 0), lsn;
+        std::vector<LuItem> zi, ui;
+        std::vector<RowItem> ri;
+        for (int l = 0; l < L; ++l) {
+            for (int t = 0; t < na; ++t) {
+                if (alevel[t] != l) continue;
+                lsn.push_back(t);
+                for (int a = 0; a < 3 * an[t]; a += 64) zi.push_back(LuItem{t, a});
+                for (int a = 0; a < 3 * ls[t].r; a += 64) ui.push_back(LuItem{t, a});
+                for (int c = ac0[t]; c < ac0[t] + an[t]; ++c) ri.push_back(RowItem{3 * c, aup[c], aup[c + 1], 0});
+            }
+            lvl[4 * (l + 1)] = (int32_t)zi.size();
+            lvl[4 * (l + 1) + 1] = (int32_t)ui.size();
+            lvl[4 * (l + 1) + 2] = (int32_t)lsn.size();
+            lvl[4 * (l + 1) + 3] = (int32_t)ri.size();
+        }
+        s->lvl_sn.assign(L, {});
+        for (int l = 0; l < L; ++l) s->lvl_sn[l].assign(lsn.begin() + lvl[4 * l + 2], lsn.begin() + lvl[4 * (l + 1) + 2]);
+        D.ns = na;
+        D.lu_nlevels = L;
         D.lu_sup = upload(s, ls);
+        D.lu_srows = upload(s, arows);
         D.lu_upd_ptr = upload(s, up_ptr);
         D.lu_upd = upload(s, upl);
+        D.lu_relmap = upload(s, relmap);
         D.ks_dst = upload(s, kdst);
         D.ks_ld = upload(s, kld);
         D.dp_ptr = upload(s, dptr);
@@ -558,20 +614,19 @@ void build_device(sim *s) {
         D.lu_zitems = upload(s, zi);
         D.lu_uitems = upload(s, ui);
         D.lu_sn = upload(s, lsn);
-        // every row of R_d past the rows in s must be a row of R_s (the factor
-        // kernel maps them through s's row table); panels must fit the LDS panel
-        for (int t = 0; t < ns; ++t)
-            for (int u = up_ptr[t]; u < up_ptr[t + 1]; ++u) {
-                const LuUpd &ud = upl[u];
-                for (int i = ud.i1; i < snr[ud.d]; ++i) (void)pos_in_R(t, rows[rptr[ud.d] + i]);
-            }
-        if (nmax > 8192) throw std::runtime_error("supernode too large for the direct adjoint");
+        D.lu_rows = upload(s, ri);
+        D.lu_upd_off = upload(s, auo);
         D.af_size = off;
         D.af_nmax = nmax;
-        // workspace: T blocks (9 m), projection scale + direction (4 nca), pivot
-        // perturbation count and |A|_inf (2), node -> panel row map (m int32)
-        D.af_ws_size = 9 * (int64_t)m + 4 * (int64_t)std::max(nca, 1) + 2 + (m + 1) / 2;
+        // workspace: T blocks (9 m), projection scale + direction (4 nca),
+        // |A|_inf (1), perturbed pivots per chunk (na int32)
+        D.af_ws_size = 9 * (int64_t)m + 4 * (int64_t)std::max(nca, 1) + 1 + (na + 1) / 2;
         D.adj_direct = hm.adj_solver == SIM_ADJ_DIRECT;
+        s->n_ubuf_bwd = D.n_ubuf;
+        if (D.adj_direct && ubuf_a > D.n_ubuf) {           // the two solves share the update buffer
+            s->n_ubuf_bwd = ubuf_a;
+            D.ubuf = zeros<double>(s, ubuf_a);
+        }
     }
     // state and work buffers
     const size_t v3 = 3 * (size_t)m;
@@ -944,14 +999,62 @@ int prepare_backward(sim *s, const double *dL_dxT, const double *dL_dvT, const d
     return rc;
 }
 
-// Direct adjoint: factor steps [a, b) (records in place, rec_step0 set), one workgroup per step.
+// Direct adjoint factorisation of the (handle, slot) pairs listed in `pairs`
+// (handle = index into hs and into the device descriptor array d_descs): one
+// assembly launch, then one launch per elimination level with a workgroup per
+// (handle, slot, supernode).  The work lists go through owner's buffers; the
+// previous use of them is waited for first.
+int factor_pairs(sim *owner, const SimDev *d_descs, const std::vector<sim *> &hs, const std::vector<int32_t> &pairs) {
+    if (pairs.empty()) return SIM_OK;
+    int rc = hip_err(hipStreamSynchronize(owner->stream));
+    if (rc) return rc;
+    int L = 0, nmax = 3;
+    for (sim *h : hs) {
+        L = std::max(L, (int)h->lvl_sn.size());
+        nmax = std::max(nmax, h->hd.af_nmax);
+    }
+    std::vector<int32_t> &buf = owner->h_work;
+    buf = pairs;
+    std::vector<size_t> loff(L + 1);
+    for (int l = 0; l < L; ++l) {
+        loff[l] = buf.size();
+        for (size_t p = 0; p < pairs.size(); p += 2) {
+            const sim *h = hs[pairs[p]];
+            if (l >= (int)h->lvl_sn.size()) continue;
+            for (int sn : h->lvl_sn[l]) {
+                buf.push_back(pairs[p]);
+                buf.push_back(pairs[p + 1]);
+                buf.push_back(sn);
+            }
+        }
+    }
+    loff[L] = buf.size();
+    if (owner->work_cap < buf.size()) {
+        dev_release(owner, owner->d_work);
+        owner->d_work = nullptr;
+        owner->work_cap = 0;
+        owner->d_work = (int32_t *)dev_alloc(owner, buf.size() * sizeof(int32_t));
+        owner->work_cap = buf.size();
+    }
+    rc = hip_err(hipMemcpyAsync(owner->d_work, buf.data(), buf.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                owner->stream));
+    if (!rc) rc = hip_err(launch_adj_assemble(d_descs, owner->d_work, (int)pairs.size() / 2, owner->stream));
+    for (int l = 0; l < L && !rc; ++l)
+        rc = hip_err(launch_adj_factor_level(d_descs, owner->d_work + loff[l], (int)((loff[l + 1] - loff[l]) / 3), nmax,
+                                             owner->stream));
+    return rc;
+}
+
+// Direct adjoint: factor steps [a, b) of one handle (records in place, rec_step0 set).
 int factor_steps(sim *s, int a, int b) {
     if (!s->hd.adj_direct) return SIM_OK;
     ensure_af(s, b - a);
     s->hd.af_step0 = a;
     int rc = push_desc(s);
     if (rc) return rc;
-    return hip_err(launch_adj_factor(s->dd, nullptr, b - a, s->hd.af_nmax, s->stream));
+    std::vector<int32_t> pairs;
+    for (int k = 0; k < b - a; ++k) { pairs.push_back(0); pairs.push_back(k); }
+    return factor_pairs(s, s->dd, {s}, pairs);
 }
 
 int backward_all(sim *s) {
@@ -1192,7 +1295,7 @@ int sim_batch_backward(sim_t *const *sims, int32_t n, const double *const *dL_dx
     return guarded([&] {
         std::vector<SimDev> descs(n);
         std::vector<int32_t> work;           // (handle, slot) of every step factor (direct adjoint)
-        int rc = SIM_OK, nmax = 3;
+        int rc = SIM_OK;
         for (int i = 0; i < n && !rc; ++i) {
             rc = prepare_backward(sims[i], dL_dxT_dev ? dL_dxT_dev[i] : nullptr, nullptr, nullptr);
             sims[i]->hd.step_begin = 0;
@@ -1201,7 +1304,6 @@ int sim_batch_backward(sim_t *const *sims, int32_t n, const double *const *dL_dx
             if (sims[i]->hd.adj_direct) {
                 ensure_af(sims[i], sims[i]->T);
                 sims[i]->hd.af_step0 = 0;
-                nmax = std::max(nmax, sims[i]->hd.af_nmax);
                 for (int k = 0; k < sims[i]->T; ++k) { work.push_back(i); work.push_back(k); }
             }
             descs[i] = sims[i]->hd;
@@ -1209,9 +1311,8 @@ int sim_batch_backward(sim_t *const *sims, int32_t n, const double *const *dL_dx
         }
         if (rc) return rc;
         SimDev *d = (SimDev *)dev_alloc(s0, n * sizeof(SimDev));
-        int32_t *dwork = work.empty() ? nullptr : upload(s0, work);
         rc = hip_err(hipMemcpyAsync(d, descs.data(), n * sizeof(SimDev), hipMemcpyHostToDevice, s0->stream));
-        if (!rc && dwork) rc = hip_err(launch_adj_factor(d, dwork, (int)work.size() / 2, nmax, s0->stream));
+        if (!rc && !work.empty()) rc = factor_pairs(s0, d, std::vector<sim *>(sims, sims + n), work);
         int fl = 0;
         const size_t lb = batch_lds(sims, n, false, fl);
         if (!rc) rc = hip_err(launch_backward(d, n, s0->hd.mixed != 0, lb, fl, s0->stream));
@@ -1226,7 +1327,6 @@ int sim_batch_backward(sim_t *const *sims, int32_t n, const double *const *dL_dx
         }
         (void)hipStreamSynchronize(s0->stream);
         dev_release(s0, d);
-        dev_release(s0, dwork);
         return rc ? rc : warn;
     });
 }

@@ -748,7 +748,8 @@ __device__ __forceinline__ int gmres_solve(const SimDev &S, auto mode, auto gbar
 // inside the block), B_s = A(R_s, s) and V_s = D_s^{-1} A(s, R_s); the Schur
 // update of descendant d onto the blocks it reaches is B_d V_d.
 
-constexpr int kLuPanel = 8192;        // doubles of LDS for one column panel of A(s, R_s)
+constexpr int kFacBlock = 256;        // threads per factorisation workgroup
+constexpr int kLuPanel = 2048;        // doubles of LDS for one row panel of A(s, R_s)^T
 
 __device__ __forceinline__ void contact_T(const SimDev &S, uint8_t md, int o, auto xi, auto ub, double *T) {
     // T = d v / d ubar of the contact update, row-major (identity off contact)
@@ -768,10 +769,18 @@ __device__ __forceinline__ void contact_T(const SimDev &S, uint8_t md, int o, au
             T[3 * r + c] = (1 - sl) * ((r == c ? 1.0 : 0.0) - nrm[r] * nrm[c]) + sl * t[r] * t[c] + mu * t[r] * nrm[c];
 }
 
-// One workgroup factors one step: work[2b] = handle, work[2b+1] = factor slot
-// (NULL: handle 0, slot = block index).  Slot k holds step af_step0 + k.
-__global__ __launch_bounds__(kBlockAdj) void k_adj_factor(const SimDev *__restrict__ sims,
-                                                          const int32_t *__restrict__ work) {
+// Workspace of a factor slot: T blocks (9 m), projection scale + direction
+// (4 nca), |A|_inf (1), perturbed pivots per supernode (ns int32).
+__device__ __forceinline__ auto slot_ws(const SimDev &S, int slot) {
+    return G(S.af_ws) + (int64_t)slot * S.af_ws_size;
+}
+__device__ __forceinline__ int64_t ws_anorm(const SimDev &S) { return 9 * (int64_t)S.m + 4 * (int64_t)max(S.nca, 1); }
+
+// Assembly of one step's A into its factor slot, one workgroup per (handle,
+// slot) pair of work (NULL: handle 0, slot = block index); slot k holds step
+// af_step0 + k.  The blocks are stored transposed (see capi: ks_dst).
+__global__ __launch_bounds__(kFacBlock) void k_adj_assemble(const SimDev *__restrict__ sims,
+                                                            const int32_t *__restrict__ work) {
     const int hidx = work ? work[2 * blockIdx.x] : 0;
     const int slot = work ? work[2 * blockIdx.x + 1] : (int)blockIdx.x;
     const SimDev &S = sims[hidx];
@@ -785,21 +794,13 @@ __global__ __launch_bounds__(kBlockAdj) void k_adj_factor(const SimDev *__restri
     const auto obst = G(S.rec_obst) + (int64_t)rs * m;
     const auto ubr = G(S.rec_ubar) + (int64_t)rs * 3 * m;
     const auto F = G(S.af) + (int64_t)slot * S.af_size;
-    const auto ws = G(S.af_ws) + (int64_t)slot * S.af_ws_size;
+    const auto ws = slot_ws(S, slot);
     const auto Tb = ws;
     const auto Gc = ws + 9 * (int64_t)m;
-    const auto npert = Gc + 4 * (int64_t)max(S.nca, 1);     // [0] perturbed pivots, [1] |A|_inf
-    const auto rowpos = (GLOBAL int32_t *)(npert + 2);
-    extern __shared__ double lds[];
-    double *fcol = lds;
-    double *panel = lds + S.af_nmax;
-    int *ipiv = (int *)(panel + kLuPanel);
-    __shared__ int piv_sh;
-    __shared__ double red[kBlockAdj / 64];
+    __shared__ double red[kFacBlock / 64];
 
     for (int64_t e = tid; e < S.af_size; e += bd) F[e] = 0.0;
-    // projection Jacobian scale and direction at x_{n+1}
-    for (int c = tid; c < S.nca; c += bd) {
+    for (int c = tid; c < S.nca; c += bd) {           // projection Jacobians at x_{n+1}
         double q0 = 0, q1 = 0, q2 = 0;
         for (int p = G(S.c_ptr)[c]; p < G(S.c_ptr)[c + 1]; ++p) {
             const int j = G(S.c_node)[p];
@@ -821,7 +822,7 @@ __global__ __launch_bounds__(kBlockAdj) void k_adj_factor(const SimDev *__restri
         for (int e = 0; e < 9; ++e) Tb[9 * (int64_t)i + e] = T[e];
     }
     __syncthreads();
-    // assembly: the thread of row i owns every block (i, j)
+    // the thread of row i owns every block (i, j)
     double anorm = 0.0;
     for (int i = tid; i < m; i += bd) {
         double rsum[3] = {0.0, 0.0, 0.0};
@@ -879,145 +880,302 @@ __global__ __launch_bounds__(kBlockAdj) void k_adj_factor(const SimDev *__restri
         anorm = fmax(anorm, fmax(rsum[0], fmax(rsum[1], rsum[2])));
     }
     anorm = block_max(anorm, red);
-    if (tid == 0) npert[1] = anorm;
-    __syncthreads();
+    if (tid == 0) ws[ws_anorm(S)] = anorm;
+}
+
+// Gauss-Jordan inverse in place of the N x N row-major block D in HBM, row
+// pivoting inside the block (pivots below 1e-13 of the block's largest entry
+// are raised to that floor); returns the number of raised pivots.  For blocks
+// too large for registers.
+__device__ __noinline__ int gj_inverse_global(GLOBAL double *D, int N, double *fcol, int *ipiv, double *red) {
+    const int tid = threadIdx.x, bd = blockDim.x;
+    __shared__ int piv_sh;
+    double dm = 0.0;
+    for (int e = tid; e < N * N; e += bd) dm = fmax(dm, fabs(D[e]));
+    const double floor_ = 1e-13 * block_max(dm, red);
     int pert = 0;
-    for (int sn = 0; sn < S.ns; ++sn) {
-        const auto &q = G(S.lu_sup)[sn];
-        const int N = 3 * q.n, R = 3 * q.r;
-        const auto D = F + q.off;
-        const auto Bp = D + (int64_t)N * N;
-        const auto C = Bp + (int64_t)R * N;
-        for (int t = tid; t < q.n; t += bd) rowpos[q.c0 + t] = t;
-        for (int t = tid; t < q.r; t += bd) rowpos[G(S.sup_rows)[q.rptr + t]] = q.n + t;
-        __syncthreads();
-        // Schur updates B_d V_d of the descendants reaching s (blocks stored
-        // transposed: Bt_d[k][a] = B_d[a][k], Vt_d[b][k] = V_d[k][b]); threads run
-        // along a, so loads and stores are contiguous
-        for (int u = G(S.lu_upd_ptr)[sn]; u < G(S.lu_upd_ptr)[sn + 1]; ++u) {
-            const auto &ud = G(S.lu_upd)[u];
-            const auto &qd = G(S.lu_sup)[ud.d];
-            const int Nd = 3 * qd.n, Rd = 3 * qd.r;
-            const auto Bd = F + qd.off + (int64_t)Nd * Nd;
-            const auto Vd = Bd + (int64_t)Rd * Nd;
-            const auto Rrows = G(S.sup_rows) + qd.rptr;
-            const int a0 = 3 * ud.i0, a1 = 3 * ud.i1, wc = a1 - a0;
-            const int nlow = (Rd - a0) * wc, nup = wc * (Rd - a1);
-            for (int idx = tid; idx < nlow + nup; idx += bd) {
-                int a, b;
-                if (idx < nlow) {
-                    b = a0 + idx / (Rd - a0);
-                    a = a0 + idx % (Rd - a0);
-                } else {
-                    const int k = idx - nlow;
-                    b = a1 + k / wc;
-                    a = a0 + k % wc;
-                }
-                const auto vb = Vd + (int64_t)b * Nd;
-                double acc = 0.0;
-#pragma unroll 4
-                for (int k = 0; k < Nd; ++k) acc += Bd[(int64_t)k * Rd + a] * vb[k];
-                const int ra = rowpos[Rrows[a / 3]], rb = rowpos[Rrows[b / 3]];
-                const int ca = a % 3, cb = b % 3;
-                if (idx < nlow) {
-                    if (ra < q.n) D[(int64_t)(3 * rb + cb) * N + 3 * ra + ca] -= acc;
-                    else Bp[(int64_t)(3 * rb + cb) * R + 3 * (ra - q.n) + ca] -= acc;
-                } else {
-                    C[(int64_t)(3 * (rb - q.n) + cb) * N + 3 * ra + ca] -= acc;
-                }
+    for (int k = 0; k < N; ++k) {
+        if (tid < 64) {
+            double best = -1.0;
+            int bi = k;
+            for (int i = k + tid; i < N; i += 64) {
+                const double v = fabs(D[(int64_t)i * N + k]);
+                if (v > best) { best = v; bi = i; }
             }
-            __syncthreads();
-        }
-        // pivot floor: 1e-13 of the largest entry of the diagonal block
-        double dm = 0.0;
-        for (int e = tid; e < N * N; e += bd) dm = fmax(dm, fabs(D[e]));
-        const double floor_ = 1e-13 * block_max(dm, red);
-        // Gauss-Jordan inversion of D in place, row pivoting inside the block
-        for (int k = 0; k < N; ++k) {
-            if (tid < 64) {
-                double best = -1.0;
-                int bi = k;
-                for (int i = k + tid; i < N; i += 64) {
-                    const double v = fabs(D[(int64_t)i * N + k]);
-                    if (v > best) { best = v; bi = i; }
-                }
 #pragma unroll
-                for (int o = 32; o > 0; o >>= 1) {
-                    const double ob = __shfl_xor(best, o, 64);
-                    const int oi = __shfl_xor(bi, o, 64);
-                    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-                }
-                if (tid == 0) { piv_sh = bi; ipiv[k] = bi; }
+            for (int o = 32; o > 0; o >>= 1) {
+                const double ob = __shfl_xor(best, o, 64);
+                const int oi = __shfl_xor(bi, o, 64);
+                if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
             }
-            __syncthreads();
-            const int p = piv_sh;
-            if (p != k)
-                for (int j = tid; j < N; j += bd) {
-                    const double t = D[(int64_t)k * N + j];
-                    D[(int64_t)k * N + j] = D[(int64_t)p * N + j];
-                    D[(int64_t)p * N + j] = t;
-                }
-            __syncthreads();
-            double pv = D[(int64_t)k * N + k];
-            if (!(fabs(pv) >= floor_)) {
-                pv = pv < 0.0 ? -floor_ : floor_;
-                if (!(pv != 0.0)) pv = 1e-300;
-                ++pert;
-            }
-            for (int i = tid; i < N; i += bd) fcol[i] = D[(int64_t)i * N + k];
-            __syncthreads();
-            const double pinv = 1.0 / pv;
-            for (int j = tid; j < N; j += bd) D[(int64_t)k * N + j] = j == k ? pinv : D[(int64_t)k * N + j] * pinv;
-            __syncthreads();
-            for (int idx = tid; idx < N * N; idx += bd) {
-                const int i = idx / N, j = idx - i * N;
-                if (i == k) continue;
-                const double f = fcol[i];
-                if (j == k) D[idx] = -f * pinv;
-                else D[idx] -= f * D[(int64_t)k * N + j];
-            }
-            __syncthreads();
+            if (tid == 0) { piv_sh = bi; ipiv[k] = bi; }
         }
-        for (int k = N - 1; k >= 0; --k) {
-            const int p = ipiv[k];
-            if (p != k)
-                for (int i = tid; i < N; i += bd) {
-                    const double t = D[(int64_t)i * N + k];
-                    D[(int64_t)i * N + k] = D[(int64_t)i * N + p];
-                    D[(int64_t)i * N + p] = t;
-                }
-            __syncthreads();
+        __syncthreads();
+        const int p = piv_sh;
+        if (p != k)
+            for (int j = tid; j < N; j += bd) {
+                const double t = D[(int64_t)k * N + j];
+                D[(int64_t)k * N + j] = D[(int64_t)p * N + j];
+                D[(int64_t)p * N + j] = t;
+            }
+        __syncthreads();
+        double pv = D[(int64_t)k * N + k];
+        if (!(fabs(pv) >= floor_)) {
+            pv = pv < 0.0 ? -floor_ : floor_;
+            if (!(pv != 0.0)) pv = 1e-300;
+            ++pert;
         }
-        // V_s = D_s^{-1} A(s, R_s); transposed: Vt = Ct (D^{-1})^T, i.e. every row
-        // of Ct times the stored inverse, a panel of rows at a time through LDS
-        if (R > 0) {
-            const int rw = max(1, min(R, kLuPanel / N));
-            for (int j0 = 0; j0 < R; j0 += rw) {
-                const int w = min(rw, R - j0);
-                for (int idx = tid; idx < w * N; idx += bd) panel[idx] = C[(int64_t)j0 * N + idx];
-                __syncthreads();
-                for (int idx = tid; idx < w * N; idx += bd) {
-                    const int jj = idx / N, i = idx - jj * N;
-                    const double *cr = panel + jj * N;
-                    double acc = 0.0;
-#pragma unroll 4
-                    for (int k = 0; k < N; ++k) acc += cr[k] * D[(int64_t)k * N + i];
-                    C[(int64_t)(j0 + jj) * N + i] = acc;
-                }
-                __syncthreads();
+        for (int i = tid; i < N; i += bd) fcol[i] = D[(int64_t)i * N + k];
+        __syncthreads();
+        const double pinv = 1.0 / pv;
+        for (int j = tid; j < N; j += bd) D[(int64_t)k * N + j] = j == k ? pinv : D[(int64_t)k * N + j] * pinv;
+        __syncthreads();
+        for (int idx = tid; idx < N * N; idx += bd) {
+            const int i = idx / N, j = idx - i * N;
+            if (i == k) continue;
+            const double f = fcol[i];
+            if (j == k) D[idx] = -f * pinv;
+            else D[idx] -= f * D[(int64_t)k * N + j];
+        }
+        __syncthreads();
+    }
+    for (int k = N - 1; k >= 0; --k) {
+        const int p = ipiv[k];
+        if (p != k)
+            for (int i = tid; i < N; i += bd) {
+                const double t = D[(int64_t)i * N + k];
+                D[(int64_t)i * N + k] = D[(int64_t)i * N + p];
+                D[(int64_t)i * N + p] = t;
+            }
+        __syncthreads();
+    }
+    return pert;
+}
+
+// The same inverse with the block in registers (N <= 16 kGjE, 256 threads):
+// thread (ty, tx) owns entries (ty + 16a, tx + 16b).  Pivot rows are chosen by
+// magnitude among the rows not used yet, without swapping rows; with p_k the
+// pivot row of column k, the array ends as X with inverse[k][p_j] = X[p_k][j],
+// which the write-back applies.  Two barriers per column.
+constexpr int kGjE = 8;
+struct GjShared {
+    double col[2][16 * kGjE];
+    double row[16 * kGjE];
+    int pk[16 * kGjE], inv[16 * kGjE];
+};
+__device__ __noinline__ int gj_inverse_regs(GLOBAL double *D, int N, GjShared *sh, double *red, double *dl) {
+    const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15, lane = tid & 63;
+    double X[kGjE][kGjE];
+    double dm = 0.0;
+#pragma unroll
+    for (int a = 0; a < kGjE; ++a)
+#pragma unroll
+        for (int b = 0; b < kGjE; ++b) {
+            const int i = ty + 16 * a, j = tx + 16 * b;
+            X[a][b] = (i < N && j < N) ? D[(int64_t)i * N + j] : 0.0;
+            dm = fmax(dm, fabs(X[a][b]));
+        }
+    const double floor_ = 1e-13 * block_max(dm, red);
+    bool used0 = false, used1 = false;      // rows lane and lane + 64, tracked by every wave alike
+    int pert = 0;
+    for (int k = 0; k < N; ++k) {
+        double *colk = sh->col[k & 1];
+        const int bk = k >> 4;
+        if (tx == (k & 15)) {
+#pragma unroll
+            for (int a = 0; a < kGjE; ++a) {
+                double v = 0.0;
+#pragma unroll
+                for (int b = 0; b < kGjE; ++b) v = b == bk ? X[a][b] : v;
+                if (ty + 16 * a < N) colk[ty + 16 * a] = v;
+            }
+        }
+        __syncthreads();
+        double best = (lane < N && !used0) ? fabs(colk[lane]) : -1.0;
+        int bi = lane;
+        const double v1 = (lane + 64 < N && !used1) ? fabs(colk[lane + 64]) : -1.0;
+        if (v1 > best) { best = v1; bi = lane + 64; }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ob = __shfl_xor(best, o, 64);
+            const int oi = __shfl_xor(bi, o, 64);
+            if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+        }
+        const int p = bi;
+        if (p == lane) used0 = true;
+        if (p == lane + 64) used1 = true;
+        double piv = colk[p];
+        if (!(fabs(piv) >= floor_)) {
+            piv = piv < 0.0 ? -floor_ : floor_;
+            if (!(piv != 0.0)) piv = 1e-300;
+            ++pert;
+        }
+        if (tid == 0) sh->pk[k] = p;
+        const int ap = p >> 4;
+        if (ty == (p & 15)) {
+#pragma unroll
+            for (int b = 0; b < kGjE; ++b) {
+                double v = 0.0;
+#pragma unroll
+                for (int a = 0; a < kGjE; ++a) v = a == ap ? X[a][b] : v;
+                if (tx + 16 * b < N) sh->row[tx + 16 * b] = v;
+            }
+        }
+        __syncthreads();
+        const double pinv = 1.0 / piv;
+#pragma unroll
+        for (int a = 0; a < kGjE; ++a) {
+            const int i = ty + 16 * a;
+            const double f = i < N ? colk[i] : 0.0;
+#pragma unroll
+            for (int b = 0; b < kGjE; ++b) {
+                const int j = tx + 16 * b;
+                if (i >= N || j >= N) continue;
+                if (i == p) X[a][b] = j == k ? pinv : X[a][b] * pinv;
+                else X[a][b] = j == k ? -f * pinv : X[a][b] - f * sh->row[j] * pinv;
             }
         }
     }
-    if (tid == 0) npert[0] = (double)pert;
+    for (int i = tid; i < N; i += (int)blockDim.x) sh->inv[sh->pk[i]] = i;
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < kGjE; ++a)
+#pragma unroll
+        for (int b = 0; b < kGjE; ++b) {
+            const int i = ty + 16 * a, j = tx + 16 * b;
+            if (i < N && j < N) {
+                const int e = sh->inv[i] * N + sh->pk[j];
+                D[e] = X[a][b];
+                dl[e] = X[a][b];
+            }
+        }
+    __syncthreads();
+    return pert;
 }
 
-// A z = b with a step factor F: forward over the levels (children first)
-//   t_s = b_s - (update entries reaching s), z_s = D_s^{-1} t_s, u_s = B_s z_s;
-// backward (parents first) x_s = z_s - V_s x_{R_s}.  Same level schedule and
-// update-buffer layout as solve_P.  One wavefront per 64-row chunk of a block,
-// one lane per row, a loop over the columns of the column-major block: every
-// factor load is one contiguous 512-byte wavefront load.  x must not alias b,
-// T or Z.
+// Schur update of supernode s by descendant d, as a tiled product: target rows
+// a and columns b of R_d (from 3 i0 on) with a or b in s, value -= sum_k
+// Bt_d[k][a] Vt_d[b][k].  64 x 64 output tiles, k in chunks of 16 staged in
+// LDS (tile: 2 x 16 x 64 doubles), a 4 x 4 block of outputs per thread.
+__device__ __forceinline__ void schur_update(const SimDev &S, GLOBAL double *F, const auto &q, const auto &ud,
+                                             double *tile) {
+    const int tid = threadIdx.x;
+    const auto &qd = G(S.lu_sup)[ud.d];
+    const int Nd = 3 * qd.n, Rd = 3 * qd.r, N = 3 * q.n, R = 3 * q.r, n = q.n;
+    const auto Bd = F + qd.off + (int64_t)Nd * Nd;          // Bt_d: Nd x Rd
+    const auto Vd = Bd + (int64_t)Rd * Nd;                  // Vt_d: Rd x Nd
+    const auto D = F + q.off;
+    const auto Bp = D + (int64_t)N * N;
+    const auto C = Bp + (int64_t)R * N;
+    const auto rel = G(S.lu_relmap) + ud.map;
+    const int a0 = 3 * ud.i0, a1 = 3 * ud.i1;
+    double *ta = tile, *tb = tile + 16 * 64;                // ta[k][a], tb[k][b]
+    const int tx = tid & 15, ty = tid >> 4;                  // outputs a = a_t + 4 tx + i, b = b_t + 4 ty + j
+    for (int at = a0; at < Rd; at += 64)
+        for (int bt = a0; bt < Rd; bt += 64) {
+            if (at >= a1 && bt >= a1) continue;             // rows and columns both beyond s
+            double acc[4][4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+            for (int k0 = 0; k0 < Nd; k0 += 16) {
+                for (int e = tid; e < 16 * 64; e += kFacBlock) {
+                    const int kk = e >> 6, c = e & 63, k = k0 + kk;
+                    ta[e] = (k < Nd && at + c < Rd) ? Bd[(int64_t)k * Rd + at + c] : 0.0;
+                    const int bb = e >> 4, k2 = k0 + (e & 15);
+                    tb[(e & 15) * 64 + bb] = (k2 < Nd && bt + bb < Rd) ? Vd[(int64_t)(bt + bb) * Nd + k2] : 0.0;
+                }
+                __syncthreads();
+#pragma unroll 4
+                for (int kk = 0; kk < 16; ++kk) {
+                    double va[4], vb[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) va[i] = ta[kk * 64 + 4 * tx + i];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) vb[j] = tb[kk * 64 + 4 * ty + j];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) acc[i][j] += va[i] * vb[j];
+                }
+                __syncthreads();
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int aa = at + 4 * tx + i, bb = bt + 4 * ty + j;
+                    if (aa >= Rd || bb >= Rd || (aa >= a1 && bb >= a1)) continue;
+                    const int ra = rel[aa / 3 - ud.i0], rb = rel[bb / 3 - ud.i0];
+                    const int ca = aa % 3, cb = bb % 3;
+                    if (bb < a1) {                          // column in s
+                        if (ra < n) D[(int64_t)(3 * rb + cb) * N + 3 * ra + ca] -= acc[i][j];
+                        else Bp[(int64_t)(3 * rb + cb) * R + 3 * (ra - n) + ca] -= acc[i][j];
+                    } else {                                // row in s, column in R_s
+                        C[(int64_t)(3 * (rb - n) + cb) * N + 3 * ra + ca] -= acc[i][j];
+                    }
+                }
+        }
+}
+
+// One workgroup per (handle, slot, supernode) of one elimination level: the
+// Schur updates of the descendants reaching s (finished by earlier launches),
+// the Gauss-Jordan inverse of the diagonal block, then V_s.  Blocks are stored
+// transposed: Dt = D^T, Bt = B^T (N x R), Ct = A(s, R_s)^T (R x N), row-major.
+// Dynamic LDS: a region of kLdsFacA doubles (update tiles; then the inverse for
+// N <= 128, or the pivot column and rows of the HBM variant) and the V panel.
+constexpr int kLdsFacA = 16 * kGjE * 16 * kGjE;
+__global__ __launch_bounds__(kFacBlock) void k_adj_factor_level(const SimDev *__restrict__ sims,
+                                                                const int32_t *__restrict__ work) {
+    const int hidx = work[3 * blockIdx.x], slot = work[3 * blockIdx.x + 1], sn = work[3 * blockIdx.x + 2];
+    const SimDev &S = sims[hidx];
+    const int tid = threadIdx.x, bd = blockDim.x;
+    const auto F = G(S.af) + (int64_t)slot * S.af_size;
+    const auto ws = slot_ws(S, slot);
+    extern __shared__ double lds[];
+    double *regA = lds;
+    double *panel = lds + kLdsFacA;
+    __shared__ GjShared small;
+    __shared__ double red[kFacBlock / 64];
+    const auto &q = G(S.lu_sup)[sn];
+    const int N = 3 * q.n, R = 3 * q.r;
+    const auto D = F + q.off;
+    const auto C = D + (int64_t)N * N + (int64_t)R * N;
+    for (int u = G(S.lu_upd_ptr)[sn]; u < G(S.lu_upd_ptr)[sn + 1]; ++u) {
+        schur_update(S, F, q, G(S.lu_upd)[u], regA);
+        __syncthreads();
+    }
+    const bool small_block = N <= 16 * kGjE;
+    const int pert = small_block ? gj_inverse_regs(D, N, &small, red, regA)
+                                 : gj_inverse_global(D, N, regA, (int *)(regA + N), red);
+    // V_s = D_s^{-1} A(s, R_s); transposed Vt = Ct (D^{-1})^T, a panel of rows of
+    // Ct at a time through LDS
+    if (R > 0) {
+        const int rw = max(1, min(R, kLuPanel / N));
+        for (int j0 = 0; j0 < R; j0 += rw) {
+            const int w = min(rw, R - j0);
+            for (int idx = tid; idx < w * N; idx += bd) panel[idx] = C[(int64_t)j0 * N + idx];
+            __syncthreads();
+            for (int idx = tid; idx < w * N; idx += bd) {
+                const int jj = idx / N, i = idx - jj * N;
+                const double *cr = panel + jj * N;
+                double acc = 0.0;
+                if (small_block) {
+#pragma unroll 8
+                    for (int k = 0; k < N; ++k) acc += cr[k] * regA[k * N + i];
+                } else {
+#pragma unroll 4
+                    for (int k = 0; k < N; ++k) acc += cr[k] * D[(int64_t)k * N + i];
+                }
+                C[(int64_t)(j0 + jj) * N + i] = acc;
+            }
+            __syncthreads();
+        }
+    }
+    if (tid == 0) ((GLOBAL int32_t *)(ws + ws_anorm(S) + 1))[sn] = pert;
+}
+
 // sum over k < n of col[k ld] v[k] in order; sixteen independent loads are
 // issued before their products (the step factors stream from HBM)
 __device__ __forceinline__ double col_dot(auto col, int64_t ld, auto v, int n) {
@@ -1038,25 +1196,25 @@ __device__ __forceinline__ void solve_A(const SimDev &S, auto F, auto b, auto T,
     const int tid = threadIdx.x, bd = blockDim.x;
     const int wave = tid >> 6, lane = tid & 63, nw = bd >> 6;
     const auto lvl = G(S.lu_lvl);
-    for (int l = 0; l < S.n_levels; ++l) {
-        for (int it = G(S.lvl_rows_ptr)[l] + tid; it < G(S.lvl_rows_ptr)[l + 1]; it += bd) {
-            const auto &ri = G(S.rows)[it];
+    for (int l = 0; l < S.lu_nlevels; ++l) {
+        for (int it = lvl[4 * l + 3] + tid; it < lvl[4 * (l + 1) + 3]; it += bd) {
+            const auto &ri = G(S.lu_rows)[it];
             double t0 = b[ri.i3], t1 = b[ri.i3 + 1], t2 = b[ri.i3 + 2];
             for (int p = ri.p0; p < ri.p1; ++p) {
-                const int o = G(S.upd_off)[p];
+                const int o = G(S.lu_upd_off)[p];
                 t0 -= U[o]; t1 -= U[o + 1]; t2 -= U[o + 2];
             }
             T[ri.i3] = t0; T[ri.i3 + 1] = t1; T[ri.i3 + 2] = t2;
         }
         __syncthreads();
-        for (int it = lvl[3 * l] + wave; it < lvl[3 * (l + 1)]; it += nw) {
+        for (int it = lvl[4 * l] + wave; it < lvl[4 * (l + 1)]; it += nw) {
             const auto &li = G(S.lu_zitems)[it];
             const auto &q = G(S.lu_sup)[li.s];
             const int N = 3 * q.n, t0 = 3 * q.c0, r = li.a + lane;
             if (r < N) Z[t0 + r] = col_dot(F + q.off + r, N, T + t0, N);
         }
         __syncthreads();
-        for (int it = lvl[3 * l + 1] + wave; it < lvl[3 * (l + 1) + 1]; it += nw) {
+        for (int it = lvl[4 * l + 1] + wave; it < lvl[4 * (l + 1) + 1]; it += nw) {
             const auto &li = G(S.lu_uitems)[it];
             const auto &q = G(S.lu_sup)[li.s];
             const int N = 3 * q.n, R = 3 * q.r, t0 = 3 * q.c0, r = li.a + lane;
@@ -1064,16 +1222,16 @@ __device__ __forceinline__ void solve_A(const SimDev &S, auto F, auto b, auto T,
         }
         __syncthreads();
     }
-    for (int l = S.n_levels - 1; l >= 0; --l) {
-        // x_{R_s} of every supernode of the level, gathered into the (now free)
-        // update buffer in the layout of u_s
-        for (int it = lvl[3 * l + 2] + wave; it < lvl[3 * (l + 1) + 2]; it += nw) {
+    for (int l = S.lu_nlevels - 1; l >= 0; --l) {
+        // x_{R_t} of every chunk of the level, gathered into the (now free)
+        // update buffer in the layout of u_t
+        for (int it = lvl[4 * l + 2] + wave; it < lvl[4 * (l + 1) + 2]; it += nw) {
             const auto &q = G(S.lu_sup)[G(S.lu_sn)[it]];
-            const auto rr = G(S.sup_rows) + q.rptr;
+            const auto rr = G(S.lu_srows) + q.rptr;
             for (int k = lane; k < 3 * q.r; k += 64) U[q.uoff + k] = x[3 * rr[k / 3] + k % 3];
         }
         __syncthreads();
-        for (int it = lvl[3 * l] + wave; it < lvl[3 * (l + 1)]; it += nw) {
+        for (int it = lvl[4 * l] + wave; it < lvl[4 * (l + 1)]; it += nw) {
             const auto &li = G(S.lu_zitems)[it];
             const auto &q = G(S.lu_sup)[li.s];
             const int N = 3 * q.n, R = 3 * q.r, t0 = 3 * q.c0, r = li.a + lane;
@@ -1159,9 +1317,8 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
             // normwise backward error |gbar - A zeta| / (|A| |zeta| + |gbar|) (max
             // norms) is at most adj_tol
             const auto F = G(S.af) + (int64_t)(n - S.af_step0) * S.af_size;
-            const auto wsn = G(S.af_ws) + (int64_t)(n - S.af_step0) * S.af_ws_size + 9 * (int64_t)m +
-                             4 * (int64_t)max(S.nca, 1);
-            const double anorm = wsn[1];
+            const auto wsn = slot_ws(S, n - S.af_step0) + ws_anorm(S);
+            const double anorm = wsn[0];
             solve_A(S, F, gbar, T, Y, zeta, U);
             double gmax = 0.0;
             for (int i = threadIdx.x; i < 3 * m; i += (int)blockDim.x) gmax = fmax(gmax, fabs(gbar[i]));
@@ -1187,7 +1344,10 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
             }
             iters_total += k;
             if (!ok) ++noconv;
-            if (threadIdx.x == 0) pert_total += (int64_t)wsn[0];
+            if (threadIdx.x == 0) {
+                const auto pc = (GLOBAL const int32_t *)(wsn + 1);
+                for (int q = 0; q < S.ns; ++q) pert_total += pc[q];
+            }
         } else {
         // fixed point zeta <- P^{-1}[gbar + dP z + (P - M)(zeta - z)], z = T^T zeta
         int k = 0;
@@ -1444,15 +1604,22 @@ hipError_t kernel_static_lds(size_t *fwd, size_t *bwd) {
     return hipSuccess;
 }
 
-// Dynamic LDS of the step factorisation: pivot column, V panel, pivot rows.
-size_t adj_factor_lds(int nmax) { return (size_t)(nmax + kLuPanel) * sizeof(double) + (size_t)nmax * sizeof(int); }
+// Dynamic LDS of a supernode factorisation: update tiles / inverse region and the V panel.
+size_t adj_factor_lds(int nmax) { return (size_t)(kLdsFacA + kLuPanel) * sizeof(double); }
 
-hipError_t launch_adj_factor(const SimDev *d_sims, const int32_t *work, int nblocks, int nmax, hipStream_t st) {
+hipError_t launch_adj_assemble(const SimDev *d_sims, const int32_t *work, int nblocks, hipStream_t st) {
+    if (nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_adj_assemble, dim3(nblocks), dim3(kFacBlock), 0, st, d_sims, work);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_factor_level(const SimDev *d_sims, const int32_t *work, int nblocks, int nmax, hipStream_t st) {
     if (nblocks <= 0) return hipSuccess;
     const size_t lds = adj_factor_lds(nmax);
-    hipError_t e = hipFuncSetAttribute((const void *)k_adj_factor, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipFuncSetAttribute((const void *)k_adj_factor_level, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_adj_factor, dim3(nblocks), dim3(kBlockAdj), lds, st, d_sims, work);
+    hipLaunchKernelGGL(k_adj_factor_level, dim3(nblocks), dim3(kFacBlock), lds, st, d_sims, work);
     return hipGetLastError();
 }
 

@@ -46,7 +46,8 @@ struct LuItem {             // direct adjoint solve: rows [a, a + 64) of a block
     int32_t s, a;
 };
 struct LuUpd {              // supernode s is updated by descendant d: rows [i0, i1) of R_d lie in s
-    int32_t d, i0, i1, pad;
+    int32_t d, i0, i1;
+    int32_t map;            // offset in lu_relmap of the panel rows (in s) of R_d[i0..r_d)
 };
 struct LuSup {              // supernode data of the direct adjoint factor
     int32_t c0, n, r;       // first node, nodes, rows of R_s
@@ -149,15 +150,20 @@ struct SimDev {
     // N = 3 n_s, R = 3 r_s, column-major blocks D_s^{-1} (N x N), B_s = A(R_s, s)
     // after the Schur updates (R x N) and V_s = D_s^{-1} A(s, R_s) (N x R)
     int adj_direct;                   // 1: adjoint steps solved with their factors
-    int ns;                           // supernodes
+    int ns;                           // supernodes of the factor (P's, cut into chunks)
+    int lu_nlevels;                   // levels of their elimination tree
     const LuSup *lu_sup;              // [ns]
+    const int32_t *lu_srows;          // R_t of every chunk (concatenated)
+    const RowItem *lu_rows;           // forward gathers by level (update-buffer entries per node)
+    const int32_t *lu_upd_off;        // their update-buffer offsets
     const int32_t *lu_upd_ptr;        // [ns+1] updaters of each supernode
     const LuUpd *lu_upd;
+    const int32_t *lu_relmap;         // panel row in s of each row of R_d from i0 on (< n_s: in s)
     const int64_t *ks_dst;            // [nnz K_s] offset of block (i, j) in a step factor
     const int32_t *ks_ld;             // [nnz K_s] row stride there
     const int32_t *dp_ptr;            // [n_inc+1] per incidence entry (node i, constraint c):
     const int32_t *dp_ks;             //   K_s entry of (i, l) for each stencil node l of c
-    const int32_t *lu_lvl;            // [3*(n_levels+1)]: per level start of z items, u items, supernodes
+    const int32_t *lu_lvl;            // [4*(levels+1)]: per level start of z items, u items, chunks, gathers
     const LuItem *lu_zitems;          // row chunks of D_s^{-1} / V_s, grouped by level
     const LuItem *lu_uitems;          // row chunks of B_s, grouped by level
     const int32_t *lu_sn;             // supernodes grouped by level
