@@ -251,6 +251,32 @@ int sim_batch_forward(sim_t *const *sims, int32_t n, const int32_t *n_steps,
 int sim_batch_backward(sim_t *const *sims, int32_t n, const double *const *dL_dxT_dev,
                        const sim_grads_t *out);
 
+/* Continuous batching.  A job on a handle is a forward rollout followed by its
+ * backward pass, run in chunks of steps so that handles can join and leave a
+ * running batch between launches (the results are bitwise those of
+ * sim_forward / sim_backward on the same handle).  Handles used this way keep
+ * every step's record (checkpoint_every must be 0).
+ *   sim_job_forward   arms a forward pass of n_steps from the initial state;
+ *   sim_job_backward  arms the backward pass of the finished forward pass
+ *                     (dL/dx_T, optional dL/dv_T; device arrays, caller order);
+ *   sim_batch_advance advances every listed handle's armed phase by up to
+ *                     steps[i] steps: one launch for all forward chunks on the
+ *                     first handle's stream and, for the backward chunks, the
+ *                     step factorisations (direct adjoint) and one launch on
+ *                     backward_stream (NULL: the same stream); all handles must
+ *                     share the first handle's stream and precision.  It
+ *                     returns when both streams are done; left[i] (host, may be
+ *                     NULL) receives the steps still to run in the phase (0:
+ *                     phase finished; x_T then via sim_state, gradients via
+ *                     sim_job_grads).  Handles without an armed phase are an
+ *                     error (SIM_ESTATE);
+ *   sim_job_grads     writes the gradients of a finished backward pass, with
+ *                     the return convention of sim_backward. */
+int sim_job_forward(sim_t *sim, int32_t n_steps);
+int sim_job_backward(sim_t *sim, const double *dL_dxT_dev, const double *dL_dvT_dev);
+int sim_batch_advance(sim_t *const *sims, int32_t n, const int32_t *steps, void *backward_stream, int32_t *left);
+int sim_job_grads(sim_t *sim, const sim_grads_t *out);
+
 /* Host-only analysis (no GPU needed): builds the constraint set, the PD
  * matrix, the ordering and the Cholesky factor exactly as sim_create does and
  * reports their sizes.  perm_out [n_nodes] (may be NULL) receives the

@@ -88,6 +88,10 @@ def lib():
             "sim_batch_forward": (c_int32, [POINTER(c_void_p), c_int32, c_int32_p, POINTER(c_void_p),
                                             POINTER(c_void_p)]),
             "sim_batch_backward": (c_int32, [POINTER(c_void_p), c_int32, POINTER(c_void_p), POINTER(SimGrads)]),
+            "sim_job_forward": (c_int32, [c_void_p, c_int32]),
+            "sim_job_backward": (c_int32, [c_void_p, c_void_p, c_void_p]),
+            "sim_batch_advance": (c_int32, [POINTER(c_void_p), c_int32, c_int32_p, c_void_p, c_int32_p]),
+            "sim_job_grads": (c_int32, [c_void_p, POINTER(SimGrads)]),
             "sim_analyze": (c_int32, [POINTER(SimMesh), POINTER(SimParams), c_int32, POINTER(SimStats), c_int32_p,
                                       c_double_p, c_int32]),
             "sim_destroy": (None, [c_void_p]),

@@ -56,6 +56,9 @@ struct sim {
     const int32_t *d_bend_centers = nullptr;
     uint8_t *d_modes_tmp = nullptr;
     int T = -1;                         // steps of the recorded rollout (-1: none)
+    int phase = 0;                      // continuous batching: 0 idle, 1 forward armed, 2 forward done,
+                                        // 3 backward armed, 4 backward done
+    int cursor = 0, target = 0;         // next step (forward) / steps still to go back (backward)
     int64_t counters_host[8] = {0};
     int nca = 0;
     int af_cap = 0;                     // step factors allocated (direct adjoint)
@@ -817,6 +820,7 @@ int sim_set_state(sim_t *s, const double *x0_dev, const double *v0_dev) {
     else rc = hip_err(launch_fill(s->start_v, 0.0, 3 * (int64_t)m, s->stream));
     if (rc) return rc;
     s->T = -1;
+    s->phase = 0;
     return SIM_OK;
 }
 
@@ -896,6 +900,7 @@ int sim_set_material(sim_t *s, const double *edge_stiffness, const double *bend_
         if (rc) return rc;
         s->hm = std::move(nm);
         s->T = -1;
+        s->phase = 0;
         return SIM_OK;
     });
 }
@@ -954,7 +959,10 @@ int finish_forward(sim *s, int n_steps, double *xT_dev, double *vT_dev) {
     if (xT_dev) rc = hip_err(launch_permute3(s->hd.x, xT_dev, s->d_perm, m, true, s->stream));
     if (!rc && vT_dev) rc = hip_err(launch_permute3(s->hd.v, vT_dev, s->d_perm, m, true, s->stream));
     if (!rc) rc = read_counters(s);
-    if (!rc) s->T = n_steps;
+    if (!rc) {
+        s->T = n_steps;
+        s->phase = 2;
+    }
     return rc;
 }
 
@@ -1328,6 +1336,130 @@ int sim_batch_backward(sim_t *const *sims, int32_t n, const double *const *dL_dx
         (void)hipStreamSynchronize(s0->stream);
         dev_release(s0, d);
         return rc ? rc : warn;
+    });
+}
+
+
+int sim_job_forward(sim_t *s, int32_t n_steps) {
+    if (!s || n_steps < 1) return SIM_EINVAL;
+    if (seg_len(s) > 0) return SIM_EINVAL;
+    return guarded([&] {
+        int rc = prepare_forward(s, n_steps);
+        if (rc) return rc;
+        s->T = -1;
+        s->phase = 1;
+        s->cursor = 0;
+        s->target = n_steps;
+        return SIM_OK;
+    });
+}
+
+int sim_job_backward(sim_t *s, const double *dL_dxT_dev, const double *dL_dvT_dev) {
+    if (!s) return SIM_EINVAL;
+    if (s->phase != 2 || s->T < 1) return SIM_ESTATE;
+    return guarded([&] {
+        int rc = prepare_backward(s, dL_dxT_dev, dL_dvT_dev, nullptr);
+        if (rc) return rc;
+        s->phase = 3;
+        s->cursor = s->T;
+        return SIM_OK;
+    });
+}
+
+int sim_batch_advance(sim_t *const *sims, int32_t n, const int32_t *steps, void *backward_stream, int32_t *left) {
+    if (!sims || n < 1 || !steps) return SIM_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        if (!sims[i] || steps[i] < 1) return SIM_EINVAL;
+        if (sims[i]->stream != sims[0]->stream || sims[i]->hd.mixed != sims[0]->hd.mixed) return SIM_EINVAL;
+        if (sims[i]->phase != 1 && sims[i]->phase != 3) return SIM_ESTATE;
+    }
+    hipStream_t sf = sims[0]->stream, sb = backward_stream ? (hipStream_t)backward_stream : sf;
+    return guarded([&] {
+        std::vector<sim *> fw, bw;
+        std::vector<SimDev> df, db;
+        std::vector<int32_t> pairs;
+        int rc = SIM_OK;
+        for (int i = 0; i < n; ++i) {
+            sim *h = sims[i];
+            if (h->phase == 1) {
+                h->hd.step_begin = h->cursor;
+                h->hd.step_end = std::min(h->target, h->cursor + steps[i]);
+                h->hd.rec_step0 = 0;
+                fw.push_back(h);
+                df.push_back(h->hd);
+            } else {
+                const int lo = std::max(0, h->cursor - steps[i]);
+                h->hd.step_begin = lo;
+                h->hd.step_end = h->cursor;
+                h->hd.rec_step0 = 0;
+                if (h->hd.adj_direct) {
+                    ensure_af(h, h->cursor - lo);
+                    h->hd.af_step0 = lo;
+                    for (int k = 0; k < h->cursor - lo; ++k) {
+                        pairs.push_back((int32_t)bw.size());
+                        pairs.push_back(k);
+                    }
+                }
+                bw.push_back(h);
+                db.push_back(h->hd);
+            }
+        }
+        SimDev *dfd = fw.empty() ? nullptr : (SimDev *)dev_alloc(sims[0], fw.size() * sizeof(SimDev));
+        SimDev *dbd = bw.empty() ? nullptr : (SimDev *)dev_alloc(sims[0], bw.size() * sizeof(SimDev));
+        if (dfd) rc = hip_err(hipMemcpyAsync(dfd, df.data(), df.size() * sizeof(SimDev), hipMemcpyHostToDevice, sf));
+        if (!rc && dbd) rc = hip_err(hipMemcpyAsync(dbd, db.data(), db.size() * sizeof(SimDev), hipMemcpyHostToDevice, sf));
+        if (!rc) rc = hip_err(hipStreamSynchronize(sf));          // descriptors in place before either stream uses them
+        if (!rc && dfd) {
+            int fl = 0;
+            const size_t lb = batch_lds(fw.data(), (int)fw.size(), true, fl);
+            rc = hip_err(launch_forward(dfd, (int)fw.size(), fw[0]->hd.mixed != 0, lb, fl, sf));
+        }
+        if (!rc && dbd) {
+            if (!pairs.empty()) {
+                hipStream_t keep = bw[0]->stream;
+                bw[0]->stream = sb;                                 // factor work lists ride on the backward stream
+                rc = factor_pairs(bw[0], dbd, bw, pairs);
+                bw[0]->stream = keep;
+            }
+            int fl = 0;
+            const size_t lb = batch_lds(bw.data(), (int)bw.size(), false, fl);
+            if (!rc) rc = hip_err(launch_backward(dbd, (int)bw.size(), bw[0]->hd.mixed != 0, lb, fl, sb));
+        }
+        const int r1 = hip_err(hipStreamSynchronize(sf));
+        const int r2 = hip_err(hipStreamSynchronize(sb));
+        if (!rc) rc = r1 ? r1 : r2;
+        dev_release(sims[0], dfd);
+        dev_release(sims[0], dbd);
+        if (rc) return rc;
+        for (sim *h : fw) {
+            h->cursor = h->hd.step_end;
+            if (h->cursor == h->target) {
+                rc = read_counters(h);
+                if (rc) return rc;
+                h->T = h->target;
+                h->phase = 2;
+            }
+        }
+        for (sim *h : bw) {
+            h->cursor = h->hd.step_begin;
+            if (h->cursor == 0) h->phase = 4;
+        }
+        if (left)
+            for (int i = 0; i < n; ++i)
+                left[i] = sims[i]->phase == 1 ? sims[i]->target - sims[i]->cursor
+                                              : sims[i]->phase == 3 ? sims[i]->cursor : 0;
+        return SIM_OK;
+    });
+}
+
+int sim_job_grads(sim_t *s, const sim_grads_t *out) {
+    if (!s) return SIM_EINVAL;
+    if (s->phase != 4) return SIM_ESTATE;
+    return guarded([&] {
+        int rc = write_grads(s, out);
+        if (!rc) rc = backward_status(s);
+        if (rc >= 0) s->phase = 2;                  // the recorded forward stays valid
+        return rc;
     });
 }
 

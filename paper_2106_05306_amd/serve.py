@@ -1,0 +1,216 @@
+"""Serving forward + gradient rollout requests by continuous batching.
+
+Each request is one cloth rollout on a mesh of its own size: the forward
+simulation, then the adjoint pass back to the initial state (gradients of a
+centroid loss with respect to the initial state, stiffness and friction).
+
+The server
+  * admits a request when the device memory it needs fits the HBM budget
+    (handles in flight plus idle cached handles; idle handles are evicted,
+    least recently used first, to make room);
+  * caches handles per mesh topology: a handle holds the factorised PD matrix
+    of its mesh and material, so a request whose topology is cached skips the
+    setup (ordering, factorisation, device tables);
+  * runs rounds: one ``batch_advance`` call advances every admitted request by
+    a chunk of steps of its current phase (forward chunks in one persistent
+    launch, adjoint chunks in another on a second stream), chunks sized so
+    that a round takes about ``round_ms``; requests that arrive during a round
+    join at the next one, and finished ones leave.
+
+``run_sequential`` serves the same requests one at a time with the same
+kernels (``sim_forward`` + ``sim_backward``), the plain GPU baseline.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Callable, Dict, List, Optional
+
+import torch
+
+from .sim import Sim, batch_advance
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    key: tuple                      # mesh topology: requests with equal keys can share a handle
+    steps: int
+    arrival: float                  # seconds after the start of the run
+    make_scene: Callable[[], object]
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    arrival: float
+    admitted: float
+    finished: float
+    status: int
+    grads: Optional[dict] = None
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+def centroid_seed(scene, xT: torch.Tensor) -> torch.Tensor:
+    """dL/dx_T of L = |centroid(x_T) - target|^2."""
+    target = torch.as_tensor(scene.target, dtype=torch.float64, device=xT.device)
+    d = xT.mean(dim=0) - target
+    return (2.0 / xT.shape[0]) * d.expand_as(xT).contiguous()
+
+
+def step_cost_ms(m: int, backward: bool) -> float:
+    """Rough time of one step (forward: K = 20 PD iterations) for m nodes; only
+    used to size the chunks of a round."""
+    return 0.2 + 0.35 * m / 1000.0 if backward else 20 * (0.06 + 0.04 * m / 1000.0)
+
+
+class _Handle:
+    def __init__(self, sim: Sim, key):
+        self.sim = sim
+        self.key = key
+        self.last_used = 0.0
+        self.base_bytes = sim.stats()["device_bytes"]
+
+    def need_bytes(self, steps: int, window: int) -> int:
+        st = self.sim.stats()
+        m = st["n_nodes"]
+        records = (steps + 1) * m * 48 + steps * m * 26
+        factors = window * (st["adj_factor_bytes"] + 8 * (9 * m + 4 * st["n_constraints_active"] + 64))
+        return self.base_bytes + records + factors
+
+
+class Server:
+    def __init__(self, device="cuda:0", hbm_budget_bytes: int = 64 << 30, round_ms: float = 40.0,
+                 max_chunk: int = 64, keep_grads: bool = False, **sim_kw):
+        self.device = torch.device(device)
+        self.budget = int(hbm_budget_bytes)
+        self.round_ms = round_ms
+        self.max_chunk = max_chunk
+        self.keep_grads = keep_grads
+        self.sim_kw = dict(sim_kw)
+        self.pool: Dict[tuple, List[_Handle]] = collections.defaultdict(list)
+        self.bstream = torch.cuda.Stream(device=self.device)
+        self.stats = collections.Counter()
+
+    # ------------------------------------------------------------------ handles
+    def _idle(self):
+        return [h for hs in self.pool.values() for h in hs]
+
+    def _used_bytes(self, busy):
+        return sum(h.sim.stats()["device_bytes"] for h in self._idle()) + sum(b for _, b in busy)
+
+    def _evict(self, need, busy) -> bool:
+        idle = sorted(self._idle(), key=lambda h: h.last_used)
+        while self._used_bytes(busy) + need > self.budget and idle:
+            h = idle.pop(0)
+            self.pool[h.key].remove(h)
+            h.sim.close()
+            self.stats["evicted"] += 1
+        return self._used_bytes(busy) + need <= self.budget
+
+    def _acquire(self, req: Request, scene):
+        if self.pool[req.key]:
+            self.stats["cache_hits"] += 1
+            return self.pool[req.key].pop()
+        self.stats["cache_misses"] += 1
+        return _Handle(Sim.from_scene(scene, device=self.device, **self.sim_kw), req.key)
+
+    # ------------------------------------------------------------------ serving
+    def run(self, requests: List[Request]) -> List[Result]:
+        queue = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        active = []                  # [req, scene, handle, phase, bytes, admitted]
+        results = []
+        t0 = time.perf_counter()
+        clock = lambda: time.perf_counter() - t0
+        while queue or active:
+            now = clock()
+            # admission, first come first served
+            while queue and queue[0].arrival <= now:
+                req = queue[0]
+                scene = req.make_scene()
+                h = self._acquire(req, scene)
+                window = min(self.max_chunk, req.steps)
+                need = h.need_bytes(req.steps, window)
+                busy = [(a[2], a[4]) for a in active]
+                if not self._evict(need, busy) and active:
+                    self.pool[req.key].append(h)          # wait for memory to free up
+                    break
+                queue.popleft()
+                if scene is not None and getattr(scene, "v0", None) is not None and (scene.v0 != 0).any():
+                    h.sim.set_state(None, torch.as_tensor(scene.v0, dtype=torch.float64))
+                else:
+                    h.sim.set_state(None, None)
+                h.sim.job_forward(req.steps)
+                active.append([req, scene, h, "fwd", need, clock()])
+            if not active:
+                time.sleep(max(0.0, min(queue[0].arrival - clock(), 0.05)))
+                continue
+            steps = []
+            for req, scene, h, phase, _, _ in active:
+                m = h.sim.m
+                k = int(self.round_ms / step_cost_ms(m, phase == "bwd"))
+                steps.append(max(1, min(k, self.max_chunk)))
+            left = batch_advance([a[2].sim for a in active], steps, self.bstream)
+            self.stats["rounds"] += 1
+            keep = []
+            for a, rem in zip(active, left):
+                req, scene, h, phase, need, adm = a
+                if rem > 0:
+                    keep.append(a)
+                elif phase == "fwd":
+                    xT, _ = h.sim.state(req.steps)
+                    h.sim.job_backward(centroid_seed(scene, xT))
+                    a[3] = "bwd"
+                    keep.append(a)
+                else:
+                    g = h.sim.job_grads()
+                    h.last_used = clock()
+                    results.append(Result(req.rid, req.arrival, adm, clock(), int(g["status"]),
+                                          g if self.keep_grads else None))
+                    self.pool[req.key].append(h)
+            active = keep
+        return results
+
+    def run_sequential(self, requests: List[Request]) -> List[Result]:
+        """The same requests one at a time (same kernels, same handle cache)."""
+        results = []
+        t0 = time.perf_counter()
+        clock = lambda: time.perf_counter() - t0
+        for req in sorted(requests, key=lambda r: r.arrival):
+            wait = req.arrival - clock()
+            if wait > 0:
+                time.sleep(wait)
+            adm = clock()
+            scene = req.make_scene()
+            h = self._acquire(req, scene)
+            self._evict(h.need_bytes(req.steps, req.steps), [])
+            if scene is not None and getattr(scene, "v0", None) is not None and (scene.v0 != 0).any():
+                h.sim.set_state(None, torch.as_tensor(scene.v0, dtype=torch.float64))
+            else:
+                h.sim.set_state(None, None)
+            xT, _, _ = h.sim.forward(req.steps)
+            g = h.sim.backward(centroid_seed(scene, xT))
+            torch.cuda.synchronize(self.device)
+            h.last_used = clock()
+            results.append(Result(req.rid, req.arrival, adm, clock(), int(g["status"]),
+                                  g if self.keep_grads else None))
+            self.pool[req.key].append(h)
+        return results
+
+    def close(self):
+        for h in self._idle():
+            h.sim.close()
+        self.pool.clear()
+
+
+def latency_summary(results: List[Result]) -> dict:
+    import numpy as np
+    lat = np.array([r.latency for r in results])
+    span = max(r.finished for r in results) - min(r.arrival for r in results)
+    return {"requests": len(results), "rollouts_per_s": len(results) / span, "makespan_s": span,
+            "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+            "mean_s": float(lat.mean())}

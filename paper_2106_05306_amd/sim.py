@@ -248,6 +248,27 @@ class Sim:
         g["status"] = code
         return self._trim(g)
 
+    # ------------------------------------------------------------------ continuous batching
+    def job_forward(self, n_steps: int):
+        """Arm a forward pass of n_steps (run by batch_advance)."""
+        B.check(B.lib().sim_job_forward(self.h, int(n_steps)), "sim_job_forward")
+        self.T = -1
+        self._job_T = int(n_steps)
+        self._gen += 1
+
+    def job_backward(self, dL_dxT: torch.Tensor, dL_dvT: Optional[torch.Tensor] = None):
+        """Arm the backward pass of the finished forward pass."""
+        a = dL_dxT.to(self.device, torch.float64).contiguous()
+        b = None if dL_dvT is None else dL_dvT.to(self.device, torch.float64).contiguous()
+        self._keep["job_seed"] = (a, b)
+        self.T = self._job_T
+        B.check(B.lib().sim_job_backward(self.h, _dptr(a), _dptr(b)), "sim_job_backward")
+
+    def job_grads(self):
+        g, s = self._grads()
+        g["status"] = B.check(B.lib().sim_job_grads(self.h, ctypes.byref(s)), "sim_job_grads")
+        return self._trim(g)
+
     def _trim(self, g):
         g["dw_edge"] = g["dw_edge"][:self.n_edges]
         g["dregion"] = g["dregion"][:self.n_regions]
@@ -310,3 +331,16 @@ def batch_backward(sims: Sequence[Sim], dL_dxT: Sequence[torch.Tensor]):
         g["status"] = code
         out.append(s._trim(g))
     return out
+
+
+def batch_advance(sims: Sequence[Sim], steps: Sequence[int], backward_stream: Optional[torch.cuda.Stream] = None):
+    """Advance every handle's armed phase by up to steps[i] steps (forward chunks
+    in one launch, backward chunks in another on backward_stream); returns the
+    steps left in each handle's phase."""
+    n = len(sims)
+    hs = (ctypes.c_void_p * n)(*[s.h for s in sims])
+    st = (ctypes.c_int32 * n)(*[int(k) for k in steps])
+    left = (ctypes.c_int32 * n)()
+    bs = None if backward_stream is None else ctypes.c_void_p(backward_stream.cuda_stream)
+    B.check(B.lib().sim_batch_advance(hs, n, st, bs, left), "sim_batch_advance")
+    return list(left)
