@@ -108,6 +108,153 @@ def copy_probe(nbytes):
     print(json.dumps({"copy_probe_bytes": nbytes}))
 
 
+def forward_bytes_per_rollout(st, m, E, C_total, K, T):
+    """Algorithmic bytes of one forward rollout (per-unit figures as in algorithmic_bytes)."""
+    per_iter = 2 * st["nnz_L"] * 12 + 4 * 3 * m * 8 + E * 16 + m * 12
+    return T * (K * per_iter + st["nnz_P"] * 12 + m * 24) + K * C_total * 48
+
+
+def bench_batch(args):
+    """64 independent rollouts of uneven size (16x16 .. 64x64 grids, each with
+    its own stiffness, friction and obstacle), 150 steps, forward + adjoint:
+    all in flight at once (one workgroup per rollout in the forward launch,
+    one per (rollout, step, supernode) in the factorisation launches, one per
+    rollout in the adjoint launches) vs the same rollouts one at a time."""
+    import numpy as np
+    import torch
+
+    import scenes
+    from paper_2106_05306_amd.serve import centroid_seed
+    from paper_2106_05306_amd.sim import Sim, batch_advance
+
+    dev = torch.device("cuda:0")
+    batch = scenes.c4_batch(seed=0, count=args.batch_count, steps=150)
+    kw = dict(precision=args.precision, adj_tol=args.adj_tol, adj_max_iters=args.adj_max_iters,
+              adj_restart=args.adj_restart, adj_solver=args.adj_solver)
+    sims = [Sim.from_scene(sc, device=dev, **kw) for sc in batch]
+    bstream = torch.cuda.Stream(device=dev)
+    T = batch[0].steps
+    window = args.batch_window
+
+    def batched(events=None):
+        for s in sims:
+            s.set_state(None, None)
+            s.job_forward(T)
+        if events:
+            events[0].record(torch.cuda.current_stream())
+        batch_advance(sims, [T] * len(sims), bstream)
+        if events:
+            events[1].record(torch.cuda.current_stream())
+        for s, sc in zip(sims, batch):
+            xT, _ = s.state(T)
+            s.job_backward(centroid_seed(sc, xT))
+        left = [T] * len(sims)
+        while max(left) > 0:
+            left = batch_advance(sims, [window] * len(sims), bstream)
+        return [s.job_grads() for s in sims]
+
+    def sequential():
+        for s, sc in zip(sims, batch):
+            s.set_state(None, None)
+            xT, _, _ = s.forward(T)
+            s.backward(centroid_seed(sc, xT))
+        torch.cuda.synchronize()
+
+    batched()                               # warm-up (allocates records and factor slots)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = batched(ev)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / args.steps
+    fwd_ms = ev[0].elapsed_time(ev[1])
+    t0 = time.perf_counter()
+    sequential()
+    ts = time.perf_counter() - t0
+    R = len(sims)
+    # forward roofline: algorithmic bytes of all rollouts / the batched forward launch
+    fbytes = 0.0
+    for s in sims:
+        st = s.stats()
+        C_total = sum(int(np.count_nonzero(s.modes(n))) for n in range(0, T, 10)) * 10
+        fbytes += forward_bytes_per_rollout(st, st["n_nodes"], st["n_edges"], C_total, 20, T)
+    achieved = fbytes / (fwd_ms * 1e-3) / 1e9
+    result = {
+        "metric": "rollouts/sec, 64 uneven forward+adjoint rollouts in flight",
+        "value": R / tb, "unit": "rollouts/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": tb * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f64+f32", "data": "synthetic",
+        "config": {"workload": f"{R} rollouts, grids 16x16..64x64 (seeded), per-rollout stiffness / mu / "
+                               f"sphere-or-plane, 150 steps h=1/120, K=20, forward + adjoint; one benchmark "
+                               f"step = the whole batch", "adj_solver": args.adj_solver,
+                   "adj_tol": args.adj_tol, "backward_window_steps": window, "precision": args.precision},
+        "cloth_steps_per_s": R * T / tb,
+        "sequential": {"rollouts_per_s": R / ts, "seconds": ts, "speedup_batched": ts / tb},
+        "roofline": {"bound": "hbm", "kernel": "k_forward (batched)", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": fbytes, "launch_ms": fwd_ms},
+        "adjoint_unconverged_rollouts": int(sum(1 for g in out if g["status"] == 2)),
+    }
+    print(json.dumps(result), flush=True)
+
+
+def bench_serve(args):
+    """Serving: forward + gradient requests on grids of round(exp(U[ln 20,
+    ln 100])) nodes per side, 100-300 steps, sphere or plane; material fixed per
+    size so handles (factors) are cached per topology.  Reports saturated
+    throughput (all requests queued at t = 0) and p50 / p99 latency under
+    Poisson arrivals at 0.8 x the measured one-at-a-time capacity, for the
+    continuous-batching server and the one-at-a-time baseline (same kernels)."""
+    import numpy as np
+    import torch
+
+    import scenes
+    from paper_2106_05306_amd.serve import Request, Server, latency_summary
+
+    dev = torch.device("cuda:0")
+    spec = scenes.c5_requests(seed=0, count=args.requests)
+    kw = dict(precision=args.precision, adj_tol=args.adj_tol, adj_max_iters=args.adj_max_iters,
+              adj_restart=args.adj_restart, adj_solver=args.adj_solver)
+
+    def reqs(arrivals):
+        return [Request(i, (n, sph), st, float(a), lambda n=n, st=st, sph=sph, i=i: scenes.request_scene(n, st, sph, i))
+                for i, ((n, st, sph), a) in enumerate(zip(spec, arrivals))]
+
+    srv = Server(dev, hbm_budget_bytes=int(args.hbm_budget_gb * (1 << 30)), round_ms=args.round_ms, **kw)
+    # warm-up: every topology once (fills the factor cache), not timed
+    seen, warm = set(), []
+    for i, (n, st, sph) in enumerate(spec):
+        if (n, sph) not in seen:
+            seen.add((n, sph))
+            warm.append(Request(-1 - i, (n, sph), 4, 0.0, lambda n=n, sph=sph: scenes.request_scene(n, 4, sph, 0)))
+    srv.run(warm)
+    torch.cuda.synchronize()
+    zeros = np.zeros(len(spec))
+    seq_sat = latency_summary(srv.run_sequential(reqs(zeros)))
+    bat_sat = latency_summary(srv.run(reqs(zeros)))
+    lam = 0.8 * seq_sat["rollouts_per_s"]
+    arr = np.cumsum(np.random.default_rng(1).exponential(1.0 / lam, len(spec)))
+    seq_poi = latency_summary(srv.run_sequential(reqs(arr)))
+    bat_poi = latency_summary(srv.run(reqs(arr)))
+    result = {
+        "metric": "served rollouts/sec (mixed sizes, forward+gradient), p99 latency",
+        "value": bat_sat["rollouts_per_s"], "unit": "rollouts/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": bat_sat["makespan_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f64+f32", "data": "synthetic",
+        "config": {"workload": f"{len(spec)} requests, grids round(exp(U[ln 20, ln 100])) per side (400-10000 nodes), "
+                               f"100-300 steps, sphere or plane, springs 1e3, mu 0.5; continuous batching",
+                   "adj_solver": args.adj_solver, "adj_tol": args.adj_tol, "precision": args.precision,
+                   "hbm_budget_gb": args.hbm_budget_gb, "round_ms": args.round_ms},
+        "saturated": {"batched": bat_sat, "sequential": seq_sat,
+                      "speedup": bat_sat["rollouts_per_s"] / seq_sat["rollouts_per_s"]},
+        "poisson": {"arrival_rate_per_s": lam, "batched": bat_poi, "sequential": seq_poi},
+        "server": dict(srv.stats),
+    }
+    srv.close()
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +269,14 @@ def main():
                     help="steps of the rollout the CPU oracle redoes (forward + adjoint)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, help="only run a device copy of this many bytes")
+    ap.add_argument("--workload", default="sphere_drop", choices=["sphere_drop", "batch", "serve"],
+                    help="sphere_drop: the 40x40 rollout (default); batch: 64 uneven rollouts in flight; "
+                         "serve: continuous-batching request server")
+    ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--batch-window", type=int, default=50, help="adjoint steps per launch in the batch workload")
+    ap.add_argument("--requests", type=int, default=40, help="requests of the serve workload")
+    ap.add_argument("--hbm-budget-gb", type=float, default=96.0)
+    ap.add_argument("--round-ms", type=float, default=40.0)
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.copy_probe)
@@ -130,6 +285,12 @@ def main():
         print(json.dumps({"error": "this benchmark runs on exactly one GPU: one rollout per workgroup, "
                                    "no collectives; run with --gpus 1"}))
         sys.exit(2)
+    if args.workload == "batch":
+        bench_batch(args)
+        return
+    if args.workload == "serve":
+        bench_serve(args)
+        return
 
     import numpy as np
     import torch
