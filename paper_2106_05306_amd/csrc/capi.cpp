@@ -86,6 +86,14 @@ int leaf_size_default() {
     return v >= 4 && v <= 256 ? v : 32;
 }
 
+// Largest merged top supernode of P (nodes); DIFFCLOTH_MERGE overrides it for
+// experiments (0: no merging).
+int merge_cap_default() {
+    const char *e = std::getenv("DIFFCLOTH_MERGE");
+    const int v = e ? std::atoi(e) : -1;
+    return v >= 0 && v <= 4096 ? v : 160;
+}
+
 void *dev_alloc(sim *s, size_t bytes) {
     if (bytes == 0) bytes = 8;
     bytes = (bytes + 255) & ~size_t(255);
@@ -457,27 +465,19 @@ void build_device(sim *s) {
     D.binc_con = upload(s, bc);
     D.binc_coef = upload(s, bcf);
     s->factor_bytes = (int64_t)gval.size() * 8;   // per copy (forward and backward each hold one)
-    // direct adjoint: its own supernode partition (the supernodes of P cut into
-    // chunks of at most kLuChunk nodes, so every diagonal block fits the
-    // register inversion), update lists, scatter targets of A's blocks, solve
-    // schedule
+    // direct adjoint: its own supernode partition (host model: P's supernodes
+    // with merged top separators kept apart, cut into chunks small enough for
+    // the register inversion), update lists, scatter targets of A's blocks,
+    // solve schedule
     {
-        const int kLuChunk = 42;
-        std::vector<int32_t> ac0, an, arptr(1, 0), arows, chunk_of(m);
-        for (int sn = 0; sn < ns; ++sn) {
-            const int nck = (sns[sn] + kLuChunk - 1) / kLuChunk, s_end = sc0[sn] + sns[sn];
-            for (int j = 0; j < nck; ++j) {
-                const int c0 = sc0[sn] + (int)((int64_t)sns[sn] * j / nck);
-                const int c1 = sc0[sn] + (int)((int64_t)sns[sn] * (j + 1) / nck);
-                for (int c = c0; c < c1; ++c) chunk_of[c] = (int32_t)ac0.size();
-                ac0.push_back(c0);
-                an.push_back(c1 - c0);
-                for (int c = c1; c < s_end; ++c) arows.push_back(c);      // later chunks of the same supernode
-                for (int q = 0; q < snr[sn]; ++q) arows.push_back(rows[rptr[sn] + q]);
-                arptr.push_back((int32_t)arows.size());
-            }
+        const int na = (int)hm.lu_c0.size() - 1;
+        std::vector<int32_t> ac0(na), an(na), chunk_of(m);
+        const std::vector<int32_t> &arptr = hm.lu_R_ptr, &arows = hm.lu_R_rows;
+        for (int t = 0; t < na; ++t) {
+            ac0[t] = hm.lu_c0[t];
+            an[t] = hm.lu_c0[t + 1] - hm.lu_c0[t];
+            for (int c = ac0[t]; c < ac0[t] + an[t]; ++c) chunk_of[c] = t;
         }
-        const int na = (int)ac0.size();
         std::vector<LuSup> ls(na);
         int64_t off = 0;
         int nmax = 3, ubuf_a = 0;
@@ -516,7 +516,8 @@ void build_device(sim *s) {
         // panel rows in t of the rows of R_d from i0 on: nodes of t first, then
         // R_t (every later row of R_d must be a row of R_t); levels: one more
         // than the highest updater
-        std::vector<int32_t> up_ptr(1, 0), relmap, alevel(na, 0);
+        std::vector<int32_t> up_ptr(1, 0), relmap;
+        const std::vector<int32_t> &alevel = hm.lu_level;
         std::vector<LuUpd> upl;
         for (int t = 0; t < na; ++t) {
             for (LuUpd ud : ul[t]) {
@@ -526,12 +527,10 @@ void build_device(sim *s) {
                     relmap.push_back(i < ud.i1 ? node - ac0[t] : an[t] + pos_in_R(t, node));
                 }
                 upl.push_back(ud);
-                alevel[t] = std::max(alevel[t], alevel[ud.d] + 1);
             }
             up_ptr.push_back((int32_t)upl.size());
         }
-        int L = 0;
-        for (int t = 0; t < na; ++t) L = std::max(L, alevel[t] + 1);
+        const int L = hm.lu_n_levels;
         // scatter target of every block (i, j) of the pattern of K_s (new order).
         // Blocks are stored transposed (column-major): D_t^T (N x N), B_t^T
         // (N x R) and A(t, R_t)^T (R x N), row-major; entry (r, c) of the 3 x 3
@@ -789,7 +788,7 @@ int sim_create(const sim_mesh_t *mesh, const sim_params_t *params, void *hip_str
     s->free_fn = free_fn;
     s->ctx = alloc_ctx;
     int rc = s->hm.build(mesh, params);
-    if (rc == SIM_OK) rc = s->hm.order_and_factor(leaf_size_default());
+    if (rc == SIM_OK) rc = s->hm.order_and_factor(leaf_size_default(), merge_cap_default());
     if (rc == SIM_OK) {
         rc = guarded([&] {
             build_device(s);
@@ -1494,7 +1493,7 @@ int sim_analyze(const sim_mesh_t *mesh, const sim_params_t *params, int32_t leaf
     HostModel hm;
     int rc = hm.build(mesh, params);
     if (rc) return rc;
-    rc = hm.order_and_factor(leaf_size > 0 ? leaf_size : 32);
+    rc = hm.order_and_factor(leaf_size > 0 ? leaf_size : 32, merge_cap_default());
     if (rc) return rc;
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));

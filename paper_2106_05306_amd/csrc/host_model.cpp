@@ -279,17 +279,19 @@ struct NDCtx {
     const std::vector<double> *X;
     int leaf;
     std::vector<int32_t> order;        // new -> old
-    std::vector<int32_t> sup_sizes;    // supernode sizes in elimination order
+    std::vector<int32_t> sup_sizes;    // block sizes in elimination order (post-order)
+    std::vector<int32_t> sep_depth;    // per block: depth of a separator, -1 for a leaf
     std::vector<int32_t> mark;         // scratch: 0 outside, 1 side A, 2 side B
 };
 
-void nd_rec(NDCtx &c, std::vector<int32_t> nodes) {
+void nd_rec(NDCtx &c, std::vector<int32_t> nodes, int depth) {
     const int n = (int)nodes.size();
     if (n == 0) return;
     if (n <= c.leaf) {
         std::sort(nodes.begin(), nodes.end());
         for (int v : nodes) c.order.push_back(v);
         c.sup_sizes.push_back(n);
+        c.sep_depth.push_back(-1);
         return;
     }
     const auto &X = *c.X;
@@ -332,25 +334,76 @@ void nd_rec(NDCtx &c, std::vector<int32_t> nodes) {
         std::sort(nodes.begin(), nodes.end());
         for (int v : nodes) c.order.push_back(v);
         c.sup_sizes.push_back(n);
+        c.sep_depth.push_back(-1);
         return;
     }
     std::vector<int32_t> &sep = best_sep, &A = best_A, &B = best_B;
-    nd_rec(c, A);
-    nd_rec(c, B);
+    nd_rec(c, A, depth + 1);
+    nd_rec(c, B, depth + 1);
     std::sort(sep.begin(), sep.end());
     for (int v : sep) c.order.push_back(v);
     c.sup_sizes.push_back((int)sep.size());
+    c.sep_depth.push_back(depth);
+}
+
+// Supernodal structure of a partition of the columns (in elimination order)
+// into consecutive blocks c0[0] < c0[1] < ...: the off-diagonal rows R_s of
+// every block (its own couplings past its last column plus the rows passed up
+// by its children) and the levels of the resulting tree.
+void symbolic(const std::vector<std::vector<int32_t>> &adj, const std::vector<int32_t> &c0,
+              std::vector<int32_t> &R_ptr, std::vector<int32_t> &R_rows, std::vector<int32_t> &level, int &n_levels) {
+    const int ns = (int)c0.size() - 1, m = (int)adj.size();
+    std::vector<int32_t> blk(m);
+    for (int s = 0; s < ns; ++s)
+        for (int c = c0[s]; c < c0[s + 1]; ++c) blk[c] = s;
+    std::vector<std::vector<int32_t>> pend(ns);
+    std::vector<int32_t> parent(ns, -1);
+    std::vector<char> seen(m, 0);
+    R_ptr.assign(1, 0);
+    R_rows.clear();
+    for (int s = 0; s < ns; ++s) {
+        const int a = c0[s], b = c0[s + 1];
+        std::vector<int32_t> rs;
+        auto add = [&](int r) {
+            if (r >= b && !seen[r]) { seen[r] = 1; rs.push_back(r); }
+        };
+        for (int c = a; c < b; ++c)
+            for (int r : adj[c]) add(r);
+        for (int r : pend[s]) add(r);
+        for (int r : rs) seen[r] = 0;
+        std::sort(rs.begin(), rs.end());
+        if (!rs.empty()) {
+            const int p = blk[rs[0]];
+            parent[s] = p;
+            pend[p].insert(pend[p].end(), rs.begin(), rs.end());
+        }
+        R_rows.insert(R_rows.end(), rs.begin(), rs.end());
+        R_ptr.push_back((int32_t)R_rows.size());
+        pend[s].clear();
+        pend[s].shrink_to_fit();
+    }
+    level.assign(ns, 0);
+    n_levels = 0;
+    for (int s = 0; s < ns; ++s) {                       // children precede parents
+        if (parent[s] >= 0) level[parent[s]] = std::max(level[parent[s]], level[s] + 1);
+        n_levels = std::max(n_levels, level[s] + 1);
+    }
 }
 
 }  // namespace
 
-int HostModel::order_and_factor(int leaf_size) {
-    order(leaf_size);
+int HostModel::order_and_factor(int leaf_size, int merge_cap) {
+    order(leaf_size, merge_cap);
     return factor();
 }
 
-void HostModel::order(int leaf_size) {
-    // ---------------------------------------------------------------- ordering
+// Nested dissection, then: the separators of the top levels of the dissection
+// tree (as many levels as keep their total at most merge_cap nodes) are
+// numbered last, in post-order.  For the factor of P they form one dense
+// supernode (one level of the solves instead of several short ones); the
+// direct adjoint keeps them as separate supernodes and cuts every supernode
+// into chunks of at most lu_chunk nodes.
+void HostModel::order(int leaf_size, int merge_cap) {
     NDCtx ctx;
     ctx.ptr = &ks_ptr;
     ctx.col = &ks_col;
@@ -359,16 +412,54 @@ void HostModel::order(int leaf_size) {
     ctx.mark.assign(m, 0);
     std::vector<int32_t> all(m);
     std::iota(all.begin(), all.end(), 0);
-    nd_rec(ctx, all);
-    perm = ctx.order;
+    nd_rec(ctx, all, 0);
+    const int nb = (int)ctx.sup_sizes.size();
+    int merge_depth = 0;
+    for (int d = 1;; ++d) {
+        int tot = 0, cnt = 0, deeper = 0;
+        for (int b = 0; b < nb; ++b) {
+            if (ctx.sep_depth[b] >= 0 && ctx.sep_depth[b] < d) { tot += ctx.sup_sizes[b]; ++cnt; }
+            if (ctx.sep_depth[b] >= d) ++deeper;
+        }
+        if (tot > merge_cap || cnt == 0) break;
+        merge_depth = d;
+        if (!deeper) break;
+    }
+    if (merge_depth < 2) merge_depth = 0;              // merging one separator changes nothing
+    // final order: blocks in post-order, the merged separators moved to the end
+    std::vector<int32_t> bstart(nb + 1, 0);
+    for (int b = 0; b < nb; ++b) bstart[b + 1] = bstart[b] + ctx.sup_sizes[b];
+    auto merged = [&](int b) { return ctx.sep_depth[b] >= 0 && ctx.sep_depth[b] < merge_depth; };
+    perm.clear();
+    std::vector<int32_t> psizes, lsizes;                 // P's blocks, the adjoint's blocks
+    for (int b = 0; b < nb; ++b)
+        if (!merged(b)) {
+            perm.insert(perm.end(), ctx.order.begin() + bstart[b], ctx.order.begin() + bstart[b + 1]);
+            psizes.push_back(ctx.sup_sizes[b]);
+            lsizes.push_back(ctx.sup_sizes[b]);
+        }
+    int mtot = 0;
+    for (int b = 0; b < nb; ++b)
+        if (merged(b)) {
+            perm.insert(perm.end(), ctx.order.begin() + bstart[b], ctx.order.begin() + bstart[b + 1]);
+            lsizes.push_back(ctx.sup_sizes[b]);
+            mtot += ctx.sup_sizes[b];
+        }
+    if (mtot) psizes.push_back(mtot);
+    merged_nodes = mtot;
     iperm.assign(m, -1);
     for (int i = 0; i < m; ++i) iperm[perm[i]] = i;
-    ns = (int)ctx.sup_sizes.size();
+    ns = (int)psizes.size();
     sup_c0.assign(ns + 1, 0);
-    for (int s = 0; s < ns; ++s) sup_c0[s + 1] = sup_c0[s] + ctx.sup_sizes[s];
+    for (int s = 0; s < ns; ++s) sup_c0[s + 1] = sup_c0[s] + psizes[s];
     sup_of.assign(m, 0);
     for (int s = 0; s < ns; ++s)
         for (int c = sup_c0[s]; c < sup_c0[s + 1]; ++c) sup_of[c] = s;
+    lu_c0.assign(1, 0);
+    for (int sz : lsizes) {
+        const int nck = (sz + lu_chunk - 1) / lu_chunk, base = lu_c0.back();
+        for (int j = 1; j <= nck; ++j) lu_c0.push_back(base + (int)((int64_t)sz * j / nck));
+    }
 
     // permuted lower pattern: for new column c, rows r > c adjacent to it
     std::vector<std::vector<int32_t>> adj(m);
@@ -379,43 +470,8 @@ void HostModel::order(int leaf_size) {
             if (rj > ci) adj[ci].push_back(rj);
         }
     }
-
-    // ---------------------------------------------------------------- symbolic
-    std::vector<std::vector<int32_t>> pend(ns), R(ns);
-    std::vector<int32_t> parent(ns, -1);
-    std::vector<char> seen(m, 0);
-    for (int s = 0; s < ns; ++s) {
-        const int c0 = sup_c0[s], c1 = sup_c0[s + 1];
-        std::vector<int32_t> rs;
-        auto add = [&](int r) {
-            if (r >= c1 && !seen[r]) { seen[r] = 1; rs.push_back(r); }
-        };
-        for (int c = c0; c < c1; ++c)
-            for (int r : adj[c]) add(r);
-        for (int r : pend[s]) add(r);
-        for (int r : rs) seen[r] = 0;
-        std::sort(rs.begin(), rs.end());
-        R[s] = rs;
-        if (!rs.empty()) {
-            int p = sup_of[rs[0]];
-            parent[s] = p;
-            pend[p].insert(pend[p].end(), rs.begin(), rs.end());
-        }
-        pend[s].clear();
-        pend[s].shrink_to_fit();
-    }
-    R_ptr.assign(ns + 1, 0);
-    R_rows.clear();
-    for (int s = 0; s < ns; ++s) {
-        R_rows.insert(R_rows.end(), R[s].begin(), R[s].end());
-        R_ptr[s + 1] = (int32_t)R_rows.size();
-    }
-    sup_level.assign(ns, 0);
-    n_levels = 0;
-    for (int s = 0; s < ns; ++s) {                       // children precede parents
-        if (parent[s] >= 0) sup_level[parent[s]] = std::max(sup_level[parent[s]], sup_level[s] + 1);
-        n_levels = std::max(n_levels, sup_level[s] + 1);
-    }
+    symbolic(adj, sup_c0, R_ptr, R_rows, sup_level, n_levels);
+    symbolic(adj, lu_c0, lu_R_ptr, lu_R_rows, lu_level, lu_n_levels);
 }
 
 // Numeric factorisation on the symbolic structure of order() (left-looking,

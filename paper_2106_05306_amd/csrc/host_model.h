@@ -59,9 +59,18 @@ struct HostModel {
 
     std::string error;
 
+    // partition of the direct adjoint's factor (same order): P's supernodes
+    // with the merged top separators kept apart, cut into chunks of at most
+    // lu_chunk nodes
+    int lu_chunk = 42;
+    std::vector<int32_t> lu_c0;             // [n_lu+1]
+    std::vector<int32_t> lu_R_ptr, lu_R_rows, lu_level;
+    int lu_n_levels = 0;
+    int merged_nodes = 0;                   // nodes of the merged top supernode of P (0: none)
+
     int build(const sim_mesh_t *mesh, const sim_params_t *p);   // SIM_OK or SIM_E*
-    int order_and_factor(int leaf_size);
-    void order(int leaf_size);               // ordering + symbolic structure
+    int order_and_factor(int leaf_size, int merge_cap = 160);
+    void order(int leaf_size, int merge_cap);   // ordering + symbolic structures
     int factor();                            // numeric factor on that structure
     void apply_regions();                    // w = base_w * region scale
     int assemble_ks(bool keep_pattern);      // K_s values (pattern fixed after the first call)
