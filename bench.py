@@ -53,18 +53,23 @@ def traffic_from_profile(kernel_name):
     return float(m.group(1)) if m else None
 
 
-def algorithmic_bytes(st, m, E, C_steps, K, T, adj_iters):
+def algorithmic_bytes(st, m, E, C_steps, K, T, adj_iters, direct):
     """Bytes the method must move (per launch), from the per-unit figures:
     per PD iteration 2 nnz(L) 12 + 4 (3m 8) + E 16 + m 12 + C 48;
     per forward step K x that + nnz(P) 12 + m 24;
-    per adjoint iteration 2 nnz(L) 12 + nnz(P) 12 + E 16 + 6 (3m 8) + C 72."""
+    adjoint, iterative: per iteration 2 nnz(L) 12 + nnz(P) 12 + E 16 + 6 (3m 8) + C 72;
+    adjoint, direct: per solve the step factor F (bytes) + 4 (3m 8), per
+    residual check nnz(P) 12 + E 16 + 6 (3m 8) (one check per solve)."""
     nnzL, nnzP = st["nnz_L"], st["nnz_P"]
     C_tot = float(sum(C_steps))
     per_iter = 2 * nnzL * 12 + 4 * 3 * m * 8 + E * 16 + m * 12
     fwd = T * (K * per_iter + nnzP * 12 + m * 24) + K * C_tot * 48
-    per_adj = 2 * nnzL * 12 + nnzP * 12 + E * 16 + 6 * 3 * m * 8
     C_avg = C_tot / max(T, 1)
-    bwd = adj_iters * (per_adj + C_avg * 72)
+    if direct:
+        bwd = adj_iters * (st["adj_factor_bytes"] + 4 * 3 * m * 8 + nnzP * 12 + E * 16 + 6 * 3 * m * 8 + C_avg * 72)
+    else:
+        per_adj = 2 * nnzL * 12 + nnzP * 12 + E * 16 + 6 * 3 * m * 8
+        bwd = adj_iters * (per_adj + C_avg * 72)
     return fwd, bwd
 
 
@@ -265,8 +270,8 @@ def main():
     ap.add_argument("--adj-max-iters", type=int, default=50)
     ap.add_argument("--adj-restart", type=int, default=30)
     ap.add_argument("--adj-solver", default="direct", choices=["direct", "iterative"])
-    ap.add_argument("--cpu-sample", default="10,40,70,100,130,160,190",
-                    help="steps of the rollout the CPU oracle redoes (forward + adjoint)")
+    ap.add_argument("--cpu-sample", default="all",
+                    help="steps of the rollout the CPU oracle redoes (forward + adjoint): 'all' or a list")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, help="only run a device copy of this many bytes")
     ap.add_argument("--workload", default="sphere_drop", choices=["sphere_drop", "batch", "serve"],
@@ -339,7 +344,8 @@ def main():
     fwd_iters = fwd_stats["fwd_iters_total"]
     C_steps = [int(np.count_nonzero(sim.modes(n))) for n in range(T)]
     adj_iters = st["adj_iters_total"] + st["adj_krylov_total"]
-    fwd_b, bwd_b = algorithmic_bytes(st, sc.n_nodes, st["n_edges"], C_steps, K, T, adj_iters)
+    fwd_b, bwd_b = algorithmic_bytes(st, sc.n_nodes, st["n_edges"], C_steps, K, T, adj_iters,
+                                     args.adj_solver == "direct")
     if bwd_ms > fwd_ms:
         kname, nbytes, ms = "k_backward", bwd_b, bwd_ms
     else:
@@ -370,21 +376,24 @@ def main():
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "algorithmic_bytes_per_launch": nbytes, "launch_ms": ms},
-        "timing_ms": {"forward_launch": fwd_ms, "backward_launch": bwd_ms},
+        "timing_ms": {"forward_launch": fwd_ms, "backward_launch": bwd_ms,
+                      "note": "backward = step factorisations (direct adjoint) + the adjoint launch"},
         "solver": {"pd_iters_per_rollout": fwd_iters, "adj_fixed_point_iters": st["adj_iters_total"],
                    "adj_krylov_iters": st["adj_krylov_total"], "adj_fallback_steps": st["adj_fallbacks"],
                    "adj_unconverged_steps": st["adj_noconv"], "nnz_L": st["nnz_L"], "nnz_P": st["nnz_P"],
                    "levels": st["n_levels"], "lds_forward": st["lds_forward"],
+                   "adj_factor_bytes_per_step": st["adj_factor_bytes"],
                    "contact_nodes_mean": float(np.mean(C_steps))},
     }
     if not args.no_cpu_baseline:
-        sample = [int(v) for v in args.cpu_sample.split(",")]
+        sample = list(range(T)) if args.cpu_sample == "all" else [int(v) for v in args.cpu_sample.split(",")]
         rate, dt, err = cpu_baseline(sim, sc, sample)
         result["cpu_baseline"] = {"value": rate, "unit": "cloth steps/s", "cores": 1, "kind": "oracle",
-                                  "sample": f"forward (K=20, contact) + direct-solve adjoint of steps {sample} "
-                                            f"of the same rollout, redone from the GPU's recorded states, "
+                                  "sample": f"forward (K=20, contact) + direct-solve adjoint of "
+                                            f"{len(sample)} steps ({sample[0]}..{sample[-1]}) of the same "
+                                            f"rollout, each redone from the GPU's recorded state, "
                                             f"FP64 NumPy/SciPy, {dt:.1f} s"}
-        result["error_vs_oracle"] = {"step_positions_max_abs_m": err, "steps_compared": sample,
+        result["error_vs_oracle"] = {"step_positions_max_abs_m": err, "steps_compared": len(sample),
                                      "precision": args.precision,
                                      "note": "one step from the same state; the 20-iteration forward is "
                                              "chaotic over whole rollouts"}
