@@ -69,3 +69,41 @@ def test_host_rejects_bad_inputs():
     with pytest.raises(B.SimError) as e:
         S.analyze(**bad_tri)
     assert e.value.code == B.SIM_EINVAL
+
+
+def test_null_handles_are_rejected_without_a_gpu():
+    # argument checks run before any device work
+    import ctypes
+    B, L = _lib()
+    assert L.sim_set_material(None, None, None, None, None) == B.SIM_EINVAL
+    assert L.sim_job_forward(None, 10) == B.SIM_EINVAL
+    assert L.sim_job_backward(None, None, None) == B.SIM_EINVAL
+    assert L.sim_job_grads(None, None) == B.SIM_EINVAL
+    assert L.sim_batch_advance(None, 0, None, None, None) == B.SIM_EINVAL
+    assert L.sim_forward(None, 5, None, None, None) == B.SIM_EINVAL
+    assert L.sim_backward(None, None, None, None, None) == B.SIM_EINVAL
+    one = (ctypes.c_void_p * 1)(None)
+    steps = (ctypes.c_int32 * 1)(3)
+    assert L.sim_batch_advance(one, 1, steps, None, None) == B.SIM_EINVAL
+
+
+def test_ordering_merges_top_separators():
+    # the elimination tree of a 40 x 40 grid with its top separators merged
+    # into one supernode is shallower than without, and both orders give
+    # L L^T = P_s[perm][:, perm]
+    import os
+    from paper_2106_05306_amd.sim import analyze, scene_kwargs
+    sc = scenes.c2_sphere_drop(0, n=12, steps=2)
+    st, perm, L = analyze(leaf_size=8, max_dense=200, **scene_kwargs(sc))
+    model = O.Model(sc)
+    P = model.P_s.toarray()[perm][:, perm]
+    assert sorted(perm.tolist()) == list(range(sc.n_nodes))
+    assert np.allclose(L @ L.T, P, rtol=1e-12, atol=1e-14 * np.abs(P).max())
+    os.environ["DIFFCLOTH_MERGE"] = "0"
+    try:
+        st0, perm0, L0 = analyze(leaf_size=8, max_dense=200, **scene_kwargs(sc))
+    finally:
+        del os.environ["DIFFCLOTH_MERGE"]
+    P0 = model.P_s.toarray()[perm0][:, perm0]
+    assert np.allclose(L0 @ L0.T, P0, rtol=1e-12, atol=1e-14 * np.abs(P0).max())
+    assert st["n_levels"] < st0["n_levels"]
