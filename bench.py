@@ -226,21 +226,33 @@ def bench_serve(args):
         return [Request(i, (n, sph), st, float(a), lambda n=n, st=st, sph=sph, i=i: scenes.request_scene(n, st, sph, i))
                 for i, ((n, st, sph), a) in enumerate(zip(spec, arrivals))]
 
-    srv = Server(dev, hbm_budget_bytes=int(args.hbm_budget_gb * (1 << 30)), round_ms=args.round_ms, **kw)
+    def progress(r):
+        print(f"served request {r.rid}: latency {r.latency:.2f} s", file=sys.stderr, flush=True)
+
+    srv = Server(dev, hbm_budget_bytes=int(args.hbm_budget_gb * (1 << 30)), round_ms=args.round_ms,
+                 on_done=progress, **kw)
     # warm-up: every topology once (fills the factor cache), not timed
     seen, warm = set(), []
     for i, (n, st, sph) in enumerate(spec):
         if (n, sph) not in seen:
             seen.add((n, sph))
             warm.append(Request(-1 - i, (n, sph), 4, 0.0, lambda n=n, sph=sph: scenes.request_scene(n, 4, sph, 0)))
+    def phase(name):
+        print(f"serve benchmark: {name}", file=sys.stderr, flush=True)
+
+    phase(f"warm-up over {len(warm)} topologies")
     srv.run(warm)
     torch.cuda.synchronize()
     zeros = np.zeros(len(spec))
+    phase("one at a time, all requests queued")
     seq_sat = latency_summary(srv.run_sequential(reqs(zeros)))
+    phase("continuous batching, all requests queued")
     bat_sat = latency_summary(srv.run(reqs(zeros)))
     lam = 0.8 * seq_sat["rollouts_per_s"]
     arr = np.cumsum(np.random.default_rng(1).exponential(1.0 / lam, len(spec)))
+    phase(f"one at a time, Poisson arrivals at {lam:.3f}/s")
     seq_poi = latency_summary(srv.run_sequential(reqs(arr)))
+    phase(f"continuous batching, Poisson arrivals at {lam:.3f}/s")
     bat_poi = latency_summary(srv.run(reqs(arr)))
     result = {
         "metric": "served rollouts/sec (mixed sizes, forward+gradient), p99 latency",

@@ -85,12 +85,13 @@ class _Handle:
 
 class Server:
     def __init__(self, device="cuda:0", hbm_budget_bytes: int = 64 << 30, round_ms: float = 40.0,
-                 max_chunk: int = 64, keep_grads: bool = False, **sim_kw):
+                 max_chunk: int = 64, keep_grads: bool = False, on_done: Optional[Callable] = None, **sim_kw):
         self.device = torch.device(device)
         self.budget = int(hbm_budget_bytes)
         self.round_ms = round_ms
         self.max_chunk = max_chunk
         self.keep_grads = keep_grads
+        self.on_done = on_done              # called with every finished Result (progress reporting)
         self.sim_kw = dict(sim_kw)
         self.pool: Dict[tuple, List[_Handle]] = collections.defaultdict(list)
         self.bstream = torch.cuda.Stream(device=self.device)
@@ -172,6 +173,8 @@ class Server:
                     results.append(Result(req.rid, req.arrival, adm, clock(), int(g["status"]),
                                           g if self.keep_grads else None))
                     self.pool[req.key].append(h)
+                    if self.on_done:
+                        self.on_done(results[-1])
             active = keep
         return results
 
@@ -199,6 +202,8 @@ class Server:
             results.append(Result(req.rid, req.arrival, adm, clock(), int(g["status"]),
                                   g if self.keep_grads else None))
             self.pool[req.key].append(h)
+            if self.on_done:
+                self.on_done(results[-1])
         return results
 
     def close(self):
