@@ -220,7 +220,7 @@ def bench_serve(args):
     dev = torch.device("cuda:0")
     spec = scenes.c5_requests(seed=0, count=args.requests)
     kw = dict(precision=args.precision, adj_tol=args.adj_tol, adj_max_iters=args.adj_max_iters,
-              adj_restart=args.adj_restart, adj_solver=args.adj_solver)
+              adj_restart=args.adj_restart, adj_solver=args.adj_solver, adj_window=32)
 
     def reqs(arrivals):
         return [Request(i, (n, sph), st, float(a), lambda n=n, st=st, sph=sph, i=i: scenes.request_scene(n, st, sph, i))
@@ -292,7 +292,7 @@ def main():
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--batch-window", type=int, default=50, help="adjoint steps per launch in the batch workload")
     ap.add_argument("--requests", type=int, default=40, help="requests of the serve workload")
-    ap.add_argument("--hbm-budget-gb", type=float, default=96.0)
+    ap.add_argument("--hbm-budget-gb", type=float, default=192.0)
     ap.add_argument("--round-ms", type=float, default=40.0)
     args = ap.parse_args()
     if args.copy_probe:

@@ -128,6 +128,9 @@ typedef struct {
  *                  |gbar - A zeta| / (|A| |zeta| + |gbar|) (max norms) is at
  *                  most adj_tol (at most adj_max_iters solves).  Device memory: one factor
  *                  per step of the segment (sim_stats_t.adj_factor_bytes each);
+ *  adj_window      direct adjoint: factor at most this many steps at a time
+ *                  (the window nearest the end first, then its solves, then
+ *                  the next window); 0: all steps of the segment at once;
  *  checkpoint_every  0: keep every step's record for the backward pass;
  *                  k > 0: keep the state every k steps and recompute segments. */
 typedef struct {
@@ -152,6 +155,7 @@ typedef struct {
     int32_t               checkpoint_every;
     int32_t               adj_restart;
     int32_t               adj_solver;
+    int32_t               adj_window;
 } sim_params_t;
 
 /* Gradient outputs (caller-allocated device arrays; any may be NULL). */
@@ -250,6 +254,13 @@ int sim_batch_forward(sim_t *const *sims, int32_t n, const int32_t *n_steps,
                       double *const *xT_dev, double *const *vT_dev);
 int sim_batch_backward(sim_t *const *sims, int32_t n, const double *const *dL_dxT_dev,
                        const sim_grads_t *out);
+
+/* Releases the device memory a handle holds only for a rollout: step records,
+ * checkpoints, the per-step loss buffer, the direct adjoint's step factors and
+ * work lists (the next rollout allocates them again).  The mesh tables and the
+ * factor of P stay.  Drops the recorded rollout (as sim_set_state); waits for
+ * the handle's stream. */
+int sim_trim(sim_t *sim);
 
 /* Continuous batching.  A job on a handle is a forward rollout followed by its
  * backward pass, run in chunks of steps so that handles can join and leave a

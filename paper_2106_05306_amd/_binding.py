@@ -41,7 +41,7 @@ class SimParams(Structure):
                 ("bend_region", c_int32_p), ("region_scale", c_double_p), ("n_regions", c_int32),
                 ("n_obstacles", c_int32), ("obstacles", POINTER(SimObstacle)), ("precision", c_int32),
                 ("adj_tol", c_double), ("adj_max_iters", c_int32), ("checkpoint_every", c_int32),
-                ("adj_restart", c_int32), ("adj_solver", c_int32)]
+                ("adj_restart", c_int32), ("adj_solver", c_int32), ("adj_window", c_int32)]
 
 
 class SimGrads(Structure):
@@ -88,6 +88,7 @@ def lib():
             "sim_batch_forward": (c_int32, [POINTER(c_void_p), c_int32, c_int32_p, POINTER(c_void_p),
                                             POINTER(c_void_p)]),
             "sim_batch_backward": (c_int32, [POINTER(c_void_p), c_int32, POINTER(c_void_p), POINTER(SimGrads)]),
+            "sim_trim": (c_int32, [c_void_p]),
             "sim_job_forward": (c_int32, [c_void_p, c_int32]),
             "sim_job_backward": (c_int32, [c_void_p, c_void_p, c_void_p]),
             "sim_batch_advance": (c_int32, [POINTER(c_void_p), c_int32, c_int32_p, c_void_p, c_int32_p]),

@@ -26,7 +26,6 @@ hipError_t launch_region_grad(const double *dw, const double *base_w, const int3
 hipError_t launch_scatter_bend(const double *dw, const int32_t *centers, int n_edges, int n_bend, double *out,
                                hipStream_t st);
 hipError_t launch_fill(double *p, double v, int64_t n, hipStream_t st);
-size_t adj_factor_lds(int nmax);
 hipError_t launch_adj_assemble(const SimDev *d_sims, const int32_t *work, int nblocks, hipStream_t st);
 hipError_t launch_adj_factor_level(const SimDev *d_sims, const int32_t *work, int nblocks, int nmax, hipStream_t st);
 }  // namespace dc
@@ -63,7 +62,8 @@ struct sim {
     int nca = 0;
     int af_cap = 0;                     // step factors allocated (direct adjoint)
     int n_ubuf_bwd = 0;                 // update-buffer doubles the backward kernel needs
-    std::vector<std::vector<int32_t>> lvl_sn;   // supernodes of each elimination level
+    std::vector<std::vector<int32_t>> lvl_sn;   // supernodes of each elimination level (adjoint factor)
+    std::vector<int32_t> lvl_nmax;      // largest diagonal block (DoF) of each of those levels
     std::vector<int32_t> h_work;        // factorisation work lists (host copy)
     int32_t *d_work = nullptr;          // and their device copy
     size_t work_cap = 0;
@@ -494,7 +494,7 @@ void build_device(sim *s) {
             off += N * N + 2 * N * R;
             nmax = std::max(nmax, (int)N);
         }
-        if (nmax > 384) throw std::runtime_error("supernode chunk too large for the direct adjoint");
+        if (nmax > 128) throw std::runtime_error("supernode chunk too large for the direct adjoint");
         // updaters: chunk d reaches chunk t through a run of rows of R_d
         std::vector<std::vector<LuUpd>> ul(na);
         for (int d = 0; d < na; ++d) {
@@ -600,7 +600,11 @@ void build_device(sim *s) {
             lvl[4 * (l + 1) + 3] = (int32_t)ri.size();
         }
         s->lvl_sn.assign(L, {});
-        for (int l = 0; l < L; ++l) s->lvl_sn[l].assign(lsn.begin() + lvl[4 * l + 2], lsn.begin() + lvl[4 * (l + 1) + 2]);
+        s->lvl_nmax.assign(L, 3);
+        for (int l = 0; l < L; ++l) {
+            s->lvl_sn[l].assign(lsn.begin() + lvl[4 * l + 2], lsn.begin() + lvl[4 * (l + 1) + 2]);
+            for (int t : s->lvl_sn[l]) s->lvl_nmax[l] = std::max(s->lvl_nmax[l], 3 * an[t]);
+        }
         D.ns = na;
         D.lu_nlevels = L;
         D.lu_sup = upload(s, ls);
@@ -1015,10 +1019,12 @@ int factor_pairs(sim *owner, const SimDev *d_descs, const std::vector<sim *> &hs
     if (pairs.empty()) return SIM_OK;
     int rc = hip_err(hipStreamSynchronize(owner->stream));
     if (rc) return rc;
-    int L = 0, nmax = 3;
-    for (sim *h : hs) {
-        L = std::max(L, (int)h->lvl_sn.size());
-        nmax = std::max(nmax, h->hd.af_nmax);
+    int L = 0;
+    for (sim *h : hs) L = std::max(L, (int)h->lvl_sn.size());
+    std::vector<int> nmax(L, 3);
+    for (size_t p = 0; p < pairs.size(); p += 2) {
+        const sim *h = hs[pairs[p]];
+        for (size_t l = 0; l < h->lvl_nmax.size(); ++l) nmax[l] = std::max(nmax[l], h->lvl_nmax[l]);
     }
     std::vector<int32_t> &buf = owner->h_work;
     buf = pairs;
@@ -1047,8 +1053,8 @@ int factor_pairs(sim *owner, const SimDev *d_descs, const std::vector<sim *> &hs
                                 owner->stream));
     if (!rc) rc = hip_err(launch_adj_assemble(d_descs, owner->d_work, (int)pairs.size() / 2, owner->stream));
     for (int l = 0; l < L && !rc; ++l)
-        rc = hip_err(launch_adj_factor_level(d_descs, owner->d_work + loff[l], (int)((loff[l + 1] - loff[l]) / 3), nmax,
-                                             owner->stream));
+        rc = hip_err(launch_adj_factor_level(d_descs, owner->d_work + loff[l], (int)((loff[l + 1] - loff[l]) / 3),
+                                             nmax[l], owner->stream));
     return rc;
 }
 
@@ -1064,17 +1070,30 @@ int factor_steps(sim *s, int a, int b) {
     return factor_pairs(s, s->dd, {s}, pairs);
 }
 
+// Backward over recorded steps [a, b) (records from rec_step0 on): with the
+// direct adjoint in windows of adj_window steps, each factored just before its
+// solves (the last window first).
+int backward_range(sim *s, int a, int b) {
+    const int W = s->hd.adj_direct && s->hm.adj_window > 0 ? s->hm.adj_window : b - a;
+    for (int hi = b; hi > a;) {
+        const int lo = std::max(a, hi - W);
+        s->hd.step_begin = lo;
+        s->hd.step_end = hi;
+        int rc = factor_steps(s, lo, hi);
+        if (!rc) rc = push_desc(s);
+        if (!rc) rc = hip_err(launch_backward(s->dd, 1, s->hd.mixed != 0, s->lds_bwd, s->flags_bwd, s->stream));
+        if (rc) return rc;
+        hi = lo;
+    }
+    return SIM_OK;
+}
+
 int backward_all(sim *s) {
     const int T = s->T, k = seg_len(s);
     const size_t v3 = 3 * (size_t)s->hd.m;
     if (k <= 0) {
-        s->hd.step_begin = 0;
-        s->hd.step_end = T;
         s->hd.rec_step0 = 0;
-        int rc = factor_steps(s, 0, T);
-        if (!rc) rc = push_desc(s);
-        if (rc) return rc;
-        return hip_err(launch_backward(s->dd, 1, s->hd.mixed != 0, s->lds_bwd, s->flags_bwd, s->stream));
+        return backward_range(s, 0, T);
     }
     const int nseg = (T + k - 1) / k;
     for (int seg = nseg - 1; seg >= 0; --seg) {
@@ -1083,12 +1102,8 @@ int backward_all(sim *s) {
         if (!rc) rc = copy_d2d(s, s->hd.v, s->ckpt + ((size_t)seg * 2 + 1) * v3, v3 * sizeof(double));
         if (!rc) rc = run_forward_range(s, a, b);             // recompute the segment's records
         if (rc) return rc;
-        s->hd.step_begin = a;
-        s->hd.step_end = b;
         s->hd.rec_step0 = a;
-        rc = factor_steps(s, a, b);
-        if (!rc) rc = push_desc(s);
-        if (!rc) rc = hip_err(launch_backward(s->dd, 1, s->hd.mixed != 0, s->lds_bwd, s->flags_bwd, s->stream));
+        rc = backward_range(s, a, b);
         if (rc) return rc;
     }
     return SIM_OK;
@@ -1338,6 +1353,27 @@ int sim_batch_backward(sim_t *const *sims, int32_t n, const double *const *dL_dx
     });
 }
 
+
+
+int sim_trim(sim_t *s) {
+    if (!s) return SIM_EINVAL;
+    int rc = hip_err(hipStreamSynchronize(s->stream));
+    if (rc) return rc;
+    for (void **p : {(void **)&s->hd.rec_x, (void **)&s->hd.rec_v, (void **)&s->hd.rec_ubar, (void **)&s->hd.rec_mode,
+                     (void **)&s->hd.rec_obst, (void **)&s->ckpt, (void **)&s->gsteps, (void **)&s->hd.af,
+                     (void **)&s->hd.af_ws, (void **)&s->d_work}) {
+        dev_release(s, *p);
+        *p = nullptr;
+    }
+    s->hd.rec_cap = 0;
+    s->ckpt_cap = 0;
+    s->gsteps_cap = 0;
+    s->af_cap = 0;
+    s->work_cap = 0;
+    s->T = -1;
+    s->phase = 0;
+    return SIM_OK;
+}
 
 int sim_job_forward(sim_t *s, int32_t n_steps) {
     if (!s || n_steps < 1) return SIM_EINVAL;

@@ -53,6 +53,7 @@ int HostModel::build(const sim_mesh_t *mesh, const sim_params_t *p) {
     checkpoint_every = std::max(0, p->checkpoint_every);
     adj_restart = p->adj_restart > 0 ? std::min(p->adj_restart, 60) : 60;
     adj_solver = p->adj_solver;
+    adj_window = std::max(0, p->adj_window);
     if (adj_solver != SIM_ADJ_ITERATIVE && adj_solver != SIM_ADJ_DIRECT) { error = "bad adj_solver"; return SIM_EINVAL; }
     if (p->n_obstacles < 0 || p->n_obstacles > 8 || (p->n_obstacles > 0 && !p->obstacles)) {
         error = "0..8 obstacles";

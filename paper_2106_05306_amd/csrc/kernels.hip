@@ -749,7 +749,6 @@ __device__ __forceinline__ int gmres_solve(const SimDev &S, auto mode, auto gbar
 // update of descendant d onto the blocks it reaches is B_d V_d.
 
 constexpr int kFacBlock = 256;        // threads per factorisation workgroup
-constexpr int kLuPanel = 2048;        // doubles of LDS for one row panel of A(s, R_s)^T
 
 __device__ __forceinline__ void contact_T(const SimDev &S, uint8_t md, int o, auto xi, auto ub, double *T) {
     // T = d v / d ubar of the contact update, row-major (identity off contact)
@@ -883,94 +882,28 @@ __global__ __launch_bounds__(kFacBlock) void k_adj_assemble(const SimDev *__rest
     if (tid == 0) ws[ws_anorm(S)] = anorm;
 }
 
-// Gauss-Jordan inverse in place of the N x N row-major block D in HBM, row
-// pivoting inside the block (pivots below 1e-13 of the block's largest entry
-// are raised to that floor); returns the number of raised pivots.  For blocks
-// too large for registers.
-__device__ __noinline__ int gj_inverse_global(GLOBAL double *D, int N, double *fcol, int *ipiv, double *red) {
-    const int tid = threadIdx.x, bd = blockDim.x;
-    __shared__ int piv_sh;
-    double dm = 0.0;
-    for (int e = tid; e < N * N; e += bd) dm = fmax(dm, fabs(D[e]));
-    const double floor_ = 1e-13 * block_max(dm, red);
-    int pert = 0;
-    for (int k = 0; k < N; ++k) {
-        if (tid < 64) {
-            double best = -1.0;
-            int bi = k;
-            for (int i = k + tid; i < N; i += 64) {
-                const double v = fabs(D[(int64_t)i * N + k]);
-                if (v > best) { best = v; bi = i; }
-            }
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                const double ob = __shfl_xor(best, o, 64);
-                const int oi = __shfl_xor(bi, o, 64);
-                if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-            }
-            if (tid == 0) { piv_sh = bi; ipiv[k] = bi; }
-        }
-        __syncthreads();
-        const int p = piv_sh;
-        if (p != k)
-            for (int j = tid; j < N; j += bd) {
-                const double t = D[(int64_t)k * N + j];
-                D[(int64_t)k * N + j] = D[(int64_t)p * N + j];
-                D[(int64_t)p * N + j] = t;
-            }
-        __syncthreads();
-        double pv = D[(int64_t)k * N + k];
-        if (!(fabs(pv) >= floor_)) {
-            pv = pv < 0.0 ? -floor_ : floor_;
-            if (!(pv != 0.0)) pv = 1e-300;
-            ++pert;
-        }
-        for (int i = tid; i < N; i += bd) fcol[i] = D[(int64_t)i * N + k];
-        __syncthreads();
-        const double pinv = 1.0 / pv;
-        for (int j = tid; j < N; j += bd) D[(int64_t)k * N + j] = j == k ? pinv : D[(int64_t)k * N + j] * pinv;
-        __syncthreads();
-        for (int idx = tid; idx < N * N; idx += bd) {
-            const int i = idx / N, j = idx - i * N;
-            if (i == k) continue;
-            const double f = fcol[i];
-            if (j == k) D[idx] = -f * pinv;
-            else D[idx] -= f * D[(int64_t)k * N + j];
-        }
-        __syncthreads();
-    }
-    for (int k = N - 1; k >= 0; --k) {
-        const int p = ipiv[k];
-        if (p != k)
-            for (int i = tid; i < N; i += bd) {
-                const double t = D[(int64_t)i * N + k];
-                D[(int64_t)i * N + k] = D[(int64_t)i * N + p];
-                D[(int64_t)i * N + p] = t;
-            }
-        __syncthreads();
-    }
-    return pert;
-}
-
-// The same inverse with the block in registers (N <= 16 kGjE, 256 threads):
-// thread (ty, tx) owns entries (ty + 16a, tx + 16b).  Pivot rows are chosen by
-// magnitude among the rows not used yet, without swapping rows; with p_k the
+// Gauss-Jordan inverse in place of the N x N row-major block D (N <= 16 E,
+// 256 threads), held in registers: thread (ty, tx) owns entries
+// (ty + 16a, tx + 16b).  Pivot rows are chosen by magnitude among the rows not
+// used yet, without swapping rows (pivoting inside the block); with p_k the
 // pivot row of column k, the array ends as X with inverse[k][p_j] = X[p_k][j],
-// which the write-back applies.  Two barriers per column.
-constexpr int kGjE = 8;
+// which the write-back applies.  Pivots below 1e-13 of the block's largest
+// entry are raised to that floor; returns how many.  Two barriers per column.
+constexpr int kGjMax = 128;           // largest block (degrees of freedom)
 struct GjShared {
-    double col[2][16 * kGjE];
-    double row[16 * kGjE];
-    int pk[16 * kGjE], inv[16 * kGjE];
+    double col[2][kGjMax];
+    double row[kGjMax];
+    int pk[kGjMax], inv[kGjMax];
 };
-__device__ __noinline__ int gj_inverse_regs(GLOBAL double *D, int N, GjShared *sh, double *red, double *dl) {
+template <int E>
+__device__ __forceinline__ int gj_inverse_regs(GLOBAL double *D, int N, GjShared *sh, double *red) {
     const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15, lane = tid & 63;
-    double X[kGjE][kGjE];
+    double X[E][E];
     double dm = 0.0;
 #pragma unroll
-    for (int a = 0; a < kGjE; ++a)
+    for (int a = 0; a < E; ++a)
 #pragma unroll
-        for (int b = 0; b < kGjE; ++b) {
+        for (int b = 0; b < E; ++b) {
             const int i = ty + 16 * a, j = tx + 16 * b;
             X[a][b] = (i < N && j < N) ? D[(int64_t)i * N + j] : 0.0;
             dm = fmax(dm, fabs(X[a][b]));
@@ -983,10 +916,10 @@ __device__ __noinline__ int gj_inverse_regs(GLOBAL double *D, int N, GjShared *s
         const int bk = k >> 4;
         if (tx == (k & 15)) {
 #pragma unroll
-            for (int a = 0; a < kGjE; ++a) {
+            for (int a = 0; a < E; ++a) {
                 double v = 0.0;
 #pragma unroll
-                for (int b = 0; b < kGjE; ++b) v = b == bk ? X[a][b] : v;
+                for (int b = 0; b < E; ++b) v = b == bk ? X[a][b] : v;
                 if (ty + 16 * a < N) colk[ty + 16 * a] = v;
             }
         }
@@ -1014,21 +947,21 @@ __device__ __noinline__ int gj_inverse_regs(GLOBAL double *D, int N, GjShared *s
         const int ap = p >> 4;
         if (ty == (p & 15)) {
 #pragma unroll
-            for (int b = 0; b < kGjE; ++b) {
+            for (int b = 0; b < E; ++b) {
                 double v = 0.0;
 #pragma unroll
-                for (int a = 0; a < kGjE; ++a) v = a == ap ? X[a][b] : v;
+                for (int a = 0; a < E; ++a) v = a == ap ? X[a][b] : v;
                 if (tx + 16 * b < N) sh->row[tx + 16 * b] = v;
             }
         }
         __syncthreads();
         const double pinv = 1.0 / piv;
 #pragma unroll
-        for (int a = 0; a < kGjE; ++a) {
+        for (int a = 0; a < E; ++a) {
             const int i = ty + 16 * a;
             const double f = i < N ? colk[i] : 0.0;
 #pragma unroll
-            for (int b = 0; b < kGjE; ++b) {
+            for (int b = 0; b < E; ++b) {
                 const int j = tx + 16 * b;
                 if (i >= N || j >= N) continue;
                 if (i == p) X[a][b] = j == k ? pinv : X[a][b] * pinv;
@@ -1039,15 +972,11 @@ __device__ __noinline__ int gj_inverse_regs(GLOBAL double *D, int N, GjShared *s
     for (int i = tid; i < N; i += (int)blockDim.x) sh->inv[sh->pk[i]] = i;
     __syncthreads();
 #pragma unroll
-    for (int a = 0; a < kGjE; ++a)
+    for (int a = 0; a < E; ++a)
 #pragma unroll
-        for (int b = 0; b < kGjE; ++b) {
+        for (int b = 0; b < E; ++b) {
             const int i = ty + 16 * a, j = tx + 16 * b;
-            if (i < N && j < N) {
-                const int e = sh->inv[i] * N + sh->pk[j];
-                D[e] = X[a][b];
-                dl[e] = X[a][b];
-            }
+            if (i < N && j < N) D[sh->inv[i] * N + sh->pk[j]] = X[a][b];
         }
     __syncthreads();
     return pert;
@@ -1119,23 +1048,76 @@ __device__ __forceinline__ void schur_update(const SimDev &S, GLOBAL double *F, 
         }
 }
 
-// One workgroup per (handle, slot, supernode) of one elimination level: the
-// Schur updates of the descendants reaching s (finished by earlier launches),
-// the Gauss-Jordan inverse of the diagonal block, then V_s.  Blocks are stored
-// transposed: Dt = D^T, Bt = B^T (N x R), Ct = A(s, R_s)^T (R x N), row-major.
-// Dynamic LDS: a region of kLdsFacA doubles (update tiles; then the inverse for
-// N <= 128, or the pivot column and rows of the HBM variant) and the V panel.
-constexpr int kLdsFacA = 16 * kGjE * 16 * kGjE;
+// V_t = D_t^{-1} A(t, R_t), transposed: Vt = Ct (D^{-1})^T with Ct (R x N) and
+// the stored inverse (D^{-1})^T (N x N), in place over Ct: 64-row bands of Ct,
+// k in chunks of 16 staged in LDS (tile: 64 x 16 + 16 x 128 doubles), a 4 x 4
+// block of outputs per thread and column tile (N <= 128: two column tiles).
+__device__ __forceinline__ void v_product(GLOBAL double *C, GLOBAL const double *Dinv, int R, int N, double *tile) {
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    double *ta = tile, *tb = tile + 64 * 16;                // ta[k][j], tb[k][i]
+    for (int jb = 0; jb < R; jb += 64) {
+        double acc[2][4][4];
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[c][i][j] = 0.0;
+        for (int k0 = 0; k0 < N; k0 += 16) {
+            for (int e = tid; e < 64 * 16; e += kFacBlock) {
+                const int jj = e >> 4, kk = e & 15;
+                ta[kk * 64 + jj] = (jb + jj < R && k0 + kk < N) ? C[(int64_t)(jb + jj) * N + k0 + kk] : 0.0;
+            }
+            for (int e = tid; e < 16 * 128; e += kFacBlock) {
+                const int kk = e >> 7, ii = e & 127;
+                tb[e] = (k0 + kk < N && ii < N) ? Dinv[(int64_t)(k0 + kk) * N + ii] : 0.0;
+            }
+            __syncthreads();
+#pragma unroll 4
+            for (int kk = 0; kk < 16; ++kk) {
+                double va[4], vb[2][4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) va[j] = ta[kk * 64 + 4 * ty + j];
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) vb[c][i] = tb[kk * 128 + 64 * c + 4 * tx + i];
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) acc[c][j][i] += va[j] * vb[c][i];
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int row = jb + 4 * ty + j, col = 64 * c + 4 * tx + i;
+                    if (row < R && col < N) C[(int64_t)row * N + col] = acc[c][j][i];
+                }
+        __syncthreads();
+    }
+}
+
+// One workgroup per (handle, slot, chunk) of one level of the factor's tree:
+// the Schur updates of the descendants reaching the chunk (finished by earlier
+// launches), the Gauss-Jordan inverse of its diagonal block (E x E register
+// tile per thread, N <= 16 E), then V.  Blocks are stored transposed: Dt = D^T,
+// Bt = B^T (N x R), Ct = A(t, R_t)^T (R x N), row-major.
+constexpr int kFacTile = 64 * 16 + 16 * 128;                 // doubles of LDS for the product tiles
+template <int E>
 __global__ __launch_bounds__(kFacBlock) void k_adj_factor_level(const SimDev *__restrict__ sims,
                                                                 const int32_t *__restrict__ work) {
     const int hidx = work[3 * blockIdx.x], slot = work[3 * blockIdx.x + 1], sn = work[3 * blockIdx.x + 2];
     const SimDev &S = sims[hidx];
-    const int tid = threadIdx.x, bd = blockDim.x;
     const auto F = G(S.af) + (int64_t)slot * S.af_size;
     const auto ws = slot_ws(S, slot);
-    extern __shared__ double lds[];
-    double *regA = lds;
-    double *panel = lds + kLdsFacA;
+    __shared__ double tile[kFacTile];
     __shared__ GjShared small;
     __shared__ double red[kFacBlock / 64];
     const auto &q = G(S.lu_sup)[sn];
@@ -1143,37 +1125,12 @@ __global__ __launch_bounds__(kFacBlock) void k_adj_factor_level(const SimDev *__
     const auto D = F + q.off;
     const auto C = D + (int64_t)N * N + (int64_t)R * N;
     for (int u = G(S.lu_upd_ptr)[sn]; u < G(S.lu_upd_ptr)[sn + 1]; ++u) {
-        schur_update(S, F, q, G(S.lu_upd)[u], regA);
+        schur_update(S, F, q, G(S.lu_upd)[u], tile);
         __syncthreads();
     }
-    const bool small_block = N <= 16 * kGjE;
-    const int pert = small_block ? gj_inverse_regs(D, N, &small, red, regA)
-                                 : gj_inverse_global(D, N, regA, (int *)(regA + N), red);
-    // V_s = D_s^{-1} A(s, R_s); transposed Vt = Ct (D^{-1})^T, a panel of rows of
-    // Ct at a time through LDS
-    if (R > 0) {
-        const int rw = max(1, min(R, kLuPanel / N));
-        for (int j0 = 0; j0 < R; j0 += rw) {
-            const int w = min(rw, R - j0);
-            for (int idx = tid; idx < w * N; idx += bd) panel[idx] = C[(int64_t)j0 * N + idx];
-            __syncthreads();
-            for (int idx = tid; idx < w * N; idx += bd) {
-                const int jj = idx / N, i = idx - jj * N;
-                const double *cr = panel + jj * N;
-                double acc = 0.0;
-                if (small_block) {
-#pragma unroll 8
-                    for (int k = 0; k < N; ++k) acc += cr[k] * regA[k * N + i];
-                } else {
-#pragma unroll 4
-                    for (int k = 0; k < N; ++k) acc += cr[k] * D[(int64_t)k * N + i];
-                }
-                C[(int64_t)(j0 + jj) * N + i] = acc;
-            }
-            __syncthreads();
-        }
-    }
-    if (tid == 0) ((GLOBAL int32_t *)(ws + ws_anorm(S) + 1))[sn] = pert;
+    const int pert = gj_inverse_regs<E>(D, N, &small, red);
+    if (R > 0) v_product(C, D, R, N, tile);
+    if (threadIdx.x == 0) ((GLOBAL int32_t *)(ws + ws_anorm(S) + 1))[sn] = pert;
 }
 
 // sum over k < n of col[k ld] v[k] in order; sixteen independent loads are
@@ -1604,22 +1561,18 @@ hipError_t kernel_static_lds(size_t *fwd, size_t *bwd) {
     return hipSuccess;
 }
 
-// Dynamic LDS of a supernode factorisation: update tiles / inverse region and the V panel.
-size_t adj_factor_lds(int nmax) { return (size_t)(kLdsFacA + kLuPanel) * sizeof(double); }
-
 hipError_t launch_adj_assemble(const SimDev *d_sims, const int32_t *work, int nblocks, hipStream_t st) {
     if (nblocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_adj_assemble, dim3(nblocks), dim3(kFacBlock), 0, st, d_sims, work);
     return hipGetLastError();
 }
 
+// nmax: largest diagonal block of the launch's chunks (degrees of freedom, <= kGjMax)
 hipError_t launch_adj_factor_level(const SimDev *d_sims, const int32_t *work, int nblocks, int nmax, hipStream_t st) {
     if (nblocks <= 0) return hipSuccess;
-    const size_t lds = adj_factor_lds(nmax);
-    hipError_t e = hipFuncSetAttribute((const void *)k_adj_factor_level, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_adj_factor_level, dim3(nblocks), dim3(kFacBlock), lds, st, d_sims, work);
+    if (nmax > kGjMax) return hipErrorInvalidValue;
+    if (nmax <= 96) hipLaunchKernelGGL(k_adj_factor_level<6>, dim3(nblocks), dim3(kFacBlock), 0, st, d_sims, work);
+    else hipLaunchKernelGGL(k_adj_factor_level<8>, dim3(nblocks), dim3(kFacBlock), 0, st, d_sims, work);
     return hipGetLastError();
 }
 

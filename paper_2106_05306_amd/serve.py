@@ -76,6 +76,8 @@ class _Handle:
         self.base_bytes = sim.stats()["device_bytes"]
 
     def need_bytes(self, steps: int, window: int) -> int:
+        """Device bytes of a rollout of `steps` steps whose adjoint runs in
+        chunks of `window` steps (tables + records + step factors)."""
         st = self.sim.stats()
         m = st["n_nodes"]
         records = (steps + 1) * m * 48 + steps * m * 26
@@ -96,6 +98,11 @@ class Server:
         self.pool: Dict[tuple, List[_Handle]] = collections.defaultdict(list)
         self.bstream = torch.cuda.Stream(device=self.device)
         self.stats = collections.Counter()
+
+    def _chunk(self, m: int, backward: bool, steps: int) -> int:
+        """Steps of one round for a rollout of m nodes (about round_ms of work)."""
+        k = int(self.round_ms / step_cost_ms(m, backward))
+        return max(1, min(k, self.max_chunk, steps))
 
     # ------------------------------------------------------------------ handles
     def _idle(self):
@@ -134,8 +141,7 @@ class Server:
                 req = queue[0]
                 scene = req.make_scene()
                 h = self._acquire(req, scene)
-                window = min(self.max_chunk, req.steps)
-                need = h.need_bytes(req.steps, window)
+                need = h.need_bytes(req.steps, self._chunk(h.sim.m, True, req.steps))
                 busy = [(a[2], a[4]) for a in active]
                 if not self._evict(need, busy) and active:
                     self.pool[req.key].append(h)          # wait for memory to free up
@@ -150,11 +156,7 @@ class Server:
             if not active:
                 time.sleep(max(0.0, min(queue[0].arrival - clock(), 0.05)))
                 continue
-            steps = []
-            for req, scene, h, phase, _, _ in active:
-                m = h.sim.m
-                k = int(self.round_ms / step_cost_ms(m, phase == "bwd"))
-                steps.append(max(1, min(k, self.max_chunk)))
+            steps = [self._chunk(h.sim.m, phase == "bwd", req.steps) for req, scene, h, phase, _, _ in active]
             left = batch_advance([a[2].sim for a in active], steps, self.bstream)
             self.stats["rounds"] += 1
             keep = []
@@ -172,6 +174,7 @@ class Server:
                     h.last_used = clock()
                     results.append(Result(req.rid, req.arrival, adm, clock(), int(g["status"]),
                                           g if self.keep_grads else None))
+                    h.sim.trim()                    # an idle handle keeps only its tables and factor
                     self.pool[req.key].append(h)
                     if self.on_done:
                         self.on_done(results[-1])
@@ -201,6 +204,7 @@ class Server:
             h.last_used = clock()
             results.append(Result(req.rid, req.arrival, adm, clock(), int(g["status"]),
                                   g if self.keep_grads else None))
+            h.sim.trim()
             self.pool[req.key].append(h)
             if self.on_done:
                 self.on_done(results[-1])

@@ -50,7 +50,7 @@ def build_structs(X, tris, node_mass, edge_stiffness, *, edges=None, h=1.0 / 120
                   attach_omega=0.0, attach_axis=(0.0, 1.0, 0.0), attach_center=(0.0, 0.0, 0.0),
                   obstacles: Sequence[dict] = (), edge_region=None, bend_region=None, region_scale=None,
                   precision="fp64", adj_tol=1e-10, adj_max_iters=500, checkpoint_every=0, adj_restart=0,
-                  adj_solver="iterative"):
+                  adj_solver="iterative", adj_window=0):
     """Marshal a mesh and its parameters into the C structs; returns
     (SimMesh, SimParams, keep-alive dict of the numpy arrays they point to)."""
     k = {}
@@ -108,6 +108,7 @@ def build_structs(X, tris, node_mass, edge_stiffness, *, edges=None, h=1.0 / 120
     p.checkpoint_every = checkpoint_every
     p.adj_restart = adj_restart
     p.adj_solver = {"iterative": B.SIM_ADJ_ITERATIVE, "direct": B.SIM_ADJ_DIRECT}[adj_solver]
+    p.adj_window = adj_window
     return mesh, p, k
 
 
@@ -247,6 +248,12 @@ class Sim:
                                                 ctypes.byref(s)), "sim_adjoint_step")
         g["status"] = code
         return self._trim(g)
+
+    def trim(self):
+        """Release the device memory held only for a rollout (records, step factors)."""
+        B.check(B.lib().sim_trim(self.h), "sim_trim")
+        self.T = -1
+        self._gen += 1
 
     # ------------------------------------------------------------------ continuous batching
     def job_forward(self, n_steps: int):

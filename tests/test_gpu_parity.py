@@ -275,8 +275,16 @@ def test_direct_adjoint_batch_and_checkpoint_are_bitwise():
         c = _sim(sc, precision="fp64", adj_solver="direct", adj_tol=1e-10, adj_max_iters=10, checkpoint_every=3)
         c.forward(sc.steps)
         gc = c.backward(gseed)
+        w = _sim(sc, precision="fp64", adj_solver="direct", adj_tol=1e-10, adj_max_iters=10, adj_window=4)
+        w.forward(sc.steps)
+        gw = w.backward(gseed)
+        w.trim()                                    # records released: a new rollout works as before
+        w.forward(sc.steps)
+        gw2 = w.backward(gseed)
         for key in ("dx0", "dv0", "dw_edge", "dmu"):
             assert torch.equal(singles[-1][key], gc[key]), key
+            assert torch.equal(singles[-1][key], gw[key]), key
+            assert torch.equal(singles[-1][key], gw2[key]), key
         sims.append(_sim(sc, precision="fp64", adj_solver="direct", adj_tol=1e-10, adj_max_iters=10))
     batch_forward(sims, [sc.steps for sc in batch])
     grads = batch_backward(sims, [torch.ones(sc.n_nodes, 3, dtype=torch.float64, device=DEV) for sc in batch])
