@@ -226,8 +226,11 @@ int sim_forward(sim_t *sim, int32_t n_steps, double *x_traj_dev, double *xT_dev,
 
 /* Back-propagates dL/dx_T (and optionally dL/dv_T and per-step dL/dx_n,
  * [(T+1)*n_nodes*3], entry n is added when the pass reaches x_n) through the
- * recorded rollout.  Returns SIM_ESTATE if no rollout is recorded; a warning
- * if an adjoint step fell back or missed its tolerance. */
+ * recorded rollout.  Returns SIM_ESTATE if no rollout is recorded,
+ * SIM_ENONFINITE if the state gradients overflowed (the adjoint of a step
+ * amplifies when its matrix is far from positive definite, e.g. after a
+ * truncated forward iteration), and a warning if an adjoint step fell back or
+ * missed its tolerance. */
 int sim_backward(sim_t *sim, const double *dL_dxT_dev, const double *dL_dvT_dev,
                  const double *dL_dx_steps_dev, const sim_grads_t *out);
 

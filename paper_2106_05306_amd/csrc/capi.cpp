@@ -1131,9 +1131,22 @@ int write_grads(sim *s, const sim_grads_t *out) {
     return rc;
 }
 
+// Warnings of the last backward pass; SIM_ENONFINITE if its state gradients
+// are not finite (an adjoint step overflowed).
 int backward_status(sim *s) {
     int rc = read_counters(s);
     if (rc) return rc;
+    {
+        const size_t v3 = 3 * (size_t)s->hd.m;
+        std::vector<double> g(2 * v3);
+        rc = hip_err(hipMemcpyAsync(g.data(), s->hd.gx, v3 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        if (!rc) rc = hip_err(hipMemcpyAsync(g.data() + v3, s->hd.gv, v3 * sizeof(double), hipMemcpyDeviceToHost,
+                                             s->stream));
+        if (!rc) rc = hip_err(hipStreamSynchronize(s->stream));
+        if (rc) return rc;
+        for (double v : g)
+            if (!std::isfinite(v)) return SIM_ENONFINITE;
+    }
     if (s->counters_host[3] > 0) return SIM_WADJ_NOCONV;
     if (s->counters_host[2] > 0) return SIM_WADJ_FALLBACK;
     return SIM_OK;

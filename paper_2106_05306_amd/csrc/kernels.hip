@@ -79,6 +79,16 @@ __device__ inline double block_sum(double v, double *red) {
 __device__ __forceinline__ void solve_P(const SimDev &S, auto b, auto T, auto Y, auto x, auto U) {
     const auto gval = G(S.gval);
     for (int l = 0; l < S.n_levels; ++l) {
+        // descriptor of this thread's first product item, fetched before the
+        // gather phase and its barrier (it does not depend on the vectors)
+        const int tl = G(S.lvl_team)[2 * l];
+        const int team = threadIdx.x / tl, lane = threadIdx.x % tl, nteams = (int)blockDim.x / tl;
+        const int i0 = G(S.lvl_items_ptr)[l], i1 = G(S.lvl_items_ptr)[l + 1];
+        int pf_g = 0, pf_ld = 0, pf_kmax = 0, pf_tb = 0, pf_out = 0;
+        if (i0 + team < i1) {
+            const auto &it = G(S.fitems)[i0 + team];
+            pf_g = it.g; pf_ld = it.ld; pf_kmax = it.kmax; pf_tb = it.tbase; pf_out = it.out;
+        }
         const int r0 = G(S.lvl_rows_ptr)[l], r1 = G(S.lvl_rows_ptr)[l + 1];
         for (int t = r0 + threadIdx.x; t < r1; t += (int)blockDim.x) {
             const auto &it = G(S.rows)[t];
@@ -90,14 +100,14 @@ __device__ __forceinline__ void solve_P(const SimDev &S, auto b, auto T, auto Y,
             T[it.i3] = a0; T[it.i3 + 1] = a1; T[it.i3 + 2] = a2;
         }
         __syncthreads();
-        const int tl = G(S.lvl_team)[2 * l];
-        const int team = threadIdx.x / tl, lane = threadIdx.x % tl, nteams = (int)blockDim.x / tl;
-        const int i0 = G(S.lvl_items_ptr)[l], i1 = G(S.lvl_items_ptr)[l + 1];
         for (int t = i0 + team; t < i1; t += nteams) {
-            const auto &it = G(S.fitems)[t];
-            const auto Gb = gval + it.g;
-            const auto Tb = T + it.tbase;
-            const int ld = it.ld, kmax = it.kmax;
+            if (t != i0 + team) {
+                const auto &it = G(S.fitems)[t];
+                pf_g = it.g; pf_ld = it.ld; pf_kmax = it.kmax; pf_tb = it.tbase; pf_out = it.out;
+            }
+            const auto Gb = gval + pf_g;
+            const auto Tb = T + pf_tb;
+            const int ld = pf_ld, kmax = pf_kmax;
             double a0 = 0, a1 = 0, a2 = 0;
             for (int k0 = lane; k0 < kmax; k0 += 8 * tl) {
                 double g[8];
@@ -114,10 +124,10 @@ __device__ __forceinline__ void solve_P(const SimDev &S, auto b, auto T, auto Y,
             }
             a0 = team_sum(a0, tl); a1 = team_sum(a1, tl); a2 = team_sum(a2, tl);
             if (lane == 0) {
-                if (it.out >= 0) {
-                    Y[it.out] = a0; Y[it.out + 1] = a1; Y[it.out + 2] = a2;
+                if (pf_out >= 0) {
+                    Y[pf_out] = a0; Y[pf_out + 1] = a1; Y[pf_out + 2] = a2;
                 } else {
-                    const int o = -it.out - 1;
+                    const int o = -pf_out - 1;
                     U[o] = a0; U[o + 1] = a1; U[o + 2] = a2;
                 }
             }
@@ -1292,8 +1302,9 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
                 }
                 rmax = block_max(rmax, red);
                 zmax = block_max(zmax, red);
-                if (!(rmax > S.adj_tol * (anorm * zmax + gmax))) { ok = true; break; }
-                if (k >= S.adj_max_iters || !(rmax == rmax)) break;
+                const bool finite = rmax == rmax && zmax == zmax && zmax < 1e300;
+                if (finite && !(rmax > S.adj_tol * (anorm * zmax + gmax))) { ok = true; break; }
+                if (k >= S.adj_max_iters || !finite) break;
                 solve_A(S, F, zeta1, T, Y, G(S.zt), U);
                 for (int i = threadIdx.x; i < 3 * m; i += (int)blockDim.x) zeta[i] += G(S.zt)[i];
                 __syncthreads();
@@ -1328,7 +1339,7 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
             zmax = block_max(zmax, red);
             ++k;
             auto tmp = zeta; zeta = zeta1; zeta1 = tmp;
-            if (!(dmax > S.adj_tol * zmax)) { ok = true; break; }
+            if (dmax == dmax && zmax == zmax && !(dmax > S.adj_tol * zmax)) { ok = true; break; }
             // divergence (3 rises in a row / non-finite) or a contraction too slow
             // to reach the tolerance within the remaining budget -> fallback
             rising = (dmax > dprev && k > 1) ? rising + 1 : 0;
