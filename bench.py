@@ -370,6 +370,8 @@ def main():
     ap.add_argument("--adj-max-iters", type=int, default=50)
     ap.add_argument("--adj-restart", type=int, default=30)
     ap.add_argument("--adj-solver", default="direct", choices=["direct", "iterative"])
+    ap.add_argument("--fwd-tol", type=float, default=0.0,
+                    help="sphere_drop: iterate each step to this velocity change (m/s) instead of K=20")
     ap.add_argument("--cpu-sample", default="all",
                     help="steps of the rollout the CPU oracle redoes (forward + adjoint): 'all' or a list")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -413,7 +415,8 @@ def main():
     T, K = sc.steps, sc.pd_iters
     sim = Sim.from_scene(sc, device=dev, precision=args.precision, adj_tol=args.adj_tol,
                          adj_max_iters=args.adj_max_iters, adj_restart=args.adj_restart,
-                         adj_solver=args.adj_solver)
+                         adj_solver=args.adj_solver, fwd_tol=args.fwd_tol, fwd_max_iters=100000)
+    from paper_2106_05306_amd import SimError
     st = sim.stats()
     target = torch.tensor(sc.target, device=dev)
     stream = sim.stream
@@ -429,7 +432,10 @@ def main():
         g = (2.0 / sc.n_nodes) * (xT.mean(dim=0) - target).expand_as(xT).contiguous()  # centroid loss
         if events:
             events[2].record(stream)
-        out = sim.backward(g)
+        try:
+            out = sim.backward(g)
+        except SimError as e:                   # the pass ran to the end; its gradients overflowed
+            out = {"status": e.code}
         if events:
             events[3].record(stream)
         return out
@@ -449,7 +455,7 @@ def main():
     fwd_iters = fwd_stats["fwd_iters_total"]
     C_steps = [int(np.count_nonzero(sim.modes(n))) for n in range(T)]
     adj_iters = st["adj_iters_total"] + st["adj_krylov_total"]
-    fwd_b, bwd_b = algorithmic_bytes(st, sc.n_nodes, st["n_edges"], C_steps, K, T, adj_iters,
+    fwd_b, bwd_b = algorithmic_bytes(st, sc.n_nodes, st["n_edges"], C_steps, fwd_iters / T, T, adj_iters,
                                      args.adj_solver == "direct")
     if bwd_ms > fwd_ms:
         kname, nbytes, ms = "k_backward", bwd_b, bwd_ms
@@ -473,8 +479,9 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f64+f32",
         "data": "synthetic",
         "config": {"workload": "sphere_drop 40x40 nodes (4800 DoF), 1 m cloth onto a 0.25 m sphere, "
-                               "200 steps h=1/120, K=20 PD iterations/step, forward + adjoint "
-                               "(one benchmark step = one rollout)",
+                               "200 steps h=1/120, " + (f"PD iterated to {args.fwd_tol:g} m/s per step"
+                                                        if args.fwd_tol > 0 else "K=20 PD iterations/step") +
+                               ", forward + adjoint (one benchmark step = one rollout)",
                    "precision": args.precision, "adj_tol": args.adj_tol, "adj_max_iters": args.adj_max_iters,
                    "adj_restart": args.adj_restart, "adj_solver": args.adj_solver,
                    "seed": 0},
@@ -483,6 +490,14 @@ def main():
                      "traffic": traffic, "algorithmic_bytes_per_launch": nbytes, "launch_ms": ms},
         "timing_ms": {"forward_launch": fwd_ms, "backward_launch": bwd_ms,
                       "note": "backward = step factorisations (direct adjoint) + the adjoint launch"},
+        "gradient": ({"status": "ok", "dv0_norm": float(out["dv0"].norm()), "dx0_norm": float(out["dx0"].norm())}
+                     if out["status"] >= 0 else
+                     {"status": "non-finite (SIM_ENONFINITE)",
+                      "note": "every adjoint step is solved (each matches the oracle's direct solve from the "
+                              "same state), but chained over 200 steps the adjoint of the truncated K=20 forward "
+                              "amplifies until it overflows: its states are far from the implicit-Euler solution "
+                              "at this stiffness/mass ratio.  The oracle shows the same growth; with the forward "
+                              "converged (1e-10 m/s, 20x20 grid, 120 steps) the chained adjoint stays bounded"}),
         "solver": {"pd_iters_per_rollout": fwd_iters, "adj_fixed_point_iters": st["adj_iters_total"],
                    "adj_krylov_iters": st["adj_krylov_total"], "adj_fallback_steps": st["adj_fallbacks"],
                    "adj_unconverged_steps": st["adj_noconv"], "nnz_L": st["nnz_L"], "nnz_P": st["nnz_P"],
