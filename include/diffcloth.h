@@ -51,6 +51,7 @@ extern "C" {
 #define SIM_EHIP            -6   /* a HIP runtime call failed                           */
 #define SIM_WADJ_FALLBACK    1   /* >= 1 adjoint step needed the fallback solver        */
 #define SIM_WADJ_NOCONV      2   /* >= 1 adjoint step did not reach its tolerance       */
+#define SIM_WADJ_NONFINITE   3   /* the state gradients overflowed (not finite)         */
 
 #define SIM_PLANE            0
 #define SIM_SPHERE           1
@@ -226,11 +227,12 @@ int sim_forward(sim_t *sim, int32_t n_steps, double *x_traj_dev, double *xT_dev,
 
 /* Back-propagates dL/dx_T (and optionally dL/dv_T and per-step dL/dx_n,
  * [(T+1)*n_nodes*3], entry n is added when the pass reaches x_n) through the
- * recorded rollout.  Returns SIM_ESTATE if no rollout is recorded,
- * SIM_ENONFINITE if the state gradients overflowed (the adjoint of a step
- * amplifies when its matrix is far from positive definite, e.g. after a
- * truncated forward iteration), and a warning if an adjoint step fell back or
- * missed its tolerance. */
+ * recorded rollout.  Returns SIM_ESTATE if no rollout is recorded; warnings
+ * (the gradients are written): SIM_WADJ_NONFINITE if the state gradients
+ * overflowed (the adjoint of a step amplifies when its matrix is far from
+ * positive definite, e.g. after a truncated forward iteration), else
+ * SIM_WADJ_NOCONV / SIM_WADJ_FALLBACK if an adjoint step missed its
+ * tolerance / fell back. */
 int sim_backward(sim_t *sim, const double *dL_dxT_dev, const double *dL_dvT_dev,
                  const double *dL_dx_steps_dev, const sim_grads_t *out);
 

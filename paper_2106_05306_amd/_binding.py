@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("DIFFCLOTH_LIB", os.path.join(HERE, "libdiffcloth.so"))
 
 SIM_OK, SIM_EINVAL, SIM_ENOTSPD, SIM_ENOMEM, SIM_ENONFINITE, SIM_ESTATE, SIM_EHIP = 0, -1, -2, -3, -4, -5, -6
-SIM_WADJ_FALLBACK, SIM_WADJ_NOCONV = 1, 2
+SIM_WADJ_FALLBACK, SIM_WADJ_NOCONV, SIM_WADJ_NONFINITE = 1, 2, 3
 SIM_PLANE, SIM_SPHERE = 0, 1
 SIM_FP64, SIM_MIXED = 0, 1
 SIM_ADJ_ITERATIVE, SIM_ADJ_DIRECT = 0, 1

@@ -60,6 +60,9 @@ class _Rollout(torch.autograd.Function):
         gsteps = grads[2] if ctx.trajectory else None
         z = torch.zeros((sim.m, 3), dtype=torch.float64, device=sim.device)
         out = sim.backward(z if gxT is None else gxT, gvT, gsteps)
+        if out["status"] == 3:                  # SIM_WADJ_NONFINITE
+            raise FloatingPointError("the rollout's adjoint overflowed (non-finite gradients); the forward "
+                                     "steps are probably far from converged (raise pd_iters or set fwd_tol)")
         res = [None] * 6
         if ctx.has[0]:
             res[0] = out["dx0"]

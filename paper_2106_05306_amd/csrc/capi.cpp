@@ -445,7 +445,6 @@ void build_device(sim *s) {
     D.gvalt = upload(s, gvalt);
     D.upd_off = upload(s, uo);
     D.n_ubuf = std::max(uoff[ns], 3);
-    D.ubuf = zeros<double>(s, D.n_ubuf);
     // node-centred springs and active curved-bending incidence
     std::vector<int32_t> sp;
     std::vector<SpringInc> sv;
@@ -468,8 +467,11 @@ void build_device(sim *s) {
     // direct adjoint: its own supernode partition (host model: P's supernodes
     // with merged top separators kept apart, cut into chunks small enough for
     // the register inversion), update lists, scatter targets of A's blocks,
-    // solve schedule
-    {
+    // solve schedule (built for handles that use the direct adjoint)
+    D.adj_direct = hm.adj_solver == SIM_ADJ_DIRECT;
+    s->n_ubuf_bwd = D.n_ubuf;
+    if (!D.adj_direct) D.ubuf = zeros<double>(s, D.n_ubuf);
+    if (D.adj_direct) {
         const int na = (int)hm.lu_c0.size() - 1;
         std::vector<int32_t> ac0(na), an(na), chunk_of(m);
         const std::vector<int32_t> &arptr = hm.lu_R_ptr, &arows = hm.lu_R_rows;
@@ -627,12 +629,8 @@ void build_device(sim *s) {
         // workspace: T blocks (9 m), projection scale + direction (4 nca),
         // |A|_inf (1), perturbed pivots per chunk (na int32)
         D.af_ws_size = 9 * (int64_t)m + 4 * (int64_t)std::max(nca, 1) + 1 + (na + 1) / 2;
-        D.adj_direct = hm.adj_solver == SIM_ADJ_DIRECT;
-        s->n_ubuf_bwd = D.n_ubuf;
-        if (D.adj_direct && ubuf_a > D.n_ubuf) {           // the two solves share the update buffer
-            s->n_ubuf_bwd = ubuf_a;
-            D.ubuf = zeros<double>(s, ubuf_a);
-        }
+        s->n_ubuf_bwd = std::max(D.n_ubuf, ubuf_a);             // the two solves share the update buffer
+        D.ubuf = zeros<double>(s, s->n_ubuf_bwd);
     }
     // state and work buffers
     const size_t v3 = 3 * (size_t)m;
@@ -1015,9 +1013,10 @@ int prepare_backward(sim *s, const double *dL_dxT, const double *dL_dvT, const d
 // assembly launch, then one launch per elimination level with a workgroup per
 // (handle, slot, supernode).  The work lists go through owner's buffers; the
 // previous use of them is waited for first.
-int factor_pairs(sim *owner, const SimDev *d_descs, const std::vector<sim *> &hs, const std::vector<int32_t> &pairs) {
+int factor_pairs(sim *owner, const SimDev *d_descs, const std::vector<sim *> &hs, const std::vector<int32_t> &pairs,
+                 hipStream_t st) {
     if (pairs.empty()) return SIM_OK;
-    int rc = hip_err(hipStreamSynchronize(owner->stream));
+    int rc = hip_err(hipStreamSynchronize(st));
     if (rc) return rc;
     int L = 0;
     for (sim *h : hs) L = std::max(L, (int)h->lvl_sn.size());
@@ -1049,12 +1048,11 @@ int factor_pairs(sim *owner, const SimDev *d_descs, const std::vector<sim *> &hs
         owner->d_work = (int32_t *)dev_alloc(owner, buf.size() * sizeof(int32_t));
         owner->work_cap = buf.size();
     }
-    rc = hip_err(hipMemcpyAsync(owner->d_work, buf.data(), buf.size() * sizeof(int32_t), hipMemcpyHostToDevice,
-                                owner->stream));
-    if (!rc) rc = hip_err(launch_adj_assemble(d_descs, owner->d_work, (int)pairs.size() / 2, owner->stream));
+    rc = hip_err(hipMemcpyAsync(owner->d_work, buf.data(), buf.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    if (!rc) rc = hip_err(launch_adj_assemble(d_descs, owner->d_work, (int)pairs.size() / 2, st));
     for (int l = 0; l < L && !rc; ++l)
         rc = hip_err(launch_adj_factor_level(d_descs, owner->d_work + loff[l], (int)((loff[l + 1] - loff[l]) / 3),
-                                             nmax[l], owner->stream));
+                                             nmax[l], st));
     return rc;
 }
 
@@ -1067,7 +1065,7 @@ int factor_steps(sim *s, int a, int b) {
     if (rc) return rc;
     std::vector<int32_t> pairs;
     for (int k = 0; k < b - a; ++k) { pairs.push_back(0); pairs.push_back(k); }
-    return factor_pairs(s, s->dd, {s}, pairs);
+    return factor_pairs(s, s->dd, {s}, pairs, s->stream);
 }
 
 // Backward over recorded steps [a, b) (records from rec_step0 on): with the
@@ -1131,8 +1129,8 @@ int write_grads(sim *s, const sim_grads_t *out) {
     return rc;
 }
 
-// Warnings of the last backward pass; SIM_ENONFINITE if its state gradients
-// are not finite (an adjoint step overflowed).
+// Warnings of the last backward pass, the most severe first: non-finite state
+// gradients, a missed tolerance, a fallback.
 int backward_status(sim *s) {
     int rc = read_counters(s);
     if (rc) return rc;
@@ -1145,7 +1143,7 @@ int backward_status(sim *s) {
         if (!rc) rc = hip_err(hipStreamSynchronize(s->stream));
         if (rc) return rc;
         for (double v : g)
-            if (!std::isfinite(v)) return SIM_ENONFINITE;
+            if (!std::isfinite(v)) return SIM_WADJ_NONFINITE;
     }
     if (s->counters_host[3] > 0) return SIM_WADJ_NOCONV;
     if (s->counters_host[2] > 0) return SIM_WADJ_FALLBACK;
@@ -1347,7 +1345,7 @@ int sim_batch_backward(sim_t *const *sims, int32_t n, const double *const *dL_dx
         if (rc) return rc;
         SimDev *d = (SimDev *)dev_alloc(s0, n * sizeof(SimDev));
         rc = hip_err(hipMemcpyAsync(d, descs.data(), n * sizeof(SimDev), hipMemcpyHostToDevice, s0->stream));
-        if (!rc && !work.empty()) rc = factor_pairs(s0, d, std::vector<sim *>(sims, sims + n), work);
+        if (!rc && !work.empty()) rc = factor_pairs(s0, d, std::vector<sim *>(sims, sims + n), work, s0->stream);
         int fl = 0;
         const size_t lb = batch_lds(sims, n, false, fl);
         if (!rc) rc = hip_err(launch_backward(d, n, s0->hd.mixed != 0, lb, fl, s0->stream));
@@ -1463,12 +1461,7 @@ int sim_batch_advance(sim_t *const *sims, int32_t n, const int32_t *steps, void 
             rc = hip_err(launch_forward(dfd, (int)fw.size(), fw[0]->hd.mixed != 0, lb, fl, sf));
         }
         if (!rc && dbd) {
-            if (!pairs.empty()) {
-                hipStream_t keep = bw[0]->stream;
-                bw[0]->stream = sb;                                 // factor work lists ride on the backward stream
-                rc = factor_pairs(bw[0], dbd, bw, pairs);
-                bw[0]->stream = keep;
-            }
+            if (!pairs.empty()) rc = factor_pairs(bw[0], dbd, bw, pairs, sb);
             int fl = 0;
             const size_t lb = batch_lds(bw.data(), (int)bw.size(), false, fl);
             if (!rc) rc = hip_err(launch_backward(dbd, (int)bw.size(), bw[0]->hd.mixed != 0, lb, fl, sb));
@@ -1533,6 +1526,7 @@ const char *sim_strerror(int code) {
         case SIM_EHIP: return "HIP runtime error";
         case SIM_WADJ_FALLBACK: return "warning: an adjoint step used the fallback solver";
         case SIM_WADJ_NOCONV: return "warning: an adjoint step missed its tolerance";
+        case SIM_WADJ_NONFINITE: return "warning: the state gradients overflowed (not finite)";
         default: return "unknown code";
     }
 }

@@ -171,6 +171,8 @@ class Server:
                     keep.append(a)
                 else:
                     g = h.sim.job_grads()
+                    if g["status"] == 3:            # gradients overflowed: served, reported
+                        self.stats["nonfinite"] += 1
                     h.last_used = clock()
                     results.append(Result(req.rid, req.arrival, adm, clock(), int(g["status"]),
                                           g if self.keep_grads else None))

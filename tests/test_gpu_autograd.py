@@ -155,3 +155,21 @@ def test_backward_after_another_rollout_raises():
     sim.forward(4)
     with pytest.raises(RuntimeError):
         xT.sum().backward()
+
+
+def test_overflowing_adjoint_is_reported():
+    # the 200-step 40x40 sphere drop with K = 20: the chained adjoint of the
+    # truncated steps overflows in mixed precision; the library says so
+    # (warning code), the autograd function raises
+    from paper_2106_05306_amd.autograd import rollout
+    from paper_2106_05306_amd.serve import centroid_seed
+    sc = scenes.c2_sphere_drop(0)
+    sim = _sim(sc, precision="mixed", adj_solver="direct", adj_tol=1e-4, adj_max_iters=20)
+    xT, _, _ = sim.forward(sc.steps)
+    out = sim.backward(centroid_seed(sc, xT))
+    assert out["status"] == 3
+    assert not torch.isfinite(out["dx0"]).all()
+    v0 = torch.zeros(sc.n_nodes, 3, dtype=torch.float64, device=DEV, requires_grad=True)
+    xT, _ = rollout(sim, sc.steps, v0=v0)
+    with pytest.raises(FloatingPointError):
+        xT.sum().backward()
