@@ -177,7 +177,8 @@ void ks_new_order(const HostModel &hm, std::vector<int32_t> &kp, std::vector<int
 // off-diagonal block:
 //   forward  y_s = L_ss^{-1} t_s and u_s = B_s y_s = (B_s L_ss^{-1}) t_s in one product,
 //   backward x_s = L_ss^{-T} y_s - (B_s L_ss^{-1})^T x_{R_s}.
-// gvalt holds every block again, row-major, for the backward solve.
+// gvalt holds every block again, row-major, for the backward solve (a thread
+// per column reads consecutive addresses across the wavefront).
 void stacked_factor(const HostModel &hm, std::vector<double> &gval, std::vector<double> &gvalt,
                     std::vector<int64_t> &goff) {
     const int ns = hm.ns;
@@ -383,16 +384,20 @@ void build_device(sim *s) {
     }
     if (gval.size() >= (size_t)INT32_MAX || uoff[ns] >= INT32_MAX / 2) throw std::runtime_error("factor too large");
     // level work lists (packed) and lanes per item
-    std::vector<int32_t> lrp(hm.n_levels + 1, 0), lip(hm.n_levels + 1, 0), team(2 * hm.n_levels, 1);
+    std::vector<int32_t> lrp(hm.n_levels + 1, 0), lip(hm.n_levels + 1, 0), lgp(hm.n_levels + 1, 0),
+        team(2 * hm.n_levels, 1);
     std::vector<RowItem> ritems;
     std::vector<BwdItem> bitems;
+    std::vector<GatherItem> bgat;
     std::vector<FwdItem> fitems;
     auto pick_team = [](int items, int maxlen) {
         int best = 1;
         double best_cost = 1e300;
-        for (int tl = 1; tl <= 32; tl *= 2) {
+        for (int tl = 1; tl <= 64; tl *= 2) {
             const int passes = (items * tl + kBlock - 1) / kBlock;
-            const double cost = passes * ((maxlen + tl - 1) / tl + 0.5 * __builtin_ctz(tl) + 1.0);
+            // dependent round trips: kSolveBatch loads per lane in flight per batch
+            const double cost = passes * ((maxlen + kSolveBatch * tl - 1) / (kSolveBatch * tl) +
+                                          0.5 * __builtin_ctz(tl) + 1.0);
             if (cost < best_cost) { best_cost = cost; best = tl; }
         }
         return best;
@@ -407,16 +412,16 @@ void build_device(sim *s) {
                 const int c = c0 + k;
                 ritems.push_back(RowItem{3 * c, up[c], up[c + 1], 0});
                 BwdItem b{};
-                b.g = (int32_t)(goff[sn] + k);
-                b.k = (int16_t)k;
-                b.ld = (int16_t)ld;
-                b.nsz = (int16_t)nsz;
-                b.ybase = 3 * c0;
-                b.rbase = rptr[sn] - nsz;
-                b.out = 3 * c;
+                b.g = (int32_t)(goff[sn] + (int64_t)k * nsz + k);
+                b.n1 = (int16_t)(nsz - k);
+                b.n2 = (int16_t)snr[sn];
+                b.ybase = 3 * c;
+                b.ubase = uoff[sn];
+                b.nsz = nsz;
                 bitems.push_back(b);
                 bmax = std::max(bmax, ld - k);
             }
+            for (int q = 0; q < snr[sn]; ++q) bgat.push_back(GatherItem{uoff[sn] + 3 * q, 3 * rows[rptr[sn] + q]});
             for (int r = 0; r < ld; ++r) {
                 FwdItem f{};
                 f.g = (int32_t)(goff[sn] + r);
@@ -430,6 +435,7 @@ void build_device(sim *s) {
         }
         lrp[l + 1] = (int32_t)ritems.size();
         lip[l + 1] = (int32_t)fitems.size();
+        lgp[l + 1] = (int32_t)bgat.size();
         team[2 * l] = pick_team(lip[l + 1] - lip[l], fmax);
         team[2 * l + 1] = pick_team(lrp[l + 1] - lrp[l], bmax);
     }
@@ -437,6 +443,8 @@ void build_device(sim *s) {
     D.lvl_rows_ptr = upload(s, lrp);
     D.lvl_items_ptr = upload(s, lip);
     D.lvl_team = upload(s, team);
+    D.lvl_gat_ptr = upload(s, lgp);
+    D.bgat = upload(s, bgat);
     D.rows = upload(s, ritems);
     D.fitems = upload(s, fitems);
     D.bitems = upload(s, bitems);

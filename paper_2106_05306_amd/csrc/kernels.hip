@@ -22,6 +22,8 @@ namespace dc {
 #define GLOBAL __attribute__((address_space(1)))
 template <class T>
 __device__ __forceinline__ GLOBAL T *G(T *p) { return (GLOBAL T *)p; }
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v2i __attribute__((ext_vector_type(2)));
 // compile-time choice between an LDS and an HBM pointer (their types differ)
 template <bool C, class P, class Q>
 __device__ __forceinline__ auto pick(P a, Q b) {
@@ -84,11 +86,9 @@ __device__ __forceinline__ void solve_P(const SimDev &S, auto b, auto T, auto Y,
         const int tl = G(S.lvl_team)[2 * l];
         const int team = threadIdx.x / tl, lane = threadIdx.x % tl, nteams = (int)blockDim.x / tl;
         const int i0 = G(S.lvl_items_ptr)[l], i1 = G(S.lvl_items_ptr)[l + 1];
-        int pf_g = 0, pf_ld = 0, pf_kmax = 0, pf_tb = 0, pf_out = 0;
-        if (i0 + team < i1) {
-            const auto &it = G(S.fitems)[i0 + team];
-            pf_g = it.g; pf_ld = it.ld; pf_kmax = it.kmax; pf_tb = it.tbase; pf_out = it.out;
-        }
+        const auto fit = (GLOBAL const v4i *)S.fitems;  // FwdItem as 16 bytes
+        v4i cur = {0, 0, 0, 0};
+        if (i0 + team < i1) cur = fit[i0 + team];
         const int r0 = G(S.lvl_rows_ptr)[l], r1 = G(S.lvl_rows_ptr)[l + 1];
         for (int t = r0 + threadIdx.x; t < r1; t += (int)blockDim.x) {
             const auto &it = G(S.rows)[t];
@@ -101,70 +101,88 @@ __device__ __forceinline__ void solve_P(const SimDev &S, auto b, auto T, auto Y,
         }
         __syncthreads();
         for (int t = i0 + team; t < i1; t += nteams) {
-            if (t != i0 + team) {
-                const auto &it = G(S.fitems)[t];
-                pf_g = it.g; pf_ld = it.ld; pf_kmax = it.kmax; pf_tb = it.tbase; pf_out = it.out;
-            }
-            const auto Gb = gval + pf_g;
-            const auto Tb = T + pf_tb;
-            const int ld = pf_ld, kmax = pf_kmax;
+            v4i nxt = {0, 0, 0, 0};            // next descriptor, in flight meanwhile
+            if (t + nteams < i1) nxt = fit[t + nteams];
+            const auto Gb = gval + cur.x;
+            const auto Tb = T + cur.z;
+            const int ld = cur.y & 0xffff, kmax = cur.y >> 16, out = cur.w;
             double a0 = 0, a1 = 0, a2 = 0;
-            for (int k0 = lane; k0 < kmax; k0 += 8 * tl) {
-                double g[8];
+            for (int k0 = lane; k0 < kmax; k0 += kSolveBatch * tl) {
+                double g[kSolveBatch];
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {            // eight independent loads in flight
+                for (int j = 0; j < kSolveBatch; ++j) {           // kSolveBatch independent loads in flight
                     const int k = k0 + j * tl;
                     g[j] = k < kmax ? Gb[k * ld] : 0.0;
                 }
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
+                for (int j = 0; j < kSolveBatch; ++j) {
                     const int k = k0 + j * tl;
                     if (k < kmax) { a0 += g[j] * Tb[3 * k]; a1 += g[j] * Tb[3 * k + 1]; a2 += g[j] * Tb[3 * k + 2]; }
                 }
             }
             a0 = team_sum(a0, tl); a1 = team_sum(a1, tl); a2 = team_sum(a2, tl);
             if (lane == 0) {
-                if (pf_out >= 0) {
-                    Y[pf_out] = a0; Y[pf_out + 1] = a1; Y[pf_out + 2] = a2;
+                if (out >= 0) {
+                    Y[out] = a0; Y[out + 1] = a1; Y[out + 2] = a2;
                 } else {
-                    const int o = -pf_out - 1;
+                    const int o = -out - 1;
                     U[o] = a0; U[o + 1] = a1; U[o + 2] = a2;
                 }
             }
+            cur = nxt;
         }
         __syncthreads();
     }
+    // backward: the update buffer is free; each level first gathers x_{R_s}
+    // of its supernodes into their update slots, then forms
+    // x_s = L_ss^{-T} y_s - (B_s L_ss^{-1})^T x_{R_s}, one item per column of G_s
+    // (row-major copy: the items of a wavefront read consecutive addresses)
     for (int l = S.n_levels - 1; l >= 0; --l) {
         const int tl = G(S.lvl_team)[2 * l + 1];
         const int team = threadIdx.x / tl, lane = threadIdx.x % tl, nteams = (int)blockDim.x / tl;
-        const int r0 = G(S.lvl_rows_ptr)[l], r1 = G(S.lvl_rows_ptr)[l + 1];
-        for (int t = r0 + team; t < r1; t += nteams) {
-            const auto &it = G(S.bitems)[t];
-            const auto Gb = G(S.gvalt) + it.g;           // row-major: element (r, k) at r * nsz
-            const auto Yb = Y + it.ybase;
-            const auto R = G(S.sup_rows) + it.rbase;
-            const int ld = it.ld, nsz = it.nsz;
+        const int c0 = G(S.lvl_rows_ptr)[l], c1 = G(S.lvl_rows_ptr)[l + 1];
+        const auto bit = (GLOBAL const v4i *)S.bitems;  // BwdItem as 2 x 16 bytes
+        v4i cur = {0, 0, 0, 0}, cur2 = {0, 0, 0, 0};
+        if (c0 + team < c1) { cur = bit[2 * (c0 + team)]; cur2 = bit[2 * (c0 + team) + 1]; }
+        const int q0 = G(S.lvl_gat_ptr)[l], q1 = G(S.lvl_gat_ptr)[l + 1];
+        if (q1 > q0) {
+            for (int q = q0 + threadIdx.x; q < q1; q += (int)blockDim.x) {
+                const v2i e = ((GLOBAL const v2i *)S.bgat)[q];   // GatherItem {u, x3}
+                U[e.x] = x[e.y]; U[e.x + 1] = x[e.y + 1]; U[e.x + 2] = x[e.y + 2];
+            }
+            __syncthreads();
+        }
+        for (int t = c0 + team; t < c1; t += nteams) {
+            v4i nxt = {0, 0, 0, 0}, nxt2 = {0, 0, 0, 0};
+            if (t + nteams < c1) { nxt = bit[2 * (t + nteams)]; nxt2 = bit[2 * (t + nteams) + 1]; }
+            const auto Gb = G(S.gvalt) + cur.x;
+            const int64_t st = cur2.x;
+            const int n1 = cur.y & 0xffff, n = n1 + (cur.y >> 16), yb = cur.z;
+            const auto Yb = Y + yb;
+            const int ub = cur.w - 3 * n1;               // U[ub + 3k] is row k >= n1
             double a0 = 0, a1 = 0, a2 = 0;
-            for (int r0i = it.k + lane; r0i < ld; r0i += 8 * tl) {
-                double g[8];
+            for (int k0 = lane; k0 < n; k0 += kSolveBatch * tl) {
+                double g[kSolveBatch];
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const int r = r0i + j * tl;
-                    g[j] = r < ld ? Gb[r * nsz] : 0.0;
+                for (int j = 0; j < kSolveBatch; ++j) {
+                    const int k = k0 + j * tl;
+                    g[j] = k < n ? Gb[k * st] : 0.0;
                 }
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const int r = r0i + j * tl;
-                    if (r < nsz) {
-                        a0 += g[j] * Yb[3 * r]; a1 += g[j] * Yb[3 * r + 1]; a2 += g[j] * Yb[3 * r + 2];
-                    } else if (r < ld) {
-                        const auto xr = x + 3 * R[r];
-                        a0 -= g[j] * xr[0]; a1 -= g[j] * xr[1]; a2 -= g[j] * xr[2];
+                for (int j = 0; j < kSolveBatch; ++j) {
+                    const int k = k0 + j * tl;
+                    if (k < n1) {
+                        a0 += g[j] * Yb[3 * k]; a1 += g[j] * Yb[3 * k + 1]; a2 += g[j] * Yb[3 * k + 2];
+                    } else if (k < n) {
+                        const int o = ub + 3 * k;
+                        a0 -= g[j] * U[o]; a1 -= g[j] * U[o + 1]; a2 -= g[j] * U[o + 2];
                     }
                 }
             }
             a0 = team_sum(a0, tl); a1 = team_sum(a1, tl); a2 = team_sum(a2, tl);
-            if (lane == 0) { x[it.out] = a0; x[it.out + 1] = a1; x[it.out + 2] = a2; }
+            if (lane == 0) { x[yb] = a0; x[yb + 1] = a1; x[yb + 2] = a2; }
+            cur = nxt;
+            cur2 = nxt2;
         }
         __syncthreads();
     }

@@ -11,6 +11,7 @@ namespace dc {
 constexpr int kMaxObstacles = 8;
 constexpr int kBlock = 1024;         // threads per workgroup of the forward kernel (16 wavefronts)
 constexpr int kBlockAdj = 1024;      // threads per workgroup of the adjoint kernel
+constexpr int kSolveBatch = 8;      // loads per lane in flight in the triangular solves of P
 constexpr int kTeam = 8;             // lanes cooperating on one solve row / column
 constexpr int kKryM = 60;            // GMRES restart length of the adjoint fallback
 
@@ -21,15 +22,20 @@ struct FwdItem {            // forward: one row r of a stacked block G_s
     int32_t tbase;          // 3 * c0: first right-hand-side entry of the supernode
     int32_t out;            // >= 0: 3 * (c0 + r) in the forward result; < 0: -(ubuf offset) - 1
 };
-struct BwdItem {            // backward: one column k of a stacked block G_s
-    int32_t g;              // offset of G_s[0, k] in gvalt (row-major copy, row stride nsz)
-    int16_t k, ld;          // first row used and column length
-    int16_t nsz, pad;       // diagonal-block size = row stride of the row-major copy
-    int32_t ybase;          // 3 * c0
-    int32_t rbase;          // offset into sup_rows of row nsz of this block (= rptr - nsz)
-    int32_t out;            // 3 * (c0 + k)
-    int32_t pad2;
+struct BwdItem {            // backward: one column k of a stacked block G_s, rows k .. ld-1
+    int32_t g;              // offset of G_s[k, k] in gvalt (row-major copy, row stride nsz)
+    int16_t n1, n2;         // rows k .. ns-1 (times y_s) and the nR rows of B_s (times x_{R_s})
+    int32_t ybase;          // 3 * (c0 + k): y_s entry of row k and output entry of column k
+    int32_t ubase;          // ubuf offset of the supernode: x_{R_s} is gathered there first
+    int32_t nsz;            // row stride of the row-major copy
+    int32_t pad[3];
 };
+struct GatherItem {         // backward: x_{R_s} entry copied into the supernode's ubuf slot
+    int32_t u;              // ubuf offset (3 doubles)
+    int32_t x3;             // 3 * node
+};
+// the kernels read these descriptors as 16-byte / 8-byte vectors (field order as declared)
+static_assert(sizeof(FwdItem) == 16 && sizeof(BwdItem) == 32 && sizeof(GatherItem) == 8, "descriptor layout");
 struct RowItem {            // forward gather: t_i = b_i - sum of update entries
     int32_t i3;             // 3 * i
     int32_t p0, p1;         // range in upd_off
@@ -94,11 +100,13 @@ struct SimDev {
     // G_s = [L_ss^{-1}; B_s L_ss^{-1}], column-major (ns + nR) x ns
     int n_levels;
     const int32_t *lvl_rows_ptr;      // [n_levels+1] into rows / bwd items (columns of each level)
+    const int32_t *lvl_gat_ptr;       // [n_levels+1] into bgat
     const int32_t *lvl_items_ptr;     // [n_levels+1] into fwd items
     const int32_t *lvl_team;          // [2*n_levels] lanes per item: forward, backward
     const RowItem *rows;
     const FwdItem *fitems;
     const BwdItem *bitems;
+    const GatherItem *bgat;
     const int32_t *sup_rows;          // off-diagonal row structure R_s (concatenated)
     const double *gval;               // stacked blocks, column-major (forward)
     const double *gvalt;              // the same blocks, row-major (backward)
