@@ -253,7 +253,8 @@ int sim_stats(const sim_t *sim, sim_stats_t *out);
 
 /* Batched forward / backward of independent handles in one persistent launch
  * (one workgroup per handle; handles may differ in size and step count).  All
- * handles must share the first handle's stream.  Per-handle arguments are
+ * handles must share the first handle's stream and precision, and for the
+ * backward call its adj_solver (else SIM_EINVAL).  Per-handle arguments are
  * arrays of length n (entries may be NULL where the single call allows it). */
 int sim_batch_forward(sim_t *const *sims, int32_t n, const int32_t *n_steps,
                       double *const *xT_dev, double *const *vT_dev);
@@ -280,7 +281,8 @@ int sim_trim(sim_t *sim);
  *                     first handle's stream and, for the backward chunks, the
  *                     step factorisations (direct adjoint) and one launch on
  *                     backward_stream (NULL: the same stream); all handles must
- *                     share the first handle's stream and precision.  It
+ *                     share the first handle's stream, precision and
+ *                     adj_solver (else SIM_EINVAL).  It
  *                     returns when both streams are done; left[i] (host, may be
  *                     NULL) receives the steps still to run in the phase (0:
  *                     phase finished; x_T then via sim_state, gradients via

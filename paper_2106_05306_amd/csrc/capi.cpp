@@ -16,7 +16,6 @@
 namespace dc {
 hipError_t launch_forward(const SimDev *d_sims, int n, bool mixed, size_t lds, int flags, hipStream_t st);
 hipError_t launch_backward(const SimDev *d_sims, int n, bool mixed, size_t lds, int flags, hipStream_t st);
-constexpr int kLdsVectors = 1, kLdsUpdates = 2, kLdsPositions = 4;
 hipError_t configure_lds(size_t fwd_bytes, size_t bwd_bytes);
 hipError_t kernel_static_lds(size_t *fwd, size_t *bwd);
 hipError_t launch_permute3(const double *in, double *out, const int32_t *perm, int m, bool to_caller, hipStream_t st);
@@ -132,6 +131,57 @@ T *zeros(sim *s, size_t n) {
         throw std::runtime_error("hip memset");
     return d;
 }
+
+// Splits the 16-column batches of one phase of the direct adjoint solve into
+// kAdjWaves contiguous runs of (nearly) equal length, in item order; a cut
+// inside an item moves to the item's boundary when that is at most one batch
+// away.  Appends the items, each wavefront's run (first item, first batch,
+// last item, end batch) and the items whose batches span several
+// wavefronts (their parts are summed in wavefront order; wavefronts with an
+// empty run in between hold no part).
+void balance_phase(const std::vector<AdjItem> &ph, std::vector<AdjItem> &items, std::vector<int32_t> &prog,
+                   std::vector<int32_t> &split, std::vector<int32_t> &sptr) {
+    const int base = (int)items.size(), ni = (int)ph.size();
+    std::vector<int64_t> pre(ni + 1, 0);                  // first batch of each item
+    for (int i = 0; i < ni; ++i) pre[i + 1] = pre[i] + std::max(1, (ph[i].K + kAdjBatch - 1) / kAdjBatch);
+    const int64_t total = pre[ni];
+    std::vector<int64_t> cut(kAdjWaves + 1, 0);
+    cut[kAdjWaves] = total;
+    for (int w = 1; w < kAdjWaves; ++w) {
+        int64_t c = (total * w + kAdjWaves / 2) / kAdjWaves;
+        const int i = (int)(std::upper_bound(pre.begin(), pre.end(), c) - pre.begin()) - 1;   // item holding batch c
+        if (i < ni) {
+            if (c - pre[i] <= 1) c = pre[i];
+            else if (pre[i + 1] - c <= 1) c = pre[i + 1];
+        }
+        cut[w] = std::max(c, cut[w - 1]);
+    }
+    auto locate = [&](int64_t c, int &item, int &batch) {           // batch c as (item, batch in item)
+        if (c >= total) { item = ni; batch = 0; return; }
+        item = (int)(std::upper_bound(pre.begin(), pre.end(), c) - pre.begin()) - 1;
+        batch = (int)(c - pre[item]);
+    };
+    std::vector<int> first_item(kAdjWaves);
+    for (int w = 0; w < kAdjWaves; ++w) {
+        int i0, b0, i1, b1;
+        locate(cut[w], i0, b0);
+        locate(cut[w + 1], i1, b1);
+        first_item[w] = i0;
+        for (int v : {base + i0, b0, base + i1, b1}) prog.push_back(v);
+    }
+    for (int i = 0; i < ni; ++i) {
+        int wa = -1, wb = -1;
+        for (int w = 0; w < kAdjWaves; ++w)
+            if (cut[w + 1] > cut[w] && cut[w] < pre[i + 1] && cut[w + 1] > pre[i]) { if (wa < 0) wa = w; wb = w; }
+        if (wa >= 0 && wb > wa)
+            for (int v : {base + i, wa, wb, 0}) split.push_back(v);
+    }
+    sptr.push_back((int32_t)(split.size() / 4));
+    items.insert(items.end(), ph.begin(), ph.end());
+}
+
+// variant bits of an adjoint launch: LDS placement plus the handle's solver
+int bwd_variant(const sim *s, int lds_flags) { return (lds_flags & 3) | (s->hd.adj_direct ? kAdjDirect : 0); }
 
 size_t lds_bytes(const sim *s, int flags, bool fwd) {
     const size_t m3 = 3 * (size_t)s->hd.m;
@@ -583,8 +633,8 @@ void build_device(sim *s) {
             }
         }
         // solve schedule by level: forward gathers (per node: the update-buffer
-        // entries reaching it), 64-row chunks of D^{-1} (z and backward products)
-        // and of B (update products), one wavefront each
+        // entries reaching it), backward gathers of x_{R_t}, and the block
+        // products in 64-row items (D^{-1}, B, V), balanced over the wavefronts
         std::vector<std::vector<int32_t>> aupd(m);
         for (int d = 0; d < na; ++d)
             for (int q = 0; q < ls[d].r; ++q) aupd[arows[arptr[d] + q]].push_back(ls[d].uoff + 3 * q);
@@ -593,28 +643,37 @@ void build_device(sim *s) {
             auo.insert(auo.end(), aupd[i].begin(), aupd[i].end());
             aup.push_back((int32_t)auo.size());
         }
-        std::vector<int32_t> lvl(4 * (L + 1), 0), lsn;
-        std::vector<LuItem> zi, ui;
+        std::vector<int32_t> lvl(2 * (L + 1), 0);
         std::vector<RowItem> ri;
-        for (int l = 0; l < L; ++l) {
-            for (int t = 0; t < na; ++t) {
-                if (alevel[t] != l) continue;
-                lsn.push_back(t);
-                for (int a = 0; a < 3 * an[t]; a += 64) zi.push_back(LuItem{t, a});
-                for (int a = 0; a < 3 * ls[t].r; a += 64) ui.push_back(LuItem{t, a});
-                for (int c = ac0[t]; c < ac0[t] + an[t]; ++c) ri.push_back(RowItem{3 * c, aup[c], aup[c + 1], 0});
-            }
-            lvl[4 * (l + 1)] = (int32_t)zi.size();
-            lvl[4 * (l + 1) + 1] = (int32_t)ui.size();
-            lvl[4 * (l + 1) + 2] = (int32_t)lsn.size();
-            lvl[4 * (l + 1) + 3] = (int32_t)ri.size();
-        }
+        std::vector<GatherItem> gat;
+        std::vector<std::vector<AdjItem>> phase(3 * L);
         s->lvl_sn.assign(L, {});
         s->lvl_nmax.assign(L, 3);
         for (int l = 0; l < L; ++l) {
-            s->lvl_sn[l].assign(lsn.begin() + lvl[4 * l + 2], lsn.begin() + lvl[4 * (l + 1) + 2]);
-            for (int t : s->lvl_sn[l]) s->lvl_nmax[l] = std::max(s->lvl_nmax[l], 3 * an[t]);
+            for (int t = 0; t < na; ++t) {
+                if (alevel[t] != l) continue;
+                const LuSup &q = ls[t];
+                const int N = 3 * q.n, R = 3 * q.r, t0 = 3 * q.c0;
+                s->lvl_sn[l].push_back(t);
+                s->lvl_nmax[l] = std::max(s->lvl_nmax[l], N);
+                for (int c = ac0[t]; c < ac0[t] + an[t]; ++c) ri.push_back(RowItem{3 * c, aup[c], aup[c + 1], 0});
+                for (int k = 0; k < q.r; ++k) gat.push_back(GatherItem{q.uoff + 3 * k, 3 * arows[q.rptr + k]});
+                for (int a = 0; a < N; a += 64) {       // z_t = D_t^{-1} t_t and x_t = z_t - V_t x_{R_t}
+                    const int nr = std::min(64, N - a);
+                    phase[3 * l].push_back(AdjItem{q.off + a, N, N, t0, t0 + a, nr, 0});
+                    phase[3 * l + 2].push_back(AdjItem{q.off + (int64_t)N * N + (int64_t)R * N + a, N, R, (int32_t)q.uoff,
+                                                       t0 + a, nr, 0});
+                }
+                for (int a = 0; a < R; a += 64)         // u_t = B_t z_t
+                    phase[3 * l + 1].push_back(AdjItem{q.off + (int64_t)N * N + a, R, N, t0, q.uoff + a,
+                                                       std::min(64, R - a), 0});
+            }
+            lvl[2 * (l + 1)] = (int32_t)ri.size();
+            lvl[2 * (l + 1) + 1] = (int32_t)gat.size();
         }
+        std::vector<AdjItem> aitems;
+        std::vector<int32_t> aprog, asplit, asptr(1, 0);
+        for (const auto &ph : phase) balance_phase(ph, aitems, aprog, asplit, asptr);
         D.ns = na;
         D.lu_nlevels = L;
         D.lu_sup = upload(s, ls);
@@ -627,9 +686,11 @@ void build_device(sim *s) {
         D.dp_ptr = upload(s, dptr);
         D.dp_ks = upload(s, dks);
         D.lu_lvl = upload(s, lvl);
-        D.lu_zitems = upload(s, zi);
-        D.lu_uitems = upload(s, ui);
-        D.lu_sn = upload(s, lsn);
+        D.lu_gat = upload(s, gat);
+        D.adj_items = upload(s, aitems);
+        D.adj_prog = upload(s, aprog);
+        D.adj_sptr = upload(s, asptr);
+        D.adj_split = upload(s, asplit);
         D.lu_rows = upload(s, ri);
         D.lu_upd_off = upload(s, auo);
         D.af_size = off;
@@ -1087,7 +1148,7 @@ int backward_range(sim *s, int a, int b) {
         s->hd.step_end = hi;
         int rc = factor_steps(s, lo, hi);
         if (!rc) rc = push_desc(s);
-        if (!rc) rc = hip_err(launch_backward(s->dd, 1, s->hd.mixed != 0, s->lds_bwd, s->flags_bwd, s->stream));
+        if (!rc) rc = hip_err(launch_backward(s->dd, 1, s->hd.mixed != 0, s->lds_bwd, bwd_variant(s, s->flags_bwd), s->stream));
         if (rc) return rc;
         hi = lo;
     }
@@ -1201,7 +1262,7 @@ int sim_adjoint_step(sim_t *s, int32_t n, const double *gx_dev, const double *gv
         s->hd.rec_step0 = 0;
         if (!rc) rc = factor_steps(s, n, n + 1);
         if (!rc) rc = push_desc(s);
-        if (!rc) rc = hip_err(launch_backward(s->dd, 1, s->hd.mixed != 0, s->lds_bwd, s->flags_bwd, s->stream));
+        if (!rc) rc = hip_err(launch_backward(s->dd, 1, s->hd.mixed != 0, s->lds_bwd, bwd_variant(s, s->flags_bwd), s->stream));
         if (!rc && dx_dev) rc = hip_err(launch_permute3(s->hd.gx, dx_dev, s->d_perm, m, true, s->stream));
         if (!rc && dv_dev) rc = hip_err(launch_permute3(s->hd.gv, dv_dev, s->d_perm, m, true, s->stream));
         if (!rc && out) {
@@ -1329,7 +1390,8 @@ int sim_batch_backward(sim_t *const *sims, int32_t n, const double *const *dL_dx
     for (int i = 0; i < n; ++i) {
         if (!sims[i]) return SIM_EINVAL;
         if (sims[i]->T < 1) return SIM_ESTATE;
-        if (seg_len(sims[i]) > 0 || sims[i]->stream != sims[0]->stream || sims[i]->hd.mixed != sims[0]->hd.mixed)
+        if (seg_len(sims[i]) > 0 || sims[i]->stream != sims[0]->stream || sims[i]->hd.mixed != sims[0]->hd.mixed ||
+            sims[i]->hd.adj_direct != sims[0]->hd.adj_direct)
             return SIM_EINVAL;
     }
     sim *s0 = sims[0];
@@ -1356,7 +1418,7 @@ int sim_batch_backward(sim_t *const *sims, int32_t n, const double *const *dL_dx
         if (!rc && !work.empty()) rc = factor_pairs(s0, d, std::vector<sim *>(sims, sims + n), work, s0->stream);
         int fl = 0;
         const size_t lb = batch_lds(sims, n, false, fl);
-        if (!rc) rc = hip_err(launch_backward(d, n, s0->hd.mixed != 0, lb, fl, s0->stream));
+        if (!rc) rc = hip_err(launch_backward(d, n, s0->hd.mixed != 0, lb, bwd_variant(s0, fl), s0->stream));
         int warn = SIM_OK;
         for (int i = 0; i < n && !rc; ++i) {
             if (out) rc = write_grads(sims[i], &out[i]);
@@ -1424,7 +1486,9 @@ int sim_batch_advance(sim_t *const *sims, int32_t n, const int32_t *steps, void 
     if (!sims || n < 1 || !steps) return SIM_EINVAL;
     for (int i = 0; i < n; ++i) {
         if (!sims[i] || steps[i] < 1) return SIM_EINVAL;
-        if (sims[i]->stream != sims[0]->stream || sims[i]->hd.mixed != sims[0]->hd.mixed) return SIM_EINVAL;
+        if (sims[i]->stream != sims[0]->stream || sims[i]->hd.mixed != sims[0]->hd.mixed ||
+            sims[i]->hd.adj_direct != sims[0]->hd.adj_direct)
+            return SIM_EINVAL;
         if (sims[i]->phase != 1 && sims[i]->phase != 3) return SIM_ESTATE;
     }
     hipStream_t sf = sims[0]->stream, sb = backward_stream ? (hipStream_t)backward_stream : sf;
@@ -1472,7 +1536,7 @@ int sim_batch_advance(sim_t *const *sims, int32_t n, const int32_t *steps, void 
             if (!pairs.empty()) rc = factor_pairs(bw[0], dbd, bw, pairs, sb);
             int fl = 0;
             const size_t lb = batch_lds(bw.data(), (int)bw.size(), false, fl);
-            if (!rc) rc = hip_err(launch_backward(dbd, (int)bw.size(), bw[0]->hd.mixed != 0, lb, fl, sb));
+            if (!rc) rc = hip_err(launch_backward(dbd, (int)bw.size(), bw[0]->hd.mixed != 0, lb, bwd_variant(bw[0], fl), sb));
         }
         const int r1 = hip_err(hipStreamSynchronize(sf));
         const int r2 = hip_err(hipStreamSynchronize(sb));

@@ -368,8 +368,6 @@ __device__ __forceinline__ void spring_rhs(const SimDev &S, auto XN, auto V, aut
     }
 }
 
-// LDS placement bits chosen by the host for a launch.
-constexpr int kLdsVectors = 1, kLdsUpdates = 2, kLdsPositions = 4;
 
 // Forward steps [step_begin, step_end) of one handle per workgroup.  The PD
 // iterate ping-pongs between two vectors A and B (LDS when they fit): B gets
@@ -1161,28 +1159,84 @@ __global__ __launch_bounds__(kFacBlock) void k_adj_factor_level(const SimDev *__
     if (threadIdx.x == 0) ((GLOBAL int32_t *)(ws + ws_anorm(S) + 1))[sn] = pert;
 }
 
-// sum over k < n of col[k ld] v[k] in order; sixteen independent loads are
-// issued before their products (the step factors stream from HBM)
-__device__ __forceinline__ double col_dot(auto col, int64_t ld, auto v, int n) {
-    double acc = 0.0;
-    int k = 0;
-    for (; k + 16 <= n; k += 16) {
-        double c[16];
+// One phase of the direct adjoint solve (see AdjItem): every wavefront runs
+// its share of the 16-column batches, a row per lane, sixteen loads in flight;
+// an item finished inside the share is written at once, a part of an item
+// that spans several wavefronts goes to part[] and is summed, in wavefront
+// order, after the barrier.  OP 0: out = M v; OP 1: out = z - M v.
+template <int OP>
+__device__ __forceinline__ void adj_phase(const SimDev &S, int ph, auto F, auto v, auto z, auto out, double *part) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const auto items = (GLOBAL const v4i *)S.adj_items;                 // AdjItem as 2 x 16 bytes
+    const v4i pr = ((GLOBAL const v4i *)S.adj_prog)[ph * kAdjWaves + wave];
+    int i = pr.x, kb = pr.y;
+    while (i < pr.z || (i == pr.z && kb < pr.w)) {
+        const v4i d0 = items[2 * i], d1 = items[2 * i + 1];
+        const int64_t moff = (int64_t)(uint32_t)d0.x | ((int64_t)d0.y << 32);
+        const int ld = d0.z, K = d0.w, vb = d1.x, ob = d1.y, nrow = d1.z;
+        const int nkb = K > 0 ? (K + kAdjBatch - 1) / kAdjBatch : 1;
+        const int kend = i == pr.z ? pr.w : nkb;
+        const bool whole = kb == 0 && kend == nkb;
+        const auto col = F + moff + lane;
+        double acc = 0.0;
+        const bool live = lane < nrow;
+        for (; kb < kend; ++kb) {
+            const int k0 = kb * kAdjBatch;
+            double c[kAdjBatch];
+            if (k0 + kAdjBatch <= K) {                  // full batch: one predicate for all loads
+                if (live) {
 #pragma unroll
-        for (int j = 0; j < 16; ++j) c[j] = col[(int64_t)(k + j) * ld];
+                    for (int j = 0; j < kAdjBatch; ++j) c[j] = col[(k0 + j) * ld];
+                } else {
 #pragma unroll
-        for (int j = 0; j < 16; ++j) acc += c[j] * v[k + j];
+                    for (int j = 0; j < kAdjBatch; ++j) c[j] = 0.0;
+                }
+#pragma unroll
+                for (int j = 0; j < kAdjBatch; ++j) acc += c[j] * v[vb + k0 + j];
+            } else {
+#pragma unroll
+                for (int j = 0; j < kAdjBatch; ++j) c[j] = live && k0 + j < K ? col[(k0 + j) * ld] : 0.0;
+#pragma unroll
+                for (int j = 0; j < kAdjBatch; ++j)
+                    if (k0 + j < K) acc += c[j] * v[vb + k0 + j];
+            }
+        }
+        if (whole) {
+            if (lane < nrow) out[ob + lane] = OP == 0 ? acc : z[ob + lane] - acc;
+        } else {
+            part[(2 * wave + (i == pr.x ? 0 : 1)) * 64 + lane] = acc;
+        }
+        ++i;
+        kb = 0;
     }
-    for (; k < n; ++k) acc += col[(int64_t)k * ld] * v[k];
-    return acc;
+    __syncthreads();
+    const int s0 = G(S.adj_sptr)[ph], s1 = G(S.adj_sptr)[ph + 1];
+    if (s1 > s0) {
+        for (int e = s0 + wave; e < s1; e += kAdjWaves) {
+            const v4i sp = ((GLOBAL const v4i *)S.adj_split)[e];
+            const v4i d1 = items[2 * sp.x + 1];
+            double acc = 0.0;
+            for (int w = sp.y; w <= sp.z; ++w) {
+                const v4i pw = ((GLOBAL const v4i *)S.adj_prog)[ph * kAdjWaves + w];
+                if (pw.x == pw.z && pw.y == pw.w) continue;          // empty run: no part
+                acc += part[(2 * w + (sp.x == pw.x ? 0 : 1)) * 64 + lane];
+            }
+            const int ob = d1.y;
+            if (lane < d1.z) out[ob + lane] = OP == 0 ? acc : z[ob + lane] - acc;
+        }
+        __syncthreads();
+    }
 }
 
-__device__ __forceinline__ void solve_A(const SimDev &S, auto F, auto b, auto T, auto Z, auto x, auto U) {
+// x = A^{-1} b with a step factor F: forward sweep by level (gather t_t,
+// z_t = D_t^{-1} t_t, u_t = B_t z_t), backward sweep (gather x_{R_t},
+// x_t = z_t - V_t x_{R_t}).  T, Z, U: work vectors; part: 2 x 64 doubles per wavefront.
+__device__ __forceinline__ void solve_A(const SimDev &S, auto F, auto b, auto T, auto Z, auto x, auto U,
+                                        double *part) {
     const int tid = threadIdx.x, bd = blockDim.x;
-    const int wave = tid >> 6, lane = tid & 63, nw = bd >> 6;
     const auto lvl = G(S.lu_lvl);
     for (int l = 0; l < S.lu_nlevels; ++l) {
-        for (int it = lvl[4 * l + 3] + tid; it < lvl[4 * (l + 1) + 3]; it += bd) {
+        for (int it = lvl[2 * l] + tid; it < lvl[2 * (l + 1)]; it += bd) {
             const auto &ri = G(S.lu_rows)[it];
             double t0 = b[ri.i3], t1 = b[ri.i3 + 1], t2 = b[ri.i3 + 2];
             for (int p = ri.p0; p < ri.p1; ++p) {
@@ -1192,37 +1246,19 @@ __device__ __forceinline__ void solve_A(const SimDev &S, auto F, auto b, auto T,
             T[ri.i3] = t0; T[ri.i3 + 1] = t1; T[ri.i3 + 2] = t2;
         }
         __syncthreads();
-        for (int it = lvl[4 * l] + wave; it < lvl[4 * (l + 1)]; it += nw) {
-            const auto &li = G(S.lu_zitems)[it];
-            const auto &q = G(S.lu_sup)[li.s];
-            const int N = 3 * q.n, t0 = 3 * q.c0, r = li.a + lane;
-            if (r < N) Z[t0 + r] = col_dot(F + q.off + r, N, T + t0, N);
-        }
-        __syncthreads();
-        for (int it = lvl[4 * l + 1] + wave; it < lvl[4 * (l + 1) + 1]; it += nw) {
-            const auto &li = G(S.lu_uitems)[it];
-            const auto &q = G(S.lu_sup)[li.s];
-            const int N = 3 * q.n, R = 3 * q.r, t0 = 3 * q.c0, r = li.a + lane;
-            if (r < R) U[q.uoff + r] = col_dot(F + q.off + (int64_t)N * N + r, R, Z + t0, N);
-        }
-        __syncthreads();
+        adj_phase<0>(S, 3 * l, F, T, Z, Z, part);
+        adj_phase<0>(S, 3 * l + 1, F, Z, Z, U, part);
     }
     for (int l = S.lu_nlevels - 1; l >= 0; --l) {
-        // x_{R_t} of every chunk of the level, gathered into the (now free)
-        // update buffer in the layout of u_t
-        for (int it = lvl[4 * l + 2] + wave; it < lvl[4 * (l + 1) + 2]; it += nw) {
-            const auto &q = G(S.lu_sup)[G(S.lu_sn)[it]];
-            const auto rr = G(S.lu_srows) + q.rptr;
-            for (int k = lane; k < 3 * q.r; k += 64) U[q.uoff + k] = x[3 * rr[k / 3] + k % 3];
+        const int q0 = lvl[2 * l + 1], q1 = lvl[2 * (l + 1) + 1];
+        if (q1 > q0) {
+            for (int q = q0 + tid; q < q1; q += bd) {
+                const v2i e = ((GLOBAL const v2i *)S.lu_gat)[q];   // GatherItem {u, x3}
+                U[e.x] = x[e.y]; U[e.x + 1] = x[e.y + 1]; U[e.x + 2] = x[e.y + 2];
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        for (int it = lvl[4 * l] + wave; it < lvl[4 * (l + 1)]; it += nw) {
-            const auto &li = G(S.lu_zitems)[it];
-            const auto &q = G(S.lu_sup)[li.s];
-            const int N = 3 * q.n, R = 3 * q.r, t0 = 3 * q.c0, r = li.a + lane;
-            if (r < N) x[t0 + r] = Z[t0 + r] - col_dot(F + q.off + (int64_t)N * N + (int64_t)R * N + r, N, U + q.uoff, R);
-        }
-        __syncthreads();
+        adj_phase<1>(S, 3 * l + 2, F, U, Z, x, part);
     }
 }
 
@@ -1232,6 +1268,7 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
     extern __shared__ double dyn[];
     __shared__ double red[kBlock / 64];
     constexpr bool kv = (FL & kLdsVectors) != 0, ku = (FL & kLdsUpdates) != 0;
+    constexpr bool direct = (FL & kAdjDirect) != 0;      // per-step factors (else fixed point + GMRES)
     auto T = pick<kv>(dyn, G(S.rhs));
     auto Y = pick<kv>(dyn + 3 * S.m, G(S.ysol));
     auto U = pick<ku>(dyn + (kv ? 6 * S.m : 0), G(S.ubuf));
@@ -1297,14 +1334,15 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
         __syncthreads();
         auto zeta = G(S.zeta);
         auto zeta1 = G(S.zeta1);
-        if (S.adj_direct) {
+        if constexpr (direct) {
             // zeta = A^{-1} gbar with the step's factor, refined against A until the
             // normwise backward error |gbar - A zeta| / (|A| |zeta| + |gbar|) (max
             // norms) is at most adj_tol
             const auto F = G(S.af) + (int64_t)(n - S.af_step0) * S.af_size;
             const auto wsn = slot_ws(S, n - S.af_step0) + ws_anorm(S);
             const double anorm = wsn[0];
-            solve_A(S, F, gbar, T, Y, zeta, U);
+            __shared__ double part[kAdjWaves * 2 * 64];       // parts of split items
+            solve_A(S, F, gbar, T, Y, zeta, U, part);
             double gmax = 0.0;
             for (int i = threadIdx.x; i < 3 * m; i += (int)blockDim.x) gmax = fmax(gmax, fabs(gbar[i]));
             gmax = block_max(gmax, red);
@@ -1323,7 +1361,7 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
                 const bool finite = rmax == rmax && zmax == zmax && zmax < 1e300;
                 if (finite && !(rmax > S.adj_tol * (anorm * zmax + gmax))) { ok = true; break; }
                 if (k >= S.adj_max_iters || !finite) break;
-                solve_A(S, F, zeta1, T, Y, G(S.zt), U);
+                solve_A(S, F, zeta1, T, Y, G(S.zt), U, part);
                 for (int i = threadIdx.x; i < 3 * m; i += (int)blockDim.x) zeta[i] += G(S.zt)[i];
                 __syncthreads();
                 ++k;
@@ -1537,9 +1575,11 @@ hipError_t launch_forward(const SimDev *d_sims, int n, bool mixed, size_t lds, i
 
 hipError_t launch_backward(const SimDev *d_sims, int n, bool mixed, size_t lds, int flags, hipStream_t st) {
     using F = void (*)(const SimDev *, int, size_t, hipStream_t);
-    static const F tab[2][4] = {{bwd_one<false, 0>, bwd_one<false, 1>, bwd_one<false, 2>, bwd_one<false, 3>},
-                                {bwd_one<true, 0>, bwd_one<true, 1>, bwd_one<true, 2>, bwd_one<true, 3>}};
-    tab[mixed ? 1 : 0][flags & 3](d_sims, n, lds, st);
+    static const F tab[2][8] = {{bwd_one<false, 0>, bwd_one<false, 1>, bwd_one<false, 2>, bwd_one<false, 3>,
+                                 bwd_one<false, 4>, bwd_one<false, 5>, bwd_one<false, 6>, bwd_one<false, 7>},
+                                {bwd_one<true, 0>, bwd_one<true, 1>, bwd_one<true, 2>, bwd_one<true, 3>,
+                                 bwd_one<true, 4>, bwd_one<true, 5>, bwd_one<true, 6>, bwd_one<true, 7>}};
+    tab[mixed ? 1 : 0][flags & 7](d_sims, n, lds, st);
     return hipGetLastError();
 }
 
@@ -1562,7 +1602,9 @@ hipError_t configure_lds(size_t fwd_bytes, size_t bwd_bytes) {
     DC_SETF(true, 0) DC_SETF(true, 1) DC_SETF(true, 2) DC_SETF(true, 3)
     DC_SETF(true, 4) DC_SETF(true, 5) DC_SETF(true, 6) DC_SETF(true, 7)
     DC_SETB(false, 0) DC_SETB(false, 1) DC_SETB(false, 2) DC_SETB(false, 3)
+    DC_SETB(false, 4) DC_SETB(false, 5) DC_SETB(false, 6) DC_SETB(false, 7)
     DC_SETB(true, 0) DC_SETB(true, 1) DC_SETB(true, 2) DC_SETB(true, 3)
+    DC_SETB(true, 4) DC_SETB(true, 5) DC_SETB(true, 6) DC_SETB(true, 7)
 #undef DC_SETF
 #undef DC_SETB
     return e;
@@ -1576,7 +1618,9 @@ hipError_t kernel_static_lds(size_t *fwd, size_t *bwd) {
     const void *fk[] = {(const void *)k_forward<false, 0>, (const void *)k_forward<false, 7>,
                         (const void *)k_forward<true, 0>, (const void *)k_forward<true, 7>};
     const void *bk[] = {(const void *)k_backward<false, 0>, (const void *)k_backward<false, 3>,
-                        (const void *)k_backward<true, 0>, (const void *)k_backward<true, 3>};
+                        (const void *)k_backward<true, 0>, (const void *)k_backward<true, 3>,
+                        (const void *)k_backward<false, 4>, (const void *)k_backward<false, 7>,
+                        (const void *)k_backward<true, 4>, (const void *)k_backward<true, 7>};
     for (const void *f : fk) {
         hipError_t e = hipFuncGetAttributes(&a, f);
         if (e != hipSuccess) return e;

@@ -12,6 +12,10 @@ constexpr int kMaxObstacles = 8;
 constexpr int kBlock = 1024;         // threads per workgroup of the forward kernel (16 wavefronts)
 constexpr int kBlockAdj = 1024;      // threads per workgroup of the adjoint kernel
 constexpr int kSolveBatch = 8;      // loads per lane in flight in the triangular solves of P
+// Variant bits of the persistent kernels: what the host placed in LDS and, for
+// the adjoint kernel, the adjoint solver (the bit value 4 means kLdsPositions
+// in the forward kernel and kAdjDirect in the adjoint kernel).
+constexpr int kLdsVectors = 1, kLdsUpdates = 2, kLdsPositions = 4, kAdjDirect = 4;
 constexpr int kTeam = 8;             // lanes cooperating on one solve row / column
 constexpr int kKryM = 60;            // GMRES restart length of the adjoint fallback
 
@@ -48,9 +52,21 @@ struct SpringInc {          // node-centred spring projection: one incident spri
     double rho, w;          // rest length and weight
 };
 
-struct LuItem {             // direct adjoint solve: rows [a, a + 64) of a block of supernode s
-    int32_t s, a;
+// Direct adjoint solve: one product y = M v with a column-major block M of a
+// step factor, rows [a, a + nrow) (a wavefront, a row per lane).  A phase of
+// the solve (one level, one kind of block) is a list of such items; its
+// 16-column batches are split evenly over the wavefronts of the workgroup.
+struct AdjItem {
+    int64_t moff;           // offset of M(a, 0) in a step factor
+    int32_t ld;             // column stride of M
+    int32_t K;              // columns of M
+    int32_t vbase;          // first entry of v
+    int32_t obase;          // first output entry (row a)
+    int32_t nrow;           // rows of the item, <= 64
+    int32_t pad;
 };
+constexpr int kAdjBatch = 16;       // columns per unit of work (loads per lane in flight)
+constexpr int kAdjWaves = kBlockAdj / 64;
 struct LuUpd {              // supernode s is updated by descendant d: rows [i0, i1) of R_d lie in s
     int32_t d, i0, i1;
     int32_t map;            // offset in lu_relmap of the panel rows (in s) of R_d[i0..r_d)
@@ -171,10 +187,13 @@ struct SimDev {
     const int32_t *ks_ld;             // [nnz K_s] row stride there
     const int32_t *dp_ptr;            // [n_inc+1] per incidence entry (node i, constraint c):
     const int32_t *dp_ks;             //   K_s entry of (i, l) for each stencil node l of c
-    const int32_t *lu_lvl;            // [4*(levels+1)]: per level start of z items, u items, chunks, gathers
-    const LuItem *lu_zitems;          // row chunks of D_s^{-1} / V_s, grouped by level
-    const LuItem *lu_uitems;          // row chunks of B_s, grouped by level
-    const int32_t *lu_sn;             // supernodes grouped by level
+    const int32_t *lu_lvl;            // [2*(levels+1)]: per level start of its row gathers, x_R gathers
+    const GatherItem *lu_gat;         // backward: x_{R_t} copied into the update slots of chunk t
+    const AdjItem *adj_items;         // items of the phases (level l: 3l = D^{-1}, 3l+1 = B, 3l+2 = V)
+    const int32_t *adj_prog;          // [3 levels * kAdjWaves * 4] per phase and wavefront: first item,
+                                      //   first batch, last item, end batch (batches [.., end) of it)
+    const int32_t *adj_sptr;          // [3 levels + 1] into adj_split
+    const int32_t *adj_split;         // [4 per entry] item, first and last wavefront holding a part, 0
     int64_t af_size;                  // doubles per step factor
     int64_t af_ws_size;               // doubles of factorisation workspace per step
     int af_nmax;                      // largest N
