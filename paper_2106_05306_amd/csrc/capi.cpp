@@ -15,7 +15,8 @@
 
 namespace dc {
 hipError_t launch_forward(const SimDev *d_sims, int n, bool mixed, size_t lds, int flags, hipStream_t st);
-hipError_t launch_backward(const SimDev *d_sims, int n, bool mixed, size_t lds, int flags, hipStream_t st);
+hipError_t launch_backward(const SimDev *d_sims, int n, bool mixed, size_t lds, int flags, int helpers,
+                           hipStream_t st);
 hipError_t configure_lds(size_t fwd_bytes, size_t bwd_bytes);
 hipError_t kernel_static_lds(size_t *fwd, size_t *bwd);
 hipError_t launch_permute3(const double *in, double *out, const int32_t *perm, int m, bool to_caller, hipStream_t st);
@@ -91,6 +92,13 @@ int merge_cap_default() {
     const char *e = std::getenv("DIFFCLOTH_MERGE");
     const int v = e ? std::atoi(e) : -1;
     return v >= 0 && v <= 4096 ? v : 160;
+}
+
+// prefetch workgroups of a single-handle direct adjoint launch (0: none)
+int adj_helpers_default() {
+    const char *e = std::getenv("DIFFCLOTH_ADJ_HELPERS");
+    const int v = e ? std::atoi(e) : -1;
+    return v >= 0 && v <= 16 ? v : kAdjHelpers;
 }
 
 void *dev_alloc(sim *s, size_t bytes) {
@@ -647,6 +655,7 @@ void build_device(sim *s) {
         std::vector<RowItem> ri;
         std::vector<GatherItem> gat;
         std::vector<std::vector<AdjItem>> phase(3 * L);
+        std::vector<std::vector<int64_t>> pf(3 * L);          // blocks read by each phase (prefetch)
         s->lvl_sn.assign(L, {});
         s->lvl_nmax.assign(L, 3);
         for (int l = 0; l < L; ++l) {
@@ -667,6 +676,11 @@ void build_device(sim *s) {
                 for (int a = 0; a < R; a += 64)         // u_t = B_t z_t
                     phase[3 * l + 1].push_back(AdjItem{q.off + (int64_t)N * N + a, R, N, t0, q.uoff + a,
                                                        std::min(64, R - a), 0});
+                pf[3 * l].insert(pf[3 * l].end(), {q.off, (int64_t)N * N});
+                if (R > 0) {
+                    pf[3 * l + 1].insert(pf[3 * l + 1].end(), {q.off + (int64_t)N * N, (int64_t)N * R});
+                    pf[3 * l + 2].insert(pf[3 * l + 2].end(), {q.off + (int64_t)N * N + (int64_t)N * R, (int64_t)N * R});
+                }
             }
             lvl[2 * (l + 1)] = (int32_t)ri.size();
             lvl[2 * (l + 1) + 1] = (int32_t)gat.size();
@@ -674,6 +688,12 @@ void build_device(sim *s) {
         std::vector<AdjItem> aitems;
         std::vector<int32_t> aprog, asplit, asptr(1, 0);
         for (const auto &ph : phase) balance_phase(ph, aitems, aprog, asplit, asptr);
+        std::vector<int64_t> pfl;
+        std::vector<int32_t> pfptr(1, 0);
+        for (const auto &r : pf) {
+            pfl.insert(pfl.end(), r.begin(), r.end());
+            pfptr.push_back((int32_t)(pfl.size() / 2));
+        }
         D.ns = na;
         D.lu_nlevels = L;
         D.lu_sup = upload(s, ls);
@@ -691,6 +711,9 @@ void build_device(sim *s) {
         D.adj_prog = upload(s, aprog);
         D.adj_sptr = upload(s, asptr);
         D.adj_split = upload(s, asplit);
+        D.adj_pf = upload(s, pfl);
+        D.adj_pfptr = upload(s, pfptr);
+        D.adj_pos = zeros<int64_t>(s, 1);
         D.lu_rows = upload(s, ri);
         D.lu_upd_off = upload(s, auo);
         D.af_size = off;
@@ -1146,9 +1169,12 @@ int backward_range(sim *s, int a, int b) {
         const int lo = std::max(a, hi - W);
         s->hd.step_begin = lo;
         s->hd.step_end = hi;
+        ++s->hd.adj_epoch;                                   // tags this launch's published positions
         int rc = factor_steps(s, lo, hi);
         if (!rc) rc = push_desc(s);
-        if (!rc) rc = hip_err(launch_backward(s->dd, 1, s->hd.mixed != 0, s->lds_bwd, bwd_variant(s, s->flags_bwd), s->stream));
+        if (!rc)
+            rc = hip_err(launch_backward(s->dd, 1, s->hd.mixed != 0, s->lds_bwd, bwd_variant(s, s->flags_bwd),
+                                         s->hd.adj_direct ? adj_helpers_default() : 0, s->stream));
         if (rc) return rc;
         hi = lo;
     }
@@ -1262,7 +1288,7 @@ int sim_adjoint_step(sim_t *s, int32_t n, const double *gx_dev, const double *gv
         s->hd.rec_step0 = 0;
         if (!rc) rc = factor_steps(s, n, n + 1);
         if (!rc) rc = push_desc(s);
-        if (!rc) rc = hip_err(launch_backward(s->dd, 1, s->hd.mixed != 0, s->lds_bwd, bwd_variant(s, s->flags_bwd), s->stream));
+        if (!rc) rc = hip_err(launch_backward(s->dd, 1, s->hd.mixed != 0, s->lds_bwd, bwd_variant(s, s->flags_bwd), 0, s->stream));
         if (!rc && dx_dev) rc = hip_err(launch_permute3(s->hd.gx, dx_dev, s->d_perm, m, true, s->stream));
         if (!rc && dv_dev) rc = hip_err(launch_permute3(s->hd.gv, dv_dev, s->d_perm, m, true, s->stream));
         if (!rc && out) {
@@ -1418,7 +1444,7 @@ int sim_batch_backward(sim_t *const *sims, int32_t n, const double *const *dL_dx
         if (!rc && !work.empty()) rc = factor_pairs(s0, d, std::vector<sim *>(sims, sims + n), work, s0->stream);
         int fl = 0;
         const size_t lb = batch_lds(sims, n, false, fl);
-        if (!rc) rc = hip_err(launch_backward(d, n, s0->hd.mixed != 0, lb, bwd_variant(s0, fl), s0->stream));
+        if (!rc) rc = hip_err(launch_backward(d, n, s0->hd.mixed != 0, lb, bwd_variant(s0, fl), 0, s0->stream));
         int warn = SIM_OK;
         for (int i = 0; i < n && !rc; ++i) {
             if (out) rc = write_grads(sims[i], &out[i]);
@@ -1536,7 +1562,7 @@ int sim_batch_advance(sim_t *const *sims, int32_t n, const int32_t *steps, void 
             if (!pairs.empty()) rc = factor_pairs(bw[0], dbd, bw, pairs, sb);
             int fl = 0;
             const size_t lb = batch_lds(bw.data(), (int)bw.size(), false, fl);
-            if (!rc) rc = hip_err(launch_backward(dbd, (int)bw.size(), bw[0]->hd.mixed != 0, lb, bwd_variant(bw[0], fl), sb));
+            if (!rc) rc = hip_err(launch_backward(dbd, (int)bw.size(), bw[0]->hd.mixed != 0, lb, bwd_variant(bw[0], fl), 0, sb));
         }
         const int r1 = hip_err(hipStreamSynchronize(sf));
         const int r2 = hip_err(hipStreamSynchronize(sb));

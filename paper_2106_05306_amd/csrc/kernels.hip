@@ -8,6 +8,7 @@
 // the phases, so results do not depend on scheduling (no floating-point
 // atomics anywhere: every sum has a fixed order).
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 #include <cmath>
 #include <cstdint>
@@ -1164,8 +1165,25 @@ __global__ __launch_bounds__(kFacBlock) void k_adj_factor_level(const SimDev *__
 // an item finished inside the share is written at once, a part of an item
 // that spans several wavefronts goes to part[] and is summed, in wavefront
 // order, after the barrier.  OP 0: out = M v; OP 1: out = z - M v.
+constexpr int64_t kPosMask = (int64_t(1) << 40) - 1;      // position bits of adj_pos
+
+// lane j's value of x, for every lane (j wave-uniform)
+__device__ __forceinline__ double lane_value(double x, int j) {
+    const uint64_t u = (uint64_t)__double_as_longlong(x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, j);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), j);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// the solving workgroup announces the phase it starts (pos: step * phases + phase)
+__device__ __forceinline__ void publish_pos(const SimDev &S, int64_t pos) {
+    if (threadIdx.x == 0)
+        __hip_atomic_store(S.adj_pos, (S.adj_epoch << 40) | pos, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <int OP>
 __device__ __forceinline__ void adj_phase(const SimDev &S, int ph, auto F, auto v, auto z, auto out, double *part) {
+    constexpr bool kGlobalV = !std::is_same_v<decltype(v), double *>;   // v not in LDS
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const auto items = (GLOBAL const v4i *)S.adj_items;                 // AdjItem as 2 x 16 bytes
     const v4i pr = ((GLOBAL const v4i *)S.adj_prog)[ph * kAdjWaves + wave];
@@ -1184,6 +1202,10 @@ __device__ __forceinline__ void adj_phase(const SimDev &S, int ph, auto F, auto 
             const int k0 = kb * kAdjBatch;
             double c[kAdjBatch];
             if (k0 + kAdjBatch <= K) {                  // full batch: one predicate for all loads
+                // v in global memory: one load by lanes 0..15, broadcast from registers
+                double vl = 0.0;
+                if constexpr (kGlobalV)
+                    if (lane < kAdjBatch) vl = v[vb + k0 + lane];
                 if (live) {
 #pragma unroll
                     for (int j = 0; j < kAdjBatch; ++j) c[j] = col[(k0 + j) * ld];
@@ -1191,8 +1213,13 @@ __device__ __forceinline__ void adj_phase(const SimDev &S, int ph, auto F, auto 
 #pragma unroll
                     for (int j = 0; j < kAdjBatch; ++j) c[j] = 0.0;
                 }
+                if constexpr (kGlobalV) {
 #pragma unroll
-                for (int j = 0; j < kAdjBatch; ++j) acc += c[j] * v[vb + k0 + j];
+                    for (int j = 0; j < kAdjBatch; ++j) acc += c[j] * lane_value(vl, j);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < kAdjBatch; ++j) acc += c[j] * v[vb + k0 + j];
+                }
             } else {
 #pragma unroll
                 for (int j = 0; j < kAdjBatch; ++j) c[j] = live && k0 + j < K ? col[(k0 + j) * ld] : 0.0;
@@ -1232,10 +1259,12 @@ __device__ __forceinline__ void adj_phase(const SimDev &S, int ph, auto F, auto 
 // z_t = D_t^{-1} t_t, u_t = B_t z_t), backward sweep (gather x_{R_t},
 // x_t = z_t - V_t x_{R_t}).  T, Z, U: work vectors; part: 2 x 64 doubles per wavefront.
 __device__ __forceinline__ void solve_A(const SimDev &S, auto F, auto b, auto T, auto Z, auto x, auto U,
-                                        double *part) {
+                                        double *part, int64_t pos0) {
     const int tid = threadIdx.x, bd = blockDim.x;
     const auto lvl = G(S.lu_lvl);
-    for (int l = 0; l < S.lu_nlevels; ++l) {
+    const int L = S.lu_nlevels;
+    for (int l = 0; l < L; ++l) {
+        publish_pos(S, pos0 + 2 * l);
         for (int it = lvl[2 * l] + tid; it < lvl[2 * (l + 1)]; it += bd) {
             const auto &ri = G(S.lu_rows)[it];
             double t0 = b[ri.i3], t1 = b[ri.i3 + 1], t2 = b[ri.i3 + 2];
@@ -1247,9 +1276,11 @@ __device__ __forceinline__ void solve_A(const SimDev &S, auto F, auto b, auto T,
         }
         __syncthreads();
         adj_phase<0>(S, 3 * l, F, T, Z, Z, part);
+        publish_pos(S, pos0 + 2 * l + 1);
         adj_phase<0>(S, 3 * l + 1, F, Z, Z, U, part);
     }
-    for (int l = S.lu_nlevels - 1; l >= 0; --l) {
+    for (int l = L - 1; l >= 0; --l) {
+        publish_pos(S, pos0 + 2 * L + (L - 1 - l));
         const int q0 = lvl[2 * l + 1], q1 = lvl[2 * (l + 1) + 1];
         if (q1 > q0) {
             for (int q = q0 + tid; q < q1; q += bd) {
@@ -1262,8 +1293,69 @@ __device__ __forceinline__ void solve_A(const SimDev &S, auto F, auto b, auto T,
     }
 }
 
+// Helper workgroup j of H (same XCD as the solving workgroup): walks the
+// phases of the launch's steps in the solver's order and touches every
+// 128-byte line of the blocks a phase reads (one load per line, results
+// discarded), at most one phase ahead of the solver's published position.  It
+// only reads; it stops when the solver is done, or when no new position has
+// arrived for 100 ms.
+__device__ void adj_prefetch(const SimDev &S, int j, int H) {
+    __shared__ int go;
+    const int L = S.lu_nlevels, PH = 3 * L;
+    const int64_t stride = (int64_t)H * blockDim.x;
+    const int64_t me = (int64_t)j * blockDim.x + threadIdx.x;
+    uint64_t sink = 0;
+    for (int k = 0; k < S.step_end - S.step_begin; ++k) {
+        const int n = S.step_end - 1 - k;
+        const auto F = G(S.af) + (int64_t)(n - S.af_step0) * S.af_size;
+        for (int q = 0; q < PH; ++q) {
+            const int64_t target = (int64_t)k * PH + q;
+            if (threadIdx.x == 0) {
+                int state = 0;                                   // 0: give up, 1: go, 2: solver done
+                const uint64_t t0 = wall_clock64();
+                while (wall_clock64() - t0 < 10000000ull) {      // 100 ms at the 100 MHz wall clock
+                    const int64_t p = __hip_atomic_load(S.adj_pos, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if ((p >> 40) == S.adj_epoch) {
+                        if ((p & kPosMask) == kPosMask) { state = 2; break; }
+                        if ((p & kPosMask) + 1 >= target) { state = 1; break; }
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+                go = state;
+            }
+            __syncthreads();
+            const int st = go;
+            __syncthreads();
+            if (st != 1) {
+                if (sink == 0x9e3779b97f4a7c15ull) G(S.red)[63] = 1.0;   // keeps the loads
+                return;
+            }
+            const int ph = q < 2 * L ? 3 * (q >> 1) + (q & 1) : 3 * (L - 1 - (q - 2 * L)) + 2;
+            int64_t line0 = 0;                                   // first line of the range in the phase
+            for (int r = G(S.adj_pfptr)[ph]; r < G(S.adj_pfptr)[ph + 1]; ++r) {
+                const int64_t o = G(S.adj_pf)[2 * r], len = G(S.adj_pf)[2 * r + 1];
+                const int64_t nl = (len + 15) / 16;
+                int64_t i = (me - line0) % stride;               // lines i of the range with line0 + i = me mod stride
+                if (i < 0) i += stride;
+                for (; i < nl; i += stride) {
+                    sink ^= (uint64_t)__double_as_longlong(F[o + 16 * i]);
+                    if (i == nl - 1) sink ^= (uint64_t)__double_as_longlong(F[o + len - 1]);
+                }
+                line0 += nl;
+            }
+        }
+    }
+    if (sink == 0x9e3779b97f4a7c15ull) G(S.red)[63] = 1.0;
+}
+
 template <bool MIXED, int FL>
-__global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict__ sims) {
+__global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict__ sims, int helpers) {
+    if (helpers > 0 && blockIdx.x > 0) {                 // single-handle launch: prefetch helpers
+        if constexpr ((FL & kAdjDirect) != 0)
+            if (blockIdx.x % kXcds == 0 && blockIdx.x / kXcds <= helpers)
+                adj_prefetch(sims[0], blockIdx.x / kXcds - 1, helpers);
+        return;
+    }
     const SimDev &S = sims[blockIdx.x];
     extern __shared__ double dyn[];
     __shared__ double red[kBlock / 64];
@@ -1342,7 +1434,8 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
             const auto wsn = slot_ws(S, n - S.af_step0) + ws_anorm(S);
             const double anorm = wsn[0];
             __shared__ double part[kAdjWaves * 2 * 64];       // parts of split items
-            solve_A(S, F, gbar, T, Y, zeta, U, part);
+            const int64_t pos0 = (int64_t)(S.step_end - 1 - n) * 3 * S.lu_nlevels;
+            solve_A(S, F, gbar, T, Y, zeta, U, part, pos0);
             double gmax = 0.0;
             for (int i = threadIdx.x; i < 3 * m; i += (int)blockDim.x) gmax = fmax(gmax, fabs(gbar[i]));
             gmax = block_max(gmax, red);
@@ -1361,7 +1454,7 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
                 const bool finite = rmax == rmax && zmax == zmax && zmax < 1e300;
                 if (finite && !(rmax > S.adj_tol * (anorm * zmax + gmax))) { ok = true; break; }
                 if (k >= S.adj_max_iters || !finite) break;
-                solve_A(S, F, zeta1, T, Y, G(S.zt), U, part);
+                solve_A(S, F, zeta1, T, Y, G(S.zt), U, part, pos0);
                 for (int i = threadIdx.x; i < 3 * m; i += (int)blockDim.x) zeta[i] += G(S.zt)[i];
                 __syncthreads();
                 ++k;
@@ -1502,6 +1595,7 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
         G(S.counters)[4] += gm_total;
         G(S.counters)[5] += pert_total;
     }
+    if constexpr (direct) publish_pos(S, kPosMask);      // releases the prefetch helpers
 }
 
 // ------------------------------------------------------------------ small helper kernels
@@ -1558,8 +1652,10 @@ static void fwd_one(const SimDev *d, int n, size_t lds, hipStream_t st) {
     hipLaunchKernelGGL((k_forward<MIXED, FL>), dim3(n), dim3(kBlock), lds, st, d);
 }
 template <bool MIXED, int FL>
-static void bwd_one(const SimDev *d, int n, size_t lds, hipStream_t st) {
-    hipLaunchKernelGGL((k_backward<MIXED, FL>), dim3(n), dim3(kBlockAdj), lds, st, d);
+static void bwd_one(const SimDev *d, int n, size_t lds, int helpers, hipStream_t st) {
+    // helpers (n == 1 only): workgroups kXcds, 2 kXcds, ... share the solver's XCD; the rest exit at once
+    const int grid = helpers > 0 ? 1 + kXcds * helpers : n;
+    hipLaunchKernelGGL((k_backward<MIXED, FL>), dim3(grid), dim3(kBlockAdj), lds, st, d, helpers);
 }
 
 hipError_t launch_forward(const SimDev *d_sims, int n, bool mixed, size_t lds, int flags, hipStream_t st) {
@@ -1573,13 +1669,15 @@ hipError_t launch_forward(const SimDev *d_sims, int n, bool mixed, size_t lds, i
     return hipGetLastError();
 }
 
-hipError_t launch_backward(const SimDev *d_sims, int n, bool mixed, size_t lds, int flags, hipStream_t st) {
-    using F = void (*)(const SimDev *, int, size_t, hipStream_t);
+hipError_t launch_backward(const SimDev *d_sims, int n, bool mixed, size_t lds, int flags, int helpers,
+                           hipStream_t st) {
+    if (helpers > 0 && n != 1) return hipErrorInvalidValue;
+    using F = void (*)(const SimDev *, int, size_t, int, hipStream_t);
     static const F tab[2][8] = {{bwd_one<false, 0>, bwd_one<false, 1>, bwd_one<false, 2>, bwd_one<false, 3>,
                                  bwd_one<false, 4>, bwd_one<false, 5>, bwd_one<false, 6>, bwd_one<false, 7>},
                                 {bwd_one<true, 0>, bwd_one<true, 1>, bwd_one<true, 2>, bwd_one<true, 3>,
                                  bwd_one<true, 4>, bwd_one<true, 5>, bwd_one<true, 6>, bwd_one<true, 7>}};
-    tab[mixed ? 1 : 0][flags & 7](d_sims, n, lds, st);
+    tab[mixed ? 1 : 0][flags & 7](d_sims, n, lds, helpers, st);
     return hipGetLastError();
 }
 

@@ -67,6 +67,8 @@ struct AdjItem {
 };
 constexpr int kAdjBatch = 16;       // columns per unit of work (loads per lane in flight)
 constexpr int kAdjWaves = kBlockAdj / 64;
+constexpr int kAdjHelpers = 4;      // prefetching workgroups of a single-handle direct adjoint launch
+constexpr int kXcds = 8;            // workgroup i of a launch runs on XCD i mod 8
 struct LuUpd {              // supernode s is updated by descendant d: rows [i0, i1) of R_d lie in s
     int32_t d, i0, i1;
     int32_t map;            // offset in lu_relmap of the panel rows (in s) of R_d[i0..r_d)
@@ -200,6 +202,14 @@ struct SimDev {
     double *af;                       // step factors: slot k holds step af_step0 + k
     double *af_ws;                    // workspace per slot
     int af_step0;
+    // L2 prefetch of the step factors for a single-handle adjoint launch: the
+    // solving workgroup publishes its position (epoch << 40 | step * phases +
+    // phase, all ones below bit 40 when done); helper workgroups on its XCD
+    // touch the blocks of the next phase
+    int64_t *adj_pos;
+    int64_t adj_epoch;
+    const int32_t *adj_pfptr;         // [3 levels + 1] into adj_pf, by phase id
+    const int64_t *adj_pf;            // [2 per range] offset and length (doubles) of a block in a step factor
 
     // run control for one launch
     int step_begin, step_end;         // forward: steps [begin, end); backward: reverse
