@@ -290,25 +290,29 @@ void slot_weights(const HostModel &hm, const std::vector<int32_t> &corder, std::
 // Node-centred springs (active springs only): every node lists the springs
 // it ends, with the spring's other data inlined.
 void spring_incidence(const HostModel &hm, const std::vector<int32_t> &corder, int nca, std::vector<int32_t> &sp,
-                      std::vector<SpringInc> &sv, int &nca_bend) {
+                      std::vector<SpringInc> &sv, std::vector<double> &srho, int &nca_bend) {
     const int m = hm.m;
-    std::vector<std::vector<SpringInc>> sl(m);
+    std::vector<std::vector<std::pair<SpringInc, double>>> sl(m);
     nca_bend = 0;
     for (int c = 0; c < nca; ++c) {
         const int canon = corder[c];
         if (canon < hm.n_edges) {
             const int a = hm.iperm[hm.c_node[hm.c_ptr[canon]]], b = hm.iperm[hm.c_node[hm.c_ptr[canon] + 1]];
             const double w0 = hm.w[canon], r0 = hm.rho[canon];
-            sl[a].push_back(SpringInc{a, b, +1, c, r0, w0});
-            sl[b].push_back(SpringInc{a, b, -1, c, r0, w0});
+            sl[a].push_back({SpringInc{b, c, w0 * r0}, r0});
+            sl[b].push_back({SpringInc{a, ~c, w0 * r0}, r0});
         } else {
             ++nca_bend;
         }
     }
     sp.assign(1, 0);
     sv.clear();
+    srho.clear();
     for (int i = 0; i < m; ++i) {
-        sv.insert(sv.end(), sl[i].begin(), sl[i].end());
+        for (const auto &e : sl[i]) {
+            sv.push_back(e.first);
+            srho.push_back(e.second);
+        }
         sp.push_back((int32_t)sv.size());
     }
 }
@@ -514,10 +518,12 @@ void build_device(sim *s) {
     // node-centred springs and active curved-bending incidence
     std::vector<int32_t> sp;
     std::vector<SpringInc> sv;
+    std::vector<double> srho;
     int nca_bend = 0;
-    spring_incidence(hm, order, nca, sp, sv, nca_bend);
+    spring_incidence(hm, order, nca, sp, sv, srho, nca_bend);
     D.sinc_ptr = upload(s, sp);
     D.sinc = upload(s, sv);
+    D.sinc_rho = upload(s, srho);
     D.nca_bend = nca_bend;
     std::vector<int32_t> bp(1, 0), bc;
     std::vector<double> bcf;
@@ -969,7 +975,8 @@ int sim_set_material(sim_t *s, const double *edge_stiffness, const double *bend_
             ks_new_order(nm, kp, kc, kv, kvf);
             slot_weights(nm, s->corder, cw, cwf);
             int nca_bend = 0;
-            spring_incidence(nm, s->corder, s->nca, sp, sv, nca_bend);
+            std::vector<double> srho;
+            spring_incidence(nm, s->corder, s->nca, sp, sv, srho, nca_bend);
             stacked_factor(nm, gval, gvalt, goff);
             auto put = [&](const void *dst, const void *src, size_t bytes) {
                 if (!rc && bytes)
@@ -980,6 +987,7 @@ int sim_set_material(sim_t *s, const double *edge_stiffness, const double *bend_
             put(D.c_w, cw.data(), cw.size() * sizeof(double));
             put(D.c_wf, cwf.data(), cwf.size() * sizeof(float));
             put(D.sinc, sv.data(), sv.size() * sizeof(SpringInc));
+            put(D.sinc_rho, srho.data(), srho.size() * sizeof(double));
             put(D.gval, gval.data(), gval.size() * sizeof(double));
             put(D.gvalt, gvalt.data(), gvalt.size() * sizeof(double));
             put(s->d_basew, nm.base_w.data(), nm.base_w.size() * sizeof(double));

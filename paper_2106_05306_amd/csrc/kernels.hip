@@ -79,6 +79,34 @@ __device__ inline double block_sum(double v, double *red) {
 // Work items are packed descriptors; the host picks the lanes per item of each
 // level.  T, Y and the update buffer U live in LDS when they fit.  b may alias
 // T; x may alias T (T is dead once a level's products are formed).
+// Forward-solve gather of one level: t_i = b_i - (the update entries reaching
+// row i, in list order), a row per thread; four update offsets and their
+// entries are loaded before the subtractions.
+__device__ __forceinline__ void gather_rows(GLOBAL const RowItem *rows, GLOBAL const int32_t *upd, int r0, int r1,
+                                            auto b, auto T, auto U) {
+    for (int t = r0 + (int)threadIdx.x; t < r1; t += (int)blockDim.x) {
+        const auto &it = rows[t];
+        const int i3 = it.i3, p1 = it.p1;
+        double a0 = b[i3], a1 = b[i3 + 1], a2 = b[i3 + 2];
+        int p = it.p0;
+        for (; p + 4 <= p1; p += 4) {
+            int o[4];
+            double u[4][3];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) o[j] = upd[p + j];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) { u[j][0] = U[o[j]]; u[j][1] = U[o[j] + 1]; u[j][2] = U[o[j] + 2]; }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) { a0 -= u[j][0]; a1 -= u[j][1]; a2 -= u[j][2]; }
+        }
+        for (; p < p1; ++p) {
+            const int o = upd[p];
+            a0 -= U[o]; a1 -= U[o + 1]; a2 -= U[o + 2];
+        }
+        T[i3] = a0; T[i3 + 1] = a1; T[i3 + 2] = a2;
+    }
+}
+
 __device__ __forceinline__ void solve_P(const SimDev &S, auto b, auto T, auto Y, auto x, auto U) {
     const auto gval = G(S.gval);
     for (int l = 0; l < S.n_levels; ++l) {
@@ -90,16 +118,7 @@ __device__ __forceinline__ void solve_P(const SimDev &S, auto b, auto T, auto Y,
         const auto fit = (GLOBAL const v4i *)S.fitems;  // FwdItem as 16 bytes
         v4i cur = {0, 0, 0, 0};
         if (i0 + team < i1) cur = fit[i0 + team];
-        const int r0 = G(S.lvl_rows_ptr)[l], r1 = G(S.lvl_rows_ptr)[l + 1];
-        for (int t = r0 + threadIdx.x; t < r1; t += (int)blockDim.x) {
-            const auto &it = G(S.rows)[t];
-            double a0 = b[it.i3], a1 = b[it.i3 + 1], a2 = b[it.i3 + 2];
-            for (int p = it.p0; p < it.p1; ++p) {
-                const int o = G(S.upd_off)[p];
-                a0 -= U[o]; a1 -= U[o + 1]; a2 -= U[o + 2];
-            }
-            T[it.i3] = a0; T[it.i3 + 1] = a1; T[it.i3 + 2] = a2;
-        }
+        gather_rows(G(S.rows), G(S.upd_off), G(S.lvl_rows_ptr)[l], G(S.lvl_rows_ptr)[l + 1], b, T, U);
         __syncthreads();
         for (int t = i0 + team; t < i1; t += nteams) {
             v4i nxt = {0, 0, 0, 0};            // next descriptor, in flight meanwhile
@@ -311,49 +330,50 @@ __device__ __forceinline__ void spring_rhs(const SimDev &S, auto XN, auto V, aut
     for (int i = threadIdx.x; i < S.m; i += (int)blockDim.x) {
         double r0 = 0, r1 = 0, r2 = 0;
         const int p0 = G(S.sinc_ptr)[i], p1 = G(S.sinc_ptr)[i + 1];
+        // q = (x_i + h v_i) - (x_j + h v_j) = sign (x_a - x_b) exactly, so the
+        // two nodes of a spring add exact negatives
+        const double y0 = XN[3 * i] + h * V[3 * i], y1 = XN[3 * i + 1] + h * V[3 * i + 1],
+                     y2 = XN[3 * i + 2] + h * V[3 * i + 2];
+        const auto rec = (GLOBAL const v4i *)S.sinc;       // SpringInc as 16 bytes
         for (int pb = p0; pb < p1; pb += 8) {
-            SpringInc spv[8];
+            v4i spv[8];
+            double rhov[8];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {                // independent record loads in flight
-                if (pb + j < p1) {
-                    const auto &g = G(S.sinc)[pb + j];
-                    spv[j].a = g.a; spv[j].b = g.b; spv[j].sign = g.sign; spv[j].pad = g.pad;
-                    spv[j].rho = g.rho; spv[j].w = g.w;
-                }
-            }
+            for (int j = 0; j < 8; ++j)                      // independent record loads in flight
+                if (pb + j < p1) { spv[j] = rec[pb + j]; rhov[j] = G(S.sinc_rho)[pb + j]; }
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 if (pb + j >= p1) break;
-                const SpringInc &sp = spv[j];
-                const double q0 = (XN[3 * sp.a] + h * V[3 * sp.a]) - (XN[3 * sp.b] + h * V[3 * sp.b]);
-                const double q1 = (XN[3 * sp.a + 1] + h * V[3 * sp.a + 1]) - (XN[3 * sp.b + 1] + h * V[3 * sp.b + 1]);
-                const double q2 = (XN[3 * sp.a + 2] + h * V[3 * sp.a + 2]) - (XN[3 * sp.b + 2] + h * V[3 * sp.b + 2]);
+                const int nj = spv[j].x, cs = spv[j].y;
+                const double wr = __longlong_as_double(((long long)spv[j].w << 32) | (uint32_t)spv[j].z);
+                const double q0 = y0 - (XN[3 * nj] + h * V[3 * nj]);
+                const double q1 = y1 - (XN[3 * nj + 1] + h * V[3 * nj + 1]);
+                const double q2 = y2 - (XN[3 * nj + 2] + h * V[3 * nj + 2]);
                 double p0v, p1v, p2v;
                 if (MIXED) {
                     const float f0 = (float)q0, f1 = (float)q1, f2 = (float)q2;
                     const float nq = sqrtf(f0 * f0 + f1 * f1 + f2 * f2);
-                    const float rho = (float)sp.rho, w = (float)sp.w;
-                    float g0, g1, g2;
-                    if (nq < 1e-12f * rho) {
-                        const auto rd = G(S.c_restdir) + 3 * sp.pad;
-                        g0 = rho * (float)rd[0]; g1 = rho * (float)rd[1]; g2 = rho * (float)rd[2];
+                    const float wrf = (float)wr;
+                    if (nq < 1e-12f * (float)rhov[j]) {
+                        const auto rd = G(S.c_restdir) + 3 * (cs >= 0 ? cs : ~cs);
+                        const float sg = cs >= 0 ? wrf : -wrf;
+                        p0v = (double)(sg * (float)rd[0]); p1v = (double)(sg * (float)rd[1]); p2v = (double)(sg * (float)rd[2]);
                     } else {
-                        const float sc = rho / nq;
-                        g0 = sc * f0; g1 = sc * f1; g2 = sc * f2;
+                        const float sc = wrf / nq;
+                        p0v = (double)(sc * f0); p1v = (double)(sc * f1); p2v = (double)(sc * f2);
                     }
-                    p0v = (double)(w * g0); p1v = (double)(w * g1); p2v = (double)(w * g2);
                 } else {
                     const double nq = sqrt(q0 * q0 + q1 * q1 + q2 * q2);
-                    if (nq < 1e-12 * sp.rho) {
-                        const auto rd = G(S.c_restdir) + 3 * sp.pad;
-                        p0v = sp.w * sp.rho * rd[0]; p1v = sp.w * sp.rho * rd[1]; p2v = sp.w * sp.rho * rd[2];
+                    if (nq < 1e-12 * rhov[j]) {
+                        const auto rd = G(S.c_restdir) + 3 * (cs >= 0 ? cs : ~cs);
+                        const double sg = cs >= 0 ? wr : -wr;
+                        p0v = sg * rd[0]; p1v = sg * rd[1]; p2v = sg * rd[2];
                     } else {
-                        const double sc = sp.w * sp.rho / nq;
+                        const double sc = wr / nq;
                         p0v = sc * q0; p1v = sc * q1; p2v = sc * q2;
                     }
                 }
-                if (sp.sign > 0) { r0 += p0v; r1 += p1v; r2 += p2v; }
-                else { r0 -= p0v; r1 -= p1v; r2 -= p2v; }
+                r0 += p0v; r1 += p1v; r2 += p2v;
             }
         }
         if (bend) {
@@ -1265,15 +1285,7 @@ __device__ __forceinline__ void solve_A(const SimDev &S, auto F, auto b, auto T,
     const int L = S.lu_nlevels;
     for (int l = 0; l < L; ++l) {
         publish_pos(S, pos0 + 2 * l);
-        for (int it = lvl[2 * l] + tid; it < lvl[2 * (l + 1)]; it += bd) {
-            const auto &ri = G(S.lu_rows)[it];
-            double t0 = b[ri.i3], t1 = b[ri.i3 + 1], t2 = b[ri.i3 + 2];
-            for (int p = ri.p0; p < ri.p1; ++p) {
-                const int o = G(S.lu_upd_off)[p];
-                t0 -= U[o]; t1 -= U[o + 1]; t2 -= U[o + 2];
-            }
-            T[ri.i3] = t0; T[ri.i3 + 1] = t1; T[ri.i3 + 2] = t2;
-        }
+        gather_rows(G(S.lu_rows), G(S.lu_upd_off), lvl[2 * l], lvl[2 * (l + 1)], b, T, U);
         __syncthreads();
         adj_phase<0>(S, 3 * l, F, T, Z, Z, part);
         publish_pos(S, pos0 + 2 * l + 1);

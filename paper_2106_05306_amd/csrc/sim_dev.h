@@ -45,12 +45,12 @@ struct RowItem {            // forward gather: t_i = b_i - sum of update entries
     int32_t p0, p1;         // range in upd_off
     int32_t pad;
 };
-struct SpringInc {          // node-centred spring projection: one incident spring
-    int32_t a, b;           // endpoints (new ids), q = x_a - x_b
-    int32_t sign;           // +1 if this node is a, -1 if b
-    int32_t pad;
-    double rho, w;          // rest length and weight
+struct SpringInc {          // node-centred spring projection: one incident spring of node i
+    int32_t j;              // the other endpoint (new id)
+    int32_t cs;             // spring's constraint slot c if i is its first endpoint, else ~c
+    double wr;              // weight times rest length
 };
+static_assert(sizeof(SpringInc) == 16, "read as a 16-byte vector");
 
 // Direct adjoint solve: one product y = M v with a column-major block M of a
 // step factor, rows [a, a + nrow) (a wavefront, a row per lane).  A phase of
@@ -134,6 +134,7 @@ struct SimDev {
     // springs, node-centred (forward local step + RHS gather in one pass)
     const int32_t *sinc_ptr;          // [m+1]
     const SpringInc *sinc;
+    const double *sinc_rho;           // rest length of each incidence (degenerate-length test)
     int nca_bend;                     // active (curved) bending constraints: device indices [nca - nca_bend, nca)
     const int32_t *binc_ptr, *binc_con;   // node -> active bending constraint incidence
     const double *binc_coef;
