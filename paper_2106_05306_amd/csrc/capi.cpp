@@ -231,16 +231,19 @@ void ks_new_order(const HostModel &hm, std::vector<int32_t> &kp, std::vector<int
 }
 
 // Supernodal factor stacked per supernode as G_s = [L_ss^{-1}; B_s L_ss^{-1}]
-// (column-major (ns + nR) x ns, offset goff[s]) with B_s = L(R_s, s) the
-// off-diagonal block:
+// (ld = ns + nR rows, ns columns) with B_s = L(R_s, s) the off-diagonal block:
 //   forward  y_s = L_ss^{-1} t_s and u_s = B_s y_s = (B_s L_ss^{-1}) t_s in one product,
 //   backward x_s = L_ss^{-T} y_s - (B_s L_ss^{-1})^T x_{R_s}.
-// gvalt holds every block again, row-major, for the backward solve (a thread
-// per column reads consecutive addresses across the wavefront).
+// gval: column-major with the column stride rounded up to even (offset
+// goff[s]); gvalt: the same block row-major with the row stride rounded up to
+// even (offset gofft[s]).  Padding is zero; every block starts at an even
+// offset, so a lane reads two rows (gval) or two columns (gvalt) with one
+// 16-byte load.
 void stacked_factor(const HostModel &hm, std::vector<double> &gval, std::vector<double> &gvalt,
-                    std::vector<int64_t> &goff) {
+                    std::vector<int64_t> &goff, std::vector<int64_t> &gofft) {
     const int ns = hm.ns;
     goff.assign(ns, 0);
+    gofft.assign(ns, 0);
     gval.clear();
     for (int sn = 0; sn < ns; ++sn) {
         const int nsz = hm.sup_c0[sn + 1] - hm.sup_c0[sn];
@@ -254,25 +257,29 @@ void stacked_factor(const HostModel &hm, std::vector<double> &gval, std::vector<
                 inv[(size_t)i * nsz + j] = acc / F[(size_t)i * nrow + i];
             }
         }
+        const int ldp = nrow + (nrow & 1);
         goff[sn] = (int64_t)gval.size();
-        gval.resize(gval.size() + (size_t)nrow * nsz, 0.0);
+        gval.resize(gval.size() + (size_t)ldp * nsz, 0.0);
         double *G = gval.data() + goff[sn];
         for (int k = 0; k < nsz; ++k) {
-            for (int r = k; r < nsz; ++r) G[(size_t)k * nrow + r] = inv[(size_t)r * nsz + k];
+            for (int r = k; r < nsz; ++r) G[(size_t)k * ldp + r] = inv[(size_t)r * nsz + k];
             for (int q = 0; q < nR; ++q) {
                 double acc = 0.0;
                 for (int j = k; j < nsz; ++j) acc += F[(size_t)j * nrow + nsz + q] * inv[(size_t)j * nsz + k];
-                G[(size_t)k * nrow + nsz + q] = acc;
+                G[(size_t)k * ldp + nsz + q] = acc;
             }
         }
     }
-    gvalt.assign(gval.size(), 0.0);
+    gvalt.clear();
     for (int sn = 0; sn < ns; ++sn) {
         const int nsz = hm.sup_c0[sn + 1] - hm.sup_c0[sn], ld = nsz + hm.R_ptr[sn + 1] - hm.R_ptr[sn];
+        const int ldp = ld + (ld & 1), nszp = nsz + (nsz & 1);
+        gofft[sn] = (int64_t)gvalt.size();
+        gvalt.resize(gvalt.size() + (size_t)ld * nszp, 0.0);
         const double *G = gval.data() + goff[sn];
-        double *Gt = gvalt.data() + goff[sn];
+        double *Gt = gvalt.data() + gofft[sn];
         for (int k = 0; k < nsz; ++k)
-            for (int r = 0; r < ld; ++r) Gt[(size_t)r * nsz + k] = G[(size_t)k * ld + r];
+            for (int r = 0; r < ld; ++r) Gt[(size_t)r * nszp + k] = G[(size_t)k * ldp + r];
     }
 }
 
@@ -424,8 +431,8 @@ void build_device(sim *s) {
     // supernodal factor (stacked blocks) and the solve's update-vector layout
     const int ns = hm.ns;
     std::vector<double> gval, gvalt;
-    std::vector<int64_t> goff;
-    stacked_factor(hm, gval, gvalt, goff);
+    std::vector<int64_t> goff, gofft;
+    stacked_factor(hm, gval, gvalt, goff, gofft);
     std::vector<int32_t> sc0(ns), sns(ns), snr(ns), rptr(ns + 1, 0), rows, uoff(ns + 1, 0);
     for (int sn = 0; sn < ns; ++sn) {
         sc0[sn] = hm.sup_c0[sn];
@@ -444,10 +451,11 @@ void build_device(sim *s) {
         uo.insert(uo.end(), upd[i].begin(), upd[i].end());
         up.push_back((int32_t)uo.size());
     }
-    if (gval.size() >= (size_t)INT32_MAX || uoff[ns] >= INT32_MAX / 2) throw std::runtime_error("factor too large");
+    if (gval.size() >= (size_t)INT32_MAX || gvalt.size() >= (size_t)INT32_MAX || uoff[ns] >= INT32_MAX / 2)
+        throw std::runtime_error("factor too large");
     // level work lists (packed) and lanes per item
     std::vector<int32_t> lrp(hm.n_levels + 1, 0), lip(hm.n_levels + 1, 0), lgp(hm.n_levels + 1, 0),
-        team(2 * hm.n_levels, 1);
+        lbp(hm.n_levels + 1, 0), team(2 * hm.n_levels, 1);
     std::vector<RowItem> ritems;
     std::vector<BwdItem> bitems;
     std::vector<GatherItem> bgat;
@@ -470,27 +478,30 @@ void build_device(sim *s) {
             if (hm.sup_level[sn] != l) continue;
             const int c0 = sc0[sn], nsz = sns[sn], ld = nsz + snr[sn];
             if (ld >= 32768) throw std::runtime_error("supernode too large");
-            for (int k = 0; k < nsz; ++k) {
-                const int c = c0 + k;
-                ritems.push_back(RowItem{3 * c, up[c], up[c + 1], 0});
+            const int ldp = ld + (ld & 1), nszp = nsz + (nsz & 1);
+            for (int k = 0; k < nsz; ++k) ritems.push_back(RowItem{3 * (c0 + k), up[c0 + k], up[c0 + k + 1], 0});
+            for (int k = 0; k < nsz; k += 2) {          // columns k, k + 1
                 BwdItem b{};
-                b.g = (int32_t)(goff[sn] + (int64_t)k * nsz + k);
+                b.g = (int32_t)(gofft[sn] + (int64_t)k * nszp + k);
                 b.n1 = (int16_t)(nsz - k);
                 b.n2 = (int16_t)snr[sn];
-                b.ybase = 3 * c;
+                b.ybase = 3 * (c0 + k);
                 b.ubase = uoff[sn];
-                b.nsz = nsz;
+                b.st = nszp;
+                b.two = k + 1 < nsz;
                 bitems.push_back(b);
                 bmax = std::max(bmax, ld - k);
             }
             for (int q = 0; q < snr[sn]; ++q) bgat.push_back(GatherItem{uoff[sn] + 3 * q, 3 * rows[rptr[sn] + q]});
-            for (int r = 0; r < ld; ++r) {
+            auto out_of = [&](int r) { return r < nsz ? 3 * (c0 + r) : -(uoff[sn] + 3 * (r - nsz)) - 1; };
+            for (int r = 0; r < ld; r += 2) {           // rows r, r + 1
                 FwdItem f{};
                 f.g = (int32_t)(goff[sn] + r);
-                f.ld = (int16_t)ld;
-                f.kmax = (int16_t)(r < nsz ? r + 1 : nsz);
+                f.ld = (int16_t)ldp;
+                f.kmax = (int16_t)(r + 1 < nsz ? r + 2 : nsz);
                 f.tbase = 3 * c0;
-                f.out = r < nsz ? 3 * (c0 + r) : -(uoff[sn] + 3 * (r - nsz)) - 1;
+                f.out0 = out_of(r);
+                f.out1 = r + 1 < ld ? out_of(r + 1) : kNoOutput;
                 fitems.push_back(f);
                 fmax = std::max(fmax, (int)f.kmax);
             }
@@ -498,14 +509,16 @@ void build_device(sim *s) {
         lrp[l + 1] = (int32_t)ritems.size();
         lip[l + 1] = (int32_t)fitems.size();
         lgp[l + 1] = (int32_t)bgat.size();
+        lbp[l + 1] = (int32_t)bitems.size();
         team[2 * l] = pick_team(lip[l + 1] - lip[l], fmax);
-        team[2 * l + 1] = pick_team(lrp[l + 1] - lrp[l], bmax);
+        team[2 * l + 1] = pick_team(lbp[l + 1] - lbp[l], bmax);
     }
     D.n_levels = hm.n_levels;
     D.lvl_rows_ptr = upload(s, lrp);
     D.lvl_items_ptr = upload(s, lip);
     D.lvl_team = upload(s, team);
     D.lvl_gat_ptr = upload(s, lgp);
+    D.lvl_bwd_ptr = upload(s, lbp);
     D.bgat = upload(s, bgat);
     D.rows = upload(s, ritems);
     D.fitems = upload(s, fitems);
@@ -964,7 +977,7 @@ int sim_set_material(sim_t *s, const double *edge_stiffness, const double *bend_
         std::vector<int32_t> kp, kc, sp;
         std::vector<double> kv, cw, gval, gvalt;
         std::vector<float> kvf, cwf;
-        std::vector<int64_t> goff;
+        std::vector<int64_t> goff, gofft;
         std::vector<SpringInc> sv;
         int rc = SIM_OK;
         if (refactor) {
@@ -977,7 +990,7 @@ int sim_set_material(sim_t *s, const double *edge_stiffness, const double *bend_
             int nca_bend = 0;
             std::vector<double> srho;
             spring_incidence(nm, s->corder, s->nca, sp, sv, srho, nca_bend);
-            stacked_factor(nm, gval, gvalt, goff);
+            stacked_factor(nm, gval, gvalt, goff, gofft);
             auto put = [&](const void *dst, const void *src, size_t bytes) {
                 if (!rc && bytes)
                     rc = hip_err(hipMemcpyAsync(const_cast<void *>(dst), src, bytes, hipMemcpyHostToDevice, s->stream));

@@ -25,6 +25,7 @@ template <class T>
 __device__ __forceinline__ GLOBAL T *G(T *p) { return (GLOBAL T *)p; }
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v2i __attribute__((ext_vector_type(2)));
+typedef double v2d __attribute__((ext_vector_type(2)));
 // compile-time choice between an LDS and an HBM pointer (their types differ)
 template <bool C, class P, class Q>
 __device__ __forceinline__ auto pick(P a, Q b) {
@@ -107,60 +108,74 @@ __device__ __forceinline__ void gather_rows(GLOBAL const RowItem *rows, GLOBAL c
     }
 }
 
+// Writes the forward-solve result of one row: Y (diagonal-block rows) or the
+// update buffer (rows of B_s), or nothing for a padding row.
+__device__ __forceinline__ void put_row(int out, double a0, double a1, double a2, auto Y, auto U) {
+    if (out >= 0) {
+        Y[out] = a0; Y[out + 1] = a1; Y[out + 2] = a2;
+    } else if (out != kNoOutput) {
+        const int o = -out - 1;
+        U[o] = a0; U[o + 1] = a1; U[o + 2] = a2;
+    }
+}
+
 __device__ __forceinline__ void solve_P(const SimDev &S, auto b, auto T, auto Y, auto x, auto U) {
-    const auto gval = G(S.gval);
+    const auto gv2 = (GLOBAL const v2d *)S.gval;        // two rows per load
+    const auto gt2 = (GLOBAL const v2d *)S.gvalt;       // two columns per load
     for (int l = 0; l < S.n_levels; ++l) {
         // descriptor of this thread's first product item, fetched before the
         // gather phase and its barrier (it does not depend on the vectors)
         const int tl = G(S.lvl_team)[2 * l];
         const int team = threadIdx.x / tl, lane = threadIdx.x % tl, nteams = (int)blockDim.x / tl;
         const int i0 = G(S.lvl_items_ptr)[l], i1 = G(S.lvl_items_ptr)[l + 1];
-        const auto fit = (GLOBAL const v4i *)S.fitems;  // FwdItem as 16 bytes
-        v4i cur = {0, 0, 0, 0};
-        if (i0 + team < i1) cur = fit[i0 + team];
+        const auto fit = (GLOBAL const v4i *)S.fitems;  // FwdItem as 2 x 16 bytes
+        v4i cur = {0, 0, 0, 0}, cur2 = {0, 0, 0, 0};
+        if (i0 + team < i1) { cur = fit[2 * (i0 + team)]; cur2 = fit[2 * (i0 + team) + 1]; }
         gather_rows(G(S.rows), G(S.upd_off), G(S.lvl_rows_ptr)[l], G(S.lvl_rows_ptr)[l + 1], b, T, U);
         __syncthreads();
         for (int t = i0 + team; t < i1; t += nteams) {
-            v4i nxt = {0, 0, 0, 0};            // next descriptor, in flight meanwhile
-            if (t + nteams < i1) nxt = fit[t + nteams];
-            const auto Gb = gval + cur.x;
+            v4i nxt = {0, 0, 0, 0}, nxt2 = {0, 0, 0, 0};  // next descriptor, in flight meanwhile
+            if (t + nteams < i1) { nxt = fit[2 * (t + nteams)]; nxt2 = fit[2 * (t + nteams) + 1]; }
+            const auto Gb = gv2 + (cur.x >> 1);
             const auto Tb = T + cur.z;
-            const int ld = cur.y & 0xffff, kmax = cur.y >> 16, out = cur.w;
-            double a0 = 0, a1 = 0, a2 = 0;
+            const int ld2 = (cur.y & 0xffff) >> 1, kmax = cur.y >> 16;
+            double a0 = 0, a1 = 0, a2 = 0, b0 = 0, b1 = 0, b2 = 0;
             for (int k0 = lane; k0 < kmax; k0 += kSolveBatch * tl) {
-                double g[kSolveBatch];
+                v2d g[kSolveBatch];
 #pragma unroll
                 for (int j = 0; j < kSolveBatch; ++j) {           // kSolveBatch independent loads in flight
                     const int k = k0 + j * tl;
-                    g[j] = k < kmax ? Gb[k * ld] : 0.0;
+                    g[j] = k < kmax ? Gb[k * ld2] : v2d{0.0, 0.0};
                 }
 #pragma unroll
                 for (int j = 0; j < kSolveBatch; ++j) {
                     const int k = k0 + j * tl;
-                    if (k < kmax) { a0 += g[j] * Tb[3 * k]; a1 += g[j] * Tb[3 * k + 1]; a2 += g[j] * Tb[3 * k + 2]; }
+                    if (k < kmax) {
+                        const double t0 = Tb[3 * k], t1 = Tb[3 * k + 1], t2 = Tb[3 * k + 2];
+                        a0 += g[j].x * t0; a1 += g[j].x * t1; a2 += g[j].x * t2;
+                        b0 += g[j].y * t0; b1 += g[j].y * t1; b2 += g[j].y * t2;
+                    }
                 }
             }
             a0 = team_sum(a0, tl); a1 = team_sum(a1, tl); a2 = team_sum(a2, tl);
+            b0 = team_sum(b0, tl); b1 = team_sum(b1, tl); b2 = team_sum(b2, tl);
             if (lane == 0) {
-                if (out >= 0) {
-                    Y[out] = a0; Y[out + 1] = a1; Y[out + 2] = a2;
-                } else {
-                    const int o = -out - 1;
-                    U[o] = a0; U[o + 1] = a1; U[o + 2] = a2;
-                }
+                put_row(cur.w, a0, a1, a2, Y, U);
+                put_row(cur2.x, b0, b1, b2, Y, U);
             }
             cur = nxt;
+            cur2 = nxt2;
         }
         __syncthreads();
     }
     // backward: the update buffer is free; each level first gathers x_{R_s}
     // of its supernodes into their update slots, then forms
-    // x_s = L_ss^{-T} y_s - (B_s L_ss^{-1})^T x_{R_s}, one item per column of G_s
-    // (row-major copy: the items of a wavefront read consecutive addresses)
+    // x_s = L_ss^{-T} y_s - (B_s L_ss^{-1})^T x_{R_s}, one item per column pair
+    // of G_s (row-major copy: the items of a wavefront read consecutive addresses)
     for (int l = S.n_levels - 1; l >= 0; --l) {
         const int tl = G(S.lvl_team)[2 * l + 1];
         const int team = threadIdx.x / tl, lane = threadIdx.x % tl, nteams = (int)blockDim.x / tl;
-        const int c0 = G(S.lvl_rows_ptr)[l], c1 = G(S.lvl_rows_ptr)[l + 1];
+        const int c0 = G(S.lvl_bwd_ptr)[l], c1 = G(S.lvl_bwd_ptr)[l + 1];
         const auto bit = (GLOBAL const v4i *)S.bitems;  // BwdItem as 2 x 16 bytes
         v4i cur = {0, 0, 0, 0}, cur2 = {0, 0, 0, 0};
         if (c0 + team < c1) { cur = bit[2 * (c0 + team)]; cur2 = bit[2 * (c0 + team) + 1]; }
@@ -175,32 +190,40 @@ __device__ __forceinline__ void solve_P(const SimDev &S, auto b, auto T, auto Y,
         for (int t = c0 + team; t < c1; t += nteams) {
             v4i nxt = {0, 0, 0, 0}, nxt2 = {0, 0, 0, 0};
             if (t + nteams < c1) { nxt = bit[2 * (t + nteams)]; nxt2 = bit[2 * (t + nteams) + 1]; }
-            const auto Gb = G(S.gvalt) + cur.x;
-            const int64_t st = cur2.x;
+            const auto Gb = gt2 + (cur.x >> 1);
+            const int st2 = cur2.x >> 1;
             const int n1 = cur.y & 0xffff, n = n1 + (cur.y >> 16), yb = cur.z;
             const auto Yb = Y + yb;
             const int ub = cur.w - 3 * n1;               // U[ub + 3k] is row k >= n1
-            double a0 = 0, a1 = 0, a2 = 0;
+            double a0 = 0, a1 = 0, a2 = 0, b0 = 0, b1 = 0, b2 = 0;
             for (int k0 = lane; k0 < n; k0 += kSolveBatch * tl) {
-                double g[kSolveBatch];
+                v2d g[kSolveBatch];
 #pragma unroll
                 for (int j = 0; j < kSolveBatch; ++j) {
                     const int k = k0 + j * tl;
-                    g[j] = k < n ? Gb[k * st] : 0.0;
+                    g[j] = k < n ? Gb[k * st2] : v2d{0.0, 0.0};
                 }
 #pragma unroll
                 for (int j = 0; j < kSolveBatch; ++j) {
                     const int k = k0 + j * tl;
                     if (k < n1) {
-                        a0 += g[j] * Yb[3 * k]; a1 += g[j] * Yb[3 * k + 1]; a2 += g[j] * Yb[3 * k + 2];
+                        const double w0 = Yb[3 * k], w1 = Yb[3 * k + 1], w2 = Yb[3 * k + 2];
+                        a0 += g[j].x * w0; a1 += g[j].x * w1; a2 += g[j].x * w2;
+                        b0 += g[j].y * w0; b1 += g[j].y * w1; b2 += g[j].y * w2;
                     } else if (k < n) {
                         const int o = ub + 3 * k;
-                        a0 -= g[j] * U[o]; a1 -= g[j] * U[o + 1]; a2 -= g[j] * U[o + 2];
+                        const double w0 = U[o], w1 = U[o + 1], w2 = U[o + 2];
+                        a0 -= g[j].x * w0; a1 -= g[j].x * w1; a2 -= g[j].x * w2;
+                        b0 -= g[j].y * w0; b1 -= g[j].y * w1; b2 -= g[j].y * w2;
                     }
                 }
             }
             a0 = team_sum(a0, tl); a1 = team_sum(a1, tl); a2 = team_sum(a2, tl);
-            if (lane == 0) { x[yb] = a0; x[yb + 1] = a1; x[yb + 2] = a2; }
+            b0 = team_sum(b0, tl); b1 = team_sum(b1, tl); b2 = team_sum(b2, tl);
+            if (lane == 0) {
+                x[yb] = a0; x[yb + 1] = a1; x[yb + 2] = a2;
+                if (cur2.y) { x[yb + 3] = b0; x[yb + 4] = b1; x[yb + 5] = b2; }
+            }
             cur = nxt;
             cur2 = nxt2;
         }

@@ -11,7 +11,7 @@ namespace dc {
 constexpr int kMaxObstacles = 8;
 constexpr int kBlock = 1024;         // threads per workgroup of the forward kernel (16 wavefronts)
 constexpr int kBlockAdj = 1024;      // threads per workgroup of the adjoint kernel
-constexpr int kSolveBatch = 8;      // loads per lane in flight in the triangular solves of P
+constexpr int kSolveBatch = 4;      // 16-byte loads per lane in flight in the triangular solves of P
 // Variant bits of the persistent kernels: what the host placed in LDS and, for
 // the adjoint kernel, the adjoint solver (the bit value 4 means kLdsPositions
 // in the forward kernel and kAdjDirect in the adjoint kernel).
@@ -20,26 +20,30 @@ constexpr int kTeam = 8;             // lanes cooperating on one solve row / col
 constexpr int kKryM = 60;            // GMRES restart length of the adjoint fallback
 
 // Packed solve work items (shared host/device layout).
-struct FwdItem {            // forward: one row r of a stacked block G_s
-    int32_t g;              // offset of G_s[r, 0] in gval (column stride ld)
-    int16_t ld, kmax;       // column stride (ns + nR) and number of columns used
+constexpr int32_t kNoOutput = INT32_MIN;   // FwdItem.out1 of a padding row
+struct FwdItem {            // forward: rows r, r + 1 (r even) of a stacked block G_s
+    int32_t g;              // offset of G_s[r, 0] in gval (column stride ld, even)
+    int16_t ld, kmax;       // padded column stride and number of columns used
     int32_t tbase;          // 3 * c0: first right-hand-side entry of the supernode
-    int32_t out;            // >= 0: 3 * (c0 + r) in the forward result; < 0: -(ubuf offset) - 1
+    int32_t out0, out1;     // per row: >= 0: 3 * (c0 + r) in the forward result; < 0: -(ubuf offset) - 1;
+                            //   kNoOutput: padding row
+    int32_t pad[3];
 };
-struct BwdItem {            // backward: one column k of a stacked block G_s, rows k .. ld-1
-    int32_t g;              // offset of G_s[k, k] in gvalt (row-major copy, row stride nsz)
+struct BwdItem {            // backward: columns k, k + 1 (k even) of a stacked block G_s, rows k .. ld-1
+    int32_t g;              // offset of G_s[k, k] in gvalt (row-major copy, row stride st, even)
     int16_t n1, n2;         // rows k .. ns-1 (times y_s) and the nR rows of B_s (times x_{R_s})
     int32_t ybase;          // 3 * (c0 + k): y_s entry of row k and output entry of column k
     int32_t ubase;          // ubuf offset of the supernode: x_{R_s} is gathered there first
-    int32_t nsz;            // row stride of the row-major copy
-    int32_t pad[3];
+    int32_t st;             // row stride of the row-major copy
+    int32_t two;            // column k + 1 exists (else padding)
+    int32_t pad[2];
 };
 struct GatherItem {         // backward: x_{R_s} entry copied into the supernode's ubuf slot
     int32_t u;              // ubuf offset (3 doubles)
     int32_t x3;             // 3 * node
 };
 // the kernels read these descriptors as 16-byte / 8-byte vectors (field order as declared)
-static_assert(sizeof(FwdItem) == 16 && sizeof(BwdItem) == 32 && sizeof(GatherItem) == 8, "descriptor layout");
+static_assert(sizeof(FwdItem) == 32 && sizeof(BwdItem) == 32 && sizeof(GatherItem) == 8, "descriptor layout");
 struct RowItem {            // forward gather: t_i = b_i - sum of update entries
     int32_t i3;             // 3 * i
     int32_t p0, p1;         // range in upd_off
@@ -117,8 +121,9 @@ struct SimDev {
     // supernodal factor of P_s (new order): per supernode the stacked dense block
     // G_s = [L_ss^{-1}; B_s L_ss^{-1}], column-major (ns + nR) x ns
     int n_levels;
-    const int32_t *lvl_rows_ptr;      // [n_levels+1] into rows / bwd items (columns of each level)
+    const int32_t *lvl_rows_ptr;      // [n_levels+1] into rows (columns of each level)
     const int32_t *lvl_gat_ptr;       // [n_levels+1] into bgat
+    const int32_t *lvl_bwd_ptr;       // [n_levels+1] into bwd items (column pairs of each level)
     const int32_t *lvl_items_ptr;     // [n_levels+1] into fwd items
     const int32_t *lvl_team;          // [2*n_levels] lanes per item: forward, backward
     const RowItem *rows;
@@ -126,8 +131,8 @@ struct SimDev {
     const BwdItem *bitems;
     const GatherItem *bgat;
     const int32_t *sup_rows;          // off-diagonal row structure R_s (concatenated)
-    const double *gval;               // stacked blocks, column-major (forward)
-    const double *gvalt;              // the same blocks, row-major (backward)
+    const double *gval;               // stacked blocks, column-major, even column stride (forward)
+    const double *gvalt;              // the same blocks, row-major, even row stride (backward)
     const int32_t *upd_off;           // ubuf offsets gathered by the forward solve
     double *ubuf;                     // update vectors u_s (3 per row of R_s), HBM copy
     int n_ubuf;                       // doubles in ubuf
