@@ -140,7 +140,7 @@ T *zeros(sim *s, size_t n) {
     return d;
 }
 
-// Splits the 16-column batches of one phase of the direct adjoint solve into
+// Splits the kAdjBatch-column batches of one phase of the direct adjoint solve into
 // kAdjWaves contiguous runs of (nearly) equal length, in item order; a cut
 // inside an item moves to the item's boundary when that is at most one batch
 // away.  Appends the items, each wavefront's run (first item, first batch,
@@ -578,7 +578,9 @@ void build_device(sim *s) {
             ubuf_a += 3 * q.r;
             q.off = off;
             const int64_t N = 3 * (int64_t)q.n, R = 3 * (int64_t)q.r;
-            off += N * N + 2 * N * R;
+            q.ldn = (int32_t)(N + (N & 1));
+            q.ldr = (int32_t)(R + (R & 1));
+            off += N * q.ldn + N * q.ldr + R * q.ldn;
             nmax = std::max(nmax, (int)N);
         }
         if (nmax > 128) throw std::runtime_error("supernode chunk too large for the direct adjoint");
@@ -629,18 +631,18 @@ void build_device(sim *s) {
                 const int j = kc[e], ti = chunk_of[i], tj = chunk_of[j];
                 if (ti == tj) {
                     const LuSup &q = ls[ti];
-                    kdst[e] = q.off + (int64_t)3 * (j - q.c0) * 3 * q.n + 3 * (i - q.c0);
-                    kld[e] = 3 * q.n;
+                    kdst[e] = q.off + (int64_t)3 * (j - q.c0) * q.ldn + 3 * (i - q.c0);
+                    kld[e] = q.ldn;
                 } else if (tj < ti) {                   // lower: i in R_tj
                     const LuSup &q = ls[tj];
-                    const int64_t N = 3 * (int64_t)q.n, R = 3 * (int64_t)q.r;
-                    kdst[e] = q.off + N * N + (int64_t)3 * (j - q.c0) * R + 3 * pos_in_R(tj, i);
-                    kld[e] = (int32_t)R;
+                    const int64_t N = 3 * (int64_t)q.n;
+                    kdst[e] = q.off + N * q.ldn + (int64_t)3 * (j - q.c0) * q.ldr + 3 * pos_in_R(tj, i);
+                    kld[e] = q.ldr;
                 } else {                                // upper: j in R_ti
                     const LuSup &q = ls[ti];
-                    const int64_t N = 3 * (int64_t)q.n, R = 3 * (int64_t)q.r;
-                    kdst[e] = q.off + N * N + R * N + (int64_t)3 * pos_in_R(ti, j) * N + 3 * (i - q.c0);
-                    kld[e] = (int32_t)N;
+                    const int64_t N = 3 * (int64_t)q.n;
+                    kdst[e] = q.off + N * q.ldn + N * q.ldr + (int64_t)3 * pos_in_R(ti, j) * q.ldn + 3 * (i - q.c0);
+                    kld[e] = q.ldn;
                 }
             }
         }
@@ -686,19 +688,18 @@ void build_device(sim *s) {
                 s->lvl_nmax[l] = std::max(s->lvl_nmax[l], N);
                 for (int c = ac0[t]; c < ac0[t] + an[t]; ++c) ri.push_back(RowItem{3 * c, aup[c], aup[c + 1], 0});
                 for (int k = 0; k < q.r; ++k) gat.push_back(GatherItem{q.uoff + 3 * k, 3 * arows[q.rptr + k]});
-                for (int a = 0; a < N; a += 64) {       // z_t = D_t^{-1} t_t and x_t = z_t - V_t x_{R_t}
-                    const int nr = std::min(64, N - a);
-                    phase[3 * l].push_back(AdjItem{q.off + a, N, N, t0, t0 + a, nr, 0});
-                    phase[3 * l + 2].push_back(AdjItem{q.off + (int64_t)N * N + (int64_t)R * N + a, N, R, (int32_t)q.uoff,
-                                                       t0 + a, nr, 0});
+                const int64_t offB = q.off + (int64_t)N * q.ldn, offV = offB + (int64_t)N * q.ldr;
+                for (int a = 0; a < N; a += kAdjRows) {  // z_t = D_t^{-1} t_t and x_t = z_t - V_t x_{R_t}
+                    const int nr = std::min(kAdjRows, N - a);
+                    phase[3 * l].push_back(AdjItem{q.off + a, q.ldn, N, t0, t0 + a, nr, 0});
+                    phase[3 * l + 2].push_back(AdjItem{offV + a, q.ldn, R, (int32_t)q.uoff, t0 + a, nr, 0});
                 }
-                for (int a = 0; a < R; a += 64)         // u_t = B_t z_t
-                    phase[3 * l + 1].push_back(AdjItem{q.off + (int64_t)N * N + a, R, N, t0, q.uoff + a,
-                                                       std::min(64, R - a), 0});
-                pf[3 * l].insert(pf[3 * l].end(), {q.off, (int64_t)N * N});
+                for (int a = 0; a < R; a += kAdjRows)   // u_t = B_t z_t
+                    phase[3 * l + 1].push_back(AdjItem{offB + a, q.ldr, N, t0, q.uoff + a, std::min(kAdjRows, R - a), 0});
+                pf[3 * l].insert(pf[3 * l].end(), {q.off, (int64_t)N * q.ldn});
                 if (R > 0) {
-                    pf[3 * l + 1].insert(pf[3 * l + 1].end(), {q.off + (int64_t)N * N, (int64_t)N * R});
-                    pf[3 * l + 2].insert(pf[3 * l + 2].end(), {q.off + (int64_t)N * N + (int64_t)N * R, (int64_t)N * R});
+                    pf[3 * l + 1].insert(pf[3 * l + 1].end(), {offB, (int64_t)N * q.ldr});
+                    pf[3 * l + 2].insert(pf[3 * l + 2].end(), {offV, (int64_t)R * q.ldn});
                 }
             }
             lvl[2 * (l + 1)] = (int32_t)ri.size();

@@ -966,7 +966,7 @@ struct GjShared {
     int pk[kGjMax], inv[kGjMax];
 };
 template <int E>
-__device__ __forceinline__ int gj_inverse_regs(GLOBAL double *D, int N, GjShared *sh, double *red) {
+__device__ __forceinline__ int gj_inverse_regs(GLOBAL double *D, int N, int ld, GjShared *sh, double *red) {
     const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15, lane = tid & 63;
     double X[E][E];
     double dm = 0.0;
@@ -975,7 +975,7 @@ __device__ __forceinline__ int gj_inverse_regs(GLOBAL double *D, int N, GjShared
 #pragma unroll
         for (int b = 0; b < E; ++b) {
             const int i = ty + 16 * a, j = tx + 16 * b;
-            X[a][b] = (i < N && j < N) ? D[(int64_t)i * N + j] : 0.0;
+            X[a][b] = (i < N && j < N) ? D[(int64_t)i * ld + j] : 0.0;
             dm = fmax(dm, fabs(X[a][b]));
         }
     const double floor_ = 1e-13 * block_max(dm, red);
@@ -1046,7 +1046,7 @@ __device__ __forceinline__ int gj_inverse_regs(GLOBAL double *D, int N, GjShared
 #pragma unroll
         for (int b = 0; b < E; ++b) {
             const int i = ty + 16 * a, j = tx + 16 * b;
-            if (i < N && j < N) D[sh->inv[i] * N + sh->pk[j]] = X[a][b];
+            if (i < N && j < N) D[(int64_t)sh->inv[i] * ld + sh->pk[j]] = X[a][b];
         }
     __syncthreads();
     return pert;
@@ -1060,12 +1060,13 @@ __device__ __forceinline__ void schur_update(const SimDev &S, GLOBAL double *F, 
                                              double *tile) {
     const int tid = threadIdx.x;
     const auto &qd = G(S.lu_sup)[ud.d];
-    const int Nd = 3 * qd.n, Rd = 3 * qd.r, N = 3 * q.n, R = 3 * q.r, n = q.n;
-    const auto Bd = F + qd.off + (int64_t)Nd * Nd;          // Bt_d: Nd x Rd
-    const auto Vd = Bd + (int64_t)Rd * Nd;                  // Vt_d: Rd x Nd
+    const int Nd = 3 * qd.n, Rd = 3 * qd.r, N = 3 * q.n, n = q.n;
+    const int ldnd = qd.ldn, ldrd = qd.ldr, ldn = q.ldn, ldr = q.ldr;
+    const auto Bd = F + qd.off + (int64_t)Nd * ldnd;        // Bt_d: Nd x Rd (row stride ldrd)
+    const auto Vd = Bd + (int64_t)Nd * ldrd;                // Vt_d: Rd x Nd (row stride ldnd)
     const auto D = F + q.off;
-    const auto Bp = D + (int64_t)N * N;
-    const auto C = Bp + (int64_t)R * N;
+    const auto Bp = D + (int64_t)N * ldn;
+    const auto C = Bp + (int64_t)N * ldr;
     const auto rel = G(S.lu_relmap) + ud.map;
     const int a0 = 3 * ud.i0, a1 = 3 * ud.i1;
     double *ta = tile, *tb = tile + 16 * 64;                // ta[k][a], tb[k][b]
@@ -1081,9 +1082,9 @@ __device__ __forceinline__ void schur_update(const SimDev &S, GLOBAL double *F, 
             for (int k0 = 0; k0 < Nd; k0 += 16) {
                 for (int e = tid; e < 16 * 64; e += kFacBlock) {
                     const int kk = e >> 6, c = e & 63, k = k0 + kk;
-                    ta[e] = (k < Nd && at + c < Rd) ? Bd[(int64_t)k * Rd + at + c] : 0.0;
+                    ta[e] = (k < Nd && at + c < Rd) ? Bd[(int64_t)k * ldrd + at + c] : 0.0;
                     const int bb = e >> 4, k2 = k0 + (e & 15);
-                    tb[(e & 15) * 64 + bb] = (k2 < Nd && bt + bb < Rd) ? Vd[(int64_t)(bt + bb) * Nd + k2] : 0.0;
+                    tb[(e & 15) * 64 + bb] = (k2 < Nd && bt + bb < Rd) ? Vd[(int64_t)(bt + bb) * ldnd + k2] : 0.0;
                 }
                 __syncthreads();
 #pragma unroll 4
@@ -1109,10 +1110,10 @@ __device__ __forceinline__ void schur_update(const SimDev &S, GLOBAL double *F, 
                     const int ra = rel[aa / 3 - ud.i0], rb = rel[bb / 3 - ud.i0];
                     const int ca = aa % 3, cb = bb % 3;
                     if (bb < a1) {                          // column in s
-                        if (ra < n) D[(int64_t)(3 * rb + cb) * N + 3 * ra + ca] -= acc[i][j];
-                        else Bp[(int64_t)(3 * rb + cb) * R + 3 * (ra - n) + ca] -= acc[i][j];
+                        if (ra < n) D[(int64_t)(3 * rb + cb) * ldn + 3 * ra + ca] -= acc[i][j];
+                        else Bp[(int64_t)(3 * rb + cb) * ldr + 3 * (ra - n) + ca] -= acc[i][j];
                     } else {                                // row in s, column in R_s
-                        C[(int64_t)(3 * (rb - n) + cb) * N + 3 * ra + ca] -= acc[i][j];
+                        C[(int64_t)(3 * (rb - n) + cb) * ldn + 3 * ra + ca] -= acc[i][j];
                     }
                 }
         }
@@ -1122,7 +1123,8 @@ __device__ __forceinline__ void schur_update(const SimDev &S, GLOBAL double *F, 
 // the stored inverse (D^{-1})^T (N x N), in place over Ct: 64-row bands of Ct,
 // k in chunks of 16 staged in LDS (tile: 64 x 16 + 16 x 128 doubles), a 4 x 4
 // block of outputs per thread and column tile (N <= 128: two column tiles).
-__device__ __forceinline__ void v_product(GLOBAL double *C, GLOBAL const double *Dinv, int R, int N, double *tile) {
+__device__ __forceinline__ void v_product(GLOBAL double *C, GLOBAL const double *Dinv, int R, int N, int ld,
+                                          double *tile) {
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
     double *ta = tile, *tb = tile + 64 * 16;                // ta[k][j], tb[k][i]
     for (int jb = 0; jb < R; jb += 64) {
@@ -1136,11 +1138,11 @@ __device__ __forceinline__ void v_product(GLOBAL double *C, GLOBAL const double 
         for (int k0 = 0; k0 < N; k0 += 16) {
             for (int e = tid; e < 64 * 16; e += kFacBlock) {
                 const int jj = e >> 4, kk = e & 15;
-                ta[kk * 64 + jj] = (jb + jj < R && k0 + kk < N) ? C[(int64_t)(jb + jj) * N + k0 + kk] : 0.0;
+                ta[kk * 64 + jj] = (jb + jj < R && k0 + kk < N) ? C[(int64_t)(jb + jj) * ld + k0 + kk] : 0.0;
             }
             for (int e = tid; e < 16 * 128; e += kFacBlock) {
                 const int kk = e >> 7, ii = e & 127;
-                tb[e] = (k0 + kk < N && ii < N) ? Dinv[(int64_t)(k0 + kk) * N + ii] : 0.0;
+                tb[e] = (k0 + kk < N && ii < N) ? Dinv[(int64_t)(k0 + kk) * ld + ii] : 0.0;
             }
             __syncthreads();
 #pragma unroll 4
@@ -1168,7 +1170,7 @@ __device__ __forceinline__ void v_product(GLOBAL double *C, GLOBAL const double 
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int row = jb + 4 * ty + j, col = 64 * c + 4 * tx + i;
-                    if (row < R && col < N) C[(int64_t)row * N + col] = acc[c][j][i];
+                    if (row < R && col < N) C[(int64_t)row * ld + col] = acc[c][j][i];
                 }
         __syncthreads();
     }
@@ -1193,21 +1195,16 @@ __global__ __launch_bounds__(kFacBlock) void k_adj_factor_level(const SimDev *__
     const auto &q = G(S.lu_sup)[sn];
     const int N = 3 * q.n, R = 3 * q.r;
     const auto D = F + q.off;
-    const auto C = D + (int64_t)N * N + (int64_t)R * N;
+    const auto C = D + (int64_t)N * q.ldn + (int64_t)N * q.ldr;
     for (int u = G(S.lu_upd_ptr)[sn]; u < G(S.lu_upd_ptr)[sn + 1]; ++u) {
         schur_update(S, F, q, G(S.lu_upd)[u], tile);
         __syncthreads();
     }
-    const int pert = gj_inverse_regs<E>(D, N, &small, red);
-    if (R > 0) v_product(C, D, R, N, tile);
+    const int pert = gj_inverse_regs<E>(D, N, q.ldn, &small, red);
+    if (R > 0) v_product(C, D, R, N, q.ldn, tile);
     if (threadIdx.x == 0) ((GLOBAL int32_t *)(ws + ws_anorm(S) + 1))[sn] = pert;
 }
 
-// One phase of the direct adjoint solve (see AdjItem): every wavefront runs
-// its share of the 16-column batches, a row per lane, sixteen loads in flight;
-// an item finished inside the share is written at once, a part of an item
-// that spans several wavefronts goes to part[] and is summed, in wavefront
-// order, after the barrier.  OP 0: out = M v; OP 1: out = z - M v.
 constexpr int64_t kPosMask = (int64_t(1) << 40) - 1;      // position bits of adj_pos
 
 // lane j's value of x, for every lane (j wave-uniform)
@@ -1224,57 +1221,73 @@ __device__ __forceinline__ void publish_pos(const SimDev &S, int64_t pos) {
         __hip_atomic_store(S.adj_pos, (S.adj_epoch << 40) | pos, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// One phase of the direct adjoint solve (see AdjItem): every wavefront runs
+// its share of the kAdjBatch-column batches, rows 2 lane and 2 lane + 1 per
+// lane (one 16-byte load per column); an item finished inside the share is
+// written at once, a part of an item that spans several wavefronts goes to
+// part[] and is summed, in wavefront order, after the barrier.
+// OP 0: out = M v; OP 1: out = z - M v.
 template <int OP>
 __device__ __forceinline__ void adj_phase(const SimDev &S, int ph, auto F, auto v, auto z, auto out, double *part) {
     constexpr bool kGlobalV = !std::is_same_v<decltype(v), double *>;   // v not in LDS
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, r0 = 2 * lane;
     const auto items = (GLOBAL const v4i *)S.adj_items;                 // AdjItem as 2 x 16 bytes
+    const auto F2 = (GLOBAL const v2d *)F;                               // step factors: even offsets
     const v4i pr = ((GLOBAL const v4i *)S.adj_prog)[ph * kAdjWaves + wave];
     int i = pr.x, kb = pr.y;
     while (i < pr.z || (i == pr.z && kb < pr.w)) {
         const v4i d0 = items[2 * i], d1 = items[2 * i + 1];
         const int64_t moff = (int64_t)(uint32_t)d0.x | ((int64_t)d0.y << 32);
-        const int ld = d0.z, K = d0.w, vb = d1.x, ob = d1.y, nrow = d1.z;
+        const int ld2 = d0.z >> 1, K = d0.w, vb = d1.x, ob = d1.y, nrow = d1.z;
         const int nkb = K > 0 ? (K + kAdjBatch - 1) / kAdjBatch : 1;
         const int kend = i == pr.z ? pr.w : nkb;
         const bool whole = kb == 0 && kend == nkb;
-        const auto col = F + moff + lane;
-        double acc = 0.0;
-        const bool live = lane < nrow;
+        const auto col = F2 + ((moff >> 1) + lane);
+        const bool live = r0 < nrow;
+        double acc0 = 0.0, acc1 = 0.0;
         for (; kb < kend; ++kb) {
             const int k0 = kb * kAdjBatch;
-            double c[kAdjBatch];
+            v2d c[kAdjBatch];
             if (k0 + kAdjBatch <= K) {                  // full batch: one predicate for all loads
-                // v in global memory: one load by lanes 0..15, broadcast from registers
+                // v in global memory: one load by lanes 0..kAdjBatch-1, broadcast from registers
                 double vl = 0.0;
                 if constexpr (kGlobalV)
                     if (lane < kAdjBatch) vl = v[vb + k0 + lane];
                 if (live) {
 #pragma unroll
-                    for (int j = 0; j < kAdjBatch; ++j) c[j] = col[(k0 + j) * ld];
+                    for (int j = 0; j < kAdjBatch; ++j) c[j] = col[(k0 + j) * ld2];
                 } else {
 #pragma unroll
-                    for (int j = 0; j < kAdjBatch; ++j) c[j] = 0.0;
+                    for (int j = 0; j < kAdjBatch; ++j) c[j] = v2d{0.0, 0.0};
                 }
-                if constexpr (kGlobalV) {
 #pragma unroll
-                    for (int j = 0; j < kAdjBatch; ++j) acc += c[j] * lane_value(vl, j);
-                } else {
-#pragma unroll
-                    for (int j = 0; j < kAdjBatch; ++j) acc += c[j] * v[vb + k0 + j];
+                for (int j = 0; j < kAdjBatch; ++j) {
+                    double vj;
+                    if constexpr (kGlobalV) vj = lane_value(vl, j);
+                    else vj = v[vb + k0 + j];
+                    acc0 += c[j].x * vj;
+                    acc1 += c[j].y * vj;
                 }
             } else {
 #pragma unroll
-                for (int j = 0; j < kAdjBatch; ++j) c[j] = live && k0 + j < K ? col[(k0 + j) * ld] : 0.0;
+                for (int j = 0; j < kAdjBatch; ++j)
+                    c[j] = live && k0 + j < K ? col[(k0 + j) * ld2] : v2d{0.0, 0.0};
 #pragma unroll
                 for (int j = 0; j < kAdjBatch; ++j)
-                    if (k0 + j < K) acc += c[j] * v[vb + k0 + j];
+                    if (k0 + j < K) {
+                        const double vj = v[vb + k0 + j];
+                        acc0 += c[j].x * vj;
+                        acc1 += c[j].y * vj;
+                    }
             }
         }
         if (whole) {
-            if (lane < nrow) out[ob + lane] = OP == 0 ? acc : z[ob + lane] - acc;
+            if (r0 < nrow) out[ob + r0] = OP == 0 ? acc0 : z[ob + r0] - acc0;
+            if (r0 + 1 < nrow) out[ob + r0 + 1] = OP == 0 ? acc1 : z[ob + r0 + 1] - acc1;
         } else {
-            part[(2 * wave + (i == pr.x ? 0 : 1)) * 64 + lane] = acc;
+            const int o = (2 * wave + (i == pr.x ? 0 : 1)) * kAdjRows + r0;
+            part[o] = acc0;
+            part[o + 1] = acc1;
         }
         ++i;
         kb = 0;
@@ -1285,14 +1298,17 @@ __device__ __forceinline__ void adj_phase(const SimDev &S, int ph, auto F, auto 
         for (int e = s0 + wave; e < s1; e += kAdjWaves) {
             const v4i sp = ((GLOBAL const v4i *)S.adj_split)[e];
             const v4i d1 = items[2 * sp.x + 1];
-            double acc = 0.0;
+            double acc0 = 0.0, acc1 = 0.0;
             for (int w = sp.y; w <= sp.z; ++w) {
                 const v4i pw = ((GLOBAL const v4i *)S.adj_prog)[ph * kAdjWaves + w];
                 if (pw.x == pw.z && pw.y == pw.w) continue;          // empty run: no part
-                acc += part[(2 * w + (sp.x == pw.x ? 0 : 1)) * 64 + lane];
+                const int o = (2 * w + (sp.x == pw.x ? 0 : 1)) * kAdjRows + r0;
+                acc0 += part[o];
+                acc1 += part[o + 1];
             }
-            const int ob = d1.y;
-            if (lane < d1.z) out[ob + lane] = OP == 0 ? acc : z[ob + lane] - acc;
+            const int ob = d1.y, nrow = d1.z;
+            if (r0 < nrow) out[ob + r0] = OP == 0 ? acc0 : z[ob + r0] - acc0;
+            if (r0 + 1 < nrow) out[ob + r0 + 1] = OP == 0 ? acc1 : z[ob + r0 + 1] - acc1;
         }
         __syncthreads();
     }
@@ -1300,7 +1316,7 @@ __device__ __forceinline__ void adj_phase(const SimDev &S, int ph, auto F, auto 
 
 // x = A^{-1} b with a step factor F: forward sweep by level (gather t_t,
 // z_t = D_t^{-1} t_t, u_t = B_t z_t), backward sweep (gather x_{R_t},
-// x_t = z_t - V_t x_{R_t}).  T, Z, U: work vectors; part: 2 x 64 doubles per wavefront.
+// x_t = z_t - V_t x_{R_t}).  T, Z, U: work vectors; part: 2 x kAdjRows doubles per wavefront.
 __device__ __forceinline__ void solve_A(const SimDev &S, auto F, auto b, auto T, auto Z, auto x, auto U,
                                         double *part, int64_t pos0) {
     const int tid = threadIdx.x, bd = blockDim.x;
@@ -1468,7 +1484,7 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
             const auto F = G(S.af) + (int64_t)(n - S.af_step0) * S.af_size;
             const auto wsn = slot_ws(S, n - S.af_step0) + ws_anorm(S);
             const double anorm = wsn[0];
-            __shared__ double part[kAdjWaves * 2 * 64];       // parts of split items
+            __shared__ double part[kAdjWaves * 2 * kAdjRows];  // parts of split items
             const int64_t pos0 = (int64_t)(S.step_end - 1 - n) * 3 * S.lu_nlevels;
             solve_A(S, F, gbar, T, Y, zeta, U, part, pos0);
             double gmax = 0.0;

@@ -57,19 +57,21 @@ struct SpringInc {          // node-centred spring projection: one incident spri
 static_assert(sizeof(SpringInc) == 16, "read as a 16-byte vector");
 
 // Direct adjoint solve: one product y = M v with a column-major block M of a
-// step factor, rows [a, a + nrow) (a wavefront, a row per lane).  A phase of
+// step factor, rows [a, a + nrow) (a wavefront, rows 2 lane and 2 lane + 1 per
+// lane; M's column stride and offset are even).  A phase of
 // the solve (one level, one kind of block) is a list of such items; its
-// 16-column batches are split evenly over the wavefronts of the workgroup.
+// kAdjBatch-column batches are split evenly over the wavefronts of the workgroup.
 struct AdjItem {
     int64_t moff;           // offset of M(a, 0) in a step factor
     int32_t ld;             // column stride of M
     int32_t K;              // columns of M
     int32_t vbase;          // first entry of v
     int32_t obase;          // first output entry (row a)
-    int32_t nrow;           // rows of the item, <= 64
+    int32_t nrow;           // rows of the item, <= kAdjRows
     int32_t pad;
 };
-constexpr int kAdjBatch = 16;       // columns per unit of work (loads per lane in flight)
+constexpr int kAdjBatch = 8;        // columns per unit of work (16-byte loads per lane in flight)
+constexpr int kAdjRows = 128;       // rows per item: two per lane, read with one 16-byte load
 constexpr int kAdjWaves = kBlockAdj / 64;
 constexpr int kAdjHelpers = 4;      // prefetching workgroups of a single-handle direct adjoint launch
 constexpr int kXcds = 8;            // workgroup i of a launch runs on XCD i mod 8
@@ -77,12 +79,15 @@ struct LuUpd {              // supernode s is updated by descendant d: rows [i0,
     int32_t d, i0, i1;
     int32_t map;            // offset in lu_relmap of the panel rows (in s) of R_d[i0..r_d)
 };
-struct LuSup {              // supernode data of the direct adjoint factor
+struct LuSup {              // supernode (chunk) data of the direct adjoint factor
     int32_t c0, n, r;       // first node, nodes, rows of R_s
     int32_t rptr;           // offset of R_s in sup_rows
     int32_t uoff;           // offset of u_s in the update buffer
+    int32_t ldn, ldr;       // N = 3n and R = 3r rounded up to even: the row strides below
     int32_t pad;
-    int64_t off;            // offset of [D_s^{-1}; B_s; V_s] in a step factor (doubles)
+    int64_t off;            // offset of the chunk's blocks in a step factor (doubles, even):
+                            //   Dt (N x ldn) at off, Bt (N x ldr) at off + N ldn,
+                            //   Ct / Vt (R x ldn) at off + N ldn + N ldr, all row-major
 };
 
 struct ObstacleDev {
