@@ -32,12 +32,17 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 KERNEL_SRC = os.path.join(ROOT, "paper_2106_05306_amd", "csrc", "kernels.hip")
+LAUNCH_SRC = os.path.join(ROOT, "paper_2106_05306_amd", "csrc", "capi.cpp")
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "sphere_drop40_pmc.txt")
 
 
 def source_hash():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the kernel source and the launch code (chunking, streams)."""
+    h = hashlib.sha256()
+    for path in (KERNEL_SRC, LAUNCH_SRC):
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_from_profile(kernel_name):
@@ -454,10 +459,13 @@ def main():
     adj_iters = st["adj_iters_total"] + st["adj_krylov_total"]
     fwd_b, bwd_b = algorithmic_bytes(st, sc.n_nodes, st["n_edges"], C_steps, fwd_iters / T, T, adj_iters,
                                      args.adj_solver == "direct")
+    # per launch: the forward pass runs as fwd_launches launches (chunks that
+    # overlap the step factorisations), the adjoint as one
     if bwd_ms > fwd_ms:
-        kname, nbytes, ms = "k_backward", bwd_b, bwd_ms
+        kname, launches, nbytes, ms = "k_backward", 1, bwd_b, bwd_ms
     else:
-        kname, nbytes, ms = "k_forward", fwd_b, fwd_ms
+        launches = max(1, int(fwd_stats.get("fwd_launches", 1)))
+        kname, nbytes, ms = "k_forward", fwd_b / launches, fwd_ms / launches
     achieved = nbytes / (ms * 1e-3) / 1e9
     traffic = traffic_from_profile(kname)
     value = args.steps * T / elapsed
@@ -484,9 +492,12 @@ def main():
                    "seed": 0},
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "algorithmic_bytes_per_launch": nbytes, "launch_ms": ms},
-        "timing_ms": {"forward_launch": fwd_ms, "backward_launch": bwd_ms,
-                      "note": "backward = step factorisations (direct adjoint) + the adjoint launch"},
+                     "traffic": traffic, "algorithmic_bytes_per_launch": nbytes, "launch_ms": ms,
+                     "launches_per_rollout": launches},
+        "timing_ms": {"forward": fwd_ms, "backward": bwd_ms,
+                      "note": "forward = the forward launches (the direct adjoint's step factorisations run "
+                              "meanwhile on a second stream, chunk by chunk); backward = the rest of the "
+                              "factorisations + the adjoint launch"},
         "gradient": ({"status": "ok", "dv0_norm": float(out["dv0"].norm()), "dx0_norm": float(out["dx0"].norm())}
                      if out["status"] != 3 else
                      {"status": "non-finite (SIM_WADJ_NONFINITE)",

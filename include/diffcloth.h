@@ -185,6 +185,10 @@ typedef struct {
     int64_t lds_forward, lds_backward; /* dynamic LDS per workgroup (0: vectors in HBM) */
     int64_t adj_factor_bytes;       /* direct adjoint: bytes of one step's factor */
     int64_t adj_pivot_perturbed;    /* direct adjoint: pivots raised to the floor in the last backward */
+    int32_t fwd_launches;           /* forward kernel launches of the last sim_forward (chunks
+                                       overlapped with the direct adjoint's step factorisations,
+                                       or checkpoint segments) */
+    int32_t pad;
 } sim_stats_t;
 
 typedef void *(*sim_alloc_fn)(size_t bytes, void *ctx);

@@ -56,7 +56,8 @@ class SimStats(Structure):
                 ("fwd_iters_total", c_int64), ("adj_iters_total", c_int64), ("adj_fallbacks", c_int32),
                 ("adj_noconv", c_int32), ("device_bytes", c_int64), ("adj_krylov_total", c_int64),
                 ("factor_bytes", c_int64), ("lds_forward", c_int64), ("lds_backward", c_int64),
-                ("adj_factor_bytes", c_int64), ("adj_pivot_perturbed", c_int64)]
+                ("adj_factor_bytes", c_int64), ("adj_pivot_perturbed", c_int64), ("fwd_launches", c_int32),
+                ("pad", c_int32)]
 
 
 ALLOC_FN = CFUNCTYPE(c_void_p, c_size_t, c_void_p)

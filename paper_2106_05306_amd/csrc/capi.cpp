@@ -67,6 +67,15 @@ struct sim {
     std::vector<int32_t> h_work;        // factorisation work lists (host copy)
     int32_t *d_work = nullptr;          // and their device copy
     size_t work_cap = 0;
+    // step factorisations overlapped with the forward pass (direct adjoint,
+    // no checkpoints, no adjoint window): a second stream factors each chunk
+    // of steps once the forward pass has recorded it
+    hipStream_t fac_stream = nullptr;
+    hipEvent_t fac_ev = nullptr, fac_done = nullptr;
+    SimDev hd_fac{};                    // descriptor the overlapped factorisation reads,
+    SimDev *dd_fac = nullptr;           //   and its device copy
+    int prefactored = 0;                // steps [0, prefactored) of the recorded rollout are factored
+    int fwd_launches = 0;               // forward launches of the last sim_forward
     std::vector<int32_t> corder;        // device constraint slot -> canonical constraint id
     int64_t factor_bytes = 0;
     size_t lds_fwd = 0, lds_bwd = 0;   // dynamic LDS of the two kernels
@@ -824,8 +833,11 @@ int push_desc(sim *s) {
 }
 
 // make room for `cap` step records
+int fac_idle(sim *s);
+
 void ensure_records(sim *s, int cap) {
     if (s->hd.rec_cap >= cap && s->hd.rec_x) return;
+    if (fac_idle(s)) throw std::runtime_error("hip");
     dev_release(s, s->hd.rec_x);
     dev_release(s, s->hd.rec_v);
     dev_release(s, s->hd.rec_ubar);
@@ -843,6 +855,7 @@ void ensure_records(sim *s, int cap) {
 // room for `cap` step factors of the direct adjoint
 void ensure_af(sim *s, int cap) {
     if (s->af_cap >= cap && s->hd.af) return;
+    if (fac_idle(s)) throw std::runtime_error("hip");
     dev_release(s, s->hd.af);
     dev_release(s, s->hd.af_ws);
     s->hd.af = nullptr;
@@ -858,6 +871,31 @@ int copy_d2d(sim *s, void *dst, const void *src, size_t bytes) {
 }
 
 int seg_len(const sim *s) { return s->hm.checkpoint_every > 0 ? s->hm.checkpoint_every : 0; }
+
+// Waits for the overlapped factorisation (before its buffers are released or
+// its factors are replaced) and forgets it.
+int fac_idle(sim *s) {
+    s->prefactored = 0;
+    return s->fac_stream ? hip_err(hipStreamSynchronize(s->fac_stream)) : SIM_OK;
+}
+
+// Forward chunks (end steps) when the factorisation overlaps the forward pass
+// (empty: no overlap).  Each chunk is half the steps left, down to 8: the
+// factorisation of a chunk (≈ 1/10 of its forward time) hides under the
+// next one, and only the last, short chunk's is left for the backward pass.
+std::vector<int> overlap_chunks(const sim *s, int n_steps) {
+    std::vector<int> ends;
+    if (!s->hd.adj_direct || seg_len(s) > 0 || s->hm.adj_window > 0 || n_steps < 16) return ends;
+    const char *e = std::getenv("DIFFCLOTH_FACTOR_OVERLAP");
+    if (e && std::atoi(e) == 0) return ends;
+    int a = 0;
+    while (n_steps - a > 8) {
+        a += std::max(4, (n_steps - a) / 2);
+        ends.push_back(a);
+    }
+    if (a < n_steps) ends.push_back(n_steps);
+    return ends;
+}
 
 // Forward over [a, b) from the handle's current state into the record buffer.
 int run_forward_range(sim *s, int a, int b) {
@@ -934,6 +972,7 @@ int sim_set_state(sim_t *s, const double *x0_dev, const double *v0_dev) {
     if (rc) return rc;
     s->T = -1;
     s->phase = 0;
+    s->prefactored = 0;
     return SIM_OK;
 }
 
@@ -980,7 +1019,8 @@ int sim_set_material(sim_t *s, const double *edge_stiffness, const double *bend_
         std::vector<float> kvf, cwf;
         std::vector<int64_t> goff, gofft;
         std::vector<SpringInc> sv;
-        int rc = SIM_OK;
+        int rc = fac_idle(s);                    // the overlapped factorisation reads these tables
+        if (rc) return rc;
         if (refactor) {
             nm.apply_regions();
             rc = nm.assemble_ks(true);
@@ -1024,6 +1064,7 @@ namespace {
 
 // Prepare a handle for a forward pass of n_steps (records / checkpoints) and reset its state.
 int prepare_forward(sim *s, int n_steps) {
+    if (fac_idle(s)) return SIM_EHIP;        // the records are about to be overwritten
     const int k = seg_len(s);
     const int cap = k > 0 ? std::min(k, n_steps) : n_steps;
     ensure_records(s, std::max(cap, 1));
@@ -1042,6 +1083,68 @@ int prepare_forward(sim *s, int n_steps) {
     return rc;
 }
 
+int factor_pairs(sim *owner, const SimDev *d_descs, const std::vector<sim *> &hs, const std::vector<int32_t> &pairs,
+                 hipStream_t st);
+
+// Forward pass in chunks (ending at ends[]) on the handle's stream; after each chunk
+// a second stream factors the chunk's steps (their records are complete once
+// the chunk has run), so only the last chunk's factorisation is left for the
+// backward pass.  Results are those of one launch (the kernel keeps no state
+// in LDS across steps).
+int forward_overlapped(sim *s, int n_steps, const std::vector<int> &ends) {
+    int rc = fac_idle(s);
+    if (rc) return rc;
+    if (!s->fac_stream) {
+        rc = hip_err(hipStreamCreateWithFlags(&s->fac_stream, hipStreamNonBlocking));
+        if (!rc) rc = hip_err(hipEventCreateWithFlags(&s->fac_ev, hipEventDisableTiming));
+        if (!rc) rc = hip_err(hipEventCreateWithFlags(&s->fac_done, hipEventDisableTiming));
+        if (!rc && !s->dd_fac) s->dd_fac = (SimDev *)dev_alloc(s, sizeof(SimDev));
+        if (rc) return rc;
+    }
+    ensure_af(s, n_steps);
+    {   // work buffer for the largest chunk, sized before any factorisation runs
+        int ch = ends[0];
+        for (size_t c = 1; c < ends.size(); ++c) ch = std::max(ch, ends[c] - ends[c - 1]);
+        size_t need = 2 * (size_t)ch;
+        for (const auto &l : s->lvl_sn) need += 3 * l.size() * (size_t)ch;
+        if (s->work_cap < need) {
+            dev_release(s, s->d_work);
+            s->d_work = (int32_t *)dev_alloc(s, need * sizeof(int32_t));
+            s->work_cap = need;
+        }
+    }
+    s->hd_fac = s->hd;                       // factor descriptor: slot k = step k, records from step 0
+    s->hd_fac.af_step0 = 0;
+    s->hd_fac.rec_step0 = 0;
+    rc = hip_err(hipMemcpyAsync(s->dd_fac, &s->hd_fac, sizeof(SimDev), hipMemcpyHostToDevice, s->stream));
+    int pa = -1, pb = -1;                    // chunk whose factorisation is still to be queued
+    for (size_t c = 0; c < ends.size() && !rc; ++c) {
+        const int a = c ? ends[c - 1] : 0, b = ends[c];
+        s->hd.step_begin = a;
+        s->hd.step_end = b;
+        s->hd.rec_step0 = 0;
+        rc = push_desc(s);
+        if (!rc) rc = hip_err(launch_forward(s->dd, 1, s->hd.mixed != 0, s->lds_fwd, s->flags_fwd, s->stream));
+        if (!rc && pa >= 0) {                // the previous chunk, queued behind this one's launch
+            std::vector<int32_t> pairs;
+            for (int n = pa; n < pb; ++n) { pairs.push_back(0); pairs.push_back(n); }
+            rc = factor_pairs(s, s->dd_fac, {s}, pairs, s->fac_stream);
+        }
+        if (!rc) rc = hip_err(hipEventRecord(s->fac_ev, s->stream));
+        if (!rc) rc = hip_err(hipStreamWaitEvent(s->fac_stream, s->fac_ev, 0));
+        pa = a;
+        pb = b;
+    }
+    if (!rc && pa >= 0) {
+        std::vector<int32_t> pairs;
+        for (int n = pa; n < pb; ++n) { pairs.push_back(0); pairs.push_back(n); }
+        rc = factor_pairs(s, s->dd_fac, {s}, pairs, s->fac_stream);
+    }
+    if (!rc) rc = hip_err(hipEventRecord(s->fac_done, s->fac_stream));
+    if (!rc) s->prefactored = n_steps;
+    return rc;
+}
+
 // Forward pass; with checkpointing, segment by segment (state saved at each segment start).
 int forward_all(sim *s, int n_steps, double *x_traj_dev) {
     const int m = s->hd.m;
@@ -1049,12 +1152,16 @@ int forward_all(sim *s, int n_steps, double *x_traj_dev) {
     const int k = seg_len(s);
     int rc = SIM_OK;
     if (k <= 0) {
-        rc = run_forward_range(s, 0, n_steps);
+        const std::vector<int> ends = overlap_chunks(s, n_steps);
+        s->fwd_launches = ends.empty() ? 1 : (int)ends.size();
+        if (!ends.empty()) rc = forward_overlapped(s, n_steps, ends);
+        else rc = run_forward_range(s, 0, n_steps);
         if (!rc && x_traj_dev)
             for (int n = 0; n <= n_steps && !rc; ++n)
                 rc = hip_err(launch_permute3(s->hd.rec_x + n * v3, x_traj_dev + n * v3, s->d_perm, m, true, s->stream));
         return rc;
     }
+    s->fwd_launches = (n_steps + k - 1) / k;
     for (int a = 0, seg = 0; a < n_steps && !rc; a += k, ++seg) {
         const int b = std::min(n_steps, a + k);
         rc = copy_d2d(s, s->ckpt + (size_t)seg * 2 * v3, s->hd.x, v3 * sizeof(double));
@@ -1173,6 +1280,12 @@ int factor_pairs(sim *owner, const SimDev *d_descs, const std::vector<sim *> &hs
 // Direct adjoint: factor steps [a, b) of one handle (records in place, rec_step0 set).
 int factor_steps(sim *s, int a, int b) {
     if (!s->hd.adj_direct) return SIM_OK;
+    if (a == 0 && s->prefactored > 0 && b == s->prefactored) {  // factored during the forward pass
+        s->hd.af_step0 = 0;
+        return hip_err(hipStreamWaitEvent(s->stream, s->fac_done, 0));
+    }
+    int rc0 = fac_idle(s);                   // these slots are about to be overwritten
+    if (rc0) return rc0;
     ensure_af(s, b - a);
     s->hd.af_step0 = a;
     int rc = push_desc(s);
@@ -1396,6 +1509,7 @@ int sim_stats(const sim_t *cs, sim_stats_t *out) {
     out->lds_backward = (int64_t)s->lds_bwd;
     out->adj_factor_bytes = s->hd.af_size * (int64_t)sizeof(double);
     out->adj_pivot_perturbed = s->counters_host[5];
+    out->fwd_launches = s->fwd_launches;
     return SIM_OK;
 }
 
@@ -1448,7 +1562,8 @@ int sim_batch_backward(sim_t *const *sims, int32_t n, const double *const *dL_dx
         std::vector<int32_t> work;           // (handle, slot) of every step factor (direct adjoint)
         int rc = SIM_OK;
         for (int i = 0; i < n && !rc; ++i) {
-            rc = prepare_backward(sims[i], dL_dxT_dev ? dL_dxT_dev[i] : nullptr, nullptr, nullptr);
+            rc = fac_idle(sims[i]);                 // its step factors are redone below
+            if (!rc) rc = prepare_backward(sims[i], dL_dxT_dev ? dL_dxT_dev[i] : nullptr, nullptr, nullptr);
             sims[i]->hd.step_begin = 0;
             sims[i]->hd.step_end = sims[i]->T;
             sims[i]->hd.rec_step0 = 0;
@@ -1487,6 +1602,7 @@ int sim_batch_backward(sim_t *const *sims, int32_t n, const double *const *dL_dx
 int sim_trim(sim_t *s) {
     if (!s) return SIM_EINVAL;
     int rc = hip_err(hipStreamSynchronize(s->stream));
+    if (!rc) rc = fac_idle(s);
     if (rc) return rc;
     for (void **p : {(void **)&s->hd.rec_x, (void **)&s->hd.rec_v, (void **)&s->hd.rec_ubar, (void **)&s->hd.rec_mode,
                      (void **)&s->hd.rec_obst, (void **)&s->ckpt, (void **)&s->gsteps, (void **)&s->hd.af,
@@ -1522,7 +1638,8 @@ int sim_job_backward(sim_t *s, const double *dL_dxT_dev, const double *dL_dvT_de
     if (!s) return SIM_EINVAL;
     if (s->phase != 2 || s->T < 1) return SIM_ESTATE;
     return guarded([&] {
-        int rc = prepare_backward(s, dL_dxT_dev, dL_dvT_dev, nullptr);
+        int rc = fac_idle(s);                       // the job refactors its steps chunk by chunk
+        if (!rc) rc = prepare_backward(s, dL_dxT_dev, dL_dvT_dev, nullptr);
         if (rc) return rc;
         s->phase = 3;
         s->cursor = s->T;
@@ -1627,6 +1744,12 @@ int sim_job_grads(sim_t *s, const sim_grads_t *out) {
 void sim_destroy(sim_t *s) {
     if (!s) return;
     if (s->stream || !s->owned.empty()) (void)hipStreamSynchronize(s->stream);
+    if (s->fac_stream) {
+        (void)hipStreamSynchronize(s->fac_stream);
+        (void)hipEventDestroy(s->fac_ev);
+        (void)hipEventDestroy(s->fac_done);
+        (void)hipStreamDestroy(s->fac_stream);
+    }
     for (void *p : s->owned) {
         if (s->free_fn) s->free_fn(p, s->ctx);
         else (void)hipFree(p);

@@ -291,3 +291,34 @@ def test_direct_adjoint_batch_and_checkpoint_are_bitwise():
     for g1, g2 in zip(singles, grads):
         for key in ("dx0", "dv0", "dw_edge", "dmu"):
             assert torch.equal(g1[key], g2[key]), key
+
+
+def test_direct_adjoint_factorisation_overlap_is_bitwise(monkeypatch):
+    # the step factorisations run on a second stream while the forward pass is
+    # still running (chunked forward launches); results equal the serial path
+    sc = scenes.c1_napkin(0)
+    sc.steps = 40
+    gseed = torch.ones(sc.n_nodes, 3, dtype=torch.float64, device=DEV)
+    res = {}
+    for overlap in ("0", "1"):
+        monkeypatch.setenv("DIFFCLOTH_FACTOR_OVERLAP", overlap)
+        s = _sim(sc, precision="fp64", adj_solver="direct", adj_tol=1e-10, adj_max_iters=10)
+        xT, vT, _ = s.forward(sc.steps)
+        assert s.stats()["fwd_launches"] == (1 if overlap == "0" else 4)   # chunks end at 20, 30, 35, 40
+        g1 = s.backward(gseed)
+        g2 = s.backward(2.0 * gseed)              # the factors are reused
+        s.set_state(None, None)
+        s.forward(sc.steps)                        # a second rollout refactors
+        g3 = s.backward(gseed)
+        n = 17
+        a = s.adjoint_step(n, gseed, gseed)        # replaces slot 0 with step n's factor
+        g4 = s.backward(gseed)                     # and the full backward factors again
+        res[overlap] = (xT, vT, g1, g2, g3, a, g4)
+        s.close()
+    r0, r1 = res["0"], res["1"]
+    assert torch.equal(r0[0], r1[0]) and torch.equal(r0[1], r1[1])
+    for k in range(2, 7):
+        for key in ("dx0", "dv0", "dw_edge", "dmu"):
+            assert torch.equal(r0[k][key], r1[k][key]), (k, key)
+    for key in ("dx0", "dv0"):                     # linear in the seed
+        assert torch.allclose(r1[2][key] * 2.0, r1[3][key], rtol=1e-12, atol=0.0), key
