@@ -243,6 +243,9 @@ void ks_new_order(const HostModel &hm, std::vector<int32_t> &kp, std::vector<int
 // (ld = ns + nR rows, ns columns) with B_s = L(R_s, s) the off-diagonal block:
 //   forward  y_s = L_ss^{-1} t_s and u_s = B_s y_s = (B_s L_ss^{-1}) t_s in one product,
 //   backward x_s = L_ss^{-T} y_s - (B_s L_ss^{-1})^T x_{R_s}.
+// A root supernode (nR = 0) stores instead the inverse of its diagonal block,
+// (L_ss L_ss^T)^{-1} = L_ss^{-T} L_ss^{-1} (dense, symmetric): its forward
+// product gives x_s at once and it has no backward product.
 // gval: column-major with the column stride rounded up to even (offset
 // goff[s]); gvalt: the same block row-major with the row stride rounded up to
 // even (offset gofft[s]).  Padding is zero; every block starts at an even
@@ -270,6 +273,15 @@ void stacked_factor(const HostModel &hm, std::vector<double> &gval, std::vector<
         goff[sn] = (int64_t)gval.size();
         gval.resize(gval.size() + (size_t)ldp * nsz, 0.0);
         double *G = gval.data() + goff[sn];
+        if (nR == 0) {                                      // root: (L L^T)^{-1}
+            for (int k = 0; k < nsz; ++k)
+                for (int r = 0; r < nsz; ++r) {
+                    double acc = 0.0;
+                    for (int j = std::max(r, k); j < nsz; ++j) acc += inv[(size_t)j * nsz + r] * inv[(size_t)j * nsz + k];
+                    G[(size_t)k * ldp + r] = acc;
+                }
+            continue;
+        }
         for (int k = 0; k < nsz; ++k) {
             for (int r = k; r < nsz; ++r) G[(size_t)k * ldp + r] = inv[(size_t)r * nsz + k];
             for (int q = 0; q < nR; ++q) {
@@ -468,6 +480,11 @@ void build_device(sim *s) {
     std::vector<RowItem> ritems;
     std::vector<BwdItem> bitems;
     std::vector<GatherItem> bgat;
+    std::vector<int32_t> root_rows;                 // 3 i for the rows of root supernodes
+    std::vector<char> is_root_row(m, 0);
+    for (int sn = 0; sn < ns; ++sn)
+        if (snr[sn] == 0)
+            for (int c = sc0[sn]; c < sc0[sn] + sns[sn]; ++c) is_root_row[c] = 1;
     std::vector<FwdItem> fitems;
     auto pick_team = [](int items, int maxlen) {
         int best = 1;
@@ -488,8 +505,11 @@ void build_device(sim *s) {
             const int c0 = sc0[sn], nsz = sns[sn], ld = nsz + snr[sn];
             if (ld >= 32768) throw std::runtime_error("supernode too large");
             const int ldp = ld + (ld & 1), nszp = nsz + (nsz & 1);
+            const bool root = snr[sn] == 0;
             for (int k = 0; k < nsz; ++k) ritems.push_back(RowItem{3 * (c0 + k), up[c0 + k], up[c0 + k + 1], 0});
-            for (int k = 0; k < nsz; k += 2) {          // columns k, k + 1
+            if (root)
+                for (int k = 0; k < nsz; ++k) root_rows.push_back(3 * (c0 + k));
+            for (int k = 0; k < nsz && !root; k += 2) {  // columns k, k + 1
                 BwdItem b{};
                 b.g = (int32_t)(gofft[sn] + (int64_t)k * nszp + k);
                 b.n1 = (int16_t)(nsz - k);
@@ -501,13 +521,16 @@ void build_device(sim *s) {
                 bitems.push_back(b);
                 bmax = std::max(bmax, ld - k);
             }
-            for (int q = 0; q < snr[sn]; ++q) bgat.push_back(GatherItem{uoff[sn] + 3 * q, 3 * rows[rptr[sn] + q]});
+            for (int q = 0; q < snr[sn]; ++q) {        // x of a root's rows is still in Y (encoded -(3i) - 1)
+                const int i = rows[rptr[sn] + q];
+                bgat.push_back(GatherItem{uoff[sn] + 3 * q, is_root_row[i] ? -3 * i - 1 : 3 * i});
+            }
             auto out_of = [&](int r) { return r < nsz ? 3 * (c0 + r) : -(uoff[sn] + 3 * (r - nsz)) - 1; };
             for (int r = 0; r < ld; r += 2) {           // rows r, r + 1
                 FwdItem f{};
                 f.g = (int32_t)(goff[sn] + r);
                 f.ld = (int16_t)ldp;
-                f.kmax = (int16_t)(r + 1 < nsz ? r + 2 : nsz);
+                f.kmax = (int16_t)(root ? nsz : r + 1 < nsz ? r + 2 : nsz);
                 f.tbase = 3 * c0;
                 f.out0 = out_of(r);
                 f.out1 = r + 1 < ld ? out_of(r + 1) : kNoOutput;
@@ -528,6 +551,8 @@ void build_device(sim *s) {
     D.lvl_team = upload(s, team);
     D.lvl_gat_ptr = upload(s, lgp);
     D.lvl_bwd_ptr = upload(s, lbp);
+    D.n_root_rows = (int)root_rows.size();
+    D.root_rows = upload(s, root_rows);
     D.bgat = upload(s, bgat);
     D.rows = upload(s, ritems);
     D.fitems = upload(s, fitems);

@@ -180,10 +180,16 @@ __device__ __forceinline__ void solve_P(const SimDev &S, auto b, auto T, auto Y,
         v4i cur = {0, 0, 0, 0}, cur2 = {0, 0, 0, 0};
         if (c0 + team < c1) { cur = bit[2 * (c0 + team)]; cur2 = bit[2 * (c0 + team) + 1]; }
         const int q0 = G(S.lvl_gat_ptr)[l], q1 = G(S.lvl_gat_ptr)[l + 1];
+        if (c1 == c0 && q1 == q0 && l > 0) continue;    // root supernodes only: solved in the forward sweep
         if (q1 > q0) {
             for (int q = q0 + threadIdx.x; q < q1; q += (int)blockDim.x) {
                 const v2i e = ((GLOBAL const v2i *)S.bgat)[q];   // GatherItem {u, x3}
-                U[e.x] = x[e.y]; U[e.x + 1] = x[e.y + 1]; U[e.x + 2] = x[e.y + 2];
+                if (e.y >= 0) {
+                    U[e.x] = x[e.y]; U[e.x + 1] = x[e.y + 1]; U[e.x + 2] = x[e.y + 2];
+                } else {                                         // a root's row: x is still in Y
+                    const int y3 = -e.y - 1;
+                    U[e.x] = Y[y3]; U[e.x + 1] = Y[y3 + 1]; U[e.x + 2] = Y[y3 + 2];
+                }
             }
             __syncthreads();
         }
@@ -227,6 +233,11 @@ __device__ __forceinline__ void solve_P(const SimDev &S, auto b, auto T, auto Y,
             cur = nxt;
             cur2 = nxt2;
         }
+        if (l == 0)                                      // the roots' x, left in Y by the forward sweep
+            for (int q = threadIdx.x; q < S.n_root_rows; q += (int)blockDim.x) {
+                const int i3 = G(S.root_rows)[q];
+                x[i3] = Y[i3]; x[i3 + 1] = Y[i3 + 1]; x[i3 + 2] = Y[i3 + 2];
+            }
         __syncthreads();
     }
 }

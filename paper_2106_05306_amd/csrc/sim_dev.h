@@ -40,7 +40,7 @@ struct BwdItem {            // backward: columns k, k + 1 (k even) of a stacked 
 };
 struct GatherItem {         // backward: x_{R_s} entry copied into the supernode's ubuf slot
     int32_t u;              // ubuf offset (3 doubles)
-    int32_t x3;             // 3 * node
+    int32_t x3;             // 3 * node; -(3 * node) - 1: a root supernode's row, read from Y
 };
 // the kernels read these descriptors as 16-byte / 8-byte vectors (field order as declared)
 static_assert(sizeof(FwdItem) == 32 && sizeof(BwdItem) == 32 && sizeof(GatherItem) == 8, "descriptor layout");
@@ -129,6 +129,8 @@ struct SimDev {
     const int32_t *lvl_rows_ptr;      // [n_levels+1] into rows (columns of each level)
     const int32_t *lvl_gat_ptr;       // [n_levels+1] into bgat
     const int32_t *lvl_bwd_ptr;       // [n_levels+1] into bwd items (column pairs of each level)
+    int n_root_rows;                  // rows of root supernodes (no R_s): their forward product
+    const int32_t *root_rows;         //   writes x_s into Y, copied to x at the end (3 i each)
     const int32_t *lvl_items_ptr;     // [n_levels+1] into fwd items
     const int32_t *lvl_team;          // [2*n_levels] lanes per item: forward, backward
     const RowItem *rows;
