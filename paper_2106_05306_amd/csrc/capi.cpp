@@ -100,7 +100,7 @@ int leaf_size_default() {
 int merge_cap_default() {
     const char *e = std::getenv("DIFFCLOTH_MERGE");
     const int v = e ? std::atoi(e) : -1;
-    return v >= 0 && v <= 4096 ? v : 160;
+    return v >= 0 && v <= 4096 ? v : 300;
 }
 
 // prefetch workgroups of a single-handle direct adjoint launch (0: none)

@@ -69,7 +69,7 @@ struct HostModel {
     int merged_nodes = 0;                   // nodes of the merged top supernode of P (0: none)
 
     int build(const sim_mesh_t *mesh, const sim_params_t *p);   // SIM_OK or SIM_E*
-    int order_and_factor(int leaf_size, int merge_cap = 160);
+    int order_and_factor(int leaf_size, int merge_cap = 300);
     void order(int leaf_size, int merge_cap);   // ordering + symbolic structures
     int factor();                            // numeric factor on that structure
     void apply_regions();                    // w = base_w * region scale
