@@ -149,7 +149,17 @@ T *zeros(sim *s, size_t n) {
     return d;
 }
 
-// Splits the kAdjBatch-column batches of one phase of the direct adjoint solve into
+// Column groups of a direct-solve item of nrow rows and K columns: as many
+// lane groups (a power of two, at most 8) as fit a wavefront beside its row
+// pairs and have columns to take.
+int adj_groups(int nrow, int K) {
+    const int rp = (nrow + 1) / 2;
+    int g = 1;
+    while (g < 8 && 2 * g * rp <= 64 && g * kAdjBatch < K) g *= 2;
+    return g;
+}
+
+// Splits the column batches of one phase of the direct adjoint solve into
 // kAdjWaves contiguous runs of (nearly) equal length, in item order; a cut
 // inside an item moves to the item's boundary when that is at most one batch
 // away.  Appends the items, each wavefront's run (first item, first batch,
@@ -160,7 +170,10 @@ void balance_phase(const std::vector<AdjItem> &ph, std::vector<AdjItem> &items, 
                    std::vector<int32_t> &split, std::vector<int32_t> &sptr) {
     const int base = (int)items.size(), ni = (int)ph.size();
     std::vector<int64_t> pre(ni + 1, 0);                  // first batch of each item
-    for (int i = 0; i < ni; ++i) pre[i + 1] = pre[i] + std::max(1, (ph[i].K + kAdjBatch - 1) / kAdjBatch);
+    for (int i = 0; i < ni; ++i) {
+        const int span = kAdjBatch * ph[i].grp;
+        pre[i + 1] = pre[i] + std::max(1, (ph[i].K + span - 1) / span);
+    }
     const int64_t total = pre[ni];
     std::vector<int64_t> cut(kAdjWaves + 1, 0);
     cut[kAdjWaves] = total;
@@ -725,11 +738,13 @@ void build_device(sim *s) {
                 const int64_t offB = q.off + (int64_t)N * q.ldn, offV = offB + (int64_t)N * q.ldr;
                 for (int a = 0; a < N; a += kAdjRows) {  // z_t = D_t^{-1} t_t and x_t = z_t - V_t x_{R_t}
                     const int nr = std::min(kAdjRows, N - a);
-                    phase[3 * l].push_back(AdjItem{q.off + a, q.ldn, N, t0, t0 + a, nr, 0});
-                    phase[3 * l + 2].push_back(AdjItem{offV + a, q.ldn, R, (int32_t)q.uoff, t0 + a, nr, 0});
+                    phase[3 * l].push_back(AdjItem{q.off + a, q.ldn, N, t0, t0 + a, nr, adj_groups(nr, N)});
+                    phase[3 * l + 2].push_back(AdjItem{offV + a, q.ldn, R, (int32_t)q.uoff, t0 + a, nr, adj_groups(nr, R)});
                 }
-                for (int a = 0; a < R; a += kAdjRows)   // u_t = B_t z_t
-                    phase[3 * l + 1].push_back(AdjItem{offB + a, q.ldr, N, t0, q.uoff + a, std::min(kAdjRows, R - a), 0});
+                for (int a = 0; a < R; a += kAdjRows) {  // u_t = B_t z_t
+                    const int nr = std::min(kAdjRows, R - a);
+                    phase[3 * l + 1].push_back(AdjItem{offB + a, q.ldr, N, t0, q.uoff + a, nr, adj_groups(nr, N)});
+                }
                 pf[3 * l].insert(pf[3 * l].end(), {q.off, (int64_t)N * q.ldn});
                 if (R > 0) {
                     pf[3 * l + 1].insert(pf[3 * l + 1].end(), {offB, (int64_t)N * q.ldr});

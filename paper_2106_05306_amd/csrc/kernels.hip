@@ -1233,15 +1233,16 @@ __device__ __forceinline__ void publish_pos(const SimDev &S, int64_t pos) {
 }
 
 // One phase of the direct adjoint solve (see AdjItem): every wavefront runs
-// its share of the kAdjBatch-column batches, rows 2 lane and 2 lane + 1 per
-// lane (one 16-byte load per column); an item finished inside the share is
-// written at once, a part of an item that spans several wavefronts goes to
-// part[] and is summed, in wavefront order, after the barrier.
+// its share of the column batches, two rows per lane (one 16-byte load per
+// column), the columns of a short item split over groups of lanes and summed
+// in a fixed tree; an item finished inside the share is written at once, a
+// part of an item that spans several wavefronts goes to part[] and is
+// summed, in wavefront order, after the barrier.
 // OP 0: out = M v; OP 1: out = z - M v.
 template <int OP>
 __device__ __forceinline__ void adj_phase(const SimDev &S, int ph, auto F, auto v, auto z, auto out, double *part) {
     constexpr bool kGlobalV = !std::is_same_v<decltype(v), double *>;   // v not in LDS
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, r0 = 2 * lane;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const auto items = (GLOBAL const v4i *)S.adj_items;                 // AdjItem as 2 x 16 bytes
     const auto F2 = (GLOBAL const v2d *)F;                               // step factors: even offsets
     const v4i pr = ((GLOBAL const v4i *)S.adj_prog)[ph * kAdjWaves + wave];
@@ -1249,24 +1250,27 @@ __device__ __forceinline__ void adj_phase(const SimDev &S, int ph, auto F, auto 
     while (i < pr.z || (i == pr.z && kb < pr.w)) {
         const v4i d0 = items[2 * i], d1 = items[2 * i + 1];
         const int64_t moff = (int64_t)(uint32_t)d0.x | ((int64_t)d0.y << 32);
-        const int ld2 = d0.z >> 1, K = d0.w, vb = d1.x, ob = d1.y, nrow = d1.z;
-        const int nkb = K > 0 ? (K + kAdjBatch - 1) / kAdjBatch : 1;
+        const int ld2 = d0.z >> 1, K = d0.w, vb = d1.x, ob = d1.y, nrow = d1.z, ng = d1.w;
+        // lane = g rp + rr: rows 2 rr, 2 rr + 1; column group g of ng
+        const int rp = (nrow + 1) >> 1, g = lane / rp, rr = lane - g * rp, r0 = 2 * rr;
+        const bool grp_ok = g < ng, live = grp_ok && r0 < nrow;
+        const int span = kAdjBatch * ng;
+        const int nkb = K > 0 ? (K + span - 1) / span : 1;
         const int kend = i == pr.z ? pr.w : nkb;
         const bool whole = kb == 0 && kend == nkb;
-        const auto col = F2 + ((moff >> 1) + lane);
-        const bool live = r0 < nrow;
+        const auto col = F2 + ((moff >> 1) + rr);
         double acc0 = 0.0, acc1 = 0.0;
         for (; kb < kend; ++kb) {
-            const int k0 = kb * kAdjBatch;
+            const int k0 = kb * span, kg = k0 + g * kAdjBatch;
             v2d c[kAdjBatch];
-            if (k0 + kAdjBatch <= K) {                  // full batch: one predicate for all loads
-                // v in global memory: one load by lanes 0..kAdjBatch-1, broadcast from registers
+            if (k0 + span <= K) {                       // full batch: one predicate for all loads
+                // v in global memory: one load by lanes 0..span-1, read back from registers
                 double vl = 0.0;
                 if constexpr (kGlobalV)
-                    if (lane < kAdjBatch) vl = v[vb + k0 + lane];
+                    if (lane < span) vl = v[vb + k0 + lane];
                 if (live) {
 #pragma unroll
-                    for (int j = 0; j < kAdjBatch; ++j) c[j] = col[(k0 + j) * ld2];
+                    for (int j = 0; j < kAdjBatch; ++j) c[j] = col[(kg + j) * ld2];
                 } else {
 #pragma unroll
                     for (int j = 0; j < kAdjBatch; ++j) c[j] = v2d{0.0, 0.0};
@@ -1274,31 +1278,37 @@ __device__ __forceinline__ void adj_phase(const SimDev &S, int ph, auto F, auto 
 #pragma unroll
                 for (int j = 0; j < kAdjBatch; ++j) {
                     double vj;
-                    if constexpr (kGlobalV) vj = lane_value(vl, j);
-                    else vj = v[vb + k0 + j];
+                    if constexpr (kGlobalV) vj = ng == 1 ? lane_value(vl, j) : __shfl(vl, g * kAdjBatch + j, 64);
+                    else vj = grp_ok ? v[vb + kg + j] : 0.0;
                     acc0 += c[j].x * vj;
                     acc1 += c[j].y * vj;
                 }
             } else {
 #pragma unroll
                 for (int j = 0; j < kAdjBatch; ++j)
-                    c[j] = live && k0 + j < K ? col[(k0 + j) * ld2] : v2d{0.0, 0.0};
+                    c[j] = live && kg + j < K ? col[(kg + j) * ld2] : v2d{0.0, 0.0};
 #pragma unroll
                 for (int j = 0; j < kAdjBatch; ++j)
-                    if (k0 + j < K) {
-                        const double vj = v[vb + k0 + j];
+                    if (grp_ok && kg + j < K) {
+                        const double vj = v[vb + kg + j];
                         acc0 += c[j].x * vj;
                         acc1 += c[j].y * vj;
                     }
             }
         }
-        if (whole) {
-            if (r0 < nrow) out[ob + r0] = OP == 0 ? acc0 : z[ob + r0] - acc0;
-            if (r0 + 1 < nrow) out[ob + r0 + 1] = OP == 0 ? acc1 : z[ob + r0 + 1] - acc1;
-        } else {
-            const int o = (2 * wave + (i == pr.x ? 0 : 1)) * kAdjRows + r0;
-            part[o] = acc0;
-            part[o + 1] = acc1;
+        for (int sft = ng >> 1; sft > 0; sft >>= 1) {   // groups summed in a fixed tree; group 0 holds the row sums
+            acc0 += __shfl_down(acc0, sft * rp, 64);
+            acc1 += __shfl_down(acc1, sft * rp, 64);
+        }
+        if (g == 0) {
+            if (whole) {
+                if (r0 < nrow) out[ob + r0] = OP == 0 ? acc0 : z[ob + r0] - acc0;
+                if (r0 + 1 < nrow) out[ob + r0 + 1] = OP == 0 ? acc1 : z[ob + r0 + 1] - acc1;
+            } else {
+                const int o = (2 * wave + (i == pr.x ? 0 : 1)) * kAdjRows + r0;
+                part[o] = acc0;
+                part[o + 1] = acc1;
+            }
         }
         ++i;
         kb = 0;
@@ -1306,6 +1316,7 @@ __device__ __forceinline__ void adj_phase(const SimDev &S, int ph, auto F, auto 
     __syncthreads();
     const int s0 = G(S.adj_sptr)[ph], s1 = G(S.adj_sptr)[ph + 1];
     if (s1 > s0) {
+        const int r0 = 2 * lane;                         // parts are stored by row
         for (int e = s0 + wave; e < s1; e += kAdjWaves) {
             const v4i sp = ((GLOBAL const v4i *)S.adj_split)[e];
             const v4i d1 = items[2 * sp.x + 1];

@@ -57,8 +57,9 @@ struct SpringInc {          // node-centred spring projection: one incident spri
 static_assert(sizeof(SpringInc) == 16, "read as a 16-byte vector");
 
 // Direct adjoint solve: one product y = M v with a column-major block M of a
-// step factor, rows [a, a + nrow) (a wavefront, rows 2 lane and 2 lane + 1 per
-// lane; M's column stride and offset are even).  A phase of
+// step factor, rows [a, a + nrow) (a wavefront, two rows per lane; M's column
+// stride and offset are even; a short item splits its columns over groups of
+// lanes).  A phase of
 // the solve (one level, one kind of block) is a list of such items; its
 // kAdjBatch-column batches are split evenly over the wavefronts of the workgroup.
 struct AdjItem {
@@ -68,7 +69,8 @@ struct AdjItem {
     int32_t vbase;          // first entry of v
     int32_t obase;          // first output entry (row a)
     int32_t nrow;           // rows of the item, <= kAdjRows
-    int32_t pad;
+    int32_t grp;            // column groups: lanes g rp .. g rp + rp - 1 (rp = row pairs) take
+                            //   columns g kAdjBatch .. of every kAdjBatch * grp (grp rp <= 64)
 };
 constexpr int kAdjBatch = 8;        // columns per unit of work (16-byte loads per lane in flight)
 constexpr int kAdjRows = 128;       // rows per item: two per lane, read with one 16-byte load

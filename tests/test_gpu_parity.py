@@ -322,3 +322,19 @@ def test_direct_adjoint_factorisation_overlap_is_bitwise(monkeypatch):
             assert torch.equal(r0[k][key], r1[k][key]), (k, key)
     for key in ("dx0", "dv0"):                     # linear in the seed
         assert torch.allclose(r1[2][key] * 2.0, r1[3][key], rtol=1e-12, atol=0.0), key
+
+
+def test_direct_adjoint_prefetch_workgroups_change_nothing(monkeypatch):
+    # the prefetch workgroups of a single-handle adjoint launch only read; the
+    # gradients with and without them are identical
+    sc = scenes.c2_sphere_drop(0, n=24, steps=30)
+    gseed = torch.ones(sc.n_nodes, 3, dtype=torch.float64, device=DEV)
+    s = _sim(sc, precision="mixed", adj_solver="direct", adj_tol=1e-8, adj_max_iters=10)
+    s.forward(sc.steps)
+    out = {}
+    for h in ("0", "4", "7"):
+        monkeypatch.setenv("DIFFCLOTH_ADJ_HELPERS", h)
+        out[h] = s.backward(gseed)
+    for key in ("dx0", "dv0", "dw_edge", "dmu"):
+        assert torch.equal(out["0"][key], out["4"][key]), key
+        assert torch.equal(out["0"][key], out["7"][key]), key
