@@ -847,25 +847,33 @@ void build_device(sim *s) {
     plan_lds(s, s->flags_bwd, s->lds_bwd, false);
 }
 
-// A batched launch shares one placement: the bits every handle has, trimmed
-// until the largest handle fits.
+// A batched launch shares one placement: the same greedy choice as for one
+// handle (vectors, then update buffer, then positions), each kind added when it
+// fits every handle of the launch.  (Intersecting the handles' own choices can
+// leave nothing: a large handle without vectors in LDS and a middle one
+// without positions.)
 size_t batch_lds(sim *const *sims, int n, bool fwd, int &flags) {
-    flags = kLdsVectors | kLdsUpdates | kLdsPositions;
-    for (int i = 0; i < n; ++i) flags &= fwd ? sims[i]->flags_fwd : sims[i]->flags_bwd;
-    for (int bit : {kLdsPositions, kLdsUpdates, kLdsVectors}) {
-        size_t mx = 0;
-        bool ok = true;
+    auto fits = [&](int f, size_t &mx) {
+        mx = 0;
         for (int i = 0; i < n; ++i) {
-            const size_t avail = sims[i]->max_lds - (fwd ? sims[i]->static_fwd : sims[i]->static_bwd);
-            const size_t b = lds_bytes(sims[i], flags, fwd);
+            const size_t st = fwd ? sims[i]->static_fwd : sims[i]->static_bwd;
+            const size_t avail = sims[i]->max_lds > st ? sims[i]->max_lds - st : 0;
+            const size_t b = lds_bytes(sims[i], f, fwd);
             mx = std::max(mx, b);
-            if (b > avail) ok = false;
+            if (b > avail) return false;
         }
-        if (ok) return mx;
-        flags &= ~bit;
-    }
+        return true;
+    };
     flags = 0;
-    return 0;
+    size_t bytes = 0, mx = 0;
+    for (int bit : {kLdsVectors, kLdsUpdates, kLdsPositions}) {
+        if (!fwd && bit == kLdsPositions) continue;
+        if (fits(flags | bit, mx)) {
+            flags |= bit;
+            bytes = mx;
+        }
+    }
+    return bytes;
 }
 
 int push_desc(sim *s) {
