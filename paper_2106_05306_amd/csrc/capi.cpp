@@ -14,7 +14,7 @@
 #include "sim_dev.h"
 
 namespace dc {
-hipError_t launch_forward(const SimDev *d_sims, int n, bool mixed, size_t lds, int flags, hipStream_t st);
+hipError_t launch_forward(const SimDev *d_sims, int n, bool mixed, size_t lds, int flags, int helpers, hipStream_t st);
 hipError_t launch_backward(const SimDev *d_sims, int n, bool mixed, size_t lds, int flags, int helpers,
                            hipStream_t st);
 hipError_t configure_lds(size_t fwd_bytes, size_t bwd_bytes);
@@ -81,6 +81,7 @@ struct sim {
     size_t lds_fwd = 0, lds_bwd = 0;   // dynamic LDS of the two kernels
     int flags_fwd = 0, flags_bwd = 0;  // what lives in LDS (kLds* bits)
     size_t static_fwd = 0, static_bwd = 0, max_lds = 0;
+    int cus = 0;                        // compute units of the device
 };
 
 namespace {
@@ -101,6 +102,21 @@ int merge_cap_default() {
     const char *e = std::getenv("DIFFCLOTH_MERGE");
     const int v = e ? std::atoi(e) : -1;
     return v >= 0 && v <= 4096 ? v : 300;
+}
+
+// Prefetch workgroups per handle of a forward launch: 2 when the largest
+// handle's factor of P (both copies) passes 3 MB (a quarter of an XCD's L2
+// is left for the rest), if every workgroup of the launch can be resident.
+int fwd_helpers(sim *const *sims, int n) {
+    const char *e = std::getenv("DIFFCLOTH_FWD_HELPERS");
+    int h = e ? std::atoi(e) : -1;
+    if (h < 0) {
+        int64_t mx = 0;
+        for (int i = 0; i < n; ++i) mx = std::max(mx, 2 * sims[i]->factor_bytes);
+        h = mx > (3 << 20) ? 2 : 0;
+    }
+    h = std::min(h, 7);
+    return h > 0 && (int64_t)n * (1 + h) <= sims[0]->cus ? h : 0;
 }
 
 // prefetch workgroups of a single-handle direct adjoint launch (0: none)
@@ -564,6 +580,24 @@ void build_device(sim *s) {
     D.lvl_team = upload(s, team);
     D.lvl_gat_ptr = upload(s, lgp);
     D.lvl_bwd_ptr = upload(s, lbp);
+    {   // forward-pass prefetch ranges, by solve phase
+        const int L = hm.n_levels;
+        std::vector<std::vector<int64_t>> ph(2 * L);
+        for (int sn = 0; sn < ns; ++sn) {
+            const int l = hm.sup_level[sn], nsz = sns[sn], ld = nsz + snr[sn];
+            ph[l].insert(ph[l].end(), {goff[sn], (int64_t)(ld + (ld & 1)) * nsz});
+            if (snr[sn] > 0) ph[L + (L - 1 - l)].insert(ph[L + (L - 1 - l)].end(), {gofft[sn], (int64_t)ld * (nsz + (nsz & 1))});
+        }
+        std::vector<int64_t> fpf;
+        std::vector<int32_t> fptr(1, 0);
+        for (const auto &r : ph) {
+            fpf.insert(fpf.end(), r.begin(), r.end());
+            fptr.push_back((int32_t)(fpf.size() / 2));
+        }
+        D.fpf = upload(s, fpf);
+        D.fpf_ptr = upload(s, fptr);
+        D.fwd_pos = zeros<int64_t>(s, 1);
+    }
     D.n_root_rows = (int)root_rows.size();
     D.root_rows = upload(s, root_rows);
     D.bgat = upload(s, bgat);
@@ -841,6 +875,8 @@ void build_device(sim *s) {
         hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
         throw std::runtime_error("hip attribute");
     if (kernel_static_lds(&s->static_fwd, &s->static_bwd) != hipSuccess) throw std::runtime_error("hip attribute");
+    if (hipDeviceGetAttribute(&s->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        throw std::runtime_error("hip attribute");
     s->max_lds = (size_t)maxlds;
     if (configure_lds(s->max_lds - s->static_fwd, s->max_lds - s->static_bwd) != hipSuccess) s->max_lds = 0;
     plan_lds(s, s->flags_fwd, s->lds_fwd, true);
@@ -950,9 +986,10 @@ int run_forward_range(sim *s, int a, int b) {
     s->hd.step_begin = a;
     s->hd.step_end = b;
     s->hd.rec_step0 = a;
+    ++s->hd.fwd_epoch;
     int rc = push_desc(s);
     if (rc) return rc;
-    return hip_err(launch_forward(s->dd, 1, s->hd.mixed != 0, s->lds_fwd, s->flags_fwd, s->stream));
+    return hip_err(launch_forward(s->dd, 1, s->hd.mixed != 0, s->lds_fwd, s->flags_fwd, fwd_helpers(&s, 1), s->stream));
 }
 
 int read_counters(sim *s) {
@@ -1171,8 +1208,10 @@ int forward_overlapped(sim *s, int n_steps, const std::vector<int> &ends) {
         s->hd.step_begin = a;
         s->hd.step_end = b;
         s->hd.rec_step0 = 0;
+        ++s->hd.fwd_epoch;
         rc = push_desc(s);
-        if (!rc) rc = hip_err(launch_forward(s->dd, 1, s->hd.mixed != 0, s->lds_fwd, s->flags_fwd, s->stream));
+        if (!rc) rc = hip_err(launch_forward(s->dd, 1, s->hd.mixed != 0, s->lds_fwd, s->flags_fwd, fwd_helpers(&s, 1),
+                                             s->stream));
         if (!rc && pa >= 0) {                // the previous chunk, queued behind this one's launch
             std::vector<int32_t> pairs;
             for (int n = pa; n < pb; ++n) { pairs.push_back(0); pairs.push_back(n); }
@@ -1578,6 +1617,7 @@ int sim_batch_forward(sim_t *const *sims, int32_t n, const int32_t *n_steps, dou
             sims[i]->hd.step_begin = 0;
             sims[i]->hd.step_end = n_steps[i];
             sims[i]->hd.rec_step0 = 0;
+            ++sims[i]->hd.fwd_epoch;
             descs[i] = sims[i]->hd;
             if (!rc) rc = push_desc(sims[i]);
         }
@@ -1586,7 +1626,7 @@ int sim_batch_forward(sim_t *const *sims, int32_t n, const int32_t *n_steps, dou
         rc = hip_err(hipMemcpyAsync(d, descs.data(), n * sizeof(SimDev), hipMemcpyHostToDevice, s0->stream));
         int fl = 0;
         const size_t lb = batch_lds(sims, n, true, fl);
-        if (!rc) rc = hip_err(launch_forward(d, n, s0->hd.mixed != 0, lb, fl, s0->stream));
+        if (!rc) rc = hip_err(launch_forward(d, n, s0->hd.mixed != 0, lb, fl, fwd_helpers(sims, n), s0->stream));
         for (int i = 0; i < n && !rc; ++i)
             rc = finish_forward(sims[i], n_steps[i], xT_dev ? xT_dev[i] : nullptr, vT_dev ? vT_dev[i] : nullptr);
         (void)hipStreamSynchronize(s0->stream);
@@ -1716,6 +1756,7 @@ int sim_batch_advance(sim_t *const *sims, int32_t n, const int32_t *steps, void 
                 h->hd.step_begin = h->cursor;
                 h->hd.step_end = std::min(h->target, h->cursor + steps[i]);
                 h->hd.rec_step0 = 0;
+                ++h->hd.fwd_epoch;
                 fw.push_back(h);
                 df.push_back(h->hd);
             } else {
@@ -1743,7 +1784,8 @@ int sim_batch_advance(sim_t *const *sims, int32_t n, const int32_t *steps, void 
         if (!rc && dfd) {
             int fl = 0;
             const size_t lb = batch_lds(fw.data(), (int)fw.size(), true, fl);
-            rc = hip_err(launch_forward(dfd, (int)fw.size(), fw[0]->hd.mixed != 0, lb, fl, sf));
+            rc = hip_err(launch_forward(dfd, (int)fw.size(), fw[0]->hd.mixed != 0, lb, fl, fwd_helpers(fw.data(), (int)fw.size()),
+                                        sf));
         }
         if (!rc && dbd) {
             if (!pairs.empty()) rc = factor_pairs(bw[0], dbd, bw, pairs, sb);

@@ -119,10 +119,19 @@ __device__ __forceinline__ void put_row(int out, double a0, double a1, double a2
     }
 }
 
-__device__ __forceinline__ void solve_P(const SimDev &S, auto b, auto T, auto Y, auto x, auto U) {
+constexpr int64_t kPosMask = (int64_t(1) << 40) - 1;      // position bits of adj_pos / fwd_pos
+
+// thread 0 announces a position (epoch << 40 | pos) to prefetch workgroups
+__device__ __forceinline__ void announce(int64_t *where, int64_t epoch, int64_t pos) {
+    if (threadIdx.x == 0) __hip_atomic_store(where, (epoch << 40) | pos, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// pos0 >= 0: the forward pass announces each level (pos0 + phase, see fwd_pos)
+__device__ __forceinline__ void solve_P(const SimDev &S, auto b, auto T, auto Y, auto x, auto U, int64_t pos0 = -1) {
     const auto gv2 = (GLOBAL const v2d *)S.gval;        // two rows per load
     const auto gt2 = (GLOBAL const v2d *)S.gvalt;       // two columns per load
     for (int l = 0; l < S.n_levels; ++l) {
+        if (pos0 >= 0) announce(S.fwd_pos, S.fwd_epoch, pos0 + l);
         // descriptor of this thread's first product item, fetched before the
         // gather phase and its barrier (it does not depend on the vectors)
         const int tl = G(S.lvl_team)[2 * l];
@@ -173,6 +182,7 @@ __device__ __forceinline__ void solve_P(const SimDev &S, auto b, auto T, auto Y,
     // x_s = L_ss^{-T} y_s - (B_s L_ss^{-1})^T x_{R_s}, one item per column pair
     // of G_s (row-major copy: the items of a wavefront read consecutive addresses)
     for (int l = S.n_levels - 1; l >= 0; --l) {
+        if (pos0 >= 0) announce(S.fwd_pos, S.fwd_epoch, pos0 + 2 * S.n_levels - 1 - l);
         const int tl = G(S.lvl_team)[2 * l + 1];
         const int team = threadIdx.x / tl, lane = threadIdx.x % tl, nteams = (int)blockDim.x / tl;
         const int c0 = G(S.lvl_bwd_ptr)[l], c1 = G(S.lvl_bwd_ptr)[l + 1];
@@ -424,13 +434,71 @@ __device__ __forceinline__ void spring_rhs(const SimDev &S, auto XN, auto V, aut
 }
 
 
+// Forward prefetch workgroup j of H (same XCD as the solving workgroup of
+// its handle): follows the announced solve phases and touches every 128-byte
+// line of the blocks of the next phase; returns when the solver is done or
+// nothing new was announced for 100 ms.
+__device__ void fwd_prefetch(const SimDev &S, int j, int H) {
+    __shared__ int go;
+    const int PH = 2 * S.n_levels;
+    const int64_t stride = (int64_t)H * blockDim.x, me = (int64_t)j * blockDim.x + threadIdx.x;
+    uint64_t sink = 0;
+    for (int64_t target = 0;; ++target) {
+        if (threadIdx.x == 0) {
+            int state = 0;                                   // 0: give up, 1: go, 2: solver done
+            const uint64_t t0 = wall_clock64();
+            while (wall_clock64() - t0 < 10000000ull) {      // 100 ms at the 100 MHz wall clock
+                const int64_t p = __hip_atomic_load(S.fwd_pos, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((p >> 40) == S.fwd_epoch) {
+                    const int64_t pm = p & kPosMask;
+                    if (pm == kPosMask) { state = 2; break; }
+                    if (pm + 1 >= target) { state = 1; break; }
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+            go = state;
+        }
+        __syncthreads();
+        const int st = go;
+        __syncthreads();
+        if (st != 1) break;
+        const int q = (int)(target % PH);
+        const auto base = G(q < S.n_levels ? S.gval : S.gvalt);
+        int64_t line0 = 0;
+        for (int r = G(S.fpf_ptr)[q]; r < G(S.fpf_ptr)[q + 1]; ++r) {
+            const int64_t o = G(S.fpf)[2 * r], len = G(S.fpf)[2 * r + 1];
+            const int64_t nl = (len + 15) / 16;
+            int64_t i = (me - line0) % stride;
+            if (i < 0) i += stride;
+            for (; i < nl; i += stride) {
+                sink ^= (uint64_t)__double_as_longlong(base[o + 16 * i]);
+                if (i == nl - 1) sink ^= (uint64_t)__double_as_longlong(base[o + len - 1]);
+            }
+            line0 += nl;
+        }
+    }
+    if (sink == 0x9e3779b97f4a7c15ull) G(S.red)[62] = 1.0;         // keeps the loads
+}
+
 // Forward steps [step_begin, step_end) of one handle per workgroup.  The PD
 // iterate ping-pongs between two vectors A and B (LDS when they fit): B gets
 // the right-hand side, the forward solve writes into A, the backward solve
-// writes the new iterate into B.
+// writes the new iterate into B.  With helpers > 0 the launch also holds
+// prefetch workgroups (see fwd_prefetch) laid out by XCD.
 template <bool MIXED, int FL>
-__global__ __launch_bounds__(kBlock) void k_forward(const SimDev *__restrict__ sims) {
-    const SimDev &S = sims[blockIdx.x];
+__global__ __launch_bounds__(kBlock) void k_forward(const SimDev *__restrict__ sims, int nsims, int helpers) {
+    int hid = blockIdx.x;
+    if (helpers > 0) {          // workgroup 8 j + x: handle (j / (H+1)) 8 + x, role j mod (H+1) (0: solver)
+        const int x = (int)blockIdx.x % kXcds, jj = (int)blockIdx.x / kXcds;
+        hid = jj / (helpers + 1) * kXcds + x;
+        const int role = jj % (helpers + 1);
+        if (hid >= nsims) return;
+        if (role > 0) {
+            fwd_prefetch(sims[hid], role - 1, helpers);
+            return;
+        }
+    }
+    const SimDev &S = sims[hid];
     extern __shared__ double dyn[];
     __shared__ double red[kBlock / 64];
     const int m = S.m;
@@ -443,7 +511,7 @@ __global__ __launch_bounds__(kBlock) void k_forward(const SimDev *__restrict__ s
     auto U = pick<ku>(dyn + off_u, G(S.ubuf));
     auto XN = pick<kx>(dyn + off_x, G(S.x));
     auto Vprev = G(S.vk1);
-    int64_t iters_total = 0;
+    int64_t iters_total = 0, it_run = 0;
     for (int n = S.step_begin; n < S.step_end; ++n) {
         const int slot = n - S.rec_step0;
         const double t1 = (n + 1) * h;
@@ -503,7 +571,8 @@ __global__ __launch_bounds__(kBlock) void k_forward(const SimDev *__restrict__ s
             if (converge)
                 for (int i = threadIdx.x; i < 3 * m; i += (int)blockDim.x) Vprev[i] = A[i];
             __syncthreads();
-            solve_P(S, B, B, A, B, U);
+            solve_P(S, B, B, A, B, U, it_run * 2 * S.n_levels);
+            ++it_run;
             double dmax = 0.0;
             for (int i = threadIdx.x; i < m; i += (int)blockDim.x) {
                 if (G(S.mode)[i] != FREE) {
@@ -553,6 +622,7 @@ __global__ __launch_bounds__(kBlock) void k_forward(const SimDev *__restrict__ s
         __syncthreads();
     }
     if (threadIdx.x == 0) G(S.counters)[0] += iters_total;
+    announce(S.fwd_pos, S.fwd_epoch, kPosMask);          // releases the prefetch workgroups
 }
 
 // ------------------------------------------------------------------ adjoint
@@ -1216,8 +1286,6 @@ __global__ __launch_bounds__(kFacBlock) void k_adj_factor_level(const SimDev *__
     if (threadIdx.x == 0) ((GLOBAL int32_t *)(ws + ws_anorm(S) + 1))[sn] = pert;
 }
 
-constexpr int64_t kPosMask = (int64_t(1) << 40) - 1;      // position bits of adj_pos
-
 // lane j's value of x, for every lane (j wave-uniform)
 __device__ __forceinline__ double lane_value(double x, int j) {
     const uint64_t u = (uint64_t)__double_as_longlong(x);
@@ -1227,10 +1295,7 @@ __device__ __forceinline__ double lane_value(double x, int j) {
 }
 
 // the solving workgroup announces the phase it starts (pos: step * phases + phase)
-__device__ __forceinline__ void publish_pos(const SimDev &S, int64_t pos) {
-    if (threadIdx.x == 0)
-        __hip_atomic_store(S.adj_pos, (S.adj_epoch << 40) | pos, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+__device__ __forceinline__ void publish_pos(const SimDev &S, int64_t pos) { announce(S.adj_pos, S.adj_epoch, pos); }
 
 // One phase of the direct adjoint solve (see AdjItem): every wavefront runs
 // its share of the column batches, two rows per lane (one 16-byte load per
@@ -1721,8 +1786,10 @@ __global__ void k_fill(double *p, double v, int64_t n) {
 // ------------------------------------------------------------------ launchers
 
 template <bool MIXED, int FL>
-static void fwd_one(const SimDev *d, int n, size_t lds, hipStream_t st) {
-    hipLaunchKernelGGL((k_forward<MIXED, FL>), dim3(n), dim3(kBlock), lds, st, d);
+static void fwd_one(const SimDev *d, int n, size_t lds, int helpers, hipStream_t st) {
+    // helpers: handle h's solver at 8 (H+1) (h / 8) + h mod 8, its helpers 8, 16, .. above (same XCD)
+    const int grid = helpers > 0 ? kXcds * (helpers + 1) * ((n + kXcds - 1) / kXcds) : n;
+    hipLaunchKernelGGL((k_forward<MIXED, FL>), dim3(grid), dim3(kBlock), lds, st, d, n, helpers);
 }
 template <bool MIXED, int FL>
 static void bwd_one(const SimDev *d, int n, size_t lds, int helpers, hipStream_t st) {
@@ -1731,14 +1798,14 @@ static void bwd_one(const SimDev *d, int n, size_t lds, int helpers, hipStream_t
     hipLaunchKernelGGL((k_backward<MIXED, FL>), dim3(grid), dim3(kBlockAdj), lds, st, d, helpers);
 }
 
-hipError_t launch_forward(const SimDev *d_sims, int n, bool mixed, size_t lds, int flags, hipStream_t st) {
-    using F = void (*)(const SimDev *, int, size_t, hipStream_t);
+hipError_t launch_forward(const SimDev *d_sims, int n, bool mixed, size_t lds, int flags, int helpers, hipStream_t st) {
+    using F = void (*)(const SimDev *, int, size_t, int, hipStream_t);
     static const F tab[2][8] = {
         {fwd_one<false, 0>, fwd_one<false, 1>, fwd_one<false, 2>, fwd_one<false, 3>, fwd_one<false, 4>,
          fwd_one<false, 5>, fwd_one<false, 6>, fwd_one<false, 7>},
         {fwd_one<true, 0>, fwd_one<true, 1>, fwd_one<true, 2>, fwd_one<true, 3>, fwd_one<true, 4>,
          fwd_one<true, 5>, fwd_one<true, 6>, fwd_one<true, 7>}};
-    tab[mixed ? 1 : 0][flags & 7](d_sims, n, lds, st);
+    tab[mixed ? 1 : 0][flags & 7](d_sims, n, lds, helpers, st);
     return hipGetLastError();
 }
 

@@ -131,6 +131,14 @@ struct SimDev {
     const int32_t *lvl_rows_ptr;      // [n_levels+1] into rows (columns of each level)
     const int32_t *lvl_gat_ptr;       // [n_levels+1] into bgat
     const int32_t *lvl_bwd_ptr;       // [n_levels+1] into bwd items (column pairs of each level)
+    // L2 prefetch for the forward pass (meshes whose factor of P overflows L2):
+    // the solving workgroup publishes (epoch << 40 | iteration * 2 levels + phase)
+    // before each level of the two triangular solves; helpers touch the blocks
+    // of the next phase (forward phases read gval, backward phases gvalt)
+    int64_t *fwd_pos;
+    int64_t fwd_epoch;
+    const int32_t *fpf_ptr;           // [2 levels + 1] into fpf: phase l < L forward level l, L + j backward level L-1-j
+    const int64_t *fpf;               // [2 per range] offset and length (doubles) of a block
     int n_root_rows;                  // rows of root supernodes (no R_s): their forward product
     const int32_t *root_rows;         //   writes x_s into Y, copied to x at the end (3 i each)
     const int32_t *lvl_items_ptr;     // [n_levels+1] into fwd items

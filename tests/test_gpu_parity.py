@@ -338,3 +338,21 @@ def test_direct_adjoint_prefetch_workgroups_change_nothing(monkeypatch):
     for key in ("dx0", "dv0", "dw_edge", "dmu"):
         assert torch.equal(out["0"][key], out["4"][key]), key
         assert torch.equal(out["0"][key], out["7"][key]), key
+
+
+def test_forward_prefetch_workgroups_change_nothing(monkeypatch):
+    # forward prefetch workgroups (forced on a small mesh, alone and in a
+    # batched launch) only read: the trajectories are identical
+    from paper_2106_05306_amd.sim import batch_forward
+    sc = scenes.c2_sphere_drop(0, n=16, steps=12)
+    outs = {}
+    for h in ("0", "3"):
+        monkeypatch.setenv("DIFFCLOTH_FWD_HELPERS", h)
+        s = _sim(sc, precision="mixed", adj_solver="direct")
+        _, _, traj = s.forward(sc.steps, trajectory=True)
+        b = [_sim(c, precision="mixed", adj_solver="direct") for c in scenes.c4_batch(seed=1, count=3, steps=8, n_lo=6, n_hi=12)]
+        batch_forward(b, [8, 8, 8])
+        outs[h] = (traj, [bb.state(8)[0] for bb in b])
+    assert torch.equal(outs["0"][0], outs["3"][0])
+    for x0, x3 in zip(outs["0"][1], outs["3"][1]):
+        assert torch.equal(x0, x3)
