@@ -817,6 +817,8 @@ void build_device(sim *s) {
         D.adj_pf = upload(s, pfl);
         D.adj_pfptr = upload(s, pfptr);
         D.adj_pos = zeros<int64_t>(s, 1);
+        D.adj_hz = zeros<double>(s, 3 * (size_t)m);
+        D.adj_dwc = zeros<double>(s, (size_t)std::max(nca, 1));
         D.lu_rows = upload(s, ri);
         D.lu_upd_off = upload(s, auo);
         D.af_size = off;

@@ -647,9 +647,9 @@ __device__ __forceinline__ void apply_TT(const SimDev &S, auto mode, auto zeta, 
 }
 
 // u_c = G_c (A_c z) with G_c = s_c (I - qhat qhat^T) (the Delta P blocks)
+// dw_mode 1: dL/dw_c += h (A_c z).(p_c - q_c); 2: (A_c z).(p_c - q_c) kept in adj_dwc
 template <bool MIXED>
-__device__ __forceinline__ void projection_jacobian_apply(const SimDev &S, auto z, auto u, bool accumulate_dw,
-                                                 double h) {
+__device__ __forceinline__ void projection_jacobian_apply(const SimDev &S, auto z, auto u, int dw_mode, double h) {
     for (int c = threadIdx.x; c < S.nca; c += (int)blockDim.x) {
         double a0 = 0, a1 = 0, a2 = 0;
         for (int p = G(S.c_ptr)[c]; p < G(S.c_ptr)[c + 1]; ++p) {
@@ -675,9 +675,11 @@ __device__ __forceinline__ void projection_jacobian_apply(const SimDev &S, auto 
             u[3 * c + 1] = sc * (a1 - qd * qh[1]);
             u[3 * c + 2] = sc * (a2 - qd * qh[2]);
         }
-        if (accumulate_dw) {
+        if (dw_mode) {
             const auto pq = G(S.adj_pq) + 3 * c;
-            G(S.dw)[G(S.c_id)[c]] += h * (a0 * pq[0] + a1 * pq[1] + a2 * pq[2]);
+            const double dot = a0 * pq[0] + a1 * pq[1] + a2 * pq[2];
+            if (dw_mode == 1) G(S.dw)[G(S.c_id)[c]] += h * dot;
+            else G(S.adj_dwc)[c] = dot;
         }
     }
 }
@@ -721,12 +723,14 @@ __device__ __forceinline__ void adjoint_rhs(const SimDev &S, auto gbar, auto u, 
     }
 }
 
-// out = A v = M v + H T^T v with H = h^2 K_s - Delta P (the contact adjoint operator)
-template <bool MIXED>
+// out = A v = M v + H T^T v with H = h^2 K_s - Delta P (the contact adjoint operator).
+// KEEP: also keep H z (adj_hz) and the weight-gradient dot products (adj_dwc)
+// of z = T^T v, which the step's gradients reuse (z and ΔP z stay in zt, wp).
+template <bool MIXED, bool KEEP = false>
 __device__ __forceinline__ void apply_adjoint_operator(const SimDev &S, auto mode, auto vin, auto out) {
     apply_TT(S, mode, vin, G(S.zt));
     __syncthreads();
-    projection_jacobian_apply<MIXED>(S, G(S.zt), G(S.wp), false, S.h);
+    projection_jacobian_apply<MIXED>(S, G(S.zt), G(S.wp), KEEP ? 2 : 0, S.h);
     __syncthreads();
     const double hh = S.h * S.h;
     for (int i = threadIdx.x; i < S.m; i += (int)blockDim.x) {
@@ -746,6 +750,11 @@ __device__ __forceinline__ void apply_adjoint_operator(const SimDev &S, auto mod
         out[3 * i] = mi * vin[3 * i] + hh * k0 - r0;
         out[3 * i + 1] = mi * vin[3 * i + 1] + hh * k1 - r1;
         out[3 * i + 2] = mi * vin[3 * i + 2] + hh * k2 - r2;
+        if constexpr (KEEP) {
+            G(S.adj_hz)[3 * i] = hh * k0 - r0;
+            G(S.adj_hz)[3 * i + 1] = hh * k1 - r1;
+            G(S.adj_hz)[3 * i + 2] = hh * k2 - r2;
+        }
     }
     __syncthreads();
 }
@@ -1580,7 +1589,7 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
             int k = 1;
             bool ok = false;
             while (true) {
-                apply_adjoint_operator<MIXED>(S, mode, zeta, zeta1);
+                apply_adjoint_operator<MIXED, true>(S, mode, zeta, zeta1);
                 double rmax = 0.0, zmax = 0.0;
                 for (int i = threadIdx.x; i < 3 * m; i += (int)blockDim.x) {
                     zeta1[i] = gbar[i] - zeta1[i];
@@ -1612,7 +1621,7 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
         while (k < S.adj_max_iters) {
             apply_TT(S, mode, zeta, G(S.zt));
             __syncthreads();
-            projection_jacobian_apply<MIXED>(S, G(S.zt), G(S.wp), false, h);
+            projection_jacobian_apply<MIXED>(S, G(S.zt), G(S.wp), 0, h);
             __syncthreads();
             adjoint_rhs<MIXED>(S, gbar, G(S.wp), zeta, G(S.zt), T);
             __syncthreads();
@@ -1649,31 +1658,43 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
             (void)stalled;
         }
         }
-        // gradients of this step
-        apply_TT(S, mode, zeta, G(S.zt));
-        __syncthreads();
-        projection_jacobian_apply<MIXED>(S, G(S.zt), G(S.wp), true, h);
-        inactive_dw(S, G(S.zt), x1, h);
-        __syncthreads();
+        // gradients of this step; the direct solve's last backward-error check
+        // (always of the final zeta) left z = T^T zeta in zt, H z in adj_hz and
+        // the weight-gradient dot products in adj_dwc
+        if constexpr (direct) {
+            for (int c = threadIdx.x; c < S.nca; c += (int)blockDim.x) G(S.dw)[G(S.c_id)[c]] += h * G(S.adj_dwc)[c];
+            inactive_dw(S, G(S.zt), x1, h);
+        } else {
+            apply_TT(S, mode, zeta, G(S.zt));
+            __syncthreads();
+            projection_jacobian_apply<MIXED>(S, G(S.zt), G(S.wp), 1, h);
+            inactive_dw(S, G(S.zt), x1, h);
+            __syncthreads();
+        }
         double dmu_local[kMaxObstacles];
         for (int o = 0; o < kMaxObstacles; ++o) dmu_local[o] = 0.0;
         const bool has_gstep = S.gx_steps != nullptr;
         const auto gstep = G(S.gx_steps) + (has_gstep ? (int64_t)n * 3 * m : 0);
         for (int i = threadIdx.x; i < m; i += (int)blockDim.x) {
             const auto z = G(S.zt) + 3 * i;
-            double r0 = 0, r1 = 0, r2 = 0;      // Delta P z
-            for (int p = G(S.inc_ptr)[i]; p < G(S.inc_ptr)[i + 1]; ++p) {
-                const int c = G(S.inc_con)[p];
-                const double a = G(S.inc_coef)[p];
-                r0 += a * G(S.wp)[3 * c]; r1 += a * G(S.wp)[3 * c + 1]; r2 += a * G(S.wp)[3 * c + 2];
+            double Hz[3];
+            if constexpr (direct) {
+                Hz[0] = G(S.adj_hz)[3 * i]; Hz[1] = G(S.adj_hz)[3 * i + 1]; Hz[2] = G(S.adj_hz)[3 * i + 2];
+            } else {
+                double r0 = 0, r1 = 0, r2 = 0;      // Delta P z
+                for (int p = G(S.inc_ptr)[i]; p < G(S.inc_ptr)[i + 1]; ++p) {
+                    const int c = G(S.inc_con)[p];
+                    const double a = G(S.inc_coef)[p];
+                    r0 += a * G(S.wp)[3 * c]; r1 += a * G(S.wp)[3 * c + 1]; r2 += a * G(S.wp)[3 * c + 2];
+                }
+                double k0 = 0, k1 = 0, k2 = 0;      // K_s z
+                for (int p = G(S.ks_ptr)[i]; p < G(S.ks_ptr)[i + 1]; ++p) {
+                    const int j = G(S.ks_col)[p];
+                    const double kv = MIXED ? (double)G(S.ks_valf)[p] : G(S.ks_val)[p];
+                    k0 += kv * G(S.zt)[3 * j]; k1 += kv * G(S.zt)[3 * j + 1]; k2 += kv * G(S.zt)[3 * j + 2];
+                }
+                Hz[0] = hh * k0 - r0; Hz[1] = hh * k1 - r1; Hz[2] = hh * k2 - r2;
             }
-            double k0 = 0, k1 = 0, k2 = 0;      // K_s z
-            for (int p = G(S.ks_ptr)[i]; p < G(S.ks_ptr)[i + 1]; ++p) {
-                const int j = G(S.ks_col)[p];
-                const double kv = MIXED ? (double)G(S.ks_valf)[p] : G(S.ks_val)[p];
-                k0 += kv * G(S.zt)[3 * j]; k1 += kv * G(S.zt)[3 * j + 1]; k2 += kv * G(S.zt)[3 * j + 2];
-            }
-            const double Hz[3] = {hh * k0 - r0, hh * k1 - r1, hh * k2 - r2};
             const double mi = G(S.mass)[i];
             double dx[3];
             for (int d = 0; d < 3; ++d) dx[d] = G(S.gx)[3 * i + d] - Hz[d] / h;

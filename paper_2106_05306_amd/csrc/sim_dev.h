@@ -229,6 +229,8 @@ struct SimDev {
     // solving workgroup publishes its position (epoch << 40 | step * phases +
     // phase, all ones below bit 40 when done); helper workgroups on its XCD
     // touch the blocks of the next phase
+    double *adj_hz;                   // direct adjoint: H T^T zeta of the last check (3m)
+    double *adj_dwc;                  //   and its weight-gradient dot products (one per active constraint)
     int64_t *adj_pos;
     int64_t adj_epoch;
     const int32_t *adj_pfptr;         // [3 levels + 1] into adj_pf, by phase id
