@@ -137,13 +137,17 @@ class Model:
     P = P_s (x) I_3 with the scalar m x m matrix P_s."""
 
     def __init__(self, scene, edge_stiffness=None, bend_weight=None, region_scale=None,
-                 mu=None, h=None):
+                 mu=None, h=None, force=None, force_scale=None):
         self.scene = scene
         self.X = np.asarray(scene.X, float)
         self.m = self.X.shape[0]
         self.h = float(scene.h if h is None else h)
         self.g = np.asarray(scene.gravity, float)
         self.mass = np.asarray(scene.node_mass, float)
+        F = scene.force if force is None else force
+        self.force = np.zeros((self.m, 3)) if F is None else np.asarray(F, float).reshape(self.m, 3)
+        fs = scene.force_scale if force_scale is None else force_scale
+        self.force_scale = None if fs is None else np.asarray(fs, float)
         edges = np.asarray(scene.edges if scene.edges is not None else triangle_edges(scene.tris),
                            np.int64)
         self.edges = edges
@@ -199,6 +203,16 @@ class Model:
         self.lu = spla.splu(self.P_s)                            # "prefactorized" P
 
     # ----------------------------------------------------------------- helpers
+    def force_at(self, n: int) -> np.ndarray:
+        """External force besides gravity during step n: s_n F (part of f_ext in
+        eqn implicit_euler; a time-invariant field F scaled per step)."""
+        s = 1.0 if self.force_scale is None else float(self.force_scale[n])
+        return s * self.force
+
+    def external_accel(self, n: int) -> np.ndarray:
+        """M^{-1} f_ext during step n: gravity plus the external force."""
+        return self.g + self.force_at(n) / self.mass[:, None]
+
     def attach_targets(self, t: float) -> np.ndarray:
         sc = self.scene
         R = rotation(sc.attach_axis, sc.attach_omega * t)
@@ -225,9 +239,9 @@ class Model:
 
 # =========================================================================== forward
 
-def inertial_predictor(model: Model, x: np.ndarray, v: np.ndarray) -> np.ndarray:
-    """y = x_n + h v_n + h^2 M^{-1} f_ext with f_ext = M g (eqn implicit_energy)."""
-    return x + model.h * v + model.h ** 2 * model.g
+def inertial_predictor(model: Model, x: np.ndarray, v: np.ndarray, n: int = 0) -> np.ndarray:
+    """y = x_n + h v_n + h^2 M^{-1} f_ext with f_ext = M g + s_n F (eqn implicit_energy)."""
+    return x + model.h * v + model.h ** 2 * model.external_accel(n)
 
 
 def detect_contacts(model: Model, x: np.ndarray, y: np.ndarray):
@@ -269,12 +283,13 @@ def local_projection(model: Model, x: np.ndarray):
     return p, q
 
 
-def constant_rhs(model: Model, x: np.ndarray, v: np.ndarray, t1: float) -> np.ndarray:
+def constant_rhs(model: Model, x: np.ndarray, v: np.ndarray, t1: float, n: int = 0) -> np.ndarray:
     """b_hat minus the parts that change inside the step (eqn pd_velocity):
-    (b(p) - P x_n)/h = M v_n + h M g - (P - M) x_n / h + h sum_att w t_j(t_{n+1})
-    + h sum_i w_i A_i^T p_i, of which the last sum is added per iteration."""
+    (b(p) - P x_n)/h = M v_n + h f_ext - (P - M) x_n / h + h sum_att w t_j(t_{n+1})
+    + h sum_i w_i A_i^T p_i with f_ext = M g + s_n F, of which the last sum is
+    added per iteration."""
     h = model.h
-    r = model.mass[:, None] * v + h * model.mass[:, None] * model.g
+    r = model.mass[:, None] * v + h * (model.mass[:, None] * model.g + model.force_at(n))
     r -= h * (model.K_s @ x)
     if model.attach.size:
         np.add.at(r, model.attach, h * model.w_att * model.attach_targets(t1))
@@ -320,11 +335,11 @@ def forward_step(model: Model, x: np.ndarray, v: np.ndarray, n: int, iters: Opti
     per-node Signorini-Coulomb update after each global step."""
     h = model.h
     t1 = (n + 1) * h
-    y = inertial_predictor(model, x, v)
+    y = inertial_predictor(model, x, v, n)
     nodes, obst, normal, gap, mu = detect_contacts(model, x, y)
     C = nodes.size
-    bhat0 = constant_rhs(model, x, v, t1)
-    vk = v + h * model.g                                      # v^0: x^0 = y
+    bhat0 = constant_rhs(model, x, v, t1, n)
+    vk = v + h * model.external_accel(n)                      # v^0: x^0 = y
     f = np.zeros((C, 3))
     ubar = np.zeros((C, 3))
     mode = np.full(C, TAKEOFF, np.int8)
@@ -556,6 +571,8 @@ class Gradients:
     dw: np.ndarray          # per constraint: springs first, then bending
     dmu: np.ndarray         # per obstacle
     dregion: Optional[np.ndarray] = None
+    dforce: Optional[np.ndarray] = None         # (m, 3) dL/dF
+    dforce_scale: Optional[np.ndarray] = None   # (T,) dL/ds_n
 
     @property
     def dk_spring(self):
@@ -565,7 +582,13 @@ class Gradients:
 def backward(model: Model, recs: List[StepRecord], dL_dxT: np.ndarray, dL_dvT=None,
              dL_dx_steps=None, direct: bool = True) -> Gradients:
     """Backpropagation through the whole rollout (Sec. 4.1, eqn adjoint): the
-    per-step adjoints chained from the last step to the first."""
+    per-step adjoints chained from the last step to the first.
+
+    External force: v_n and f_ext,n enter step n only through b_hat (as M v_n
+    and h f_ext,n; eqn pd_velocity) and through the predictor and the initial
+    guess, which the adjoint of the converged step does not see, so
+    dL/df_ext,n = h M^{-1} dL/dv_n = h z_n.  With f_ext,n = s_n F this gives
+    dL/dF = h sum_n s_n z_n and dL/ds_n = h F . z_n."""
     gx = np.asarray(dL_dxT, float).copy()
     if dL_dx_steps is not None:                               # a per-step loss term on x_T as well
         gx = gx + dL_dx_steps[len(recs)]
@@ -573,10 +596,16 @@ def backward(model: Model, recs: List[StepRecord], dL_dxT: np.ndarray, dL_dvT=No
     dw = np.zeros(model.nc)
     dmu = np.zeros(len(model.obstacles))
     T = len(recs)
+    dF = np.zeros((model.m, 3))
+    ds = np.zeros(T)
     for n in range(T - 1, -1, -1):
         dx, dv, dwn, dmun, _ = backward_step(model, recs[n], gx, gv, n, direct=direct)
         dw += dwn
         dmu += dmun
+        hz = model.h * dv / model.mass[:, None]               # h z_n = dL/df_ext,n
+        s = 1.0 if model.force_scale is None else model.force_scale[n]
+        dF += s * hz
+        ds[n] = np.sum(model.force * hz)
         gx, gv = dx, dv
         if dL_dx_steps is not None:
             gx = gx + dL_dx_steps[n]
@@ -584,7 +613,7 @@ def backward(model: Model, recs: List[StepRecord], dL_dxT: np.ndarray, dL_dvT=No
     if model.region is not None:
         dregion = np.zeros(model.region_scale.size)
         np.add.at(dregion, model.region, dw * model.base_w)
-    return Gradients(gx, gv, dw, dmu, dregion)
+    return Gradients(gx, gv, dw, dmu, dregion, dF, ds)
 
 
 # =========================================================================== losses

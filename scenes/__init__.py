@@ -67,6 +67,10 @@ class Scene:
     edge_region: Optional[np.ndarray] = None
     bend_region: Optional[np.ndarray] = None
     region_scale: Optional[np.ndarray] = None
+    # Optional external force besides gravity: node j receives force_scale[n] * force[j]
+    # (newtons) during step n (force_scale None: 1 at every step).
+    force: Optional[np.ndarray] = None           # (m, 3)
+    force_scale: Optional[np.ndarray] = None     # (steps,)
     # Loss description (inputs only; each side evaluates it itself).
     loss: str = "centroid"          # "centroid" | "apex"
     target: Optional[np.ndarray] = None          # centroid target (3,)
@@ -176,6 +180,45 @@ def c2_sphere_drop(seed: int = 0, n: int = 40, steps: int = 200) -> Scene:
         node_mass=np.full(m, AREAL_DENSITY / m), v0=np.zeros((m, 3)), steps=steps,
         obstacles=[Obstacle(SPHERE, (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 0.25, mu)],
         target=_centroid_target(rng, X), seed=seed)
+
+
+def wind_napkin(seed: int = 0, n: int = 24, steps: int = 200, h: float = 1.0 / 90.0) -> Scene:
+    """Hanging napkin under a synthetic wind (the Wind benchmark's setting:
+    h = 1/90 s, 200 steps): n x n square cloth, 1 m side, hanging in the
+    xy-plane from its two top corners; every node receives the force
+    s_n * d * m_j / mean(m) with d a seeded 3-vector (|d| ~ 0.3 m_j g) and the
+    gust profile s_n = 0.5 [sin(omega t_{n+1} + phase) + 1] (the T-shirt wind
+    model), omega and phase seeded; no obstacle."""
+    rng = np.random.default_rng(seed)
+    Xg, tris, edges = grid_mesh(n, 1.0, (0.0, 0.0, 0.0))
+    X = np.stack([Xg[:, 0], 1.0 - Xg[:, 2], np.zeros(Xg.shape[0])], axis=1)
+    m = X.shape[0]
+    mass = np.full(m, AREAL_DENSITY / m)
+    d = rng.normal(0.0, 1.0, 3)
+    d[2] = abs(d[2]) + 1.0                   # blowing mostly through the cloth
+    d *= 0.3 * 9.8 * mass[0] / np.linalg.norm(d)
+    omega = float(rng.uniform(2.0, 8.0))
+    phase = float(rng.uniform(0.0, 2.0 * math.pi))
+    t1 = (np.arange(steps) + 1) * h
+    return Scene(
+        name=f"wind{n}x{n}", X=X, tris=tris, edges=edges,
+        edge_stiffness=_log_uniform(rng, 5.0e2, 5.0e3, edges.shape[0]),
+        node_mass=mass, v0=np.zeros((m, 3)), steps=steps, h=h,
+        attach=np.array([0, (n - 1) * n], np.int32),
+        force=np.tile(d, (m, 1)), force_scale=0.5 * (np.sin(omega * t1 + phase) + 1.0),
+        target=_centroid_target(rng, X), seed=seed)
+
+
+def flying_napkin(seed: int = 0, n: int = 10, steps: int = 60) -> Scene:
+    """The napkin above the ground plane with a time-invariant external force on
+    every node (3 n^2 force variables; the Flying Napkin control problem):
+    forces normal with deviation 0.3 m_j g per component, no pins."""
+    s = c1_napkin(seed, n, steps)
+    rng = np.random.default_rng(seed + 1000)
+    s.name = f"flying_napkin{n}x{n}"
+    s.attach = np.zeros(0, np.int32)
+    s.force = rng.normal(0.0, 0.3 * 9.8, (s.n_nodes, 3)) * s.node_mass[:, None]
+    return s
 
 
 def c3_skirt(seed: int = 0, n_around: int = 40, n_rings: int = 91, steps: int = 125,

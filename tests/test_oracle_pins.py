@@ -525,3 +525,85 @@ def test_per_step_loss_terms_match_finite_differences():
     e = 1e-6
     fd = (loss(sc.v0 + e * d)[2] - loss(sc.v0 - e * d)[2]) / (2 * e)
     assert abs(fd - np.sum(G.dv0 * d)) <= 1e-6 * abs(fd) + 1e-12
+
+
+# ------------------------------------------------------------------ external force (wind) parameters
+
+def _uniform_accel_scene(seed, steps=9):
+    # no pins, no obstacle, uniform masses: a force proportional to each node's mass
+    # moves the rest shape rigidly (every constraint stays at its rest value)
+    sc = scenes.tiny_scene(4, steps=steps, obstacle=None, seed=seed)
+    rng = np.random.default_rng(seed)
+    d = rng.normal(size=3)
+    sc.force = sc.node_mass[:, None] * d[None, :]
+    sc.force_scale = rng.uniform(0.2, 1.5, steps)
+    return sc, d
+
+
+def test_uniform_external_force_translates_rigidly():
+    sc, d = _uniform_accel_scene(21)
+    recs = O.rollout(O.Model(sc))
+    T, h, g, s = sc.steps, sc.h, np.asarray(sc.gravity), sc.force_scale
+    # v_{k+1} = v_k + h (g + s_k d), x_T = x_0 + h sum_k v_{k+1}
+    acc = np.cumsum(s)                                      # sum_{n <= k} s_n
+    expect = sc.X + h * h * (g * T * (T + 1) / 2 + d * np.sum(acc))
+    assert np.allclose(recs[-1].x1, expect, rtol=0, atol=1e-12)
+
+
+def test_external_force_gradients_closed_form():
+    # centroid loss of a rigid translation: x_T shifts by h^2 (T - n) d per unit of
+    # s_n, and by h^2 sum_n s_n (T - n) e per unit of a force m_j e on every node
+    sc, d = _uniform_accel_scene(22)
+    model = O.Model(sc)
+    recs = O.rollout(model)
+    L, g = O.centroid_loss(model, recs[-1].x1, sc.target)
+    G = O.backward(model, recs, g)
+    T, h = sc.steps, sc.h
+    c = recs[-1].x1.mean(axis=0) - sc.target
+    n = np.arange(T)
+    expect_ds = 2.0 * float(c @ d) * h * h * (T - n)
+    assert np.allclose(G.dforce_scale, expect_ds, rtol=1e-9, atol=1e-15)
+    for e in np.eye(3):
+        got = float(np.sum(G.dforce * (sc.node_mass[:, None] * e[None, :])))
+        want = 2.0 * float(c @ e) * h * h * float(np.sum(sc.force_scale * (T - n)))
+        assert abs(got - want) <= 1e-9 * abs(want) + 1e-15, (got, want)
+
+
+@pytest.mark.parametrize("obst", ["plane", "sphere", None])
+def test_external_force_gradients_match_finite_differences(obst):
+    sc = scenes.tiny_scene(3, steps=8, obstacle=obst, k=50.0, mu=0.4, seed=3, height=0.005,
+                           v0_scale=0.05, bend=0.02, pins=obst is None)
+    rng = np.random.default_rng(7)
+    F0 = rng.normal(0.0, 0.5 * 9.8, (sc.n_nodes, 3)) * sc.node_mass[:, None]
+    s0 = rng.uniform(0.3, 1.2, sc.steps)
+    model, recs, L, g = converged_loss(sc, force=F0, force_scale=s0)
+    G = O.backward(model, recs, g)
+    assert G.dforce.shape == (sc.n_nodes, 3) and G.dforce_scale.shape == (sc.steps,)
+    base_modes = modes_of(recs)
+    checks = 0
+
+    def fd(eps, **kw):
+        _, rp, Lp, _ = converged_loss(sc, **{k: v[0] for k, v in kw.items()})
+        _, rm, Lm, _ = converged_loss(sc, **{k: v[1] for k, v in kw.items()})
+        if modes_of(rp) != base_modes or modes_of(rm) != base_modes:
+            return None
+        return (Lp - Lm) / (2 * eps)
+
+    for _ in range(2):
+        dF = rng.normal(size=F0.shape) * sc.node_mass[:, None]
+        e = 1e-3
+        val = fd(e, force=(F0 + e * dF, F0 - e * dF), force_scale=(s0, s0))
+        if val is not None:
+            ad = float(np.sum(G.dforce * dF))
+            assert abs(val - ad) <= 1e-5 * abs(val) + 1e-12, (val, ad)
+            checks += 1
+    for n in (0, 3, sc.steps - 1):
+        e = 1e-5
+        up, dn = s0.copy(), s0.copy()
+        up[n] += e
+        dn[n] -= e
+        val = fd(e, force=(F0, F0), force_scale=(up, dn))
+        if val is not None:
+            assert abs(val - G.dforce_scale[n]) <= 1e-5 * abs(val) + 1e-12, (n, val, G.dforce_scale[n])
+            checks += 1
+    assert checks >= 3
