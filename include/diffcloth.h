@@ -168,6 +168,10 @@ typedef struct {
                                      node j); 0 for boundary nodes            */
     double *dregion;  /* [n_regions] dL/d(region_scale)                        */
     double *dmu;      /* [n_obstacles] dL/d(mu)                                */
+    double *dforce;   /* [n_nodes*3] dL/dF of the external force field F (see
+                         sim_set_external_force); zeros when no force is set  */
+    double *dforce_scale; /* [T] dL/ds_n of its per-step multipliers over the
+                         T recorded steps; zeros when no force is set          */
 } sim_grads_t;
 
 typedef struct {
@@ -204,6 +208,25 @@ typedef void  (*sim_free_fn)(void *ptr, void *ctx);
  * non-positive pivot, SIM_ENOMEM / SIM_EHIP on device failures. */
 int sim_create(const sim_mesh_t *mesh, const sim_params_t *params, void *hip_stream,
                sim_alloc_fn alloc, sim_free_fn free_fn, void *alloc_ctx, sim_t **out);
+
+/* External force besides gravity, part of f_ext in the implicit Euler step
+ * (Sec. 3.1): during step n node j receives scale[n] * force[j] newtons, which
+ * enters the inertial predictor, the initial guess and the constant part of the
+ * right-hand side b_hat (eqn pd_velocity); the applications' wind models
+ * (Sec. 6: a sinusoidal gust times a direction, per-node coefficients) and the
+ * time-invariant per-node control forces of Sec. 5 are of this form.
+ *  force_dev   device [n_nodes*3] (caller order), copied on the handle's
+ *              stream; NULL removes the external force;
+ *  scale_host  host [n_scale] per-step multipliers s_n, copied before return;
+ *              NULL: s_n = 1 at every step (n_scale ignored); n_scale >= 1
+ *              otherwise.
+ * A later forward pass over more than n_scale steps returns SIM_EINVAL.
+ * The backward pass then also returns dL/dF = h sum_n s_n z_n and
+ * dL/ds_n = h F . z_n (z_n = T^T zeta of step n; sim_grads_t.dforce,
+ * dforce_scale).  Invalidates any recorded rollout.  SIM_EINVAL on a NULL
+ * handle, n_scale < 1 with a scale, or a non-finite multiplier; SIM_ENOMEM /
+ * SIM_EHIP on device failures. */
+int sim_set_external_force(sim_t *sim, const double *force_dev, int32_t n_scale, const double *scale_host);
 
 /* Sets the initial state (device arrays [n_nodes*3], caller order).  NULL x0
  * = rest shape; NULL v0 = zero.  Invalidates any recorded rollout. */

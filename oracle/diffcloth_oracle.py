@@ -579,6 +579,14 @@ class Gradients:
         return self.dw
 
 
+def force_gradients_of_step(model: Model, n: int, dL_dvn: np.ndarray):
+    """Step n's share of dL/dF and dL/ds_n from dL/dv_n = M z_n: the external
+    force enters b_hat as h s_n F, next to M v_n, so dL/df_ext,n = h z_n."""
+    hz = model.h * dL_dvn / model.mass[:, None]
+    s = 1.0 if model.force_scale is None else float(model.force_scale[n])
+    return s * hz, float(np.sum(model.force * hz))
+
+
 def backward(model: Model, recs: List[StepRecord], dL_dxT: np.ndarray, dL_dvT=None,
              dL_dx_steps=None, direct: bool = True) -> Gradients:
     """Backpropagation through the whole rollout (Sec. 4.1, eqn adjoint): the
@@ -602,10 +610,8 @@ def backward(model: Model, recs: List[StepRecord], dL_dxT: np.ndarray, dL_dvT=No
         dx, dv, dwn, dmun, _ = backward_step(model, recs[n], gx, gv, n, direct=direct)
         dw += dwn
         dmu += dmun
-        hz = model.h * dv / model.mass[:, None]               # h z_n = dL/df_ext,n
-        s = 1.0 if model.force_scale is None else model.force_scale[n]
-        dF += s * hz
-        ds[n] = np.sum(model.force * hz)
+        dFn, ds[n] = force_gradients_of_step(model, n, dv)
+        dF += dFn
         gx, gv = dx, dv
         if dL_dx_steps is not None:
             gx = gx + dL_dx_steps[n]

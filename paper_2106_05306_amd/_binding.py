@@ -46,7 +46,7 @@ class SimParams(Structure):
 
 class SimGrads(Structure):
     _fields_ = [("dx0", c_void_p), ("dv0", c_void_p), ("dw_edge", c_void_p), ("dw_bend", c_void_p),
-                ("dregion", c_void_p), ("dmu", c_void_p)]
+                ("dregion", c_void_p), ("dmu", c_void_p), ("dforce", c_void_p), ("dforce_scale", c_void_p)]
 
 
 class SimStats(Structure):
@@ -79,6 +79,7 @@ def lib():
                                      POINTER(c_void_p)]),
             "sim_set_state": (c_int32, [c_void_p, c_void_p, c_void_p]),
             "sim_set_material": (c_int32, [c_void_p, c_double_p, c_double_p, c_double_p, c_double_p]),
+            "sim_set_external_force": (c_int32, [c_void_p, c_void_p, c_int32, c_double_p]),
             "sim_forward": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
             "sim_backward": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, POINTER(SimGrads)]),
             "sim_adjoint_step": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,

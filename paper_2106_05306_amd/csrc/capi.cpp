@@ -49,6 +49,12 @@ struct sim {
     double *ckpt = nullptr;             // checkpoints: [n_seg][2][m*3]
     int ckpt_cap = 0;
     double *gsteps = nullptr;           // per-step loss gradients, new order
+    double *fext_buf = nullptr;         // external force field, new order
+    double *fscale_buf = nullptr;       // its per-step multipliers
+    int n_fscale = 0, fscale_cap = 0;
+    double *dfext_buf = nullptr;        // dL/d(force field), new order
+    double *dfscale_buf = nullptr;      // dL/d(multiplier) per step
+    int dfscale_cap = 0;
     int gsteps_cap = 0;
     const double *d_basew = nullptr;
     const int32_t *d_region = nullptr;
@@ -1064,6 +1070,51 @@ int sim_set_state(sim_t *s, const double *x0_dev, const double *v0_dev) {
 }
 
 
+int sim_set_external_force(sim_t *s, const double *force_dev, int32_t n_scale, const double *scale_host) {
+    if (!s) return SIM_EINVAL;
+    if (force_dev && scale_host) {
+        if (n_scale < 1) return SIM_EINVAL;
+        for (int n = 0; n < n_scale; ++n)
+            if (!std::isfinite(scale_host[n])) return SIM_EINVAL;
+    }
+    return guarded([&] {
+        int rc = hip_err(hipStreamSynchronize(s->stream));   // no pass still reads the old force
+        if (rc) return rc;
+        s->T = -1;
+        s->phase = 0;
+        s->prefactored = 0;
+        if (!force_dev) {
+            s->hd.fext = nullptr;
+            s->hd.fscale = nullptr;
+            s->n_fscale = 0;
+            return SIM_OK;
+        }
+        const int m = s->hd.m;
+        if (!s->fext_buf) s->fext_buf = (double *)dev_alloc(s, 3 * (size_t)m * sizeof(double));
+        rc = hip_err(launch_permute3(force_dev, s->fext_buf, s->d_perm, m, false, s->stream));
+        if (rc) return rc;
+        s->hd.fext = s->fext_buf;
+        s->hd.fscale = nullptr;
+        s->n_fscale = 0;
+        if (scale_host) {
+            if (s->fscale_cap < n_scale) {
+                dev_release(s, s->fscale_buf);
+                s->fscale_buf = nullptr;
+                s->fscale_cap = 0;
+                s->fscale_buf = (double *)dev_alloc(s, n_scale * sizeof(double));
+                s->fscale_cap = n_scale;
+            }
+            rc = hip_err(hipMemcpyAsync(s->fscale_buf, scale_host, n_scale * sizeof(double), hipMemcpyHostToDevice,
+                                        s->stream));
+            if (!rc) rc = hip_err(hipStreamSynchronize(s->stream));   // scale_host may go away on return
+            if (rc) return rc;
+            s->hd.fscale = s->fscale_buf;
+            s->n_fscale = n_scale;
+        }
+        return SIM_OK;
+    });
+}
+
 int sim_set_material(sim_t *s, const double *edge_stiffness, const double *bend_weight, const double *region_scale,
                      const double *obstacle_mu) {
     if (!s) return SIM_EINVAL;
@@ -1151,6 +1202,7 @@ namespace {
 
 // Prepare a handle for a forward pass of n_steps (records / checkpoints) and reset its state.
 int prepare_forward(sim *s, int n_steps) {
+    if (s->hd.fscale && n_steps > s->n_fscale) return SIM_EINVAL;   // multipliers run out
     if (fac_idle(s)) return SIM_EHIP;        // the records are about to be overwritten
     const int k = seg_len(s);
     const int cap = k > 0 ? std::min(k, n_steps) : n_steps;
@@ -1277,6 +1329,28 @@ int finish_forward(sim *s, int n_steps, double *xT_dev, double *vT_dev) {
     return rc;
 }
 
+// Zero the parameter-gradient accumulators of a backward pass over the T
+// recorded steps (weights, friction, external force).
+int zero_param_grads(sim *s) {
+    int rc = hip_err(launch_fill(s->hd.dw, 0.0, std::max(s->hm.nc, 1), s->stream));
+    if (!rc) rc = hip_err(launch_fill(s->hd.dmu, 0.0, kMaxObstacles, s->stream));
+    if (!rc && s->hd.fext) {
+        if (!s->dfext_buf) s->dfext_buf = (double *)dev_alloc(s, 3 * (size_t)s->hd.m * sizeof(double));
+        if (s->dfscale_cap < std::max(s->T, 1)) {
+            dev_release(s, s->dfscale_buf);
+            s->dfscale_buf = nullptr;
+            s->dfscale_cap = 0;
+            s->dfscale_buf = (double *)dev_alloc(s, std::max(s->T, 1) * sizeof(double));
+            s->dfscale_cap = std::max(s->T, 1);
+        }
+        s->hd.dfext = s->dfext_buf;
+        s->hd.dfscale = s->dfscale_buf;
+        rc = hip_err(launch_fill(s->hd.dfext, 0.0, 3 * (int64_t)s->hd.m, s->stream));
+        if (!rc) rc = hip_err(launch_fill(s->hd.dfscale, 0.0, s->dfscale_cap, s->stream));
+    }
+    return rc;
+}
+
 // Seed the adjoint: gx = dL/dx_T (+ per-step term at T), gv = dL/dv_T; zero the accumulators.
 int prepare_backward(sim *s, const double *dL_dxT, const double *dL_dvT, const double *dL_dx_steps) {
     const int m = s->hd.m, T = s->T;
@@ -1312,8 +1386,7 @@ int prepare_backward(sim *s, const double *dL_dxT, const double *dL_dvT, const d
         if (dL_dvT) rc = hip_err(launch_permute3(dL_dvT, s->hd.gv, s->d_perm, m, false, s->stream));
         else rc = hip_err(launch_fill(s->hd.gv, 0.0, (int64_t)v3, s->stream));
     }
-    if (!rc) rc = hip_err(launch_fill(s->hd.dw, 0.0, std::max(s->hm.nc, 1), s->stream));
-    if (!rc) rc = hip_err(launch_fill(s->hd.dmu, 0.0, kMaxObstacles, s->stream));
+    if (!rc) rc = zero_param_grads(s);
     if (!rc) rc = hip_err(hipMemsetAsync(s->hd.counters, 0, 8 * sizeof(int64_t), s->stream));
     return rc;
 }
@@ -1445,6 +1518,14 @@ int write_grads(sim *s, const sim_grads_t *out) {
                                         (int)s->hm.region_scale.size(), out->dregion, s->stream));
     if (!rc && out->dmu && s->hd.n_obst)
         rc = copy_d2d(s, out->dmu, s->hd.dmu, s->hd.n_obst * sizeof(double));
+    if (!rc && out->dforce) {
+        if (s->hd.fext) rc = hip_err(launch_permute3(s->hd.dfext, out->dforce, s->d_perm, m, true, s->stream));
+        else rc = hip_err(launch_fill(out->dforce, 0.0, 3 * (int64_t)m, s->stream));
+    }
+    if (!rc && out->dforce_scale && s->T > 0) {
+        if (s->hd.fext) rc = copy_d2d(s, out->dforce_scale, s->hd.dfscale, s->T * sizeof(double));
+        else rc = hip_err(launch_fill(out->dforce_scale, 0.0, s->T, s->stream));
+    }
     return rc;
 }
 
@@ -1503,8 +1584,7 @@ int sim_adjoint_step(sim_t *s, int32_t n, const double *gx_dev, const double *gv
         const int m = s->hd.m;
         int rc = hip_err(launch_permute3(gx_dev, s->hd.gx, s->d_perm, m, false, s->stream));
         if (!rc) rc = hip_err(launch_permute3(gv_dev, s->hd.gv, s->d_perm, m, false, s->stream));
-        if (!rc) rc = hip_err(launch_fill(s->hd.dw, 0.0, std::max(s->hm.nc, 1), s->stream));
-        if (!rc) rc = hip_err(launch_fill(s->hd.dmu, 0.0, kMaxObstacles, s->stream));
+        if (!rc) rc = zero_param_grads(s);
         if (!rc) rc = hip_err(hipMemsetAsync(s->hd.counters, 0, 8 * sizeof(int64_t), s->stream));
         s->hd.gx_steps = nullptr;
         s->hd.step_begin = n;

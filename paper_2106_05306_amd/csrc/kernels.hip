@@ -517,15 +517,22 @@ __global__ __launch_bounds__(kBlock) void k_forward(const SimDev *__restrict__ s
         const double t1 = (n + 1) * h;
         auto xrec = G(S.rec_x) + (int64_t)slot * 3 * m;
         auto vrec = G(S.rec_v) + (int64_t)slot * 3 * m;
-        // predictor, detection on y, constant right-hand side, initial guess
+        const double fs = S.fext == nullptr ? 0.0 : (S.fscale == nullptr ? 1.0 : G(S.fscale)[n]);
+        // predictor, detection on y, constant right-hand side, initial guess; the
+        // external force f_ext = M g + fs F enters all four
         for (int i = threadIdx.x; i < m; i += (int)blockDim.x) {
             const double xi[3] = {G(S.x)[3 * i], G(S.x)[3 * i + 1], G(S.x)[3 * i + 2]};
             const double vi[3] = {G(S.v)[3 * i], G(S.v)[3 * i + 1], G(S.v)[3 * i + 2]};
             if (n == S.step_begin) {
                 for (int d = 0; d < 3; ++d) { xrec[3 * i + d] = xi[d]; vrec[3 * i + d] = vi[d]; }
             }
+            const double mi = G(S.mass)[i];
+            double fe[3] = {0.0, 0.0, 0.0}, ae[3];           // external force, M^{-1} f_ext
+            if (S.fext != nullptr)
+                for (int d = 0; d < 3; ++d) fe[d] = fs * G(S.fext)[3 * i + d];
+            for (int d = 0; d < 3; ++d) ae[d] = S.g[d] + fe[d] / mi;
             double y[3];
-            for (int d = 0; d < 3; ++d) y[d] = xi[d] + h * vi[d] + h * h * S.g[d];
+            for (int d = 0; d < 3; ++d) y[d] = xi[d] + h * vi[d] + h * h * ae[d];
             double best = 0.0;
             int ob = -1;
             for (int o = 0; o < S.n_obst; ++o) {
@@ -543,9 +550,9 @@ __global__ __launch_bounds__(kBlock) void k_forward(const SimDev *__restrict__ s
                 kx1 += kv * G(S.x)[3 * j + 1];
                 kx2 += kv * G(S.x)[3 * j + 2];
             }
-            const double mi = G(S.mass)[i];
-            double b[3] = {mi * vi[0] + h * mi * S.g[0] - h * kx0, mi * vi[1] + h * mi * S.g[1] - h * kx1,
-                           mi * vi[2] + h * mi * S.g[2] - h * kx2};
+            double b[3] = {mi * vi[0] + h * (mi * S.g[0] + fe[0]) - h * kx0,
+                           mi * vi[1] + h * (mi * S.g[1] + fe[1]) - h * kx1,
+                           mi * vi[2] + h * (mi * S.g[2] + fe[2]) - h * kx2};
             const int as = G(S.att_of)[i];
             if (as >= 0) {
                 double tg[3];
@@ -555,7 +562,7 @@ __global__ __launch_bounds__(kBlock) void k_forward(const SimDev *__restrict__ s
             for (int d = 0; d < 3; ++d) {
                 G(S.b0)[3 * i + d] = b[d];
                 G(S.f)[3 * i + d] = 0.0;
-                A[3 * i + d] = vi[d] + h * S.g[d];
+                A[3 * i + d] = vi[d] + h * ae[d];
             }
             if constexpr ((FL & kLdsPositions) != 0)
                 for (int d = 0; d < 3; ++d) XN[3 * i + d] = xi[d];
@@ -1673,6 +1680,10 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
         }
         double dmu_local[kMaxObstacles];
         for (int o = 0; o < kMaxObstacles; ++o) dmu_local[o] = 0.0;
+        // external force: dL/df_ext,n = h z_n, so dL/dF += h s_n z_n and dL/ds_n = h F . z_n
+        const bool has_force = S.fext != nullptr;
+        const double fs = has_force && S.fscale != nullptr ? G(S.fscale)[n] : 1.0;
+        double fz = 0.0;
         const bool has_gstep = S.gx_steps != nullptr;
         const auto gstep = G(S.gx_steps) + (has_gstep ? (int64_t)n * 3 * m : 0);
         for (int i = threadIdx.x; i < m; i += (int)blockDim.x) {
@@ -1741,6 +1752,15 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
                 G(S.gx)[3 * i + d] = dx[d] + (has_gstep ? gstep[3 * i + d] : 0.0);
                 G(S.gv)[3 * i + d] = mi * z[d];
             }
+            if (has_force)
+                for (int d = 0; d < 3; ++d) {
+                    G(S.dfext)[3 * i + d] += h * fs * z[d];
+                    fz += G(S.fext)[3 * i + d] * z[d];
+                }
+        }
+        if (has_force) {
+            const double v = block_sum(fz, red);            // one fixed-order sum per step
+            if (threadIdx.x == 0) G(S.dfscale)[n] = h * v;
         }
         for (int o = 0; o < S.n_obst; ++o) {
             const double v = block_sum(dmu_local[o], red);   // one fixed-order sum per step

@@ -189,6 +189,12 @@ struct SimDev {
     double *dw;                       // [nc_total] accumulated weight gradients (canonical)
     double *dmu;                      // [kMaxObstacles]
     const double *gx_steps;           // optional per-step dL/dx_n [(T+1)*m*3], new order
+    // external force besides gravity: step n adds fscale[n] * fext (fext nullptr:
+    // none; fscale nullptr: 1 at every step), and its gradients
+    const double *fext;               // [m*3] new order
+    const double *fscale;             // [steps] per-step multipliers
+    double *dfext;                    // [m*3] dL/dfext, new order
+    double *dfscale;                  // [T] dL/dfscale[n]
 
     // Krylov fallback workspace (GMRES)
     double *kry;                      // [(kry_m+1) * m*3] Krylov basis

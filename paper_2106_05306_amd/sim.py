@@ -178,6 +178,9 @@ class Sim:
         v0 = np.asarray(getattr(scene, "v0", None) if getattr(scene, "v0", None) is not None else 0.0)
         if np.any(v0 != 0):
             sim.set_state(None, torch.as_tensor(np.broadcast_to(v0, (sim.m, 3)).copy(), dtype=torch.float64))
+        if getattr(scene, "force", None) is not None:
+            sim.set_external_force(torch.as_tensor(np.asarray(scene.force, np.float64)),
+                                   getattr(scene, "force_scale", None))
         return sim
 
     # ------------------------------------------------------------------ calls
@@ -212,6 +215,22 @@ class Sim:
         self.T = -1
         self._gen += 1
 
+    def set_external_force(self, force: Optional[torch.Tensor] = None, scale=None):
+        """External force besides gravity: node j receives scale[n] * force[j]
+        (newtons) during step n (scale None: 1 at every step; force None:
+        remove).  The backward pass then returns dforce (m, 3) and dforce_scale (T,)."""
+        f = None if force is None else force.to(self.device, torch.float64).reshape(self.m, 3).contiguous()
+        sc = None
+        if f is not None and scale is not None:
+            sc = np.ascontiguousarray(np.asarray(scale.detach().cpu() if torch.is_tensor(scale) else scale,
+                                                 dtype=np.float64).reshape(-1))
+        self._keep["force"] = f
+        B.check(B.lib().sim_set_external_force(self.h, _dptr(f), 0 if sc is None else sc.size,
+                                               None if sc is None else sc.ctypes.data_as(B.c_double_p)),
+                "sim_set_external_force")
+        self.T = -1
+        self._gen += 1
+
     def forward(self, n_steps: int, trajectory: bool = False):
         xT, vT = self._vec(), self._vec()
         traj = torch.empty((n_steps + 1, self.m, 3), dtype=torch.float64, device=self.device) if trajectory else None
@@ -225,9 +244,11 @@ class Sim:
                  dw_edge=torch.zeros(max(self.n_edges, 1), dtype=torch.float64, device=self.device),
                  dw_bend=torch.zeros(self.m, dtype=torch.float64, device=self.device),
                  dregion=torch.zeros(max(self.n_regions, 1), dtype=torch.float64, device=self.device),
-                 dmu=torch.zeros(max(self.n_obstacles, 1), dtype=torch.float64, device=self.device))
+                 dmu=torch.zeros(max(self.n_obstacles, 1), dtype=torch.float64, device=self.device),
+                 dforce=self._vec(),
+                 dforce_scale=torch.zeros(max(self.T, 1), dtype=torch.float64, device=self.device))
         s = B.SimGrads(*[ctypes.c_void_p(g[k].data_ptr()) for k in ("dx0", "dv0", "dw_edge", "dw_bend", "dregion",
-                                                                     "dmu")])
+                                                                     "dmu", "dforce", "dforce_scale")])
         return g, s
 
     def backward(self, dL_dxT: torch.Tensor, dL_dvT: Optional[torch.Tensor] = None,
@@ -280,6 +301,7 @@ class Sim:
         g["dw_edge"] = g["dw_edge"][:self.n_edges]
         g["dregion"] = g["dregion"][:self.n_regions]
         g["dmu"] = g["dmu"][:self.n_obstacles]
+        g["dforce_scale"] = g["dforce_scale"][:max(self.T, 0)]
         return g
 
     def state(self, n: int):
