@@ -297,6 +297,101 @@ def bench_skirt(args):
     print(json.dumps(result), flush=True)
 
 
+def bench_napkin_force(args):
+    """Flying napkin (the control problem of Sec. 5 with time-invariant forces
+    on every node): n x n napkins, n = 4, 5, 7, 10 (48, 75, 147 and 300 force
+    variables), 60 steps above the ground plane, K = 20, FP64, direct adjoint.
+    Per size: forward + adjoint rollouts per second with the gradient w.r.t.
+    every force variable, and that gradient's error against the oracle.  At
+    10 x 10 a central finite difference of the loss along a random force
+    direction (forward converged to 1e-10 m/s) checks the gradient end to end,
+    and the oracle's own forward + adjoint rollout is timed (one thread)."""
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except Exception:                                   # pragma: no cover
+        pass
+    import numpy as np
+    import torch
+
+    import scenes
+    from oracle import diffcloth_oracle as O
+    from paper_2106_05306_amd.sim import Sim
+
+    dev = torch.device("cuda:0")
+    sizes = []
+    for n in (4, 5, 7, 10):
+        sc = scenes.flying_napkin(0, n=n, steps=60)
+        sim = Sim.from_scene(sc, device=dev, precision="fp64", adj_solver="direct", adj_tol=1e-10,
+                             adj_max_iters=20)
+        target = torch.tensor(sc.target, device=dev)
+
+        def grad_once():
+            xT, _, _ = sim.forward(sc.steps)
+            d = xT.mean(dim=0) - target
+            g = (2.0 * d / sc.n_nodes).expand(sc.n_nodes, 3).contiguous()
+            return sim.backward(g)
+
+        out = grad_once()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            out = grad_once()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        model = O.Model(sc)
+        t0 = time.perf_counter()
+        recs = O.rollout(model)
+        L, gl = O.centroid_loss(model, recs[-1].x1, sc.target)
+        G = O.backward(model, recs, gl)
+        t_or = time.perf_counter() - t0
+        dF = out["dforce"].cpu().numpy()
+        err = float(np.linalg.norm(dF - G.dforce) / np.linalg.norm(G.dforce))
+        row = {"nodes": f"{n}x{n}", "force_variables": 3 * n * n, "ms_per_rollout": dt * 1e3,
+               "rollouts_per_s": 1.0 / dt, "status": int(out["status"]), "dforce_rel_err_vs_oracle": err,
+               "oracle_ms_per_rollout": t_or * 1e3}
+        print(f"napkin_force {row}", file=sys.stderr, flush=True)
+        sizes.append(row)
+        sim.close()
+    # end-to-end finite difference at 10 x 10 (forward converged)
+    sc = scenes.flying_napkin(0, n=10, steps=60)
+    simc = Sim.from_scene(sc, device=dev, precision="fp64", adj_solver="direct", adj_tol=1e-12, adj_max_iters=20,
+                          fwd_tol=1e-10, fwd_max_iters=100000)
+    target = torch.tensor(sc.target, device=dev)
+
+    def loss(sim):
+        xT, _, _ = sim.forward(sc.steps)
+        d = xT.mean(dim=0) - target
+        return float((d * d).sum()), (2.0 * d / sc.n_nodes).expand(sc.n_nodes, 3).contiguous()
+
+    _, g = loss(simc)
+    ad_F = simc.backward(g)["dforce"].cpu().numpy()
+    D = np.random.default_rng(1).normal(size=sc.force.shape) * sc.node_mass[:, None]
+    eps = 1e-4
+    vals = []
+    for sgn in (1.0, -1.0):
+        simc.set_external_force(torch.as_tensor(sc.force + sgn * eps * D), None)
+        vals.append(loss(simc)[0])
+    fd = (vals[0] - vals[1]) / (2 * eps)
+    ad = float(np.sum(ad_F * D))
+    last = sizes[-1]
+    result = {
+        "metric": "forward+adjoint rollouts/sec, flying napkin 10x10 (300 force variables)",
+        "value": last["rollouts_per_s"], "unit": "rollouts/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": last["ms_per_rollout"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "flying napkin n x n (n = 4, 5, 7, 10), 1 m side, 0.2 m above a ground plane "
+                               "(mu 0.5), time-invariant seeded force on every node, 60 steps h=1/120, K=20, "
+                               "centroid loss, direct adjoint (backward error 1e-10)", "precision": "fp64"},
+        "sizes": sizes,
+        "cpu_baseline": {"value": 1e3 / last["oracle_ms_per_rollout"], "unit": "rollouts/s", "cores": 1,
+                         "kind": "oracle", "sample": "one whole 10x10 rollout, forward + direct-solve adjoint"},
+        "finite_difference_check": {"size": "10x10", "forward": "converged to 1e-10 m/s", "eps": eps,
+                                    "fd": fd, "adjoint": ad, "rel_err": abs(fd - ad) / abs(fd)},
+    }
+    print(json.dumps(result), flush=True)
+
+
 def bench_serve(args):
     """Serving: forward + gradient requests on grids of round(exp(U[ln 20,
     ln 100])) nodes per side, 100-300 steps, sphere or plane; material fixed per
@@ -382,9 +477,11 @@ def main():
                     help="steps of the rollout the CPU oracle redoes (forward + adjoint): 'all' or a list")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, help="only run a device copy of this many bytes")
-    ap.add_argument("--workload", default="sphere_drop", choices=["sphere_drop", "batch", "serve", "skirt"],
+    ap.add_argument("--workload", default="sphere_drop",
+                    choices=["sphere_drop", "batch", "serve", "skirt", "napkin_force"],
                     help="sphere_drop: the 40x40 rollout (default); batch: 64 uneven rollouts in flight; "
-                         "serve: continuous-batching request server")
+                         "serve: continuous-batching request server; skirt: region-stiffness gradients; "
+                         "napkin_force: gradients w.r.t. per-node external forces")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--batch-window", type=int, default=50, help="adjoint steps per launch in the batch workload")
     ap.add_argument("--requests", type=int, default=40, help="requests of the serve workload")
@@ -408,6 +505,9 @@ def main():
         return
     if args.workload == "skirt":
         bench_skirt(args)
+        return
+    if args.workload == "napkin_force":
+        bench_napkin_force(args)
         return
 
     import numpy as np
