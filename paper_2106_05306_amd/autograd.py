@@ -12,7 +12,13 @@ to the inputs:
                   its region scale;
   region_scale    dL/ds_r = sum over the constraints c of region r of
                   dL/dw_c * (base weight of c);
-  mu              dL/dmu per obstacle.
+  mu              dL/dmu per obstacle;
+  force           dL/dF of the external force field (m, 3);
+  force_scale     dL/ds_n of its per-step multipliers (T,): node j receives
+                  force_scale[n] * force[j] during step n (Sec. 3.1, f_ext).
+                  A parametric wind model (a gust profile, a direction, per-node
+                  coefficients) is written in PyTorch on top of these two and
+                  its parameters' gradients follow by autograd.
 
 Material inputs (stiffness, bending weight, region scales, friction) are sent
 to the handle with ``Sim.set_material`` before the forward pass, which
@@ -35,17 +41,21 @@ def _host(t):
 class _Rollout(torch.autograd.Function):
     @staticmethod
     def forward(ctx, sim: Sim, n_steps: int, trajectory: bool, x0, v0, edge_stiffness, bend_weight, region_scale,
-                mu):
+                mu, force, force_scale):
         if any(t is not None for t in (edge_stiffness, bend_weight, region_scale, mu)):
             sim.set_material(_host(edge_stiffness), _host(bend_weight), _host(region_scale), _host(mu))
+        if force is not None:
+            sim.set_external_force(force.detach(), _host(force_scale))
+        elif force_scale is not None:
+            raise ValueError("force_scale needs a force field")
         sim.set_state(None if x0 is None else x0.detach(), None if v0 is None else v0.detach())
         xT, vT, traj = sim.forward(n_steps, trajectory=trajectory)
         ctx.sim = sim
         ctx.gen = sim._gen
         ctx.trajectory = trajectory
-        ctx.has = [t is not None for t in (x0, v0, edge_stiffness, bend_weight, region_scale, mu)]
-        ctx.dtypes = [None if t is None else (t.dtype, t.device) for t in
-                      (x0, v0, edge_stiffness, bend_weight, region_scale, mu)]
+        ins = (x0, v0, edge_stiffness, bend_weight, region_scale, mu, force, force_scale)
+        ctx.has = [t is not None for t in ins]
+        ctx.dtypes = [None if t is None else (t.dtype, t.device) for t in ins]
         if trajectory:
             return xT, vT, traj
         return xT, vT
@@ -63,7 +73,7 @@ class _Rollout(torch.autograd.Function):
         if out["status"] == 3:                  # SIM_WADJ_NONFINITE
             raise FloatingPointError("the rollout's adjoint overflowed (non-finite gradients); the forward "
                                      "steps are probably far from converged (raise pd_iters or set fwd_tol)")
-        res = [None] * 6
+        res = [None] * 8
         if ctx.has[0]:
             res[0] = out["dx0"]
         if ctx.has[1]:
@@ -81,6 +91,10 @@ class _Rollout(torch.autograd.Function):
             res[4] = out["dregion"]
         if ctx.has[5]:
             res[5] = out["dmu"]
+        if ctx.has[6]:
+            res[6] = out["dforce"]
+        if ctx.has[7]:
+            res[7] = out["dforce_scale"]
         for i, (r, dd) in enumerate(zip(res, ctx.dtypes)):
             if r is not None:
                 res[i] = r.to(dtype=dd[0], device=dd[1])
@@ -91,10 +105,11 @@ class _Rollout(torch.autograd.Function):
 def rollout(sim: Sim, n_steps: int, x0: Optional[torch.Tensor] = None, v0: Optional[torch.Tensor] = None, *,
             edge_stiffness: Optional[torch.Tensor] = None, bend_weight: Optional[torch.Tensor] = None,
             region_scale: Optional[torch.Tensor] = None, mu: Optional[torch.Tensor] = None,
+            force: Optional[torch.Tensor] = None, force_scale: Optional[torch.Tensor] = None,
             trajectory: bool = False):
     """Differentiable rollout of ``n_steps`` from (x0, v0) (None: rest shape,
     zero velocity).  Returns (x_T, v_T) or, with ``trajectory``, (x_T, v_T,
     x_0..x_T).  ``bend_weight`` is a one-element tensor.  The handle keeps
     one recorded rollout: back-propagate before running it again."""
     return _Rollout.apply(sim, int(n_steps), bool(trajectory), x0, v0, edge_stiffness, bend_weight, region_scale,
-                          mu)
+                          mu, force, force_scale)

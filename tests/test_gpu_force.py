@@ -155,3 +155,40 @@ def test_force_removed_and_scale_too_short():
     gb = plain.backward(torch.ones_like(b))
     assert torch.equal(ga["dx0"], gb["dx0"])
     assert not ga["dforce"].any() and not ga["dforce_scale"].any()
+
+
+def test_wind_model_parameters_through_autograd():
+    # the T-shirt wind of Sec. 6: every node receives 0.5 [sin(omega t + phi) + 1] d;
+    # gradients of (omega, phi, d) by autograd through the rollout vs central
+    # finite differences of the same GPU rollout with its forward converged
+    from paper_2106_05306_amd.autograd import rollout
+    sc = scenes.wind_napkin(6, n=6, steps=30)
+    sc.edge_stiffness = np.full(sc.edges.shape[0], 30.0)
+    sim = _sim(sc, precision="fp64", adj_solver="direct", fwd_tol=1e-11, fwd_max_iters=200000)
+    t1 = torch.tensor((np.arange(sc.steps) + 1) * sc.h, device=DEV)
+    target = torch.tensor(sc.target, device=DEV)
+    m = sc.n_nodes
+
+    def loss(theta):
+        omega, phi, d = theta[0], theta[1], theta[2:5]
+        s = 0.5 * (torch.sin(omega * t1 + phi) + 1.0)
+        F = d.expand(m, 3)
+        xT, _ = rollout(sim, sc.steps, force=F, force_scale=s)
+        c = xT.mean(dim=0) - target
+        return (c * c).sum()
+
+    d0 = torch.tensor(sc.force[0], device=DEV)
+    theta0 = torch.cat([torch.tensor([5.0, 0.7], dtype=torch.float64, device=DEV), d0])
+    th = theta0.clone().requires_grad_(True)
+    loss(th).backward()
+    ad = th.grad.cpu().numpy()
+    fd = np.zeros(5)
+    with torch.no_grad():
+        for k in range(5):
+            e = 1e-5 * max(abs(float(theta0[k])), 1e-3)
+            up, dn = theta0.clone(), theta0.clone()
+            up[k] += e
+            dn[k] -= e
+            fd[k] = (float(loss(up)) - float(loss(dn))) / (2 * e)
+    print("wind parameters: autograd", ad, "finite differences", fd)
+    assert np.all(np.abs(fd - ad) <= 1e-5 * np.abs(fd).max()), (ad, fd)
