@@ -44,7 +44,8 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 FREE, TAKEOFF, STICK, SLIP = 0, 1, 2, 3
-PLANE, SPHERE = 0, 1
+PLANE, SPHERE, MESH = 0, 1, 2
+FACE, VERTEX, EDGE = 0, 1, 2
 DEGENERATE_REL = 1e-12
 
 
@@ -227,14 +228,107 @@ class Model:
     def signed_distance(self, o, x: np.ndarray) -> np.ndarray:
         if o.kind == PLANE:
             return (x - np.asarray(o.point)) @ np.asarray(o.normal, float)
+        if o.kind == MESH:
+            return mesh_query(o, x)[0]
         d = x - np.asarray(o.point, float)
         return np.linalg.norm(d, axis=1) - o.radius
 
     def normal_at(self, o, x: np.ndarray) -> np.ndarray:
         if o.kind == PLANE:
             return np.tile(np.asarray(o.normal, float), (x.shape[0], 1))
+        if o.kind == MESH:
+            return mesh_query(o, x)[1]
         d = x - np.asarray(o.point, float)
         return d / np.linalg.norm(d, axis=1)[:, None]
+
+
+# =========================================================================== triangle-mesh obstacles
+
+def closest_point_on_triangle(p, a, b, c):
+    """Closest point of triangle abc to each point p (Voronoi-region tests of
+    Ericson, Real-Time Collision Detection, Sec. 5.1.5), vectorised over rows:
+    p, a, b, c are (N, 3).  Returns the point (N, 3), the region (FACE, VERTEX
+    or EDGE) and, for EDGE, the unit edge direction (N, 3; zeros otherwise).
+    The region tests run in the order vertex a, vertex b, edge ab, vertex c,
+    edge ac, edge bc, face; the first that holds decides."""
+    dot = lambda u, v: np.sum(u * v, axis=1)
+    ab, ac, ap = b - a, c - a, p - a
+    d1, d2 = dot(ab, ap), dot(ac, ap)
+    bp = p - b
+    d3, d4 = dot(ab, bp), dot(ac, bp)
+    cp = p - c
+    d5, d6 = dot(ab, cp), dot(ac, cp)
+    vc = d1 * d4 - d3 * d2
+    vb = d5 * d2 - d1 * d6
+    va = d3 * d6 - d5 * d4
+    N = p.shape[0]
+    q = np.zeros((N, 3))
+    region = np.full(N, -1, np.int8)
+    e = np.zeros((N, 3))
+    undecided = np.ones(N, bool)
+
+    def take(mask, point, reg, edge=None):
+        sel = undecided & mask
+        q[sel] = point[sel]
+        region[sel] = reg
+        if edge is not None:
+            e[sel] = edge[sel] / np.linalg.norm(edge[sel], axis=1)[:, None]
+        undecided[sel] = False
+
+    with np.errstate(divide="ignore", invalid="ignore"):
+        take((d1 <= 0) & (d2 <= 0), a, VERTEX)
+        take((d3 >= 0) & (d4 <= d3), b, VERTEX)
+        take((vc <= 0) & (d1 >= 0) & (d3 <= 0), a + (d1 / (d1 - d3))[:, None] * ab, EDGE, ab)
+        take((d6 >= 0) & (d5 <= d6), c, VERTEX)
+        take((vb <= 0) & (d2 >= 0) & (d6 <= 0), a + (d2 / (d2 - d6))[:, None] * ac, EDGE, ac)
+        take((va <= 0) & (d4 - d3 >= 0) & (d5 - d6 >= 0),
+             b + ((d4 - d3) / ((d4 - d3) + (d5 - d6)))[:, None] * (c - b), EDGE, c - b)
+        den = va + vb + vc
+        take(np.ones(N, bool), a + (vb / den)[:, None] * ab + (vc / den)[:, None] * ac, FACE)
+    return q, region, e
+
+
+def mesh_query(o, x: np.ndarray):
+    """Signed distance and contact normal of points x (N, 3) to a triangle-mesh
+    obstacle (Sec. 5.1, the discretized sphere; reading): the closest triangle
+    (ties to the lowest index); on its face phi = n_t.(x - a) and n = n_t, the
+    unit face normal of (v1 - v0) x (v2 - v0); on an edge or vertex with closest
+    point c, r = |x - c|, s = sign(n_t.(x - c)) (+1 at 0), phi = s r and
+    n = s (x - c) / r (n = n_t when r = 0).  Returns phi (N,), n (N, 3), the
+    region (N,) and the unit edge direction (N, 3) of EDGE regions."""
+    V = np.asarray(o.verts, float)
+    Tr = np.asarray(o.tris, np.int64)
+    x = np.atleast_2d(np.asarray(x, float))
+    N, T = x.shape[0], Tr.shape[0]
+    A, B, C = V[Tr[:, 0]], V[Tr[:, 1]], V[Tr[:, 2]]
+    nt = np.cross(B - A, C - A)
+    nt /= np.linalg.norm(nt, axis=1)[:, None]
+    P = np.repeat(x, T, axis=0)
+    q, reg, e = closest_point_on_triangle(P, np.tile(A, (N, 1)), np.tile(B, (N, 1)), np.tile(C, (N, 1)))
+    ntr = np.tile(nt, (N, 1))
+    face_d = np.sum(ntr * (P - np.tile(A, (N, 1))), axis=1)
+    dist = np.where(reg == FACE, np.abs(face_d), np.linalg.norm(P - q, axis=1)).reshape(N, T)
+    best = np.argmin(dist, axis=1)                 # ties -> lowest triangle index
+    k = np.arange(N) * T + best
+    phi = np.zeros(N)
+    n = np.zeros((N, 3))
+    region = reg[k]
+    edge = e[k]
+    for i in range(N):
+        j = k[i]
+        if region[i] == FACE:
+            phi[i] = face_d[j]
+            n[i] = ntr[j]
+        else:
+            d = P[j] - q[j]
+            r = np.linalg.norm(d)
+            sgn = 1.0 if ntr[j] @ d >= 0.0 else -1.0
+            if r > 0.0:
+                phi[i] = sgn * r
+                n[i] = sgn * d / r
+            else:
+                n[i] = ntr[j]
+    return phi, n, region, edge
 
 
 # =========================================================================== forward
@@ -533,6 +627,23 @@ def backward_step(model: Model, rec: StepRecord, gx: np.ndarray, gv: np.ndarray,
         np.add.at(dx, j, dphi[:, None] * nrm)                 # grad phi = n (plane, sphere)
         dn = np.einsum('cji,cj->ci', dv_dn, lam)              # (dv/dn)^T lambda
         for oi, o in enumerate(model.obstacles):
+            if o.kind == MESH:
+                # dn/dx of the frame at x_n: 0 on a face, (I - n n^T)/phi at a
+                # vertex, (I - n n^T - e e^T)/phi on an edge (the closest point
+                # slides along it); phi = 0 exactly: taken as a face
+                so = np.nonzero(ct.obstacle[act] == oi)[0]
+                if so.size == 0:
+                    continue
+                phim, nm, regm, em = mesh_query(o, rec.x0[j[so]])
+                for q_, i_ in enumerate(so):
+                    if regm[q_] == FACE or phim[q_] == 0.0:
+                        continue
+                    dni = dn[i_]
+                    g = dni - (nm[q_] @ dni) * nm[q_]
+                    if regm[q_] == EDGE:
+                        g = g - (em[q_] @ dni) * em[q_]
+                    dx[j[i_]] += g / phim[q_]
+                continue
             if o.kind != SPHERE:
                 continue
             so = ct.obstacle[act] == oi

@@ -26,6 +26,7 @@ import numpy as np
 
 PLANE = 0
 SPHERE = 1
+MESH = 2
 
 GRAVITY = (0.0, -9.8, 0.0)
 AREAL_DENSITY = 0.1          # kg per m^2 (0.1 kg over a 1 m x 1 m square cloth)
@@ -40,6 +41,8 @@ class Obstacle:
     normal: tuple = (0.0, 1.0, 0.0) # plane normal (unit); unused for spheres
     radius: float = 0.0             # sphere radius
     mu: float = 0.5                 # Coulomb friction coefficient
+    verts: Optional[np.ndarray] = None   # MESH: (nv, 3) vertices
+    tris: Optional[np.ndarray] = None    # MESH: (nt, 3) int32, outward normal by (v1-v0) x (v2-v0)
 
 
 @dataclasses.dataclass
@@ -147,6 +150,57 @@ def _log_uniform(rng, lo, hi, size=None):
 
 def _centroid_target(rng, X):
     return X.mean(axis=0) + rng.normal(0.0, 0.1, 3)
+
+
+def icosphere(center, radius: float, level: int):
+    """Triangulated sphere: an icosahedron subdivided ``level`` times (each
+    triangle into four), vertices pushed onto the sphere; outward winding.
+    20 * 4**level triangles."""
+    t = (1.0 + math.sqrt(5.0)) / 2.0
+    V = [(-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0), (0, -1, t), (0, 1, t), (0, -1, -t), (0, 1, -t),
+         (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)]
+    F = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4), (11, 10, 2),
+         (10, 7, 6), (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9), (4, 9, 5), (2, 4, 11),
+         (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+    V = [np.asarray(v, float) / np.linalg.norm(v) for v in V]
+    for _ in range(level):
+        mid = {}
+
+        def midpoint(a, b):
+            key = (min(a, b), max(a, b))
+            if key not in mid:
+                m = V[a] + V[b]
+                V.append(m / np.linalg.norm(m))
+                mid[key] = len(V) - 1
+            return mid[key]
+        F2 = []
+        for a, b, c in F:
+            ab, bc, ca = midpoint(a, b), midpoint(b, c), midpoint(c, a)
+            F2 += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        F = F2
+    verts = np.asarray(center, float) + radius * np.stack(V)
+    tris = np.asarray(F, np.int32)
+    # outward winding: (v1 - v0) x (v2 - v0) points away from the centre
+    nrm = np.cross(verts[tris[:, 1]] - verts[tris[:, 0]], verts[tris[:, 2]] - verts[tris[:, 0]])
+    flip = np.sum(nrm * (verts[tris[:, 0]] - np.asarray(center, float)), axis=1) < 0
+    tris[flip] = tris[flip][:, [0, 2, 1]]
+    return verts, tris
+
+
+def mesh_obstacle(verts, tris, mu: float) -> Obstacle:
+    return Obstacle(MESH, (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 0.0, mu, np.asarray(verts, float),
+                    np.asarray(tris, np.int32))
+
+
+def discretized_sphere_drop(seed: int = 0, n: int = 40, steps: int = 200, level: int = 2) -> Scene:
+    """The sphere drop onto a triangulated sphere (icosphere, 20 * 4**level
+    triangles) of the same centre and radius (the discretized-sphere study)."""
+    s = c2_sphere_drop(seed, n, steps)
+    o = s.obstacles[0]
+    V, T = icosphere(o.point, o.radius, level)
+    s.obstacles = [mesh_obstacle(V, T, o.mu)]
+    s.name = f"mesh_sphere_drop{n}x{n}_L{level}"
+    return s
 
 
 # --------------------------------------------------------------------------- workloads

@@ -607,3 +607,120 @@ def test_external_force_gradients_match_finite_differences(obst):
             assert abs(val - G.dforce_scale[n]) <= 1e-5 * abs(val) + 1e-12, (n, val, G.dforce_scale[n])
             checks += 1
     assert checks >= 3
+
+
+# ------------------------------------------------------------------ triangle-mesh obstacles
+
+def _segment_closest(p, a, b):
+    t = np.clip(np.dot(p - a, b - a) / np.dot(b - a, b - a), 0.0, 1.0)
+    return a + t * (b - a)
+
+
+def test_closest_point_on_triangle_against_feature_enumeration():
+    # the exact distance from the candidates of a quadratic program over the
+    # triangle: the plane projection when it falls inside, else the three edges
+    rng = np.random.default_rng(11)
+    for _ in range(300):
+        a, b, c = rng.normal(size=(3, 3))
+        p = rng.normal(size=3) * 2.0
+        q, reg, e = O.closest_point_on_triangle(p[None], a[None], b[None], c[None])
+        nrm = np.cross(b - a, c - a)
+        nrm /= np.linalg.norm(nrm)
+        proj = p - np.dot(p - a, nrm) * nrm
+        # barycentric coordinates of the projection
+        M = np.stack([b - a, c - a], axis=1)
+        uv = np.linalg.lstsq(M, proj - a, rcond=None)[0]
+        inside = uv[0] >= 0 and uv[1] >= 0 and uv.sum() <= 1
+        cands = [proj] if inside else [_segment_closest(p, a, b), _segment_closest(p, b, c),
+                                       _segment_closest(p, a, c)]
+        best = min(np.linalg.norm(p - x) for x in cands)
+        assert abs(np.linalg.norm(p - q[0]) - best) <= 1e-12 * (1 + best)
+        assert (reg[0] == O.FACE) == inside
+        if reg[0] == O.EDGE:                        # p - q is perpendicular to the edge
+            assert abs(np.dot(p - q[0], e[0])) <= 1e-12 * (1 + np.linalg.norm(p - q[0]))
+
+
+def test_triangulated_plane_equals_the_plane():
+    sc = scenes.tiny_scene(4, steps=14, obstacle="plane", seed=12, height=0.004, v0_scale=0.1, mu=0.3)
+    L = 10.0
+    V = np.array([[-L, 0.0, -L], [L, 0.0, -L], [L, 0.0, L], [-L, 0.0, L]])
+    T = np.array([[0, 3, 2], [0, 2, 1]], np.int32)           # normals +y
+    sm = scenes.tiny_scene(4, steps=14, obstacle="plane", seed=12, height=0.004, v0_scale=0.1, mu=0.3)
+    sm.obstacles = [scenes.mesh_obstacle(V, T, 0.3)]
+    a = O.Model(sc)
+    b = O.Model(sm)
+    ra, rb = O.rollout(a), O.rollout(b)
+    assert modes_of(ra) == modes_of(rb) and any(r.contact.nodes.size for r in ra)
+    assert np.array_equal(ra[-1].x1, rb[-1].x1)
+    _, g = O.centroid_loss(a, ra[-1].x1, sc.target)
+    Ga, Gb = O.backward(a, ra, g), O.backward(b, rb, g)
+    for u, v in ((Ga.dx0, Gb.dx0), (Ga.dv0, Gb.dv0), (Ga.dw, Gb.dw), (Ga.dmu, Gb.dmu)):
+        assert np.array_equal(u, v)
+
+
+def test_icosphere_distance_brackets_the_sphere():
+    # the icosphere is inscribed in its sphere: outside points are at least as
+    # far from it as from the sphere, and at most the sagitta farther
+    V, T = scenes.icosphere((0.1, -0.2, 0.05), 0.3, 2)
+    o = scenes.mesh_obstacle(V, T, 0.5)
+    rng = np.random.default_rng(13)
+    d = rng.normal(size=(400, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    x = np.asarray((0.1, -0.2, 0.05)) + d * rng.uniform(0.31, 0.6, (400, 1))
+    phi, n, reg, _ = O.mesh_query(o, x)
+    ps = np.linalg.norm(x - np.asarray((0.1, -0.2, 0.05)), axis=1) - 0.3
+    # sagitta: largest distance from the sphere to a face plane inside it
+    A, B, C = V[T[:, 0]], V[T[:, 1]], V[T[:, 2]]
+    nt = np.cross(B - A, C - A)
+    nt /= np.linalg.norm(nt, axis=1)[:, None]
+    sag = 0.3 - np.min(np.abs(np.sum(nt * (A - np.asarray((0.1, -0.2, 0.05))), axis=1)))
+    assert np.all(phi >= ps - 1e-12) and np.all(phi <= ps + sag + 1e-12)
+    assert np.allclose(np.linalg.norm(n, axis=1), 1.0, atol=1e-14)
+    assert set(np.unique(reg)) >= {O.FACE}
+
+
+def test_mesh_obstacle_gradients_match_finite_differences():
+    # a coarse icosphere (80 triangles) under a small cloth: contacts on faces,
+    # edges and vertices, each with its own frame derivative
+    sc = scenes.tiny_scene(3, steps=8, obstacle="sphere", k=50.0, mu=0.4, seed=14, height=0.004,
+                           v0_scale=0.05, bend=0.02)
+    o = sc.obstacles[0]
+    V, T = scenes.icosphere(o.point, o.radius, 1)
+    sc.obstacles = [scenes.mesh_obstacle(V, T, o.mu)]
+    model, recs, L, g = converged_loss(sc)
+    regions = set()
+    for r in recs:
+        act = r.contact.mode != O.TAKEOFF
+        if np.any(act):
+            regions |= set(O.mesh_query(sc.obstacles[0], r.x0[r.contact.nodes[act]])[2].tolist())
+    assert len(regions) >= 2, regions                 # not only faces
+    G = O.backward(model, recs, g)
+    base_modes = modes_of(recs)
+    rng = np.random.default_rng(15)
+    checks = 0
+
+    def fd(eps, **kw):
+        _, rp, Lp, _ = converged_loss(sc, **{k: v[0] for k, v in kw.items()})
+        _, rm, Lm, _ = converged_loss(sc, **{k: v[1] for k, v in kw.items()})
+        if modes_of(rp) != base_modes or modes_of(rm) != base_modes:
+            return None
+        return (Lp - Lm) / (2 * eps)
+
+    for _ in range(2):
+        d = rng.normal(size=sc.X.shape)
+        e = 1e-6
+        val = fd(e, x0=(sc.X + e * d, sc.X - e * d))
+        if val is not None:
+            assert abs(val - np.sum(G.dx0 * d)) <= 1e-5 * abs(val) + 1e-12, (val, np.sum(G.dx0 * d))
+            checks += 1
+    d = rng.normal(size=sc.X.shape)
+    val = fd(1e-6, v0=(sc.v0 + 1e-6 * d, sc.v0 - 1e-6 * d))
+    if val is not None:
+        assert abs(val - np.sum(G.dv0 * d)) <= 1e-5 * abs(val) + 1e-12
+        checks += 1
+    mu = sc.obstacles[0].mu
+    val = fd(1e-5, mu=([mu + 1e-5], [mu - 1e-5]))
+    if val is not None:
+        assert abs(val - G.dmu[0]) <= 1e-5 * abs(val) + 1e-10, (val, G.dmu[0])
+        checks += 1
+    assert checks >= 3
