@@ -55,6 +55,7 @@ extern "C" {
 
 #define SIM_PLANE            0
 #define SIM_SPHERE           1
+#define SIM_MESH             2
 
 #define SIM_FP64             0   /* every step in float64                               */
 #define SIM_MIXED            1   /* float32 local projections, projection Jacobians and
@@ -73,15 +74,29 @@ extern "C" {
 /* ---------------------------------------------------------------- types */
 typedef struct sim sim_t;
 
-/* Static analytic obstacle.  Plane: {x : n.(x - p) = 0}, signed distance
- * n.(x - p) with unit normal n.  Sphere: centre p, radius r, signed distance
- * |x - p| - r.  mu is its Coulomb friction coefficient. */
+/* Static obstacle.  Plane: {x : n.(x - p) = 0}, signed distance n.(x - p)
+ * with unit normal n.  Sphere: centre p, radius r, signed distance |x - p| - r.
+ * Mesh (the triangulated obstacles of Sec. 5.1's discretized-sphere study):
+ * n_tris triangles over n_verts vertices (host arrays verts [n_verts*3],
+ * tris [n_tris*3], copied by sim_create; at most 65536 triangles, none
+ * degenerate); the outward side of triangle t is that of
+ * (v1 - v0) x (v2 - v0).  A point's closest triangle (ties to the lowest index)
+ * gives its frame: on the triangle's face the face normal and the plane
+ * distance; at an edge or vertex with closest point c, the direction of
+ * x - c and |x - c|, signed by the side of the triangle's face.  The scan over
+ * all triangles suits obstacles of a few thousand triangles.  mu is the
+ * Coulomb friction coefficient of any type; the mesh fields are ignored for
+ * planes and spheres. */
 typedef struct {
-    int32_t type;          /* SIM_PLANE or SIM_SPHERE */
+    int32_t type;          /* SIM_PLANE, SIM_SPHERE or SIM_MESH */
     double  p[3];
     double  n[3];
     double  radius;
     double  mu;
+    int32_t n_verts;       /* SIM_MESH */
+    int32_t n_tris;
+    const double  *verts;
+    const int32_t *tris;
 } sim_obstacle_t;
 
 /* Triangle mesh.  X is the rest shape, also the default initial state.

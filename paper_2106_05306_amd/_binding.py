@@ -14,7 +14,7 @@ LIB_PATH = os.environ.get("DIFFCLOTH_LIB", os.path.join(HERE, "libdiffcloth.so")
 
 SIM_OK, SIM_EINVAL, SIM_ENOTSPD, SIM_ENOMEM, SIM_ENONFINITE, SIM_ESTATE, SIM_EHIP = 0, -1, -2, -3, -4, -5, -6
 SIM_WADJ_FALLBACK, SIM_WADJ_NOCONV, SIM_WADJ_NONFINITE = 1, 2, 3
-SIM_PLANE, SIM_SPHERE = 0, 1
+SIM_PLANE, SIM_SPHERE, SIM_MESH = 0, 1, 2
 SIM_FP64, SIM_MIXED = 0, 1
 SIM_ADJ_ITERATIVE, SIM_ADJ_DIRECT = 0, 1
 MODE_FREE, MODE_TAKEOFF, MODE_STICK, MODE_SLIP = 0, 1, 2, 3
@@ -25,7 +25,8 @@ c_int32_p = POINTER(c_int32)
 
 class SimObstacle(Structure):
     _fields_ = [("type", c_int32), ("p", c_double * 3), ("n", c_double * 3), ("radius", c_double),
-                ("mu", c_double)]
+                ("mu", c_double), ("n_verts", c_int32), ("n_tris", c_int32), ("verts", c_double_p),
+                ("tris", c_int32_p)]
 
 
 class SimMesh(Structure):

@@ -410,6 +410,9 @@ void build_device(sim *s) {
         for (int d = 0; d < 3; ++d) { D.obst[o].p[d] = ob.p[d]; D.obst[o].n[d] = ob.n[d]; }
         D.obst[o].radius = ob.radius;
         D.obst[o].mu = ob.mu;
+        D.obst[o].n_tris = ob.type == SIM_MESH ? ob.n_tris : 0;
+        D.obst[o].tri = ob.type == SIM_MESH ? upload(s, hm.obst_tri[o]) : nullptr;
+        if (ob.type == SIM_MESH && !D.cfr) D.cfr = zeros<double>(s, 4 * (size_t)m);
     }
     const auto &perm = hm.perm, &iperm = hm.iperm;
     // masses

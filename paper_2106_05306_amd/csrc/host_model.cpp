@@ -67,11 +67,44 @@ int HostModel::build(const sim_mesh_t *mesh, const sim_params_t *p) {
             for (int d = 0; d < 3; ++d) o.n[d] /= nn;
         } else if (o.type == SIM_SPHERE) {
             if (!(o.radius > 0)) { error = "sphere radius must be positive"; return SIM_EINVAL; }
+        } else if (o.type == SIM_MESH) {
+            if (o.n_verts < 3 || o.n_tris < 1 || o.n_tris > 65536 || !o.verts || !o.tris) {
+                error = "mesh obstacle needs vertices and 1..65536 triangles";
+                return SIM_EINVAL;
+            }
         } else {
             error = "unknown obstacle type";
             return SIM_EINVAL;
         }
         if (!(o.mu >= 0) || !std::isfinite(o.mu)) { error = "friction must be >= 0"; return SIM_EINVAL; }
+    }
+    obst_tri.assign(obstacles.size(), {});
+    for (size_t k = 0; k < obstacles.size(); ++k) {
+        sim_obstacle_t &o = obstacles[k];
+        if (o.type == SIM_MESH) {
+            std::vector<double> &tri = obst_tri[k];
+            tri.resize(12 * (size_t)o.n_tris);
+            for (int t = 0; t < o.n_tris; ++t) {
+                const double *v[3];
+                for (int r = 0; r < 3; ++r) {
+                    const int32_t vi = o.tris[3 * t + r];
+                    if (vi < 0 || vi >= o.n_verts) { error = "mesh obstacle: vertex index out of range"; return SIM_EINVAL; }
+                    v[r] = o.verts + 3 * (size_t)vi;
+                    for (int d = 0; d < 3; ++d) {
+                        if (!std::isfinite(v[r][d])) { error = "mesh obstacle: non-finite vertex"; return SIM_EINVAL; }
+                        tri[12 * t + 3 * r + d] = v[r][d];
+                    }
+                }
+                const double u[3] = {v[1][0] - v[0][0], v[1][1] - v[0][1], v[1][2] - v[0][2]};
+                const double w[3] = {v[2][0] - v[0][0], v[2][1] - v[0][1], v[2][2] - v[0][2]};
+                double nn[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
+                const double ln = norm3(nn);
+                if (!(ln > 0)) { error = "mesh obstacle: degenerate triangle"; return SIM_EINVAL; }
+                for (int d = 0; d < 3; ++d) tri[12 * t + 9 + d] = nn[d] / ln;
+            }
+        }
+        o.verts = nullptr;                    // the caller's arrays are not kept
+        o.tris = nullptr;
     }
 
     // ---------------------------------------------------------------- triangles

@@ -21,7 +21,10 @@ struct HostModel {
     int pd_iters = 20, fwd_max_iters = 0, adj_max_iters = 500, precision = SIM_FP64;
     double fwd_tol = 0, adj_tol = 1e-10;
     int checkpoint_every = 0, adj_restart = 60, adj_solver = SIM_ADJ_ITERATIVE, adj_window = 0;
-    std::vector<sim_obstacle_t> obstacles;
+    std::vector<sim_obstacle_t> obstacles;  // mesh pointers cleared; geometry in obst_tri
+    // triangle-mesh obstacles: per obstacle, per triangle its vertices a, b, c
+    // and unit face normal (12 doubles), empty for planes and spheres
+    std::vector<std::vector<double>> obst_tri;
 
     // ------------------------------------------------------------ constraints
     // All "norm" constraints (springs, then bending): A_c x = sum_k a_ck x_k,

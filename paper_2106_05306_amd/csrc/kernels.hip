@@ -254,9 +254,106 @@ __device__ __forceinline__ void solve_P(const SimDev &S, auto b, auto T, auto Y,
 
 // ------------------------------------------------------------------ geometry
 
+// Frame of a triangle-mesh obstacle at x: the closest triangle (a scan over
+// all of them, ties to the lowest index) and on it the closest point by its
+// Voronoi regions (tested in the order vertex a, vertex b, edge ab, vertex c,
+// edge ac, edge bc, face).  Face: n = the face normal, phi = n.(x - a).  Edge
+// or vertex with closest point q: r = |x - q|, s = the side of the face,
+// phi = s r, n = s (x - q) / r (the face normal when r = 0).  region: 0 face,
+// 1 vertex, 2 edge, whose unit direction goes to e.
+__device__ __noinline__ void mesh_frame(const ObstacleDev &ob, const double *x, double *n, double &phi, int &region,
+                                        double *e) {
+    const auto tri = (GLOBAL const double *)ob.tri;
+    double best = INFINITY, bfd = 0.0, bq[3] = {0.0, 0.0, 0.0}, bn[3] = {0.0, 1.0, 0.0}, bed[3] = {0.0, 0.0, 0.0};
+    int breg = 0;
+    for (int t = 0; t < ob.n_tris; ++t) {
+        const auto T = tri + 12 * (int64_t)t;
+        const double a[3] = {T[0], T[1], T[2]}, b[3] = {T[3], T[4], T[5]}, c[3] = {T[6], T[7], T[8]};
+        double ab[3], ac[3], ap[3], bp[3], cp[3];
+        for (int d = 0; d < 3; ++d) {
+            ab[d] = b[d] - a[d]; ac[d] = c[d] - a[d];
+            ap[d] = x[d] - a[d]; bp[d] = x[d] - b[d]; cp[d] = x[d] - c[d];
+        }
+        const double d1 = ab[0] * ap[0] + ab[1] * ap[1] + ab[2] * ap[2];
+        const double d2 = ac[0] * ap[0] + ac[1] * ap[1] + ac[2] * ap[2];
+        const double d3 = ab[0] * bp[0] + ab[1] * bp[1] + ab[2] * bp[2];
+        const double d4 = ac[0] * bp[0] + ac[1] * bp[1] + ac[2] * bp[2];
+        const double d5 = ab[0] * cp[0] + ab[1] * cp[1] + ab[2] * cp[2];
+        const double d6 = ac[0] * cp[0] + ac[1] * cp[1] + ac[2] * cp[2];
+        const double vc = d1 * d4 - d3 * d2, vb = d5 * d2 - d1 * d6, va = d3 * d6 - d5 * d4;
+        double q[3], ed[3] = {0.0, 0.0, 0.0};
+        int reg;
+        if (d1 <= 0 && d2 <= 0) {
+            reg = 1;
+            for (int d = 0; d < 3; ++d) q[d] = a[d];
+        } else if (d3 >= 0 && d4 <= d3) {
+            reg = 1;
+            for (int d = 0; d < 3; ++d) q[d] = b[d];
+        } else if (vc <= 0 && d1 >= 0 && d3 <= 0) {
+            reg = 2;
+            const double v = d1 / (d1 - d3);
+            for (int d = 0; d < 3; ++d) { q[d] = a[d] + v * ab[d]; ed[d] = ab[d]; }
+        } else if (d6 >= 0 && d5 <= d6) {
+            reg = 1;
+            for (int d = 0; d < 3; ++d) q[d] = c[d];
+        } else if (vb <= 0 && d2 >= 0 && d6 <= 0) {
+            reg = 2;
+            const double w = d2 / (d2 - d6);
+            for (int d = 0; d < 3; ++d) { q[d] = a[d] + w * ac[d]; ed[d] = ac[d]; }
+        } else if (va <= 0 && d4 - d3 >= 0 && d5 - d6 >= 0) {
+            reg = 2;
+            const double w = (d4 - d3) / ((d4 - d3) + (d5 - d6));
+            for (int d = 0; d < 3; ++d) { q[d] = b[d] + w * (c[d] - b[d]); ed[d] = c[d] - b[d]; }
+        } else {
+            reg = 0;
+            for (int d = 0; d < 3; ++d) q[d] = 0.0;
+        }
+        const double fd = T[9] * ap[0] + T[10] * ap[1] + T[11] * ap[2];
+        double dist;
+        if (reg == 0) {
+            dist = fabs(fd);
+        } else {
+            const double r0 = x[0] - q[0], r1 = x[1] - q[1], r2 = x[2] - q[2];
+            dist = sqrt(r0 * r0 + r1 * r1 + r2 * r2);
+        }
+        if (dist < best) {
+            best = dist;
+            breg = reg;
+            bfd = fd;
+            for (int d = 0; d < 3; ++d) { bq[d] = q[d]; bn[d] = T[9 + d]; bed[d] = ed[d]; }
+        }
+    }
+    region = breg;
+    e[0] = e[1] = e[2] = 0.0;
+    if (breg == 0) {
+        phi = bfd;
+        for (int d = 0; d < 3; ++d) n[d] = bn[d];
+        return;
+    }
+    const double r0 = x[0] - bq[0], r1 = x[1] - bq[1], r2 = x[2] - bq[2];
+    const double r = sqrt(r0 * r0 + r1 * r1 + r2 * r2);
+    const double sg = (bn[0] * r0 + bn[1] * r1 + bn[2] * r2 >= 0.0) ? 1.0 : -1.0;
+    if (r > 0.0) {
+        phi = sg * r;
+        n[0] = sg * r0 / r; n[1] = sg * r1 / r; n[2] = sg * r2 / r;
+    } else {
+        phi = 0.0;
+        for (int d = 0; d < 3; ++d) n[d] = bn[d];
+    }
+    if (breg == 2) {
+        const double le = sqrt(bed[0] * bed[0] + bed[1] * bed[1] + bed[2] * bed[2]);
+        for (int d = 0; d < 3; ++d) e[d] = bed[d] / le;
+    }
+}
+
 __device__ __forceinline__ void contact_frame(const SimDev &S, int o, auto xi, double *n, double &phi) {
     const ObstacleDev &ob = S.obst[o];
-    if (ob.type == 0) {
+    if (ob.type == 2) {
+        const double x[3] = {xi[0], xi[1], xi[2]};
+        int reg;
+        double e[3];
+        mesh_frame(ob, x, n, phi, reg, e);
+    } else if (ob.type == 0) {
         n[0] = ob.n[0]; n[1] = ob.n[1]; n[2] = ob.n[2];
         phi = (xi[0] - ob.p[0]) * n[0] + (xi[1] - ob.p[1]) * n[1] + (xi[2] - ob.p[2]) * n[2];
     } else {
@@ -268,6 +365,12 @@ __device__ __forceinline__ void contact_frame(const SimDev &S, int o, auto xi, d
 }
 
 __device__ __forceinline__ double signed_distance(const ObstacleDev &ob, const double *y) {
+    if (ob.type == 2) {
+        double n[3], phi, e[3];
+        int reg;
+        mesh_frame(ob, y, n, phi, reg, e);
+        return phi;
+    }
     if (ob.type == 0)
         return (y[0] - ob.p[0]) * ob.n[0] + (y[1] - ob.p[1]) * ob.n[1] + (y[2] - ob.p[2]) * ob.n[2];
     const double d0 = y[0] - ob.p[0], d1 = y[1] - ob.p[1], d2 = y[2] - ob.p[2];
@@ -542,6 +645,12 @@ __global__ __launch_bounds__(kBlock) void k_forward(const SimDev *__restrict__ s
             const bool contact = ob >= 0 && best <= 0.0;
             G(S.mode)[i] = contact ? TAKEOFF : FREE;
             G(S.cobst)[i] = contact ? (int8_t)ob : (int8_t)-1;
+            if (contact && S.obst[ob].type == 2) {         // the step's frame at x_n, scanned once
+                double nr[3], ph;
+                contact_frame(S, ob, xi, nr, ph);
+                for (int d = 0; d < 3; ++d) G(S.cfr)[4 * i + d] = nr[d];
+                G(S.cfr)[4 * i + 3] = ph;
+            }
             double kx0 = 0, kx1 = 0, kx2 = 0;
             for (int p = G(S.ks_ptr)[i]; p < G(S.ks_ptr)[i + 1]; ++p) {
                 const int j = G(S.ks_col)[p];
@@ -587,7 +696,12 @@ __global__ __launch_bounds__(kBlock) void k_forward(const SimDev *__restrict__ s
                     const double ub[3] = {B[3 * i] - G(S.f)[3 * i] / mi, B[3 * i + 1] - G(S.f)[3 * i + 1] / mi,
                                           B[3 * i + 2] - G(S.f)[3 * i + 2] / mi};
                     double nrm[3], phi, vv[3], ff[3];
-                    contact_frame(S, G(S.cobst)[i], XN + 3 * i, nrm, phi);
+                    if (S.obst[G(S.cobst)[i]].type == 2) {         // mesh: the frame cached at the step's start
+                        for (int d = 0; d < 3; ++d) nrm[d] = G(S.cfr)[4 * i + d];
+                        phi = G(S.cfr)[4 * i + 3];
+                    } else {
+                        contact_frame(S, G(S.cobst)[i], XN + 3 * i, nrm, phi);
+                    }
                     G(S.mode)[i] = signorini_coulomb(ub, nrm, phi, S.obst[G(S.cobst)[i]].mu, h, mi, vv, ff);
                     for (int d = 0; d < 3; ++d) {
                         B[3 * i + d] = vv[d];
@@ -1746,6 +1860,18 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
                     const double r = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
                     const double ndn = nrm[0] * dn[0] + nrm[1] * dn[1] + nrm[2] * dn[2];
                     for (int d = 0; d < 3; ++d) dx[d] += (dn[d] - ndn * nrm[d]) / r;
+                } else if (S.obst[o].type == 2) {
+                    // dn/dx of the mesh frame at x_n: 0 on a face, (I - n n^T)/phi at
+                    // a vertex, (I - n n^T - e e^T)/phi on an edge; phi = 0: as a face
+                    const double xv[3] = {x0[3 * i], x0[3 * i + 1], x0[3 * i + 2]};
+                    double nm[3], pm, em[3];
+                    int reg;
+                    mesh_frame(S.obst[o], xv, nm, pm, reg, em);
+                    if (reg != 0 && pm != 0.0) {
+                        const double ndn = nm[0] * dn[0] + nm[1] * dn[1] + nm[2] * dn[2];
+                        const double edn = em[0] * dn[0] + em[1] * dn[1] + em[2] * dn[2];
+                        for (int d = 0; d < 3; ++d) dx[d] += (dn[d] - ndn * nm[d] - edn * em[d]) / pm;
+                    }
                 }
             }
             for (int d = 0; d < 3; ++d) {

@@ -93,8 +93,10 @@ struct LuSup {              // supernode (chunk) data of the direct adjoint fact
 };
 
 struct ObstacleDev {
-    int type;                         // 0 plane, 1 sphere
+    int type;                         // 0 plane, 1 sphere, 2 triangle mesh
+    int n_tris;                       // mesh: triangles
     double p[3], n[3], radius, mu;
+    const double *tri;                // mesh: per triangle a, b, c, unit face normal (12 doubles)
 };
 
 struct SimDev {
@@ -189,6 +191,7 @@ struct SimDev {
     double *dw;                       // [nc_total] accumulated weight gradients (canonical)
     double *dmu;                      // [kMaxObstacles]
     const double *gx_steps;           // optional per-step dL/dx_n [(T+1)*m*3], new order
+    double *cfr;                      // [m*4] mesh obstacles: the current step's contact frame (n, phi)
     // external force besides gravity: step n adds fscale[n] * fext (fext nullptr:
     // none; fscale nullptr: 1 at every step), and its gradients
     const double *fext;               // [m*3] new order

@@ -99,6 +99,13 @@ def build_structs(X, tris, node_mass, edge_stiffness, *, edges=None, h=1.0 / 120
         obs[i].n[:] = list(o.get("n", (0.0, 1.0, 0.0)))
         obs[i].radius = o.get("radius", 0.0)
         obs[i].mu = o["mu"]
+        if o.get("verts") is not None:          # triangle mesh (copied by sim_create)
+            k[f"ov{i}"] = _arr(o["verts"], np.float64).reshape(-1)
+            k[f"ot{i}"] = _arr(o["tris"], np.int32).reshape(-1)
+            obs[i].n_verts = k[f"ov{i}"].size // 3
+            obs[i].n_tris = k[f"ot{i}"].size // 3
+            obs[i].verts = k[f"ov{i}"].ctypes.data_as(B.c_double_p)
+            obs[i].tris = k[f"ot{i}"].ctypes.data_as(B.c_int32_p)
     k["obs"] = obs
     p.n_obstacles = len(obstacles)
     p.obstacles = obs
@@ -115,7 +122,8 @@ def build_structs(X, tris, node_mass, edge_stiffness, *, edges=None, h=1.0 / 120
 def scene_kwargs(scene, **kw):
     """Keyword arguments of build_structs / Sim for an object carrying the
     workload fields (X, tris, edges, node_mass, edge_stiffness, obstacles, ...)."""
-    obstacles = [dict(type=o.kind, p=o.point, n=o.normal, radius=o.radius, mu=o.mu) for o in scene.obstacles]
+    obstacles = [dict(type=o.kind, p=o.point, n=o.normal, radius=o.radius, mu=o.mu,
+                      verts=getattr(o, "verts", None), tris=getattr(o, "tris", None)) for o in scene.obstacles]
     args = dict(X=scene.X, tris=scene.tris, node_mass=scene.node_mass, edge_stiffness=scene.edge_stiffness,
                 edges=scene.edges, h=scene.h, pd_iters=scene.pd_iters, gravity=scene.gravity,
                 bend_weight=scene.bend_weight, attach=scene.attach, attach_weight=scene.attach_weight,
