@@ -482,6 +482,8 @@ def main():
                     help="sphere_drop: the 40x40 rollout (default); batch: 64 uneven rollouts in flight; "
                          "serve: continuous-batching request server; skirt: region-stiffness gradients; "
                          "napkin_force: gradients w.r.t. per-node external forces")
+    ap.add_argument("--obstacle", default="sphere", choices=["sphere", "icosphere2", "icosphere3"],
+                    help="sphere_drop: the analytic sphere (default) or a triangulated one (320 / 1280 triangles)")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--batch-window", type=int, default=50, help="adjoint steps per launch in the batch workload")
     ap.add_argument("--requests", type=int, default=40, help="requests of the serve workload")
@@ -517,7 +519,8 @@ def main():
     from paper_2106_05306_amd.sim import Sim
 
     dev = torch.device("cuda:0")
-    sc = scenes.c2_sphere_drop(0)
+    sc = scenes.c2_sphere_drop(0) if args.obstacle == "sphere" else \
+        scenes.discretized_sphere_drop(0, level=int(args.obstacle[-1]))
     T, K = sc.steps, sc.pd_iters
     sim = Sim.from_scene(sc, device=dev, precision=args.precision, adj_tol=args.adj_tol,
                          adj_max_iters=args.adj_max_iters, adj_restart=args.adj_restart,
@@ -567,7 +570,7 @@ def main():
         launches = max(1, int(fwd_stats.get("fwd_launches", 1)))
         kname, nbytes, ms = "k_forward", fwd_b / launches, fwd_ms / launches
     achieved = nbytes / (ms * 1e-3) / 1e9
-    traffic = traffic_from_profile(kname)
+    traffic = traffic_from_profile(kname) if args.obstacle == "sphere" else None
     value = args.steps * T / elapsed
 
     result = {
@@ -583,7 +586,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f64+f32",
         "data": "synthetic",
-        "config": {"workload": "sphere_drop 40x40 nodes (4800 DoF), 1 m cloth onto a 0.25 m sphere, "
+        "config": {"workload": "sphere_drop 40x40 nodes (4800 DoF), 1 m cloth onto a 0.25 m sphere"
+                               + ("" if args.obstacle == "sphere" else
+                                  f" triangulated as an icosphere of {20 * 4 ** int(args.obstacle[-1])} triangles")
+                               + ", "
                                "200 steps h=1/120, " + (f"PD iterated to {args.fwd_tol:g} m/s per step"
                                                         if args.fwd_tol > 0 else "K=20 PD iterations/step") +
                                ", forward + adjoint (one benchmark step = one rollout)",

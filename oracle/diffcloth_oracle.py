@@ -321,8 +321,8 @@ def mesh_query(o, x: np.ndarray):
             n[i] = ntr[j]
         else:
             d = P[j] - q[j]
-            r = np.linalg.norm(d)
-            sgn = 1.0 if ntr[j] @ d >= 0.0 else -1.0
+            r = math.sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2])
+            sgn = 1.0 if ntr[j, 0] * d[0] + ntr[j, 1] * d[1] + ntr[j, 2] * d[2] >= 0.0 else -1.0
             if r > 0.0:
                 phi[i] = sgn * r
                 n[i] = sgn * d / r

@@ -263,6 +263,10 @@ __device__ __forceinline__ void solve_P(const SimDev &S, auto b, auto T, auto Y,
 // 1 vertex, 2 edge, whose unit direction goes to e.
 __device__ __noinline__ void mesh_frame(const ObstacleDev &ob, const double *x, double *n, double &phi, int &region,
                                         double *e) {
+    // unfused arithmetic in the written order: a node resting on a face has
+    // phi = 0 exactly, and the contact test phi <= 0 must come out the same
+    // in any implementation that evaluates these formulas as written
+#pragma clang fp contract(off)
     const auto tri = (GLOBAL const double *)ob.tri;
     double best = INFINITY, bfd = 0.0, bq[3] = {0.0, 0.0, 0.0}, bn[3] = {0.0, 1.0, 0.0}, bed[3] = {0.0, 0.0, 0.0};
     int breg = 0;
@@ -635,7 +639,10 @@ __global__ __launch_bounds__(kBlock) void k_forward(const SimDev *__restrict__ s
                 for (int d = 0; d < 3; ++d) fe[d] = fs * G(S.fext)[3 * i + d];
             for (int d = 0; d < 3; ++d) ae[d] = S.g[d] + fe[d] / mi;
             double y[3];
-            for (int d = 0; d < 3; ++d) y[d] = xi[d] + h * vi[d] + h * h * ae[d];
+            {
+#pragma clang fp contract(off)                           // (x + h v) + (h h) a, unfused: see mesh_frame
+                for (int d = 0; d < 3; ++d) y[d] = xi[d] + h * vi[d] + h * h * ae[d];
+            }
             double best = 0.0;
             int ob = -1;
             for (int o = 0; o < S.n_obst; ++o) {

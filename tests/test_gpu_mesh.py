@@ -129,3 +129,21 @@ def test_mesh_sphere_drop_steps_from_recorded_states():
         contact_steps += rec.contact.nodes.size > 0
         print(f"step {n}: {rec.contact.nodes.size} contacts, position err {err:.2e}", flush=True)
     assert contact_steps >= 2
+
+
+def test_resting_nodes_decide_contact_alike():
+    # nodes resting on a face have phi(y) = 0 exactly at the next step; the
+    # contact test phi <= 0 must come out as in the oracle (unfused arithmetic
+    # in the written order on both sides).  40 x 40 drop on the 320-triangle
+    # icosphere, FP64, every step of the contact phase redone from the GPU's state
+    sc = scenes.discretized_sphere_drop(0, level=2, steps=100)
+    model = O.Model(sc)
+    sim = _sim(sc, precision="fp64", adj_solver="direct", adj_tol=1e-4, adj_max_iters=50)
+    sim.forward(sc.steps)
+    for n in range(60, 100):
+        x, v = sim.state(n)
+        rec = O.forward_step(model, x.cpu().numpy(), v.cpu().numpy(), n)
+        x1, _ = sim.state(n + 1)
+        assert np.array_equal(sim.modes(n), _modes(model, rec)), n
+        err = np.abs(x1.cpu().numpy() - rec.x1).max()
+        assert err <= 1e-9, (n, err)
