@@ -14,8 +14,9 @@
 #include "sim_dev.h"
 
 namespace dc {
-hipError_t launch_forward(const SimDev *d_sims, int n, bool mixed, size_t lds, int flags, int helpers, hipStream_t st);
-hipError_t launch_backward(const SimDev *d_sims, int n, bool mixed, size_t lds, int flags, int helpers,
+hipError_t launch_forward(const SimDev *d_sims, int n, bool mixed, size_t lds, int flags, int helpers, bool mesh,
+                          hipStream_t st);
+hipError_t launch_backward(const SimDev *d_sims, int n, bool mixed, size_t lds, int flags, int helpers, bool mesh,
                            hipStream_t st);
 hipError_t configure_lds(size_t fwd_bytes, size_t bwd_bytes);
 hipError_t kernel_static_lds(size_t *fwd, size_t *bwd);
@@ -234,6 +235,14 @@ void balance_phase(const std::vector<AdjItem> &ph, std::vector<AdjItem> &items, 
 
 // variant bits of an adjoint launch: LDS placement plus the handle's solver
 int bwd_variant(const sim *s, int lds_flags) { return (lds_flags & 3) | (s->hd.adj_direct ? kAdjDirect : 0); }
+
+// A handle of the launch has a triangle-mesh obstacle: the kernels' mesh variant.
+bool has_mesh(sim *const *hs, int n) {
+    for (int i = 0; i < n; ++i)
+        for (const sim_obstacle_t &o : hs[i]->hm.obstacles)
+            if (o.type == SIM_MESH) return true;
+    return false;
+}
 
 size_t lds_bytes(const sim *s, int flags, bool fwd) {
     const size_t m3 = 3 * (size_t)s->hd.m;
@@ -1000,7 +1009,8 @@ int run_forward_range(sim *s, int a, int b) {
     ++s->hd.fwd_epoch;
     int rc = push_desc(s);
     if (rc) return rc;
-    return hip_err(launch_forward(s->dd, 1, s->hd.mixed != 0, s->lds_fwd, s->flags_fwd, fwd_helpers(&s, 1), s->stream));
+    return hip_err(launch_forward(s->dd, 1, s->hd.mixed != 0, s->lds_fwd, s->flags_fwd, fwd_helpers(&s, 1),
+                                  has_mesh(&s, 1), s->stream));
 }
 
 int read_counters(sim *s) {
@@ -1268,6 +1278,7 @@ int forward_overlapped(sim *s, int n_steps, const std::vector<int> &ends) {
         ++s->hd.fwd_epoch;
         rc = push_desc(s);
         if (!rc) rc = hip_err(launch_forward(s->dd, 1, s->hd.mixed != 0, s->lds_fwd, s->flags_fwd, fwd_helpers(&s, 1),
+                                             has_mesh(&s, 1),
                                              s->stream));
         if (!rc && pa >= 0) {                // the previous chunk, queued behind this one's launch
             std::vector<int32_t> pairs;
@@ -1474,7 +1485,7 @@ int backward_range(sim *s, int a, int b) {
         if (!rc) rc = push_desc(s);
         if (!rc)
             rc = hip_err(launch_backward(s->dd, 1, s->hd.mixed != 0, s->lds_bwd, bwd_variant(s, s->flags_bwd),
-                                         s->hd.adj_direct ? adj_helpers_default() : 0, s->stream));
+                                         s->hd.adj_direct ? adj_helpers_default() : 0, has_mesh(&s, 1), s->stream));
         if (rc) return rc;
         hi = lo;
     }
@@ -1595,7 +1606,8 @@ int sim_adjoint_step(sim_t *s, int32_t n, const double *gx_dev, const double *gv
         s->hd.rec_step0 = 0;
         if (!rc) rc = factor_steps(s, n, n + 1);
         if (!rc) rc = push_desc(s);
-        if (!rc) rc = hip_err(launch_backward(s->dd, 1, s->hd.mixed != 0, s->lds_bwd, bwd_variant(s, s->flags_bwd), 0, s->stream));
+        if (!rc) rc = hip_err(launch_backward(s->dd, 1, s->hd.mixed != 0, s->lds_bwd, bwd_variant(s, s->flags_bwd), 0,
+                                              has_mesh(&s, 1), s->stream));
         if (!rc && dx_dev) rc = hip_err(launch_permute3(s->hd.gx, dx_dev, s->d_perm, m, true, s->stream));
         if (!rc && dv_dev) rc = hip_err(launch_permute3(s->hd.gv, dv_dev, s->d_perm, m, true, s->stream));
         if (!rc && out) {
@@ -1711,7 +1723,8 @@ int sim_batch_forward(sim_t *const *sims, int32_t n, const int32_t *n_steps, dou
         rc = hip_err(hipMemcpyAsync(d, descs.data(), n * sizeof(SimDev), hipMemcpyHostToDevice, s0->stream));
         int fl = 0;
         const size_t lb = batch_lds(sims, n, true, fl);
-        if (!rc) rc = hip_err(launch_forward(d, n, s0->hd.mixed != 0, lb, fl, fwd_helpers(sims, n), s0->stream));
+        if (!rc) rc = hip_err(launch_forward(d, n, s0->hd.mixed != 0, lb, fl, fwd_helpers(sims, n), has_mesh(sims, n),
+                                             s0->stream));
         for (int i = 0; i < n && !rc; ++i)
             rc = finish_forward(sims[i], n_steps[i], xT_dev ? xT_dev[i] : nullptr, vT_dev ? vT_dev[i] : nullptr);
         (void)hipStreamSynchronize(s0->stream);
@@ -1754,7 +1767,8 @@ int sim_batch_backward(sim_t *const *sims, int32_t n, const double *const *dL_dx
         if (!rc && !work.empty()) rc = factor_pairs(s0, d, std::vector<sim *>(sims, sims + n), work, s0->stream);
         int fl = 0;
         const size_t lb = batch_lds(sims, n, false, fl);
-        if (!rc) rc = hip_err(launch_backward(d, n, s0->hd.mixed != 0, lb, bwd_variant(s0, fl), 0, s0->stream));
+        if (!rc) rc = hip_err(launch_backward(d, n, s0->hd.mixed != 0, lb, bwd_variant(s0, fl), 0, has_mesh(sims, n),
+                                              s0->stream));
         int warn = SIM_OK;
         for (int i = 0; i < n && !rc; ++i) {
             if (out) rc = write_grads(sims[i], &out[i]);
@@ -1870,13 +1884,15 @@ int sim_batch_advance(sim_t *const *sims, int32_t n, const int32_t *steps, void 
             int fl = 0;
             const size_t lb = batch_lds(fw.data(), (int)fw.size(), true, fl);
             rc = hip_err(launch_forward(dfd, (int)fw.size(), fw[0]->hd.mixed != 0, lb, fl, fwd_helpers(fw.data(), (int)fw.size()),
+                                        has_mesh(fw.data(), (int)fw.size()),
                                         sf));
         }
         if (!rc && dbd) {
             if (!pairs.empty()) rc = factor_pairs(bw[0], dbd, bw, pairs, sb);
             int fl = 0;
             const size_t lb = batch_lds(bw.data(), (int)bw.size(), false, fl);
-            if (!rc) rc = hip_err(launch_backward(dbd, (int)bw.size(), bw[0]->hd.mixed != 0, lb, bwd_variant(bw[0], fl), 0, sb));
+            if (!rc) rc = hip_err(launch_backward(dbd, (int)bw.size(), bw[0]->hd.mixed != 0, lb, bwd_variant(bw[0], fl), 0,
+                                                  has_mesh(bw.data(), (int)bw.size()), sb));
         }
         const int r1 = hip_err(hipStreamSynchronize(sf));
         const int r2 = hip_err(hipStreamSynchronize(sb));

@@ -261,7 +261,7 @@ __device__ __forceinline__ void solve_P(const SimDev &S, auto b, auto T, auto Y,
 // or vertex with closest point q: r = |x - q|, s = the side of the face,
 // phi = s r, n = s (x - q) / r (the face normal when r = 0).  region: 0 face,
 // 1 vertex, 2 edge, whose unit direction goes to e.
-__device__ __noinline__ void mesh_frame(const ObstacleDev &ob, const double *x, double *n, double &phi, int &region,
+__device__ __forceinline__ void mesh_frame(const ObstacleDev &ob, const double *x, double *n, double &phi, int &region,
                                         double *e) {
     // unfused arithmetic in the written order: a node resting on a face has
     // phi = 0 exactly, and the contact test phi <= 0 must come out the same
@@ -350,14 +350,19 @@ __device__ __noinline__ void mesh_frame(const ObstacleDev &ob, const double *x, 
     }
 }
 
+template <bool MESH = true>
 __device__ __forceinline__ void contact_frame(const SimDev &S, int o, auto xi, double *n, double &phi) {
     const ObstacleDev &ob = S.obst[o];
-    if (ob.type == 2) {
-        const double x[3] = {xi[0], xi[1], xi[2]};
-        int reg;
-        double e[3];
-        mesh_frame(ob, x, n, phi, reg, e);
-    } else if (ob.type == 0) {
+    if constexpr (MESH) {
+        if (ob.type == 2) {
+            const double x[3] = {xi[0], xi[1], xi[2]};
+            int reg;
+            double e[3];
+            mesh_frame(ob, x, n, phi, reg, e);
+            return;
+        }
+    }
+    if (ob.type == 0) {
         n[0] = ob.n[0]; n[1] = ob.n[1]; n[2] = ob.n[2];
         phi = (xi[0] - ob.p[0]) * n[0] + (xi[1] - ob.p[1]) * n[1] + (xi[2] - ob.p[2]) * n[2];
     } else {
@@ -368,12 +373,15 @@ __device__ __forceinline__ void contact_frame(const SimDev &S, int o, auto xi, d
     }
 }
 
+template <bool MESH>
 __device__ __forceinline__ double signed_distance(const ObstacleDev &ob, const double *y) {
-    if (ob.type == 2) {
-        double n[3], phi, e[3];
-        int reg;
-        mesh_frame(ob, y, n, phi, reg, e);
-        return phi;
+    if constexpr (MESH) {
+        if (ob.type == 2) {
+            double n[3], phi, e[3];
+            int reg;
+            mesh_frame(ob, y, n, phi, reg, e);
+            return phi;
+        }
     }
     if (ob.type == 0)
         return (y[0] - ob.p[0]) * ob.n[0] + (y[1] - ob.p[1]) * ob.n[1] + (y[2] - ob.p[2]) * ob.n[2];
@@ -612,6 +620,7 @@ __global__ __launch_bounds__(kBlock) void k_forward(const SimDev *__restrict__ s
     const double h = S.h;
     const bool converge = S.fwd_tol > 0;
     constexpr bool kv = (FL & kLdsVectors) != 0, ku = (FL & kLdsUpdates) != 0, kx = (FL & kLdsPositions) != 0;
+    constexpr bool km = (FL & kMeshObst) != 0;
     const int off_u = kv ? 6 * m : 0, off_x = off_u + (ku ? S.n_ubuf : 0);
     auto A = pick<kv>(dyn, G(S.vk));
     auto B = pick<kv>(dyn + 3 * m, G(S.rhs));
@@ -646,17 +655,19 @@ __global__ __launch_bounds__(kBlock) void k_forward(const SimDev *__restrict__ s
             double best = 0.0;
             int ob = -1;
             for (int o = 0; o < S.n_obst; ++o) {
-                const double phi = signed_distance(S.obst[o], y);
+                const double phi = signed_distance<km>(S.obst[o], y);
                 if (ob < 0 || phi < best) { best = phi; ob = o; }
             }
             const bool contact = ob >= 0 && best <= 0.0;
             G(S.mode)[i] = contact ? TAKEOFF : FREE;
             G(S.cobst)[i] = contact ? (int8_t)ob : (int8_t)-1;
-            if (contact && S.obst[ob].type == 2) {         // the step's frame at x_n, scanned once
-                double nr[3], ph;
-                contact_frame(S, ob, xi, nr, ph);
-                for (int d = 0; d < 3; ++d) G(S.cfr)[4 * i + d] = nr[d];
-                G(S.cfr)[4 * i + 3] = ph;
+            if constexpr (km) {
+                if (contact && S.obst[ob].type == 2) {     // the step's frame at x_n, scanned once
+                    double nr[3], ph;
+                    contact_frame<true>(S, ob, xi, nr, ph);
+                    for (int d = 0; d < 3; ++d) G(S.cfr)[4 * i + d] = nr[d];
+                    G(S.cfr)[4 * i + 3] = ph;
+                }
             }
             double kx0 = 0, kx1 = 0, kx2 = 0;
             for (int p = G(S.ks_ptr)[i]; p < G(S.ks_ptr)[i + 1]; ++p) {
@@ -703,11 +714,13 @@ __global__ __launch_bounds__(kBlock) void k_forward(const SimDev *__restrict__ s
                     const double ub[3] = {B[3 * i] - G(S.f)[3 * i] / mi, B[3 * i + 1] - G(S.f)[3 * i + 1] / mi,
                                           B[3 * i + 2] - G(S.f)[3 * i + 2] / mi};
                     double nrm[3], phi, vv[3], ff[3];
-                    if (S.obst[G(S.cobst)[i]].type == 2) {         // mesh: the frame cached at the step's start
+                    bool cached = false;                            // mesh: the frame of the step's start
+                    if constexpr (km) cached = S.obst[G(S.cobst)[i]].type == 2;
+                    if (cached) {
                         for (int d = 0; d < 3; ++d) nrm[d] = G(S.cfr)[4 * i + d];
                         phi = G(S.cfr)[4 * i + 3];
                     } else {
-                        contact_frame(S, G(S.cobst)[i], XN + 3 * i, nrm, phi);
+                        contact_frame<false>(S, G(S.cobst)[i], XN + 3 * i, nrm, phi);
                     }
                     G(S.mode)[i] = signorini_coulomb(ub, nrm, phi, S.obst[G(S.cobst)[i]].mu, h, mi, vv, ff);
                     for (int d = 0; d < 3; ++d) {
@@ -1636,6 +1649,7 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
     __shared__ double red[kBlock / 64];
     constexpr bool kv = (FL & kLdsVectors) != 0, ku = (FL & kLdsUpdates) != 0;
     constexpr bool direct = (FL & kAdjDirect) != 0;      // per-step factors (else fixed point + GMRES)
+    constexpr bool km = (FL & kMeshObst) != 0;
     auto T = pick<kv>(dyn, G(S.rhs));
     auto Y = pick<kv>(dyn + 3 * S.m, G(S.ysol));
     auto U = pick<ku>(dyn + (kv ? 6 * S.m : 0), G(S.ubuf));
@@ -1682,7 +1696,7 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
             }
             if (mode[i] == SLIP) {
                 double nrm[3], phi;
-                contact_frame(S, obst[i], x0 + 3 * i, nrm, phi);
+                contact_frame<km>(S, obst[i], x0 + 3 * i, nrm, phi);
                 const auto ub = ubr + 3 * i;
                 const double mu = S.obst[obst[i]].mu;
                 const double un = nrm[0] * ub[0] + nrm[1] * ub[1] + nrm[2] * ub[2];
@@ -1834,7 +1848,7 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
             if (md == STICK || md == SLIP) {
                 const int o = obst[i];
                 double nrm[3], phi;
-                contact_frame(S, o, x0 + 3 * i, nrm, phi);
+                contact_frame<km>(S, o, x0 + 3 * i, nrm, phi);
                 const double lam[3] = {mi * zeta[3 * i], mi * zeta[3 * i + 1], mi * zeta[3 * i + 2]};
                 const double nl = nrm[0] * lam[0] + nrm[1] * lam[1] + nrm[2] * lam[2];
                 double dphi, dn[3];
@@ -1867,17 +1881,19 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
                     const double r = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
                     const double ndn = nrm[0] * dn[0] + nrm[1] * dn[1] + nrm[2] * dn[2];
                     for (int d = 0; d < 3; ++d) dx[d] += (dn[d] - ndn * nrm[d]) / r;
-                } else if (S.obst[o].type == 2) {
-                    // dn/dx of the mesh frame at x_n: 0 on a face, (I - n n^T)/phi at
-                    // a vertex, (I - n n^T - e e^T)/phi on an edge; phi = 0: as a face
-                    const double xv[3] = {x0[3 * i], x0[3 * i + 1], x0[3 * i + 2]};
-                    double nm[3], pm, em[3];
-                    int reg;
-                    mesh_frame(S.obst[o], xv, nm, pm, reg, em);
-                    if (reg != 0 && pm != 0.0) {
-                        const double ndn = nm[0] * dn[0] + nm[1] * dn[1] + nm[2] * dn[2];
-                        const double edn = em[0] * dn[0] + em[1] * dn[1] + em[2] * dn[2];
-                        for (int d = 0; d < 3; ++d) dx[d] += (dn[d] - ndn * nm[d] - edn * em[d]) / pm;
+                } else if constexpr (km) {
+                    if (S.obst[o].type == 2) {
+                        // dn/dx of the mesh frame at x_n: 0 on a face, (I - n n^T)/phi at
+                        // a vertex, (I - n n^T - e e^T)/phi on an edge; phi = 0: as a face
+                        const double xv[3] = {x0[3 * i], x0[3 * i + 1], x0[3 * i + 2]};
+                        double nm[3], pm, em[3];
+                        int reg;
+                        mesh_frame(S.obst[o], xv, nm, pm, reg, em);
+                        if (reg != 0 && pm != 0.0) {
+                            const double ndn = nm[0] * dn[0] + nm[1] * dn[1] + nm[2] * dn[2];
+                            const double edn = em[0] * dn[0] + em[1] * dn[1] + em[2] * dn[2];
+                            for (int d = 0; d < 3; ++d) dx[d] += (dn[d] - ndn * nm[d] - edn * em[d]) / pm;
+                        }
                     }
                 }
             }
@@ -1972,26 +1988,24 @@ static void bwd_one(const SimDev *d, int n, size_t lds, int helpers, hipStream_t
     hipLaunchKernelGGL((k_backward<MIXED, FL>), dim3(grid), dim3(kBlockAdj), lds, st, d, helpers);
 }
 
-hipError_t launch_forward(const SimDev *d_sims, int n, bool mixed, size_t lds, int flags, int helpers, hipStream_t st) {
+#define DC_V16(f, M) f<M, 0>, f<M, 1>, f<M, 2>, f<M, 3>, f<M, 4>, f<M, 5>, f<M, 6>, f<M, 7>, \
+    f<M, 8>, f<M, 9>, f<M, 10>, f<M, 11>, f<M, 12>, f<M, 13>, f<M, 14>, f<M, 15>
+
+// mesh: a handle of the launch has a triangle-mesh obstacle (the kMeshObst variant)
+hipError_t launch_forward(const SimDev *d_sims, int n, bool mixed, size_t lds, int flags, int helpers, bool mesh,
+                          hipStream_t st) {
     using F = void (*)(const SimDev *, int, size_t, int, hipStream_t);
-    static const F tab[2][8] = {
-        {fwd_one<false, 0>, fwd_one<false, 1>, fwd_one<false, 2>, fwd_one<false, 3>, fwd_one<false, 4>,
-         fwd_one<false, 5>, fwd_one<false, 6>, fwd_one<false, 7>},
-        {fwd_one<true, 0>, fwd_one<true, 1>, fwd_one<true, 2>, fwd_one<true, 3>, fwd_one<true, 4>,
-         fwd_one<true, 5>, fwd_one<true, 6>, fwd_one<true, 7>}};
-    tab[mixed ? 1 : 0][flags & 7](d_sims, n, lds, helpers, st);
+    static const F tab[2][16] = {{DC_V16(fwd_one, false)}, {DC_V16(fwd_one, true)}};
+    tab[mixed ? 1 : 0][(flags & 7) | (mesh ? kMeshObst : 0)](d_sims, n, lds, helpers, st);
     return hipGetLastError();
 }
 
-hipError_t launch_backward(const SimDev *d_sims, int n, bool mixed, size_t lds, int flags, int helpers,
+hipError_t launch_backward(const SimDev *d_sims, int n, bool mixed, size_t lds, int flags, int helpers, bool mesh,
                            hipStream_t st) {
     if (helpers > 0 && n != 1) return hipErrorInvalidValue;
     using F = void (*)(const SimDev *, int, size_t, int, hipStream_t);
-    static const F tab[2][8] = {{bwd_one<false, 0>, bwd_one<false, 1>, bwd_one<false, 2>, bwd_one<false, 3>,
-                                 bwd_one<false, 4>, bwd_one<false, 5>, bwd_one<false, 6>, bwd_one<false, 7>},
-                                {bwd_one<true, 0>, bwd_one<true, 1>, bwd_one<true, 2>, bwd_one<true, 3>,
-                                 bwd_one<true, 4>, bwd_one<true, 5>, bwd_one<true, 6>, bwd_one<true, 7>}};
-    tab[mixed ? 1 : 0][flags & 7](d_sims, n, lds, helpers, st);
+    static const F tab[2][16] = {{DC_V16(bwd_one, false)}, {DC_V16(bwd_one, true)}};
+    tab[mixed ? 1 : 0][(flags & 7) | (mesh ? kMeshObst : 0)](d_sims, n, lds, helpers, st);
     return hipGetLastError();
 }
 
@@ -2009,14 +2023,11 @@ hipError_t configure_lds(size_t fwd_bytes, size_t bwd_bytes) {
     hipError_t e = hipSuccess, r;
 #define DC_SETF(M, F) if ((r = set_fwd<M, F>(fwd_bytes)) != hipSuccess) e = r;
 #define DC_SETB(M, F) if ((r = set_bwd<M, F>(bwd_bytes)) != hipSuccess) e = r;
-    DC_SETF(false, 0) DC_SETF(false, 1) DC_SETF(false, 2) DC_SETF(false, 3)
-    DC_SETF(false, 4) DC_SETF(false, 5) DC_SETF(false, 6) DC_SETF(false, 7)
-    DC_SETF(true, 0) DC_SETF(true, 1) DC_SETF(true, 2) DC_SETF(true, 3)
-    DC_SETF(true, 4) DC_SETF(true, 5) DC_SETF(true, 6) DC_SETF(true, 7)
-    DC_SETB(false, 0) DC_SETB(false, 1) DC_SETB(false, 2) DC_SETB(false, 3)
-    DC_SETB(false, 4) DC_SETB(false, 5) DC_SETB(false, 6) DC_SETB(false, 7)
-    DC_SETB(true, 0) DC_SETB(true, 1) DC_SETB(true, 2) DC_SETB(true, 3)
-    DC_SETB(true, 4) DC_SETB(true, 5) DC_SETB(true, 6) DC_SETB(true, 7)
+#define DC_SET16(X, M) X(M, 0) X(M, 1) X(M, 2) X(M, 3) X(M, 4) X(M, 5) X(M, 6) X(M, 7) \
+    X(M, 8) X(M, 9) X(M, 10) X(M, 11) X(M, 12) X(M, 13) X(M, 14) X(M, 15)
+    DC_SET16(DC_SETF, false) DC_SET16(DC_SETF, true)
+    DC_SET16(DC_SETB, false) DC_SET16(DC_SETB, true)
+#undef DC_SET16
 #undef DC_SETF
 #undef DC_SETB
     return e;
@@ -2028,11 +2039,13 @@ hipError_t kernel_static_lds(size_t *fwd, size_t *bwd) {
     *fwd = 0;
     *bwd = 0;
     const void *fk[] = {(const void *)k_forward<false, 0>, (const void *)k_forward<false, 7>,
-                        (const void *)k_forward<true, 0>, (const void *)k_forward<true, 7>};
+                        (const void *)k_forward<true, 0>, (const void *)k_forward<true, 7>,
+                        (const void *)k_forward<false, 8>, (const void *)k_forward<true, 15>};
     const void *bk[] = {(const void *)k_backward<false, 0>, (const void *)k_backward<false, 3>,
                         (const void *)k_backward<true, 0>, (const void *)k_backward<true, 3>,
                         (const void *)k_backward<false, 4>, (const void *)k_backward<false, 7>,
-                        (const void *)k_backward<true, 4>, (const void *)k_backward<true, 7>};
+                        (const void *)k_backward<true, 4>, (const void *)k_backward<true, 7>,
+                        (const void *)k_backward<false, 8>, (const void *)k_backward<true, 15>};
     for (const void *f : fk) {
         hipError_t e = hipFuncGetAttributes(&a, f);
         if (e != hipSuccess) return e;

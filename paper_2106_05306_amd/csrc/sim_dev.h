@@ -16,6 +16,9 @@ constexpr int kSolveBatch = 4;      // 16-byte loads per lane in flight in the t
 // the adjoint kernel, the adjoint solver (the bit value 4 means kLdsPositions
 // in the forward kernel and kAdjDirect in the adjoint kernel).
 constexpr int kLdsVectors = 1, kLdsUpdates = 2, kLdsPositions = 4, kAdjDirect = 4;
+// variant bit of both kernels: code for triangle-mesh obstacles compiled in
+// (kept out of the other variants, whose register budget it would cost)
+constexpr int kMeshObst = 8;
 constexpr int kTeam = 8;             // lanes cooperating on one solve row / column
 constexpr int kKryM = 60;            // GMRES restart length of the adjoint fallback
 

@@ -71,8 +71,10 @@ def test_triangulated_plane_equals_the_plane():
     sm.obstacles = [scenes.mesh_obstacle(V, np.array([[0, 3, 2], [0, 2, 1]], np.int32), 0.3)]
     a, ga, _ = _parity(sp, precision="fp64")
     b, gb, _ = _parity(sm, precision="fp64")
+    # the two run different kernel variants (with and without the mesh code),
+    # compiled apart: equal up to the rounding of fused arithmetic
     for k in ("dx0", "dv0", "dw_edge", "dmu"):
-        assert torch.allclose(ga[k], gb[k], rtol=1e-12, atol=0), k
+        assert _rel(ga[k].cpu().numpy(), gb[k].cpu().numpy()) <= 1e-10, k
 
 
 @pytest.mark.parametrize("level,solver", [(1, "direct"), (1, "iterative"), (2, "direct")])
