@@ -420,8 +420,10 @@ void build_device(sim *s) {
         D.obst[o].radius = ob.radius;
         D.obst[o].mu = ob.mu;
         D.obst[o].n_tris = ob.type == SIM_MESH ? ob.n_tris : 0;
+        D.obst[o].closed = ob.type == SIM_MESH ? hm.obst_closed[o] : 0;
+        for (int d = 0; d < 4; ++d) D.obst[o].ball[d] = hm.obst_ball.empty() ? 0.0 : hm.obst_ball[4 * o + d];
         D.obst[o].tri = ob.type == SIM_MESH ? upload(s, hm.obst_tri[o]) : nullptr;
-        if (ob.type == SIM_MESH && !D.cfr) D.cfr = zeros<double>(s, 4 * (size_t)m);
+        if (ob.type == SIM_MESH && !D.cfr) D.cfr = zeros<double>(s, 8 * (size_t)m);
     }
     const auto &perm = hm.perm, &iperm = hm.iperm;
     // masses

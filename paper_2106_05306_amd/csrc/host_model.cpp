@@ -79,11 +79,13 @@ int HostModel::build(const sim_mesh_t *mesh, const sim_params_t *p) {
         if (!(o.mu >= 0) || !std::isfinite(o.mu)) { error = "friction must be >= 0"; return SIM_EINVAL; }
     }
     obst_tri.assign(obstacles.size(), {});
+    obst_closed.assign(obstacles.size(), 0);
+    obst_ball.assign(4 * obstacles.size(), 0.0);
     for (size_t k = 0; k < obstacles.size(); ++k) {
         sim_obstacle_t &o = obstacles[k];
         if (o.type == SIM_MESH) {
             std::vector<double> &tri = obst_tri[k];
-            tri.resize(12 * (size_t)o.n_tris);
+            tri.resize(16 * (size_t)o.n_tris);
             for (int t = 0; t < o.n_tris; ++t) {
                 const double *v[3];
                 for (int r = 0; r < 3; ++r) {
@@ -92,7 +94,7 @@ int HostModel::build(const sim_mesh_t *mesh, const sim_params_t *p) {
                     v[r] = o.verts + 3 * (size_t)vi;
                     for (int d = 0; d < 3; ++d) {
                         if (!std::isfinite(v[r][d])) { error = "mesh obstacle: non-finite vertex"; return SIM_EINVAL; }
-                        tri[12 * t + 3 * r + d] = v[r][d];
+                        tri[16 * t + 3 * r + d] = v[r][d];
                     }
                 }
                 const double u[3] = {v[1][0] - v[0][0], v[1][1] - v[0][1], v[1][2] - v[0][2]};
@@ -100,8 +102,38 @@ int HostModel::build(const sim_mesh_t *mesh, const sim_params_t *p) {
                 double nn[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
                 const double ln = norm3(nn);
                 if (!(ln > 0)) { error = "mesh obstacle: degenerate triangle"; return SIM_EINVAL; }
-                for (int d = 0; d < 3; ++d) tri[12 * t + 9 + d] = nn[d] / ln;
+                for (int d = 0; d < 3; ++d) tri[16 * t + 9 + d] = nn[d] / ln;
+                // bounding ball: the centroid and the largest vertex distance (+ margin)
+                double c[3], rb = 0.0;
+                for (int d = 0; d < 3; ++d) c[d] = (v[0][d] + v[1][d] + v[2][d]) / 3.0;
+                for (int r = 0; r < 3; ++r) {
+                    const double e[3] = {v[r][0] - c[0], v[r][1] - c[1], v[r][2] - c[2]};
+                    rb = std::max(rb, norm3(e));
+                }
+                for (int d = 0; d < 3; ++d) tri[16 * t + 12 + d] = c[d];
+                tri[16 * t + 15] = rb * (1.0 + 1e-12) + 1e-300;
             }
+        }
+        if (o.type == SIM_MESH) {
+            // closed: each directed edge appears once and its reverse once
+            std::map<std::pair<int, int>, int> de;
+            for (int t = 0; t < o.n_tris; ++t)
+                for (int r = 0; r < 3; ++r) ++de[{o.tris[3 * t + r], o.tris[3 * t + (r + 1) % 3]}];
+            bool closed = true;
+            for (const auto &kv : de) {
+                auto it = de.find({kv.first.second, kv.first.first});
+                if (kv.second != 1 || it == de.end() || it->second != 1) { closed = false; break; }
+            }
+            double c[3] = {0, 0, 0}, r = 0;
+            for (int v = 0; v < o.n_verts; ++v)
+                for (int d = 0; d < 3; ++d) c[d] += o.verts[3 * v + d] / o.n_verts;
+            for (int v = 0; v < o.n_verts; ++v) {
+                const double e[3] = {o.verts[3 * v] - c[0], o.verts[3 * v + 1] - c[1], o.verts[3 * v + 2] - c[2]};
+                r = std::max(r, norm3(e));
+            }
+            obst_closed[k] = closed ? 1 : 0;
+            for (int d = 0; d < 3; ++d) obst_ball[4 * k + d] = c[d];
+            obst_ball[4 * k + 3] = r * (1.0 + 1e-12) + 1e-12;    // rounding margin
         }
         o.verts = nullptr;                    // the caller's arrays are not kept
         o.tris = nullptr;

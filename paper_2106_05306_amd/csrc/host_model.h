@@ -22,9 +22,14 @@ struct HostModel {
     double fwd_tol = 0, adj_tol = 1e-10;
     int checkpoint_every = 0, adj_restart = 60, adj_solver = SIM_ADJ_ITERATIVE, adj_window = 0;
     std::vector<sim_obstacle_t> obstacles;  // mesh pointers cleared; geometry in obst_tri
-    // triangle-mesh obstacles: per obstacle, per triangle its vertices a, b, c
-    // and unit face normal (12 doubles), empty for planes and spheres
+    // triangle-mesh obstacles: per obstacle, per triangle its vertices a, b, c,
+    // unit face normal and bounding ball (centre, radius): 16 doubles; empty
+    // for planes and spheres
     std::vector<std::vector<double>> obst_tri;
+    // closed meshes (every edge shared by two triangles in opposite directions):
+    // a ball holding every vertex, outside of which phi > 0 without a scan
+    std::vector<int> obst_closed;
+    std::vector<double> obst_ball;          // per obstacle centre (3) and radius
 
     // ------------------------------------------------------------ constraints
     // All "norm" constraints (springs, then bending): A_c x = sum_k a_ck x_k,

@@ -254,87 +254,114 @@ __device__ __forceinline__ void solve_P(const SimDev &S, auto b, auto T, auto Y,
 
 // ------------------------------------------------------------------ geometry
 
-// Frame of a triangle-mesh obstacle at x: the closest triangle (a scan over
-// all of them, ties to the lowest index) and on it the closest point by its
-// Voronoi regions (tested in the order vertex a, vertex b, edge ab, vertex c,
-// edge ac, edge bc, face).  Face: n = the face normal, phi = n.(x - a).  Edge
-// or vertex with closest point q: r = |x - q|, s = the side of the face,
-// phi = s r, n = s (x - q) / r (the face normal when r = 0).  region: 0 face,
-// 1 vertex, 2 edge, whose unit direction goes to e.
+// Closest point of triangle T (a, b, c, unit face normal, bounding-ball
+// centre and radius: 16 doubles) to x
+// by Voronoi regions; returns the distance (plane distance on the face) and
+// the region (0 face, 1 vertex, 2 edge).  WANT: also the closest point q, the
+// edge vector ed (unnormalised) and the face distance fd.
+template <bool WANT>
+__device__ __forceinline__ double tri_closest(GLOBAL const double *T, const double *x, int &reg, double *q, double *ed,
+                                              double &fd) {
+#pragma clang fp contract(off)
+    const double ab[3] = {T[3] - T[0], T[4] - T[1], T[5] - T[2]};
+    const double ac[3] = {T[6] - T[0], T[7] - T[1], T[8] - T[2]};
+    const double ap[3] = {x[0] - T[0], x[1] - T[1], x[2] - T[2]};
+    const double bp[3] = {x[0] - T[3], x[1] - T[4], x[2] - T[5]};
+    const double cp[3] = {x[0] - T[6], x[1] - T[7], x[2] - T[8]};
+    const double d1 = ab[0] * ap[0] + ab[1] * ap[1] + ab[2] * ap[2];
+    const double d2 = ac[0] * ap[0] + ac[1] * ap[1] + ac[2] * ap[2];
+    const double d3 = ab[0] * bp[0] + ab[1] * bp[1] + ab[2] * bp[2];
+    const double d4 = ac[0] * bp[0] + ac[1] * bp[1] + ac[2] * bp[2];
+    const double d5 = ab[0] * cp[0] + ab[1] * cp[1] + ab[2] * cp[2];
+    const double d6 = ac[0] * cp[0] + ac[1] * cp[1] + ac[2] * cp[2];
+    const double vc = d1 * d4 - d3 * d2, vb = d5 * d2 - d1 * d6, va = d3 * d6 - d5 * d4;
+    double r[3];                                     // x - q
+    if (d1 <= 0 && d2 <= 0) {
+        reg = 1;
+        for (int d = 0; d < 3; ++d) r[d] = ap[d];
+        if constexpr (WANT) for (int d = 0; d < 3; ++d) q[d] = T[d];
+    } else if (d3 >= 0 && d4 <= d3) {
+        reg = 1;
+        for (int d = 0; d < 3; ++d) r[d] = bp[d];
+        if constexpr (WANT) for (int d = 0; d < 3; ++d) q[d] = T[3 + d];
+    } else if (vc <= 0 && d1 >= 0 && d3 <= 0) {
+        reg = 2;
+        const double v = d1 / (d1 - d3);
+        double qq[3];
+        for (int d = 0; d < 3; ++d) { qq[d] = T[d] + v * ab[d]; r[d] = x[d] - qq[d]; }
+        if constexpr (WANT) for (int d = 0; d < 3; ++d) { q[d] = qq[d]; ed[d] = ab[d]; }
+    } else if (d6 >= 0 && d5 <= d6) {
+        reg = 1;
+        for (int d = 0; d < 3; ++d) r[d] = cp[d];
+        if constexpr (WANT) for (int d = 0; d < 3; ++d) q[d] = T[6 + d];
+    } else if (vb <= 0 && d2 >= 0 && d6 <= 0) {
+        reg = 2;
+        const double w = d2 / (d2 - d6);
+        double qq[3];
+        for (int d = 0; d < 3; ++d) { qq[d] = T[d] + w * ac[d]; r[d] = x[d] - qq[d]; }
+        if constexpr (WANT) for (int d = 0; d < 3; ++d) { q[d] = qq[d]; ed[d] = ac[d]; }
+    } else if (va <= 0 && d4 - d3 >= 0 && d5 - d6 >= 0) {
+        reg = 2;
+        const double w = (d4 - d3) / ((d4 - d3) + (d5 - d6));
+        double qq[3];
+        for (int d = 0; d < 3; ++d) { qq[d] = T[3 + d] + w * (T[6 + d] - T[3 + d]); r[d] = x[d] - qq[d]; }
+        if constexpr (WANT) for (int d = 0; d < 3; ++d) { q[d] = qq[d]; ed[d] = T[6 + d] - T[3 + d]; }
+    } else {
+        reg = 0;
+        r[0] = r[1] = r[2] = 0.0;
+    }
+    const double f = T[9] * ap[0] + T[10] * ap[1] + T[11] * ap[2];
+    if constexpr (WANT) fd = f;
+    return reg == 0 ? fabs(f) : sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+}
+
+// Frame of a triangle-mesh obstacle at x: the closest triangle (ties to the
+// lowest index; a first sweep bounds the distance by the triangles' balls,
+// |x - c_t| + r_t, and the exact test runs only where |x - c_t| - r_t can
+// reach that bound), then
+// its closest point by Voronoi regions (tested in the order vertex a, vertex
+// b, edge ab, vertex c, edge ac, edge bc, face).  Face: n = the face normal,
+// phi = n.(x - a).  Edge or vertex with closest point q: r = |x - q|, s = the
+// side of the face, phi = s r, n = s (x - q) / r (the face normal when r = 0).
+// region: 0 face, 1 vertex, 2 edge, whose unit direction goes to e.  The
+// arithmetic is unfused, in the written order: a node resting on a face has
+// phi = 0 exactly, and the contact test phi <= 0 must come out the same in any
+// implementation that evaluates these formulas as written.
 __device__ __forceinline__ void mesh_frame(const ObstacleDev &ob, const double *x, double *n, double &phi, int &region,
-                                        double *e) {
-    // unfused arithmetic in the written order: a node resting on a face has
-    // phi = 0 exactly, and the contact test phi <= 0 must come out the same
-    // in any implementation that evaluates these formulas as written
+                                           double *e) {
 #pragma clang fp contract(off)
     const auto tri = (GLOBAL const double *)ob.tri;
-    double best = INFINITY, bfd = 0.0, bq[3] = {0.0, 0.0, 0.0}, bn[3] = {0.0, 1.0, 0.0}, bed[3] = {0.0, 0.0, 0.0};
-    int breg = 0;
+    double ub = INFINITY;                            // >= the distance to the mesh
     for (int t = 0; t < ob.n_tris; ++t) {
-        const auto T = tri + 12 * (int64_t)t;
-        const double a[3] = {T[0], T[1], T[2]}, b[3] = {T[3], T[4], T[5]}, c[3] = {T[6], T[7], T[8]};
-        double ab[3], ac[3], ap[3], bp[3], cp[3];
-        for (int d = 0; d < 3; ++d) {
-            ab[d] = b[d] - a[d]; ac[d] = c[d] - a[d];
-            ap[d] = x[d] - a[d]; bp[d] = x[d] - b[d]; cp[d] = x[d] - c[d];
-        }
-        const double d1 = ab[0] * ap[0] + ab[1] * ap[1] + ab[2] * ap[2];
-        const double d2 = ac[0] * ap[0] + ac[1] * ap[1] + ac[2] * ap[2];
-        const double d3 = ab[0] * bp[0] + ab[1] * bp[1] + ab[2] * bp[2];
-        const double d4 = ac[0] * bp[0] + ac[1] * bp[1] + ac[2] * bp[2];
-        const double d5 = ab[0] * cp[0] + ab[1] * cp[1] + ab[2] * cp[2];
-        const double d6 = ac[0] * cp[0] + ac[1] * cp[1] + ac[2] * cp[2];
-        const double vc = d1 * d4 - d3 * d2, vb = d5 * d2 - d1 * d6, va = d3 * d6 - d5 * d4;
-        double q[3], ed[3] = {0.0, 0.0, 0.0};
-        int reg;
-        if (d1 <= 0 && d2 <= 0) {
-            reg = 1;
-            for (int d = 0; d < 3; ++d) q[d] = a[d];
-        } else if (d3 >= 0 && d4 <= d3) {
-            reg = 1;
-            for (int d = 0; d < 3; ++d) q[d] = b[d];
-        } else if (vc <= 0 && d1 >= 0 && d3 <= 0) {
-            reg = 2;
-            const double v = d1 / (d1 - d3);
-            for (int d = 0; d < 3; ++d) { q[d] = a[d] + v * ab[d]; ed[d] = ab[d]; }
-        } else if (d6 >= 0 && d5 <= d6) {
-            reg = 1;
-            for (int d = 0; d < 3; ++d) q[d] = c[d];
-        } else if (vb <= 0 && d2 >= 0 && d6 <= 0) {
-            reg = 2;
-            const double w = d2 / (d2 - d6);
-            for (int d = 0; d < 3; ++d) { q[d] = a[d] + w * ac[d]; ed[d] = ac[d]; }
-        } else if (va <= 0 && d4 - d3 >= 0 && d5 - d6 >= 0) {
-            reg = 2;
-            const double w = (d4 - d3) / ((d4 - d3) + (d5 - d6));
-            for (int d = 0; d < 3; ++d) { q[d] = b[d] + w * (c[d] - b[d]); ed[d] = c[d] - b[d]; }
-        } else {
-            reg = 0;
-            for (int d = 0; d < 3; ++d) q[d] = 0.0;
-        }
-        const double fd = T[9] * ap[0] + T[10] * ap[1] + T[11] * ap[2];
-        double dist;
-        if (reg == 0) {
-            dist = fabs(fd);
-        } else {
-            const double r0 = x[0] - q[0], r1 = x[1] - q[1], r2 = x[2] - q[2];
-            dist = sqrt(r0 * r0 + r1 * r1 + r2 * r2);
-        }
-        if (dist < best) {
-            best = dist;
-            breg = reg;
-            bfd = fd;
-            for (int d = 0; d < 3; ++d) { bq[d] = q[d]; bn[d] = T[9 + d]; bed[d] = ed[d]; }
-        }
+        const auto B = tri + 16 * (int64_t)t + 12;
+        const double c0 = x[0] - B[0], c1 = x[1] - B[1], c2 = x[2] - B[2];
+        ub = fmin(ub, sqrt(c0 * c0 + c1 * c1 + c2 * c2) + B[3]);
     }
+    ub = ub * (1.0 + 1e-12) + 1e-300;                // rounding margin of the bounds
+    double best = INFINITY;
+    int bt = 0;
+    for (int t = 0; t < ob.n_tris; ++t) {
+        const auto B = tri + 16 * (int64_t)t + 12;
+        const double c0 = x[0] - B[0], c1 = x[1] - B[1], c2 = x[2] - B[2];
+        if (sqrt(c0 * c0 + c1 * c1 + c2 * c2) - B[3] > ub) continue;   // farther than the bound
+        int reg;
+        double fd;
+        const double dist = tri_closest<false>(tri + 16 * (int64_t)t, x, reg, nullptr, nullptr, fd);
+        if (dist < best) { best = dist; bt = t; }
+    }
+    const auto T = tri + 16 * (int64_t)bt;
+    double q[3] = {0.0, 0.0, 0.0}, ed[3] = {0.0, 0.0, 0.0}, fd;
+    int breg;
+    (void)tri_closest<true>(T, x, breg, q, ed, fd);
+    const double bn[3] = {T[9], T[10], T[11]};
     region = breg;
     e[0] = e[1] = e[2] = 0.0;
     if (breg == 0) {
-        phi = bfd;
+        phi = fd;
         for (int d = 0; d < 3; ++d) n[d] = bn[d];
         return;
     }
-    const double r0 = x[0] - bq[0], r1 = x[1] - bq[1], r2 = x[2] - bq[2];
+    const double r0 = x[0] - q[0], r1 = x[1] - q[1], r2 = x[2] - q[2];
     const double r = sqrt(r0 * r0 + r1 * r1 + r2 * r2);
     const double sg = (bn[0] * r0 + bn[1] * r1 + bn[2] * r2 >= 0.0) ? 1.0 : -1.0;
     if (r > 0.0) {
@@ -345,8 +372,8 @@ __device__ __forceinline__ void mesh_frame(const ObstacleDev &ob, const double *
         for (int d = 0; d < 3; ++d) n[d] = bn[d];
     }
     if (breg == 2) {
-        const double le = sqrt(bed[0] * bed[0] + bed[1] * bed[1] + bed[2] * bed[2]);
-        for (int d = 0; d < 3; ++d) e[d] = bed[d] / le;
+        const double le = sqrt(ed[0] * ed[0] + ed[1] * ed[1] + ed[2] * ed[2]);
+        for (int d = 0; d < 3; ++d) e[d] = ed[d] / le;
     }
 }
 
@@ -377,6 +404,13 @@ template <bool MESH>
 __device__ __forceinline__ double signed_distance(const ObstacleDev &ob, const double *y) {
     if constexpr (MESH) {
         if (ob.type == 2) {
+            if (ob.closed) {
+                // outside a ball around a closed surface: outside the surface, and
+                // phi > 0 is all the contact test needs (not its value)
+                const double b0 = y[0] - ob.ball[0], b1 = y[1] - ob.ball[1], b2 = y[2] - ob.ball[2];
+                const double db = sqrt(b0 * b0 + b1 * b1 + b2 * b2);
+                if (db > ob.ball[3]) return db - ob.ball[3];
+            }
             double n[3], phi, e[3];
             int reg;
             mesh_frame(ob, y, n, phi, reg, e);
@@ -665,8 +699,8 @@ __global__ __launch_bounds__(kBlock) void k_forward(const SimDev *__restrict__ s
                 if (contact && S.obst[ob].type == 2) {     // the step's frame at x_n, scanned once
                     double nr[3], ph;
                     contact_frame<true>(S, ob, xi, nr, ph);
-                    for (int d = 0; d < 3; ++d) G(S.cfr)[4 * i + d] = nr[d];
-                    G(S.cfr)[4 * i + 3] = ph;
+                    for (int d = 0; d < 3; ++d) G(S.cfr)[8 * i + d] = nr[d];
+                    G(S.cfr)[8 * i + 3] = ph;
                 }
             }
             double kx0 = 0, kx1 = 0, kx2 = 0;
@@ -717,8 +751,8 @@ __global__ __launch_bounds__(kBlock) void k_forward(const SimDev *__restrict__ s
                     bool cached = false;                            // mesh: the frame of the step's start
                     if constexpr (km) cached = S.obst[G(S.cobst)[i]].type == 2;
                     if (cached) {
-                        for (int d = 0; d < 3; ++d) nrm[d] = G(S.cfr)[4 * i + d];
-                        phi = G(S.cfr)[4 * i + 3];
+                        for (int d = 0; d < 3; ++d) nrm[d] = G(S.cfr)[8 * i + d];
+                        phi = G(S.cfr)[8 * i + 3];
                     } else {
                         contact_frame<false>(S, G(S.cobst)[i], XN + 3 * i, nrm, phi);
                     }
@@ -1694,9 +1728,30 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
                 gbar[3 * i + d] = G(S.gv)[3 * i + d] + h * G(S.gx)[3 * i + d];
                 G(S.zeta)[3 * i + d] = 0.0;
             }
+            bool cached = false;
+            if constexpr (km) {
+                // mesh: the frame at x_n (normal, gap, edge direction, region) scanned
+                // once per step and node, for the blocks T_j and the gradients
+                if ((mode[i] == STICK || mode[i] == SLIP) && S.obst[obst[i]].type == 2) {
+                    const double xv[3] = {x0[3 * i], x0[3 * i + 1], x0[3 * i + 2]};
+                    double nm[3], pm, em[3];
+                    int reg;
+                    mesh_frame(S.obst[obst[i]], xv, nm, pm, reg, em);
+                    auto cf = G(S.cfr) + 8 * (int64_t)i;
+                    for (int d = 0; d < 3; ++d) { cf[d] = nm[d]; cf[4 + d] = em[d]; }
+                    cf[3] = pm;
+                    cf[7] = (double)reg;
+                    cached = true;
+                }
+            }
             if (mode[i] == SLIP) {
                 double nrm[3], phi;
-                contact_frame<km>(S, obst[i], x0 + 3 * i, nrm, phi);
+                if (cached) {
+                    for (int d = 0; d < 3; ++d) nrm[d] = G(S.cfr)[8 * i + d];
+                    phi = G(S.cfr)[8 * i + 3];
+                } else {
+                    contact_frame<false>(S, obst[i], x0 + 3 * i, nrm, phi);
+                }
                 const auto ub = ubr + 3 * i;
                 const double mu = S.obst[obst[i]].mu;
                 const double un = nrm[0] * ub[0] + nrm[1] * ub[1] + nrm[2] * ub[2];
@@ -1848,7 +1903,14 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
             if (md == STICK || md == SLIP) {
                 const int o = obst[i];
                 double nrm[3], phi;
-                contact_frame<km>(S, o, x0 + 3 * i, nrm, phi);
+                bool cached = false;                         // mesh: the frame scanned for T_j above
+                if constexpr (km) cached = S.obst[o].type == 2;
+                if (cached) {
+                    for (int d = 0; d < 3; ++d) nrm[d] = G(S.cfr)[8 * i + d];
+                    phi = G(S.cfr)[8 * i + 3];
+                } else {
+                    contact_frame<false>(S, o, x0 + 3 * i, nrm, phi);
+                }
                 const double lam[3] = {mi * zeta[3 * i], mi * zeta[3 * i + 1], mi * zeta[3 * i + 2]};
                 const double nl = nrm[0] * lam[0] + nrm[1] * lam[1] + nrm[2] * lam[2];
                 double dphi, dn[3];
@@ -1885,10 +1947,9 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
                     if (S.obst[o].type == 2) {
                         // dn/dx of the mesh frame at x_n: 0 on a face, (I - n n^T)/phi at
                         // a vertex, (I - n n^T - e e^T)/phi on an edge; phi = 0: as a face
-                        const double xv[3] = {x0[3 * i], x0[3 * i + 1], x0[3 * i + 2]};
-                        double nm[3], pm, em[3];
-                        int reg;
-                        mesh_frame(S.obst[o], xv, nm, pm, reg, em);
+                        const auto cf = G(S.cfr) + 8 * (int64_t)i;
+                        const double nm[3] = {cf[0], cf[1], cf[2]}, pm = cf[3], em[3] = {cf[4], cf[5], cf[6]};
+                        const int reg = (int)cf[7];
                         if (reg != 0 && pm != 0.0) {
                             const double ndn = nm[0] * dn[0] + nm[1] * dn[1] + nm[2] * dn[2];
                             const double edn = em[0] * dn[0] + em[1] * dn[1] + em[2] * dn[2];

@@ -98,8 +98,10 @@ struct LuSup {              // supernode (chunk) data of the direct adjoint fact
 struct ObstacleDev {
     int type;                         // 0 plane, 1 sphere, 2 triangle mesh
     int n_tris;                       // mesh: triangles
+    int closed;                       // mesh: closed surface (ball[] bounds it)
     double p[3], n[3], radius, mu;
-    const double *tri;                // mesh: per triangle a, b, c, unit face normal (12 doubles)
+    double ball[4];                   // mesh: centre and radius of a ball holding every vertex
+    const double *tri;                // mesh: per triangle a, b, c, unit face normal, ball (16 doubles)
 };
 
 struct SimDev {
@@ -194,7 +196,8 @@ struct SimDev {
     double *dw;                       // [nc_total] accumulated weight gradients (canonical)
     double *dmu;                      // [kMaxObstacles]
     const double *gx_steps;           // optional per-step dL/dx_n [(T+1)*m*3], new order
-    double *cfr;                      // [m*4] mesh obstacles: the current step's contact frame (n, phi)
+    double *cfr;                      // [m*8] mesh obstacles, per node the current step's contact
+                                      // frame: n, phi, edge direction, region
     // external force besides gravity: step n adds fscale[n] * fext (fext nullptr:
     // none; fscale nullptr: 1 at every step), and its gradients
     const double *fext;               // [m*3] new order
