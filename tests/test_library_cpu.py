@@ -71,11 +71,28 @@ def test_host_rejects_bad_inputs():
     assert e.value.code == B.SIM_EINVAL
 
 
+def test_host_checks_mesh_obstacles():
+    from paper_2106_05306_amd import sim as S
+    from paper_2106_05306_amd import _binding as B
+    sc = scenes.tiny_scene(3, obstacle="sphere")
+    V, T = scenes.icosphere((0.0, 0.0, 0.0), 0.25, 1)
+    ok = dict(type=B.SIM_MESH, p=(0, 0, 0), mu=0.4, verts=V, tris=T)
+    S.analyze(**S.scene_kwargs(sc, obstacles=[ok]))                  # accepted
+    for bad in (dict(ok, tris=np.where(T == 3, 999, T)),               # vertex index out of range
+                dict(ok, tris=np.array([[0, 1, 1]], np.int32)),        # degenerate triangle
+                dict(ok, verts=np.where(V == V[0, 0], np.nan, V)),     # non-finite vertex
+                dict(ok, tris=np.zeros((0, 3), np.int32))):            # no triangles
+        with pytest.raises(B.SimError) as e:
+            S.analyze(**S.scene_kwargs(sc, obstacles=[bad]))
+        assert e.value.code == B.SIM_EINVAL
+
+
 def test_null_handles_are_rejected_without_a_gpu():
     # argument checks run before any device work
     import ctypes
     B, L = _lib()
     assert L.sim_set_material(None, None, None, None, None) == B.SIM_EINVAL
+    assert L.sim_set_external_force(None, None, 0, None) == B.SIM_EINVAL
     assert L.sim_job_forward(None, 10) == B.SIM_EINVAL
     assert L.sim_job_backward(None, None, None) == B.SIM_EINVAL
     assert L.sim_job_grads(None, None) == B.SIM_EINVAL
