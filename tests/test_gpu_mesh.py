@@ -149,3 +149,39 @@ def test_resting_nodes_decide_contact_alike():
         assert np.array_equal(sim.modes(n), _modes(model, rec)), n
         err = np.abs(x1.cpu().numpy() - rec.x1).max()
         assert err <= 1e-9, (n, err)
+
+
+def test_batched_launch_mixing_mesh_and_analytic_obstacles():
+    # a batch whose handles mix a triangulated and an analytic sphere runs the
+    # mesh variant for all of them: every result equals its solo run bitwise
+    from paper_2106_05306_amd.sim import batch_backward, batch_forward
+    scs = []
+    for seed, mesh in ((21, True), (22, False), (23, True)):
+        sc = scenes.tiny_scene(5, steps=12, obstacle="sphere", k=80.0, mu=0.4, seed=seed, height=0.004,
+                               v0_scale=0.05)
+        if mesh:
+            o = sc.obstacles[0]
+            V, T = scenes.icosphere(o.point, o.radius, 1)
+            sc.obstacles = [scenes.mesh_obstacle(V, T, o.mu)]
+        scs.append(sc)
+    kw = dict(precision="fp64", adj_solver="direct", adj_tol=1e-10, adj_max_iters=20)
+    solo = []
+    for sc in scs:
+        s = _sim(sc, **kw)
+        xT, _, _ = s.forward(sc.steps)
+        solo.append((xT.clone(), s.backward(torch.ones_like(xT))))
+    sims = [_sim(sc, **kw) for sc in scs]
+    outs = batch_forward(sims, [sc.steps for sc in scs])
+    grads = batch_backward(sims, [torch.ones((sc.n_nodes, 3), dtype=torch.float64, device=DEV) for sc in scs])
+    for (xa, ga), (xb, _), gb, sc in zip(solo, outs, grads, scs):
+        # the analytic handle ran the other kernel variant alone: equal to rounding there
+        exact = sc.obstacles[0].kind == O.MESH
+        if exact:
+            assert torch.equal(xa, xb)
+        else:
+            assert _rel(xa.cpu().numpy(), xb.cpu().numpy()) <= 1e-12
+        for k in ("dx0", "dv0", "dw_edge", "dmu"):
+            if exact:
+                assert torch.equal(ga[k], gb[k]), k
+            else:
+                assert _rel(ga[k].cpu().numpy(), gb[k].cpu().numpy()) <= 1e-9, k
