@@ -353,6 +353,32 @@ def bench_napkin_force(args):
         print(f"napkin_force {row}", file=sys.stderr, flush=True)
         sizes.append(row)
         sim.close()
+    # 64 napkins with different forces (the samples of a population-based
+    # optimiser, or parallel restarts) in one batched forward and backward
+    from paper_2106_05306_amd.sim import batch_backward, batch_forward
+    nb = 64
+    scb = [scenes.flying_napkin(s, n=10, steps=60) for s in range(nb)]
+    sims_b = [Sim.from_scene(c, device=dev, precision="fp64", adj_solver="direct", adj_tol=1e-10,
+                             adj_max_iters=20) for c in scb]
+    seeds_b = [torch.ones((c.n_nodes, 3), dtype=torch.float64, device=dev) / c.n_nodes for c in scb]
+
+    def batched():
+        batch_forward(sims_b, [c.steps for c in scb])
+        return batch_backward(sims_b, seeds_b)
+
+    outs_b = batched()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        outs_b = batched()
+    torch.cuda.synchronize()
+    dt_b = (time.perf_counter() - t0) / args.steps
+    batch_row = {"rollouts": nb, "nodes": "10x10", "ms_per_batch": dt_b * 1e3, "rollouts_per_s": nb / dt_b,
+                 "speedup_vs_one_at_a_time": (nb / dt_b) / sizes[-1]["rollouts_per_s"],
+                 "statuses": sorted({int(o["status"]) for o in outs_b})}
+    print(f"napkin_force batch {batch_row}", file=sys.stderr, flush=True)
+    for sm in sims_b:
+        sm.close()
     # end-to-end finite difference at 10 x 10 (forward converged)
     sc = scenes.flying_napkin(0, n=10, steps=60)
     simc = Sim.from_scene(sc, device=dev, precision="fp64", adj_solver="direct", adj_tol=1e-12, adj_max_iters=20,
@@ -384,6 +410,7 @@ def bench_napkin_force(args):
                                "(mu 0.5), time-invariant seeded force on every node, 60 steps h=1/120, K=20, "
                                "centroid loss, direct adjoint (backward error 1e-10)", "precision": "fp64"},
         "sizes": sizes,
+        "batched": batch_row,
         "cpu_baseline": {"value": 1e3 / last["oracle_ms_per_rollout"], "unit": "rollouts/s", "cores": 1,
                          "kind": "oracle", "sample": "one whole 10x10 rollout, forward + direct-solve adjoint"},
         "finite_difference_check": {"size": "10x10", "forward": "converged to 1e-10 m/s", "eps": eps,
