@@ -239,8 +239,10 @@ int sim_create(const sim_mesh_t *mesh, const sim_params_t *params, void *hip_str
  * The backward pass then also returns dL/dF = h sum_n s_n z_n and
  * dL/ds_n = h F . z_n (z_n = T^T zeta of step n; sim_grads_t.dforce,
  * dforce_scale).  Invalidates any recorded rollout.  SIM_EINVAL on a NULL
- * handle, n_scale < 1 with a scale, or a non-finite multiplier; SIM_ENOMEM /
- * SIM_EHIP on device failures. */
+ * handle, n_scale < 1 with a scale, or a non-finite multiplier (the device
+ * field is not inspected: non-finite forces surface as non-finite states and
+ * the backward pass's SIM_WADJ_NONFINITE); SIM_ENOMEM / SIM_EHIP on device
+ * failures. */
 int sim_set_external_force(sim_t *sim, const double *force_dev, int32_t n_scale, const double *scale_host);
 
 /* Sets the initial state (device arrays [n_nodes*3], caller order).  NULL x0
