@@ -316,9 +316,9 @@ __device__ __forceinline__ double tri_closest(GLOBAL const double *T, const doub
 }
 
 // Frame of a triangle-mesh obstacle at x: the closest triangle (ties to the
-// lowest index; a first sweep bounds the distance by the triangles' balls,
-// |x - c_t| + r_t, and the exact test runs only where |x - c_t| - r_t can
-// reach that bound), then
+// lowest index; a first sweep bounds the distance by the nearest centroid c_t,
+// a point of the mesh, and the exact test runs only where the triangle's ball
+// can reach that bound, |x - c_t| - r_t <= bound), then
 // its closest point by Voronoi regions (tested in the order vertex a, vertex
 // b, edge ab, vertex c, edge ac, edge bc, face).  Face: n = the face normal,
 // phi = n.(x - a).  Edge or vertex with closest point q: r = |x - q|, s = the
@@ -331,19 +331,22 @@ __device__ __forceinline__ void mesh_frame(const ObstacleDev &ob, const double *
                                            double *e) {
 #pragma clang fp contract(off)
     const auto tri = (GLOBAL const double *)ob.tri;
-    double ub = INFINITY;                            // >= the distance to the mesh
-    for (int t = 0; t < ob.n_tris; ++t) {
+    double ub2 = INFINITY;                           // the centroids lie on the mesh: min |x - c_t|
+    for (int t = 0; t < ob.n_tris; ++t) {            // bounds the distance from above
         const auto B = tri + 16 * (int64_t)t + 12;
         const double c0 = x[0] - B[0], c1 = x[1] - B[1], c2 = x[2] - B[2];
-        ub = fmin(ub, sqrt(c0 * c0 + c1 * c1 + c2 * c2) + B[3]);
+        ub2 = fmin(ub2, c0 * c0 + c1 * c1 + c2 * c2);
     }
-    ub = ub * (1.0 + 1e-12) + 1e-300;                // rounding margin of the bounds
+    // rounding margin: relative, plus 1e-12 m for centroids rounded off their
+    // triangle (coordinates of order metres)
+    const double ub = sqrt(ub2) * (1.0 + 1e-12) + 1e-12;
     double best = INFINITY;
     int bt = 0;
     for (int t = 0; t < ob.n_tris; ++t) {
         const auto B = tri + 16 * (int64_t)t + 12;
         const double c0 = x[0] - B[0], c1 = x[1] - B[1], c2 = x[2] - B[2];
-        if (sqrt(c0 * c0 + c1 * c1 + c2 * c2) - B[3] > ub) continue;   // farther than the bound
+        const double reach = ub + B[3];
+        if (c0 * c0 + c1 * c1 + c2 * c2 > reach * reach) continue;    // |x - c_t| - r_t > ub
         int reg;
         double fd;
         const double dist = tri_closest<false>(tri + 16 * (int64_t)t, x, reg, nullptr, nullptr, fd);
