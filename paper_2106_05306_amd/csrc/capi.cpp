@@ -423,6 +423,15 @@ void build_device(sim *s) {
         D.obst[o].closed = ob.type == SIM_MESH ? hm.obst_closed[o] : 0;
         for (int d = 0; d < 4; ++d) D.obst[o].ball[d] = hm.obst_ball.empty() ? 0.0 : hm.obst_ball[4 * o + d];
         D.obst[o].tri = ob.type == SIM_MESH ? upload(s, hm.obst_tri[o]) : nullptr;
+        if (ob.type == SIM_MESH) {       // float copy of the triangles' balls for the culling sweeps
+            const std::vector<double> &tr = hm.obst_tri[o];
+            std::vector<float> b32(4 * (size_t)ob.n_tris);
+            for (int t = 0; t < ob.n_tris; ++t) {
+                for (int d = 0; d < 4; ++d) b32[4 * t + d] = (float)tr[16 * t + 12 + d];
+                b32[4 * t + 3] = std::nextafter((float)tr[16 * t + 15], INFINITY);   // radius rounded up
+            }
+            D.obst[o].ball32 = upload(s, b32);
+        }
         if (ob.type == SIM_MESH && !D.cfr) D.cfr = zeros<double>(s, 8 * (size_t)m);
     }
     const auto &perm = hm.perm, &iperm = hm.iperm;

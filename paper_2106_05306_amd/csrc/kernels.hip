@@ -26,6 +26,7 @@ __device__ __forceinline__ GLOBAL T *G(T *p) { return (GLOBAL T *)p; }
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v2i __attribute__((ext_vector_type(2)));
 typedef double v2d __attribute__((ext_vector_type(2)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 // compile-time choice between an LDS and an HBM pointer (their types differ)
 template <bool C, class P, class Q>
 __device__ __forceinline__ auto pick(P a, Q b) {
@@ -318,7 +319,8 @@ __device__ __forceinline__ double tri_closest(GLOBAL const double *T, const doub
 // Frame of a triangle-mesh obstacle at x: the closest triangle (ties to the
 // lowest index; a first sweep bounds the distance by the nearest centroid c_t,
 // a point of the mesh, and the exact test runs only where the triangle's ball
-// can reach that bound, |x - c_t| - r_t <= bound), then
+// can reach that bound, |x - c_t| - r_t <= bound; both sweeps in float with
+// margins), then
 // its closest point by Voronoi regions (tested in the order vertex a, vertex
 // b, edge ab, vertex c, edge ac, edge bc, face).  Face: n = the face normal,
 // phi = n.(x - a).  Edge or vertex with closest point q: r = |x - q|, s = the
@@ -331,22 +333,25 @@ __device__ __forceinline__ void mesh_frame(const ObstacleDev &ob, const double *
                                            double *e) {
 #pragma clang fp contract(off)
     const auto tri = (GLOBAL const double *)ob.tri;
-    double ub2 = INFINITY;                           // the centroids lie on the mesh: min |x - c_t|
+    const auto b32 = (GLOBAL const v4f *)ob.ball32;
+    // culling in float: coordinates of order metres round by < 1e-7 m, so the
+    // bounds carry a margin of 1e-6 m (a looser cull, never a wrong one)
+    constexpr float kCullMargin = 1e-6f;
+    const float xf0 = (float)x[0], xf1 = (float)x[1], xf2 = (float)x[2];
+    float ub2 = INFINITY;                            // the centroids lie on the mesh: min |x - c_t|
     for (int t = 0; t < ob.n_tris; ++t) {            // bounds the distance from above
-        const auto B = tri + 16 * (int64_t)t + 12;
-        const double c0 = x[0] - B[0], c1 = x[1] - B[1], c2 = x[2] - B[2];
-        ub2 = fmin(ub2, c0 * c0 + c1 * c1 + c2 * c2);
+        const v4f B = b32[t];
+        const float c0 = xf0 - B.x, c1 = xf1 - B.y, c2 = xf2 - B.z;
+        ub2 = fminf(ub2, c0 * c0 + c1 * c1 + c2 * c2);
     }
-    // rounding margin: relative, plus 1e-12 m for centroids rounded off their
-    // triangle (coordinates of order metres)
-    const double ub = sqrt(ub2) * (1.0 + 1e-12) + 1e-12;
+    const float ub = sqrtf(ub2) * (1.0f + 1e-6f) + 2.0f * kCullMargin;
     double best = INFINITY;
     int bt = 0;
     for (int t = 0; t < ob.n_tris; ++t) {
-        const auto B = tri + 16 * (int64_t)t + 12;
-        const double c0 = x[0] - B[0], c1 = x[1] - B[1], c2 = x[2] - B[2];
-        const double reach = ub + B[3];
-        if (c0 * c0 + c1 * c1 + c2 * c2 > reach * reach) continue;    // |x - c_t| - r_t > ub
+        const v4f B = b32[t];
+        const float c0 = xf0 - B.x, c1 = xf1 - B.y, c2 = xf2 - B.z;
+        const float reach = ub + B.w + kCullMargin;
+        if (c0 * c0 + c1 * c1 + c2 * c2 > reach * reach * (1.0f + 1e-6f)) continue;   // |x - c_t| - r_t > ub
         int reg;
         double fd;
         const double dist = tri_closest<false>(tri + 16 * (int64_t)t, x, reg, nullptr, nullptr, fd);

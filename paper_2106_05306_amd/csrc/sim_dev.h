@@ -102,6 +102,7 @@ struct ObstacleDev {
     double p[3], n[3], radius, mu;
     double ball[4];                   // mesh: centre and radius of a ball holding every vertex
     const double *tri;                // mesh: per triangle a, b, c, unit face normal, ball (16 doubles)
+    const float *ball32;              // mesh: per triangle its ball (centre, radius) in float
 };
 
 struct SimDev {
