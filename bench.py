@@ -298,7 +298,7 @@ def bench_skirt(args):
 
 
 def bench_napkin_force(args):
-    """Flying napkin (the control problem of Sec. 5 with time-invariant forces
+    """Flying napkin (the control problem of Sec. 5.2 with time-invariant forces
     on every node): n x n napkins, n = 4, 5, 7, 10 (48, 75, 147 and 300 force
     variables), 60 steps above the ground plane, K = 20, FP64, direct adjoint.
     Per size: forward + adjoint rollouts per second with the gradient w.r.t.

@@ -229,7 +229,7 @@ int sim_create(const sim_mesh_t *mesh, const sim_params_t *params, void *hip_str
  * enters the inertial predictor, the initial guess and the constant part of the
  * right-hand side b_hat (eqn pd_velocity); the applications' wind models
  * (Sec. 6: a sinusoidal gust times a direction, per-node coefficients) and the
- * time-invariant per-node control forces of Sec. 5 are of this form.
+ * time-invariant per-node control forces of Sec. 5.2 are of this form.
  *  force_dev   device [n_nodes*3] (caller order), copied on the handle's
  *              stream; NULL removes the external force;
  *  scale_host  host [n_scale] per-step multipliers s_n, copied before return;

@@ -206,7 +206,7 @@ class Model:
     # ----------------------------------------------------------------- helpers
     def force_at(self, n: int) -> np.ndarray:
         """External force besides gravity during step n: s_n F (part of f_ext in
-        eqn implicit_euler; a time-invariant field F scaled per step)."""
+        eqn implicit_v; a time-invariant field F scaled per step)."""
         s = 1.0 if self.force_scale is None else float(self.force_scale[n])
         return s * self.force
 
