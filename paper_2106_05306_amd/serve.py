@@ -27,6 +27,7 @@ import dataclasses
 import time
 from typing import Callable, Dict, List, Optional
 
+import numpy as np
 import torch
 
 from .sim import Sim, batch_advance
@@ -53,6 +54,22 @@ class Result:
     @property
     def latency(self) -> float:
         return self.finished - self.arrival
+
+
+def _start(sim: Sim, scene):
+    """The request's initial velocity and external force on a handle that may
+    come from the cache (it keeps neither from its previous request)."""
+    v0 = None if scene is None else getattr(scene, "v0", None)
+    if v0 is not None and (np.asarray(v0) != 0).any():
+        sim.set_state(None, torch.as_tensor(np.asarray(v0), dtype=torch.float64))
+    else:
+        sim.set_state(None, None)
+    f = None if scene is None else getattr(scene, "force", None)
+    if f is not None:
+        sim.set_external_force(torch.as_tensor(np.asarray(f), dtype=torch.float64),
+                               getattr(scene, "force_scale", None))
+    elif sim._keep.get("force") is not None:
+        sim.set_external_force(None)
 
 
 def centroid_seed(scene, xT: torch.Tensor) -> torch.Tensor:
@@ -147,10 +164,7 @@ class Server:
                     self.pool[req.key].append(h)          # wait for memory to free up
                     break
                 queue.popleft()
-                if scene is not None and getattr(scene, "v0", None) is not None and (scene.v0 != 0).any():
-                    h.sim.set_state(None, torch.as_tensor(scene.v0, dtype=torch.float64))
-                else:
-                    h.sim.set_state(None, None)
+                _start(h.sim, scene)
                 h.sim.job_forward(req.steps)
                 active.append([req, scene, h, "fwd", need, clock()])
             if not active:
@@ -196,10 +210,7 @@ class Server:
             scene = req.make_scene()
             h = self._acquire(req, scene)
             self._evict(h.need_bytes(req.steps, req.steps), [])
-            if scene is not None and getattr(scene, "v0", None) is not None and (scene.v0 != 0).any():
-                h.sim.set_state(None, torch.as_tensor(scene.v0, dtype=torch.float64))
-            else:
-                h.sim.set_state(None, None)
+            _start(h.sim, scene)
             xT, _, _ = h.sim.forward(req.steps)
             g = h.sim.backward(centroid_seed(scene, xT))
             torch.cuda.synchronize(self.device)

@@ -67,3 +67,29 @@ def test_budget_evicts_idle_handles():
     for r in res:
         assert r.status >= 0
     srv.close()
+
+
+def test_forces_travel_with_requests_not_with_cached_handles():
+    # same topology, alternating with and without an external force: every
+    # served result equals its solo run, so a cached handle never carries the
+    # previous request's force
+    from paper_2106_05306_amd.serve import Request, Server
+
+    def make(rid, force):
+        def f():
+            sc = scenes.request_scene(8, 10, True, seed=rid)
+            if force:
+                rng = np.random.default_rng(rid)
+                sc.force = rng.normal(0.0, 0.3 * 9.8, (sc.n_nodes, 3)) * sc.node_mass[:, None]
+                sc.force_scale = rng.uniform(0.5, 1.5, sc.steps)
+            return sc
+        return f
+    reqs = [Request(rid, (8, True), 10, 0.0, make(rid, rid % 2 == 0)) for rid in range(4)]
+    srv = Server(DEV, keep_grads=True, round_ms=0.5, max_chunk=4, **KW)
+    for run in (srv.run, srv.run_sequential, srv.run):
+        res = run(reqs)
+        for r in res:
+            solo = _solo(reqs[r.rid])
+            for key in ("dx0", "dv0", "dw_edge"):
+                assert torch.equal(r.grads[key], solo[key]), (r.rid, key)
+    srv.close()
