@@ -33,13 +33,15 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 KERNEL_SRC = os.path.join(ROOT, "paper_2106_05306_amd", "csrc", "kernels.hip")
 LAUNCH_SRC = os.path.join(ROOT, "paper_2106_05306_amd", "csrc", "capi.cpp")
+LAYOUT_SRC = os.path.join(ROOT, "paper_2106_05306_amd", "csrc", "sim_dev.h")
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "sphere_drop40_pmc.txt")
 
 
 def source_hash():
-    """Hash of the kernel source and the launch code (chunking, streams)."""
+    """Hash of the kernel source, the launch code (chunking, streams) and the
+    shared layout and launch constants."""
     h = hashlib.sha256()
-    for path in (KERNEL_SRC, LAUNCH_SRC):
+    for path in (KERNEL_SRC, LAUNCH_SRC, LAYOUT_SRC):
         with open(path, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

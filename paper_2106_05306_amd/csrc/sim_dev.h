@@ -78,7 +78,7 @@ struct AdjItem {
 constexpr int kAdjBatch = 8;        // columns per unit of work (16-byte loads per lane in flight)
 constexpr int kAdjRows = 128;       // rows per item: two per lane, read with one 16-byte load
 constexpr int kAdjWaves = kBlockAdj / 64;
-constexpr int kAdjHelpers = 4;      // prefetching workgroups of a single-handle direct adjoint launch
+constexpr int kAdjHelpers = 8;      // prefetching workgroups of a single-handle direct adjoint launch
 constexpr int kXcds = 8;            // workgroup i of a launch runs on XCD i mod 8
 struct LuUpd {              // supernode s is updated by descendant d: rows [i0, i1) of R_d lie in s
     int32_t d, i0, i1;
