@@ -126,6 +126,42 @@ def forward_bytes_per_rollout(st, m, E, C_total, K, T):
     return T * (K * per_iter + st["nnz_P"] * 12 + m * 24) + K * C_total * 48
 
 
+def batch_cpu_baseline(sims, batch, T, samples=128):
+    """The oracle (FP64, one thread) on a bounded sample of the batch: for
+    `samples` (rollout, step) pairs spread over the batch and the rollouts'
+    steps it redoes the forward step from the GPU's recorded state (K = 20,
+    contact) and its adjoint step (direct solve).  Reported as rollouts/s of
+    one core (cloth steps/s over the mean rollout length)."""
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except Exception:                                   # pragma: no cover
+        pass
+    import numpy as np
+
+    from oracle import diffcloth_oracle as O
+    rng = np.random.default_rng(0)
+    dt, done = 0.0, 0
+    for q in range(samples):
+        r = (q * 37) % len(sims)
+        n = int(rng.integers(0, T))
+        sc = batch[r]
+        model = O.Model(sc)
+        x, v = sims[r].state(n)
+        x, v = x.cpu().numpy(), v.cpu().numpy()
+        gx, gv = rng.normal(size=(2,) + x.shape)
+        t0 = time.perf_counter()
+        rec = O.forward_step(model, x, v, n)
+        O.backward_step(model, rec, gx, gv, n)
+        dt += time.perf_counter() - t0
+        done += 1
+    steps_per_s = done / dt
+    return {"value": steps_per_s / T, "unit": "rollouts/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} (rollout, step) pairs of the batch, forward (K=20, contact) + direct-solve adjoint "
+                      f"each redone from the GPU's recorded state, FP64 NumPy/SciPy, {dt:.1f} s; "
+                      f"{steps_per_s:.2f} cloth steps/s over {T}-step rollouts"}
+
+
 def bench_batch(args):
     """64 independent rollouts of uneven size (16x16 .. 64x64 grids, each with
     its own stiffness, friction and obstacle), 150 steps, forward + adjoint:
@@ -185,6 +221,7 @@ def bench_batch(args):
     sequential()
     ts = time.perf_counter() - t0
     R = len(sims)
+    cpu = None if args.no_cpu_baseline else batch_cpu_baseline(sims, batch, T)
     # forward roofline: algorithmic bytes of all rollouts / the batched forward launch
     fbytes = 0.0
     for s in sims:
@@ -206,6 +243,7 @@ def bench_batch(args):
         "roofline": {"bound": "hbm", "kernel": "k_forward (batched)", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "algorithmic_bytes_per_launch": fbytes, "launch_ms": fwd_ms},
+        "cpu_baseline": cpu,
         "adjoint_unconverged_rollouts": int(sum(1 for g in out if g["status"] == 2)),
         "gradient_nonfinite_rollouts": int(sum(1 for g in out if g["status"] == 3)),
     }
