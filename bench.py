@@ -301,6 +301,33 @@ def bench_skirt(args):
     dt = (time.perf_counter() - t0) / args.steps
     pd_iters = sim.stats()["fwd_iters_total"]
     print(f"skirt: {dt * 1e3:.0f} ms per 125-step forward+adjoint rollout", file=sys.stderr, flush=True)
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle (FP64, one thread) redoing sampled steps of the last rollout
+        # from the GPU's recorded states: forward to the same tolerance + adjoint
+        try:
+            from threadpoolctl import threadpool_limits
+            threadpool_limits(1)
+        except Exception:                               # pragma: no cover
+            pass
+        from oracle import diffcloth_oracle as O
+        model = O.Model(sc, region_scale=theta0.cpu().numpy())
+        rng = np.random.default_rng(0)
+        sample = list(range(3, sc.steps, 16))
+        tc = 0.0
+        for n in sample:
+            x, v = sim.state(n)
+            x, v = x.cpu().numpy(), v.cpu().numpy()
+            gx, gv = rng.normal(size=(2,) + x.shape)
+            t0 = time.perf_counter()
+            rec = O.forward_step(model, x, v, n, tol=args.skirt_tol, max_iters=20000)
+            O.backward_step(model, rec, gx, gv, n)
+            tc += time.perf_counter() - t0
+        cpu = {"value": len(sample) / tc, "unit": "cloth steps/s", "cores": 1, "kind": "oracle",
+               "sample": f"steps {sample[0]}..{sample[-1]} (every 16th) of the rollout, forward to "
+                         f"{args.skirt_tol:g} m/s + direct-solve adjoint, each redone from the GPU's recorded "
+                         f"state, FP64 NumPy/SciPy, {tc:.1f} s"}
+        print(f"skirt: oracle {cpu['value']:.3f} cloth steps/s on one core", file=sys.stderr, flush=True)
     # finite differences, forward converged
     T = args.fd_steps
     simc = Sim.from_scene(sc, device=dev, precision="fp64", fwd_tol=1e-10, fwd_max_iters=20000,
@@ -327,6 +354,7 @@ def bench_skirt(args):
         "config": {"workload": f"skirt 40 x 91 rings (3640 nodes), waist rotating at 4 rad/s, 125 steps, forward "
                                f"to {args.skirt_tol:g} m/s per step, checkpoint every 25, apex-angle loss, "
                                f"4 region scales", "precision": args.precision, "adj_solver": args.adj_solver},
+        "cpu_baseline": cpu,
         "apex_angle_rad": ang, "gradient": g.cpu().tolist(), "pd_iterations_per_step": pd_iters / 125.0,
         "fixed_K20": fixed_k,
         "finite_difference_check": {"steps": T, "forward": "converged to 1e-10 m/s", "eps_rel": 1e-5,
