@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_header_is_plain_c():
     # the boundary is a C ABI: the header compiles as C99 on its own, with
-    # every struct laid out as the binding's ctypes mirrors expect
+    # every struct's size and field offsets as the binding's ctypes mirrors expect
     import shutil
     import subprocess
     import tempfile
@@ -42,17 +42,26 @@ def test_header_is_plain_c():
         pytest.skip("no C compiler")
     from paper_2106_05306_amd import _binding as B
     inc = os.path.join(ROOT, "include")
-    src = "#include <stdio.h>\n#include <stddef.h>\n#include \"diffcloth.h\"\nint main(void) {\n" + "".join(
-        f'  printf("%zu\\n", sizeof({t}));\n' for t in ("sim_obstacle_t", "sim_mesh_t", "sim_params_t",
-                                                        "sim_grads_t", "sim_stats_t")) + "  return 0;\n}\n"
+    import ctypes
+    pairs = list(zip(("sim_obstacle_t", "sim_mesh_t", "sim_params_t", "sim_grads_t", "sim_stats_t"),
+                     (B.SimObstacle, B.SimMesh, B.SimParams, B.SimGrads, B.SimStats)))
+    body = ""
+    expect = []
+    for cname, py in pairs:
+        body += f'  printf("%zu\\n", sizeof({cname}));\n'
+        expect.append(ctypes.sizeof(py))
+        for fname, _ in py._fields_:             # every field at the offset the mirror uses
+            body += f'  printf("%zu\\n", offsetof({cname}, {fname}));\n'
+            expect.append(getattr(py, fname).offset)
+    src = ("#include <stdio.h>\n#include <stddef.h>\n#include \"diffcloth.h\"\nint main(void) {\n" + body +
+           "  return 0;\n}\n")
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "t.c")
         exe = os.path.join(d, "t")
         open(c, "w").write(src)
         subprocess.run([gcc, "-std=c99", "-Wall", "-Werror", "-I", inc, c, "-o", exe], check=True)
         sizes = [int(v) for v in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()]
-    import ctypes
-    assert sizes == [ctypes.sizeof(t) for t in (B.SimObstacle, B.SimMesh, B.SimParams, B.SimGrads, B.SimStats)]
+    assert sizes == expect
 
 
 def test_error_strings():
