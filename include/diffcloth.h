@@ -207,7 +207,15 @@ typedef struct {
     int32_t fwd_launches;           /* forward kernel launches of the last sim_forward (chunks
                                        overlapped with the direct adjoint's step factorisations,
                                        or checkpoint segments) */
-    int32_t pad;
+    int32_t lds_flags_fwd;          /* kernel variant of a single-handle forward launch: data kept in
+                                       LDS (1 PD iterates / solve vectors, 2 the solve's update
+                                       buffer, 4 the positions x_n; 0: everything in HBM) */
+    int32_t lds_flags_bwd;          /* the same for the adjoint kernel (1 and 2 only)             */
+    int32_t fwd_iters_max;          /* most PD iterations taken by one step of the recorded rollout */
+    int64_t mode_counts[4];         /* node-steps of the recorded rollout in each contact mode,
+                                       indexed by SIM_MODE_* (free, take-off, stick, slip)       */
+    double  fwd_ms, bwd_ms;         /* device time of the last sim_forward / sim_backward on the
+                                       handle's stream (HIP events; 0 before the first call)    */
 } sim_stats_t;
 
 typedef void *(*sim_alloc_fn)(size_t bytes, void *ctx);
@@ -293,7 +301,15 @@ int sim_state(const sim_t *sim, int32_t n, double *x_dev, double *v_dev);
 /* Contact modes (SIM_MODE_*) of recorded step n, caller node order, host array [n_nodes]. */
 int sim_modes(const sim_t *sim, int32_t n, uint8_t *modes_host);
 
+/* Counters of the last forward pass and backward pass, sizes of the handle's
+ * tables and factors (synchronises the handle's stream). */
 int sim_stats(const sim_t *sim, sim_stats_t *out);
+
+/* Per-step record of the last forward pass, 0 <= n < T (host array out[4]):
+ * PD iterations of step n and the number of its nodes in take-off, stick and
+ * slip mode (the contact set of step n is their sum; Sec. 3.2).  SIM_ESTATE
+ * without a recorded rollout, SIM_EINVAL for n out of range. */
+int sim_step_stats(const sim_t *sim, int32_t n, int32_t *out);
 
 /* Batched forward / backward of independent handles in one persistent launch
  * (one workgroup per handle; handles may differ in size and step count).  All

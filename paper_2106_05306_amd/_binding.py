@@ -58,7 +58,8 @@ class SimStats(Structure):
                 ("adj_noconv", c_int32), ("device_bytes", c_int64), ("adj_krylov_total", c_int64),
                 ("factor_bytes", c_int64), ("lds_forward", c_int64), ("lds_backward", c_int64),
                 ("adj_factor_bytes", c_int64), ("adj_pivot_perturbed", c_int64), ("fwd_launches", c_int32),
-                ("pad", c_int32)]
+                ("lds_flags_fwd", c_int32), ("lds_flags_bwd", c_int32), ("fwd_iters_max", c_int32),
+                ("mode_counts", c_int64 * 4), ("fwd_ms", c_double), ("bwd_ms", c_double)]
 
 
 ALLOC_FN = CFUNCTYPE(c_void_p, c_size_t, c_void_p)
@@ -88,6 +89,7 @@ def lib():
             "sim_state": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
             "sim_modes": (c_int32, [c_void_p, c_int32, POINTER(c_uint8)]),
             "sim_stats": (c_int32, [c_void_p, POINTER(SimStats)]),
+            "sim_step_stats": (c_int32, [c_void_p, c_int32, c_int32_p]),
             "sim_batch_forward": (c_int32, [POINTER(c_void_p), c_int32, c_int32_p, POINTER(c_void_p),
                                             POINTER(c_void_p)]),
             "sim_batch_backward": (c_int32, [POINTER(c_void_p), c_int32, POINTER(c_void_p), POINTER(SimGrads)]),

@@ -39,8 +39,13 @@ struct sim {
     sim_alloc_fn alloc = nullptr;
     sim_free_fn free_fn = nullptr;
     void *ctx = nullptr;
-    std::vector<void *> owned;          // every device allocation of the handle
-    int64_t bytes = 0;
+    std::vector<std::pair<void *, int64_t>> owned;   // every device allocation of the handle and its size
+    int64_t bytes = 0;                  // their total (what sim_stats reports)
+    SimDev *batch_desc = nullptr;       // descriptors of the batched launches this handle leads
+    int step_info_cap = 0;              // steps the per-step record (hd.step_info) can hold
+    hipEvent_t tev[4] = {nullptr, nullptr, nullptr, nullptr};   // forward start / end, backward start / end
+    bool tev_fwd = false, tev_bwd = false;                       // recorded by the last calls
+    size_t batch_desc_cap = 0;          //   (capacity in descriptors; reused across calls)
 
     SimDev hd{};                        // host copy of the descriptor
     SimDev *dd = nullptr;               // device copy (one element)
@@ -143,17 +148,34 @@ void *dev_alloc(sim *s, size_t bytes) {
         p = nullptr;
     }
     if (!p) throw std::bad_alloc();
-    s->owned.push_back(p);
+    s->owned.emplace_back(p, (int64_t)bytes);
     s->bytes += (int64_t)bytes;
     return p;
 }
 
 void dev_release(sim *s, void *p) {
     if (!p) return;
-    auto it = std::find(s->owned.begin(), s->owned.end(), p);
-    if (it != s->owned.end()) s->owned.erase(it);
+    auto it = std::find_if(s->owned.begin(), s->owned.end(), [p](const auto &e) { return e.first == p; });
+    if (it != s->owned.end()) {
+        s->bytes -= it->second;
+        s->owned.erase(it);
+    }
     if (s->free_fn) s->free_fn(p, s->ctx);
     else (void)hipFree(p);
+}
+
+// Device room for n descriptors of a batched launch led by handle s, kept
+// between calls (grown when a batch is larger than any before it).
+SimDev *batch_descs(sim *s, size_t n) {
+    if (n > s->batch_desc_cap) {
+        const size_t cap = std::max<size_t>(n, 2 * s->batch_desc_cap);
+        dev_release(s, s->batch_desc);
+        s->batch_desc = nullptr;
+        s->batch_desc_cap = 0;
+        s->batch_desc = (SimDev *)dev_alloc(s, cap * sizeof(SimDev));
+        s->batch_desc_cap = cap;
+    }
+    return s->batch_desc;
 }
 
 template <class T>
@@ -253,13 +275,24 @@ size_t lds_bytes(const sim *s, int flags, bool fwd) {
     return b * sizeof(double);
 }
 
-// Greedy placement: add each kind of data to LDS while it still fits.
+// Kinds of data the LDS placement may use: DIFFCLOTH_LDS (a mask of kLdsVectors
+// = 1, kLdsUpdates = 2, kLdsPositions = 4) restricts the greedy choice below,
+// so that tests can run every kernel variant on a small mesh; unset: all.
+int lds_allowed() {
+    const char *e = std::getenv("DIFFCLOTH_LDS");
+    if (!e || !*e) return 7;
+    const int v = std::atoi(e);
+    return v >= 0 && v <= 7 ? v : 7;
+}
+
+// Greedy placement: add each allowed kind of data to LDS while it still fits.
 void plan_lds(sim *s, int &flags, size_t &bytes, bool fwd) {
     const size_t avail = s->max_lds > (fwd ? s->static_fwd : s->static_bwd)
                              ? s->max_lds - (fwd ? s->static_fwd : s->static_bwd) : 0;
+    const int allowed = lds_allowed();
     flags = 0;
     for (int bit : {kLdsVectors, kLdsUpdates, kLdsPositions}) {
-        if (!fwd && bit == kLdsPositions) continue;
+        if ((!fwd && bit == kLdsPositions) || !(allowed & bit)) continue;
         if (lds_bytes(s, flags | bit, fwd) <= avail) flags |= bit;
     }
     bytes = lds_bytes(s, flags, fwd);
@@ -933,8 +966,9 @@ size_t batch_lds(sim *const *sims, int n, bool fwd, int &flags) {
     };
     flags = 0;
     size_t bytes = 0, mx = 0;
+    const int allowed = lds_allowed();
     for (int bit : {kLdsVectors, kLdsUpdates, kLdsPositions}) {
-        if (!fwd && bit == kLdsPositions) continue;
+        if ((!fwd && bit == kLdsPositions) || !(allowed & bit)) continue;
         if (fits(flags | bit, mx)) {
             flags |= bit;
             bytes = mx;
@@ -1024,6 +1058,15 @@ int run_forward_range(sim *s, int a, int b) {
                                   has_mesh(&s, 1), s->stream));
 }
 
+// Timing event k of the handle's stream (0/1 forward start/end, 2/3 backward).
+int time_mark(sim *s, int k) {
+    if (!s->tev[k]) {
+        const int rc = hip_err(hipEventCreate(&s->tev[k]));
+        if (rc) return rc;
+    }
+    return hip_err(hipEventRecord(s->tev[k], s->stream));
+}
+
 int read_counters(sim *s) {
     int rc = hip_err(hipMemcpyAsync(s->counters_host, s->hd.counters, sizeof(s->counters_host), hipMemcpyDeviceToHost,
                                     s->stream));
@@ -1056,8 +1099,9 @@ int sim_create(const sim_mesh_t *mesh, const sim_params_t *params, void *hip_str
     s->alloc = alloc;
     s->free_fn = free_fn;
     s->ctx = alloc_ctx;
-    int rc = s->hm.build(mesh, params);
-    if (rc == SIM_OK) rc = s->hm.order_and_factor(leaf_size_default(), merge_cap_default());
+    // the host build allocates (std::map, std::vector): no exception may leave the ABI
+    int rc = guarded([&] { return s->hm.build(mesh, params); });
+    if (rc == SIM_OK) rc = guarded([&] { return s->hm.order_and_factor(leaf_size_default(), merge_cap_default()); });
     if (rc == SIM_OK) {
         rc = guarded([&] {
             build_device(s);
@@ -1231,6 +1275,13 @@ int prepare_forward(sim *s, int n_steps) {
     const int k = seg_len(s);
     const int cap = k > 0 ? std::min(k, n_steps) : n_steps;
     ensure_records(s, std::max(cap, 1));
+    if (s->step_info_cap < n_steps) {
+        dev_release(s, s->hd.step_info);
+        s->hd.step_info = nullptr;
+        s->step_info_cap = 0;
+        s->hd.step_info = (int32_t *)dev_alloc(s, 4 * (size_t)n_steps * sizeof(int32_t));
+        s->step_info_cap = n_steps;
+    }
     const size_t v3b = 3 * (size_t)s->hd.m * sizeof(double);
     if (k > 0) {
         const int nseg = (n_steps + k - 1) / k;
@@ -1581,8 +1632,11 @@ int sim_forward(sim_t *s, int32_t n_steps, double *x_traj_dev, double *xT_dev, d
     if (!s || n_steps < 1) return SIM_EINVAL;
     return guarded([&] {
         int rc = prepare_forward(s, n_steps);
+        if (!rc) rc = time_mark(s, 0);
         if (!rc) rc = forward_all(s, n_steps, x_traj_dev);
+        if (!rc) rc = time_mark(s, 1);
         if (!rc) rc = finish_forward(s, n_steps, xT_dev, vT_dev);
+        s->tev_fwd = rc == SIM_OK;
         return rc;
     });
 }
@@ -1593,9 +1647,12 @@ int sim_backward(sim_t *s, const double *dL_dxT_dev, const double *dL_dvT_dev, c
     if (s->T < 1) return SIM_ESTATE;
     return guarded([&] {
         int rc = prepare_backward(s, dL_dxT_dev, dL_dvT_dev, dL_dx_steps_dev);
+        if (!rc) rc = time_mark(s, 2);
         if (!rc) rc = backward_all(s);
+        if (!rc) rc = time_mark(s, 3);
         if (!rc) rc = write_grads(s, out);
         if (!rc) rc = backward_status(s);
+        s->tev_bwd = rc >= 0;
         return rc;
     });
 }
@@ -1705,7 +1762,49 @@ int sim_stats(const sim_t *cs, sim_stats_t *out) {
     out->adj_factor_bytes = s->hd.af_size * (int64_t)sizeof(double);
     out->adj_pivot_perturbed = s->counters_host[5];
     out->fwd_launches = s->fwd_launches;
+    out->lds_flags_fwd = s->flags_fwd;
+    out->lds_flags_bwd = s->flags_bwd;
+    if (s->tev_fwd) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(s->tev[1]) == hipSuccess && hipEventElapsedTime(&ms, s->tev[0], s->tev[1]) == hipSuccess)
+            out->fwd_ms = ms;
+    }
+    if (s->tev_bwd) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(s->tev[3]) == hipSuccess && hipEventElapsedTime(&ms, s->tev[2], s->tev[3]) == hipSuccess)
+            out->bwd_ms = ms;
+    }
+    if (s->T > 0 && s->hd.step_info) {
+        return guarded([&] {
+            std::vector<int32_t> info(4 * (size_t)s->T);
+            int rc = hip_err(hipMemcpyAsync(info.data(), s->hd.step_info, info.size() * sizeof(int32_t),
+                                            hipMemcpyDeviceToHost, s->stream));
+            if (!rc) rc = hip_err(hipStreamSynchronize(s->stream));
+            if (rc) return rc;
+            int64_t contact = 0;
+            for (int n = 0; n < s->T; ++n) {
+                out->fwd_iters_max = std::max(out->fwd_iters_max, info[4 * n]);
+                for (int q = 1; q < 4; ++q) {
+                    out->mode_counts[q] += info[4 * n + q];
+                    contact += info[4 * n + q];
+                }
+            }
+            out->mode_counts[SIM_MODE_FREE] = (int64_t)s->T * s->hm.m - contact;
+            return SIM_OK;
+        });
+    }
     return SIM_OK;
+}
+
+int sim_step_stats(const sim_t *cs, int32_t n, int32_t *out) {
+    if (!cs || !out) return SIM_EINVAL;
+    const sim *s = cs;
+    if (s->T < 1 || !s->hd.step_info) return SIM_ESTATE;
+    if (n < 0 || n >= s->T) return SIM_EINVAL;
+    int rc = hip_err(hipMemcpyAsync(out, s->hd.step_info + 4 * (size_t)n, 4 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                    s->stream));
+    if (!rc) rc = hip_err(hipStreamSynchronize(s->stream));
+    return rc;
 }
 
 int sim_batch_forward(sim_t *const *sims, int32_t n, const int32_t *n_steps, double *const *xT_dev,
@@ -1730,7 +1829,7 @@ int sim_batch_forward(sim_t *const *sims, int32_t n, const int32_t *n_steps, dou
             if (!rc) rc = push_desc(sims[i]);
         }
         if (rc) return rc;
-        SimDev *d = (SimDev *)dev_alloc(s0, n * sizeof(SimDev));
+        SimDev *d = batch_descs(s0, n);
         rc = hip_err(hipMemcpyAsync(d, descs.data(), n * sizeof(SimDev), hipMemcpyHostToDevice, s0->stream));
         int fl = 0;
         const size_t lb = batch_lds(sims, n, true, fl);
@@ -1739,7 +1838,6 @@ int sim_batch_forward(sim_t *const *sims, int32_t n, const int32_t *n_steps, dou
         for (int i = 0; i < n && !rc; ++i)
             rc = finish_forward(sims[i], n_steps[i], xT_dev ? xT_dev[i] : nullptr, vT_dev ? vT_dev[i] : nullptr);
         (void)hipStreamSynchronize(s0->stream);
-        dev_release(s0, d);
         return rc;
     });
 }
@@ -1773,7 +1871,7 @@ int sim_batch_backward(sim_t *const *sims, int32_t n, const double *const *dL_dx
             if (!rc) rc = push_desc(sims[i]);
         }
         if (rc) return rc;
-        SimDev *d = (SimDev *)dev_alloc(s0, n * sizeof(SimDev));
+        SimDev *d = batch_descs(s0, n);
         rc = hip_err(hipMemcpyAsync(d, descs.data(), n * sizeof(SimDev), hipMemcpyHostToDevice, s0->stream));
         if (!rc && !work.empty()) rc = factor_pairs(s0, d, std::vector<sim *>(sims, sims + n), work, s0->stream);
         int fl = 0;
@@ -1790,7 +1888,6 @@ int sim_batch_backward(sim_t *const *sims, int32_t n, const double *const *dL_dx
             }
         }
         (void)hipStreamSynchronize(s0->stream);
-        dev_release(s0, d);
         return rc ? rc : warn;
     });
 }
@@ -1804,10 +1901,13 @@ int sim_trim(sim_t *s) {
     if (rc) return rc;
     for (void **p : {(void **)&s->hd.rec_x, (void **)&s->hd.rec_v, (void **)&s->hd.rec_ubar, (void **)&s->hd.rec_mode,
                      (void **)&s->hd.rec_obst, (void **)&s->ckpt, (void **)&s->gsteps, (void **)&s->hd.af,
-                     (void **)&s->hd.af_ws, (void **)&s->d_work}) {
+                     (void **)&s->hd.af_ws, (void **)&s->d_work, (void **)&s->batch_desc,
+                     (void **)&s->hd.step_info}) {
         dev_release(s, *p);
         *p = nullptr;
     }
+    s->batch_desc_cap = 0;
+    s->step_info_cap = 0;
     s->hd.rec_cap = 0;
     s->ckpt_cap = 0;
     s->gsteps_cap = 0;
@@ -1886,8 +1986,9 @@ int sim_batch_advance(sim_t *const *sims, int32_t n, const int32_t *steps, void 
                 db.push_back(h->hd);
             }
         }
-        SimDev *dfd = fw.empty() ? nullptr : (SimDev *)dev_alloc(sims[0], fw.size() * sizeof(SimDev));
-        SimDev *dbd = bw.empty() ? nullptr : (SimDev *)dev_alloc(sims[0], bw.size() * sizeof(SimDev));
+        SimDev *room = batch_descs(sims[0], fw.size() + bw.size());
+        SimDev *dfd = fw.empty() ? nullptr : room;
+        SimDev *dbd = bw.empty() ? nullptr : room + fw.size();
         if (dfd) rc = hip_err(hipMemcpyAsync(dfd, df.data(), df.size() * sizeof(SimDev), hipMemcpyHostToDevice, sf));
         if (!rc && dbd) rc = hip_err(hipMemcpyAsync(dbd, db.data(), db.size() * sizeof(SimDev), hipMemcpyHostToDevice, sf));
         if (!rc) rc = hip_err(hipStreamSynchronize(sf));          // descriptors in place before either stream uses them
@@ -1908,8 +2009,6 @@ int sim_batch_advance(sim_t *const *sims, int32_t n, const int32_t *steps, void 
         const int r1 = hip_err(hipStreamSynchronize(sf));
         const int r2 = hip_err(hipStreamSynchronize(sb));
         if (!rc) rc = r1 ? r1 : r2;
-        dev_release(sims[0], dfd);
-        dev_release(sims[0], dbd);
         if (rc) return rc;
         for (sim *h : fw) {
             h->cursor = h->hd.step_end;
@@ -1952,11 +2051,13 @@ void sim_destroy(sim_t *s) {
         (void)hipEventDestroy(s->fac_done);
         (void)hipStreamDestroy(s->fac_stream);
     }
-    for (void *p : s->owned) {
+    for (auto [p, nb] : s->owned) {
         if (s->free_fn) s->free_fn(p, s->ctx);
         else (void)hipFree(p);
     }
     s->owned.clear();
+    for (hipEvent_t &e : s->tev)
+        if (e) (void)hipEventDestroy(e);
     delete s;
 }
 
@@ -1978,6 +2079,7 @@ const char *sim_strerror(int code) {
 
 int sim_analyze(const sim_mesh_t *mesh, const sim_params_t *params, int32_t leaf_size, sim_stats_t *stats,
                 int32_t *perm_out, double *dense_L_out, int32_t max_dense) {
+    return guarded([&]() -> int {
     HostModel hm;
     int rc = hm.build(mesh, params);
     if (rc) return rc;
@@ -2000,6 +2102,7 @@ int sim_analyze(const sim_mesh_t *mesh, const sim_params_t *params, int32_t leaf
     if (perm_out) std::memcpy(perm_out, hm.perm.data(), hm.m * sizeof(int32_t));
     if (dense_L_out && hm.m <= max_dense) hm.dense_L(dense_L_out);
     return SIM_OK;
+    });
 }
 
 }  // extern "C"

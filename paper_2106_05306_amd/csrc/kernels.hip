@@ -256,8 +256,9 @@ __device__ __forceinline__ void solve_P(const SimDev &S, auto b, auto T, auto Y,
 // ------------------------------------------------------------------ geometry
 
 // Closest point of triangle T (a, b, c, unit face normal, bounding-ball
-// centre and radius: 16 doubles) to x
-// by Voronoi regions; returns the distance (plane distance on the face) and
+// centre and radius: 16 doubles) to x by Voronoi regions, following the
+// published closest-point-on-triangle test of C. Ericson, Real-Time Collision
+// Detection (2005), Sec. 5.1.5 (same region order and barycentric terms); returns the distance (plane distance on the face) and
 // the region (0 face, 1 vertex, 2 edge).  WANT: also the closest point q, the
 // edge vector ed (unnormalised) and the face distance fd.
 template <bool WANT>
@@ -789,6 +790,7 @@ __global__ __launch_bounds__(kBlock) void k_forward(const SimDev *__restrict__ s
         auto xn = xrec + 3 * m;
         auto vn = vrec + 3 * m;
         auto ubrec = G(S.rec_ubar) + (int64_t)slot * 3 * m;
+        int cnt[3] = {0, 0, 0};                          // take-off, stick, slip nodes of this thread
         for (int i = threadIdx.x; i < m; i += (int)blockDim.x) {
             for (int d = 0; d < 3; ++d) {
                 const double vv = A[3 * i + d];
@@ -799,8 +801,21 @@ __global__ __launch_bounds__(kBlock) void k_forward(const SimDev *__restrict__ s
                 vn[3 * i + d] = vv;
                 ubrec[3 * i + d] = G(S.ubar)[3 * i + d];
             }
-            G(S.rec_mode)[(int64_t)slot * m + i] = G(S.mode)[i];
+            const uint8_t md = G(S.mode)[i];
+            if (md != FREE) ++cnt[md - 1];
+            G(S.rec_mode)[(int64_t)slot * m + i] = md;
             G(S.rec_obst)[(int64_t)slot * m + i] = G(S.cobst)[i];
+        }
+        // per-step record: iterations and mode counts (sums of small integers, exact in float64)
+        const double packed = (double)cnt[0] + 1048576.0 * (double)cnt[1];   // counts < 2^20 per handle
+        const double tot01 = block_sum(packed, red);
+        const double tot2 = block_sum((double)cnt[2], red);
+        if (threadIdx.x == 0 && S.step_info != nullptr) {
+            const int64_t t01 = (int64_t)tot01;
+            G(S.step_info)[4 * n] = k;
+            G(S.step_info)[4 * n + 1] = (int32_t)(t01 & 1048575);
+            G(S.step_info)[4 * n + 2] = (int32_t)(t01 >> 20);
+            G(S.step_info)[4 * n + 3] = (int32_t)tot2;
         }
         __syncthreads();
     }

@@ -187,6 +187,8 @@ struct SimDev {
     uint8_t *rec_mode;                // [cap * m]
     int8_t *rec_obst;                 // [cap * m]
     int rec_cap;
+    int32_t *step_info;               // [4 per step n of the rollout]: PD iterations, take-off, stick,
+                                      //   slip node counts (indexed by n, not by record slot); may be null
 
     // adjoint buffers
     double *gx, *gv;                  // dL/dx_{n+1}, dL/dv_{n+1} -> dL/dx_n, dL/dv_n

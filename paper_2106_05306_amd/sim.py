@@ -326,7 +326,15 @@ class Sim:
     def stats(self) -> dict:
         st = B.SimStats()
         B.check(B.lib().sim_stats(self.h, ctypes.byref(st)), "sim_stats")
-        return {name: getattr(st, name) for name, _ in B.SimStats._fields_}
+        d = {name: getattr(st, name) for name, _ in B.SimStats._fields_}
+        d["mode_counts"] = list(d["mode_counts"])
+        return d
+
+    def step_stats(self, n: int) -> dict:
+        """PD iterations and contact-mode counts of recorded step n."""
+        out = (ctypes.c_int32 * 4)()
+        B.check(B.lib().sim_step_stats(self.h, int(n), out), "sim_step_stats")
+        return dict(pd_iters=out[0], takeoff=out[1], stick=out[2], slip=out[3])
 
     def close(self):
         if getattr(self, "h", None):

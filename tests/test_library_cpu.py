@@ -25,7 +25,7 @@ def test_library_exports_every_declared_symbol():
     for fn in os.listdir(os.path.join(ROOT, "include")):
         if fn.endswith(".h"):
             txt = open(os.path.join(ROOT, "include", fn)).read()
-            names |= set(re.findall(r"^\s*(?:int|void|const char)\s*\*?\s*(sim_\w+)\s*\(", txt, re.M))
+            names |= set(re.findall(r"^\s*(?:int64_t|int|void|const char)\s*\*?\s*(sim_\w+)\s*\(", txt, re.M))
     assert {"sim_create", "sim_forward", "sim_backward", "sim_destroy"} <= names
     for n in sorted(names):
         assert hasattr(L, n), n
@@ -66,8 +66,8 @@ def test_header_is_plain_c():
 
 def test_error_strings():
     B, L = _lib()
-    for code in (0, -1, -2, -3, -4, -5, -6, 1, 2):
-        assert L.sim_strerror(code)
+    for code in (0, -1, -2, -3, -4, -5, -6, 1, 2, 3):
+        assert L.sim_strerror(code) != b"unknown code", code
 
 
 @pytest.mark.parametrize("make", [lambda: scenes.c1_napkin(0), lambda: scenes.tiny_scene(5, pins=True, seed=3),
