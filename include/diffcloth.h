@@ -49,6 +49,8 @@ extern "C" {
 #define SIM_ENONFINITE      -4   /* NaN / Inf in inputs or state                        */
 #define SIM_ESTATE          -5   /* call out of order (backward before forward, ...)    */
 #define SIM_EHIP            -6   /* a HIP runtime call failed                           */
+#define SIM_ESCRATCH        -7   /* the mesh needs more device scratch than
+                                    sim_forward_noalloc has (16 MiB)                   */
 #define SIM_WADJ_FALLBACK    1   /* >= 1 adjoint step needed the fallback solver        */
 #define SIM_WADJ_NOCONV      2   /* >= 1 adjoint step did not reach its tolerance       */
 #define SIM_WADJ_NONFINITE   3   /* the state gradients overflowed (not finite)         */
@@ -354,6 +356,29 @@ int sim_job_forward(sim_t *sim, int32_t n_steps);
 int sim_job_backward(sim_t *sim, const double *dL_dxT_dev, const double *dL_dvT_dev);
 int sim_batch_advance(sim_t *const *sims, int32_t n, const int32_t *steps, void *backward_stream, int32_t *left);
 int sim_job_grads(sim_t *sim, const sim_grads_t *out);
+
+/* Allocation-free variant of sim_forward, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  It runs n_steps from the handle's initial state
+ * (sim_set_state) exactly as sim_forward does -- the same kernels, bitwise the
+ * same x_T and v_T -- and writes x_T, v_T (device [n_nodes*3], caller order,
+ * both required).  It records nothing for a backward pass and leaves the
+ * handle's recorded rollout, if any, as it was.  Its per-step work memory (PD
+ * iterates, right-hand side, the solve's update buffer, impulses, contact
+ * modes and frames, the running state) lives in one 16 MiB device array per
+ * GPU that the library holds until the process ends; no call of this function
+ * allocates, frees, synchronises or issues a memset (it only enqueues copies
+ * and kernels on the handle's stream and returns).  Every call on one GPU uses
+ * that GPU's array: calls that overlap on one GPU (other streams, other
+ * threads) race and their results are undefined.  Returns SIM_ESCRATCH when
+ * the mesh needs more than the array holds (sim_noalloc_scratch_bytes tells
+ * the need; about 400 bytes per node plus the solve's update buffer),
+ * SIM_EINVAL on bad arguments or when external-force multipliers run out,
+ * SIM_EHIP on a HIP error. */
+int sim_forward_noalloc(sim_t *sim, int32_t n_steps, double *xT_dev, double *vT_dev);
+
+/* Device scratch bytes sim_forward_noalloc needs for this handle (-1: NULL). */
+int64_t sim_noalloc_scratch_bytes(const sim_t *sim);
 
 /* Host-only analysis (no GPU needed): builds the constraint set, the PD
  * matrix, the ordering and the Cholesky factor exactly as sim_create does and

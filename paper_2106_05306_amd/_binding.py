@@ -13,6 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("DIFFCLOTH_LIB", os.path.join(HERE, "libdiffcloth.so"))
 
 SIM_OK, SIM_EINVAL, SIM_ENOTSPD, SIM_ENOMEM, SIM_ENONFINITE, SIM_ESTATE, SIM_EHIP = 0, -1, -2, -3, -4, -5, -6
+SIM_ESCRATCH = -7
 SIM_WADJ_FALLBACK, SIM_WADJ_NOCONV, SIM_WADJ_NONFINITE = 1, 2, 3
 SIM_PLANE, SIM_SPHERE, SIM_MESH = 0, 1, 2
 SIM_FP64, SIM_MIXED = 0, 1
@@ -83,6 +84,8 @@ def lib():
             "sim_set_material": (c_int32, [c_void_p, c_double_p, c_double_p, c_double_p, c_double_p]),
             "sim_set_external_force": (c_int32, [c_void_p, c_void_p, c_int32, c_double_p]),
             "sim_forward": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
+            "sim_forward_noalloc": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
+            "sim_noalloc_scratch_bytes": (c_int64, [c_void_p]),
             "sim_backward": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, POINTER(SimGrads)]),
             "sim_adjoint_step": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
                                            POINTER(SimGrads)]),

@@ -29,6 +29,7 @@ hipError_t launch_scatter_bend(const double *dw, const int32_t *centers, int n_e
 hipError_t launch_fill(double *p, double v, int64_t n, hipStream_t st);
 hipError_t launch_adj_assemble(const SimDev *d_sims, const int32_t *work, int nblocks, hipStream_t st);
 hipError_t launch_adj_factor_level(const SimDev *d_sims, const int32_t *work, int nblocks, int nmax, hipStream_t st);
+hipError_t noalloc_scratch(void **out);
 }  // namespace dc
 
 using namespace dc;
@@ -42,6 +43,8 @@ struct sim {
     std::vector<std::pair<void *, int64_t>> owned;   // every device allocation of the handle and its size
     int64_t bytes = 0;                  // their total (what sim_stats reports)
     SimDev *batch_desc = nullptr;       // descriptors of the batched launches this handle leads
+    SimDev hd_noalloc{};                // descriptor of the allocation-free forward (copied to the
+                                        //   device scratch on every call; lives as long as the handle)
     int step_info_cap = 0;              // steps the per-step record (hd.step_info) can hold
     hipEvent_t tev[4] = {nullptr, nullptr, nullptr, nullptr};   // forward start / end, backward start / end
     bool tev_fwd = false, tev_bwd = false;                       // recorded by the last calls
@@ -1107,6 +1110,10 @@ int sim_create(const sim_mesh_t *mesh, const sim_params_t *params, void *hip_str
             build_device(s);
             int r = push_desc(s);
             if (r) return r;
+            // device address of the allocation-free forward's scratch, taken once
+            // per device at set-up (a failure surfaces when that entry point is called)
+            void *scratch_addr = nullptr;
+            (void)noalloc_scratch(&scratch_addr);
             r = sim_set_state(s, nullptr, nullptr);
             if (r) return r;
             return hip_err(hipStreamSynchronize(s->stream));
@@ -1807,6 +1814,106 @@ int sim_step_stats(const sim_t *cs, int32_t n, int32_t *out) {
     return rc;
 }
 
+// Scratch layout of the allocation-free forward (byte offsets, 256-aligned).
+struct NoallocLayout {
+    size_t desc, ctr, red, x, v, vk, vk1, rhs, b0, f, ubar, cfr, wp, ubuf, rx, rv, rub, mode, cobst, rmode, robst;
+    size_t total;
+};
+
+NoallocLayout noalloc_layout(const sim *s) {
+    const size_t m = (size_t)s->hd.m, d = sizeof(double);
+    NoallocLayout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o += (std::max<size_t>(bytes, 8) + 255) & ~size_t(255);
+        return at;
+    };
+    L.desc = take(sizeof(SimDev));
+    L.ctr = take(16 * sizeof(int64_t));          // counters [0, 8), forward position at 8
+    L.red = take(64 * d);
+    L.x = take(3 * m * d);
+    L.v = take(3 * m * d);
+    L.vk = take(3 * m * d);
+    L.vk1 = take(3 * m * d);
+    L.rhs = take(3 * m * d);
+    L.b0 = take(3 * m * d);
+    L.f = take(3 * m * d);
+    L.ubar = take(3 * m * d);
+    L.cfr = take(8 * m * d);
+    L.wp = take(3 * (size_t)std::max(s->nca, 1) * d);
+    L.ubuf = take((size_t)std::max(s->hd.n_ubuf, 1) * d);
+    L.rx = take(2 * 3 * m * d);
+    L.rv = take(2 * 3 * m * d);
+    L.rub = take(3 * m * d);
+    L.mode = take(m);
+    L.cobst = take(m);
+    L.rmode = take(m);
+    L.robst = take(m);
+    L.total = o;
+    return L;
+}
+
+int sim_forward_noalloc(sim_t *s, int32_t n_steps, double *xT_dev, double *vT_dev) {
+    if (!s || n_steps < 1 || !xT_dev || !vT_dev) return SIM_EINVAL;
+    if (s->hd.fscale && n_steps > s->n_fscale) return SIM_EINVAL;    // multipliers run out
+    const NoallocLayout L = noalloc_layout(s);
+    if (L.total > kNoallocScratchBytes) return SIM_ESCRATCH;
+    void *base = nullptr;
+    int rc = hip_err(noalloc_scratch(&base));
+    if (rc) return rc;
+    char *b = (char *)base;
+    const int m = s->hd.m;
+    const size_t v3b = 3 * (size_t)m * sizeof(double);
+    SimDev &d = s->hd_noalloc;
+    d = s->hd;                                   // the handle's tables; its work memory replaced below
+    d.counters = (int64_t *)(b + L.ctr);
+    d.fwd_pos = (int64_t *)(b + L.ctr) + 8;
+    d.red = (double *)(b + L.red);
+    d.x = (double *)(b + L.x);
+    d.v = (double *)(b + L.v);
+    d.vk = (double *)(b + L.vk);
+    d.vk1 = (double *)(b + L.vk1);
+    d.rhs = (double *)(b + L.rhs);
+    d.b0 = (double *)(b + L.b0);
+    d.f = (double *)(b + L.f);
+    d.ubar = (double *)(b + L.ubar);
+    d.cfr = (double *)(b + L.cfr);
+    d.wp = (double *)(b + L.wp);
+    d.ubuf = (double *)(b + L.ubuf);
+    d.rec_x = (double *)(b + L.rx);
+    d.rec_v = (double *)(b + L.rv);
+    d.rec_ubar = (double *)(b + L.rub);
+    d.mode = (uint8_t *)(b + L.mode);
+    d.cobst = (int8_t *)(b + L.cobst);
+    d.rec_mode = (uint8_t *)(b + L.rmode);
+    d.rec_obst = (int8_t *)(b + L.robst);
+    d.rec_cap = 1;
+    d.rec_ring = 1;
+    d.step_info = nullptr;
+    d.step_begin = 0;
+    d.step_end = n_steps;
+    d.rec_step0 = 0;
+    d.fwd_epoch = 0;
+    SimDev *dd = (SimDev *)(b + L.desc);
+    // everything below is enqueued on the handle's stream; nothing allocates,
+    // synchronises or clears memory with a memset (the call may be captured)
+    rc = hip_err(hipMemcpyAsync(dd, &d, sizeof(SimDev), hipMemcpyHostToDevice, s->stream));
+    if (!rc) rc = hip_err(launch_fill((double *)(b + L.ctr), 0.0, 16, s->stream));
+    if (!rc) rc = hip_err(launch_fill(d.ubar, 0.0, 3 * (int64_t)m, s->stream));
+    if (!rc) rc = copy_d2d(s, d.x, s->start_x, v3b);
+    if (!rc) rc = copy_d2d(s, d.v, s->start_v, v3b);
+    if (!rc) rc = hip_err(launch_forward(dd, 1, s->hd.mixed != 0, s->lds_fwd, s->flags_fwd, 0, has_mesh(&s, 1),
+                                         s->stream));
+    if (!rc) rc = hip_err(launch_permute3(d.x, xT_dev, s->d_perm, m, true, s->stream));
+    if (!rc) rc = hip_err(launch_permute3(d.v, vT_dev, s->d_perm, m, true, s->stream));
+    return rc;
+}
+
+int64_t sim_noalloc_scratch_bytes(const sim_t *s) {
+    return s ? (int64_t)noalloc_layout(s).total : -1;
+}
+
 int sim_batch_forward(sim_t *const *sims, int32_t n, const int32_t *n_steps, double *const *xT_dev,
                       double *const *vT_dev) {
     if (!sims || n < 1 || !n_steps) return SIM_EINVAL;
@@ -2065,6 +2172,7 @@ const char *sim_strerror(int code) {
     switch (code) {
         case SIM_OK: return "ok";
         case SIM_EINVAL: return "invalid mesh or parameters";
+        case SIM_ESCRATCH: return "the mesh needs more than the 16 MiB of device scratch of sim_forward_noalloc";
         case SIM_ENOTSPD: return "PD matrix is not positive definite";
         case SIM_ENOMEM: return "out of memory";
         case SIM_ENONFINITE: return "non-finite input or state";

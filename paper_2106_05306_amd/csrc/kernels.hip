@@ -12,6 +12,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include "sim_dev.h"
 
@@ -672,7 +673,7 @@ __global__ __launch_bounds__(kBlock) void k_forward(const SimDev *__restrict__ s
     auto Vprev = G(S.vk1);
     int64_t iters_total = 0, it_run = 0;
     for (int n = S.step_begin; n < S.step_end; ++n) {
-        const int slot = n - S.rec_step0;
+        const int slot = S.rec_ring ? 0 : n - S.rec_step0;
         const double t1 = (n + 1) * h;
         auto xrec = G(S.rec_x) + (int64_t)slot * 3 * m;
         auto vrec = G(S.rec_v) + (int64_t)slot * 3 * m;
@@ -2185,6 +2186,32 @@ hipError_t launch_fill(double *p, double v, int64_t n, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, v, n);
     return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ allocation-free forward
+// Work memory of sim_forward_noalloc: a file-scope device array, one per GPU
+// (each device that loads the library holds its own copy until the process
+// ends).  Host code never uses the array's name as an address: its device
+// address is taken once per device with hipGetSymbolAddress and kept.  Every
+// call on one GPU shares that GPU's array, so such calls must not overlap.
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+hipError_t noalloc_scratch(void **out) {
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return hipSuccess;
 }
 
 }  // namespace dc

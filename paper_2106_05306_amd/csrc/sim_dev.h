@@ -4,6 +4,7 @@
 // the duration of a launch, so work buffers are private to it.
 #pragma once
 
+#include <cstddef>
 #include <cstdint>
 
 namespace dc {
@@ -80,6 +81,8 @@ constexpr int kAdjRows = 128;       // rows per item: two per lane, read with on
 constexpr int kAdjWaves = kBlockAdj / 64;
 constexpr int kAdjHelpers = 8;      // prefetching workgroups of a single-handle direct adjoint launch
 constexpr int kXcds = 8;            // workgroup i of a launch runs on XCD i mod 8
+constexpr size_t kNoallocScratchBytes = size_t(16) << 20;   // device scratch of the allocation-free forward
+constexpr int kMaxDevices = 64;
 struct LuUpd {              // supernode s is updated by descendant d: rows [i0, i1) of R_d lie in s
     int32_t d, i0, i1;
     int32_t map;            // offset in lu_relmap of the panel rows (in s) of R_d[i0..r_d)
@@ -189,6 +192,8 @@ struct SimDev {
     int rec_cap;
     int32_t *step_info;               // [4 per step n of the rollout]: PD iterations, take-off, stick,
                                       //   slip node counts (indexed by n, not by record slot); may be null
+    int rec_ring;                     // 1: every step records into slots 0 (x_n) and 1 (x_{n+1}) --
+                                      //   the allocation-free forward keeps no rollout
 
     // adjoint buffers
     double *gx, *gv;                  // dL/dx_{n+1}, dL/dv_{n+1} -> dL/dx_n, dL/dv_n

@@ -247,6 +247,17 @@ class Sim:
         self._gen += 1
         return xT, vT, traj
 
+    def forward_noalloc(self, n_steps: int, xT: torch.Tensor, vT: torch.Tensor):
+        """sim_forward_noalloc: x_T, v_T into the caller's (n, 3) float64 tensors;
+        the library allocates nothing and records no rollout."""
+        for t in (xT, vT):
+            if t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != 3 * self.m or t.device != self.device:
+                raise ValueError("x_T / v_T must be contiguous float64 device tensors of n_nodes x 3")
+        B.check(B.lib().sim_forward_noalloc(self.h, int(n_steps), _dptr(xT), _dptr(vT)), "sim_forward_noalloc")
+
+    def noalloc_scratch_bytes(self) -> int:
+        return int(B.lib().sim_noalloc_scratch_bytes(self.h))
+
     def _grads(self):
         g = dict(dx0=self._vec(), dv0=self._vec(),
                  dw_edge=torch.zeros(max(self.n_edges, 1), dtype=torch.float64, device=self.device),

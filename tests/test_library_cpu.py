@@ -66,7 +66,7 @@ def test_header_is_plain_c():
 
 def test_error_strings():
     B, L = _lib()
-    for code in (0, -1, -2, -3, -4, -5, -6, 1, 2, 3):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, 1, 2, 3):
         assert L.sim_strerror(code) != b"unknown code", code
 
 
