@@ -28,7 +28,8 @@ Readings of the paper taken here (the paper is silent or ambiguous on them):
     p = rho0 l(x)/|l(x)|, rho0 = |l(X)|, p = 0 when rho0 = 0; attachments
     p = target(t).
   * Degenerate |q| < 1e-12 rho: use the rest direction and a zero projection Jacobian.
-  * Initial guess per step: v^0 = v_n + h g, contact impulses 0.
+  * Initial guess per step: v^0 = v_n + h g, contact impulses 0, or (warm
+    start) the previous step's impulses on the nodes of the contact set.
   * Backward projections re-evaluated at x_{n+1} = x_n + h v_{n+1}.
 Every function cites the passage it follows.  Parity is pinned by the
 ``-m "not gpu"`` tests in ``tests/test_oracle_pins.py``.
@@ -422,11 +423,18 @@ def signorini_coulomb(ubar, n, phi, mu, h, mass):
 
 
 def forward_step(model: Model, x: np.ndarray, v: np.ndarray, n: int, iters: Optional[int] = None,
-                 tol: Optional[float] = None, max_iters: int = 100000, energy_log=None):
+                 tol: Optional[float] = None, max_iters: int = 100000, energy_log=None,
+                 f_prev: Optional[np.ndarray] = None):
     """One implicit-Euler step with dry frictional contact (eqn
     implicit_with_contact) solved by PD local/global iterations (Sec. 3.1) with
     contact impulses on the right-hand side (eqn pd_velocity_with_contact) and a
-    per-node Signorini-Coulomb update after each global step."""
+    per-node Signorini-Coulomb update after each global step.
+
+    f_prev (m, 3): warm start of the contact iteration (Sec. 4.2, Convergence,
+    as a remedy for slow forward convergence): every node of this step's
+    contact set starts from its impulse at the end of the previous step
+    (zero for nodes that were not in contact), instead of from zero.  The
+    iteration's fixed point does not depend on its start."""
     h = model.h
     t1 = (n + 1) * h
     y = inertial_predictor(model, x, v, n)
@@ -434,7 +442,7 @@ def forward_step(model: Model, x: np.ndarray, v: np.ndarray, n: int, iters: Opti
     C = nodes.size
     bhat0 = constant_rhs(model, x, v, t1, n)
     vk = v + h * model.external_accel(n)                      # v^0: x^0 = y
-    f = np.zeros((C, 3))
+    f = np.zeros((C, 3)) if f_prev is None else np.asarray(f_prev, float)[nodes].copy()
     ubar = np.zeros((C, 3))
     mode = np.full(C, TAKEOFF, np.int8)
     K = model.scene.pd_iters if iters is None else iters
@@ -446,12 +454,17 @@ def forward_step(model: Model, x: np.ndarray, v: np.ndarray, n: int, iters: Opti
         if C:
             np.add.at(rhs, nodes, f)                          # h J^T r
         vnew = model.solve_P(rhs)                             # global step
+        df = 0.0
         if C:                                                 # contact update per node
             ubar = vnew[nodes] - f / model.mass[nodes, None]
-            vc, f, mode = signorini_coulomb(ubar, normal, gap, mu, h, model.mass[nodes])
+            vc, fn, mode = signorini_coulomb(ubar, normal, gap, mu, h, model.mass[nodes])
+            df = np.max(np.abs(fn - f) / model.mass[nodes, None])
+            f = fn
             vnew[nodes] = vc
         k += 1
-        dv = np.max(np.abs(vnew - vk)) if vk.size else 0.0
+        # the iterate is the pair (v, impulses): a contact node held by the
+        # contact update keeps its velocity while its impulse still changes
+        dv = max(np.max(np.abs(vnew - vk)) if vk.size else 0.0, df)
         vk = vnew
         if energy_log is not None:
             energy_log.append(implicit_energy(model, x + h * vk, y, t1))
@@ -465,16 +478,29 @@ def forward_step(model: Model, x: np.ndarray, v: np.ndarray, n: int, iters: Opti
                       Contact(nodes, obst, normal, gap, mu, ubar, f, mode), k)
 
 
-def rollout(model: Model, x0=None, v0=None, steps: Optional[int] = None, iters=None, tol=None):
-    """Forward simulation over T steps; returns the list of step records."""
+def step_impulses(model: Model, rec: StepRecord) -> np.ndarray:
+    """Per-node impulses (m, 3) at the end of a recorded step (zero off contact)."""
+    f = np.zeros((model.m, 3))
+    f[rec.contact.nodes] = rec.contact.impulse
+    return f
+
+
+def rollout(model: Model, x0=None, v0=None, steps: Optional[int] = None, iters=None, tol=None,
+            warm_start: bool = False, max_iters: int = 100000):
+    """Forward simulation over T steps; returns the list of step records.
+    warm_start: each step's contact iteration starts from the previous step's
+    impulses (see forward_step)."""
     x = np.asarray(model.X if x0 is None else x0, float).copy()
     v = np.asarray(model.scene.v0 if v0 is None else v0, float).copy()
     T = model.scene.steps if steps is None else steps
     recs = []
+    fp = None
     for n in range(T):
-        r = forward_step(model, x, v, n, iters=iters, tol=tol)
+        r = forward_step(model, x, v, n, iters=iters, tol=tol, max_iters=max_iters,
+                         f_prev=fp if warm_start else None)
         recs.append(r)
         x, v = r.x1, r.v1
+        fp = step_impulses(model, r)
     return recs
 
 

@@ -724,3 +724,73 @@ def test_mesh_obstacle_gradients_match_finite_differences():
         assert abs(val - G.dmu[0]) <= 1e-5 * abs(val) + 1e-10, (val, G.dmu[0])
         checks += 1
     assert checks >= 3
+
+
+# ------------------------------------------------------------------ warm-started contact impulses
+
+def _is_contact_fixed_point(model, rec, n):
+    """The recorded (v_{n+1}, impulses) solve the step's equations: the global
+    momentum balance P v = b(p(x_n + h v)) + f (eqn pd_velocity_with_contact),
+    and at every contact node the Signorini-Coulomb law (eqn contact_all):
+    one more contact update from the recorded state changes nothing."""
+    h = model.h
+    ct = rec.contact
+    b0 = O.constant_rhs(model, rec.x0, rec.v0, (n + 1) * h, n)
+    p, _ = O.local_projection(model, rec.x1)
+    rhs = b0 + h * (model.A.T @ (model.w[:, None] * p))
+    np.add.at(rhs, ct.nodes, ct.impulse)
+    v = model.solve_P(rhs)
+    scale = np.abs(rec.v1).max() + 1e-3
+    if np.abs(v - rec.v1).max() > 1e-9 * scale:
+        return False
+    if ct.nodes.size == 0:
+        return True
+    ub = v[ct.nodes] - ct.impulse / model.mass[ct.nodes, None]
+    vc, f, md = O.signorini_coulomb(ub, ct.normal, ct.gap, ct.mu, h, model.mass[ct.nodes])
+    return (np.abs(vc - rec.v1[ct.nodes]).max() <= 1e-9 * scale and np.array_equal(md, ct.mode))
+
+
+@pytest.mark.parametrize("obst,n,steps,height", [("sphere", 4, 12, 0.004), ("plane", 5, 8, 0.0005)])
+def test_warm_start_keeps_the_converged_state(obst, n, steps, height):
+    # starting each step's contact iteration from the previous step's impulses
+    # changes where the iteration starts, not its fixed point: converged
+    # rollouts agree to the tolerance, with the same modes, and every
+    # converged step solves the step's equations.  (On the plane the cloth
+    # settles with every node in contact; a stopping rule on the velocities
+    # alone stops there while the impulses still change -- every velocity is
+    # held by the contact update -- and fails the fixed-point check.)
+    sc = scenes.tiny_scene(n, steps=steps, obstacle=obst, seed=5, height=height, v0_scale=0.05, k=50.0)
+    model = O.Model(sc)
+    cold = O.rollout(model, tol=1e-13)
+    warm = O.rollout(model, tol=1e-13, warm_start=True)
+    assert any(r.contact.nodes.size for r in cold)
+    for k, (a, b) in enumerate(zip(cold, warm)):
+        assert np.abs(a.x1 - b.x1).max() <= 1e-11
+        assert np.array_equal(a.contact.nodes, b.contact.nodes)
+        assert np.array_equal(a.contact.mode, b.contact.mode)
+        assert _is_contact_fixed_point(model, a, k) and _is_contact_fixed_point(model, b, k)
+
+
+def test_warm_start_starts_from_the_previous_impulses():
+    # one PD iteration per step: with warm start the first global solve of
+    # step n already carries step n-1's impulses, so a cloth lying at rest on
+    # the ground (every node supporting its own weight, f_j = m_j g h) is
+    # exactly still after its first step; from zero impulses the single
+    # iteration leaves the free-fall velocity in the global solve
+    pts = np.array([[a, 0.0, b] for a in (0.0, 0.2, 0.4) for b in (0.0, 0.2, 0.4)])
+    sc = particle_scene(pts, [scenes.Obstacle(scenes.PLANE, (0, 0, 0), (0, 1, 0), 0.0, 0.5)], (0.0, 0.0, 0.0),
+                        steps=4)
+    sc.edge_stiffness[:] = 100.0                    # springs at rest length
+    model = O.Model(sc)
+    warm = O.rollout(model, iters=1, warm_start=True)
+    for r in warm:
+        assert np.all(r.contact.mode == O.STICK)
+        mgh = sc.node_mass[:, None] * 9.8 * sc.h
+        assert np.allclose(r.contact.impulse, np.array([0.0, 1.0, 0.0]) * mgh, rtol=1e-12, atol=1e-12 * mgh.max())
+        assert np.abs(r.v1).max() <= 1e-15
+    # the cold iteration's impulse comes from the free velocity of that one
+    # solve; the warm one adds the previous impulse on the right-hand side
+    # first, so its free velocity u = v - f/m equals the cold one exactly
+    cold = O.rollout(model, iters=1)
+    for a, b in zip(cold[1:], warm[1:]):
+        assert np.allclose(a.contact.ubar, b.contact.ubar, rtol=1e-12, atol=1e-12 * np.abs(a.contact.ubar).max())
