@@ -150,7 +150,14 @@ typedef struct {
  *                  (the window nearest the end first, then its solves, then
  *                  the next window); 0: all steps of the segment at once;
  *  checkpoint_every  0: keep every step's record for the backward pass;
- *                  k > 0: keep the state every k steps and recompute segments. */
+ *                  k > 0: keep the state every k steps and recompute segments;
+ *  warm_start      1: each step's contact iteration starts from the previous
+ *                  step's impulses on the nodes of its contact set (0: from
+ *                  zero impulses); the converged state does not depend on it,
+ *                  a fixed pd_iters result does.  Checkpoints keep the
+ *                  impulses, so replayed segments reproduce their records.
+ *  (The tolerance rule of fwd_tol measures the change of the velocities and
+ *  of the contact impulses in velocity units, |f^{k+1} - f^k| / m_j.) */
 typedef struct {
     double                h;
     int32_t               pd_iters;
@@ -174,6 +181,7 @@ typedef struct {
     int32_t               adj_restart;
     int32_t               adj_solver;
     int32_t               adj_window;
+    int32_t               warm_start;
 } sim_params_t;
 
 /* Gradient outputs (caller-allocated device arrays; any may be NULL). */

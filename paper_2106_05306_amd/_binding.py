@@ -43,7 +43,8 @@ class SimParams(Structure):
                 ("bend_region", c_int32_p), ("region_scale", c_double_p), ("n_regions", c_int32),
                 ("n_obstacles", c_int32), ("obstacles", POINTER(SimObstacle)), ("precision", c_int32),
                 ("adj_tol", c_double), ("adj_max_iters", c_int32), ("checkpoint_every", c_int32),
-                ("adj_restart", c_int32), ("adj_solver", c_int32), ("adj_window", c_int32)]
+                ("adj_restart", c_int32), ("adj_solver", c_int32), ("adj_window", c_int32),
+                ("warm_start", c_int32)]
 
 
 class SimGrads(Structure):

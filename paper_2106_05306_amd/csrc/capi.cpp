@@ -55,7 +55,7 @@ struct sim {
     int32_t *d_perm = nullptr;          // new -> caller
     double *rest_x = nullptr;           // rest shape, new order
     double *start_x = nullptr, *start_v = nullptr;  // state a forward pass starts from
-    double *ckpt = nullptr;             // checkpoints: [n_seg][2][m*3]
+    double *ckpt = nullptr;             // checkpoints: [n_seg][3][m*3] (x, v, contact impulses)
     int ckpt_cap = 0;
     double *gsteps = nullptr;           // per-step loss gradients, new order
     double *fext_buf = nullptr;         // external force field, new order
@@ -441,6 +441,7 @@ void build_device(sim *s) {
     D.mixed = hm.precision == SIM_MIXED;
     D.h = hm.h;
     D.fwd_tol = hm.fwd_tol;
+    D.warm_start = hm.warm_start;
     D.adj_tol = hm.adj_tol;
     for (int d = 0; d < 3; ++d) {
         D.g[d] = hm.g[d];
@@ -1294,13 +1295,34 @@ int prepare_forward(sim *s, int n_steps) {
         const int nseg = (n_steps + k - 1) / k;
         if (s->ckpt_cap < nseg) {
             dev_release(s, s->ckpt);
-            s->ckpt = (double *)dev_alloc(s, (size_t)nseg * 2 * v3b);
+            s->ckpt = (double *)dev_alloc(s, (size_t)nseg * 3 * v3b);
             s->ckpt_cap = nseg;
         }
     }
     int rc = copy_d2d(s, s->hd.x, s->start_x, v3b);
     if (!rc) rc = copy_d2d(s, s->hd.v, s->start_v, v3b);
+    if (!rc) rc = hip_err(launch_fill(s->hd.f, 0.0, 3 * (int64_t)s->hd.m, s->stream));   // no impulses before step 0
     if (!rc) rc = hip_err(hipMemsetAsync(s->hd.counters, 0, 8 * sizeof(int64_t), s->stream));
+    return rc;
+}
+
+// Checkpoint seg: the state entering its first step and the contact impulses
+// of the step before (the warm start of that step).
+int save_ckpt(sim *s, int seg) {
+    const size_t v3 = 3 * (size_t)s->hd.m, b = v3 * sizeof(double);
+    double *c = s->ckpt + (size_t)seg * 3 * v3;
+    int rc = copy_d2d(s, c, s->hd.x, b);
+    if (!rc) rc = copy_d2d(s, c + v3, s->hd.v, b);
+    if (!rc) rc = copy_d2d(s, c + 2 * v3, s->hd.f, b);
+    return rc;
+}
+
+int load_ckpt(sim *s, int seg) {
+    const size_t v3 = 3 * (size_t)s->hd.m, b = v3 * sizeof(double);
+    const double *c = s->ckpt + (size_t)seg * 3 * v3;
+    int rc = copy_d2d(s, s->hd.x, c, b);
+    if (!rc) rc = copy_d2d(s, s->hd.v, c + v3, b);
+    if (!rc) rc = copy_d2d(s, s->hd.f, c + 2 * v3, b);
     return rc;
 }
 
@@ -1388,8 +1410,7 @@ int forward_all(sim *s, int n_steps, double *x_traj_dev) {
     s->fwd_launches = (n_steps + k - 1) / k;
     for (int a = 0, seg = 0; a < n_steps && !rc; a += k, ++seg) {
         const int b = std::min(n_steps, a + k);
-        rc = copy_d2d(s, s->ckpt + (size_t)seg * 2 * v3, s->hd.x, v3 * sizeof(double));
-        if (!rc) rc = copy_d2d(s, s->ckpt + ((size_t)seg * 2 + 1) * v3, s->hd.v, v3 * sizeof(double));
+        rc = save_ckpt(s, seg);
         if (!rc) rc = run_forward_range(s, a, b);
         if (!rc && x_traj_dev)
             for (int n = a; n <= b && !rc; ++n)
@@ -1571,8 +1592,7 @@ int backward_all(sim *s) {
     const int nseg = (T + k - 1) / k;
     for (int seg = nseg - 1; seg >= 0; --seg) {
         const int a = seg * k, b = std::min(T, a + k);
-        int rc = copy_d2d(s, s->hd.x, s->ckpt + (size_t)seg * 2 * v3, v3 * sizeof(double));
-        if (!rc) rc = copy_d2d(s, s->hd.v, s->ckpt + ((size_t)seg * 2 + 1) * v3, v3 * sizeof(double));
+        int rc = load_ckpt(s, seg);
         if (!rc) rc = run_forward_range(s, a, b);             // recompute the segment's records
         if (rc) return rc;
         s->hd.rec_step0 = a;
@@ -1708,8 +1728,7 @@ int sim_state(const sim_t *cs, int32_t n, double *x_dev, double *v_dev) {
         int slot = n;
         if (k > 0) {
             const int seg = std::min(n / k, (s->T - 1) / k), a = seg * k, b = std::min(s->T, a + k);
-            rc = copy_d2d(s, s->hd.x, s->ckpt + (size_t)seg * 2 * v3, v3 * sizeof(double));
-            if (!rc) rc = copy_d2d(s, s->hd.v, s->ckpt + ((size_t)seg * 2 + 1) * v3, v3 * sizeof(double));
+            rc = load_ckpt(s, seg);
             if (!rc) rc = run_forward_range(s, a, b);
             slot = n - a;
         }
@@ -1731,9 +1750,7 @@ int sim_modes(const sim_t *cs, int32_t n, uint8_t *modes_host) {
         int slot = n;
         if (k > 0) {                        // recompute the segment holding step n
             const int seg = n / k, a = seg * k, b = std::min(s->T, a + k);
-            const size_t v3 = 3 * (size_t)m;
-            rc = copy_d2d(s, s->hd.x, s->ckpt + (size_t)seg * 2 * v3, v3 * sizeof(double));
-            if (!rc) rc = copy_d2d(s, s->hd.v, s->ckpt + ((size_t)seg * 2 + 1) * v3, v3 * sizeof(double));
+            rc = load_ckpt(s, seg);
             if (!rc) rc = run_forward_range(s, a, b);
             slot = n - a;
         }
@@ -1901,6 +1918,7 @@ int sim_forward_noalloc(sim_t *s, int32_t n_steps, double *xT_dev, double *vT_de
     rc = hip_err(hipMemcpyAsync(dd, &d, sizeof(SimDev), hipMemcpyHostToDevice, s->stream));
     if (!rc) rc = hip_err(launch_fill((double *)(b + L.ctr), 0.0, 16, s->stream));
     if (!rc) rc = hip_err(launch_fill(d.ubar, 0.0, 3 * (int64_t)m, s->stream));
+    if (!rc) rc = hip_err(launch_fill(d.f, 0.0, 3 * (int64_t)m, s->stream));        // warm start of step 0
     if (!rc) rc = copy_d2d(s, d.x, s->start_x, v3b);
     if (!rc) rc = copy_d2d(s, d.v, s->start_v, v3b);
     if (!rc) rc = hip_err(launch_forward(dd, 1, s->hd.mixed != 0, s->lds_fwd, s->flags_fwd, 0, has_mesh(&s, 1),

@@ -44,6 +44,7 @@ int HostModel::build(const sim_mesh_t *mesh, const sim_params_t *p) {
     for (int d = 0; d < 3; ++d) g[d] = p->gravity[d];
     pd_iters = p->pd_iters;
     fwd_tol = p->fwd_tol;
+    warm_start = p->warm_start ? 1 : 0;
     fwd_max_iters = p->fwd_max_iters > 0 ? p->fwd_max_iters : 100000;
     if (fwd_tol <= 0 && pd_iters < 1) { error = "pd_iters must be >= 1"; return SIM_EINVAL; }
     adj_tol = p->adj_tol > 0 ? p->adj_tol : 1e-10;

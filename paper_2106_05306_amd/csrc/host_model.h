@@ -20,6 +20,7 @@ struct HostModel {
     double h = 0, g[3] = {0, 0, 0};
     int pd_iters = 20, fwd_max_iters = 0, adj_max_iters = 500, precision = SIM_FP64;
     double fwd_tol = 0, adj_tol = 1e-10;
+    int warm_start = 0;
     int checkpoint_every = 0, adj_restart = 60, adj_solver = SIM_ADJ_ITERATIVE, adj_window = 0;
     std::vector<sim_obstacle_t> obstacles;  // mesh pointers cleared; geometry in obst_tri
     // triangle-mesh obstacles: per obstacle, per triangle its vertices a, b, c,

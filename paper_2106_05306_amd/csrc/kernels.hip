@@ -730,9 +730,12 @@ __global__ __launch_bounds__(kBlock) void k_forward(const SimDev *__restrict__ s
                 attach_target(S, G(S.att_rest) + 3 * as, t1, tg);
                 for (int d = 0; d < 3; ++d) b[d] += h * S.w_att * tg[d];
             }
+            // impulses: zero, or (warm start) the previous step's on the nodes of
+            // this step's contact set (zero where the node was not in contact)
+            const bool keep = S.warm_start && contact;
             for (int d = 0; d < 3; ++d) {
                 G(S.b0)[3 * i + d] = b[d];
-                G(S.f)[3 * i + d] = 0.0;
+                if (!keep) G(S.f)[3 * i + d] = 0.0;
                 A[3 * i + d] = vi[d] + h * ae[d];
             }
             if constexpr ((FL & kLdsPositions) != 0)
@@ -768,6 +771,9 @@ __global__ __launch_bounds__(kBlock) void k_forward(const SimDev *__restrict__ s
                     }
                     G(S.mode)[i] = signorini_coulomb(ub, nrm, phi, S.obst[G(S.cobst)[i]].mu, h, mi, vv, ff);
                     for (int d = 0; d < 3; ++d) {
+                        // the iterate is (v, f): a node held by the contact update
+                        // keeps its velocity while its impulse may still change
+                        if (converge) dmax = fmax(dmax, fabs(ff[d] - G(S.f)[3 * i + d]) / mi);
                         B[3 * i + d] = vv[d];
                         G(S.f)[3 * i + d] = ff[d];
                         G(S.ubar)[3 * i + d] = ub[d];

@@ -115,6 +115,7 @@ struct SimDev {
     int nc_total;                     // all norm constraints (canonical numbering)
     int n_obst, na;
     int K, fwd_max_iters, adj_max_iters, mixed;
+    int warm_start;                   // contact impulses start from the previous step's
     double h, fwd_tol, adj_tol;
     double g[3];
     double w_att, att_omega, att_axis[3], att_center[3];

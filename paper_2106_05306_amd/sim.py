@@ -50,7 +50,7 @@ def build_structs(X, tris, node_mass, edge_stiffness, *, edges=None, h=1.0 / 120
                   attach_omega=0.0, attach_axis=(0.0, 1.0, 0.0), attach_center=(0.0, 0.0, 0.0),
                   obstacles: Sequence[dict] = (), edge_region=None, bend_region=None, region_scale=None,
                   precision="fp64", adj_tol=1e-10, adj_max_iters=500, checkpoint_every=0, adj_restart=0,
-                  adj_solver="iterative", adj_window=0):
+                  adj_solver="iterative", adj_window=0, warm_start=False):
     """Marshal a mesh and its parameters into the C structs; returns
     (SimMesh, SimParams, keep-alive dict of the numpy arrays they point to)."""
     k = {}
@@ -116,6 +116,7 @@ def build_structs(X, tris, node_mass, edge_stiffness, *, edges=None, h=1.0 / 120
     p.adj_restart = adj_restart
     p.adj_solver = {"iterative": B.SIM_ADJ_ITERATIVE, "direct": B.SIM_ADJ_DIRECT}[adj_solver]
     p.adj_window = adj_window
+    p.warm_start = 1 if warm_start else 0
     return mesh, p, k
 
 
