@@ -51,6 +51,9 @@ extern "C" {
 #define SIM_EHIP            -6   /* a HIP runtime call failed                           */
 #define SIM_ESCRATCH        -7   /* the mesh needs more device scratch than
                                     sim_forward_noalloc has (16 MiB)                   */
+#define SIM_ESYNC           -8   /* a multi-workgroup forward launch gave up waiting at
+                                    a barrier (its workgroups were not all resident
+                                    in time); the rollout is not recorded              */
 #define SIM_WADJ_FALLBACK    1   /* >= 1 adjoint step needed the fallback solver        */
 #define SIM_WADJ_NOCONV      2   /* >= 1 adjoint step did not reach its tolerance       */
 #define SIM_WADJ_NONFINITE   3   /* the state gradients overflowed (not finite)         */

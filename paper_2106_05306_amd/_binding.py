@@ -14,6 +14,7 @@ LIB_PATH = os.environ.get("DIFFCLOTH_LIB", os.path.join(HERE, "libdiffcloth.so")
 
 SIM_OK, SIM_EINVAL, SIM_ENOTSPD, SIM_ENOMEM, SIM_ENONFINITE, SIM_ESTATE, SIM_EHIP = 0, -1, -2, -3, -4, -5, -6
 SIM_ESCRATCH = -7
+SIM_ESYNC = -8
 SIM_WADJ_FALLBACK, SIM_WADJ_NOCONV, SIM_WADJ_NONFINITE = 1, 2, 3
 SIM_PLANE, SIM_SPHERE, SIM_MESH = 0, 1, 2
 SIM_FP64, SIM_MIXED = 0, 1

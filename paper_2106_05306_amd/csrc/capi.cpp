@@ -30,6 +30,7 @@ hipError_t launch_fill(double *p, double v, int64_t n, hipStream_t st);
 hipError_t launch_adj_assemble(const SimDev *d_sims, const int32_t *work, int nblocks, hipStream_t st);
 hipError_t launch_adj_factor_level(const SimDev *d_sims, const int32_t *work, int nblocks, int nmax, hipStream_t st);
 hipError_t noalloc_scratch(void **out);
+hipError_t launch_forward_mw(const SimDev *d, int W, bool mixed, bool mesh, hipStream_t st);
 }  // namespace dc
 
 using namespace dc;
@@ -43,6 +44,7 @@ struct sim {
     std::vector<std::pair<void *, int64_t>> owned;   // every device allocation of the handle and its size
     int64_t bytes = 0;                  // their total (what sim_stats reports)
     SimDev *batch_desc = nullptr;       // descriptors of the batched launches this handle leads
+    bool mw_used = false;               // a multi-workgroup forward ran since the last mw_check
     SimDev hd_noalloc{};                // descriptor of the allocation-free forward (copied to the
                                         //   device scratch on every call; lives as long as the handle)
     int step_info_cap = 0;              // steps the per-step record (hd.step_info) can hold
@@ -132,6 +134,21 @@ int fwd_helpers(sim *const *sims, int n) {
     }
     h = std::min(h, 7);
     return h > 0 && (int64_t)n * (1 + h) <= sims[0]->cus ? h : 0;
+}
+
+// Workgroups of a single handle's forward launch (the multi-workgroup kernel
+// when the elimination tree allows it): DIFFCLOTH_FWD_WGS, 0 or 1 = one.
+int mw_workgroups_default() {
+    const char *e = std::getenv("DIFFCLOTH_FWD_WGS");
+    const int v = e ? std::atoi(e) : -1;
+    return v >= 0 ? std::min(v, kMwMax) : kMwMax;
+}
+
+// wall-clock ticks (100 MHz) a multi-workgroup barrier waits before giving up
+int64_t mw_spin_default() {
+    const char *e = std::getenv("DIFFCLOTH_MW_SPIN");
+    const long long v = e ? std::atoll(e) : -1;
+    return v >= 0 ? (int64_t)v : (int64_t)100000000;       // 1 s
 }
 
 // prefetch workgroups of a single-handle direct adjoint launch (0: none)
@@ -441,6 +458,11 @@ void build_device(sim *s) {
     D.mixed = hm.precision == SIM_MIXED;
     D.h = hm.h;
     D.fwd_tol = hm.fwd_tol;
+    D.mw_spin = mw_spin_default();
+    {
+        const char *e = std::getenv("DIFFCLOTH_MW_TEST_ABSENT");   // failure-handling tests
+        D.mw_absent = e && std::atoi(e) > 0 ? 1 : 0;
+    }
     D.warm_start = hm.warm_start;
     D.adj_tol = hm.adj_tol;
     for (int d = 0; d < 3; ++d) {
@@ -593,45 +615,51 @@ void build_device(sim *s) {
         }
         return best;
     };
+    // work items of one supernode (gather rows, forward row pairs, backward
+    // column pairs, backward gathers); returns its longest forward / backward item
+    auto emit = [&](int sn, std::vector<RowItem> &ri, std::vector<FwdItem> &fi, std::vector<BwdItem> &bi,
+                    std::vector<GatherItem> &gi, int &fmx, int &bmx) {
+        const int c0 = sc0[sn], nsz = sns[sn], ld = nsz + snr[sn];
+        if (ld >= 32768) throw std::runtime_error("supernode too large");
+        const int ldp = ld + (ld & 1), nszp = nsz + (nsz & 1);
+        const bool root = snr[sn] == 0;
+        for (int k = 0; k < nsz; ++k) ri.push_back(RowItem{3 * (c0 + k), up[c0 + k], up[c0 + k + 1], 0});
+        for (int k = 0; k < nsz && !root; k += 2) {  // columns k, k + 1
+            BwdItem b{};
+            b.g = (int32_t)(gofft[sn] + (int64_t)k * nszp + k);
+            b.n1 = (int16_t)(nsz - k);
+            b.n2 = (int16_t)snr[sn];
+            b.ybase = 3 * (c0 + k);
+            b.ubase = uoff[sn];
+            b.st = nszp;
+            b.two = k + 1 < nsz;
+            bi.push_back(b);
+            bmx = std::max(bmx, ld - k);
+        }
+        for (int q = 0; q < snr[sn]; ++q) {        // x of a root's rows is still in Y (encoded -(3i) - 1)
+            const int i = rows[rptr[sn] + q];
+            gi.push_back(GatherItem{uoff[sn] + 3 * q, is_root_row[i] ? -3 * i - 1 : 3 * i});
+        }
+        auto out_of = [&](int r) { return r < nsz ? 3 * (c0 + r) : -(uoff[sn] + 3 * (r - nsz)) - 1; };
+        for (int r = 0; r < ld; r += 2) {           // rows r, r + 1
+            FwdItem f{};
+            f.g = (int32_t)(goff[sn] + r);
+            f.ld = (int16_t)ldp;
+            f.kmax = (int16_t)(root ? nsz : r + 1 < nsz ? r + 2 : nsz);
+            f.tbase = 3 * c0;
+            f.out0 = out_of(r);
+            f.out1 = r + 1 < ld ? out_of(r + 1) : kNoOutput;
+            fi.push_back(f);
+            fmx = std::max(fmx, (int)f.kmax);
+        }
+    };
     for (int l = 0; l < hm.n_levels; ++l) {
         int fmax = 1, bmax = 1;
         for (int sn = 0; sn < ns; ++sn) {
             if (hm.sup_level[sn] != l) continue;
-            const int c0 = sc0[sn], nsz = sns[sn], ld = nsz + snr[sn];
-            if (ld >= 32768) throw std::runtime_error("supernode too large");
-            const int ldp = ld + (ld & 1), nszp = nsz + (nsz & 1);
-            const bool root = snr[sn] == 0;
-            for (int k = 0; k < nsz; ++k) ritems.push_back(RowItem{3 * (c0 + k), up[c0 + k], up[c0 + k + 1], 0});
-            if (root)
-                for (int k = 0; k < nsz; ++k) root_rows.push_back(3 * (c0 + k));
-            for (int k = 0; k < nsz && !root; k += 2) {  // columns k, k + 1
-                BwdItem b{};
-                b.g = (int32_t)(gofft[sn] + (int64_t)k * nszp + k);
-                b.n1 = (int16_t)(nsz - k);
-                b.n2 = (int16_t)snr[sn];
-                b.ybase = 3 * (c0 + k);
-                b.ubase = uoff[sn];
-                b.st = nszp;
-                b.two = k + 1 < nsz;
-                bitems.push_back(b);
-                bmax = std::max(bmax, ld - k);
-            }
-            for (int q = 0; q < snr[sn]; ++q) {        // x of a root's rows is still in Y (encoded -(3i) - 1)
-                const int i = rows[rptr[sn] + q];
-                bgat.push_back(GatherItem{uoff[sn] + 3 * q, is_root_row[i] ? -3 * i - 1 : 3 * i});
-            }
-            auto out_of = [&](int r) { return r < nsz ? 3 * (c0 + r) : -(uoff[sn] + 3 * (r - nsz)) - 1; };
-            for (int r = 0; r < ld; r += 2) {           // rows r, r + 1
-                FwdItem f{};
-                f.g = (int32_t)(goff[sn] + r);
-                f.ld = (int16_t)ldp;
-                f.kmax = (int16_t)(root ? nsz : r + 1 < nsz ? r + 2 : nsz);
-                f.tbase = 3 * c0;
-                f.out0 = out_of(r);
-                f.out1 = r + 1 < ld ? out_of(r + 1) : kNoOutput;
-                fitems.push_back(f);
-                fmax = std::max(fmax, (int)f.kmax);
-            }
+            if (snr[sn] == 0)
+                for (int k = 0; k < sns[sn]; ++k) root_rows.push_back(3 * (sc0[sn] + k));
+            emit(sn, ritems, fitems, bitems, bgat, fmax, bmax);
         }
         lrp[l + 1] = (int32_t)ritems.size();
         lip[l + 1] = (int32_t)fitems.size();
@@ -639,6 +667,106 @@ void build_device(sim *s) {
         lbp[l + 1] = (int32_t)bitems.size();
         team[2 * l] = pick_team(lip[l + 1] - lip[l], fmax);
         team[2 * l + 1] = pick_team(lbp[l + 1] - lbp[l], bmax);
+    }
+    // Multi-workgroup forward: with one root supernode (the merged top
+    // separators) whose children head subtrees of their own columns, W
+    // workgroups each solve whole subtrees alone and share the root.  Subtrees
+    // go to the least loaded workgroup (factor entries, largest first); every
+    // workgroup also owns a slice of the root's columns.
+    D.mw = 0;
+    {
+        const int L = hm.n_levels;
+        std::vector<int> parent(ns, -1);
+        for (int sn = 0; sn < ns; ++sn)
+            if (snr[sn] > 0) parent[sn] = hm.sup_of[rows[rptr[sn]]];
+        int nroot = 0, root = -1;
+        for (int sn = 0; sn < ns; ++sn)
+            if (parent[sn] < 0) { ++nroot; root = sn; }
+        std::vector<int> kids;
+        for (int sn = 0; sn < ns; ++sn)
+            if (parent[sn] >= 0 && parent[sn] == root) kids.push_back(sn);
+        const int want = mw_workgroups_default();
+        int W = std::min<int>({want, (int)kids.size(), kMwMax});
+        bool ok = nroot == 1 && L >= 2 && W >= 2 && sns[root] <= kMwRootMax && hm.sup_level[root] == L - 1;
+        for (int sn = 0; sn < ns && ok; ++sn)
+            if (sn != root && hm.sup_level[sn] == L - 1) ok = false;   // the root alone on the top level
+        if (ok) {
+            std::vector<int> head(ns, -1);          // root child heading each supernode's subtree
+            std::vector<int> kid_of(ns, -1);
+            for (size_t k = 0; k < kids.size(); ++k) kid_of[kids[k]] = (int)k;
+            for (int sn = 0; sn < ns; ++sn) {
+                int t = sn;
+                while (t >= 0 && parent[t] >= 0 && parent[t] != root) t = parent[t];
+                head[sn] = (t >= 0 && parent[t] == root) ? kid_of[t] : -1;
+            }
+            std::vector<double> wt(kids.size(), 0.0);
+            std::vector<int> lo(kids.size(), INT32_MAX), hi(kids.size(), -1), cnt(kids.size(), 0);
+            for (int sn = 0; sn < ns; ++sn) {
+                const int k = head[sn];
+                if (k < 0) continue;
+                wt[k] += (double)sns[sn] * (sns[sn] + snr[sn]);
+                lo[k] = std::min(lo[k], sc0[sn]);
+                hi[k] = std::max(hi[k], sc0[sn] + sns[sn]);
+                cnt[k] += sns[sn];
+            }
+            for (size_t k = 0; k < kids.size(); ++k)
+                if (hi[k] - lo[k] != cnt[k]) ok = false;     // a subtree's columns are contiguous
+            std::vector<int> order(kids.size()), owner(kids.size(), 0);
+            for (size_t k = 0; k < kids.size(); ++k) order[k] = (int)k;
+            std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return wt[a] > wt[b]; });
+            std::vector<double> load(W, 0.0);
+            std::vector<int> nsub(W, 0);
+            for (int k : order) {
+                const int wbest = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+                owner[k] = wbest;
+                load[wbest] += wt[k];
+                ++nsub[wbest];
+            }
+            for (int w = 0; w < W; ++w)
+                if (nsub[w] + 1 > kMwRanges) ok = false;
+            if (ok) {
+                std::vector<int32_t> nodes((size_t)W * kMwRanges * 2, 0);
+                std::vector<int> used(W, 0);
+                for (size_t k = 0; k < kids.size(); ++k) {
+                    const int w = owner[k], r = used[w]++;
+                    nodes[2 * ((size_t)w * kMwRanges + r)] = lo[k];
+                    nodes[2 * ((size_t)w * kMwRanges + r) + 1] = hi[k];
+                }
+                const int rc0 = sc0[root], rn = sns[root];
+                for (int w = 0; w < W; ++w) {           // the root's columns, in W slices
+                    const int r = used[w]++;
+                    nodes[2 * ((size_t)w * kMwRanges + r)] = rc0 + (int)((int64_t)rn * w / W);
+                    nodes[2 * ((size_t)w * kMwRanges + r) + 1] = rc0 + (int)((int64_t)rn * (w + 1) / W);
+                }
+                std::vector<RowItem> mri;
+                std::vector<FwdItem> mfi;
+                std::vector<BwdItem> mbi;
+                std::vector<GatherItem> mgi;
+                const int Q = W * (L - 1);
+                std::vector<int32_t> ptr(4 * ((size_t)Q + 1), 0);     // rows, fwd, bwd, gather
+                for (int w = 0; w < W; ++w)
+                    for (int l = 0; l < L - 1; ++l) {
+                        int fmx = 1, bmx = 1;
+                        for (int sn = 0; sn < ns; ++sn)
+                            if (hm.sup_level[sn] == l && head[sn] >= 0 && owner[head[sn]] == w)
+                                emit(sn, mri, mfi, mbi, mgi, fmx, bmx);
+                        const int q = w * (L - 1) + l + 1;
+                        ptr[q] = (int32_t)mri.size();
+                        ptr[(Q + 1) + q] = (int32_t)mfi.size();
+                        ptr[2 * (Q + 1) + q] = (int32_t)mbi.size();
+                        ptr[3 * (Q + 1) + q] = (int32_t)mgi.size();
+                    }
+                D.mw = W;
+                D.mw_root_c0 = rc0;
+                D.mw_ptr = upload(s, ptr);
+                D.mw_rows = upload(s, mri);
+                D.mw_fitems = upload(s, mfi);
+                D.mw_bitems = upload(s, mbi);
+                D.mw_bgat = upload(s, mgi);
+                D.mw_nodes = upload(s, nodes);
+                D.mw_sync = (uint32_t *)zeros<double>(s, kMwSyncDoubles);
+            }
+        }
     }
     D.n_levels = hm.n_levels;
     D.lvl_rows_ptr = upload(s, lrp);
@@ -1051,6 +1179,20 @@ std::vector<int> overlap_chunks(const sim *s, int n_steps) {
 }
 
 // Forward over [a, b) from the handle's current state into the record buffer.
+// Forward launch of one handle (descriptor already pushed): the
+// multi-workgroup kernel when the handle's tree allows it, its barrier block
+// cleared first (a fill kernel), else one workgroup (plus prefetchers).
+int launch_single_forward(sim *s) {
+    if (s->hd.mw >= 2) {
+        int rc = hip_err(launch_fill((double *)s->hd.mw_sync, 0.0, kMwSyncDoubles, s->stream));
+        if (!rc) rc = hip_err(launch_forward_mw(s->dd, s->hd.mw, s->hd.mixed != 0, has_mesh(&s, 1), s->stream));
+        s->mw_used = true;
+        return rc;
+    }
+    return hip_err(launch_forward(s->dd, 1, s->hd.mixed != 0, s->lds_fwd, s->flags_fwd, fwd_helpers(&s, 1),
+                                  has_mesh(&s, 1), s->stream));
+}
+
 int run_forward_range(sim *s, int a, int b) {
     s->hd.step_begin = a;
     s->hd.step_end = b;
@@ -1058,8 +1200,19 @@ int run_forward_range(sim *s, int a, int b) {
     ++s->hd.fwd_epoch;
     int rc = push_desc(s);
     if (rc) return rc;
-    return hip_err(launch_forward(s->dd, 1, s->hd.mixed != 0, s->lds_fwd, s->flags_fwd, fwd_helpers(&s, 1),
-                                  has_mesh(&s, 1), s->stream));
+    return launch_single_forward(s);
+}
+
+// A multi-workgroup forward launch since the last check gave up at a barrier
+// (a workgroup waited longer than mw_spin): SIM_ESYNC; clears the flag.
+int mw_check(sim *s) {
+    if (!s->mw_used) return SIM_OK;
+    uint32_t flag[4] = {0, 0, 0, 0};
+    int rc = hip_err(hipMemcpyAsync(flag, s->hd.mw_sync, sizeof(flag), hipMemcpyDeviceToHost, s->stream));
+    if (!rc) rc = hip_err(hipStreamSynchronize(s->stream));
+    if (rc) return rc;
+    s->mw_used = false;
+    return flag[2] ? SIM_ESYNC : SIM_OK;
 }
 
 // Timing event k of the handle's stream (0/1 forward start/end, 2/3 backward).
@@ -1368,9 +1521,7 @@ int forward_overlapped(sim *s, int n_steps, const std::vector<int> &ends) {
         s->hd.rec_step0 = 0;
         ++s->hd.fwd_epoch;
         rc = push_desc(s);
-        if (!rc) rc = hip_err(launch_forward(s->dd, 1, s->hd.mixed != 0, s->lds_fwd, s->flags_fwd, fwd_helpers(&s, 1),
-                                             has_mesh(&s, 1),
-                                             s->stream));
+        if (!rc) rc = launch_single_forward(s);
         if (!rc && pa >= 0) {                // the previous chunk, queued behind this one's launch
             std::vector<int32_t> pairs;
             for (int n = pa; n < pb; ++n) { pairs.push_back(0); pairs.push_back(n); }
@@ -1422,8 +1573,9 @@ int forward_all(sim *s, int n_steps, double *x_traj_dev) {
 
 int finish_forward(sim *s, int n_steps, double *xT_dev, double *vT_dev) {
     const int m = s->hd.m;
-    int rc = SIM_OK;
-    if (xT_dev) rc = hip_err(launch_permute3(s->hd.x, xT_dev, s->d_perm, m, true, s->stream));
+    int rc = mw_check(s);
+    if (rc) s->T = -1;                        // nothing usable was recorded
+    if (!rc && xT_dev) rc = hip_err(launch_permute3(s->hd.x, xT_dev, s->d_perm, m, true, s->stream));
     if (!rc && vT_dev) rc = hip_err(launch_permute3(s->hd.v, vT_dev, s->d_perm, m, true, s->stream));
     if (!rc) rc = read_counters(s);
     if (!rc) {
@@ -1635,7 +1787,8 @@ int write_grads(sim *s, const sim_grads_t *out) {
 // Warnings of the last backward pass, the most severe first: non-finite state
 // gradients, a missed tolerance, a fallback.
 int backward_status(sim *s) {
-    int rc = read_counters(s);
+    int rc = mw_check(s);                   // checkpoint segments replayed by the forward kernel
+    if (!rc) rc = read_counters(s);
     if (rc) return rc;
     {
         const size_t v3 = 3 * (size_t)s->hd.m;
@@ -1730,6 +1883,7 @@ int sim_state(const sim_t *cs, int32_t n, double *x_dev, double *v_dev) {
             const int seg = std::min(n / k, (s->T - 1) / k), a = seg * k, b = std::min(s->T, a + k);
             rc = load_ckpt(s, seg);
             if (!rc) rc = run_forward_range(s, a, b);
+            if (!rc) rc = mw_check(s);
             slot = n - a;
         }
         if (!rc && x_dev) rc = hip_err(launch_permute3(s->hd.rec_x + slot * v3, x_dev, s->d_perm, m, true, s->stream));
@@ -1752,6 +1906,7 @@ int sim_modes(const sim_t *cs, int32_t n, uint8_t *modes_host) {
             const int seg = n / k, a = seg * k, b = std::min(s->T, a + k);
             rc = load_ckpt(s, seg);
             if (!rc) rc = run_forward_range(s, a, b);
+            if (!rc) rc = mw_check(s);
             slot = n - a;
         }
         if (!rc) rc = hip_err(launch_modes(s->hd.rec_mode + (size_t)slot * m, s->d_modes_tmp, s->d_perm, m, s->stream));
@@ -2190,6 +2345,7 @@ const char *sim_strerror(int code) {
     switch (code) {
         case SIM_OK: return "ok";
         case SIM_EINVAL: return "invalid mesh or parameters";
+        case SIM_ESYNC: return "a multi-workgroup forward launch gave up waiting at a barrier";
         case SIM_ESCRATCH: return "the mesh needs more than the 16 MiB of device scratch of sim_forward_noalloc";
         case SIM_ENOTSPD: return "PD matrix is not positive definite";
         case SIM_ENOMEM: return "out of memory";

@@ -128,6 +128,107 @@ __device__ __forceinline__ void announce(int64_t *where, int64_t epoch, int64_t 
     if (threadIdx.x == 0) __hip_atomic_store(where, (epoch << 40) | pos, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Forward-solve products of items t0, t0 + stride, ... < t1 (rows r, r + 1 of a
+// stacked block G_s times the gathered right-hand side), one team of tl lanes
+// per item; cur / cur2 hold the first item's descriptor (fetched early by the
+// caller), the next one is in flight while the current one is computed.
+__device__ __forceinline__ void fwd_products(GLOBAL const v4i *fit, GLOBAL const v2d *gv2, int t0, int t1, int stride,
+                                             int tl, int lane, v4i cur, v4i cur2, auto T, auto Y, auto U) {
+    for (int t = t0; t < t1; t += stride) {
+        v4i nxt = {0, 0, 0, 0}, nxt2 = {0, 0, 0, 0};  // next descriptor, in flight meanwhile
+        if (t + stride < t1) { nxt = fit[2 * (t + stride)]; nxt2 = fit[2 * (t + stride) + 1]; }
+        const auto Gb = gv2 + (cur.x >> 1);
+        const auto Tb = T + cur.z;
+        const int ld2 = (cur.y & 0xffff) >> 1, kmax = cur.y >> 16;
+        double a0 = 0, a1 = 0, a2 = 0, b0 = 0, b1 = 0, b2 = 0;
+        for (int k0 = lane; k0 < kmax; k0 += kSolveBatch * tl) {
+            v2d g[kSolveBatch];
+#pragma unroll
+            for (int j = 0; j < kSolveBatch; ++j) {           // kSolveBatch independent loads in flight
+                const int k = k0 + j * tl;
+                g[j] = k < kmax ? Gb[k * ld2] : v2d{0.0, 0.0};
+            }
+#pragma unroll
+            for (int j = 0; j < kSolveBatch; ++j) {
+                const int k = k0 + j * tl;
+                if (k < kmax) {
+                    const double t0v = Tb[3 * k], t1v = Tb[3 * k + 1], t2v = Tb[3 * k + 2];
+                    a0 += g[j].x * t0v; a1 += g[j].x * t1v; a2 += g[j].x * t2v;
+                    b0 += g[j].y * t0v; b1 += g[j].y * t1v; b2 += g[j].y * t2v;
+                }
+            }
+        }
+        a0 = team_sum(a0, tl); a1 = team_sum(a1, tl); a2 = team_sum(a2, tl);
+        b0 = team_sum(b0, tl); b1 = team_sum(b1, tl); b2 = team_sum(b2, tl);
+        if (lane == 0) {
+            put_row(cur.w, a0, a1, a2, Y, U);
+            put_row(cur2.x, b0, b1, b2, Y, U);
+        }
+        cur = nxt;
+        cur2 = nxt2;
+    }
+}
+
+// Backward-solve products of items t0, t0 + stride, ... < t1 (column pairs of
+// a stacked block: x_s = L_ss^{-T} y_s - (B_s L_ss^{-1})^T x_{R_s}, x_{R_s}
+// gathered into the supernode's update slots first).
+__device__ __forceinline__ void bwd_products(GLOBAL const v4i *bit, GLOBAL const v2d *gt2, int t0, int t1, int stride,
+                                             int tl, int lane, v4i cur, v4i cur2, auto Y, auto x, auto U) {
+    for (int t = t0; t < t1; t += stride) {
+        v4i nxt = {0, 0, 0, 0}, nxt2 = {0, 0, 0, 0};
+        if (t + stride < t1) { nxt = bit[2 * (t + stride)]; nxt2 = bit[2 * (t + stride) + 1]; }
+        const auto Gb = gt2 + (cur.x >> 1);
+        const int st2 = cur2.x >> 1;
+        const int n1 = cur.y & 0xffff, n = n1 + (cur.y >> 16), yb = cur.z;
+        const auto Yb = Y + yb;
+        const int ub = cur.w - 3 * n1;               // U[ub + 3k] is row k >= n1
+        double a0 = 0, a1 = 0, a2 = 0, b0 = 0, b1 = 0, b2 = 0;
+        for (int k0 = lane; k0 < n; k0 += kSolveBatch * tl) {
+            v2d g[kSolveBatch];
+#pragma unroll
+            for (int j = 0; j < kSolveBatch; ++j) {
+                const int k = k0 + j * tl;
+                g[j] = k < n ? Gb[k * st2] : v2d{0.0, 0.0};
+            }
+#pragma unroll
+            for (int j = 0; j < kSolveBatch; ++j) {
+                const int k = k0 + j * tl;
+                if (k < n1) {
+                    const double w0 = Yb[3 * k], w1 = Yb[3 * k + 1], w2 = Yb[3 * k + 2];
+                    a0 += g[j].x * w0; a1 += g[j].x * w1; a2 += g[j].x * w2;
+                    b0 += g[j].y * w0; b1 += g[j].y * w1; b2 += g[j].y * w2;
+                } else if (k < n) {
+                    const int o = ub + 3 * k;
+                    const double w0 = U[o], w1 = U[o + 1], w2 = U[o + 2];
+                    a0 -= g[j].x * w0; a1 -= g[j].x * w1; a2 -= g[j].x * w2;
+                    b0 -= g[j].y * w0; b1 -= g[j].y * w1; b2 -= g[j].y * w2;
+                }
+            }
+        }
+        a0 = team_sum(a0, tl); a1 = team_sum(a1, tl); a2 = team_sum(a2, tl);
+        b0 = team_sum(b0, tl); b1 = team_sum(b1, tl); b2 = team_sum(b2, tl);
+        if (lane == 0) {
+            x[yb] = a0; x[yb + 1] = a1; x[yb + 2] = a2;
+            if (cur2.y) { x[yb + 3] = b0; x[yb + 4] = b1; x[yb + 5] = b2; }
+        }
+        cur = nxt;
+        cur2 = nxt2;
+    }
+}
+
+// backward gathers q0 .. q1 - 1 (x_{R_s} into the update slots; a root's rows read from Y), from thread t
+__device__ __forceinline__ void bwd_gather(GLOBAL const v2i *bg, int q0, int q1, int t, int nt, auto x, auto Y, auto U) {
+    for (int q = q0 + t; q < q1; q += nt) {
+        const v2i e = bg[q];                             // GatherItem {u, x3}
+        if (e.y >= 0) {
+            U[e.x] = x[e.y]; U[e.x + 1] = x[e.y + 1]; U[e.x + 2] = x[e.y + 2];
+        } else {                                         // a root's row: x is still in Y
+            const int y3 = -e.y - 1;
+            U[e.x] = Y[y3]; U[e.x + 1] = Y[y3 + 1]; U[e.x + 2] = Y[y3 + 2];
+        }
+    }
+}
+
 // pos0 >= 0: the forward pass announces each level (pos0 + phase, see fwd_pos)
 __device__ __forceinline__ void solve_P(const SimDev &S, auto b, auto T, auto Y, auto x, auto U, int64_t pos0 = -1) {
     const auto gv2 = (GLOBAL const v2d *)S.gval;        // two rows per load
@@ -144,39 +245,7 @@ __device__ __forceinline__ void solve_P(const SimDev &S, auto b, auto T, auto Y,
         if (i0 + team < i1) { cur = fit[2 * (i0 + team)]; cur2 = fit[2 * (i0 + team) + 1]; }
         gather_rows(G(S.rows), G(S.upd_off), G(S.lvl_rows_ptr)[l], G(S.lvl_rows_ptr)[l + 1], b, T, U);
         __syncthreads();
-        for (int t = i0 + team; t < i1; t += nteams) {
-            v4i nxt = {0, 0, 0, 0}, nxt2 = {0, 0, 0, 0};  // next descriptor, in flight meanwhile
-            if (t + nteams < i1) { nxt = fit[2 * (t + nteams)]; nxt2 = fit[2 * (t + nteams) + 1]; }
-            const auto Gb = gv2 + (cur.x >> 1);
-            const auto Tb = T + cur.z;
-            const int ld2 = (cur.y & 0xffff) >> 1, kmax = cur.y >> 16;
-            double a0 = 0, a1 = 0, a2 = 0, b0 = 0, b1 = 0, b2 = 0;
-            for (int k0 = lane; k0 < kmax; k0 += kSolveBatch * tl) {
-                v2d g[kSolveBatch];
-#pragma unroll
-                for (int j = 0; j < kSolveBatch; ++j) {           // kSolveBatch independent loads in flight
-                    const int k = k0 + j * tl;
-                    g[j] = k < kmax ? Gb[k * ld2] : v2d{0.0, 0.0};
-                }
-#pragma unroll
-                for (int j = 0; j < kSolveBatch; ++j) {
-                    const int k = k0 + j * tl;
-                    if (k < kmax) {
-                        const double t0 = Tb[3 * k], t1 = Tb[3 * k + 1], t2 = Tb[3 * k + 2];
-                        a0 += g[j].x * t0; a1 += g[j].x * t1; a2 += g[j].x * t2;
-                        b0 += g[j].y * t0; b1 += g[j].y * t1; b2 += g[j].y * t2;
-                    }
-                }
-            }
-            a0 = team_sum(a0, tl); a1 = team_sum(a1, tl); a2 = team_sum(a2, tl);
-            b0 = team_sum(b0, tl); b1 = team_sum(b1, tl); b2 = team_sum(b2, tl);
-            if (lane == 0) {
-                put_row(cur.w, a0, a1, a2, Y, U);
-                put_row(cur2.x, b0, b1, b2, Y, U);
-            }
-            cur = nxt;
-            cur2 = nxt2;
-        }
+        fwd_products(fit, gv2, i0 + team, i1, nteams, tl, lane, cur, cur2, T, Y, U);
         __syncthreads();
     }
     // backward: the update buffer is free; each level first gathers x_{R_s}
@@ -194,57 +263,10 @@ __device__ __forceinline__ void solve_P(const SimDev &S, auto b, auto T, auto Y,
         const int q0 = G(S.lvl_gat_ptr)[l], q1 = G(S.lvl_gat_ptr)[l + 1];
         if (c1 == c0 && q1 == q0 && l > 0) continue;    // root supernodes only: solved in the forward sweep
         if (q1 > q0) {
-            for (int q = q0 + threadIdx.x; q < q1; q += (int)blockDim.x) {
-                const v2i e = ((GLOBAL const v2i *)S.bgat)[q];   // GatherItem {u, x3}
-                if (e.y >= 0) {
-                    U[e.x] = x[e.y]; U[e.x + 1] = x[e.y + 1]; U[e.x + 2] = x[e.y + 2];
-                } else {                                         // a root's row: x is still in Y
-                    const int y3 = -e.y - 1;
-                    U[e.x] = Y[y3]; U[e.x + 1] = Y[y3 + 1]; U[e.x + 2] = Y[y3 + 2];
-                }
-            }
+            bwd_gather((GLOBAL const v2i *)S.bgat, q0, q1, threadIdx.x, blockDim.x, x, Y, U);
             __syncthreads();
         }
-        for (int t = c0 + team; t < c1; t += nteams) {
-            v4i nxt = {0, 0, 0, 0}, nxt2 = {0, 0, 0, 0};
-            if (t + nteams < c1) { nxt = bit[2 * (t + nteams)]; nxt2 = bit[2 * (t + nteams) + 1]; }
-            const auto Gb = gt2 + (cur.x >> 1);
-            const int st2 = cur2.x >> 1;
-            const int n1 = cur.y & 0xffff, n = n1 + (cur.y >> 16), yb = cur.z;
-            const auto Yb = Y + yb;
-            const int ub = cur.w - 3 * n1;               // U[ub + 3k] is row k >= n1
-            double a0 = 0, a1 = 0, a2 = 0, b0 = 0, b1 = 0, b2 = 0;
-            for (int k0 = lane; k0 < n; k0 += kSolveBatch * tl) {
-                v2d g[kSolveBatch];
-#pragma unroll
-                for (int j = 0; j < kSolveBatch; ++j) {
-                    const int k = k0 + j * tl;
-                    g[j] = k < n ? Gb[k * st2] : v2d{0.0, 0.0};
-                }
-#pragma unroll
-                for (int j = 0; j < kSolveBatch; ++j) {
-                    const int k = k0 + j * tl;
-                    if (k < n1) {
-                        const double w0 = Yb[3 * k], w1 = Yb[3 * k + 1], w2 = Yb[3 * k + 2];
-                        a0 += g[j].x * w0; a1 += g[j].x * w1; a2 += g[j].x * w2;
-                        b0 += g[j].y * w0; b1 += g[j].y * w1; b2 += g[j].y * w2;
-                    } else if (k < n) {
-                        const int o = ub + 3 * k;
-                        const double w0 = U[o], w1 = U[o + 1], w2 = U[o + 2];
-                        a0 -= g[j].x * w0; a1 -= g[j].x * w1; a2 -= g[j].x * w2;
-                        b0 -= g[j].y * w0; b1 -= g[j].y * w1; b2 -= g[j].y * w2;
-                    }
-                }
-            }
-            a0 = team_sum(a0, tl); a1 = team_sum(a1, tl); a2 = team_sum(a2, tl);
-            b0 = team_sum(b0, tl); b1 = team_sum(b1, tl); b2 = team_sum(b2, tl);
-            if (lane == 0) {
-                x[yb] = a0; x[yb + 1] = a1; x[yb + 2] = a2;
-                if (cur2.y) { x[yb + 3] = b0; x[yb + 4] = b1; x[yb + 5] = b2; }
-            }
-            cur = nxt;
-            cur2 = nxt2;
-        }
+        bwd_products(bit, gt2, c0 + team, c1, nteams, tl, lane, cur, cur2, Y, x, U);
         if (l == 0)                                      // the roots' x, left in Y by the forward sweep
             for (int q = threadIdx.x; q < S.n_root_rows; q += (int)blockDim.x) {
                 const int i3 = G(S.root_rows)[q];
@@ -521,16 +543,16 @@ __device__ __forceinline__ void local_projection(const SimDev &S, auto XN, auto 
     }
 }
 
-// Right-hand side of the global step (eqn pd_velocity_with_contact):
-// out_i = b0_i + h sum_c a_ci w_c p_c + f_i.  Springs are projected here,
+// Right-hand side of the global step (eqn pd_velocity_with_contact), nodes
+// [i0, i1): out_i = b0_i + h sum_c a_ci w_c p_c + f_i.  Springs are projected here,
 // node-centred (each spring on both of its nodes, with the same arithmetic, so
 // the two contributions are exact negatives); curved-bending projections come
 // from wp.
 template <bool MIXED>
-__device__ __forceinline__ void spring_rhs(const SimDev &S, auto XN, auto V, auto out) {
+__device__ __forceinline__ void spring_rhs(const SimDev &S, auto XN, auto V, auto out, int i0, int i1) {
     const double h = S.h;
     const bool bend = S.nca_bend > 0;
-    for (int i = threadIdx.x; i < S.m; i += (int)blockDim.x) {
+    for (int i = i0 + (int)threadIdx.x; i < i1; i += (int)blockDim.x) {
         double r0 = 0, r1 = 0, r2 = 0;
         const int p0 = G(S.sinc_ptr)[i], p1 = G(S.sinc_ptr)[i + 1];
         // q = (x_i + h v_i) - (x_j + h v_j) = sign (x_a - x_b) exactly, so the
@@ -639,6 +661,138 @@ __device__ void fwd_prefetch(const SimDev &S, int j, int H) {
     if (sink == 0x9e3779b97f4a7c15ull) G(S.red)[62] = 1.0;         // keeps the loads
 }
 
+// Step prologue of node i: predictor, detection on y, constant right-hand
+// side, initial guess and impulses; the external force f_ext = M g + fs F
+// enters all four.  KX: also copy x_n to XN (positions placed in LDS).
+template <bool km, bool KX>
+__device__ __forceinline__ void fwd_prologue_node(const SimDev &S, int i, double fs, double t1, bool first,
+                                                  GLOBAL double *xrec, GLOBAL double *vrec, auto A, auto XN) {
+    const double h = S.h;
+    const double xi[3] = {G(S.x)[3 * i], G(S.x)[3 * i + 1], G(S.x)[3 * i + 2]};
+    const double vi[3] = {G(S.v)[3 * i], G(S.v)[3 * i + 1], G(S.v)[3 * i + 2]};
+    if (first) {
+        for (int d = 0; d < 3; ++d) { xrec[3 * i + d] = xi[d]; vrec[3 * i + d] = vi[d]; }
+    }
+    const double mi = G(S.mass)[i];
+    double fe[3] = {0.0, 0.0, 0.0}, ae[3];           // external force, M^{-1} f_ext
+    if (S.fext != nullptr)
+        for (int d = 0; d < 3; ++d) fe[d] = fs * G(S.fext)[3 * i + d];
+    for (int d = 0; d < 3; ++d) ae[d] = S.g[d] + fe[d] / mi;
+    double y[3];
+    {
+#pragma clang fp contract(off)                       // (x + h v) + (h h) a, unfused: see mesh_frame
+        for (int d = 0; d < 3; ++d) y[d] = xi[d] + h * vi[d] + h * h * ae[d];
+    }
+    double best = 0.0;
+    int ob = -1;
+    for (int o = 0; o < S.n_obst; ++o) {
+        const double phi = signed_distance<km>(S.obst[o], y);
+        if (ob < 0 || phi < best) { best = phi; ob = o; }
+    }
+    const bool contact = ob >= 0 && best <= 0.0;
+    G(S.mode)[i] = contact ? TAKEOFF : FREE;
+    G(S.cobst)[i] = contact ? (int8_t)ob : (int8_t)-1;
+    if constexpr (km) {
+        if (contact && S.obst[ob].type == 2) {     // the step's frame at x_n, scanned once
+            double nr[3], ph;
+            contact_frame<true>(S, ob, xi, nr, ph);
+            for (int d = 0; d < 3; ++d) G(S.cfr)[8 * i + d] = nr[d];
+            G(S.cfr)[8 * i + 3] = ph;
+        }
+    }
+    double kx0 = 0, kx1 = 0, kx2 = 0;
+    for (int p = G(S.ks_ptr)[i]; p < G(S.ks_ptr)[i + 1]; ++p) {
+        const int j = G(S.ks_col)[p];
+        const double kv = G(S.ks_val)[p];
+        kx0 += kv * G(S.x)[3 * j];
+        kx1 += kv * G(S.x)[3 * j + 1];
+        kx2 += kv * G(S.x)[3 * j + 2];
+    }
+    double b[3] = {mi * vi[0] + h * (mi * S.g[0] + fe[0]) - h * kx0,
+                   mi * vi[1] + h * (mi * S.g[1] + fe[1]) - h * kx1,
+                   mi * vi[2] + h * (mi * S.g[2] + fe[2]) - h * kx2};
+    const int as = G(S.att_of)[i];
+    if (as >= 0) {
+        double tg[3];
+        attach_target(S, G(S.att_rest) + 3 * as, t1, tg);
+        for (int d = 0; d < 3; ++d) b[d] += h * S.w_att * tg[d];
+    }
+    // impulses: zero, or (warm start) the previous step's on the nodes of
+    // this step's contact set (zero where the node was not in contact)
+    const bool keep = S.warm_start && contact;
+    for (int d = 0; d < 3; ++d) {
+        G(S.b0)[3 * i + d] = b[d];
+        if (!keep) G(S.f)[3 * i + d] = 0.0;
+        A[3 * i + d] = vi[d] + h * ae[d];
+    }
+    if constexpr (KX)
+        for (int d = 0; d < 3; ++d) XN[3 * i + d] = xi[d];
+}
+
+// Contact update of node i after a global solve (its new velocity in B), and
+// the node's share of the iteration's change max(|dv|, |df| / m).
+template <bool km>
+__device__ __forceinline__ void fwd_contact_node(const SimDev &S, int i, auto B, auto XN, auto Vprev, bool converge,
+                                                 double &dmax) {
+    const double h = S.h;
+    if (G(S.mode)[i] != FREE) {
+        const double mi = G(S.mass)[i];
+        const double ub[3] = {B[3 * i] - G(S.f)[3 * i] / mi, B[3 * i + 1] - G(S.f)[3 * i + 1] / mi,
+                              B[3 * i + 2] - G(S.f)[3 * i + 2] / mi};
+        double nrm[3], phi, vv[3], ff[3];
+        bool cached = false;                            // mesh: the frame of the step's start
+        if constexpr (km) cached = S.obst[G(S.cobst)[i]].type == 2;
+        if (cached) {
+            for (int d = 0; d < 3; ++d) nrm[d] = G(S.cfr)[8 * i + d];
+            phi = G(S.cfr)[8 * i + 3];
+        } else {
+            contact_frame<false>(S, G(S.cobst)[i], XN + 3 * i, nrm, phi);
+        }
+        G(S.mode)[i] = signorini_coulomb(ub, nrm, phi, S.obst[G(S.cobst)[i]].mu, h, mi, vv, ff);
+        for (int d = 0; d < 3; ++d) {
+            // the iterate is (v, f): a node held by the contact update
+            // keeps its velocity while its impulse may still change
+            if (converge) dmax = fmax(dmax, fabs(ff[d] - G(S.f)[3 * i + d]) / mi);
+            B[3 * i + d] = vv[d];
+            G(S.f)[3 * i + d] = ff[d];
+            G(S.ubar)[3 * i + d] = ub[d];
+        }
+    }
+    if (converge)
+        for (int d = 0; d < 3; ++d) dmax = fmax(dmax, fabs(B[3 * i + d] - Vprev[3 * i + d]));
+}
+
+// Advance and record node i (the converged iterate is in A); counts its mode.
+__device__ __forceinline__ void fwd_record_node(const SimDev &S, int i, int slot, auto A, auto XN, GLOBAL double *xn,
+                                                GLOBAL double *vn, GLOBAL double *ubrec, int *cnt) {
+    const int m = S.m;
+    const double h = S.h;
+    for (int d = 0; d < 3; ++d) {
+        const double vv = A[3 * i + d];
+        const double xx = XN[3 * i + d] + h * vv;
+        G(S.x)[3 * i + d] = xx;
+        G(S.v)[3 * i + d] = vv;
+        xn[3 * i + d] = xx;
+        vn[3 * i + d] = vv;
+        ubrec[3 * i + d] = G(S.ubar)[3 * i + d];
+    }
+    const uint8_t md = G(S.mode)[i];
+    if (md != FREE) ++cnt[md - 1];
+    G(S.rec_mode)[(int64_t)slot * m + i] = md;
+    G(S.rec_obst)[(int64_t)slot * m + i] = G(S.cobst)[i];
+}
+
+// per-step record of step n: PD iterations and mode counts
+__device__ __forceinline__ void put_step_info(const SimDev &S, int n, int k, int64_t takeoff, int64_t stick,
+                                              int64_t slip) {
+    if (S.step_info != nullptr) {
+        G(S.step_info)[4 * n] = k;
+        G(S.step_info)[4 * n + 1] = (int32_t)takeoff;
+        G(S.step_info)[4 * n + 2] = (int32_t)stick;
+        G(S.step_info)[4 * n + 3] = (int32_t)slip;
+    }
+}
+
 // Forward steps [step_begin, step_end) of one handle per workgroup.  The PD
 // iterate ping-pongs between two vectors A and B (LDS when they fit): B gets
 // the right-hand side, the forward solve writes into A, the backward solve
@@ -678,69 +832,8 @@ __global__ __launch_bounds__(kBlock) void k_forward(const SimDev *__restrict__ s
         auto xrec = G(S.rec_x) + (int64_t)slot * 3 * m;
         auto vrec = G(S.rec_v) + (int64_t)slot * 3 * m;
         const double fs = S.fext == nullptr ? 0.0 : (S.fscale == nullptr ? 1.0 : G(S.fscale)[n]);
-        // predictor, detection on y, constant right-hand side, initial guess; the
-        // external force f_ext = M g + fs F enters all four
-        for (int i = threadIdx.x; i < m; i += (int)blockDim.x) {
-            const double xi[3] = {G(S.x)[3 * i], G(S.x)[3 * i + 1], G(S.x)[3 * i + 2]};
-            const double vi[3] = {G(S.v)[3 * i], G(S.v)[3 * i + 1], G(S.v)[3 * i + 2]};
-            if (n == S.step_begin) {
-                for (int d = 0; d < 3; ++d) { xrec[3 * i + d] = xi[d]; vrec[3 * i + d] = vi[d]; }
-            }
-            const double mi = G(S.mass)[i];
-            double fe[3] = {0.0, 0.0, 0.0}, ae[3];           // external force, M^{-1} f_ext
-            if (S.fext != nullptr)
-                for (int d = 0; d < 3; ++d) fe[d] = fs * G(S.fext)[3 * i + d];
-            for (int d = 0; d < 3; ++d) ae[d] = S.g[d] + fe[d] / mi;
-            double y[3];
-            {
-#pragma clang fp contract(off)                           // (x + h v) + (h h) a, unfused: see mesh_frame
-                for (int d = 0; d < 3; ++d) y[d] = xi[d] + h * vi[d] + h * h * ae[d];
-            }
-            double best = 0.0;
-            int ob = -1;
-            for (int o = 0; o < S.n_obst; ++o) {
-                const double phi = signed_distance<km>(S.obst[o], y);
-                if (ob < 0 || phi < best) { best = phi; ob = o; }
-            }
-            const bool contact = ob >= 0 && best <= 0.0;
-            G(S.mode)[i] = contact ? TAKEOFF : FREE;
-            G(S.cobst)[i] = contact ? (int8_t)ob : (int8_t)-1;
-            if constexpr (km) {
-                if (contact && S.obst[ob].type == 2) {     // the step's frame at x_n, scanned once
-                    double nr[3], ph;
-                    contact_frame<true>(S, ob, xi, nr, ph);
-                    for (int d = 0; d < 3; ++d) G(S.cfr)[8 * i + d] = nr[d];
-                    G(S.cfr)[8 * i + 3] = ph;
-                }
-            }
-            double kx0 = 0, kx1 = 0, kx2 = 0;
-            for (int p = G(S.ks_ptr)[i]; p < G(S.ks_ptr)[i + 1]; ++p) {
-                const int j = G(S.ks_col)[p];
-                const double kv = G(S.ks_val)[p];
-                kx0 += kv * G(S.x)[3 * j];
-                kx1 += kv * G(S.x)[3 * j + 1];
-                kx2 += kv * G(S.x)[3 * j + 2];
-            }
-            double b[3] = {mi * vi[0] + h * (mi * S.g[0] + fe[0]) - h * kx0,
-                           mi * vi[1] + h * (mi * S.g[1] + fe[1]) - h * kx1,
-                           mi * vi[2] + h * (mi * S.g[2] + fe[2]) - h * kx2};
-            const int as = G(S.att_of)[i];
-            if (as >= 0) {
-                double tg[3];
-                attach_target(S, G(S.att_rest) + 3 * as, t1, tg);
-                for (int d = 0; d < 3; ++d) b[d] += h * S.w_att * tg[d];
-            }
-            // impulses: zero, or (warm start) the previous step's on the nodes of
-            // this step's contact set (zero where the node was not in contact)
-            const bool keep = S.warm_start && contact;
-            for (int d = 0; d < 3; ++d) {
-                G(S.b0)[3 * i + d] = b[d];
-                if (!keep) G(S.f)[3 * i + d] = 0.0;
-                A[3 * i + d] = vi[d] + h * ae[d];
-            }
-            if constexpr ((FL & kLdsPositions) != 0)
-                for (int d = 0; d < 3; ++d) XN[3 * i + d] = xi[d];
-        }
+        for (int i = threadIdx.x; i < m; i += (int)blockDim.x)
+            fwd_prologue_node<km, kx>(S, i, fs, t1, n == S.step_begin, xrec, vrec, A, XN);
         __syncthreads();
         int k = 0;
         while (true) {
@@ -748,40 +841,14 @@ __global__ __launch_bounds__(kBlock) void k_forward(const SimDev *__restrict__ s
                 local_projection<MIXED>(S, XN, A, S.nca - S.nca_bend, S.nca);
                 __syncthreads();
             }
-            spring_rhs<MIXED>(S, XN, A, B);
+            spring_rhs<MIXED>(S, XN, A, B, 0, m);
             if (converge)
                 for (int i = threadIdx.x; i < 3 * m; i += (int)blockDim.x) Vprev[i] = A[i];
             __syncthreads();
             solve_P(S, B, B, A, B, U, it_run * 2 * S.n_levels);
             ++it_run;
             double dmax = 0.0;
-            for (int i = threadIdx.x; i < m; i += (int)blockDim.x) {
-                if (G(S.mode)[i] != FREE) {
-                    const double mi = G(S.mass)[i];
-                    const double ub[3] = {B[3 * i] - G(S.f)[3 * i] / mi, B[3 * i + 1] - G(S.f)[3 * i + 1] / mi,
-                                          B[3 * i + 2] - G(S.f)[3 * i + 2] / mi};
-                    double nrm[3], phi, vv[3], ff[3];
-                    bool cached = false;                            // mesh: the frame of the step's start
-                    if constexpr (km) cached = S.obst[G(S.cobst)[i]].type == 2;
-                    if (cached) {
-                        for (int d = 0; d < 3; ++d) nrm[d] = G(S.cfr)[8 * i + d];
-                        phi = G(S.cfr)[8 * i + 3];
-                    } else {
-                        contact_frame<false>(S, G(S.cobst)[i], XN + 3 * i, nrm, phi);
-                    }
-                    G(S.mode)[i] = signorini_coulomb(ub, nrm, phi, S.obst[G(S.cobst)[i]].mu, h, mi, vv, ff);
-                    for (int d = 0; d < 3; ++d) {
-                        // the iterate is (v, f): a node held by the contact update
-                        // keeps its velocity while its impulse may still change
-                        if (converge) dmax = fmax(dmax, fabs(ff[d] - G(S.f)[3 * i + d]) / mi);
-                        B[3 * i + d] = vv[d];
-                        G(S.f)[3 * i + d] = ff[d];
-                        G(S.ubar)[3 * i + d] = ub[d];
-                    }
-                }
-                if (converge)
-                    for (int d = 0; d < 3; ++d) dmax = fmax(dmax, fabs(B[3 * i + d] - Vprev[3 * i + d]));
-            }
+            for (int i = threadIdx.x; i < m; i += (int)blockDim.x) fwd_contact_node<km>(S, i, B, XN, Vprev, converge, dmax);
             ++k;
             auto tmp = A; A = B; B = tmp;
             if (converge) {
@@ -798,36 +865,233 @@ __global__ __launch_bounds__(kBlock) void k_forward(const SimDev *__restrict__ s
         auto vn = vrec + 3 * m;
         auto ubrec = G(S.rec_ubar) + (int64_t)slot * 3 * m;
         int cnt[3] = {0, 0, 0};                          // take-off, stick, slip nodes of this thread
-        for (int i = threadIdx.x; i < m; i += (int)blockDim.x) {
-            for (int d = 0; d < 3; ++d) {
-                const double vv = A[3 * i + d];
-                const double xx = XN[3 * i + d] + h * vv;
-                G(S.x)[3 * i + d] = xx;
-                G(S.v)[3 * i + d] = vv;
-                xn[3 * i + d] = xx;
-                vn[3 * i + d] = vv;
-                ubrec[3 * i + d] = G(S.ubar)[3 * i + d];
-            }
-            const uint8_t md = G(S.mode)[i];
-            if (md != FREE) ++cnt[md - 1];
-            G(S.rec_mode)[(int64_t)slot * m + i] = md;
-            G(S.rec_obst)[(int64_t)slot * m + i] = G(S.cobst)[i];
-        }
+        for (int i = threadIdx.x; i < m; i += (int)blockDim.x) fwd_record_node(S, i, slot, A, XN, xn, vn, ubrec, cnt);
         // per-step record: iterations and mode counts (sums of small integers, exact in float64)
         const double packed = (double)cnt[0] + 1048576.0 * (double)cnt[1];   // counts < 2^20 per handle
         const double tot01 = block_sum(packed, red);
         const double tot2 = block_sum((double)cnt[2], red);
-        if (threadIdx.x == 0 && S.step_info != nullptr) {
+        if (threadIdx.x == 0) {
             const int64_t t01 = (int64_t)tot01;
-            G(S.step_info)[4 * n] = k;
-            G(S.step_info)[4 * n + 1] = (int32_t)(t01 & 1048575);
-            G(S.step_info)[4 * n + 2] = (int32_t)(t01 >> 20);
-            G(S.step_info)[4 * n + 3] = (int32_t)tot2;
+            put_step_info(S, n, k, t01 & 1048575, t01 >> 20, (int64_t)tot2);
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) G(S.counters)[0] += iters_total;
     announce(S.fwd_pos, S.fwd_epoch, kPosMask);          // releases the prefetch workgroups
+}
+
+// ------------------------------------------------------------------ multi-workgroup forward
+
+// A right-hand-side vector held from column c0 on (the root's gathered rows in
+// LDS), indexed with the global offsets the work items carry.
+struct Shifted {
+    double *p;
+    int off;
+    __device__ double &operator[](int i) const { return p[i - off]; }
+    __device__ Shifted operator+(int k) const { return Shifted{p, off - k}; }
+};
+
+// Barrier of the S.mw workgroups of a multi-workgroup forward launch (placed
+// on one XCD).  An agent-scope release before arriving and an acquire after
+// leaving make every workgroup's global writes visible to the others.  Thread
+// 0 waits at most S.mw_spin ticks of the 100 MHz wall clock; then, or when
+// another workgroup has already given up, it raises the failure flag, and
+// every thread of the workgroup gets false (the kernel then returns and the
+// host reports the failure).  gen: thread 0's count of barriers passed.
+__device__ __forceinline__ bool mw_barrier(const SimDev &S, uint32_t &gen, int &ok_lds) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t *cnt = S.mw_sync, *gn = S.mw_sync + 1, *fail = S.mw_sync + 2;
+        int ok = 1;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (__hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+            ok = 0;
+        } else {
+            const uint32_t g = gen;
+            const uint32_t arrived = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+            if (arrived == (uint32_t)S.mw) {
+                __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(gn, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                const uint64_t t0 = wall_clock64();
+                while (__hip_atomic_load(gn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                    if (__hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                        wall_clock64() - t0 > (uint64_t)S.mw_spin) {
+                        ok = 0;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+            gen = g + 1u;
+        }
+        if (!ok) __hip_atomic_store(fail, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        ok_lds = ok;
+    }
+    __syncthreads();
+    return ok_lds != 0;
+}
+
+// Forward steps [step_begin, step_end) of one handle on S.mw workgroups of one
+// XCD (workgroups 8 w; the others of the grid return at once).  Workgroup w
+// owns whole subtrees of the elimination tree below the root supernode and a
+// slice of the root's columns (node ranges S.mw_nodes): it does their step
+// prologue, right-hand side, both triangular solves and contact updates; the
+// root's forward product (its stored inverse) is split over all workgroups,
+// each of which first gathers the root's whole right-hand side into LDS.
+// Barriers per PD iteration: after the subtrees' forward solves, after the
+// root product, after the contact updates (and after the bending projections
+// when there are curved bending constraints).  Every node, row and item is
+// computed with the arithmetic of k_forward (same items, team sizes and
+// summation orders), so results are bitwise those of the single-workgroup
+// kernel.  Vectors live in HBM and are shared through the XCD's L2.
+template <bool MIXED, bool km>
+__global__ __launch_bounds__(kBlock) void k_forward_mw(const SimDev *__restrict__ sims) {
+    if ((int)blockIdx.x % kXcds != 0) return;
+    const SimDev &S = sims[0];
+    const int W = S.mw, w = (int)blockIdx.x / kXcds;
+    if (w >= W || (S.mw_absent && w == W - 1)) return;
+    __shared__ double red[kBlock / 64];
+    __shared__ double troot[3 * kMwRootMax];
+    __shared__ int ok_lds;
+    uint32_t gen = 0;
+    const int m = S.m, L = S.n_levels, Q = W * (L - 1);
+    const double h = S.h;
+    const bool converge = S.fwd_tol > 0;
+    auto A = G(S.vk);
+    auto B = G(S.rhs);
+    auto U = G(S.ubuf);
+    auto XN = G(S.x);
+    auto Y = G(S.ysol);
+    auto Vprev = G(S.vk1);
+    const auto gv2 = (GLOBAL const v2d *)S.gval;
+    const auto gt2 = (GLOBAL const v2d *)S.gvalt;
+    auto part = (GLOBAL double *)(S.mw_sync + 4);         // partials: W maxima, then 3 W counts
+    if (threadIdx.x == 0) gen = __hip_atomic_load(S.mw_sync + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int ra[kMwRanges], rb[kMwRanges];
+    for (int r = 0; r < kMwRanges; ++r) {
+        ra[r] = G(S.mw_nodes)[2 * (w * kMwRanges + r)];
+        rb[r] = G(S.mw_nodes)[2 * (w * kMwRanges + r) + 1];
+    }
+    auto own = [&](auto &&f) {
+        for (int r = 0; r < kMwRanges; ++r)
+            for (int i = ra[r] + (int)threadIdx.x; i < rb[r]; i += (int)blockDim.x) f(i);
+    };
+    const int rs0 = S.mw_root_c0, rn = S.n_root_rows;
+    const int ys0 = rs0 + (int)((int64_t)rn * w / W), ys1 = rs0 + (int)((int64_t)rn * (w + 1) / W);
+    int64_t iters_total = 0;
+    for (int n = S.step_begin; n < S.step_end; ++n) {
+        const int slot = S.rec_ring ? 0 : n - S.rec_step0;
+        const double t1 = (n + 1) * h;
+        auto xrec = G(S.rec_x) + (int64_t)slot * 3 * m;
+        auto vrec = G(S.rec_v) + (int64_t)slot * 3 * m;
+        const double fs = S.fext == nullptr ? 0.0 : (S.fscale == nullptr ? 1.0 : G(S.fscale)[n]);
+        own([&](int i) { fwd_prologue_node<km, false>(S, i, fs, t1, n == S.step_begin, xrec, vrec, A, XN); });
+        if (!mw_barrier(S, gen, ok_lds)) return;
+        int k = 0;
+        while (true) {
+            if (S.nca_bend > 0) {                          // curved bending: constraints split by workgroup
+                const int c0 = S.nca - S.nca_bend, nb = S.nca_bend;
+                local_projection<MIXED>(S, XN, A, c0 + (int)((int64_t)nb * w / W), c0 + (int)((int64_t)nb * (w + 1) / W));
+                if (!mw_barrier(S, gen, ok_lds)) return;
+            }
+            for (int r = 0; r < kMwRanges; ++r)
+                if (rb[r] > ra[r]) spring_rhs<MIXED>(S, XN, A, B, ra[r], rb[r]);
+            if (converge) own([&](int i) { for (int d = 0; d < 3; ++d) Vprev[3 * i + d] = A[3 * i + d]; });
+            __syncthreads();
+            // forward solve of this workgroup's subtrees, level by level
+            for (int l = 0; l < L - 1; ++l) {
+                const int q = w * (L - 1) + l;
+                const int tl = G(S.lvl_team)[2 * l];
+                const int team = threadIdx.x / tl, lane = threadIdx.x % tl, nteams = (int)blockDim.x / tl;
+                const int i0 = G(S.mw_ptr)[(Q + 1) + q], i1 = G(S.mw_ptr)[(Q + 1) + q + 1];
+                const auto fit = (GLOBAL const v4i *)S.mw_fitems;
+                v4i cur = {0, 0, 0, 0}, cur2 = {0, 0, 0, 0};
+                if (i0 + team < i1) { cur = fit[2 * (i0 + team)]; cur2 = fit[2 * (i0 + team) + 1]; }
+                gather_rows(G(S.mw_rows), G(S.upd_off), G(S.mw_ptr)[q], G(S.mw_ptr)[q + 1], B, B, U);
+                __syncthreads();
+                fwd_products(fit, gv2, i0 + team, i1, nteams, tl, lane, cur, cur2, B, Y, U);
+                __syncthreads();
+            }
+            if (!mw_barrier(S, gen, ok_lds)) return;       // every subtree's updates of the root rows are in U
+            {   // the root: its right-hand side gathered here, this workgroup's share of its product
+                const int l = L - 1;
+                const int tl = G(S.lvl_team)[2 * l];
+                const int team = threadIdx.x / tl, lane = threadIdx.x % tl, nteams = (int)blockDim.x / tl;
+                const int i0 = G(S.lvl_items_ptr)[l], i1 = G(S.lvl_items_ptr)[l + 1];
+                const auto fit = (GLOBAL const v4i *)S.fitems;
+                const int t0 = i0 + w * nteams + team;
+                v4i cur = {0, 0, 0, 0}, cur2 = {0, 0, 0, 0};
+                if (t0 < i1) { cur = fit[2 * t0]; cur2 = fit[2 * t0 + 1]; }
+                const Shifted T{troot, 3 * rs0};
+                gather_rows(G(S.rows), G(S.upd_off), G(S.lvl_rows_ptr)[l], G(S.lvl_rows_ptr)[l + 1], B, T, U);
+                __syncthreads();
+                fwd_products(fit, gv2, t0, i1, W * nteams, tl, lane, cur, cur2, T, Y, U);
+            }
+            if (!mw_barrier(S, gen, ok_lds)) return;       // the root's x (in Y) is complete
+            // backward solve of this workgroup's subtrees, top level first
+            for (int l = L - 2; l >= 0; --l) {
+                const int q = w * (L - 1) + l;
+                const int tl = G(S.lvl_team)[2 * l + 1];
+                const int team = threadIdx.x / tl, lane = threadIdx.x % tl, nteams = (int)blockDim.x / tl;
+                const int c0 = G(S.mw_ptr)[2 * (Q + 1) + q], c1 = G(S.mw_ptr)[2 * (Q + 1) + q + 1];
+                const int q0 = G(S.mw_ptr)[3 * (Q + 1) + q], q1 = G(S.mw_ptr)[3 * (Q + 1) + q + 1];
+                const auto bit = (GLOBAL const v4i *)S.mw_bitems;
+                v4i cur = {0, 0, 0, 0}, cur2 = {0, 0, 0, 0};
+                if (c0 + team < c1) { cur = bit[2 * (c0 + team)]; cur2 = bit[2 * (c0 + team) + 1]; }
+                if (q1 > q0) {
+                    bwd_gather((GLOBAL const v2i *)S.mw_bgat, q0, q1, threadIdx.x, blockDim.x, B, Y, U);
+                    __syncthreads();
+                }
+                bwd_products(bit, gt2, c0 + team, c1, nteams, tl, lane, cur, cur2, Y, B, U);
+                __syncthreads();
+            }
+            for (int i = ys0 + (int)threadIdx.x; i < ys1; i += (int)blockDim.x)   // this slice of the root: x from Y
+                for (int d = 0; d < 3; ++d) B[3 * i + d] = Y[3 * i + d];
+            __syncthreads();
+            double dmax = 0.0;
+            own([&](int i) { fwd_contact_node<km>(S, i, B, XN, Vprev, converge, dmax); });
+            ++k;
+            auto tmp = A; A = B; B = tmp;
+            if (converge) {
+                dmax = block_max(dmax, red);
+                if (threadIdx.x == 0) part[w] = dmax;
+                if (!mw_barrier(S, gen, ok_lds)) return;
+                double mx = 0.0;
+                for (int q = 0; q < W; ++q) mx = fmax(mx, part[q]);
+                if (!(mx > S.fwd_tol) || k >= S.fwd_max_iters) break;
+            } else {
+                if (!mw_barrier(S, gen, ok_lds)) return;
+                if (k >= S.K) break;
+            }
+        }
+        iters_total += k;
+        auto xn = xrec + 3 * m;
+        auto vn = vrec + 3 * m;
+        auto ubrec = G(S.rec_ubar) + (int64_t)slot * 3 * m;
+        int cnt[3] = {0, 0, 0};
+        own([&](int i) { fwd_record_node(S, i, slot, A, XN, xn, vn, ubrec, cnt); });
+        const double packed = (double)cnt[0] + 1048576.0 * (double)cnt[1];
+        const double tot01 = block_sum(packed, red);
+        const double tot2 = block_sum((double)cnt[2], red);
+        if (threadIdx.x == 0) {
+            part[W + 2 * w] = tot01;
+            part[W + 2 * w + 1] = tot2;
+        }
+        if (!mw_barrier(S, gen, ok_lds)) return;           // also: x_{n+1} of every node before the next prologue
+        if (w == 0 && threadIdx.x == 0) {
+            int64_t a = 0, b = 0, c = 0;
+            for (int q = 0; q < W; ++q) {
+                const int64_t t01 = (int64_t)part[W + 2 * q];
+                a += t01 & 1048575;
+                b += t01 >> 20;
+                c += (int64_t)part[W + 2 * q + 1];
+            }
+            put_step_info(S, n, k, a, b, c);
+        }
+    }
+    if (w == 0 && threadIdx.x == 0) G(S.counters)[0] += iters_total;
 }
 
 // ------------------------------------------------------------------ adjoint
@@ -2097,6 +2361,15 @@ hipError_t launch_backward(const SimDev *d_sims, int n, bool mixed, size_t lds, 
     using F = void (*)(const SimDev *, int, size_t, int, hipStream_t);
     static const F tab[2][16] = {{DC_V16(bwd_one, false)}, {DC_V16(bwd_one, true)}};
     tab[mixed ? 1 : 0][(flags & 7) | (mesh ? kMeshObst : 0)](d_sims, n, lds, helpers, st);
+    return hipGetLastError();
+}
+
+// multi-workgroup forward of one handle (d: its descriptor), grid 8 W
+hipError_t launch_forward_mw(const SimDev *d, int W, bool mixed, bool mesh, hipStream_t st) {
+    if (W < 2 || W > kMwMax) return hipErrorInvalidValue;
+    auto k = mixed ? (mesh ? k_forward_mw<true, true> : k_forward_mw<true, false>)
+                   : (mesh ? k_forward_mw<false, true> : k_forward_mw<false, false>);
+    hipLaunchKernelGGL(k, dim3(kXcds * W), dim3(kBlock), 0, st, d);
     return hipGetLastError();
 }
 

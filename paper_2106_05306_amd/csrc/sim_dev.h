@@ -81,6 +81,12 @@ constexpr int kAdjRows = 128;       // rows per item: two per lane, read with on
 constexpr int kAdjWaves = kBlockAdj / 64;
 constexpr int kAdjHelpers = 8;      // prefetching workgroups of a single-handle direct adjoint launch
 constexpr int kXcds = 8;            // workgroup i of a launch runs on XCD i mod 8
+// multi-workgroup forward of one handle: at most kMwMax workgroups (all on one
+// XCD), a root supernode of at most kMwRootMax columns, kMwRanges node ranges
+// per workgroup; its barrier block: counter, generation, failure flag (16
+// bytes), then one partial maximum and three partial counts per workgroup
+constexpr int kMwMax = 16, kMwRootMax = 512, kMwRanges = 6;
+constexpr int kMwSyncDoubles = 2 + 4 * kMwMax;
 constexpr size_t kNoallocScratchBytes = size_t(16) << 20;   // device scratch of the allocation-free forward
 constexpr int kMaxDevices = 64;
 struct LuUpd {              // supernode s is updated by descendant d: rows [i0, i1) of R_d lie in s
@@ -259,6 +265,23 @@ struct SimDev {
     int64_t adj_epoch;
     const int32_t *adj_pfptr;         // [3 levels + 1] into adj_pf, by phase id
     const int64_t *adj_pf;            // [2 per range] offset and length (doubles) of a block in a step factor
+
+    // multi-workgroup forward (one handle on mw workgroups of one XCD; 0: not
+    // available): workgroup w solves whole subtrees below the root supernode
+    // alone and shares the root (its columns mw_root_c0 ..)
+    int mw;
+    int mw_root_c0;
+    const int32_t *mw_ptr;            // [4 (mw (levels - 1) + 1)]: per (workgroup, level below the
+                                      //   root) ranges into mw_rows, mw_fitems, mw_bitems, mw_bgat
+    const RowItem *mw_rows;
+    const FwdItem *mw_fitems;
+    const BwdItem *mw_bitems;
+    const GatherItem *mw_bgat;
+    const int32_t *mw_nodes;          // [mw][kMwRanges][2] node ranges [a, b) of each workgroup
+    uint32_t *mw_sync;                // barrier block (kMwSyncDoubles doubles)
+    int64_t mw_spin;                  // wall-clock ticks (100 MHz) a barrier waits before giving up
+    int mw_absent;                    // failure-handling tests only: the last workgroup returns at
+                                      //   once, so every barrier wait ends at its limit
 
     // run control for one launch
     int step_begin, step_end;         // forward: steps [begin, end); backward: reverse

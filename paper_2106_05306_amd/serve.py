@@ -85,12 +85,29 @@ def step_cost_ms(m: int, backward: bool) -> float:
     return 0.2 + 0.35 * m / 1000.0 if backward else 20 * (0.06 + 0.04 * m / 1000.0)
 
 
+def _material(scene):
+    """What a cached handle's factor and friction depend on besides the topology."""
+    return (np.asarray(scene.edge_stiffness, np.float64).tobytes(), float(scene.bend_weight),
+            np.asarray(scene.region_scale if scene.region_scale is not None else [], np.float64).tobytes(),
+            tuple(float(o.mu) for o in scene.obstacles))
+
+
 class _Handle:
-    def __init__(self, sim: Sim, key):
+    def __init__(self, sim: Sim, key, material=None):
         self.sim = sim
         self.key = key
+        self.material = material
         self.last_used = 0.0
         self.base_bytes = sim.stats()["device_bytes"]
+
+    def match(self, scene):
+        """Give the handle the request's material (stiffness, bending weight,
+        region scales, friction) if the handle last served another one."""
+        mat = _material(scene)
+        if mat != self.material:
+            self.sim.set_material(edge_stiffness=scene.edge_stiffness, bend_weight=scene.bend_weight,
+                                  region_scale=scene.region_scale, mu=[o.mu for o in scene.obstacles])
+            self.material = mat
 
     def need_bytes(self, steps: int, window: int) -> int:
         """Device bytes of a rollout of `steps` steps whose adjoint runs in
@@ -140,9 +157,11 @@ class Server:
     def _acquire(self, req: Request, scene):
         if self.pool[req.key]:
             self.stats["cache_hits"] += 1
-            return self.pool[req.key].pop()
+            h = self.pool[req.key].pop()
+            h.match(scene)
+            return h
         self.stats["cache_misses"] += 1
-        return _Handle(Sim.from_scene(scene, device=self.device, **self.sim_kw), req.key)
+        return _Handle(Sim.from_scene(scene, device=self.device, **self.sim_kw), req.key, _material(scene))
 
     # ------------------------------------------------------------------ serving
     def run(self, requests: List[Request]) -> List[Result]:
