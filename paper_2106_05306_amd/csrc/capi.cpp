@@ -30,7 +30,8 @@ hipError_t launch_fill(double *p, double v, int64_t n, hipStream_t st);
 hipError_t launch_adj_assemble(const SimDev *d_sims, const int32_t *work, int nblocks, hipStream_t st);
 hipError_t launch_adj_factor_level(const SimDev *d_sims, const int32_t *work, int nblocks, int nmax, hipStream_t st);
 hipError_t noalloc_scratch(void **out);
-hipError_t launch_forward_mw(const SimDev *d, int W, bool mixed, bool mesh, hipStream_t st);
+hipError_t launch_forward_mw(const SimDev *d, int W, bool mixed, bool mesh, size_t lds, hipStream_t st);
+hipError_t configure_mw_lds(size_t bytes);
 }  // namespace dc
 
 using namespace dc;
@@ -45,6 +46,7 @@ struct sim {
     int64_t bytes = 0;                  // their total (what sim_stats reports)
     SimDev *batch_desc = nullptr;       // descriptors of the batched launches this handle leads
     bool mw_used = false;               // a multi-workgroup forward ran since the last mw_check
+    size_t mw_lds = 0;                  // dynamic LDS of its workgroups (0: vectors in HBM)
     SimDev hd_noalloc{};                // descriptor of the allocation-free forward (copied to the
                                         //   device scratch on every call; lives as long as the handle)
     int step_info_cap = 0;              // steps the per-step record (hd.step_info) can hold
@@ -137,11 +139,23 @@ int fwd_helpers(sim *const *sims, int n) {
 }
 
 // Workgroups of a single handle's forward launch (the multi-workgroup kernel
-// when the elimination tree allows it): DIFFCLOTH_FWD_WGS, 0 or 1 = one.
-int mw_workgroups_default() {
+// when the elimination tree allows it): DIFFCLOTH_FWD_WGS, 0 or 1 = one;
+// unset: as many as the root has subtrees (at most 16) from 1 200 nodes on --
+// below that its barriers cost more than the split saves (24 x 24 nodes: 39
+// against 27 us per PD iteration; 40 x 40: 61 against 73; 64 x 64: 136
+// against 340, measured on MI355X).
+int mw_workgroups_default(int m) {
     const char *e = std::getenv("DIFFCLOTH_FWD_WGS");
     const int v = e ? std::atoi(e) : -1;
-    return v >= 0 ? std::min(v, kMwMax) : kMwMax;
+    if (v >= 0) return std::min(v, kMwMax);
+    return m >= 1200 ? kMwMax : 0;
+}
+
+// Whether a multi-workgroup forward solves each workgroup's subtree in LDS
+// (DIFFCLOTH_MW_LDS=0: vectors in HBM).
+bool mw_lds_default() {
+    const char *e = std::getenv("DIFFCLOTH_MW_LDS");
+    return !(e && *e == '0');
 }
 
 // wall-clock ticks (100 MHz) a multi-workgroup barrier waits before giving up
@@ -685,7 +699,7 @@ void build_device(sim *s) {
         std::vector<int> kids;
         for (int sn = 0; sn < ns; ++sn)
             if (parent[sn] >= 0 && parent[sn] == root) kids.push_back(sn);
-        const int want = mw_workgroups_default();
+        const int want = mw_workgroups_default(m);
         int W = std::min<int>({want, (int)kids.size(), kMwMax});
         bool ok = nroot == 1 && L >= 2 && W >= 2 && sns[root] <= kMwRootMax && hm.sup_level[root] == L - 1;
         for (int sn = 0; sn < ns && ok; ++sn)
@@ -756,6 +770,35 @@ void build_device(sim *s) {
                         ptr[2 * (Q + 1) + q] = (int32_t)mbi.size();
                         ptr[3 * (Q + 1) + q] = (int32_t)mgi.size();
                     }
+                // one subtree per workgroup: its columns and update slots, solved in LDS
+                bool one = (int)kids.size() == W;
+                std::vector<int32_t> win(4 * (size_t)W, 0);
+                size_t need = 0;
+                for (size_t k = 0; k < kids.size() && one; ++k) {
+                    int ulo = INT32_MAX, uhi = -1, nu = 0;
+                    for (int sn = 0; sn < ns; ++sn)
+                        if (head[sn] == (int)k) {
+                            ulo = std::min(ulo, uoff[sn]);
+                            uhi = std::max(uhi, uoff[sn + 1]);
+                            nu += uoff[sn + 1] - uoff[sn];
+                        }
+                    if (uhi - ulo != nu) { one = false; break; }
+                    const int w = owner[k];
+                    win[4 * w] = lo[k];
+                    win[4 * w + 1] = hi[k];
+                    win[4 * w + 2] = ulo;
+                    win[4 * w + 3] = uhi;
+                    need = std::max(need, (size_t)(6 * (hi[k] - lo[k]) + (uhi - ulo)) * sizeof(double));
+                }
+                const size_t mw_static = (3 * kMwRootMax + kBlock / 64 + 8) * sizeof(double);
+                int dev = 0, maxlds = 0;
+                const bool attr = hipGetDevice(&dev) == hipSuccess &&
+                                  hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess;
+                if (one && attr && mw_lds_default() && need + mw_static <= (size_t)maxlds &&
+                    configure_mw_lds((size_t)maxlds - mw_static) == hipSuccess) {   // the largest any handle may need
+                    D.mw_win = upload(s, win);
+                    s->mw_lds = std::max<size_t>(need, 8);
+                }
                 D.mw = W;
                 D.mw_root_c0 = rc0;
                 D.mw_ptr = upload(s, ptr);
@@ -1185,7 +1228,7 @@ std::vector<int> overlap_chunks(const sim *s, int n_steps) {
 int launch_single_forward(sim *s) {
     if (s->hd.mw >= 2) {
         int rc = hip_err(launch_fill((double *)s->hd.mw_sync, 0.0, kMwSyncDoubles, s->stream));
-        if (!rc) rc = hip_err(launch_forward_mw(s->dd, s->hd.mw, s->hd.mixed != 0, has_mesh(&s, 1), s->stream));
+        if (!rc) rc = hip_err(launch_forward_mw(s->dd, s->hd.mw, s->hd.mixed != 0, has_mesh(&s, 1), s->mw_lds, s->stream));
         s->mw_used = true;
         return rc;
     }

@@ -946,12 +946,13 @@ __device__ __forceinline__ bool mw_barrier(const SimDev &S, uint32_t &gen, int &
 // computed with the arithmetic of k_forward (same items, team sizes and
 // summation orders), so results are bitwise those of the single-workgroup
 // kernel.  Vectors live in HBM and are shared through the XCD's L2.
-template <bool MIXED, bool km>
+template <bool MIXED, bool km, bool LW>
 __global__ __launch_bounds__(kBlock) void k_forward_mw(const SimDev *__restrict__ sims) {
     if ((int)blockIdx.x % kXcds != 0) return;
     const SimDev &S = sims[0];
     const int W = S.mw, w = (int)blockIdx.x / kXcds;
     if (w >= W || (S.mw_absent && w == W - 1)) return;
+    extern __shared__ double dyn[];
     __shared__ double red[kBlock / 64];
     __shared__ double troot[3 * kMwRootMax];
     __shared__ int ok_lds;
@@ -967,7 +968,7 @@ __global__ __launch_bounds__(kBlock) void k_forward_mw(const SimDev *__restrict_
     auto Vprev = G(S.vk1);
     const auto gv2 = (GLOBAL const v2d *)S.gval;
     const auto gt2 = (GLOBAL const v2d *)S.gvalt;
-    auto part = (GLOBAL double *)(S.mw_sync + 4);         // partials: W maxima, then 3 W counts
+    auto part = (GLOBAL double *)(S.mw_sync + 4);         // partials: W maxima, then 2 W packed counts
     if (threadIdx.x == 0) gen = __hip_atomic_load(S.mw_sync + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int ra[kMwRanges], rb[kMwRanges];
     for (int r = 0; r < kMwRanges; ++r) {
@@ -980,6 +981,17 @@ __global__ __launch_bounds__(kBlock) void k_forward_mw(const SimDev *__restrict_
     };
     const int rs0 = S.mw_root_c0, rn = S.n_root_rows;
     const int ys0 = rs0 + (int)((int64_t)rn * w / W), ys1 = rs0 + (int)((int64_t)rn * (w + 1) / W);
+    // LW: the workgroup's one subtree (columns [lo, hi), update slots [ulo, uhi))
+    // is solved in LDS: right-hand side / solution, forward result and update
+    // buffer; what other workgroups read goes out to HBM (the root rows' update
+    // entries after the forward solve, the new iterate after the contact update)
+    const int lo = LW ? G(S.mw_win)[4 * w] : 0, hi = LW ? G(S.mw_win)[4 * w + 1] : 0;
+    const int ulo = LW ? G(S.mw_win)[4 * w + 2] : 0, uhi = LW ? G(S.mw_win)[4 * w + 3] : 0;
+    const int nl = hi - lo;
+    const Shifted sB{dyn, 3 * lo}, sY{dyn + 3 * nl, 3 * lo}, sU{dyn + 6 * nl, ulo};
+    auto TB = pick<LW>(sB, B);                             // own rows of the solve's vectors
+    auto TY = pick<LW>(sY, Y);
+    auto TU = pick<LW>(sU, U);
     int64_t iters_total = 0;
     for (int n = S.step_begin; n < S.step_end; ++n) {
         const int slot = S.rec_ring ? 0 : n - S.rec_step0;
@@ -996,8 +1008,13 @@ __global__ __launch_bounds__(kBlock) void k_forward_mw(const SimDev *__restrict_
                 local_projection<MIXED>(S, XN, A, c0 + (int)((int64_t)nb * w / W), c0 + (int)((int64_t)nb * (w + 1) / W));
                 if (!mw_barrier(S, gen, ok_lds)) return;
             }
-            for (int r = 0; r < kMwRanges; ++r)
-                if (rb[r] > ra[r]) spring_rhs<MIXED>(S, XN, A, B, ra[r], rb[r]);
+            if constexpr (LW) {
+                spring_rhs<MIXED>(S, XN, A, sB, lo, hi);
+                spring_rhs<MIXED>(S, XN, A, B, ys0, ys1);
+            } else {
+                for (int r = 0; r < kMwRanges; ++r)
+                    if (rb[r] > ra[r]) spring_rhs<MIXED>(S, XN, A, B, ra[r], rb[r]);
+            }
             if (converge) own([&](int i) { for (int d = 0; d < 3; ++d) Vprev[3 * i + d] = A[3 * i + d]; });
             __syncthreads();
             // forward solve of this workgroup's subtrees, level by level
@@ -1009,10 +1026,18 @@ __global__ __launch_bounds__(kBlock) void k_forward_mw(const SimDev *__restrict_
                 const auto fit = (GLOBAL const v4i *)S.mw_fitems;
                 v4i cur = {0, 0, 0, 0}, cur2 = {0, 0, 0, 0};
                 if (i0 + team < i1) { cur = fit[2 * (i0 + team)]; cur2 = fit[2 * (i0 + team) + 1]; }
-                gather_rows(G(S.mw_rows), G(S.upd_off), G(S.mw_ptr)[q], G(S.mw_ptr)[q + 1], B, B, U);
+                gather_rows(G(S.mw_rows), G(S.upd_off), G(S.mw_ptr)[q], G(S.mw_ptr)[q + 1], TB, TB, TU);
                 __syncthreads();
-                fwd_products(fit, gv2, i0 + team, i1, nteams, tl, lane, cur, cur2, B, Y, U);
+                fwd_products(fit, gv2, i0 + team, i1, nteams, tl, lane, cur, cur2, TB, TY, TU);
                 __syncthreads();
+            }
+            if constexpr (LW) {                            // the root rows' update entries, for every workgroup
+                const auto bg = (GLOBAL const v2i *)S.mw_bgat;
+                const int g0 = G(S.mw_ptr)[3 * (Q + 1) + w * (L - 1)], g1 = G(S.mw_ptr)[3 * (Q + 1) + (w + 1) * (L - 1)];
+                for (int q = g0 + (int)threadIdx.x; q < g1; q += (int)blockDim.x) {
+                    const v2i e = bg[q];
+                    if (e.y < 0) { U[e.x] = sU[e.x]; U[e.x + 1] = sU[e.x + 1]; U[e.x + 2] = sU[e.x + 2]; }
+                }
             }
             if (!mw_barrier(S, gen, ok_lds)) return;       // every subtree's updates of the root rows are in U
             {   // the root: its right-hand side gathered here, this workgroup's share of its product
@@ -1041,17 +1066,26 @@ __global__ __launch_bounds__(kBlock) void k_forward_mw(const SimDev *__restrict_
                 v4i cur = {0, 0, 0, 0}, cur2 = {0, 0, 0, 0};
                 if (c0 + team < c1) { cur = bit[2 * (c0 + team)]; cur2 = bit[2 * (c0 + team) + 1]; }
                 if (q1 > q0) {
-                    bwd_gather((GLOBAL const v2i *)S.mw_bgat, q0, q1, threadIdx.x, blockDim.x, B, Y, U);
+                    bwd_gather((GLOBAL const v2i *)S.mw_bgat, q0, q1, threadIdx.x, blockDim.x, TB, Y, TU);
                     __syncthreads();
                 }
-                bwd_products(bit, gt2, c0 + team, c1, nteams, tl, lane, cur, cur2, Y, B, U);
+                bwd_products(bit, gt2, c0 + team, c1, nteams, tl, lane, cur, cur2, TY, TB, TU);
                 __syncthreads();
             }
             for (int i = ys0 + (int)threadIdx.x; i < ys1; i += (int)blockDim.x)   // this slice of the root: x from Y
                 for (int d = 0; d < 3; ++d) B[3 * i + d] = Y[3 * i + d];
             __syncthreads();
             double dmax = 0.0;
-            own([&](int i) { fwd_contact_node<km>(S, i, B, XN, Vprev, converge, dmax); });
+            if constexpr (LW) {
+                for (int i = lo + (int)threadIdx.x; i < hi; i += (int)blockDim.x) {
+                    fwd_contact_node<km>(S, i, sB, XN, Vprev, converge, dmax);
+                    for (int d = 0; d < 3; ++d) B[3 * i + d] = sB[3 * i + d];     // the new iterate, for every workgroup
+                }
+                for (int i = ys0 + (int)threadIdx.x; i < ys1; i += (int)blockDim.x)
+                    fwd_contact_node<km>(S, i, B, XN, Vprev, converge, dmax);
+            } else {
+                own([&](int i) { fwd_contact_node<km>(S, i, B, XN, Vprev, converge, dmax); });
+            }
             ++k;
             auto tmp = A; A = B; B = tmp;
             if (converge) {
@@ -2365,12 +2399,24 @@ hipError_t launch_backward(const SimDev *d_sims, int n, bool mixed, size_t lds, 
 }
 
 // multi-workgroup forward of one handle (d: its descriptor), grid 8 W
-hipError_t launch_forward_mw(const SimDev *d, int W, bool mixed, bool mesh, hipStream_t st) {
+// lds > 0: each workgroup solves its one subtree in that much dynamic LDS
+hipError_t launch_forward_mw(const SimDev *d, int W, bool mixed, bool mesh, size_t lds, hipStream_t st) {
     if (W < 2 || W > kMwMax) return hipErrorInvalidValue;
-    auto k = mixed ? (mesh ? k_forward_mw<true, true> : k_forward_mw<true, false>)
-                   : (mesh ? k_forward_mw<false, true> : k_forward_mw<false, false>);
-    hipLaunchKernelGGL(k, dim3(kXcds * W), dim3(kBlock), 0, st, d);
+    using F = void (*)(const SimDev *);
+    static const F tab[2][2][2] = {{{k_forward_mw<false, false, false>, k_forward_mw<false, false, true>},
+                                    {k_forward_mw<false, true, false>, k_forward_mw<false, true, true>}},
+                                   {{k_forward_mw<true, false, false>, k_forward_mw<true, false, true>},
+                                    {k_forward_mw<true, true, false>, k_forward_mw<true, true, true>}}};
+    hipLaunchKernelGGL(tab[mixed][mesh][lds > 0], dim3(kXcds * W), dim3(kBlock), lds, st, d);
     return hipGetLastError();
+}
+
+hipError_t configure_mw_lds(size_t bytes) {
+    hipError_t e = hipSuccess, r;
+    for (const void *f : {(const void *)k_forward_mw<false, false, true>, (const void *)k_forward_mw<false, true, true>,
+                          (const void *)k_forward_mw<true, false, true>, (const void *)k_forward_mw<true, true, true>})
+        if ((r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) e = r;
+    return e;
 }
 
 // Allow the dynamic LDS the kernels may request (data resident in LDS).

@@ -278,6 +278,8 @@ struct SimDev {
     const BwdItem *mw_bitems;
     const GatherItem *mw_bgat;
     const int32_t *mw_nodes;          // [mw][kMwRanges][2] node ranges [a, b) of each workgroup
+    const int32_t *mw_win;            // [mw][4]: one subtree per workgroup, solved in LDS: its columns
+                                      //   [lo, hi) and update slots [ulo, uhi) (null: vectors in HBM)
     uint32_t *mw_sync;                // barrier block (kMwSyncDoubles doubles)
     int64_t mw_spin;                  // wall-clock ticks (100 MHz) a barrier waits before giving up
     int mw_absent;                    // failure-handling tests only: the last workgroup returns at
