@@ -357,17 +357,24 @@ void ks_new_order(const HostModel &hm, std::vector<int32_t> &kp, std::vector<int
 // A root supernode (nR = 0) stores instead the inverse of its diagonal block,
 // (L_ss L_ss^T)^{-1} = L_ss^{-T} L_ss^{-1} (dense, symmetric): its forward
 // product gives x_s at once and it has no backward product.
-// gval: column-major with the column stride rounded up to even (offset
-// goff[s]); gvalt: the same block row-major with the row stride rounded up to
-// even (offset gofft[s]).  Padding is zero; every block starts at an even
-// offset, so a lane reads two rows (gval) or two columns (gvalt) with one
-// 16-byte load.
+// Stored item by item, in the order the solve's work items read them, so that
+// the lanes of an item read consecutive 16-byte words:
+//   gval (offset goff[s]): per forward row pair (r, r + 1), for k = 0 ..
+//     fwd_pair_cols - 1 the pair {G[r][k], G[r+1][k]} (a row past the block: 0);
+//   gvalt (offset gofft[s], none for a root): per backward column pair
+//     (k, k + 1), for rows j = k .. ld - 1 the pair {G[j][k], G[j][k+1]}
+//     (a column past the block: 0).
+// Every item starts at an even offset.
+int fwd_pair_cols(int nsz, int r, bool root) { return root ? nsz : r + 1 < nsz ? r + 2 : nsz; }
+
 void stacked_factor(const HostModel &hm, std::vector<double> &gval, std::vector<double> &gvalt,
                     std::vector<int64_t> &goff, std::vector<int64_t> &gofft) {
     const int ns = hm.ns;
     goff.assign(ns, 0);
     gofft.assign(ns, 0);
     gval.clear();
+    gvalt.clear();
+    std::vector<double> Gd;
     for (int sn = 0; sn < ns; ++sn) {
         const int nsz = hm.sup_c0[sn + 1] - hm.sup_c0[sn];
         const int nR = hm.R_ptr[sn + 1] - hm.R_ptr[sn], nrow = nsz + nR;
@@ -381,9 +388,8 @@ void stacked_factor(const HostModel &hm, std::vector<double> &gval, std::vector<
             }
         }
         const int ldp = nrow + (nrow & 1);
-        goff[sn] = (int64_t)gval.size();
-        gval.resize(gval.size() + (size_t)ldp * nsz, 0.0);
-        double *G = gval.data() + goff[sn];
+        Gd.assign((size_t)ldp * nsz, 0.0);                  // the block, column-major, zero padding row
+        double *G = Gd.data();
         if (nR == 0) {                                      // root: (L L^T)^{-1}
             for (int k = 0; k < nsz; ++k)
                 for (int r = 0; r < nsz; ++r) {
@@ -391,27 +397,31 @@ void stacked_factor(const HostModel &hm, std::vector<double> &gval, std::vector<
                     for (int j = std::max(r, k); j < nsz; ++j) acc += inv[(size_t)j * nsz + r] * inv[(size_t)j * nsz + k];
                     G[(size_t)k * ldp + r] = acc;
                 }
-            continue;
-        }
-        for (int k = 0; k < nsz; ++k) {
-            for (int r = k; r < nsz; ++r) G[(size_t)k * ldp + r] = inv[(size_t)r * nsz + k];
-            for (int q = 0; q < nR; ++q) {
-                double acc = 0.0;
-                for (int j = k; j < nsz; ++j) acc += F[(size_t)j * nrow + nsz + q] * inv[(size_t)j * nsz + k];
-                G[(size_t)k * ldp + nsz + q] = acc;
+        } else {
+            for (int k = 0; k < nsz; ++k) {
+                for (int r = k; r < nsz; ++r) G[(size_t)k * ldp + r] = inv[(size_t)r * nsz + k];
+                for (int q = 0; q < nR; ++q) {
+                    double acc = 0.0;
+                    for (int j = k; j < nsz; ++j) acc += F[(size_t)j * nrow + nsz + q] * inv[(size_t)j * nsz + k];
+                    G[(size_t)k * ldp + nsz + q] = acc;
+                }
             }
         }
-    }
-    gvalt.clear();
-    for (int sn = 0; sn < ns; ++sn) {
-        const int nsz = hm.sup_c0[sn + 1] - hm.sup_c0[sn], ld = nsz + hm.R_ptr[sn + 1] - hm.R_ptr[sn];
-        const int ldp = ld + (ld & 1), nszp = nsz + (nsz & 1);
+        goff[sn] = (int64_t)gval.size();
+        for (int r = 0; r < nrow; r += 2) {
+            const int km = fwd_pair_cols(nsz, r, nR == 0);
+            for (int k = 0; k < km; ++k) {
+                gval.push_back(G[(size_t)k * ldp + r]);
+                gval.push_back(G[(size_t)k * ldp + r + 1]);     // r + 1 = ldp - 1: the zero padding row
+            }
+        }
         gofft[sn] = (int64_t)gvalt.size();
-        gvalt.resize(gvalt.size() + (size_t)ld * nszp, 0.0);
-        const double *G = gval.data() + goff[sn];
-        double *Gt = gvalt.data() + gofft[sn];
-        for (int k = 0; k < nsz; ++k)
-            for (int r = 0; r < ld; ++r) Gt[(size_t)r * nszp + k] = G[(size_t)k * ldp + r];
+        if (nR == 0) continue;
+        for (int k = 0; k < nsz; k += 2)
+            for (int j = k; j < nrow; ++j) {
+                gvalt.push_back(G[(size_t)k * ldp + j]);
+                gvalt.push_back(k + 1 < nsz ? G[(size_t)(k + 1) * ldp + j] : 0.0);
+            }
     }
 }
 
@@ -637,17 +647,21 @@ void build_device(sim *s) {
         if (ld >= 32768) throw std::runtime_error("supernode too large");
         const int ldp = ld + (ld & 1), nszp = nsz + (nsz & 1);
         const bool root = snr[sn] == 0;
+        (void)ldp;
+        (void)nszp;
         for (int k = 0; k < nsz; ++k) ri.push_back(RowItem{3 * (c0 + k), up[c0 + k], up[c0 + k + 1], 0});
+        int64_t bo = gofft[sn];                       // items' pairs stored one after another (stacked_factor)
         for (int k = 0; k < nsz && !root; k += 2) {  // columns k, k + 1
             BwdItem b{};
-            b.g = (int32_t)(gofft[sn] + (int64_t)k * nszp + k);
+            b.g = (int32_t)bo;
             b.n1 = (int16_t)(nsz - k);
             b.n2 = (int16_t)snr[sn];
             b.ybase = 3 * (c0 + k);
             b.ubase = uoff[sn];
-            b.st = nszp;
+            b.st = 2;                                 // consecutive rows: consecutive 16-byte pairs
             b.two = k + 1 < nsz;
             bi.push_back(b);
+            bo += 2 * (int64_t)(ld - k);
             bmx = std::max(bmx, ld - k);
         }
         for (int q = 0; q < snr[sn]; ++q) {        // x of a root's rows is still in Y (encoded -(3i) - 1)
@@ -655,11 +669,13 @@ void build_device(sim *s) {
             gi.push_back(GatherItem{uoff[sn] + 3 * q, is_root_row[i] ? -3 * i - 1 : 3 * i});
         }
         auto out_of = [&](int r) { return r < nsz ? 3 * (c0 + r) : -(uoff[sn] + 3 * (r - nsz)) - 1; };
+        int64_t fo = goff[sn];
         for (int r = 0; r < ld; r += 2) {           // rows r, r + 1
             FwdItem f{};
-            f.g = (int32_t)(goff[sn] + r);
-            f.ld = (int16_t)ldp;
-            f.kmax = (int16_t)(root ? nsz : r + 1 < nsz ? r + 2 : nsz);
+            f.g = (int32_t)fo;
+            f.ld = 2;                                 // consecutive columns: consecutive 16-byte pairs
+            f.kmax = (int16_t)fwd_pair_cols(nsz, r, root);
+            fo += 2 * (int64_t)f.kmax;
             f.tbase = 3 * c0;
             f.out0 = out_of(r);
             f.out1 = r + 1 < ld ? out_of(r + 1) : kNoOutput;
@@ -822,8 +838,12 @@ void build_device(sim *s) {
         std::vector<std::vector<int64_t>> ph(2 * L);
         for (int sn = 0; sn < ns; ++sn) {
             const int l = hm.sup_level[sn], nsz = sns[sn], ld = nsz + snr[sn];
-            ph[l].insert(ph[l].end(), {goff[sn], (int64_t)(ld + (ld & 1)) * nsz});
-            if (snr[sn] > 0) ph[L + (L - 1 - l)].insert(ph[L + (L - 1 - l)].end(), {gofft[sn], (int64_t)ld * (nsz + (nsz & 1))});
+            const int64_t fe = sn + 1 < ns ? goff[sn + 1] : (int64_t)gval.size();
+            const int64_t be = sn + 1 < ns ? gofft[sn + 1] : (int64_t)gvalt.size();
+            (void)ld;
+            (void)nsz;
+            ph[l].insert(ph[l].end(), {goff[sn], fe - goff[sn]});
+            if (snr[sn] > 0) ph[L + (L - 1 - l)].insert(ph[L + (L - 1 - l)].end(), {gofft[sn], be - gofft[sn]});
         }
         std::vector<int64_t> fpf;
         std::vector<int32_t> fptr(1, 0);
