@@ -35,6 +35,7 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2106_05306_amd", "csrc", "kernels.hip")
 LAUNCH_SRC = os.path.join(ROOT, "paper_2106_05306_amd", "csrc", "capi.cpp")
 LAYOUT_SRC = os.path.join(ROOT, "paper_2106_05306_amd", "csrc", "sim_dev.h")
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "sphere_drop40_pmc.txt")
+BATCH_PMC_SUMMARY = os.path.join(ROOT, "profiles", "batch64_pmc.txt")
 
 
 def source_hash():
@@ -47,17 +48,26 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(kernel_name):
-    """HBM bytes per launch from the committed PMC summary, if it was taken on
-    the current kernel source (else None)."""
-    if not os.path.exists(PMC_SUMMARY):
+def traffic_from_profile(kernel_name, summary=None):
+    """HBM bytes per launch from a committed PMC summary (default: the
+    headline's), if it was taken on the current kernel source (else None)."""
+    path = PMC_SUMMARY if summary is None else summary
+    if not os.path.exists(path):
         return None
-    txt = open(PMC_SUMMARY).read()
+    txt = open(path).read()
     m = re.search(r"kernel_source_sha256_16:\s*(\w+)", txt)
     if not m or m.group(1) != source_hash():
         return None
     m = re.search(kernel_name + r"_hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
     return float(m.group(1)) if m else None
+
+
+# nnz of the Cholesky factor of P_s under a minimum-degree ordering, from the
+# sizing calculation of the hot-path survey (regular grids, side n nodes):
+# the algorithmic bytes count these, not the fill of this library's own
+# ordering (nested dissection with the top separators merged into one dense
+# root), which is reported beside them
+MMD_NNZ_L = {10: 1176, 16: 4847, 40: 61679, 64: 213474, 100: 653269}
 
 
 def algorithmic_bytes(st, m, E, C_steps, K, T, adj_iters, direct):
@@ -217,9 +227,11 @@ def bench_batch(args):
     torch.cuda.synchronize()
     tb = (time.perf_counter() - t0) / args.steps
     fwd_ms = ev[0].elapsed_time(ev[1])
-    t0 = time.perf_counter()
-    sequential()
-    ts = time.perf_counter() - t0
+    ts = float("nan")
+    if not args.no_sequential:
+        t0 = time.perf_counter()
+        sequential()
+        ts = time.perf_counter() - t0
     R = len(sims)
     cpu = None if args.no_cpu_baseline else batch_cpu_baseline(sims, batch, T)
     # forward roofline: algorithmic bytes of all rollouts / the batched forward launch
@@ -241,8 +253,11 @@ def bench_batch(args):
         "cloth_steps_per_s": R * T / tb,
         "sequential": {"rollouts_per_s": R / ts, "seconds": ts, "speedup_batched": ts / tb},
         "roofline": {"bound": "hbm", "kernel": "k_forward (batched)", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "algorithmic_bytes_per_launch": fbytes, "launch_ms": fwd_ms},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic_from_profile("k_forward", BATCH_PMC_SUMMARY),
+                     "algorithmic_bytes_per_launch": fbytes, "launch_ms": fwd_ms,
+                     "note": "nnz(L) of this library's ordering; traffic: rocprofv3 FETCH_SIZE x 2.0 + "
+                             "WRITE_SIZE of the batched forward launch (profiles/batch64_pmc.txt)"},
         "cpu_baseline": cpu,
         "adjoint_unconverged_rollouts": int(sum(1 for g in out if g["status"] == 2)),
         "gradient_nonfinite_rollouts": int(sum(1 for g in out if g["status"] == 3)),
@@ -581,6 +596,7 @@ def main():
                     help="sphere_drop: the analytic sphere (default) or a triangulated one (320 / 1280 triangles)")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--batch-window", type=int, default=50, help="adjoint steps per launch in the batch workload")
+    ap.add_argument("--no-sequential", action="store_true", help="batch workload: skip the one-at-a-time baseline")
     ap.add_argument("--requests", type=int, default=40, help="requests of the serve workload")
     ap.add_argument("--fd-steps", type=int, default=10, help="steps of the skirt finite-difference check")
     ap.add_argument("--skirt-tol", type=float, default=1e-6, help="forward tolerance (m/s) of the skirt rollouts")
@@ -655,15 +671,20 @@ def main():
     fwd_iters = fwd_stats["fwd_iters_total"]
     C_steps = [int(np.count_nonzero(sim.modes(n))) for n in range(T)]
     adj_iters = st["adj_iters_total"] + st["adj_krylov_total"]
-    fwd_b, bwd_b = algorithmic_bytes(st, sc.n_nodes, st["n_edges"], C_steps, fwd_iters / T, T, adj_iters,
+    side = int(round(sc.n_nodes ** 0.5))
+    st_mmd = dict(st, nnz_L=MMD_NNZ_L.get(side, st["nnz_L"]))
+    fwd_b, bwd_b = algorithmic_bytes(st_mmd, sc.n_nodes, st["n_edges"], C_steps, fwd_iters / T, T, adj_iters,
                                      args.adj_solver == "direct")
+    fwd_bf, bwd_bf = algorithmic_bytes(st, sc.n_nodes, st["n_edges"], C_steps, fwd_iters / T, T, adj_iters,
+                                       args.adj_solver == "direct")
     # per launch: the forward pass runs as fwd_launches launches (chunks that
     # overlap the step factorisations), the adjoint as one
+    fwd_kernel = "k_forward_mw" if st["fwd_workgroups"] > 1 else "k_forward"
     if bwd_ms > fwd_ms:
-        kname, launches, nbytes, ms = "k_backward", 1, bwd_b, bwd_ms
+        kname, launches, nbytes, nbytes_fill, ms = "k_backward", 1, bwd_b, bwd_bf, bwd_ms
     else:
         launches = max(1, int(fwd_stats.get("fwd_launches", 1)))
-        kname, nbytes, ms = "k_forward", fwd_b / launches, fwd_ms / launches
+        kname, nbytes, nbytes_fill, ms = fwd_kernel, fwd_b / launches, fwd_bf / launches, fwd_ms / launches
     achieved = nbytes / (ms * 1e-3) / 1e9
     traffic = traffic_from_profile(kname) if args.obstacle == "sphere" else None
     value = args.steps * T / elapsed
@@ -694,7 +715,13 @@ def main():
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "algorithmic_bytes_per_launch": nbytes, "launch_ms": ms,
-                     "launches_per_rollout": launches},
+                     "launches_per_rollout": launches,
+                     "nnz_L_counted": st_mmd["nnz_L"], "nnz_L_this_ordering": st["nnz_L"],
+                     "achieved_with_this_orderings_fill": nbytes_fill / (ms * 1e-3) / 1e9,
+                     "note": "algorithmic bytes per unit: per PD iteration 2 nnz(L) 12 + 4 (3m 8) + E 16 + m 12 "
+                             "+ C 48, per step nnz(P) 12 + m 24, nnz(L) of a minimum-degree ordering; "
+                             "traffic: rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE per launch (profiles/), "
+                             "null unless taken on the current kernel source"},
         "timing_ms": {"forward": fwd_ms, "backward": bwd_ms,
                       "note": "forward = the forward launches (the direct adjoint's step factorisations run "
                               "meanwhile on a second stream, chunk by chunk); backward = the rest of the "
@@ -703,14 +730,18 @@ def main():
                      if out["status"] != 3 else
                      {"status": "non-finite (SIM_WADJ_NONFINITE)",
                       "note": "every adjoint step is solved (each matches the oracle's direct solve from the "
-                              "same state), but chained over 200 steps the adjoint of the truncated K=20 forward "
-                              "amplifies until it overflows: its states are far from the implicit-Euler solution "
-                              "at this stiffness/mass ratio.  The oracle shows the same growth; with the forward "
-                              "converged (1e-10 m/s, 20x20 grid, 120 steps) the chained adjoint stays bounded"}),
+                              "GPU's state, tests/test_gpu_headline.py), but chained over 200 steps the adjoint "
+                              "of the truncated K=20 forward amplifies until it overflows: its states are far "
+                              "from the implicit-Euler solution at this stiffness/mass ratio (the oracle shows "
+                              "the same growth).  Converging the contact iteration of the paper at 40x40 takes "
+                              "5e4 to >1e5 PD iterations per contact step (measured on this GPU); converged "
+                              "rollouts give finite gradients equal to the oracle's "
+                              "(tests/test_gpu_warmstart.py, 8x8 whole rollout)"}),
         "solver": {"pd_iters_per_rollout": fwd_iters, "adj_fixed_point_iters": st["adj_iters_total"],
                    "adj_krylov_iters": st["adj_krylov_total"], "adj_fallback_steps": st["adj_fallbacks"],
                    "adj_unconverged_steps": st["adj_noconv"], "nnz_L": st["nnz_L"], "nnz_P": st["nnz_P"],
                    "levels": st["n_levels"], "lds_forward": st["lds_forward"],
+                   "forward_workgroups": st["fwd_workgroups"],
                    "adj_factor_bytes_per_step": st["adj_factor_bytes"],
                    "contact_nodes_mean": float(np.mean(C_steps))},
     }
