@@ -229,6 +229,10 @@ typedef struct {
                                        indexed by SIM_MODE_* (free, take-off, stick, slip)       */
     double  fwd_ms, bwd_ms;         /* device time of the last sim_forward / sim_backward on the
                                        handle's stream (HIP events; 0 before the first call)    */
+    int32_t fwd_workgroups;         /* workgroups of a single-handle forward launch (> 1: the
+                                       multi-workgroup kernel, subtrees of the elimination tree per
+                                       workgroup)                                               */
+    int32_t pad;
 } sim_stats_t;
 
 typedef void *(*sim_alloc_fn)(size_t bytes, void *ctx);

@@ -62,7 +62,8 @@ class SimStats(Structure):
                 ("factor_bytes", c_int64), ("lds_forward", c_int64), ("lds_backward", c_int64),
                 ("adj_factor_bytes", c_int64), ("adj_pivot_perturbed", c_int64), ("fwd_launches", c_int32),
                 ("lds_flags_fwd", c_int32), ("lds_flags_bwd", c_int32), ("fwd_iters_max", c_int32),
-                ("mode_counts", c_int64 * 4), ("fwd_ms", c_double), ("bwd_ms", c_double)]
+                ("mode_counts", c_int64 * 4), ("fwd_ms", c_double), ("bwd_ms", c_double),
+                ("fwd_workgroups", c_int32), ("pad", c_int32)]
 
 
 ALLOC_FN = CFUNCTYPE(c_void_p, c_size_t, c_void_p)

@@ -2005,6 +2005,7 @@ int sim_stats(const sim_t *cs, sim_stats_t *out) {
     out->adj_pivot_perturbed = s->counters_host[5];
     out->fwd_launches = s->fwd_launches;
     out->lds_flags_fwd = s->flags_fwd;
+    out->fwd_workgroups = s->hd.mw >= 2 ? s->hd.mw : 1;
     out->lds_flags_bwd = s->flags_bwd;
     if (s->tev_fwd) {
         float ms = 0.0f;
