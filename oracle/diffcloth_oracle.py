@@ -31,6 +31,12 @@ Readings of the paper taken here (the paper is silent or ambiguous on them):
   * Initial guess per step: v^0 = v_n + h g, contact impulses 0, or (warm
     start) the previous step's impulses on the nodes of the contact set.
   * Backward projections re-evaluated at x_{n+1} = x_n + h v_{n+1}.
+  * Node-node self-collision (Sec. 4.2, Extensions): pairs found on the
+    predictor y among nodes outside the obstacle contact set (each node in at
+    most one contact); the pair's normal is the direction of x_i - x_j at x_n,
+    its gap |x_i - x_j| - d, the law acts on the relative velocity with the
+    pair's reduced mass, and the pair's impulse is +f on i and -f on j.  The
+    adjoint takes T with two-node blocks in the mass-weighted form M T M^{-1}.
 Every function cites the passage it follows.  Parity is pinned by the
 ``-m "not gpu"`` tests in ``tests/test_oracle_pins.py``.
 """
@@ -123,6 +129,27 @@ class Contact:
 
 
 @dataclasses.dataclass
+class SelfContact:
+    """Per-step node-node contact record (Sec. 4.2, Extensions: a row of J
+    with two node blocks, the normal along the pair's relative position)."""
+    i: np.ndarray           # (S,) lower node id of each pair
+    j: np.ndarray           # (S,) higher node id
+    normal: np.ndarray      # (S, 3) (x_i - x_j) / |x_i - x_j| at x_n
+    gap: np.ndarray         # (S,) |x_i - x_j| - d at x_n
+    dist: np.ndarray        # (S,) |x_i - x_j| at x_n
+    mred: np.ndarray        # (S,) reduced mass m_i m_j / (m_i + m_j)
+    ubar: np.ndarray        # (S, 3) free relative velocity of the last contact update
+    impulse: np.ndarray     # (S, 3) impulse on node i (node j receives its negative)
+    mode: np.ndarray        # (S,) TAKEOFF / STICK / SLIP
+
+
+def no_self_contact() -> SelfContact:
+    z = np.zeros(0, np.int64)
+    return SelfContact(z, z, np.zeros((0, 3)), np.zeros(0), np.zeros(0), np.zeros(0),
+                       np.zeros((0, 3)), np.zeros((0, 3)), np.zeros(0, np.int8))
+
+
+@dataclasses.dataclass
 class StepRecord:
     x0: np.ndarray          # x_n
     v0: np.ndarray          # v_n
@@ -130,6 +157,7 @@ class StepRecord:
     v1: np.ndarray          # v_{n+1}
     contact: Contact
     iters: int
+    pairs: Optional[SelfContact] = None     # node-node contacts (None: none)
 
 
 class Model:
@@ -139,7 +167,7 @@ class Model:
     P = P_s (x) I_3 with the scalar m x m matrix P_s."""
 
     def __init__(self, scene, edge_stiffness=None, bend_weight=None, region_scale=None,
-                 mu=None, h=None, force=None, force_scale=None):
+                 mu=None, h=None, force=None, force_scale=None, self_mu=None):
         self.scene = scene
         self.X = np.asarray(scene.X, float)
         self.m = self.X.shape[0]
@@ -203,6 +231,19 @@ class Model:
         self.K_s = (self.A.T @ sp.diags(self.w) @ self.A + Patt).tocsr()   # sum w A^T A (scalar)
         self.P_s = (sp.diags(self.mass) + h2 * self.K_s).tocsc()
         self.lu = spla.splu(self.P_s)                            # "prefactorized" P
+        # node-node self-collision: thickness d (0: off) and friction coefficient;
+        # nodes that share a constraint stencil never form a pair
+        self.self_d = float(getattr(scene, "self_thickness", 0.0) or 0.0)
+        self.self_r = float(getattr(scene, "self_radius", 0.0) or 0.0) or self.self_d
+        self.self_mu = float(getattr(scene, "self_mu", 0.0) if self_mu is None else self_mu)
+        self._shared = None
+
+    def shares_stencil(self) -> np.ndarray:
+        """(m, m) bool: nodes i, j appear together in a spring or bending stencil."""
+        if self._shared is None:
+            Aa = abs(self.A)
+            self._shared = (Aa.T @ Aa).toarray() != 0
+        return self._shared
 
     # ----------------------------------------------------------------- helpers
     def force_at(self, n: int) -> np.ndarray:
@@ -364,6 +405,48 @@ def detect_contacts(model: Model, x: np.ndarray, y: np.ndarray):
     return nodes, obst, normal, gap, mu
 
 
+def detect_self_pairs(model: Model, x: np.ndarray, y: np.ndarray, busy: np.ndarray,
+                      f_prev: Optional[np.ndarray] = None) -> SelfContact:
+    """Node-node contact set on the predictor y (Sec. 4.2, Extensions; reading).
+    Node i's candidates are the nodes j != i that share no constraint stencil
+    with i, are both outside the obstacle contact set (busy), have x_i != x_j
+    and |y_i - y_j| <= r, the detection radius (r >= d; squared distances
+    compared, summed over x, y, z in that order); its partner is its nearest candidate, ties to the lowest
+    index; i and j form a pair when each is the other's partner.  The pair's
+    frame is taken at x_n (as for obstacles): normal (x_i - x_j)/|x_i - x_j|
+    for i < j, gap |x_i - x_j| - d.  Its impulse starts from zero, or (warm
+    start) from node i's impulse at the end of the previous step."""
+    d = model.self_d
+    if d <= 0.0:
+        return no_self_contact()
+    m = model.m
+
+    def sq(P):
+        D = P[:, None, :] - P[None, :, :]
+        return D[..., 0] * D[..., 0] + D[..., 1] * D[..., 1] + D[..., 2] * D[..., 2]
+
+    rr = model.self_r
+    d2 = sq(y)
+    ok = (d2 <= rr * rr) & (sq(x) > 0.0) & ~model.shares_stencil()
+    ok &= ~busy[:, None] & ~busy[None, :]
+    np.fill_diagonal(ok, False)
+    d2 = np.where(ok, d2, np.inf)
+    nn = np.argmin(d2, axis=1)                                 # ties -> lowest index
+    nn[~np.isfinite(d2[np.arange(m), nn])] = -1
+    i = np.nonzero((nn > np.arange(m)) & (nn[np.maximum(nn, 0)] == np.arange(m)))[0]
+    j = nn[i]
+    S = i.size
+    sc = no_self_contact()
+    if S == 0:
+        return sc
+    e = x[i] - x[j]
+    r = np.sqrt(e[:, 0] * e[:, 0] + e[:, 1] * e[:, 1] + e[:, 2] * e[:, 2])
+    mi, mj = model.mass[i], model.mass[j]
+    f0 = np.zeros((S, 3)) if f_prev is None else np.asarray(f_prev, float)[i].copy()
+    return SelfContact(i, j, e / r[:, None], r - d, r, mi * mj / (mi + mj), np.zeros((S, 3)), f0,
+                       np.full(S, TAKEOFF, np.int8))
+
+
 def local_projection(model: Model, x: np.ndarray):
     """Local step (eqn pd_project): p_i = argmin over M_i of |A_i x - p|.
     Springs/bending: the sphere of radius rho_i; returns (p, q = A x)."""
@@ -440,6 +523,11 @@ def forward_step(model: Model, x: np.ndarray, v: np.ndarray, n: int, iters: Opti
     y = inertial_predictor(model, x, v, n)
     nodes, obst, normal, gap, mu = detect_contacts(model, x, y)
     C = nodes.size
+    busy = np.zeros(model.m, bool)
+    busy[nodes] = True
+    ps = detect_self_pairs(model, x, y, busy, f_prev)          # node-node contacts
+    S = ps.i.size
+    pf = ps.impulse
     bhat0 = constant_rhs(model, x, v, t1, n)
     vk = v + h * model.external_accel(n)                      # v^0: x^0 = y
     f = np.zeros((C, 3)) if f_prev is None else np.asarray(f_prev, float)[nodes].copy()
@@ -453,6 +541,9 @@ def forward_step(model: Model, x: np.ndarray, v: np.ndarray, n: int, iters: Opti
         rhs = bhat0 + h * (model.A.T @ (model.w[:, None] * p))
         if C:
             np.add.at(rhs, nodes, f)                          # h J^T r
+        if S:                                                 # pair rows: +f on i, -f on j
+            np.add.at(rhs, ps.i, pf)
+            np.add.at(rhs, ps.j, -pf)
         vnew = model.solve_P(rhs)                             # global step
         df = 0.0
         if C:                                                 # contact update per node
@@ -461,6 +552,17 @@ def forward_step(model: Model, x: np.ndarray, v: np.ndarray, n: int, iters: Opti
             df = np.max(np.abs(fn - f) / model.mass[nodes, None])
             f = fn
             vnew[nodes] = vc
+        if S:                                                 # contact update per pair
+            mi, mj = model.mass[ps.i, None], model.mass[ps.j, None]
+            ubi = vnew[ps.i] - pf / mi                        # free velocities of both nodes
+            ubj = vnew[ps.j] + pf / mj
+            urel = ubi - ubj                                  # relative response f / m_ij
+            _, fn, ps.mode = signorini_coulomb(urel, ps.normal, ps.gap, np.full(S, model.self_mu), h, ps.mred)
+            df = max(df, np.max(np.abs(fn - pf) / mi), np.max(np.abs(fn - pf) / mj))
+            pf = fn
+            ps.ubar = urel
+            vnew[ps.i] = ubi + fn / mi
+            vnew[ps.j] = ubj - fn / mj
         k += 1
         # the iterate is the pair (v, impulses): a contact node held by the
         # contact update keeps its velocity while its impulse still changes
@@ -474,14 +576,18 @@ def forward_step(model: Model, x: np.ndarray, v: np.ndarray, n: int, iters: Opti
         elif dv <= tol or k >= max_iters:
             break
     x1 = x + h * vk
+    ps.impulse = pf
     return StepRecord(x.copy(), v.copy(), x1, vk.copy(),
-                      Contact(nodes, obst, normal, gap, mu, ubar, f, mode), k)
+                      Contact(nodes, obst, normal, gap, mu, ubar, f, mode), k, ps)
 
 
 def step_impulses(model: Model, rec: StepRecord) -> np.ndarray:
     """Per-node impulses (m, 3) at the end of a recorded step (zero off contact)."""
     f = np.zeros((model.m, 3))
     f[rec.contact.nodes] = rec.contact.impulse
+    if rec.pairs is not None and rec.pairs.i.size:
+        f[rec.pairs.i] = rec.pairs.impulse
+        f[rec.pairs.j] = -rec.pairs.impulse
     return f
 
 
@@ -559,38 +665,106 @@ def delta_P(model: Model, x: np.ndarray) -> sp.csr_matrix:
     return (At.T @ D @ At).tocsr()
 
 
-def contact_jacobian_blocks(contact: Contact, h: float):
-    """T_j = d v_j / d ubar_j of the closed-form contact update: identity for
-    take-off, zero for stick, (1-s)Pi + s t t^T + mu t n^T for slip, with
-    Pi = I - n n^T, t the unit free tangential velocity and s = mu(-a)/|u_T|."""
-    C = contact.nodes.size
+def sc_jacobian_blocks(ubar, normal, gap, mu, mode, h: float):
+    """T = d v / d ubar of the closed-form contact update (eqn contact_all) per
+    contact: identity for take-off, zero for stick, (1-s)Pi + s t t^T + mu t n^T
+    for slip, with Pi = I - n n^T, t the unit free tangential velocity and
+    s = mu(-a)/|u_T|.  Vectorised: ubar, normal (C, 3); gap, mu, mode (C,)."""
+    C = mode.size
     T = np.zeros((C, 3, 3))
-    T[contact.mode == TAKEOFF] = np.eye(3)
-    sl = contact.mode == SLIP
+    T[mode == TAKEOFF] = np.eye(3)
+    sl = mode == SLIP
     if np.any(sl):
-        n = contact.normal[sl]
-        ub = contact.ubar[sl]
+        n = normal[sl]
+        ub = ubar[sl]
         un = np.sum(n * ub, axis=1)
         ut = ub - un[:, None] * n
         tau = np.linalg.norm(ut, axis=1)
         t = ut / tau[:, None]
-        a = un + contact.gap[sl] / h
-        mu = contact.mu[sl]
-        s = mu * (-a) / tau
+        a = un + gap[sl] / h
+        m_ = mu[sl]
+        s = m_ * (-a) / tau
         Pi = np.eye(3)[None] - n[:, :, None] * n[:, None, :]
         T[sl] = ((1 - s)[:, None, None] * Pi + s[:, None, None] * t[:, :, None] * t[:, None, :]
-                 + mu[:, None, None] * t[:, :, None] * n[:, None, :])
+                 + m_[:, None, None] * t[:, :, None] * n[:, None, :])
     return T
+
+
+def contact_jacobian_blocks(contact: Contact, h: float):
+    """T_j = d v_j / d ubar_j of the obstacle contacts (see sc_jacobian_blocks)."""
+    return sc_jacobian_blocks(contact.ubar, contact.normal, contact.gap, contact.mu, contact.mode, h)
+
+
+def step_contact_jacobian(model: Model, rec: StepRecord) -> sp.csr_matrix:
+    """T = d v / d ubar of the step's whole contact update (3m x 3m): identity
+    off contact, the per-node blocks of the obstacle contacts, and for a pair
+    (i, j) with relative block T_r and D = T_r - I the two-node block
+    [[I + a_i D, -a_i D], [-a_j D, I + a_j D]], a_i = m_ij / m_i, since
+    v_i = ubar_i + f/m_i, v_j = ubar_j - f/m_j with f = m_ij (u - ubar_i + ubar_j)."""
+    m = model.m
+    h = model.h
+    Tb = np.tile(np.eye(3), (m, 1, 1))
+    if rec.contact.nodes.size:
+        Tb[rec.contact.nodes] = contact_jacobian_blocks(rec.contact, h)
+    T = _blockdiag3(Tb).tolil()
+    ps = rec.pairs
+    if ps is not None and ps.i.size:
+        D = sc_jacobian_blocks(ps.ubar, ps.normal, ps.gap, np.full(ps.i.size, model.self_mu), ps.mode, h)
+        D = D - np.eye(3)[None]
+        for q in range(ps.i.size):
+            i, j = int(ps.i[q]), int(ps.j[q])
+            ai, aj = ps.mred[q] / model.mass[i], ps.mred[q] / model.mass[j]
+            for (r, c, blk) in ((i, i, np.eye(3) + ai * D[q]), (i, j, -ai * D[q]),
+                                (j, i, -aj * D[q]), (j, j, np.eye(3) + aj * D[q])):
+                T[3 * r:3 * r + 3, 3 * c:3 * c + 3] = blk
+    return T.tocsr()
+
+
+def frame_gradients(lam, normal, gap, ubar, mu, mode, h: float):
+    """For active contacts (stick / slip) with multipliers lam = M zeta (a pair:
+    m_ij (zeta_i - zeta_j)): lam^T dv/dphi, (dv/dn)^T lam (ubar and the gap held
+    fixed) and lam^T dv/dmu of the closed-form update, v = -(phi/h) n (stick),
+    -(phi/h) n + u_T + mu a t (slip).  Returns (C,), (C, 3), (C,)."""
+    I3 = np.eye(3)[None]
+    nrm, phi, ub = normal, gap, ubar
+    un = np.sum(nrm * ub, axis=1)
+    a = un + phi / h
+    ut = ub - un[:, None] * nrm
+    tau = np.linalg.norm(ut, axis=1)
+    sl = mode == SLIP
+    t = np.zeros_like(ut)
+    t[sl] = ut[sl] / tau[sl, None]
+    # d v / d phi: stick -n/h, slip (-n + mu t)/h
+    dv_dphi = (-nrm + (mu * sl)[:, None] * t) / h
+    # d v / d n (ubar, phi held fixed)
+    dv_dn = -(phi / h)[:, None, None] * I3 * np.ones((mode.size, 1, 1))
+    dmu = np.zeros(mode.size)
+    if np.any(sl):
+        nn, ubs, ts, taus, As, mus = nrm[sl], ub[sl], t[sl], tau[sl], a[sl], mu[sl]
+        dut_dn = -un[sl][:, None, None] * I3 - nn[:, :, None] * ubs[:, None, :]
+        dt_dut = (I3 - ts[:, :, None] * ts[:, None, :]) / taus[:, None, None]
+        dv_dn[sl] += (dut_dn + mus[:, None, None] * ts[:, :, None] * ubs[:, None, :]
+                      + (mus * As)[:, None, None] * np.einsum('cij,cjk->cik', dt_dut, dut_dn))
+        dmu[sl] = np.sum(lam[sl] * ts, axis=1) * As
+    dphi = np.sum(lam * dv_dphi, axis=1)
+    dn = np.einsum('cji,cj->ci', dv_dn, lam)                  # (dv/dn)^T lambda
+    return dphi, dn, dmu
 
 
 def backward_step(model: Model, rec: StepRecord, gx: np.ndarray, gv: np.ndarray,
                   n: int, direct: bool = True, iter_tol: float = 1e-12, iter_max: int = 100000):
     """Adjoint of one step (Sec. 4.2, eqns adjoint_vv, adjoint_v, ppr_adjoint):
-    given dL/dx_{n+1} and dL/dv_{n+1}, solve (M + H T^T) zeta = gbar with
-    H = h^2 Hess W(x_{n+1}) = P - M - Delta P and return dL/dx_n, dL/dv_n and the
-    parameter gradients of this step.  The plain definition of the adjoint is
-    the direct solve (the paper's ground truth); ``direct=False`` runs the
-    paper's iteration P zeta^{k+1} = (Delta P + Delta R) zeta^k + gbar instead."""
+    given dL/dx_{n+1} and dL/dv_{n+1}, solve (M + H Tc^T) zeta = gbar with
+    H = h^2 Hess W(x_{n+1}) = P - M - Delta P and Tc = M T M^{-1} (T = dv/dubar
+    of the contact update; Tc = T when T is block diagonal per node), and
+    return dL/dx_n, dL/dv_n and the parameter gradients of this step.
+
+    Why Tc: the converged step satisfies M ubar + h grad W(x_n + h v) = c with
+    v = V(ubar), so dL/dc = (M + H T)^{-T} T^T gbar = Tc^T zeta.  The plain
+    definition of the adjoint is the direct solve (the paper's ground truth);
+    ``direct=False`` runs the paper's iteration P zeta^{k+1} = (Delta P +
+    Delta R) zeta^k + gbar instead.  dmu holds one entry per obstacle, then
+    (with self-collision on) the self-friction coefficient's."""
     h = model.h
     m = model.m
     x1 = rec.x1
@@ -598,12 +772,10 @@ def backward_step(model: Model, rec: StepRecord, gx: np.ndarray, gv: np.ndarray,
     dP = delta_P(model, x1)
     PmM = _kron3(h * h * model.K_s)
     Hm = (PmM - dP).tocsr()                                   # h^2 Hess W(x_{n+1})
-    C = rec.contact.nodes.size
-    Tb = np.tile(np.eye(3), (m, 1, 1))
-    if C:
-        Tb[rec.contact.nodes] = contact_jacobian_blocks(rec.contact, h)
-    TT = _blockdiag3(np.transpose(Tb, (0, 2, 1)))             # T^T
     Mk = sp.diags(np.repeat(model.mass, 3))
+    Minv = sp.diags(1.0 / np.repeat(model.mass, 3))
+    T = step_contact_jacobian(model, rec)
+    TT = (Mk @ T @ Minv).T.tocsr()                            # Tc^T
     Aadj = (Mk + Hm @ TT).tocsc()
     gb = gbar.reshape(-1)
     if direct:
@@ -620,38 +792,17 @@ def backward_step(model: Model, rec: StepRecord, gx: np.ndarray, gv: np.ndarray,
     p, q = local_projection(model, x1)
     Az = model.A @ z3
     dw = h * np.sum(Az * (p - q), axis=1)
-    dmu = np.zeros(len(model.obstacles))
+    self_on = model.self_d > 0
+    dmu = np.zeros(len(model.obstacles) + (1 if self_on else 0))
     ct = rec.contact
     act = ct.mode != TAKEOFF
     if np.any(act):
         j = ct.nodes[act]
         nrm = ct.normal[act]
-        phi = ct.gap[act]
-        ub = ct.ubar[act]
-        mu = ct.mu[act]
         lam = model.mass[j, None] * zeta3[j]                  # lambda = M zeta
-        I3 = np.eye(3)[None]
-        un = np.sum(nrm * ub, axis=1)
-        a = un + phi / h
-        ut = ub - un[:, None] * nrm
-        tau = np.linalg.norm(ut, axis=1)
-        sl = ct.mode[act] == SLIP
-        t = np.zeros_like(ut)
-        t[sl] = ut[sl] / tau[sl, None]
-        # d v / d phi: stick -n/h, slip (-n + mu t)/h
-        dv_dphi = (-nrm + (mu * sl)[:, None] * t) / h
-        # d v / d n (ubar, phi held fixed)
-        dv_dn = -(phi / h)[:, None, None] * I3 * np.ones((j.size, 1, 1))
-        if np.any(sl):
-            nn, ubs, ts, taus, As, mus = nrm[sl], ub[sl], t[sl], tau[sl], a[sl], mu[sl]
-            dut_dn = -un[sl][:, None, None] * I3 - nn[:, :, None] * ubs[:, None, :]
-            dt_dut = (I3 - ts[:, :, None] * ts[:, None, :]) / taus[:, None, None]
-            dv_dn[sl] += (dut_dn + mus[:, None, None] * ts[:, :, None] * ubs[:, None, :]
-                          + (mus * As)[:, None, None] * np.einsum('cij,cjk->cik', dt_dut, dut_dn))
-            np.add.at(dmu, ct.obstacle[act][sl], np.sum(lam[sl] * ts, axis=1) * As)
-        dphi = np.sum(lam * dv_dphi, axis=1)
+        dphi, dn, dmu_c = frame_gradients(lam, nrm, ct.gap[act], ct.ubar[act], ct.mu[act], ct.mode[act], h)
+        np.add.at(dmu, ct.obstacle[act], dmu_c)
         np.add.at(dx, j, dphi[:, None] * nrm)                 # grad phi = n (plane, sphere)
-        dn = np.einsum('cji,cj->ci', dv_dn, lam)              # (dv/dn)^T lambda
         for oi, o in enumerate(model.obstacles):
             if o.kind == MESH:
                 # dn/dx of the frame at x_n: 0 on a face, (I - n n^T)/phi at a
@@ -680,6 +831,22 @@ def backward_step(model: Model, rec: StepRecord, gx: np.ndarray, gv: np.ndarray,
             dns = dn[so]
             proj = dns - np.sum(ns * dns, axis=1)[:, None] * ns   # (I - n n^T) dn
             np.add.at(dx, j[so], proj / r[:, None])
+    ps = rec.pairs
+    if ps is not None and ps.i.size and np.any(ps.mode != TAKEOFF):
+        # pairs: v_i, v_j move by +-(m_ij/m) du, so the multiplier of the relative
+        # update is m_ij (zeta_i - zeta_j); phi = |x_i - x_j| - d and
+        # n = (x_i - x_j)/|x_i - x_j| give d phi/dx_i = n, dn/dx_i = (I - n n^T)/r,
+        # and the negatives for x_j
+        a_ = ps.mode != TAKEOFF
+        i, j = ps.i[a_], ps.j[a_]
+        nrm = ps.normal[a_]
+        lam = ps.mred[a_, None] * (zeta3[i] - zeta3[j])
+        dphi, dn, dmu_c = frame_gradients(lam, nrm, ps.gap[a_], ps.ubar[a_],
+                                          np.full(i.size, model.self_mu), ps.mode[a_], h)
+        g = dphi[:, None] * nrm + (dn - np.sum(nrm * dn, axis=1)[:, None] * nrm) / ps.dist[a_, None]
+        np.add.at(dx, i, g)
+        np.add.at(dx, j, -g)
+        dmu[-1] += np.sum(dmu_c)
     return dx, dv, dw, dmu, iters
 
 
@@ -706,7 +873,7 @@ class Gradients:
     dx0: np.ndarray
     dv0: np.ndarray
     dw: np.ndarray          # per constraint: springs first, then bending
-    dmu: np.ndarray         # per obstacle
+    dmu: np.ndarray         # per obstacle, then self-friction (with self-collision on)
     dregion: Optional[np.ndarray] = None
     dforce: Optional[np.ndarray] = None         # (m, 3) dL/dF
     dforce_scale: Optional[np.ndarray] = None   # (T,) dL/ds_n
@@ -739,7 +906,7 @@ def backward(model: Model, recs: List[StepRecord], dL_dxT: np.ndarray, dL_dvT=No
         gx = gx + dL_dx_steps[len(recs)]
     gv = np.zeros_like(gx) if dL_dvT is None else np.asarray(dL_dvT, float).copy()
     dw = np.zeros(model.nc)
-    dmu = np.zeros(len(model.obstacles))
+    dmu = np.zeros(len(model.obstacles) + (1 if model.self_d > 0 else 0))
     T = len(recs)
     dF = np.zeros((model.m, 3))
     ds = np.zeros(T)

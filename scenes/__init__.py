@@ -74,6 +74,11 @@ class Scene:
     # (newtons) during step n (force_scale None: 1 at every step).
     force: Optional[np.ndarray] = None           # (m, 3)
     force_scale: Optional[np.ndarray] = None     # (steps,)
+    # Node-node self-collision: thickness d (m; 0 = off), detection radius on the
+    # predictor (m; 0 = the thickness) and friction coefficient.
+    self_thickness: float = 0.0
+    self_radius: float = 0.0
+    self_mu: float = 0.0
     # Loss description (inputs only; each side evaluates it itself).
     loss: str = "centroid"          # "centroid" | "apex"
     target: Optional[np.ndarray] = None          # centroid target (3,)
@@ -363,6 +368,42 @@ def request_scene(n: int, steps: int, sphere: bool, seed: int = 0) -> Scene:
     s = mixed_grid(rng, n, steps, 1.0e3, 0.5, sphere)
     s.seed = seed
     return s
+
+
+def stacked_sheets(n: int = 6, steps: int = 12, gap: float = 0.012, shift: float = 0.1,
+                   k: float = 200.0, self_mu: float = 0.5, seed: int = 0,
+                   v0_top=(0.08, -0.5, 0.03), h: float = 1.0 / 120.0, ground: bool = False,
+                   pinned: bool = True) -> Scene:
+    """Two aligned n x n sheets (spacing 2 cm): the bottom one pinned at its
+    four corners 0.3 m above the ground plane, the top one hanging gap metres
+    above it, shifted by shift grid spacings along x and z and moving at v0_top
+    (plus noise).  Node masses vary by +-30 % so that pairs have unequal
+    masses.  Self-collision thickness 0.6 grid spacings, detection radius 1.5
+    times that (pairs at rest at the thickness stay detected).  ground: the bottom
+    sheet lies 2 mm above the plane instead, unpinned; pinned=False: no pins
+    (both sheets fly free)."""
+    rng = np.random.default_rng(seed)
+    a = 0.02
+    side = a * (n - 1)
+    y0 = 0.002 if ground else 0.3
+    Xb, tris, edges = grid_mesh(n, side, (0.0, y0, 0.0))
+    Xt = Xb + np.array([shift * a, gap, shift * a])
+    mb = Xb.shape[0]
+    X = np.concatenate([Xb, Xt]) + rng.normal(0.0, 2e-4, (2 * mb, 3))
+    tris2 = np.concatenate([tris, tris + mb]).astype(np.int32)
+    edges2 = np.concatenate([edges, edges + mb]).astype(np.int32)
+    m = 2 * mb
+    v0 = np.zeros((m, 3))
+    v0[mb:] = np.asarray(v0_top, float) + 0.05 * rng.normal(0.0, 1.0, (mb, 3))
+    mass = AREAL_DENSITY * side * side / mb * np.exp(rng.uniform(-0.3, 0.3, m)) + 1e-4
+    attach = (np.array([0, n - 1, n * (n - 1), n * n - 1], np.int32) if pinned and not ground
+              else np.zeros(0, np.int32))
+    return Scene(
+        name=f"stacked{n}x{n}", X=X, tris=tris2, edges=edges2,
+        edge_stiffness=k * np.exp(rng.uniform(-0.3, 0.3, edges2.shape[0])),
+        node_mass=mass, v0=v0, steps=steps, h=h, attach=attach,
+        obstacles=[Obstacle(PLANE, (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 0.0, 0.4)],
+        self_thickness=0.6 * a, self_radius=0.9 * a, self_mu=self_mu, target=_centroid_target(rng, X), seed=seed)
 
 
 def tiny_scene(n: int = 3, steps: int = 10, obstacle: Optional[str] = "plane",

@@ -794,3 +794,152 @@ def test_warm_start_starts_from_the_previous_impulses():
     cold = O.rollout(model, iters=1)
     for a, b in zip(cold[1:], warm[1:]):
         assert np.allclose(a.contact.ubar, b.contact.ubar, rtol=1e-12, atol=1e-12 * np.abs(a.contact.ubar).max())
+
+
+# ------------------------------------------------------------------ node-node self-collision
+
+def free_particles(X, v0, mass, d, radius, mu, h=0.01, steps=1):
+    """Particles with no springs or bending, node-node contact on."""
+    X = np.asarray(X, float)
+    return scenes.Scene(
+        name="pair", X=X, tris=np.zeros((0, 3), np.int32), edges=np.zeros((0, 2), np.int32),
+        edge_stiffness=np.zeros(0), node_mass=np.asarray(mass, float), v0=np.asarray(v0, float), h=h,
+        steps=steps, bend_weight=0.0, self_thickness=d, self_radius=radius, self_mu=mu)
+
+
+def test_two_particle_pair_closed_form():
+    # P = M: one global solve is exact, so two PD iterations reach the fixed point
+    rows = [ln.split() for ln in open(os.path.join(GOLDEN, "two_particle_pair.txt"))
+            if ln.strip() and not ln.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        mu = float(r[1])
+        v0 = np.array(r[2:8], float).reshape(2, 3)
+        want = np.array(r[8:14], float).reshape(2, 3)
+        sc = free_particles([[0, 0.105, 0], [0, 0, 0]], v0, [1.0, 3.0], 0.1, 0.15, mu)
+        rec = O.forward_step(O.Model(sc), sc.X, v0, 0, iters=3)
+        assert rec.pairs.i.tolist() == [0] and rec.pairs.j.tolist() == [1], r[0]
+        assert int(rec.pairs.mode[0]) == int(r[14]), r[0]
+        assert np.allclose(rec.v1, want, rtol=0, atol=1e-12), (r[0], rec.v1, want)
+
+
+def test_pairs_are_mutual_nearest_outside_stencils_and_obstacle_contacts():
+    # brute force over a tiny configuration: three particles on a line (B is
+    # nearest to both A and C, A-B the closer pair), a fourth one far away, and
+    # a cloth whose own nodes are close but share stencils
+    sc = free_particles([[0, 0, 0], [0.03, 0, 0], [0.07, 0, 0], [1, 0, 0]], np.zeros((4, 3)),
+                        [1.0, 1.0, 1.0, 1.0], 0.05, 0.08, 0.3)
+    rec = O.forward_step(O.Model(sc), sc.X, sc.v0, 0, iters=2)
+    assert list(zip(rec.pairs.i.tolist(), rec.pairs.j.tolist())) == [(0, 1)]
+    for kw in (dict(), dict(pinned=False, shift=0.0), dict(ground=True)):
+        sc = scenes.stacked_sheets(n=4, **kw)
+        model = O.Model(sc)
+        x, v = sc.X, sc.v0
+        for n in range(3):
+            rec = O.forward_step(model, x, v, n)
+            y = O.inertial_predictor(model, x, v, n)
+            busy = set(rec.contact.nodes.tolist())
+            shared = model.shares_stencil()
+            m = model.m
+            nearest = []
+            for i in range(m):
+                best, bj = None, -1
+                for j in range(m):
+                    if j == i or i in busy or j in busy or shared[i, j] or np.all(x[i] == x[j]):
+                        continue
+                    dd = sum((y[i, c] - y[j, c]) ** 2 for c in range(3))
+                    if dd <= model.self_r ** 2 and (best is None or dd < best):
+                        best, bj = dd, j
+                nearest.append(bj)
+            want = [(i, nearest[i]) for i in range(m) if nearest[i] > i and nearest[nearest[i]] == i]
+            assert list(zip(rec.pairs.i.tolist(), rec.pairs.j.tolist())) == want, (kw, n)
+            if kw.get("ground") and n > 0:
+                assert rec.contact.nodes.size > 0
+            x, v = rec.x1, rec.v1
+
+
+def test_pair_impulses_conserve_momentum_and_hold_the_thickness():
+    # free sheets (no pins, no obstacle contact): springs and pair impulses are
+    # internal, so total momentum changes by h sum m g per step; a pair in stick
+    # or slip ends each converged step at normal separation d
+    sc = scenes.stacked_sheets(n=4, steps=6, pinned=False)
+    model = O.Model(sc)
+    recs = O.rollout(model, tol=1e-12, max_iters=50000)
+    modes = np.concatenate([r.pairs.mode for r in recs])
+    assert {1, 2, 3} <= set(modes.tolist())                    # take-off, stick and slip all occur
+    M = model.mass[:, None]
+    dp_want = model.h * np.sum(model.mass) * np.asarray(model.g)
+    for r in recs:
+        dp = np.sum(M * r.v1, axis=0) - np.sum(M * r.v0, axis=0)
+        assert np.allclose(dp, dp_want, rtol=0, atol=1e-12 * np.sum(M)), (dp, dp_want)
+        ps = r.pairs
+        act = ps.mode != O.TAKEOFF
+        sep = np.sum(ps.normal * (r.x1[ps.i] - r.x1[ps.j]), axis=1)
+        assert np.allclose(sep[act], model.self_d, rtol=0, atol=1e-12)
+        assert np.all(sep[~act] >= model.self_d - 1e-12)
+
+
+def test_self_collision_off_changes_nothing():
+    sc = scenes.stacked_sheets(n=4, steps=3)
+    on = O.rollout(O.Model(sc))
+    sc.self_thickness = 0.0
+    off = O.rollout(O.Model(sc))
+    assert sum(r.pairs.i.size for r in on) > 0 and sum(r.pairs.i.size for r in off) == 0
+    sc2 = scenes.tiny_scene(3, steps=4, obstacle="plane", height=0.005)
+    a = O.rollout(O.Model(sc2))
+    assert all(r.pairs.i.size == 0 for r in a)
+
+
+def test_self_adjoint_fixed_point_equals_direct_solve():
+    sc = scenes.stacked_sheets(n=4, steps=4, pinned=False)
+    model = O.Model(sc)
+    recs = O.rollout(model, tol=1e-12, max_iters=50000)
+    rng = np.random.default_rng(3)
+    for n in range(len(recs)):
+        assert recs[n].pairs.i.size > 0
+        gx, gv = rng.normal(size=(2, model.m, 3))
+        d = O.backward_step(model, recs[n], gx, gv, n, direct=True)
+        it = O.backward_step(model, recs[n], gx, gv, n, direct=False, iter_tol=1e-14)
+        for a, b in zip(d[:4], it[:4]):
+            assert np.allclose(a, b, rtol=1e-8, atol=1e-10 * max(1.0, np.abs(a).max()))
+
+
+def self_modes_of(recs):
+    return [tuple(r.pairs.i.tolist()) + tuple(r.pairs.j.tolist()) + tuple(r.pairs.mode.tolist())
+            + tuple(r.contact.nodes.tolist()) + tuple(r.contact.mode.tolist()) for r in recs]
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_self_collision_gradients_match_central_finite_differences(seed):
+    # the top sheet lands on the pinned one: pairs in slip, then stick; steps
+    # of 1e-7 keep the central differences clear of the nearest mode boundary
+    sc = scenes.stacked_sheets(n=3, steps=4, k=50.0, seed=seed)
+    model, recs, L, g = converged_loss(sc, tol=1e-13)
+    assert sum(int(np.sum(r.pairs.mode != O.TAKEOFF)) for r in recs) > 0
+    G = O.backward(model, recs, g)
+    base = self_modes_of(recs)
+    rng = np.random.default_rng(5)
+
+    def fd(eps, **kw):
+        _, rp, Lp, _ = converged_loss(sc, tol=1e-13, **{k: v[0] for k, v in kw.items()})
+        _, rm, Lm, _ = converged_loss(sc, tol=1e-13, **{k: v[1] for k, v in kw.items()})
+        assert self_modes_of(rp) == base and self_modes_of(rm) == base
+        return (Lp - Lm) / (2 * eps)
+
+    e = 1e-7
+    d = rng.normal(size=sc.X.shape)
+    val = fd(e, x0=(sc.X + e * d, sc.X - e * d))
+    assert abs(val - np.sum(G.dx0 * d)) <= 1e-5 * abs(val) + 1e-12, (val, np.sum(G.dx0 * d))
+    d = rng.normal(size=sc.X.shape)
+    val = fd(e, v0=(sc.v0 + e * d, sc.v0 - e * d))
+    assert abs(val - np.sum(G.dv0 * d)) <= 1e-5 * abs(val) + 1e-12, (val, np.sum(G.dv0 * d))
+    k = sc.edge_stiffness
+    d = rng.normal(size=k.shape) * k
+    e = 1e-4
+    val = fd(e, edge_stiffness=(k + e * d, k - e * d))
+    ad = np.sum(G.dw[:model.n_spring] * d)
+    assert abs(val - ad) <= 1e-4 * abs(val) + 1e-14, (val, ad)
+    e = 1e-6
+    mu = sc.self_mu
+    val = fd(e, self_mu=(mu + e, mu - e))
+    assert abs(val - G.dmu[-1]) <= 1e-5 * abs(val) + 1e-10, (val, G.dmu[-1])
