@@ -159,6 +159,21 @@ typedef struct {
  *                  zero impulses); the converged state does not depend on it,
  *                  a fixed pd_iters result does.  Checkpoints keep the
  *                  impulses, so replayed segments reproduce their records.
+ *  self_thickness  node-node self-collision (Sec. 4.2, Extensions; 0: off):
+ *                  thickness d (m).  Each step, on the inertial predictor y,
+ *                  every node outside the obstacle contact set takes as
+ *                  partner its nearest node j with |y_i - y_j| <= self_radius
+ *                  (0: d) that shares no spring or bending stencil with it and
+ *                  sits elsewhere at x_n (ties to the lower caller id);
+ *                  mutually nearest nodes form a pair.  The pair's normal is
+ *                  n = (x_i - x_j)/|x_i - x_j| at x_n (i the lower caller id),
+ *                  its gap |x_i - x_j| - d; the law of eqn contact_all acts on
+ *                  v_i - v_j with the reduced mass m_i m_j / (m_i + m_j) and
+ *                  friction self_mu, impulse +f on i and -f on j.  Needs
+ *                  SIM_ADJ_ITERATIVE (SIM_EINVAL otherwise: a pair's adjoint
+ *                  block lies outside the direct factor's pattern); a rollout
+ *                  runs on one workgroup per handle.  The pair search scans all
+ *                  nodes (O(n^2) per step).
  *  (The tolerance rule of fwd_tol measures the change of the velocities and
  *  of the contact impulses in velocity units, |f^{k+1} - f^k| / m_j.) */
 typedef struct {
@@ -185,6 +200,9 @@ typedef struct {
     int32_t               adj_solver;
     int32_t               adj_window;
     int32_t               warm_start;
+    double                self_thickness;
+    double                self_radius;
+    double                self_mu;
 } sim_params_t;
 
 /* Gradient outputs (caller-allocated device arrays; any may be NULL). */
@@ -200,6 +218,7 @@ typedef struct {
                          sim_set_external_force); zeros when no force is set  */
     double *dforce_scale; /* [T] dL/ds_n of its per-step multipliers over the
                          T recorded steps; zeros when no force is set          */
+    double *dmu_self; /* [1] dL/d(self_mu) of node-node contacts (0 when off)  */
 } sim_grads_t;
 
 typedef struct {
@@ -317,6 +336,13 @@ int sim_state(const sim_t *sim, int32_t n, double *x_dev, double *v_dev);
 
 /* Contact modes (SIM_MODE_*) of recorded step n, caller node order, host array [n_nodes]. */
 int sim_modes(const sim_t *sim, int32_t n, uint8_t *modes_host);
+
+/* Node-node contact pairs of recorded step n (Sec. 4.2, Extensions): host
+ * array partner_host [n_nodes], caller node order and ids; -1 for a node in no
+ * pair.  A pair's nodes carry its contact mode in sim_modes.  With
+ * self-collision off every entry is -1.  SIM_ESTATE without a recorded
+ * rollout, SIM_EINVAL for n out of range. */
+int sim_self_pairs(const sim_t *sim, int32_t n, int32_t *partner_host);
 
 /* Counters of the last forward pass and backward pass, sizes of the handle's
  * tables and factors (synchronises the handle's stream). */

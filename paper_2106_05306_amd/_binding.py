@@ -45,12 +45,14 @@ class SimParams(Structure):
                 ("n_obstacles", c_int32), ("obstacles", POINTER(SimObstacle)), ("precision", c_int32),
                 ("adj_tol", c_double), ("adj_max_iters", c_int32), ("checkpoint_every", c_int32),
                 ("adj_restart", c_int32), ("adj_solver", c_int32), ("adj_window", c_int32),
-                ("warm_start", c_int32)]
+                ("warm_start", c_int32), ("self_thickness", c_double), ("self_radius", c_double),
+                ("self_mu", c_double)]
 
 
 class SimGrads(Structure):
     _fields_ = [("dx0", c_void_p), ("dv0", c_void_p), ("dw_edge", c_void_p), ("dw_bend", c_void_p),
-                ("dregion", c_void_p), ("dmu", c_void_p), ("dforce", c_void_p), ("dforce_scale", c_void_p)]
+                ("dregion", c_void_p), ("dmu", c_void_p), ("dforce", c_void_p), ("dforce_scale", c_void_p),
+                ("dmu_self", c_void_p)]
 
 
 class SimStats(Structure):
@@ -94,6 +96,7 @@ def lib():
                                            POINTER(SimGrads)]),
             "sim_state": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
             "sim_modes": (c_int32, [c_void_p, c_int32, POINTER(c_uint8)]),
+            "sim_self_pairs": (c_int32, [c_void_p, c_int32, POINTER(c_int32)]),
             "sim_stats": (c_int32, [c_void_p, POINTER(SimStats)]),
             "sim_step_stats": (c_int32, [c_void_p, c_int32, c_int32_p]),
             "sim_batch_forward": (c_int32, [POINTER(c_void_p), c_int32, c_int32_p, POINTER(c_void_p),

@@ -488,6 +488,10 @@ void build_device(sim *s) {
         D.mw_absent = e && std::atoi(e) > 0 ? 1 : 0;
     }
     D.warm_start = hm.warm_start;
+    D.self_on = hm.self_d > 0 ? 1 : 0;
+    D.self_d = hm.self_d;
+    D.self_r2 = hm.self_r * hm.self_r;
+    D.self_mu = hm.self_mu;
     D.adj_tol = hm.adj_tol;
     for (int d = 0; d < 3; ++d) {
         D.g[d] = hm.g[d];
@@ -715,7 +719,7 @@ void build_device(sim *s) {
         std::vector<int> kids;
         for (int sn = 0; sn < ns; ++sn)
             if (parent[sn] >= 0 && parent[sn] == root) kids.push_back(sn);
-        const int want = mw_workgroups_default(m);
+        const int want = D.self_on ? 0 : mw_workgroups_default(m);   // pairs may join any two subtrees
         int W = std::min<int>({want, (int)kids.size(), kMwMax});
         bool ok = nroot == 1 && L >= 2 && W >= 2 && sns[root] <= kMwRootMax && hm.sup_level[root] == L - 1;
         for (int sn = 0; sn < ns && ok; ++sn)
@@ -1111,7 +1115,7 @@ void build_device(sim *s) {
     D.adj_pq = zeros<double>(s, 3 * (size_t)std::max(nca, 1));
     D.tblk = zeros<double>(s, 9 * (size_t)m);
     D.dw = zeros<double>(s, std::max(hm.nc, 1));
-    D.dmu = zeros<double>(s, kMaxObstacles);
+    D.dmu = zeros<double>(s, kMaxObstacles + 1);
     D.counters = zeros<int64_t>(s, 8);
     D.kry_m = std::min(hm.adj_restart, kKryM);
     D.kry = zeros<double>(s, (size_t)(D.kry_m + 1) * v3);
@@ -1127,6 +1131,29 @@ void build_device(sim *s) {
     if (!hm.region.empty()) s->d_region = upload(s, hm.region);
     s->d_bend_centers = upload(s, hm.bend_center);
     s->d_modes_tmp = zeros<uint8_t>(s, m);
+    if (D.self_on) {
+        // node-node contact: caller ids, the nodes sharing a stencil with each
+        // node (new order, every spring and bending stencil), search buffers
+        D.caller_id = s->d_perm;
+        std::vector<std::vector<int32_t>> nb(m);
+        for (int c = 0; c < hm.nc; ++c)
+            for (int p = hm.c_ptr[c]; p < hm.c_ptr[c + 1]; ++p)
+                for (int q = hm.c_ptr[c]; q < hm.c_ptr[c + 1]; ++q)
+                    if (p != q) nb[iperm[hm.c_node[p]]].push_back(iperm[hm.c_node[q]]);
+        std::vector<int32_t> ap(1, 0), ac;
+        for (int i = 0; i < m; ++i) {
+            std::sort(nb[i].begin(), nb[i].end());
+            nb[i].erase(std::unique(nb[i].begin(), nb[i].end()), nb[i].end());
+            ac.insert(ac.end(), nb[i].begin(), nb[i].end());
+            ap.push_back((int32_t)ac.size());
+        }
+        if (ac.empty()) ac.push_back(-1);
+        D.adj_ptr = upload(s, ap);
+        D.adj_col = upload(s, ac);
+        D.ybuf = zeros<double>(s, v3);
+        D.cand = zeros<int32_t>(s, m);
+        D.partner = zeros<int32_t>(s, m);
+    }
     s->dd = (SimDev *)dev_alloc(s, sizeof(SimDev));
     // LDS placement: the solve vectors first, then the update buffer, then x_n
     int dev = 0, maxlds = 0;
@@ -1187,12 +1214,15 @@ void ensure_records(sim *s, int cap) {
     dev_release(s, s->hd.rec_ubar);
     dev_release(s, s->hd.rec_mode);
     dev_release(s, s->hd.rec_obst);
+    dev_release(s, s->hd.rec_partner);
+    s->hd.rec_partner = nullptr;
     const size_t v3 = 3 * (size_t)s->hd.m;
     s->hd.rec_x = (double *)dev_alloc(s, (cap + 1) * v3 * sizeof(double));
     s->hd.rec_v = (double *)dev_alloc(s, (cap + 1) * v3 * sizeof(double));
     s->hd.rec_ubar = (double *)dev_alloc(s, cap * v3 * sizeof(double));
     s->hd.rec_mode = (uint8_t *)dev_alloc(s, (size_t)cap * s->hd.m);
     s->hd.rec_obst = (int8_t *)dev_alloc(s, (size_t)cap * s->hd.m);
+    if (s->hd.self_on) s->hd.rec_partner = (int32_t *)dev_alloc(s, (size_t)cap * s->hd.m * sizeof(int32_t));
     s->hd.rec_cap = cap;
 }
 
@@ -1652,7 +1682,7 @@ int finish_forward(sim *s, int n_steps, double *xT_dev, double *vT_dev) {
 // recorded steps (weights, friction, external force).
 int zero_param_grads(sim *s) {
     int rc = hip_err(launch_fill(s->hd.dw, 0.0, std::max(s->hm.nc, 1), s->stream));
-    if (!rc) rc = hip_err(launch_fill(s->hd.dmu, 0.0, kMaxObstacles, s->stream));
+    if (!rc) rc = hip_err(launch_fill(s->hd.dmu, 0.0, kMaxObstacles + 1, s->stream));
     if (!rc && s->hd.fext) {
         if (!s->dfext_buf) s->dfext_buf = (double *)dev_alloc(s, 3 * (size_t)s->hd.m * sizeof(double));
         if (s->dfscale_cap < std::max(s->T, 1)) {
@@ -1836,6 +1866,7 @@ int write_grads(sim *s, const sim_grads_t *out) {
                                         (int)s->hm.region_scale.size(), out->dregion, s->stream));
     if (!rc && out->dmu && s->hd.n_obst)
         rc = copy_d2d(s, out->dmu, s->hd.dmu, s->hd.n_obst * sizeof(double));
+    if (!rc && out->dmu_self) rc = copy_d2d(s, out->dmu_self, s->hd.dmu + kMaxObstacles, sizeof(double));
     if (!rc && out->dforce) {
         if (s->hd.fext) rc = hip_err(launch_permute3(s->hd.dfext, out->dforce, s->d_perm, m, true, s->stream));
         else rc = hip_err(launch_fill(out->dforce, 0.0, 3 * (int64_t)m, s->stream));
@@ -1979,6 +2010,38 @@ int sim_modes(const sim_t *cs, int32_t n, uint8_t *modes_host) {
     });
 }
 
+int sim_self_pairs(const sim_t *cs, int32_t n, int32_t *partner_host) {
+    sim *s = const_cast<sim *>(cs);
+    if (!s || !partner_host) return SIM_EINVAL;
+    if (s->T < 1) return SIM_ESTATE;
+    if (n < 0 || n >= s->T) return SIM_EINVAL;
+    const int k = seg_len(s);
+    return guarded([&] {
+        const int m = s->hd.m;
+        if (!s->hd.self_on) {
+            std::fill(partner_host, partner_host + m, -1);
+            return SIM_OK;
+        }
+        int rc = SIM_OK;
+        int slot = n;
+        if (k > 0) {                        // recompute the segment holding step n
+            const int seg = n / k, a = seg * k, b = std::min(s->T, a + k);
+            rc = load_ckpt(s, seg);
+            if (!rc) rc = run_forward_range(s, a, b);
+            if (!rc) rc = mw_check(s);
+            slot = n - a;
+        }
+        std::vector<int32_t> p(m);
+        if (!rc)
+            rc = hip_err(hipMemcpyAsync(p.data(), s->hd.rec_partner + (size_t)slot * m, m * sizeof(int32_t),
+                                        hipMemcpyDeviceToHost, s->stream));
+        if (!rc) rc = hip_err(hipStreamSynchronize(s->stream));
+        if (!rc)
+            for (int i = 0; i < m; ++i) partner_host[s->hm.perm[i]] = p[i] >= 0 ? s->hm.perm[p[i]] : -1;
+        return rc;
+    });
+}
+
 int sim_stats(const sim_t *cs, sim_stats_t *out) {
     if (!cs || !out) return SIM_EINVAL;
     const sim *s = cs;
@@ -2053,6 +2116,7 @@ int sim_step_stats(const sim_t *cs, int32_t n, int32_t *out) {
 // Scratch layout of the allocation-free forward (byte offsets, 256-aligned).
 struct NoallocLayout {
     size_t desc, ctr, red, x, v, vk, vk1, rhs, b0, f, ubar, cfr, wp, ubuf, rx, rv, rub, mode, cobst, rmode, robst;
+    size_t ybuf, cand, partner, rpartner;       // node-node contact (self-collision on)
     size_t total;
 };
 
@@ -2086,6 +2150,12 @@ NoallocLayout noalloc_layout(const sim *s) {
     L.cobst = take(m);
     L.rmode = take(m);
     L.robst = take(m);
+    if (s->hd.self_on) {
+        L.ybuf = take(3 * m * d);
+        L.cand = take(m * sizeof(int32_t));
+        L.partner = take(m * sizeof(int32_t));
+        L.rpartner = take(m * sizeof(int32_t));
+    }
     L.total = o;
     return L;
 }
@@ -2124,6 +2194,12 @@ int sim_forward_noalloc(sim_t *s, int32_t n_steps, double *xT_dev, double *vT_de
     d.cobst = (int8_t *)(b + L.cobst);
     d.rec_mode = (uint8_t *)(b + L.rmode);
     d.rec_obst = (int8_t *)(b + L.robst);
+    if (d.self_on) {
+        d.ybuf = (double *)(b + L.ybuf);
+        d.cand = (int32_t *)(b + L.cand);
+        d.partner = (int32_t *)(b + L.partner);
+        d.rec_partner = (int32_t *)(b + L.rpartner);
+    }
     d.rec_cap = 1;
     d.rec_ring = 1;
     d.step_info = nullptr;

@@ -56,6 +56,18 @@ int HostModel::build(const sim_mesh_t *mesh, const sim_params_t *p) {
     adj_solver = p->adj_solver;
     adj_window = std::max(0, p->adj_window);
     if (adj_solver != SIM_ADJ_ITERATIVE && adj_solver != SIM_ADJ_DIRECT) { error = "bad adj_solver"; return SIM_EINVAL; }
+    self_d = p->self_thickness;
+    self_r = p->self_radius > 0 ? p->self_radius : p->self_thickness;
+    self_mu = p->self_mu;
+    if (!(self_d >= 0) || !std::isfinite(self_d) || !(p->self_radius >= 0) || !std::isfinite(p->self_radius) ||
+        !(self_mu >= 0) || !std::isfinite(self_mu)) {
+        error = "self-collision thickness, radius and friction must be finite and >= 0";
+        return SIM_EINVAL;
+    }
+    if (self_d > 0 && adj_solver == SIM_ADJ_DIRECT) {
+        error = "self-collision needs the iterative adjoint (pair blocks lie outside the factor's pattern)";
+        return SIM_EINVAL;
+    }
     if (p->n_obstacles < 0 || p->n_obstacles > 8 || (p->n_obstacles > 0 && !p->obstacles)) {
         error = "0..8 obstacles";
         return SIM_EINVAL;

@@ -21,6 +21,7 @@ struct HostModel {
     int pd_iters = 20, fwd_max_iters = 0, adj_max_iters = 500, precision = SIM_FP64;
     double fwd_tol = 0, adj_tol = 1e-10;
     int warm_start = 0;
+    double self_d = 0, self_r = 0, self_mu = 0;   // node-node contact: thickness, detection radius, friction
     int checkpoint_every = 0, adj_restart = 60, adj_solver = SIM_ADJ_ITERATIVE, adj_window = 0;
     std::vector<sim_obstacle_t> obstacles;  // mesh pointers cleared; geometry in obst_tri
     // triangle-mesh obstacles: per obstacle, per triangle its vertices a, b, c,

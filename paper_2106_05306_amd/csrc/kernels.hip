@@ -717,9 +717,12 @@ __device__ __forceinline__ void fwd_prologue_node(const SimDev &S, int i, double
         attach_target(S, G(S.att_rest) + 3 * as, t1, tg);
         for (int d = 0; d < 3; ++d) b[d] += h * S.w_att * tg[d];
     }
+    if (S.self_on)
+        for (int d = 0; d < 3; ++d) G(S.ybuf)[3 * i + d] = y[d];
     // impulses: zero, or (warm start) the previous step's on the nodes of
-    // this step's contact set (zero where the node was not in contact)
-    const bool keep = S.warm_start && contact;
+    // this step's contact set (zero where the node was not in contact; with
+    // self-collision every node keeps its impulse until the pairs are known)
+    const bool keep = S.warm_start && (contact || S.self_on);
     for (int d = 0; d < 3; ++d) {
         G(S.b0)[3 * i + d] = b[d];
         if (!keep) G(S.f)[3 * i + d] = 0.0;
@@ -729,12 +732,116 @@ __device__ __forceinline__ void fwd_prologue_node(const SimDev &S, int i, double
         for (int d = 0; d < 3; ++d) XN[3 * i + d] = xi[d];
 }
 
+// ------------------------------------------------------------------ node-node self-collision
+
+// Nodes i and j share a constraint stencil (never a pair).
+__device__ __forceinline__ bool self_adjacent(const SimDev &S, int i, int j) {
+    for (int p = G(S.adj_ptr)[i]; p < G(S.adj_ptr)[i + 1]; ++p)
+        if (G(S.adj_col)[p] == j) return true;
+    return false;
+}
+
+// Nearest eligible node of node i on the predictor (Sec. 4.2, Extensions):
+// both nodes outside the obstacle contact set, not sharing a stencil, apart at
+// x_n, |y_i - y_j|^2 <= r^2 (squared distances summed over x, y, z in that
+// order, unfused); ties to the lower caller id.  Brute force over all nodes
+// (every lane of a wavefront reads the same y_j).
+__device__ __forceinline__ void self_nearest(const SimDev &S, int i, auto XN) {
+#pragma clang fp contract(off)
+    int best = -1;
+    double bd = 0.0;
+    if (G(S.mode)[i] == FREE) {
+        const double y0 = G(S.ybuf)[3 * i], y1 = G(S.ybuf)[3 * i + 1], y2 = G(S.ybuf)[3 * i + 2];
+        const int m = S.m;
+        for (int j = 0; j < m; ++j) {
+            const double e0 = y0 - G(S.ybuf)[3 * j], e1 = y1 - G(S.ybuf)[3 * j + 1], e2 = y2 - G(S.ybuf)[3 * j + 2];
+            const double d2 = e0 * e0 + e1 * e1 + e2 * e2;
+            if (!(d2 <= S.self_r2) || j == i || G(S.mode)[j] != FREE) continue;
+            if (best >= 0 && (d2 > bd || (d2 == bd && G(S.caller_id)[j] > G(S.caller_id)[best]))) continue;
+            const double x0 = XN[3 * i] - XN[3 * j], x1 = XN[3 * i + 1] - XN[3 * j + 1], x2 = XN[3 * i + 2] - XN[3 * j + 2];
+            if (!(x0 * x0 + x1 * x1 + x2 * x2 > 0.0) || self_adjacent(S, i, j)) continue;
+            best = j;
+            bd = d2;
+        }
+    }
+    G(S.cand)[i] = best;
+}
+
+// Pairs are the mutually nearest nodes; a pair node enters the contact set.
+// Impulses: a pair starts from zero or (warm start) from its leader's impulse
+// at the end of the previous step (the follower takes its negative); nodes in
+// no contact start from zero.
+__device__ __forceinline__ void self_pair_setup(const SimDev &S, int i) {
+    const int c = G(S.cand)[i];
+    const int p = (c >= 0 && G(S.cand)[c] == i) ? c : -1;
+    G(S.partner)[i] = p;
+    if (p >= 0) {
+        G(S.mode)[i] = TAKEOFF;
+        if (G(S.caller_id)[i] > G(S.caller_id)[p])            // follower (the leader keeps its own)
+            for (int d = 0; d < 3; ++d) G(S.f)[3 * i + d] = S.warm_start ? -G(S.f)[3 * p + d] : 0.0;
+    } else if (G(S.mode)[i] == FREE) {
+        for (int d = 0; d < 3; ++d) G(S.f)[3 * i + d] = 0.0;
+    }
+}
+
+// Pair frame at x_n: n = (x_L - x_F) / r, gap r - d (L the leader).
+__device__ __forceinline__ void self_frame(const SimDev &S, int L, int F, auto XN, double *n, double &phi,
+                                           double &r) {
+    const double e0 = XN[3 * L] - XN[3 * F], e1 = XN[3 * L + 1] - XN[3 * F + 1], e2 = XN[3 * L + 2] - XN[3 * F + 2];
+    r = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+    n[0] = e0 / r; n[1] = e1 / r; n[2] = e2 / r;
+    phi = r - S.self_d;
+}
+
+// Contact update of a pair, run by its leader L for both nodes: the free
+// velocities ub_L = v_L - f/m_L, ub_F = v_F + f/m_F, the closed-form law on
+// their difference with the reduced mass, then v_L = ub_L + f'/m_L,
+// v_F = ub_F - f'/m_F; both nodes' share of the iteration's change.
+__device__ __forceinline__ void self_pair_update(const SimDev &S, int L, int F, auto B, auto XN, auto Vprev,
+                                                 bool converge, double &dmax) {
+    const double mL = G(S.mass)[L], mF = G(S.mass)[F];
+    double ubL[3], ubF[3], ur[3], fp[3];
+    for (int d = 0; d < 3; ++d) {
+        fp[d] = G(S.f)[3 * L + d];
+        ubL[d] = B[3 * L + d] - fp[d] / mL;
+        ubF[d] = B[3 * F + d] + fp[d] / mF;
+        ur[d] = ubL[d] - ubF[d];
+    }
+    double nrm[3], phi, r, u[3], fn[3];
+    self_frame(S, L, F, XN, nrm, phi, r);
+    const double mred = mL * mF / (mL + mF);
+    const uint8_t md = signorini_coulomb(ur, nrm, phi, S.self_mu, S.h, mred, u, fn);
+    G(S.mode)[L] = md;
+    G(S.mode)[F] = md;
+    for (int d = 0; d < 3; ++d) {
+        const double vL = ubL[d] + fn[d] / mL, vF = ubF[d] - fn[d] / mF;
+        if (converge) {
+            dmax = fmax(dmax, fmax(fabs(fn[d] - fp[d]) / mL, fabs(fn[d] - fp[d]) / mF));
+            dmax = fmax(dmax, fmax(fabs(vL - Vprev[3 * L + d]), fabs(vF - Vprev[3 * F + d])));
+        }
+        B[3 * L + d] = vL;
+        B[3 * F + d] = vF;
+        G(S.f)[3 * L + d] = fn[d];
+        G(S.f)[3 * F + d] = -fn[d];
+        G(S.ubar)[3 * L + d] = ubL[d];
+        G(S.ubar)[3 * F + d] = ubF[d];
+    }
+}
+
 // Contact update of node i after a global solve (its new velocity in B), and
-// the node's share of the iteration's change max(|dv|, |df| / m).
+// the node's share of the iteration's change max(|dv|, |df| / m).  A pair
+// node: its leader updates both nodes (the follower does nothing here).
 template <bool km>
 __device__ __forceinline__ void fwd_contact_node(const SimDev &S, int i, auto B, auto XN, auto Vprev, bool converge,
                                                  double &dmax) {
     const double h = S.h;
+    if (S.self_on) {
+        const int p = G(S.partner)[i];
+        if (p >= 0) {
+            if (G(S.caller_id)[i] < G(S.caller_id)[p]) self_pair_update(S, i, p, B, XN, Vprev, converge, dmax);
+            return;
+        }
+    }
     if (G(S.mode)[i] != FREE) {
         const double mi = G(S.mass)[i];
         const double ub[3] = {B[3 * i] - G(S.f)[3 * i] / mi, B[3 * i + 1] - G(S.f)[3 * i + 1] / mi,
@@ -780,6 +887,7 @@ __device__ __forceinline__ void fwd_record_node(const SimDev &S, int i, int slot
     if (md != FREE) ++cnt[md - 1];
     G(S.rec_mode)[(int64_t)slot * m + i] = md;
     G(S.rec_obst)[(int64_t)slot * m + i] = G(S.cobst)[i];
+    if (S.self_on) G(S.rec_partner)[(int64_t)slot * m + i] = G(S.partner)[i];
 }
 
 // per-step record of step n: PD iterations and mode counts
@@ -835,6 +943,12 @@ __global__ __launch_bounds__(kBlock) void k_forward(const SimDev *__restrict__ s
         for (int i = threadIdx.x; i < m; i += (int)blockDim.x)
             fwd_prologue_node<km, kx>(S, i, fs, t1, n == S.step_begin, xrec, vrec, A, XN);
         __syncthreads();
+        if (S.self_on) {                                 // node-node contacts of this step
+            for (int i = threadIdx.x; i < m; i += (int)blockDim.x) self_nearest(S, i, XN);
+            __syncthreads();
+            for (int i = threadIdx.x; i < m; i += (int)blockDim.x) self_pair_setup(S, i);
+            __syncthreads();
+        }
         int k = 0;
         while (true) {
             if (S.nca_bend > 0) {
@@ -1131,13 +1245,33 @@ __global__ __launch_bounds__(kBlock) void k_forward_mw(const SimDev *__restrict_
 // ------------------------------------------------------------------ adjoint
 
 // z = T^T zeta per node (T = I off contact / take-off, 0 for stick, the slip
-// block otherwise); also keeps zeta - z for the (P - M) term.
-__device__ __forceinline__ void apply_TT(const SimDev &S, auto mode, auto zeta, auto z) {
+// block otherwise); also keeps zeta - z for the (P - M) term.  A pair (L, F) in
+// stick or slip with relative block T_r (in tblk of both nodes) and
+// D = T_r - I enters in the mass-weighted form M T M^{-1}:
+// z_L = zeta_L + (m_LF/m_L) D^T (zeta_L - zeta_F),
+// z_F = zeta_F - (m_LF/m_F) D^T (zeta_L - zeta_F)  (m_LF the reduced mass).
+__device__ __forceinline__ void apply_TT(const SimDev &S, auto mode, auto prt, auto zeta, auto z) {
     for (int i = threadIdx.x; i < S.m; i += (int)blockDim.x) {
         const uint8_t md = mode[i];
         const double a0 = zeta[3 * i], a1 = zeta[3 * i + 1], a2 = zeta[3 * i + 2];
+        const int p = S.self_on ? prt[i] : -1;
         if (md == FREE || md == TAKEOFF) {
             z[3 * i] = a0; z[3 * i + 1] = a1; z[3 * i + 2] = a2;
+        } else if (p >= 0) {
+            const bool lead = G(S.caller_id)[i] < G(S.caller_id)[p];
+            const int L = lead ? i : p, F = lead ? p : i;
+            const double mL = G(S.mass)[L], mF = G(S.mass)[F];
+            const double sa = (lead ? 1.0 : -1.0) * (mL * mF / (mL + mF)) / G(S.mass)[i];
+            const double e[3] = {zeta[3 * L] - zeta[3 * F], zeta[3 * L + 1] - zeta[3 * F + 1],
+                                 zeta[3 * L + 2] - zeta[3 * F + 2]};
+            double De[3];                                    // D^T e
+            if (md == STICK) {
+                De[0] = -e[0]; De[1] = -e[1]; De[2] = -e[2];
+            } else {
+                const auto T = G(S.tblk) + 9 * (int64_t)i;
+                for (int c = 0; c < 3; ++c) De[c] = T[c] * e[0] + T[3 + c] * e[1] + T[6 + c] * e[2] - e[c];
+            }
+            z[3 * i] = a0 + sa * De[0]; z[3 * i + 1] = a1 + sa * De[1]; z[3 * i + 2] = a2 + sa * De[2];
         } else if (md == STICK) {
             z[3 * i] = 0.0; z[3 * i + 1] = 0.0; z[3 * i + 2] = 0.0;
         } else {
@@ -1230,8 +1364,8 @@ __device__ __forceinline__ void adjoint_rhs(const SimDev &S, auto gbar, auto u, 
 // KEEP: also keep H z (adj_hz) and the weight-gradient dot products (adj_dwc)
 // of z = T^T v, which the step's gradients reuse (z and ΔP z stay in zt, wp).
 template <bool MIXED, bool KEEP = false>
-__device__ __forceinline__ void apply_adjoint_operator(const SimDev &S, auto mode, auto vin, auto out) {
-    apply_TT(S, mode, vin, G(S.zt));
+__device__ __forceinline__ void apply_adjoint_operator(const SimDev &S, auto mode, auto prt, auto vin, auto out) {
+    apply_TT(S, mode, prt, vin, G(S.zt));
     __syncthreads();
     projection_jacobian_apply<MIXED>(S, G(S.zt), G(S.wp), KEEP ? 2 : 0, S.h);
     __syncthreads();
@@ -1297,7 +1431,7 @@ __device__ __forceinline__ void block_dots(auto V, int64_t ld, int nk, auto w, i
 // diverges.  Stops when |P^{-1}(gbar - A zeta)| <= tol |P^{-1} gbar|.
 // Returns the number of Krylov iterations, negative if the tolerance was missed.
 template <bool MIXED>
-__device__ __forceinline__ int gmres_solve(const SimDev &S, auto mode, auto gbar, auto zeta, double tol, int max_iters,
+__device__ __forceinline__ int gmres_solve(const SimDev &S, auto mode, auto prt, auto gbar, auto zeta, double tol, int max_iters,
                            double *red, auto T, auto Y, auto U) {
     __shared__ double Hs[(kKryM + 1) * kKryM];
     __shared__ double cs[kKryM], sn[kKryM], gv[kKryM + 1], yk[kKryM + 1];
@@ -1312,7 +1446,7 @@ __device__ __forceinline__ int gmres_solve(const SimDev &S, auto mode, auto gbar
     __syncthreads();
     while (true) {
         // r = P^{-1}(gbar - A zeta)
-        apply_adjoint_operator<MIXED>(S, mode, zeta, G(S.rhs));
+        apply_adjoint_operator<MIXED>(S, mode, prt, zeta, G(S.rhs));
         for (int i = threadIdx.x; i < n3; i += (int)blockDim.x) G(S.rhs)[i] = gbar[i] - G(S.rhs)[i];
         __syncthreads();
         solve_P(S, G(S.rhs), T, Y, V, U);
@@ -1331,7 +1465,7 @@ __device__ __forceinline__ int gmres_solve(const SimDev &S, auto mode, auto gbar
         int jdone = 0;
         for (int j = 0; j < S.kry_m; ++j) {
             auto w = V + (j + 1) * ld;
-            apply_adjoint_operator<MIXED>(S, mode, V + j * ld, G(S.rhs));
+            apply_adjoint_operator<MIXED>(S, mode, prt, V + j * ld, G(S.rhs));
             solve_P(S, G(S.rhs), T, Y, w, U);
             // classical Gram-Schmidt; a second pass only when the first one
             // cancelled most of w (|w| dropped below 0.7 of its norm)
@@ -1998,6 +2132,51 @@ __device__ void adj_prefetch(const SimDev &S, int j, int H) {
     if (sink == 0x9e3779b97f4a7c15ull) G(S.red)[63] = 1.0;
 }
 
+// Slip block T = dv/dubar = (1 - s)(I - n n^T) + s t t^T + mu t n^T of the
+// closed-form law (t the unit free tangential velocity, s = mu(-a)/|u_T|),
+// written row-major to T.
+__device__ __forceinline__ void slip_block(const double *ub, const double *nrm, double phi, double mu, double h,
+                                           GLOBAL double *T) {
+    const double un = nrm[0] * ub[0] + nrm[1] * ub[1] + nrm[2] * ub[2];
+    const double a = un + phi / h;
+    double t[3] = {ub[0] - un * nrm[0], ub[1] - un * nrm[1], ub[2] - un * nrm[2]};
+    const double tau = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+    t[0] /= tau; t[1] /= tau; t[2] /= tau;
+    const double s = mu * (-a) / tau;
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+            T[3 * r + c] = (1 - s) * ((r == c ? 1.0 : 0.0) - nrm[r] * nrm[c]) + s * t[r] * t[c] + mu * t[r] * nrm[c];
+}
+
+// Gradients through the contact frame of an active contact (stick / slip)
+// with multiplier lam (M zeta; a pair: its reduced mass times zeta_L - zeta_F):
+// dphi = lam^T dv/dphi, dn = (dv/dn)^T lam (ubar and the gap held fixed) and
+// lam^T dv/dmu, for v = -(phi/h) n (stick), -(phi/h) n + u_T + mu a t (slip).
+__device__ __forceinline__ void frame_grad(const double *lam, const double *nrm, double phi, const double *ub,
+                                           double mu, bool slip, double h, double &dphi, double *dn,
+                                           double &dmu) {
+    const double nl = nrm[0] * lam[0] + nrm[1] * lam[1] + nrm[2] * lam[2];
+    dmu = 0.0;
+    if (!slip) {
+        dphi = -nl / h;
+        for (int d = 0; d < 3; ++d) dn[d] = -(phi / h) * lam[d];
+        return;
+    }
+    const double un = nrm[0] * ub[0] + nrm[1] * ub[1] + nrm[2] * ub[2];
+    const double a = un + phi / h;
+    double t[3] = {ub[0] - un * nrm[0], ub[1] - un * nrm[1], ub[2] - un * nrm[2]};
+    const double tau = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+    t[0] /= tau; t[1] /= tau; t[2] /= tau;
+    const double tl = t[0] * lam[0] + t[1] * lam[1] + t[2] * lam[2];
+    dphi = (-nl + mu * tl) / h;
+    dmu = a * tl;
+    double El[3];
+    for (int d = 0; d < 3; ++d) El[d] = (lam[d] - t[d] * tl) / tau;
+    const double nE = nrm[0] * El[0] + nrm[1] * El[1] + nrm[2] * El[2];
+    for (int d = 0; d < 3; ++d)
+        dn[d] = -(phi / h) * lam[d] + (-un * lam[d] - ub[d] * nl) + mu * tl * ub[d] + mu * a * (-un * El[d] - ub[d] * nE);
+}
+
 template <bool MIXED, int FL>
 __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict__ sims, int helpers) {
     if (helpers > 0 && blockIdx.x > 0) {                 // single-handle launch: prefetch helpers
@@ -2025,6 +2204,7 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
         const auto x1 = x0 + 3 * m;
         const auto mode = G(S.rec_mode) + (int64_t)slot * m;
         const auto obst = G(S.rec_obst) + (int64_t)slot * m;
+        const auto prt = G(S.rec_partner) + (S.self_on ? (int64_t)slot * m : 0);
         const auto ubr = G(S.rec_ubar) + (int64_t)slot * 3 * m;
         auto gbar = G(S.b0);
         // projections and their Jacobians at x_{n+1}
@@ -2056,6 +2236,20 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
                 gbar[3 * i + d] = G(S.gv)[3 * i + d] + h * G(S.gx)[3 * i + d];
                 G(S.zeta)[3 * i + d] = 0.0;
             }
+            if (S.self_on && prt[i] >= 0) {
+                // a pair in slip: its relative block T_r, the same in both nodes
+                if (mode[i] == SLIP) {
+                    const int p = prt[i];
+                    const bool lead = G(S.caller_id)[i] < G(S.caller_id)[p];
+                    const int L = lead ? i : p, F = lead ? p : i;
+                    double nrm[3], phi, r;
+                    self_frame(S, L, F, x0, nrm, phi, r);
+                    const double ub[3] = {ubr[3 * L] - ubr[3 * F], ubr[3 * L + 1] - ubr[3 * F + 1],
+                                          ubr[3 * L + 2] - ubr[3 * F + 2]};
+                    slip_block(ub, nrm, phi, S.self_mu, h, G(S.tblk) + 9 * (int64_t)i);
+                }
+                continue;
+            }
             bool cached = false;
             if constexpr (km) {
                 // mesh: the frame at x_n (normal, gap, edge direction, region) scanned
@@ -2081,18 +2275,8 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
                     contact_frame<false>(S, obst[i], x0 + 3 * i, nrm, phi);
                 }
                 const auto ub = ubr + 3 * i;
-                const double mu = S.obst[obst[i]].mu;
-                const double un = nrm[0] * ub[0] + nrm[1] * ub[1] + nrm[2] * ub[2];
-                const double a = un + phi / h;
-                double t[3] = {ub[0] - un * nrm[0], ub[1] - un * nrm[1], ub[2] - un * nrm[2]};
-                const double tau = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
-                t[0] /= tau; t[1] /= tau; t[2] /= tau;
-                const double s = mu * (-a) / tau;
-                auto T = G(S.tblk) + 9 * (int64_t)i;
-                for (int r = 0; r < 3; ++r)
-                    for (int c = 0; c < 3; ++c)
-                        T[3 * r + c] = (1 - s) * ((r == c ? 1.0 : 0.0) - nrm[r] * nrm[c]) + s * t[r] * t[c] +
-                                       mu * t[r] * nrm[c];
+                const double ubv[3] = {ub[0], ub[1], ub[2]};
+                slip_block(ubv, nrm, phi, S.obst[obst[i]].mu, h, G(S.tblk) + 9 * (int64_t)i);
             }
         }
         __syncthreads();
@@ -2114,7 +2298,7 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
             int k = 1;
             bool ok = false;
             while (true) {
-                apply_adjoint_operator<MIXED, true>(S, mode, zeta, zeta1);
+                apply_adjoint_operator<MIXED, true>(S, mode, prt, zeta, zeta1);
                 double rmax = 0.0, zmax = 0.0;
                 for (int i = threadIdx.x; i < 3 * m; i += (int)blockDim.x) {
                     zeta1[i] = gbar[i] - zeta1[i];
@@ -2144,7 +2328,7 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
         double dprev = 0.0, d5 = 0.0;
         int rising = 0;
         while (k < S.adj_max_iters) {
-            apply_TT(S, mode, zeta, G(S.zt));
+            apply_TT(S, mode, prt, zeta, G(S.zt));
             __syncthreads();
             projection_jacobian_apply<MIXED>(S, G(S.zt), G(S.wp), 0, h);
             __syncthreads();
@@ -2176,7 +2360,7 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
         iters_total += k;
         if (!ok) {
             if (threadIdx.x == 0) G(S.counters)[2] += 1;
-            const int it = gmres_solve<MIXED>(S, mode, gbar, G(S.zeta), S.adj_tol, S.adj_max_iters, red, T, Y, U);
+            const int it = gmres_solve<MIXED>(S, mode, prt, gbar, G(S.zeta), S.adj_tol, S.adj_max_iters, red, T, Y, U);
             zeta = G(S.zeta);
             if (it < 0) ++noconv;
             gm_total += it < 0 ? -it - 1 : it;
@@ -2190,7 +2374,7 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
             for (int c = threadIdx.x; c < S.nca; c += (int)blockDim.x) G(S.dw)[G(S.c_id)[c]] += h * G(S.adj_dwc)[c];
             inactive_dw(S, G(S.zt), x1, h);
         } else {
-            apply_TT(S, mode, zeta, G(S.zt));
+            apply_TT(S, mode, prt, zeta, G(S.zt));
             __syncthreads();
             projection_jacobian_apply<MIXED>(S, G(S.zt), G(S.wp), 1, h);
             inactive_dw(S, G(S.zt), x1, h);
@@ -2198,6 +2382,7 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
         }
         double dmu_local[kMaxObstacles];
         for (int o = 0; o < kMaxObstacles; ++o) dmu_local[o] = 0.0;
+        double dmu_self = 0.0;
         // external force: dL/df_ext,n = h z_n, so dL/dF += h s_n z_n and dL/ds_n = h F . z_n
         const bool has_force = S.fext != nullptr;
         const double fs = has_force && S.fscale != nullptr ? G(S.fscale)[n] : 1.0;
@@ -2228,7 +2413,27 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
             double dx[3];
             for (int d = 0; d < 3; ++d) dx[d] = G(S.gx)[3 * i + d] - Hz[d] / h;
             const uint8_t md = mode[i];
-            if (md == STICK || md == SLIP) {
+            const int pi_ = S.self_on ? prt[i] : -1;
+            if (pi_ >= 0 && (md == STICK || md == SLIP)) {
+                // pair: multiplier m_LF (zeta_L - zeta_F); phi = |x_L - x_F| - d and
+                // n = (x_L - x_F)/r give dphi/dx_L = n, dn/dx_L = (I - n n^T)/r,
+                // the negatives for x_F
+                const bool lead = G(S.caller_id)[i] < G(S.caller_id)[pi_];
+                const int L = lead ? i : pi_, F = lead ? pi_ : i;
+                const double mL = G(S.mass)[L], mF = G(S.mass)[F], mred = mL * mF / (mL + mF);
+                double nrm[3], phi, r;
+                self_frame(S, L, F, x0, nrm, phi, r);
+                const double lam[3] = {mred * (zeta[3 * L] - zeta[3 * F]), mred * (zeta[3 * L + 1] - zeta[3 * F + 1]),
+                                       mred * (zeta[3 * L + 2] - zeta[3 * F + 2])};
+                const double ub[3] = {ubr[3 * L] - ubr[3 * F], ubr[3 * L + 1] - ubr[3 * F + 1],
+                                      ubr[3 * L + 2] - ubr[3 * F + 2]};
+                double dphi, dn[3], dmt;
+                frame_grad(lam, nrm, phi, ub, S.self_mu, md == SLIP, h, dphi, dn, dmt);
+                if (lead) dmu_self += dmt;
+                const double ndn = nrm[0] * dn[0] + nrm[1] * dn[1] + nrm[2] * dn[2];
+                const double sg = lead ? 1.0 : -1.0;
+                for (int d = 0; d < 3; ++d) dx[d] += sg * (dphi * nrm[d] + (dn[d] - ndn * nrm[d]) / r);
+            } else if (md == STICK || md == SLIP) {
                 const int o = obst[i];
                 double nrm[3], phi;
                 bool cached = false;                         // mesh: the frame scanned for T_j above
@@ -2240,30 +2445,11 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
                     contact_frame<false>(S, o, x0 + 3 * i, nrm, phi);
                 }
                 const double lam[3] = {mi * zeta[3 * i], mi * zeta[3 * i + 1], mi * zeta[3 * i + 2]};
-                const double nl = nrm[0] * lam[0] + nrm[1] * lam[1] + nrm[2] * lam[2];
-                double dphi, dn[3];
-                if (md == STICK) {
-                    dphi = -nl / h;
-                    for (int d = 0; d < 3; ++d) dn[d] = -(phi / h) * lam[d];
-                } else {
-                    const auto ub = ubr + 3 * i;
-                    const double mu = S.obst[o].mu;
-                    const double un = nrm[0] * ub[0] + nrm[1] * ub[1] + nrm[2] * ub[2];
-                    const double a = un + phi / h;
-                    double t[3] = {ub[0] - un * nrm[0], ub[1] - un * nrm[1], ub[2] - un * nrm[2]};
-                    const double tau = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
-                    t[0] /= tau; t[1] /= tau; t[2] /= tau;
-                    const double tl = t[0] * lam[0] + t[1] * lam[1] + t[2] * lam[2];
-                    dphi = (-nl + mu * tl) / h;
-                    dmu_local[o] += a * tl;
-                    // (dv/dn)^T lambda for v = -(phi/h) n + u_T + mu a t
-                    double El[3];
-                    for (int d = 0; d < 3; ++d) El[d] = (lam[d] - t[d] * tl) / tau;
-                    const double nE = nrm[0] * El[0] + nrm[1] * El[1] + nrm[2] * El[2];
-                    for (int d = 0; d < 3; ++d)
-                        dn[d] = -(phi / h) * lam[d] + (-un * lam[d] - ub[d] * nl) + mu * tl * ub[d] +
-                                mu * a * (-un * El[d] - ub[d] * nE);
-                }
+                const auto ub = ubr + 3 * i;
+                const double ubv[3] = {ub[0], ub[1], ub[2]};
+                double dphi, dn[3], dmt;
+                frame_grad(lam, nrm, phi, ubv, S.obst[o].mu, md == SLIP, h, dphi, dn, dmt);
+                dmu_local[o] += dmt;
                 for (int d = 0; d < 3; ++d) dx[d] += dphi * nrm[d];
                 if (S.obst[o].type == 1) {
                     const double e0 = x0[3 * i] - S.obst[o].p[0], e1 = x0[3 * i + 1] - S.obst[o].p[1],
@@ -2303,6 +2489,10 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
         for (int o = 0; o < S.n_obst; ++o) {
             const double v = block_sum(dmu_local[o], red);   // one fixed-order sum per step
             if (threadIdx.x == 0) G(S.dmu)[o] += v;
+        }
+        if (S.self_on) {
+            const double v = block_sum(dmu_self, red);
+            if (threadIdx.x == 0) G(S.dmu)[kMaxObstacles] += v;
         }
         __syncthreads();
     }

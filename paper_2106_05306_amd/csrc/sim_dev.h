@@ -209,7 +209,7 @@ struct SimDev {
     double *adj_pq;                   // [nca*3] p - q at x_{n+1}
     double *tblk;                     // [m*9] T_j blocks (contact nodes)
     double *dw;                       // [nc_total] accumulated weight gradients (canonical)
-    double *dmu;                      // [kMaxObstacles]
+    double *dmu;                      // [kMaxObstacles + 1]: per obstacle, then (last) self-friction
     const double *gx_steps;           // optional per-step dL/dx_n [(T+1)*m*3], new order
     double *cfr;                      // [m*8] mesh obstacles, per node the current step's contact
                                       // frame: n, phi, edge direction, region
@@ -284,6 +284,18 @@ struct SimDev {
     int64_t mw_spin;                  // wall-clock ticks (100 MHz) a barrier waits before giving up
     int mw_absent;                    // failure-handling tests only: the last workgroup returns at
                                       //   once, so every barrier wait ends at its limit
+
+    // node-node self-collision (off when self_on == 0): pairs of mutually
+    // nearest eligible nodes found on the predictor each step; the pair's
+    // leader (lower caller id) runs its contact update for both nodes
+    int self_on;
+    double self_d, self_r2, self_mu;  // thickness, squared detection radius, friction
+    const int32_t *caller_id;         // [m] caller id of each node (pair leader, ties)
+    const int32_t *adj_ptr, *adj_col; // nodes sharing a constraint stencil (never paired)
+    double *ybuf;                     // [m*3] predictor of the current step
+    int32_t *cand;                    // [m] nearest eligible node or -1
+    int32_t *partner;                 // [m] pair partner of the current step or -1
+    int32_t *rec_partner;             // [cap * m] partner per recorded step
 
     // run control for one launch
     int step_begin, step_end;         // forward: steps [begin, end); backward: reverse

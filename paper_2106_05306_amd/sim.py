@@ -50,7 +50,8 @@ def build_structs(X, tris, node_mass, edge_stiffness, *, edges=None, h=1.0 / 120
                   attach_omega=0.0, attach_axis=(0.0, 1.0, 0.0), attach_center=(0.0, 0.0, 0.0),
                   obstacles: Sequence[dict] = (), edge_region=None, bend_region=None, region_scale=None,
                   precision="fp64", adj_tol=1e-10, adj_max_iters=500, checkpoint_every=0, adj_restart=0,
-                  adj_solver="iterative", adj_window=0, warm_start=False):
+                  adj_solver="iterative", adj_window=0, warm_start=False, self_thickness=0.0, self_radius=0.0,
+                  self_mu=0.0):
     """Marshal a mesh and its parameters into the C structs; returns
     (SimMesh, SimParams, keep-alive dict of the numpy arrays they point to)."""
     k = {}
@@ -117,6 +118,9 @@ def build_structs(X, tris, node_mass, edge_stiffness, *, edges=None, h=1.0 / 120
     p.adj_solver = {"iterative": B.SIM_ADJ_ITERATIVE, "direct": B.SIM_ADJ_DIRECT}[adj_solver]
     p.adj_window = adj_window
     p.warm_start = 1 if warm_start else 0
+    p.self_thickness = self_thickness
+    p.self_radius = self_radius
+    p.self_mu = self_mu
     return mesh, p, k
 
 
@@ -130,6 +134,8 @@ def scene_kwargs(scene, **kw):
                 bend_weight=scene.bend_weight, attach=scene.attach, attach_weight=scene.attach_weight,
                 attach_omega=scene.attach_omega, attach_axis=scene.attach_axis, attach_center=scene.attach_center,
                 obstacles=obstacles)
+    if getattr(scene, "self_thickness", 0.0):
+        args.update(self_thickness=scene.self_thickness, self_radius=scene.self_radius, self_mu=scene.self_mu)
     if scene.region_scale is not None:
         args.update(edge_region=scene.edge_region, bend_region=scene.bend_region, region_scale=scene.region_scale)
     args.update(kw)
@@ -266,9 +272,10 @@ class Sim:
                  dregion=torch.zeros(max(self.n_regions, 1), dtype=torch.float64, device=self.device),
                  dmu=torch.zeros(max(self.n_obstacles, 1), dtype=torch.float64, device=self.device),
                  dforce=self._vec(),
-                 dforce_scale=torch.zeros(max(self.T, 1), dtype=torch.float64, device=self.device))
+                 dforce_scale=torch.zeros(max(self.T, 1), dtype=torch.float64, device=self.device),
+                 dmu_self=torch.zeros(1, dtype=torch.float64, device=self.device))
         s = B.SimGrads(*[ctypes.c_void_p(g[k].data_ptr()) for k in ("dx0", "dv0", "dw_edge", "dw_bend", "dregion",
-                                                                     "dmu", "dforce", "dforce_scale")])
+                                                                     "dmu", "dforce", "dforce_scale", "dmu_self")])
         return g, s
 
     def backward(self, dL_dxT: torch.Tensor, dL_dvT: Optional[torch.Tensor] = None,
@@ -333,6 +340,13 @@ class Sim:
     def modes(self, n: int) -> np.ndarray:
         out = np.zeros(self.m, np.uint8)
         B.check(B.lib().sim_modes(self.h, n, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))), "sim_modes")
+        return out
+
+    def self_pairs(self, n: int) -> np.ndarray:
+        """Node-node contact partner of every node at recorded step n (-1: none)."""
+        out = np.zeros(self.m, np.int32)
+        B.check(B.lib().sim_self_pairs(self.h, n, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))),
+                "sim_self_pairs")
         return out
 
     def stats(self) -> dict:
