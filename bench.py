@@ -571,6 +571,126 @@ def bench_serve(args):
     print(json.dumps(result), flush=True)
 
 
+def sphere_self_scene():
+    """The sphere drop with node-node self-collision on (the paper's Sphere
+    example drops a square cloth on a sphere with self-collisions): thickness
+    0.6 grid spacings, detection radius 0.9 spacings, self friction 0.3."""
+    import scenes
+    sc = scenes.c2_sphere_drop(0)
+    a = 1.0 / (int(round(sc.n_nodes ** 0.5)) - 1)
+    sc.self_thickness, sc.self_radius, sc.self_mu = 0.6 * a, 0.9 * a, 0.3
+    return sc
+
+
+def bench_sphere_self(args):
+    """Forward+adjoint cloth steps/s of the 40x40 sphere drop with self-collision
+    (the pair search scans all nodes every step; pairs need the iterative
+    adjoint).  Also times the forward alone with self-collision off on the same
+    single-workgroup kernel, so the pair search and pair updates show as the
+    difference, and redoes sampled steps with the oracle (positions and pairs)."""
+    import os
+
+    import numpy as np
+    import torch
+
+    from oracle import diffcloth_oracle as O
+    from paper_2106_05306_amd.sim import Sim
+
+    dev = torch.device("cuda:0")
+    sc = sphere_self_scene()
+    T = sc.steps
+    kw = dict(device=dev, precision=args.precision, adj_solver="iterative", adj_tol=args.adj_tol,
+              adj_max_iters=args.adj_max_iters, adj_restart=60)
+    sim = Sim.from_scene(sc, **kw)
+    target = torch.tensor(sc.target, device=dev)
+    stream = sim.stream
+
+    def rollout(events=None):
+        if events:
+            events[0].record(stream)
+        xT, _, _ = sim.forward(T)
+        if events:
+            events[1].record(stream)
+        g = (2.0 / sc.n_nodes) * (xT.mean(dim=0) - target).expand_as(xT).contiguous()
+        out = sim.backward(g)
+        if events:
+            events[2].record(stream)
+        return out
+
+    for _ in range(args.warmup):
+        rollout()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for e in evs:
+        out = rollout(e)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    fwd_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    bwd_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    st = sim.stats()
+    pairs = [sim.self_pairs(n) for n in range(T)]
+    pair_steps = int(sum(np.count_nonzero(p >= 0) for p in pairs) // 2)
+    # the forward alone, self-collision off, on the same single-workgroup kernel
+    old = os.environ.get("DIFFCLOTH_FWD_WGS")
+    os.environ["DIFFCLOTH_FWD_WGS"] = "0"
+    sc_off = sphere_self_scene()
+    sc_off.self_thickness = 0.0
+    off = Sim.from_scene(sc_off, **kw)
+    if old is None:
+        del os.environ["DIFFCLOTH_FWD_WGS"]
+    else:
+        os.environ["DIFFCLOTH_FWD_WGS"] = old
+    off.forward(T)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(off.stream)
+    for _ in range(args.steps):
+        off.forward(T)
+    e1.record(off.stream)
+    torch.cuda.synchronize()
+    off_ms = e0.elapsed_time(e1) / args.steps
+    off.close()
+    # oracle: sampled steps redone from the GPU's recorded state
+    model = O.Model(sc)
+    sample = [int(v) for v in np.linspace(T // 2, T - 1, 6)]
+    err, mism, dt = 0.0, 0, 0.0
+    for n in sample:
+        x, v = (t.cpu().numpy() for t in sim.state(n))
+        x1 = sim.state(n + 1)[0].cpu().numpy()
+        t1 = time.perf_counter()
+        rec = O.forward_step(model, x, v, n)
+        dt += time.perf_counter() - t1
+        err = max(err, float(np.abs(rec.x1 - x1).max()))
+        want = np.full(model.m, -1)
+        want[rec.pairs.i] = rec.pairs.j
+        want[rec.pairs.j] = rec.pairs.i
+        mism += int(np.count_nonzero(want != pairs[n]))
+    status = {0: "ok", 1: "fallback", 2: "not converged (SIM_WADJ_NOCONV)", 3: "non-finite (SIM_WADJ_NONFINITE)"}
+    result = {
+        "metric": "forward+adjoint cloth steps/sec at 4800 DoF, self-collision on",
+        "value": args.steps * T / elapsed, "unit": "cloth steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": "sphere_drop 40x40 nodes (4800 DoF) with node-node self-collision (thickness 0.6, "
+                               "detection radius 0.9 grid spacings, self mu 0.3), 200 steps h=1/120, K=20 PD "
+                               "iterations/step, forward + iterative adjoint (one benchmark step = one rollout)",
+                   "precision": args.precision, "adj_tol": args.adj_tol, "adj_max_iters": args.adj_max_iters,
+                   "seed": 0},
+        "timing_ms": {"forward": fwd_ms, "backward": bwd_ms, "forward_self_off_same_kernel": off_ms,
+                      "pair_search_and_updates": fwd_ms - off_ms},
+        "self_collision": {"pair_steps": pair_steps, "pairs_per_step_max": int(max(np.count_nonzero(p >= 0)
+                                                                                    for p in pairs) // 2),
+                           "forward_workgroups": st["fwd_workgroups"]},
+        "gradient": {"status": status.get(out["status"], str(out["status"])),
+                     "adj_unconverged_steps": st["adj_noconv"], "adj_fallback_steps": st["adj_fallbacks"]},
+        "oracle_check": {"steps": sample, "max_one_step_position_error_m": err,
+                         "pair_partner_mismatches": mism, "oracle_forward_s": dt},
+    }
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -588,10 +708,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, help="only run a device copy of this many bytes")
     ap.add_argument("--workload", default="sphere_drop",
-                    choices=["sphere_drop", "batch", "serve", "skirt", "napkin_force"],
+                    choices=["sphere_drop", "batch", "serve", "skirt", "napkin_force", "sphere_self"],
                     help="sphere_drop: the 40x40 rollout (default); batch: 64 uneven rollouts in flight; "
                          "serve: continuous-batching request server; skirt: region-stiffness gradients; "
-                         "napkin_force: gradients w.r.t. per-node external forces")
+                         "napkin_force: gradients w.r.t. per-node external forces; "
+                         "sphere_self: the sphere drop with node-node self-collision")
     ap.add_argument("--obstacle", default="sphere", choices=["sphere", "icosphere2", "icosphere3"],
                     help="sphere_drop: the analytic sphere (default) or a triangulated one (320 / 1280 triangles)")
     ap.add_argument("--batch-count", type=int, default=64)
@@ -621,6 +742,9 @@ def main():
         return
     if args.workload == "napkin_force":
         bench_napkin_force(args)
+        return
+    if args.workload == "sphere_self":
+        bench_sphere_self(args)
         return
 
     import numpy as np

@@ -1151,6 +1151,12 @@ void build_device(sim *s) {
         D.adj_ptr = upload(s, ap);
         D.adj_col = upload(s, ac);
         D.ybuf = zeros<double>(s, v3);
+        int hs = 1;
+        while (hs < 2 * m) hs *= 2;
+        D.self_hmask = hs - 1;
+        D.self_inv_cell = 1.0 / (hm.self_r * (1.0 + 1e-6));
+        D.self_head = zeros<int32_t>(s, hs);
+        D.self_next = zeros<int32_t>(s, m);
         D.cand = zeros<int32_t>(s, m);
         D.partner = zeros<int32_t>(s, m);
     }
@@ -2116,7 +2122,7 @@ int sim_step_stats(const sim_t *cs, int32_t n, int32_t *out) {
 // Scratch layout of the allocation-free forward (byte offsets, 256-aligned).
 struct NoallocLayout {
     size_t desc, ctr, red, x, v, vk, vk1, rhs, b0, f, ubar, cfr, wp, ubuf, rx, rv, rub, mode, cobst, rmode, robst;
-    size_t ybuf, cand, partner, rpartner;       // node-node contact (self-collision on)
+    size_t ybuf, cand, partner, rpartner, shead, snext;   // node-node contact (self-collision on)
     size_t total;
 };
 
@@ -2155,6 +2161,8 @@ NoallocLayout noalloc_layout(const sim *s) {
         L.cand = take(m * sizeof(int32_t));
         L.partner = take(m * sizeof(int32_t));
         L.rpartner = take(m * sizeof(int32_t));
+        L.shead = take((size_t)(s->hd.self_hmask + 1) * sizeof(int32_t));
+        L.snext = take(m * sizeof(int32_t));
     }
     L.total = o;
     return L;
@@ -2199,6 +2207,8 @@ int sim_forward_noalloc(sim_t *s, int32_t n_steps, double *xT_dev, double *vT_de
         d.cand = (int32_t *)(b + L.cand);
         d.partner = (int32_t *)(b + L.partner);
         d.rec_partner = (int32_t *)(b + L.rpartner);
+        d.self_head = (int32_t *)(b + L.shead);
+        d.self_next = (int32_t *)(b + L.snext);
     }
     d.rec_cap = 1;
     d.rec_ring = 1;

@@ -741,27 +741,64 @@ __device__ __forceinline__ bool self_adjacent(const SimDev &S, int i, int j) {
     return false;
 }
 
+// Uniform grid over the predictor with cells no smaller than the detection
+// radius, hashed into a table of linked lists (the spatial hashing of
+// Teschner et al., "Optimized Spatial Hashing for Collision Detection of
+// Deformable Objects", VMV 2003): every node within the radius of y_i lies in
+// one of the 27 cells around y_i's cell.  Bucket lists are built with atomic
+// exchanges, so their order varies from run to run; the search below takes a
+// minimum under a total order, so its result does not.
+__device__ __forceinline__ int self_cell(double y, double inv) {
+    return (int)floor(fmin(fmax(y * inv, -1.0e9), 1.0e9));
+}
+__device__ __forceinline__ int self_bucket(const SimDev &S, int cx, int cy, int cz) {
+    return (int)(((uint32_t)cx * 73856093u ^ (uint32_t)cy * 19349663u ^ (uint32_t)cz * 83492791u) &
+                 (uint32_t)S.self_hmask);
+}
+__device__ __forceinline__ int32_t self_load(GLOBAL int32_t *p) {   // past any stale cached copy
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void self_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// Node i (outside the obstacle contact set) joins the bucket of its cell.
+__device__ __forceinline__ void self_insert(const SimDev &S, int i) {
+    if (G(S.mode)[i] != FREE) return;
+    const double inv = S.self_inv_cell;
+    const int b = self_bucket(S, self_cell(G(S.ybuf)[3 * i], inv), self_cell(G(S.ybuf)[3 * i + 1], inv),
+                              self_cell(G(S.ybuf)[3 * i + 2], inv));
+    G(S.self_next)[i] = __hip_atomic_exchange(G(S.self_head) + b, i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Nearest eligible node of node i on the predictor (Sec. 4.2, Extensions):
 // both nodes outside the obstacle contact set, not sharing a stencil, apart at
 // x_n, |y_i - y_j|^2 <= r^2 (squared distances summed over x, y, z in that
-// order, unfused); ties to the lower caller id.  Brute force over all nodes
-// (every lane of a wavefront reads the same y_j).
+// order, unfused); ties to the lower caller id.  Candidates come from the 27
+// grid cells around y_i (a bucket met twice is scanned twice, harmlessly).
 __device__ __forceinline__ void self_nearest(const SimDev &S, int i, auto XN) {
 #pragma clang fp contract(off)
     int best = -1;
     double bd = 0.0;
     if (G(S.mode)[i] == FREE) {
         const double y0 = G(S.ybuf)[3 * i], y1 = G(S.ybuf)[3 * i + 1], y2 = G(S.ybuf)[3 * i + 2];
-        const int m = S.m;
-        for (int j = 0; j < m; ++j) {
-            const double e0 = y0 - G(S.ybuf)[3 * j], e1 = y1 - G(S.ybuf)[3 * j + 1], e2 = y2 - G(S.ybuf)[3 * j + 2];
-            const double d2 = e0 * e0 + e1 * e1 + e2 * e2;
-            if (!(d2 <= S.self_r2) || j == i || G(S.mode)[j] != FREE) continue;
-            if (best >= 0 && (d2 > bd || (d2 == bd && G(S.caller_id)[j] > G(S.caller_id)[best]))) continue;
-            const double x0 = XN[3 * i] - XN[3 * j], x1 = XN[3 * i + 1] - XN[3 * j + 1], x2 = XN[3 * i + 2] - XN[3 * j + 2];
-            if (!(x0 * x0 + x1 * x1 + x2 * x2 > 0.0) || self_adjacent(S, i, j)) continue;
-            best = j;
-            bd = d2;
+        const double inv = S.self_inv_cell;
+        const int cx = self_cell(y0, inv), cy = self_cell(y1, inv), cz = self_cell(y2, inv);
+        for (int q = 0; q < 27; ++q) {
+            const int b = self_bucket(S, cx + q % 3 - 1, cy + (q / 3) % 3 - 1, cz + q / 9 - 1);
+            for (int j = self_load(G(S.self_head) + b); j >= 0; j = self_load(G(S.self_next) + j)) {
+                const double e0 = y0 - G(S.ybuf)[3 * j], e1 = y1 - G(S.ybuf)[3 * j + 1], e2 = y2 - G(S.ybuf)[3 * j + 2];
+                const double d2 = e0 * e0 + e1 * e1 + e2 * e2;
+                if (!(d2 <= S.self_r2) || j == i) continue;
+                if (best >= 0 && (d2 > bd || (d2 == bd && G(S.caller_id)[j] >= G(S.caller_id)[best]))) continue;
+                const double x0 = XN[3 * i] - XN[3 * j], x1 = XN[3 * i + 1] - XN[3 * j + 1],
+                             x2 = XN[3 * i + 2] - XN[3 * j + 2];
+                if (!(x0 * x0 + x1 * x1 + x2 * x2 > 0.0) || self_adjacent(S, i, j)) continue;
+                best = j;
+                bd = d2;
+            }
         }
     }
     G(S.cand)[i] = best;
@@ -944,6 +981,13 @@ __global__ __launch_bounds__(kBlock) void k_forward(const SimDev *__restrict__ s
             fwd_prologue_node<km, kx>(S, i, fs, t1, n == S.step_begin, xrec, vrec, A, XN);
         __syncthreads();
         if (S.self_on) {                                 // node-node contacts of this step
+            // the grid's table is cleared and filled with atomics at the device's
+            // L2: agent-scope fences around the barriers order plain stores,
+            // atomics and loads of the lists
+            for (int b = threadIdx.x; b <= S.self_hmask; b += (int)blockDim.x) G(S.self_head)[b] = -1;
+            self_sync();
+            for (int i = threadIdx.x; i < m; i += (int)blockDim.x) self_insert(S, i);
+            self_sync();
             for (int i = threadIdx.x; i < m; i += (int)blockDim.x) self_nearest(S, i, XN);
             __syncthreads();
             for (int i = threadIdx.x; i < m; i += (int)blockDim.x) self_pair_setup(S, i);

@@ -293,6 +293,10 @@ struct SimDev {
     const int32_t *caller_id;         // [m] caller id of each node (pair leader, ties)
     const int32_t *adj_ptr, *adj_col; // nodes sharing a constraint stencil (never paired)
     double *ybuf;                     // [m*3] predictor of the current step
+    double self_inv_cell;             // 1 / grid cell size (the detection radius, widened by 1e-6)
+    int self_hmask;                   // hash table size - 1 (a power of two >= 2 m)
+    int32_t *self_head;               // [self_hmask + 1] first node of each hash bucket (-1: empty)
+    int32_t *self_next;               // [m] next node of the same bucket
     int32_t *cand;                    // [m] nearest eligible node or -1
     int32_t *partner;                 // [m] pair partner of the current step or -1
     int32_t *rec_partner;             // [cap * m] partner per recorded step
