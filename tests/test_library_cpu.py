@@ -102,6 +102,13 @@ def test_host_rejects_bad_inputs():
     with pytest.raises(B.SimError) as e:
         S.analyze(**bad_tri)
     assert e.value.code == B.SIM_EINVAL
+    # self-collision: finite non-negative parameters, and only with the iterative adjoint
+    S.analyze(**dict(kw, self_thickness=0.01, self_radius=0.02, self_mu=0.3))
+    for bad in (dict(self_thickness=-0.01), dict(self_thickness=0.01, self_mu=np.nan),
+                dict(self_thickness=0.01, self_radius=-1.0), dict(self_thickness=0.01, adj_solver="direct")):
+        with pytest.raises(B.SimError) as e:
+            S.analyze(**dict(kw, **bad))
+        assert e.value.code == B.SIM_EINVAL, bad
 
 
 def test_host_checks_mesh_obstacles():
