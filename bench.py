@@ -20,6 +20,7 @@ Prints one JSON line.  Extra objects:
                    precision) against the oracle over that sample.
 """
 import argparse
+import collections
 import hashlib
 import json
 import os
@@ -343,7 +344,39 @@ def bench_skirt(args):
                          f"{args.skirt_tol:g} m/s + direct-solve adjoint, each redone from the GPU's recorded "
                          f"state, FP64 NumPy/SciPy, {tc:.1f} s"}
         print(f"skirt: oracle {cpu['value']:.3f} cloth steps/s on one core", file=sys.stderr, flush=True)
-    # finite differences, forward converged
+    # per-step adjoints at full size against the oracle: sampled steps of a
+    # rollout recorded without checkpoints, each adjoint step redone by the
+    # oracle's direct solve from the GPU's recorded state (FP64)
+    from oracle import diffcloth_oracle as O
+    model = O.Model(sc, region_scale=theta0.cpu().numpy())
+    sims = Sim.from_scene(sc, device=dev, precision="fp64", fwd_tol=args.skirt_tol, fwd_max_iters=20000,
+                          adj_tol=1e-12, adj_max_iters=20, adj_solver="direct", region_scale=theta0.cpu().numpy())
+    sims.forward(args.fd_steps)
+    rng = np.random.default_rng(7)
+    step_err = []
+    for n in sorted({0, args.fd_steps // 3, (2 * args.fd_steps) // 3, args.fd_steps - 1}):
+        x0, v0 = (t.cpu().numpy() for t in sims.state(n))
+        x1, v1 = (t.cpu().numpy() for t in sims.state(n + 1))
+        rec = O.forward_step(model, x0, v0, n, tol=args.skirt_tol, max_iters=20000)
+        at_gpu = O.StepRecord(x0, v0, x1, v1, rec.contact, rec.iters)
+        gx, gv = rng.normal(size=(2,) + x0.shape)
+        out = sims.adjoint_step(n, torch.tensor(gx, device=dev), torch.tensor(gv, device=dev))
+        dx, dv, dw, _, _ = O.backward_step(model, at_gpu, gx, gv, n)
+        dreg = np.zeros(4)
+        np.add.at(dreg, model.region, dw * model.base_w)
+        g_reg = np.zeros(4)
+        dwe = out["dw_edge"].cpu().numpy()
+        dwb = out["dw_bend"].cpu().numpy()
+        np.add.at(g_reg, model.region[:model.n_spring], dwe * model.base_w[:model.n_spring])
+        np.add.at(g_reg, model.region[model.n_spring:], dwb[model.bend_centers] * model.base_w[model.n_spring:])
+        rel = lambda a, b: float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+        step_err.append({"step": n, "dx": rel(out["dx0"].cpu().numpy(), dx), "dv": rel(out["dv0"].cpu().numpy(), dv),
+                         "region_rel_err": (np.abs(g_reg - dreg) / np.abs(dreg)).tolist()})
+        print(f"skirt: adjoint step {n} vs oracle {step_err[-1]}", file=sys.stderr, flush=True)
+    sims.close()
+    # finite differences, forward converged; a relative step of 1e-3 keeps the
+    # tolerance noise of the converged forward far below the smallest region's
+    # change (the loss is smooth in the scales: truncation error ~1e-6 relative)
     T = args.fd_steps
     simc = Sim.from_scene(sc, device=dev, precision="fp64", fwd_tol=1e-10, fwd_max_iters=20000,
                           checkpoint_every=5, adj_tol=1e-12, adj_max_iters=20, adj_solver="direct")
@@ -351,7 +384,7 @@ def bench_skirt(args):
     fd = []
     with torch.no_grad():
         for r in range(4):
-            e = 1e-5 * float(theta0[r])
+            e = args.fd_eps * float(theta0[r])
             vals = []
             for sgn in (1.0, -1.0):
                 th = theta0.clone()
@@ -372,7 +405,8 @@ def bench_skirt(args):
         "cpu_baseline": cpu,
         "apex_angle_rad": ang, "gradient": g.cpu().tolist(), "pd_iterations_per_step": pd_iters / 125.0,
         "fixed_K20": fixed_k,
-        "finite_difference_check": {"steps": T, "forward": "converged to 1e-10 m/s", "eps_rel": 1e-5,
+        "adjoint_steps_vs_oracle": step_err,
+        "finite_difference_check": {"steps": T, "forward": "converged to 1e-10 m/s", "eps_rel": args.fd_eps,
                                     "fd": fd.tolist(), "adjoint": ad.tolist(),
                                     "max_err_rel_to_largest": float(np.max(np.abs(fd - ad)) / np.max(np.abs(ad))),
                                     "rel_err_per_region": (np.abs(fd - ad) / np.abs(ad)).tolist()},
@@ -542,28 +576,44 @@ def bench_serve(args):
     srv.run(warm)
     torch.cuda.synchronize()
     zeros = np.zeros(len(spec))
-    phase("one at a time, all requests queued")
-    seq_sat = latency_summary(srv.run_sequential(reqs(zeros)))
-    phase("continuous batching, all requests queued")
-    bat_sat = latency_summary(srv.run(reqs(zeros)))
-    lam = 0.8 * seq_sat["rollouts_per_s"]
-    arr = np.cumsum(np.random.default_rng(1).exponential(1.0 / lam, len(spec)))
-    phase(f"one at a time, Poisson arrivals at {lam:.3f}/s")
-    seq_poi = latency_summary(srv.run_sequential(reqs(arr)))
-    phase(f"continuous batching, Poisson arrivals at {lam:.3f}/s")
-    bat_poi = latency_summary(srv.run(reqs(arr)))
+    wanted = set(args.serve_phases.split(","))
+    out = {}
+
+    def run_phase(key, label, arrivals, sequential):
+        phase(label)
+        res = (srv.run_sequential if sequential else srv.run)(reqs(arrivals))
+        summ = latency_summary(res)
+        summ["gradient_status"] = {str(k): int(v) for k, v in
+                                   sorted(collections.Counter(r.status for r in res).items())}
+        out[key] = summ
+
+    if "seq_sat" in wanted:
+        run_phase("seq_sat", "one at a time, all requests queued", zeros, True)
+    if "bat_sat" in wanted:
+        run_phase("bat_sat", "continuous batching, all requests queued", zeros, False)
+    lam = args.arrival_rate or (0.8 * out["seq_sat"]["rollouts_per_s"] if "seq_sat" in out else 0.0)
+    if ("seq_poisson" in wanted or "bat_poisson" in wanted) and not lam > 0:
+        raise SystemExit("Poisson phases need --arrival-rate or the seq_sat phase")
+    arr = np.cumsum(np.random.default_rng(1).exponential(1.0 / lam, len(spec))) if lam > 0 else zeros
+    if "seq_poisson" in wanted:
+        run_phase("seq_poisson", f"one at a time, Poisson arrivals at {lam:.3f}/s", arr, True)
+    if "bat_poisson" in wanted:
+        run_phase("bat_poisson", f"continuous batching, Poisson arrivals at {lam:.3f}/s", arr, False)
+    head = out.get("bat_sat") or out.get("bat_poisson") or next(iter(out.values()))
     result = {
         "metric": "served rollouts/sec (mixed sizes, forward+gradient), p99 latency",
-        "value": bat_sat["rollouts_per_s"], "unit": "rollouts/s", "n_gpus": 1, "steps": 1, "warmup": 1,
-        "ms_per_step": bat_sat["makespan_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "value": head["rollouts_per_s"], "unit": "rollouts/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": head["makespan_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f64+f32", "data": "synthetic",
         "config": {"workload": f"{len(spec)} requests, grids round(exp(U[ln 20, ln 100])) per side (400-10000 nodes), "
                                f"100-300 steps, sphere or plane, springs 1e3, mu 0.5; continuous batching",
                    "adj_solver": args.adj_solver, "adj_tol": args.adj_tol, "precision": args.precision,
-                   "hbm_budget_gb": args.hbm_budget_gb, "round_ms": args.round_ms},
-        "saturated": {"batched": bat_sat, "sequential": seq_sat,
-                      "speedup": bat_sat["rollouts_per_s"] / seq_sat["rollouts_per_s"]},
-        "poisson": {"arrival_rate_per_s": lam, "batched": bat_poi, "sequential": seq_poi},
+                   "hbm_budget_gb": args.hbm_budget_gb, "round_ms": args.round_ms, "phases": sorted(out)},
+        "saturated": {"batched": out.get("bat_sat"), "sequential": out.get("seq_sat"),
+                      "speedup": (out["bat_sat"]["rollouts_per_s"] / out["seq_sat"]["rollouts_per_s"]
+                                  if "bat_sat" in out and "seq_sat" in out else None)},
+        "poisson": {"arrival_rate_per_s": lam, "batched": out.get("bat_poisson"),
+                    "sequential": out.get("seq_poisson")},
         "server": dict(srv.stats),
         "gradient_nonfinite_requests": srv.stats.get("nonfinite", 0),
     }
@@ -719,7 +769,13 @@ def main():
     ap.add_argument("--batch-window", type=int, default=50, help="adjoint steps per launch in the batch workload")
     ap.add_argument("--no-sequential", action="store_true", help="batch workload: skip the one-at-a-time baseline")
     ap.add_argument("--requests", type=int, default=40, help="requests of the serve workload")
-    ap.add_argument("--fd-steps", type=int, default=10, help="steps of the skirt finite-difference check")
+    ap.add_argument("--serve-phases", default="seq_sat,bat_sat,seq_poisson,bat_poisson",
+                    help="serve workload: phases to run (one at a time / continuous batching, all queued at "
+                         "t = 0 / Poisson arrivals)")
+    ap.add_argument("--arrival-rate", type=float, default=0.0,
+                    help="serve workload: Poisson rate (1/s); 0: 0.8 x the measured one-at-a-time capacity")
+    ap.add_argument("--fd-steps", type=int, default=30, help="steps of the skirt finite-difference check")
+    ap.add_argument("--fd-eps", type=float, default=1e-3, help="relative step of the skirt finite differences")
     ap.add_argument("--skirt-tol", type=float, default=1e-6, help="forward tolerance (m/s) of the skirt rollouts")
     ap.add_argument("--hbm-budget-gb", type=float, default=192.0)
     ap.add_argument("--round-ms", type=float, default=40.0)

@@ -268,6 +268,26 @@ typedef void  (*sim_free_fn)(void *ptr, void *ctx);
 int sim_create(const sim_mesh_t *mesh, const sim_params_t *params, void *hip_stream,
                sim_alloc_fn alloc, sim_free_fn free_fn, void *alloc_ctx, sim_t **out);
 
+/* sim_create in two parts, for callers that prepare handles off their
+ * serving thread:
+ *  sim_plan_create      the host part -- constraint tables, the PD matrix, the
+ *                       ordering and the Cholesky factor (Sec. 3.1) -- with no
+ *                       GPU call; distinct plans may be built on different
+ *                       threads at the same time.  Errors as sim_create's host
+ *                       checks (SIM_EINVAL, SIM_ENONFINITE, SIM_ENOTSPD, SIM_ENOMEM).
+ *  sim_create_from_plan the device part (tables uploaded, kernels configured)
+ *                       on the given stream and allocator, as sim_create; it
+ *                       takes the plan over on success (do not destroy it then)
+ *                       and leaves it usable on failure.  Device set-ups are
+ *                       serialised within a process.
+ *  sim_plan_destroy     releases a plan that was not used (NULL is ignored).
+ * sim_create is sim_plan_create followed by sim_create_from_plan. */
+typedef struct sim_plan sim_plan_t;
+int  sim_plan_create(const sim_mesh_t *mesh, const sim_params_t *params, sim_plan_t **out);
+int  sim_create_from_plan(sim_plan_t *plan, void *hip_stream, sim_alloc_fn alloc, sim_free_fn free_fn,
+                          void *alloc_ctx, sim_t **out);
+void sim_plan_destroy(sim_plan_t *plan);
+
 /* External force besides gravity, part of f_ext in the implicit Euler step
  * (Sec. 3.1): during step n node j receives scale[n] * force[j] newtons, which
  * enters the inertial predictor, the initial guess and the constant part of the

@@ -97,6 +97,9 @@ def lib():
             "sim_state": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
             "sim_modes": (c_int32, [c_void_p, c_int32, POINTER(c_uint8)]),
             "sim_self_pairs": (c_int32, [c_void_p, c_int32, POINTER(c_int32)]),
+            "sim_plan_create": (c_int32, [POINTER(SimMesh), POINTER(SimParams), POINTER(c_void_p)]),
+            "sim_create_from_plan": (c_int32, [c_void_p, c_void_p, ALLOC_FN, FREE_FN, c_void_p, POINTER(c_void_p)]),
+            "sim_plan_destroy": (None, [c_void_p]),
             "sim_stats": (c_int32, [c_void_p, POINTER(SimStats)]),
             "sim_step_stats": (c_int32, [c_void_p, c_int32, c_int32_p]),
             "sim_batch_forward": (c_int32, [POINTER(c_void_p), c_int32, c_int32_p, POINTER(c_void_p),

@@ -6,6 +6,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <exception>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -1345,9 +1346,31 @@ int guarded(F &&f) {
 
 extern "C" {
 
-int sim_create(const sim_mesh_t *mesh, const sim_params_t *params, void *hip_stream, sim_alloc_fn alloc,
-               sim_free_fn free_fn, void *alloc_ctx, sim_t **out) {
+struct sim_plan {
+    HostModel hm;
+};
+
+int sim_plan_create(const sim_mesh_t *mesh, const sim_params_t *params, sim_plan_t **out) {
     if (!out) return SIM_EINVAL;
+    *out = nullptr;
+    sim_plan *pl = new (std::nothrow) sim_plan();
+    if (!pl) return SIM_ENOMEM;
+    // the host build allocates (std::map, std::vector): no exception may leave the ABI
+    int rc = guarded([&] { return pl->hm.build(mesh, params); });
+    if (rc == SIM_OK) rc = guarded([&] { return pl->hm.order_and_factor(leaf_size_default(), merge_cap_default()); });
+    if (rc != SIM_OK) {
+        delete pl;
+        return rc;
+    }
+    *out = pl;
+    return SIM_OK;
+}
+
+void sim_plan_destroy(sim_plan_t *plan) { delete plan; }
+
+int sim_create_from_plan(sim_plan_t *plan, void *hip_stream, sim_alloc_fn alloc, sim_free_fn free_fn,
+                         void *alloc_ctx, sim_t **out) {
+    if (!out || !plan) return SIM_EINVAL;
     *out = nullptr;
     sim *s = new (std::nothrow) sim();
     if (!s) return SIM_ENOMEM;
@@ -1355,29 +1378,44 @@ int sim_create(const sim_mesh_t *mesh, const sim_params_t *params, void *hip_str
     s->alloc = alloc;
     s->free_fn = free_fn;
     s->ctx = alloc_ctx;
-    // the host build allocates (std::map, std::vector): no exception may leave the ABI
-    int rc = guarded([&] { return s->hm.build(mesh, params); });
-    if (rc == SIM_OK) rc = guarded([&] { return s->hm.order_and_factor(leaf_size_default(), merge_cap_default()); });
-    if (rc == SIM_OK) {
-        rc = guarded([&] {
-            build_device(s);
-            int r = push_desc(s);
-            if (r) return r;
-            // device address of the allocation-free forward's scratch, taken once
-            // per device at set-up (a failure surfaces when that entry point is called)
-            void *scratch_addr = nullptr;
-            (void)noalloc_scratch(&scratch_addr);
-            r = sim_set_state(s, nullptr, nullptr);
-            if (r) return r;
-            return hip_err(hipStreamSynchronize(s->stream));
-        });
-    }
+    s->hm = std::move(plan->hm);
+    // the device set-up queries and sets kernel attributes (which loads the
+    // code object on first use) and uploads the tables: one handle at a time
+    // in a process
+    static std::mutex device_setup;
+    std::lock_guard<std::mutex> lock(device_setup);
+    int rc = guarded([&] {
+        build_device(s);
+        int r = push_desc(s);
+        if (r) return r;
+        // device address of the allocation-free forward's scratch, taken once
+        // per device at set-up (a failure surfaces when that entry point is called)
+        void *scratch_addr = nullptr;
+        (void)noalloc_scratch(&scratch_addr);
+        r = sim_set_state(s, nullptr, nullptr);
+        if (r) return r;
+        return hip_err(hipStreamSynchronize(s->stream));
+    });
     if (rc != SIM_OK) {
+        plan->hm = std::move(s->hm);        // the plan stays usable
         sim_destroy(s);
         return rc;
     }
+    delete plan;
     *out = s;
     return SIM_OK;
+}
+
+int sim_create(const sim_mesh_t *mesh, const sim_params_t *params, void *hip_stream, sim_alloc_fn alloc,
+               sim_free_fn free_fn, void *alloc_ctx, sim_t **out) {
+    if (!out) return SIM_EINVAL;
+    *out = nullptr;
+    sim_plan_t *plan = nullptr;
+    int rc = sim_plan_create(mesh, params, &plan);
+    if (rc != SIM_OK) return rc;
+    rc = sim_create_from_plan(plan, hip_stream, alloc, free_fn, alloc_ctx, out);
+    if (rc != SIM_OK) sim_plan_destroy(plan);
+    return rc;
 }
 
 int sim_set_state(sim_t *s, const double *x0_dev, const double *v0_dev) {

@@ -11,6 +11,14 @@ The server
   * caches handles per mesh topology: a handle holds the factorised PD matrix
     of its mesh and material, so a request whose topology is cached skips the
     setup (ordering, factorisation, device tables);
+  * prepares the handle of a request whose topology is not cached on worker
+    threads: the host part (constraint tables, ordering, Cholesky
+    factorisation: ``Plan``) makes no GPU call, so rounds of the requests
+    already admitted keep running meanwhile; the device part (uploads) runs
+    on the serving thread between rounds, so no two threads drive the GPU.
+    The request is admitted at the first round after its plan is ready
+    (requests behind it whose handles are ready go first), while a request
+    waiting for memory holds back the ones behind it;
   * runs rounds: one ``batch_advance`` call advances every admitted request by
     a chunk of steps of its current phase (forward chunks in one persistent
     launch, adjoint chunks in another on a second stream), chunks sized so
@@ -23,6 +31,7 @@ kernels (``sim_forward`` + ``sim_backward``), the plain GPU baseline.
 from __future__ import annotations
 
 import collections
+import concurrent.futures
 import dataclasses
 import time
 from typing import Callable, Dict, List, Optional
@@ -30,7 +39,7 @@ from typing import Callable, Dict, List, Optional
 import numpy as np
 import torch
 
-from .sim import Sim, batch_advance
+from .sim import Plan, Sim, batch_advance
 
 
 @dataclasses.dataclass
@@ -121,7 +130,8 @@ class _Handle:
 
 class Server:
     def __init__(self, device="cuda:0", hbm_budget_bytes: int = 64 << 30, round_ms: float = 40.0,
-                 max_chunk: int = 64, keep_grads: bool = False, on_done: Optional[Callable] = None, **sim_kw):
+                 max_chunk: int = 64, keep_grads: bool = False, on_done: Optional[Callable] = None,
+                 builders: int = 2, **sim_kw):
         self.device = torch.device(device)
         self.budget = int(hbm_budget_bytes)
         self.round_ms = round_ms
@@ -130,8 +140,11 @@ class Server:
         self.on_done = on_done              # called with every finished Result (progress reporting)
         self.sim_kw = dict(sim_kw)
         self.pool: Dict[tuple, List[_Handle]] = collections.defaultdict(list)
+        self.stream = torch.cuda.current_stream(self.device)   # every handle's stream (batched launches)
         self.bstream = torch.cuda.Stream(device=self.device)
         self.stats = collections.Counter()
+        self.builder = concurrent.futures.ThreadPoolExecutor(max_workers=max(1, builders)) if builders else None
+        self.orphans: List[concurrent.futures.Future] = []    # builds whose request took a cached handle
 
     def _chunk(self, m: int, backward: bool, steps: int) -> int:
         """Steps of one round for a rollout of m nodes (about round_ms of work)."""
@@ -154,40 +167,99 @@ class Server:
             self.stats["evicted"] += 1
         return self._used_bytes(busy) + need <= self.budget
 
-    def _acquire(self, req: Request, scene):
-        if self.pool[req.key]:
+    def _build(self, key, scene) -> _Handle:
+        return _Handle(Sim.from_scene(scene, device=self.device, stream=self.stream, **self.sim_kw), key,
+                       _material(scene))
+
+    def _plan(self, key, scene):
+        """Host part of a handle (worker thread: no GPU call)."""
+        return key, Plan.from_scene(scene, **self.sim_kw), _material(scene)
+
+    def _finish(self, planned) -> _Handle:
+        """Device part of a planned handle (serving thread)."""
+        key, plan, material = planned
+        return _Handle(Sim.from_plan(plan, device=self.device, stream=self.stream), key, material)
+
+    def _take_idle(self, key, scene):
+        if self.pool[key]:
             self.stats["cache_hits"] += 1
-            h = self.pool[req.key].pop()
+            h = self.pool[key].pop()
             h.match(scene)
             return h
+        return None
+
+    def _acquire(self, req: Request, scene):
+        h = self._take_idle(req.key, scene)
+        if h is not None:
+            return h
         self.stats["cache_misses"] += 1
-        return _Handle(Sim.from_scene(scene, device=self.device, **self.sim_kw), req.key, _material(scene))
+        return self._build(req.key, scene)
+
+    def _adopt_orphans(self):
+        keep = []
+        for f in self.orphans:
+            if f.done():
+                h = self._finish(f.result())
+                self.pool[h.key].append(h)
+            else:
+                keep.append(f)
+        self.orphans = keep
 
     # ------------------------------------------------------------------ serving
     def run(self, requests: List[Request]) -> List[Result]:
         queue = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        waiting = []                 # arrived, not admitted: [req, scene, handle or None, build future or None]
         active = []                  # [req, scene, handle, phase, bytes, admitted]
         results = []
         t0 = time.perf_counter()
         clock = lambda: time.perf_counter() - t0
-        while queue or active:
+        while queue or waiting or active:
             now = clock()
-            # admission, first come first served
             while queue and queue[0].arrival <= now:
-                req = queue[0]
+                req = queue.popleft()
                 scene = req.make_scene()
-                h = self._acquire(req, scene)
+                h = self._take_idle(req.key, scene)
+                fut = None
+                if h is None:
+                    self.stats["cache_misses"] += 1
+                    if self.builder is None:
+                        h = self._build(req.key, scene)
+                    else:
+                        fut = self.builder.submit(self._plan, req.key, scene)
+                waiting.append([req, scene, h, fut])
+            self._adopt_orphans()
+            # admission in arrival order: a request whose handle is still being
+            # built lets the ones behind it pass; one waiting for memory does not
+            still, blocked = [], False
+            for item in waiting:
+                req, scene, h, fut = item
+                if not blocked and h is None:
+                    h = self._take_idle(req.key, scene)     # a handle freed meanwhile
+                    if h is not None:
+                        if fut is not None:
+                            self.orphans.append(fut)
+                    elif fut is not None and fut.done():
+                        h = self._finish(fut.result())
+                    if h is not None:
+                        item[2], item[3] = h, None
+                if blocked or h is None:
+                    still.append(item)
+                    continue
                 need = h.need_bytes(req.steps, self._chunk(h.sim.m, True, req.steps))
                 busy = [(a[2], a[4]) for a in active]
                 if not self._evict(need, busy) and active:
-                    self.pool[req.key].append(h)          # wait for memory to free up
-                    break
-                queue.popleft()
+                    blocked = True                          # wait for memory to free up
+                    self.pool[req.key].append(h)            # (counted as idle meanwhile)
+                    item[2] = None
+                    still.append(item)
+                    continue
                 _start(h.sim, scene)
                 h.sim.job_forward(req.steps)
                 active.append([req, scene, h, "fwd", need, clock()])
+            waiting = still
             if not active:
-                time.sleep(max(0.0, min(queue[0].arrival - clock(), 0.05)))
+                nxt = queue[0].arrival - clock() if queue else 0.05
+                time.sleep(max(0.0, min(nxt, 0.005 if waiting else 0.05)))
                 continue
             steps = [self._chunk(h.sim.m, phase == "bwd", req.steps) for req, scene, h, phase, _, _ in active]
             left = batch_advance([a[2].sim for a in active], steps, self.bstream)
@@ -214,6 +286,9 @@ class Server:
                     if self.on_done:
                         self.on_done(results[-1])
             active = keep
+        for f in self.orphans:
+            f.result()
+        self._adopt_orphans()
         return results
 
     def run_sequential(self, requests: List[Request]) -> List[Result]:
@@ -243,6 +318,11 @@ class Server:
         return results
 
     def close(self):
+        for f in self.orphans:
+            f.result()
+        self._adopt_orphans()
+        if self.builder is not None:
+            self.builder.shutdown(wait=True)
         for h in self._idle():
             h.sim.close()
         self.pool.clear()

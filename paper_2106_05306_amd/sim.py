@@ -156,15 +156,46 @@ def analyze(leaf_size=32, max_dense=0, **kw):
     return {name: getattr(st, name) for name, _ in B.SimStats._fields_}, perm, L
 
 
+class Plan:
+    """The host part of a handle (``sim_plan_create``: constraint tables, PD
+    matrix, ordering, Cholesky factor) built without any GPU call, so it may
+    run on a worker thread; ``Sim.from_plan`` turns it into a handle."""
+
+    def __init__(self, X, tris, node_mass, edge_stiffness, **kw):
+        self.kw = kw
+        self._mesh, self._params, self._keep = build_structs(X, tris, node_mass, edge_stiffness, **kw)
+        out = ctypes.c_void_p()
+        B.check(B.lib().sim_plan_create(ctypes.byref(self._mesh), ctypes.byref(self._params), ctypes.byref(out)),
+                "sim_plan_create")
+        self.h = out
+
+    @classmethod
+    def from_scene(cls, scene, **kw):
+        a = scene_kwargs(scene, **kw)
+        return cls(a.pop("X"), a.pop("tris"), a.pop("node_mass"), a.pop("edge_stiffness"), **a)
+
+    def close(self):
+        if getattr(self, "h", None):
+            B.lib().sim_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+
 class Sim:
     """A cloth handle: mesh + parameters -> factorised PD system on the GPU."""
 
     def __init__(self, X, tris, node_mass, edge_stiffness, *, device="cuda",
-                 stream: Optional[torch.cuda.Stream] = None, **kw):
+                 stream: Optional[torch.cuda.Stream] = None, plan: Optional[Plan] = None, **kw):
         self.device = torch.device(device)
         self.stream = stream or torch.cuda.current_stream(self.device)
         self._alloc = _TorchAllocator(self.device)
-        mesh, p, self._keep = build_structs(X, tris, node_mass, edge_stiffness, **kw)
+        if plan is not None:
+            kw = plan.kw
+            mesh, p, self._keep = plan._mesh, plan._params, dict(plan._keep)
+        else:
+            mesh, p, self._keep = build_structs(X, tris, node_mass, edge_stiffness, **kw)
         self.m = mesh.n_nodes
         self.n_regions = int(p.n_regions)
         self._gen = 0                       # bumped by every call that replaces the recorded rollout
@@ -176,15 +207,26 @@ class Sim:
         self._mesh, self._params = mesh, p
         h_out = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            B.check(B.lib().sim_create(ctypes.byref(mesh), ctypes.byref(p), ctypes.c_void_p(self.stream.cuda_stream),
-                                       self._alloc.c_alloc, self._alloc.c_free, None, ctypes.byref(h_out)),
-                    "sim_create")
+            if plan is not None:
+                B.check(B.lib().sim_create_from_plan(plan.h, ctypes.c_void_p(self.stream.cuda_stream),
+                                                     self._alloc.c_alloc, self._alloc.c_free, None,
+                                                     ctypes.byref(h_out)), "sim_create_from_plan")
+                plan.h = None                   # taken over by the handle
+            else:
+                B.check(B.lib().sim_create(ctypes.byref(mesh), ctypes.byref(p),
+                                           ctypes.c_void_p(self.stream.cuda_stream), self._alloc.c_alloc,
+                                           self._alloc.c_free, None, ctypes.byref(h_out)), "sim_create")
         self.h = h_out
         st = self.stats()
         self.n_edges = st["n_edges"]
         self.T = -1
 
     # ------------------------------------------------------------------ construction helpers
+    @classmethod
+    def from_plan(cls, plan: Plan, device="cuda", stream: Optional[torch.cuda.Stream] = None):
+        """The handle of a host plan (its device part; the plan is used up)."""
+        return cls(None, None, None, None, device=device, stream=stream, plan=plan)
+
     @classmethod
     def from_scene(cls, scene, **kw):
         """Build from an object carrying the workload fields (see scene_kwargs)."""

@@ -164,3 +164,21 @@ def test_ordering_merges_top_separators():
     P0 = model.P_s.toarray()[perm0][:, perm0]
     assert np.allclose(L0 @ L0.T, P0, rtol=1e-12, atol=1e-14 * np.abs(P0).max())
     assert st["n_levels"] < st0["n_levels"]
+
+
+def test_plans_are_host_only_and_build_on_threads():
+    # the host part of a handle needs no GPU (none here) and distinct plans
+    # build concurrently; errors come back as from sim_create
+    import concurrent.futures
+    from paper_2106_05306_amd import sim as S
+    from paper_2106_05306_amd import _binding as B
+    scs = [scenes.request_scene(n, 10, bool(n % 2), seed=n) for n in (12, 17, 23, 30, 12, 17)]
+    with concurrent.futures.ThreadPoolExecutor(max_workers=4) as ex:
+        plans = list(ex.map(S.Plan.from_scene, scs))
+    assert all(p.h for p in plans)
+    for p in plans:
+        p.close()
+        assert p.h is None
+    with pytest.raises(B.SimError) as e:
+        S.Plan.from_scene(scs[0], bend_weight=-1.0)
+    assert e.value.code == B.SIM_EINVAL
