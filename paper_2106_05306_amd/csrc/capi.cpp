@@ -31,7 +31,7 @@ hipError_t launch_fill(double *p, double v, int64_t n, hipStream_t st);
 hipError_t launch_adj_assemble(const SimDev *d_sims, const int32_t *work, int nblocks, hipStream_t st);
 hipError_t launch_adj_factor_level(const SimDev *d_sims, const int32_t *work, int nblocks, int nmax, hipStream_t st);
 hipError_t noalloc_scratch(void **out);
-hipError_t launch_forward_mw(const SimDev *d, int W, bool mixed, bool mesh, size_t lds, hipStream_t st);
+hipError_t launch_forward_mw(const SimDev *d, int W, bool mixed, bool mesh, size_t lds, int threads, hipStream_t st);
 hipError_t configure_mw_lds(size_t bytes);
 }  // namespace dc
 
@@ -164,6 +164,16 @@ int64_t mw_spin_default() {
     const char *e = std::getenv("DIFFCLOTH_MW_SPIN");
     const long long v = e ? std::atoll(e) : -1;
     return v >= 0 ? (int64_t)v : (int64_t)100000000;       // 1 s
+}
+
+// Threads per workgroup of the multi-workgroup forward (a multiple of 64 up
+// to 1024; DIFFCLOTH_MW_THREADS).  The work of a subtree is split into items
+// and nodes that any thread count covers in the same arithmetic, so the count
+// changes timing only.
+int mw_threads_default() {
+    const char *e = std::getenv("DIFFCLOTH_MW_THREADS");
+    const int v = e ? std::atoi(e) : 0;
+    return v >= 64 && v <= 1024 && v % 64 == 0 ? v : 1024;
 }
 
 // prefetch workgroups of a single-handle direct adjoint launch (0: none)
@@ -1285,7 +1295,9 @@ std::vector<int> overlap_chunks(const sim *s, int n_steps) {
 int launch_single_forward(sim *s) {
     if (s->hd.mw >= 2) {
         int rc = hip_err(launch_fill((double *)s->hd.mw_sync, 0.0, kMwSyncDoubles, s->stream));
-        if (!rc) rc = hip_err(launch_forward_mw(s->dd, s->hd.mw, s->hd.mixed != 0, has_mesh(&s, 1), s->mw_lds, s->stream));
+        if (!rc)
+            rc = hip_err(launch_forward_mw(s->dd, s->hd.mw, s->hd.mixed != 0, has_mesh(&s, 1), s->mw_lds,
+                                           mw_threads_default(), s->stream));
         s->mw_used = true;
         return rc;
     }

@@ -2634,14 +2634,15 @@ hipError_t launch_backward(const SimDev *d_sims, int n, bool mixed, size_t lds, 
 
 // multi-workgroup forward of one handle (d: its descriptor), grid 8 W
 // lds > 0: each workgroup solves its one subtree in that much dynamic LDS
-hipError_t launch_forward_mw(const SimDev *d, int W, bool mixed, bool mesh, size_t lds, hipStream_t st) {
+hipError_t launch_forward_mw(const SimDev *d, int W, bool mixed, bool mesh, size_t lds, int threads, hipStream_t st) {
     if (W < 2 || W > kMwMax) return hipErrorInvalidValue;
+    if (threads < 64 || threads > kBlock || threads % 64 != 0) return hipErrorInvalidValue;
     using F = void (*)(const SimDev *);
     static const F tab[2][2][2] = {{{k_forward_mw<false, false, false>, k_forward_mw<false, false, true>},
                                     {k_forward_mw<false, true, false>, k_forward_mw<false, true, true>}},
                                    {{k_forward_mw<true, false, false>, k_forward_mw<true, false, true>},
                                     {k_forward_mw<true, true, false>, k_forward_mw<true, true, true>}}};
-    hipLaunchKernelGGL(tab[mixed][mesh][lds > 0], dim3(kXcds * W), dim3(kBlock), lds, st, d);
+    hipLaunchKernelGGL(tab[mixed][mesh][lds > 0], dim3(kXcds * W), dim3(threads), lds, st, d);
     return hipGetLastError();
 }
 

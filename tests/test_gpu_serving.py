@@ -93,3 +93,28 @@ def test_forces_travel_with_requests_not_with_cached_handles():
             for key in ("dx0", "dv0", "dw_edge"):
                 assert torch.equal(r.grads[key], solo[key]), (r.rid, key)
     srv.close()
+
+
+def test_planned_handle_equals_a_created_one():
+    # the host plan (built on a worker thread here) plus its device set-up on
+    # this thread gives bitwise the handle sim_create gives
+    import concurrent.futures
+    from paper_2106_05306_amd.serve import centroid_seed
+    from paper_2106_05306_amd.sim import Plan, Sim
+    sc = scenes.request_scene(14, 10, True, seed=3)
+    with concurrent.futures.ThreadPoolExecutor(max_workers=1) as ex:
+        plan = ex.submit(Plan.from_scene, sc, **KW).result()
+    a = Sim.from_plan(plan)
+    assert plan.h is None                               # taken over by the handle
+    a.set_state(None, torch.as_tensor(sc.v0))
+    b = Sim.from_scene(sc, device=DEV, **KW)
+    outs = []
+    for s in (a, b):
+        xT, _, _ = s.forward(sc.steps)
+        outs.append((xT.clone(), s.backward(centroid_seed(sc, xT))))
+    assert torch.equal(outs[0][0], outs[1][0])
+    for key in ("dx0", "dv0", "dw_edge", "dmu"):
+        assert torch.equal(outs[0][1][key], outs[1][1][key]), key
+    assert a.stats()["nnz_L"] == b.stats()["nnz_L"]
+    a.close()
+    b.close()
