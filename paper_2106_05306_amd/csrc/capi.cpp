@@ -730,7 +730,7 @@ void build_device(sim *s) {
         std::vector<int> kids;
         for (int sn = 0; sn < ns; ++sn)
             if (parent[sn] >= 0 && parent[sn] == root) kids.push_back(sn);
-        const int want = D.self_on ? 0 : mw_workgroups_default(m);   // pairs may join any two subtrees
+        const int want = mw_workgroups_default(m);
         int W = std::min<int>({want, (int)kids.size(), kMwMax});
         bool ok = nroot == 1 && L >= 2 && W >= 2 && sns[root] <= kMwRootMax && hm.sup_level[root] == L - 1;
         for (int sn = 0; sn < ns && ok; ++sn)
@@ -825,7 +825,9 @@ void build_device(sim *s) {
                 int dev = 0, maxlds = 0;
                 const bool attr = hipGetDevice(&dev) == hipSuccess &&
                                   hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess;
-                if (one && attr && mw_lds_default() && need + mw_static <= (size_t)maxlds &&
+                // (with node-node contacts a pair's leader updates its follower's row,
+                // which another workgroup's LDS window would hold: vectors in HBM)
+                if (one && attr && mw_lds_default() && !D.self_on && need + mw_static <= (size_t)maxlds &&
                     configure_mw_lds((size_t)maxlds - mw_static) == hipSuccess) {   // the largest any handle may need
                     D.mw_win = upload(s, win);
                     s->mw_lds = std::max<size_t>(need, 8);

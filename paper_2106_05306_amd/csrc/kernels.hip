@@ -1147,8 +1147,7 @@ __global__ __launch_bounds__(kBlock) void k_forward_mw(const SimDev *__restrict_
     const int ulo = LW ? G(S.mw_win)[4 * w + 2] : 0, uhi = LW ? G(S.mw_win)[4 * w + 3] : 0;
     const int nl = hi - lo;
     const Shifted sB{dyn, 3 * lo}, sY{dyn + 3 * nl, 3 * lo}, sU{dyn + 6 * nl, ulo};
-    auto TB = pick<LW>(sB, B);                             // own rows of the solve's vectors
-    auto TY = pick<LW>(sY, Y);
+    auto TY = pick<LW>(sY, Y);                             // own rows of the solve's vectors
     auto TU = pick<LW>(sU, U);
     int64_t iters_total = 0;
     for (int n = S.step_begin; n < S.step_end; ++n) {
@@ -1159,8 +1158,23 @@ __global__ __launch_bounds__(kBlock) void k_forward_mw(const SimDev *__restrict_
         const double fs = S.fext == nullptr ? 0.0 : (S.fscale == nullptr ? 1.0 : G(S.fscale)[n]);
         own([&](int i) { fwd_prologue_node<km, false>(S, i, fs, t1, n == S.step_begin, xrec, vrec, A, XN); });
         if (!mw_barrier(S, gen, ok_lds)) return;
+        if (S.self_on) {            // node-node contacts: the grid, the search and the pairs over all workgroups
+            const int hs = S.self_hmask + 1;
+            for (int b = hs * w / W + (int)threadIdx.x; b < hs * (w + 1) / W; b += (int)blockDim.x)
+                G(S.self_head)[b] = -1;
+            if (!mw_barrier(S, gen, ok_lds)) return;
+            own([&](int i) { self_insert(S, i); });
+            if (!mw_barrier(S, gen, ok_lds)) return;
+            own([&](int i) { self_nearest(S, i, XN); });
+            if (!mw_barrier(S, gen, ok_lds)) return;
+            own([&](int i) { self_pair_setup(S, i); });
+            if (!mw_barrier(S, gen, ok_lds)) return;
+        }
         int k = 0;
         while (true) {
+            // the solve runs in place in B (or its LDS window), which changes
+            // with every swap of the iterates
+            auto TB = pick<LW>(sB, B);
             if (S.nca_bend > 0) {                          // curved bending: constraints split by workgroup
                 const int c0 = S.nca - S.nca_bend, nb = S.nca_bend;
                 local_projection<MIXED>(S, XN, A, c0 + (int)((int64_t)nb * w / W), c0 + (int)((int64_t)nb * (w + 1) / W));
@@ -1233,6 +1247,8 @@ __global__ __launch_bounds__(kBlock) void k_forward_mw(const SimDev *__restrict_
             for (int i = ys0 + (int)threadIdx.x; i < ys1; i += (int)blockDim.x)   // this slice of the root: x from Y
                 for (int d = 0; d < 3; ++d) B[3 * i + d] = Y[3 * i + d];
             __syncthreads();
+            if (S.self_on)              // a pair's leader reads its follower's new velocity, maybe another's
+                if (!mw_barrier(S, gen, ok_lds)) return;
             double dmax = 0.0;
             if constexpr (LW) {
                 for (int i = lo + (int)threadIdx.x; i < hi; i += (int)blockDim.x) {

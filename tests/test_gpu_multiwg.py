@@ -56,6 +56,23 @@ def test_multi_workgroup_forward_is_bitwise(monkeypatch, n, prec, kw):
     assert a[2]["mode_counts"] == b[2]["mode_counts"]
 
 
+@pytest.mark.parametrize("n,threads", [(24, "1024"), (40, "256")])
+def test_multi_workgroup_forward_with_vectors_in_hbm_is_bitwise(monkeypatch, n, threads):
+    # the variant for subtrees whose vectors do not fit LDS (large meshes): the
+    # solve runs in place in the iterate buffer, which swaps every PD iteration;
+    # also fewer threads per workgroup (timing only)
+    sc = scenes.c2_sphere_drop(0, n=n, steps=30)
+    a = _run(sc, monkeypatch, 1, precision="mixed")
+    monkeypatch.setenv("DIFFCLOTH_MW_LDS", "0")
+    monkeypatch.setenv("DIFFCLOTH_MW_THREADS", threads)
+    b = _run(sc, monkeypatch, 16, precision="mixed")
+    assert b[2]["fwd_workgroups"] > 1
+    assert torch.equal(a[0], b[0])
+    for k in KEYS:
+        assert torch.equal(a[1][k], b[1][k]), k
+    assert a[3] == b[3]
+
+
 def test_multi_workgroup_converged_forward_matches_oracle(monkeypatch):
     # tolerance-terminated forward: the stop decision is a maximum over all
     # workgroups' nodes, taken identically by every workgroup

@@ -215,3 +215,22 @@ def test_direct_adjoint_is_refused_with_pairs():
     with pytest.raises(B.SimError) as e:
         _sim(sc, adj_solver="direct")
     assert e.value.code == B.SIM_EINVAL
+
+
+def test_pairs_on_several_workgroups_are_bitwise(monkeypatch):
+    # the multi-workgroup forward with node-node contacts (vectors in HBM: a
+    # pair's leader may update a row another workgroup owns) equals the
+    # one-workgroup forward bitwise
+    sc = scenes.stacked_sheets(n=20, steps=10)
+    res = []
+    for wgs in ("0", "16"):
+        monkeypatch.setenv("DIFFCLOTH_FWD_WGS", wgs)
+        traj, pairs, modes, g, st = _run(sc, statuses=(0, 1, 2), precision="mixed")
+        res.append((traj, pairs, modes, g, st))
+    assert res[0][4]["fwd_workgroups"] == 1 and res[1][4]["fwd_workgroups"] > 1
+    assert np.count_nonzero(res[0][1] >= 0) > 0
+    assert np.array_equal(res[0][0], res[1][0])
+    assert np.array_equal(res[0][1], res[1][1])
+    assert np.array_equal(res[0][2], res[1][2])
+    for k in KEYS:
+        assert np.array_equal(res[0][3][k], res[1][3][k]), k
