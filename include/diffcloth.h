@@ -171,9 +171,9 @@ typedef struct {
  *                  v_i - v_j with the reduced mass m_i m_j / (m_i + m_j) and
  *                  friction self_mu, impulse +f on i and -f on j.  Needs
  *                  SIM_ADJ_ITERATIVE (SIM_EINVAL otherwise: a pair's adjoint
- *                  block lies outside the direct factor's pattern); a rollout
- *                  runs on one workgroup per handle.  The pair search scans all
- *                  nodes (O(n^2) per step).
+ *                  block lies outside the direct factor's pattern).  The pair
+ *                  search hashes the predictors into a uniform grid of cells
+ *                  no smaller than the detection radius (27 cells per node).
  *  (The tolerance rule of fwd_tol measures the change of the velocities and
  *  of the contact impulses in velocity units, |f^{k+1} - f^k| / m_j.) */
 typedef struct {
