@@ -31,7 +31,8 @@ hipError_t launch_fill(double *p, double v, int64_t n, hipStream_t st);
 hipError_t launch_adj_assemble(const SimDev *d_sims, const int32_t *work, int nblocks, hipStream_t st);
 hipError_t launch_adj_factor_level(const SimDev *d_sims, const int32_t *work, int nblocks, int nmax, hipStream_t st);
 hipError_t noalloc_scratch(void **out);
-hipError_t launch_forward_mw(const SimDev *d, int W, bool mixed, bool mesh, size_t lds, int threads, hipStream_t st);
+hipError_t launch_forward_mw(const SimDev *d, int W, bool mixed, bool mesh, bool lw, size_t lds, int threads,
+                             hipStream_t st);
 hipError_t configure_mw_lds(size_t bytes);
 }  // namespace dc
 
@@ -47,7 +48,8 @@ struct sim {
     int64_t bytes = 0;                  // their total (what sim_stats reports)
     SimDev *batch_desc = nullptr;       // descriptors of the batched launches this handle leads
     bool mw_used = false;               // a multi-workgroup forward ran since the last mw_check
-    size_t mw_lds = 0;                  // dynamic LDS of its workgroups (0: vectors in HBM)
+    size_t mw_lds = 0;                  // dynamic LDS of its workgroups
+    bool mw_lw = false;                 // each of them solves its subtree in LDS (else vectors in HBM)
     SimDev hd_noalloc{};                // descriptor of the allocation-free forward (copied to the
                                         //   device scratch on every call; lives as long as the handle)
     int step_info_cap = 0;              // steps the per-step record (hd.step_info) can hold
@@ -141,7 +143,7 @@ int fwd_helpers(sim *const *sims, int n) {
 
 // Workgroups of a single handle's forward launch (the multi-workgroup kernel
 // when the elimination tree allows it): DIFFCLOTH_FWD_WGS, 0 or 1 = one;
-// unset: as many as the root has subtrees (at most 16) from 1 200 nodes on --
+// unset: as many as the root has subtrees (at most 16) from kMwMinNodes on --
 // below that its barriers cost more than the split saves (24 x 24 nodes: 39
 // against 27 us per PD iteration; 40 x 40: 61 against 73; 64 x 64: 136
 // against 340, measured on MI355X).
@@ -149,13 +151,20 @@ int mw_workgroups_default(int m) {
     const char *e = std::getenv("DIFFCLOTH_FWD_WGS");
     const int v = e ? std::atoi(e) : -1;
     if (v >= 0) return std::min(v, kMwMax);
-    return m >= 1200 ? kMwMax : 0;
+    return m >= kMwMinNodes ? kMwMax : 0;
 }
 
 // Whether a multi-workgroup forward solves each workgroup's subtree in LDS
 // (DIFFCLOTH_MW_LDS=0: vectors in HBM).
 bool mw_lds_default() {
     const char *e = std::getenv("DIFFCLOTH_MW_LDS");
+    return !(e && *e == '0');
+}
+
+// Whether each workgroup of a multi-workgroup forward keeps its run of the
+// root's stored inverse in LDS (DIFFCLOTH_MW_ROOT_LDS=0: read from L2).
+bool mw_root_lds_default() {
+    const char *e = std::getenv("DIFFCLOTH_MW_ROOT_LDS");
     return !(e && *e == '0');
 }
 
@@ -712,6 +721,11 @@ void build_device(sim *s) {
         lbp[l + 1] = (int32_t)bitems.size();
         team[2 * l] = pick_team(lip[l + 1] - lip[l], fmax);
         team[2 * l + 1] = pick_team(lbp[l + 1] - lbp[l], bmax);
+        // a large root (the stored inverse) of a mesh the multi-workgroup
+        // forward serves: 16 lanes per row pair, so that each workgroup's run of
+        // a few row pairs is short (the one-workgroup kernel, which must sum in
+        // the same order, pays about 15 % more on this product)
+        if (l == hm.n_levels - 1 && m >= kMwMinNodes && fmax >= 128) team[2 * l] = std::max(team[2 * l], 16);
     }
     // Multi-workgroup forward: with one root supernode (the merged top
     // separators) whose children head subtrees of their own columns, W
@@ -821,17 +835,42 @@ void build_device(sim *s) {
                     win[4 * w + 3] = uhi;
                     need = std::max(need, (size_t)(6 * (hi[k] - lo[k]) + (uhi - ulo)) * sizeof(double));
                 }
+                // the root's forward items (row pairs of its stored inverse) in W
+                // contiguous runs, and where each run's factor entries lie in gval
+                std::vector<int32_t> rootw(4 * (size_t)W, 0);
+                size_t rootc = 0;
+                {
+                    const int i0 = lip[L - 1], nit = lip[L] - lip[L - 1];
+                    for (int w = 0; w < W; ++w) {
+                        const int a = i0 + (int)((int64_t)nit * w / W), b = i0 + (int)((int64_t)nit * (w + 1) / W);
+                        rootw[4 * w] = a;
+                        rootw[4 * w + 1] = b;
+                        if (b > a) {        // an item's pairs follow the previous item's (emit)
+                            const int64_t g0 = fitems[a].g;
+                            const int64_t g1 = (int64_t)fitems[b - 1].g + 2 * (int64_t)fitems[b - 1].kmax;
+                            rootw[4 * w + 2] = (int32_t)g0;
+                            rootw[4 * w + 3] = (int32_t)(g1 - g0);
+                            rootc = std::max(rootc, (size_t)(g1 - g0) * sizeof(double));
+                        }
+                    }
+                }
                 const size_t mw_static = (3 * kMwRootMax + kBlock / 64 + 8) * sizeof(double);
                 int dev = 0, maxlds = 0;
                 const bool attr = hipGetDevice(&dev) == hipSuccess &&
                                   hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess;
                 // (with node-node contacts a pair's leader updates its follower's row,
                 // which another workgroup's LDS window would hold: vectors in HBM)
-                if (one && attr && mw_lds_default() && !D.self_on && need + mw_static <= (size_t)maxlds &&
-                    configure_mw_lds((size_t)maxlds - mw_static) == hipSuccess) {   // the largest any handle may need
-                    D.mw_win = upload(s, win);
-                    s->mw_lds = std::max<size_t>(need, 8);
-                }
+                bool lw = one && attr && mw_lds_default() && !D.self_on && need + mw_static <= (size_t)maxlds;
+                const size_t wbytes = lw ? (need + 15) / 16 * 16 : 0;
+                bool rl = attr && mw_root_lds_default() && rootc > 0 && wbytes + rootc + mw_static <= (size_t)maxlds;
+                if ((lw || rl) && configure_mw_lds((size_t)maxlds - mw_static) != hipSuccess)   // the largest any handle may need
+                    lw = rl = false;
+                if (lw) D.mw_win = upload(s, win);
+                s->mw_lw = lw;
+                s->mw_lds = lw || rl ? std::max<size_t>(wbytes + (rl ? rootc : 0), 8) : 0;
+                D.mw_rootw = upload(s, rootw);
+                D.mw_root_lds = rl ? 1 : 0;
+                D.mw_root_off = (int)(wbytes / sizeof(double));
                 D.mw = W;
                 D.mw_root_c0 = rc0;
                 D.mw_ptr = upload(s, ptr);
@@ -1298,7 +1337,7 @@ int launch_single_forward(sim *s) {
     if (s->hd.mw >= 2) {
         int rc = hip_err(launch_fill((double *)s->hd.mw_sync, 0.0, kMwSyncDoubles, s->stream));
         if (!rc)
-            rc = hip_err(launch_forward_mw(s->dd, s->hd.mw, s->hd.mixed != 0, has_mesh(&s, 1), s->mw_lds,
+            rc = hip_err(launch_forward_mw(s->dd, s->hd.mw, s->hd.mixed != 0, has_mesh(&s, 1), s->mw_lw, s->mw_lds,
                                            mw_threads_default(), s->stream));
         s->mw_used = true;
         return rc;

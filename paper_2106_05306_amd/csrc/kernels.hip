@@ -132,7 +132,7 @@ __device__ __forceinline__ void announce(int64_t *where, int64_t epoch, int64_t 
 // stacked block G_s times the gathered right-hand side), one team of tl lanes
 // per item; cur / cur2 hold the first item's descriptor (fetched early by the
 // caller), the next one is in flight while the current one is computed.
-__device__ __forceinline__ void fwd_products(GLOBAL const v4i *fit, GLOBAL const v2d *gv2, int t0, int t1, int stride,
+__device__ __forceinline__ void fwd_products(GLOBAL const v4i *fit, auto gv2, int t0, int t1, int stride,
                                              int tl, int lane, v4i cur, v4i cur2, auto T, auto Y, auto U) {
     for (int t = t0; t < t1; t += stride) {
         v4i nxt = {0, 0, 0, 0}, nxt2 = {0, 0, 0, 0};  // next descriptor, in flight meanwhile
@@ -1049,6 +1049,36 @@ struct Shifted {
     __device__ Shifted operator+(int k) const { return Shifted{p, off - k}; }
 };
 
+// Pairs of factor entries copied into LDS, indexed like the pairs in gval
+// (pair index minus the copy's first pair), for fwd_products.
+struct LdsPairs {
+    const double *p;
+    int off;
+    __device__ LdsPairs operator+(int k) const { return LdsPairs{p, off - k}; }
+    __device__ v2d operator[](int i) const {
+        const int j = 2 * (i - off);
+        return v2d{p[j], p[j + 1]};
+    }
+};
+
+// Copies n doubles (n even, src 16-byte aligned) from global memory into LDS,
+// the whole workgroup, four 16-byte loads per thread in flight.
+__device__ __forceinline__ void lds_copy(double *dst, GLOBAL const double *src, int n) {
+    const auto s2 = (GLOBAL const v2d *)src;
+    const int np = n >> 1, bd = (int)blockDim.x;
+    for (int j = (int)threadIdx.x; j < np; j += 4 * bd) {
+        v2d v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = j + u * bd < np ? s2[j + u * bd] : v2d{0.0, 0.0};
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (j + u * bd < np) {
+                dst[2 * (j + u * bd)] = v[u].x;
+                dst[2 * (j + u * bd) + 1] = v[u].y;
+            }
+    }
+}
+
 // Barrier of the S.mw workgroups of a multi-workgroup forward launch (placed
 // on one XCD).  An agent-scope release before arriving and an acquire after
 // leaving make every workgroup's global writes visible to the others.  Thread
@@ -1096,8 +1126,10 @@ __device__ __forceinline__ bool mw_barrier(const SimDev &S, uint32_t &gen, int &
 // owns whole subtrees of the elimination tree below the root supernode and a
 // slice of the root's columns (node ranges S.mw_nodes): it does their step
 // prologue, right-hand side, both triangular solves and contact updates; the
-// root's forward product (its stored inverse) is split over all workgroups,
-// each of which first gathers the root's whole right-hand side into LDS.
+// root's forward product (its stored inverse) is split over all workgroups in
+// contiguous runs of row pairs, each of which first gathers the root's whole
+// right-hand side into LDS; its run of the stored inverse is copied into LDS
+// once per launch when it fits (S.mw_root_lds).
 // Barriers per PD iteration: after the subtrees' forward solves, after the
 // root product, after the contact updates (and after the bending projections
 // when there are curved bending constraints).  Every node, row and item is
@@ -1149,6 +1181,13 @@ __global__ __launch_bounds__(kBlock) void k_forward_mw(const SimDev *__restrict_
     const Shifted sB{dyn, 3 * lo}, sY{dyn + 3 * nl, 3 * lo}, sU{dyn + 6 * nl, ulo};
     auto TY = pick<LW>(sY, Y);                             // own rows of the solve's vectors
     auto TU = pick<LW>(sU, U);
+    const int ria = G(S.mw_rootw)[4 * w], rib = G(S.mw_rootw)[4 * w + 1];
+    const int rgb = G(S.mw_rootw)[4 * w + 2], rgc = G(S.mw_rootw)[4 * w + 3];
+    double *rootG = dyn + S.mw_root_off;
+    if (S.mw_root_lds) {                                   // this workgroup's run of the root's inverse
+        lds_copy(rootG, G(S.gval) + rgb, rgc);
+        __syncthreads();
+    }
     int64_t iters_total = 0;
     for (int n = S.step_begin; n < S.step_end; ++n) {
         const int slot = S.rec_ring ? 0 : n - S.rec_step0;
@@ -1212,19 +1251,21 @@ __global__ __launch_bounds__(kBlock) void k_forward_mw(const SimDev *__restrict_
                 }
             }
             if (!mw_barrier(S, gen, ok_lds)) return;       // every subtree's updates of the root rows are in U
-            {   // the root: its right-hand side gathered here, this workgroup's share of its product
+            {   // the root: its right-hand side gathered here, this workgroup's run of its product
                 const int l = L - 1;
                 const int tl = G(S.lvl_team)[2 * l];
                 const int team = threadIdx.x / tl, lane = threadIdx.x % tl, nteams = (int)blockDim.x / tl;
-                const int i0 = G(S.lvl_items_ptr)[l], i1 = G(S.lvl_items_ptr)[l + 1];
                 const auto fit = (GLOBAL const v4i *)S.fitems;
-                const int t0 = i0 + w * nteams + team;
+                const int t0 = ria + team;
                 v4i cur = {0, 0, 0, 0}, cur2 = {0, 0, 0, 0};
-                if (t0 < i1) { cur = fit[2 * t0]; cur2 = fit[2 * t0 + 1]; }
+                if (t0 < rib) { cur = fit[2 * t0]; cur2 = fit[2 * t0 + 1]; }
                 const Shifted T{troot, 3 * rs0};
                 gather_rows(G(S.rows), G(S.upd_off), G(S.lvl_rows_ptr)[l], G(S.lvl_rows_ptr)[l + 1], B, T, U);
                 __syncthreads();
-                fwd_products(fit, gv2, t0, i1, W * nteams, tl, lane, cur, cur2, T, Y, U);
+                if (S.mw_root_lds)
+                    fwd_products(fit, LdsPairs{rootG, rgb >> 1}, t0, rib, nteams, tl, lane, cur, cur2, T, Y, U);
+                else
+                    fwd_products(fit, gv2, t0, rib, nteams, tl, lane, cur, cur2, T, Y, U);
             }
             if (!mw_barrier(S, gen, ok_lds)) return;       // the root's x (in Y) is complete
             // backward solve of this workgroup's subtrees, top level first
@@ -2648,9 +2689,10 @@ hipError_t launch_backward(const SimDev *d_sims, int n, bool mixed, size_t lds, 
     return hipGetLastError();
 }
 
-// multi-workgroup forward of one handle (d: its descriptor), grid 8 W
-// lds > 0: each workgroup solves its one subtree in that much dynamic LDS
-hipError_t launch_forward_mw(const SimDev *d, int W, bool mixed, bool mesh, size_t lds, int threads, hipStream_t st) {
+// multi-workgroup forward of one handle (d: its descriptor), grid 8 W, lds
+// bytes of dynamic LDS; lw: each workgroup solves its one subtree in LDS
+hipError_t launch_forward_mw(const SimDev *d, int W, bool mixed, bool mesh, bool lw, size_t lds, int threads,
+                             hipStream_t st) {
     if (W < 2 || W > kMwMax) return hipErrorInvalidValue;
     if (threads < 64 || threads > kBlock || threads % 64 != 0) return hipErrorInvalidValue;
     using F = void (*)(const SimDev *);
@@ -2658,14 +2700,16 @@ hipError_t launch_forward_mw(const SimDev *d, int W, bool mixed, bool mesh, size
                                     {k_forward_mw<false, true, false>, k_forward_mw<false, true, true>}},
                                    {{k_forward_mw<true, false, false>, k_forward_mw<true, false, true>},
                                     {k_forward_mw<true, true, false>, k_forward_mw<true, true, true>}}};
-    hipLaunchKernelGGL(tab[mixed][mesh][lds > 0], dim3(kXcds * W), dim3(threads), lds, st, d);
+    hipLaunchKernelGGL(tab[mixed][mesh][lw], dim3(kXcds * W), dim3(threads), lds, st, d);
     return hipGetLastError();
 }
 
 hipError_t configure_mw_lds(size_t bytes) {
     hipError_t e = hipSuccess, r;
-    for (const void *f : {(const void *)k_forward_mw<false, false, true>, (const void *)k_forward_mw<false, true, true>,
-                          (const void *)k_forward_mw<true, false, true>, (const void *)k_forward_mw<true, true, true>})
+    for (const void *f : {(const void *)k_forward_mw<false, false, false>, (const void *)k_forward_mw<false, false, true>,
+                          (const void *)k_forward_mw<false, true, false>, (const void *)k_forward_mw<false, true, true>,
+                          (const void *)k_forward_mw<true, false, false>, (const void *)k_forward_mw<true, false, true>,
+                          (const void *)k_forward_mw<true, true, false>, (const void *)k_forward_mw<true, true, true>})
         if ((r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) e = r;
     return e;
 }

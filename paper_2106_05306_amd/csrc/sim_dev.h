@@ -86,6 +86,7 @@ constexpr int kXcds = 8;            // workgroup i of a launch runs on XCD i mod
 // per workgroup; its barrier block: counter, generation, failure flag (16
 // bytes), then one partial maximum and three partial counts per workgroup
 constexpr int kMwMax = 16, kMwRootMax = 512, kMwRanges = 6;
+constexpr int kMwMinNodes = 1200;   // nodes from which a handle runs it by default
 constexpr int kMwSyncDoubles = 2 + 4 * kMwMax;
 constexpr size_t kNoallocScratchBytes = size_t(16) << 20;   // device scratch of the allocation-free forward
 constexpr int kMaxDevices = 64;
@@ -280,6 +281,10 @@ struct SimDev {
     const int32_t *mw_nodes;          // [mw][kMwRanges][2] node ranges [a, b) of each workgroup
     const int32_t *mw_win;            // [mw][4]: one subtree per workgroup, solved in LDS: its columns
                                       //   [lo, hi) and update slots [ulo, uhi) (null: vectors in HBM)
+    const int32_t *mw_rootw;          // [mw][4]: the root's forward items [a, b) of each workgroup and
+                                      //   where their factor entries start in gval and how many (doubles)
+    int mw_root_lds;                  // 1: each workgroup copies its root entries into LDS once per launch
+    int mw_root_off;                  //   (after this many doubles of dynamic LDS: the subtree window)
     uint32_t *mw_sync;                // barrier block (kMwSyncDoubles doubles)
     int64_t mw_spin;                  // wall-clock ticks (100 MHz) a barrier waits before giving up
     int mw_absent;                    // failure-handling tests only: the last workgroup returns at

@@ -3,7 +3,9 @@ one XCD: whole subtrees of the elimination tree per workgroup, the root
 supernode shared) against the single-workgroup kernel and the oracle.
 
 Every node, row and work item is computed with the single-workgroup kernel's
-arithmetic (same items, team sizes and summation orders), so trajectories,
+arithmetic (same items, team sizes and summation orders; which workgroup takes
+which run of the root's row pairs, and whether it reads them from L2 or from
+its LDS copy, changes no sum), so trajectories,
 records and gradients are bitwise equal; the float64 run also matches the
 oracle.  A barrier that waits longer than its limit gives up (a limit of 0
 ticks from the host forces it): the launch returns SIM_ESYNC and the kernel
@@ -56,15 +58,17 @@ def test_multi_workgroup_forward_is_bitwise(monkeypatch, n, prec, kw):
     assert a[2]["mode_counts"] == b[2]["mode_counts"]
 
 
-@pytest.mark.parametrize("n,threads", [(24, "1024"), (40, "256")])
-def test_multi_workgroup_forward_with_vectors_in_hbm_is_bitwise(monkeypatch, n, threads):
+@pytest.mark.parametrize("n,threads,root_lds", [(24, "1024", "1"), (40, "256", "1"), (40, "1024", "0")])
+def test_multi_workgroup_forward_with_vectors_in_hbm_is_bitwise(monkeypatch, n, threads, root_lds):
     # the variant for subtrees whose vectors do not fit LDS (large meshes): the
     # solve runs in place in the iterate buffer, which swaps every PD iteration;
-    # also fewer threads per workgroup (timing only)
+    # also fewer threads per workgroup (timing only), and each workgroup's run
+    # of the root's stored inverse read from L2 instead of its LDS copy
     sc = scenes.c2_sphere_drop(0, n=n, steps=30)
     a = _run(sc, monkeypatch, 1, precision="mixed")
     monkeypatch.setenv("DIFFCLOTH_MW_LDS", "0")
     monkeypatch.setenv("DIFFCLOTH_MW_THREADS", threads)
+    monkeypatch.setenv("DIFFCLOTH_MW_ROOT_LDS", root_lds)
     b = _run(sc, monkeypatch, 16, precision="mixed")
     assert b[2]["fwd_workgroups"] > 1
     assert torch.equal(a[0], b[0])
