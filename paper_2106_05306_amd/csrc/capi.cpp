@@ -651,6 +651,7 @@ void build_device(sim *s) {
         if (snr[sn] == 0)
             for (int c = sc0[sn]; c < sc0[sn] + sns[sn]; ++c) is_root_row[c] = 1;
     std::vector<FwdItem> fitems;
+    std::vector<int> lfmax(hm.n_levels, 1), lbmax(hm.n_levels, 1);   // longest item per level
     auto pick_team = [](int items, int maxlen) {
         int best = 1;
         double best_cost = 1e300;
@@ -719,6 +720,8 @@ void build_device(sim *s) {
         lip[l + 1] = (int32_t)fitems.size();
         lgp[l + 1] = (int32_t)bgat.size();
         lbp[l + 1] = (int32_t)bitems.size();
+        lfmax[l] = fmax;
+        lbmax[l] = bmax;
         team[2 * l] = pick_team(lip[l + 1] - lip[l], fmax);
         team[2 * l + 1] = pick_team(lbp[l + 1] - lbp[l], bmax);
         // a large root (the stored inverse) of a mesh the multi-workgroup
@@ -744,6 +747,17 @@ void build_device(sim *s) {
         std::vector<int> kids;
         for (int sn = 0; sn < ns; ++sn)
             if (parent[sn] >= 0 && parent[sn] == root) kids.push_back(sn);
+        // a mesh the multi-workgroup forward serves by default: lanes per item
+        // of the levels below the root sized for one workgroup's share of a
+        // level's items (whether or not that kernel runs: the one-workgroup
+        // kernel takes the same teams, so both sum in the same order)
+        if (m >= kMwMinNodes && nroot == 1 && kids.size() >= 2) {
+            const int Wt = std::min<int>((int)kids.size(), kMwMax);
+            for (int l = 0; l + 1 < L; ++l) {
+                team[2 * l] = pick_team((lip[l + 1] - lip[l] + Wt - 1) / Wt, lfmax[l]);
+                team[2 * l + 1] = pick_team((lbp[l + 1] - lbp[l] + Wt - 1) / Wt, lbmax[l]);
+            }
+        }
         const int want = mw_workgroups_default(m);
         int W = std::min<int>({want, (int)kids.size(), kMwMax});
         bool ok = nroot == 1 && L >= 2 && W >= 2 && sns[root] <= kMwRootMax && hm.sup_level[root] == L - 1;
