@@ -132,6 +132,8 @@ __device__ __forceinline__ void announce(int64_t *where, int64_t epoch, int64_t 
 // stacked block G_s times the gathered right-hand side), one team of tl lanes
 // per item; cur / cur2 hold the first item's descriptor (fetched early by the
 // caller), the next one is in flight while the current one is computed.
+// Whole batches of a lane's columns run without bounds checks, the last,
+// partial one with them; the columns are taken in the same order either way.
 __device__ __forceinline__ void fwd_products(GLOBAL const v4i *fit, auto gv2, int t0, int t1, int stride,
                                              int tl, int lane, v4i cur, v4i cur2, auto T, auto Y, auto U) {
     for (int t = t0; t < t1; t += stride) {
@@ -141,22 +143,30 @@ __device__ __forceinline__ void fwd_products(GLOBAL const v4i *fit, auto gv2, in
         const auto Tb = T + cur.z;
         const int ld2 = (cur.y & 0xffff) >> 1, kmax = cur.y >> 16;
         double a0 = 0, a1 = 0, a2 = 0, b0 = 0, b1 = 0, b2 = 0;
-        for (int k0 = lane; k0 < kmax; k0 += kSolveBatch * tl) {
+        auto acc = [&](v2d g, int k) {
+            const double t0v = Tb[3 * k], t1v = Tb[3 * k + 1], t2v = Tb[3 * k + 2];
+            a0 += g.x * t0v; a1 += g.x * t1v; a2 += g.x * t2v;
+            b0 += g.y * t0v; b1 += g.y * t1v; b2 += g.y * t2v;
+        };
+        const int step = kSolveBatch * tl;
+        int k0 = lane;
+        for (; k0 + (kSolveBatch - 1) * tl < kmax; k0 += step) {
             v2d g[kSolveBatch];
 #pragma unroll
-            for (int j = 0; j < kSolveBatch; ++j) {           // kSolveBatch independent loads in flight
+            for (int j = 0; j < kSolveBatch; ++j) g[j] = Gb[(k0 + j * tl) * ld2];   // loads in flight together
+#pragma unroll
+            for (int j = 0; j < kSolveBatch; ++j) acc(g[j], k0 + j * tl);
+        }
+        if (k0 < kmax) {
+            v2d g[kSolveBatch];
+#pragma unroll
+            for (int j = 0; j < kSolveBatch; ++j) {
                 const int k = k0 + j * tl;
                 g[j] = k < kmax ? Gb[k * ld2] : v2d{0.0, 0.0};
             }
 #pragma unroll
-            for (int j = 0; j < kSolveBatch; ++j) {
-                const int k = k0 + j * tl;
-                if (k < kmax) {
-                    const double t0v = Tb[3 * k], t1v = Tb[3 * k + 1], t2v = Tb[3 * k + 2];
-                    a0 += g[j].x * t0v; a1 += g[j].x * t1v; a2 += g[j].x * t2v;
-                    b0 += g[j].y * t0v; b1 += g[j].y * t1v; b2 += g[j].y * t2v;
-                }
-            }
+            for (int j = 0; j < kSolveBatch; ++j)
+                if (k0 + j * tl < kmax) acc(g[j], k0 + j * tl);
         }
         a0 = team_sum(a0, tl); a1 = team_sum(a1, tl); a2 = team_sum(a2, tl);
         b0 = team_sum(b0, tl); b1 = team_sum(b1, tl); b2 = team_sum(b2, tl);
@@ -171,7 +181,9 @@ __device__ __forceinline__ void fwd_products(GLOBAL const v4i *fit, auto gv2, in
 
 // Backward-solve products of items t0, t0 + stride, ... < t1 (column pairs of
 // a stacked block: x_s = L_ss^{-T} y_s - (B_s L_ss^{-1})^T x_{R_s}, x_{R_s}
-// gathered into the supernode's update slots first).
+// gathered into the supernode's update slots first).  A lane's rows of the
+// diagonal block come first, then those of B_s; whole batches on either side
+// run without bounds checks, in the same order as the checked batches.
 __device__ __forceinline__ void bwd_products(GLOBAL const v4i *bit, GLOBAL const v2d *gt2, int t0, int t1, int stride,
                                              int tl, int lane, v4i cur, v4i cur2, auto Y, auto x, auto U) {
     for (int t = t0; t < t1; t += stride) {
@@ -183,7 +195,27 @@ __device__ __forceinline__ void bwd_products(GLOBAL const v4i *bit, GLOBAL const
         const auto Yb = Y + yb;
         const int ub = cur.w - 3 * n1;               // U[ub + 3k] is row k >= n1
         double a0 = 0, a1 = 0, a2 = 0, b0 = 0, b1 = 0, b2 = 0;
-        for (int k0 = lane; k0 < n; k0 += kSolveBatch * tl) {
+        auto acc_y = [&](v2d g, int k) {                 // row k < n1: times y_s
+            const double w0 = Yb[3 * k], w1 = Yb[3 * k + 1], w2 = Yb[3 * k + 2];
+            a0 += g.x * w0; a1 += g.x * w1; a2 += g.x * w2;
+            b0 += g.y * w0; b1 += g.y * w1; b2 += g.y * w2;
+        };
+        auto acc_u = [&](v2d g, int k) {                 // row k >= n1: minus times x_{R_s}
+            const int o = ub + 3 * k;
+            const double w0 = U[o], w1 = U[o + 1], w2 = U[o + 2];
+            a0 -= g.x * w0; a1 -= g.x * w1; a2 -= g.x * w2;
+            b0 -= g.y * w0; b1 -= g.y * w1; b2 -= g.y * w2;
+        };
+        const int step = kSolveBatch * tl;
+        int k0 = lane;
+        for (; k0 + (kSolveBatch - 1) * tl < n1; k0 += step) {   // whole batches of y_s rows
+            v2d g[kSolveBatch];
+#pragma unroll
+            for (int j = 0; j < kSolveBatch; ++j) g[j] = Gb[(k0 + j * tl) * st2];
+#pragma unroll
+            for (int j = 0; j < kSolveBatch; ++j) acc_y(g[j], k0 + j * tl);
+        }
+        if (k0 < n) {                                            // the batch reaching past n1 (checked)
             v2d g[kSolveBatch];
 #pragma unroll
             for (int j = 0; j < kSolveBatch; ++j) {
@@ -193,17 +225,28 @@ __device__ __forceinline__ void bwd_products(GLOBAL const v4i *bit, GLOBAL const
 #pragma unroll
             for (int j = 0; j < kSolveBatch; ++j) {
                 const int k = k0 + j * tl;
-                if (k < n1) {
-                    const double w0 = Yb[3 * k], w1 = Yb[3 * k + 1], w2 = Yb[3 * k + 2];
-                    a0 += g[j].x * w0; a1 += g[j].x * w1; a2 += g[j].x * w2;
-                    b0 += g[j].y * w0; b1 += g[j].y * w1; b2 += g[j].y * w2;
-                } else if (k < n) {
-                    const int o = ub + 3 * k;
-                    const double w0 = U[o], w1 = U[o + 1], w2 = U[o + 2];
-                    a0 -= g[j].x * w0; a1 -= g[j].x * w1; a2 -= g[j].x * w2;
-                    b0 -= g[j].y * w0; b1 -= g[j].y * w1; b2 -= g[j].y * w2;
-                }
+                if (k < n1) acc_y(g[j], k);
+                else if (k < n) acc_u(g[j], k);
             }
+            k0 += step;
+        }
+        for (; k0 + (kSolveBatch - 1) * tl < n; k0 += step) {    // whole batches of x_{R_s} rows
+            v2d g[kSolveBatch];
+#pragma unroll
+            for (int j = 0; j < kSolveBatch; ++j) g[j] = Gb[(k0 + j * tl) * st2];
+#pragma unroll
+            for (int j = 0; j < kSolveBatch; ++j) acc_u(g[j], k0 + j * tl);
+        }
+        if (k0 < n) {                                            // the last, partial batch
+            v2d g[kSolveBatch];
+#pragma unroll
+            for (int j = 0; j < kSolveBatch; ++j) {
+                const int k = k0 + j * tl;
+                g[j] = k < n ? Gb[k * st2] : v2d{0.0, 0.0};
+            }
+#pragma unroll
+            for (int j = 0; j < kSolveBatch; ++j)
+                if (k0 + j * tl < n) acc_u(g[j], k0 + j * tl);
         }
         a0 = team_sum(a0, tl); a1 = team_sum(a1, tl); a2 = team_sum(a2, tl);
         b0 = team_sum(b0, tl); b1 = team_sum(b1, tl); b2 = team_sum(b2, tl);
