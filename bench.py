@@ -636,8 +636,10 @@ def bench_sphere_self(args):
     """Forward+adjoint cloth steps/s of the 40x40 sphere drop with self-collision
     (the pair search scans all nodes every step; pairs need the iterative
     adjoint).  Also times the forward alone with self-collision off on the same
-    single-workgroup kernel, so the pair search and pair updates show as the
-    difference, and redoes sampled steps with the oracle (positions and pairs)."""
+    kernel variant (the multi-workgroup forward with its vectors in HBM, as
+    self-collision requires), so the pair search, pair updates and the extra
+    barrier show as the difference, and redoes sampled steps with the oracle
+    (positions and pairs)."""
     import os
 
     import numpy as np
@@ -681,16 +683,16 @@ def bench_sphere_self(args):
     st = sim.stats()
     pairs = [sim.self_pairs(n) for n in range(T)]
     pair_steps = int(sum(np.count_nonzero(p >= 0) for p in pairs) // 2)
-    # the forward alone, self-collision off, on the same single-workgroup kernel
-    old = os.environ.get("DIFFCLOTH_FWD_WGS")
-    os.environ["DIFFCLOTH_FWD_WGS"] = "0"
+    # the forward alone, self-collision off, on the same kernel variant
+    old = os.environ.get("DIFFCLOTH_MW_LDS")
+    os.environ["DIFFCLOTH_MW_LDS"] = "0"                 # the variant self-collision runs
     sc_off = sphere_self_scene()
     sc_off.self_thickness = 0.0
     off = Sim.from_scene(sc_off, **kw)
     if old is None:
-        del os.environ["DIFFCLOTH_FWD_WGS"]
+        del os.environ["DIFFCLOTH_MW_LDS"]
     else:
-        os.environ["DIFFCLOTH_FWD_WGS"] = old
+        os.environ["DIFFCLOTH_MW_LDS"] = old
     off.forward(T)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -700,6 +702,7 @@ def bench_sphere_self(args):
     e1.record(off.stream)
     torch.cuda.synchronize()
     off_ms = e0.elapsed_time(e1) / args.steps
+    off_wgs = off.stats()["fwd_workgroups"]
     off.close()
     # oracle: sampled steps redone from the GPU's recorded state
     model = O.Model(sc)
@@ -729,7 +732,7 @@ def bench_sphere_self(args):
                    "precision": args.precision, "adj_tol": args.adj_tol, "adj_max_iters": args.adj_max_iters,
                    "seed": 0},
         "timing_ms": {"forward": fwd_ms, "backward": bwd_ms, "forward_self_off_same_kernel": off_ms,
-                      "pair_search_and_updates": fwd_ms - off_ms},
+                      "forward_self_off_workgroups": off_wgs, "pair_search_and_updates": fwd_ms - off_ms},
         "self_collision": {"pair_steps": pair_steps, "pairs_per_step_max": int(max(np.count_nonzero(p >= 0)
                                                                                     for p in pairs) // 2),
                            "forward_workgroups": st["fwd_workgroups"]},

@@ -641,7 +641,7 @@ void build_device(sim *s) {
         throw std::runtime_error("factor too large");
     // level work lists (packed) and lanes per item
     std::vector<int32_t> lrp(hm.n_levels + 1, 0), lip(hm.n_levels + 1, 0), lgp(hm.n_levels + 1, 0),
-        lbp(hm.n_levels + 1, 0), team(2 * hm.n_levels, 1);
+        lbp(hm.n_levels + 1, 0), team(2 * hm.n_levels, 1), team_adj(2 * hm.n_levels, 1);
     std::vector<RowItem> ritems;
     std::vector<BwdItem> bitems;
     std::vector<GatherItem> bgat;
@@ -722,8 +722,8 @@ void build_device(sim *s) {
         lbp[l + 1] = (int32_t)bitems.size();
         lfmax[l] = fmax;
         lbmax[l] = bmax;
-        team[2 * l] = pick_team(lip[l + 1] - lip[l], fmax);
-        team[2 * l + 1] = pick_team(lbp[l + 1] - lbp[l], bmax);
+        team_adj[2 * l] = team[2 * l] = pick_team(lip[l + 1] - lip[l], fmax);
+        team_adj[2 * l + 1] = team[2 * l + 1] = pick_team(lbp[l + 1] - lbp[l], bmax);
         // a large root (the stored inverse) of a mesh the multi-workgroup
         // forward serves: 16 lanes per row pair, so that each workgroup's run of
         // a few row pairs is short (the one-workgroup kernel, which must sum in
@@ -901,6 +901,9 @@ void build_device(sim *s) {
     D.lvl_rows_ptr = upload(s, lrp);
     D.lvl_items_ptr = upload(s, lip);
     D.lvl_team = upload(s, team);
+    // the adjoint (one workgroup per handle, no forward to match) keeps the
+    // teams the cost model picks for one workgroup
+    D.lvl_team_adj = upload(s, team_adj);
     D.lvl_gat_ptr = upload(s, lgp);
     D.lvl_bwd_ptr = upload(s, lbp);
     {   // forward-pass prefetch ranges, by solve phase

@@ -273,14 +273,15 @@ __device__ __forceinline__ void bwd_gather(GLOBAL const v2i *bg, int q0, int q1,
 }
 
 // pos0 >= 0: the forward pass announces each level (pos0 + phase, see fwd_pos)
-__device__ __forceinline__ void solve_P(const SimDev &S, auto b, auto T, auto Y, auto x, auto U, int64_t pos0 = -1) {
+__device__ __forceinline__ void solve_P(const SimDev &S, GLOBAL const int32_t *team_of, auto b, auto T, auto Y, auto x, auto U,
+                                        int64_t pos0 = -1) {
     const auto gv2 = (GLOBAL const v2d *)S.gval;        // two rows per load
     const auto gt2 = (GLOBAL const v2d *)S.gvalt;       // two columns per load
     for (int l = 0; l < S.n_levels; ++l) {
         if (pos0 >= 0) announce(S.fwd_pos, S.fwd_epoch, pos0 + l);
         // descriptor of this thread's first product item, fetched before the
         // gather phase and its barrier (it does not depend on the vectors)
-        const int tl = G(S.lvl_team)[2 * l];
+        const int tl = team_of[2 * l];
         const int team = threadIdx.x / tl, lane = threadIdx.x % tl, nteams = (int)blockDim.x / tl;
         const int i0 = G(S.lvl_items_ptr)[l], i1 = G(S.lvl_items_ptr)[l + 1];
         const auto fit = (GLOBAL const v4i *)S.fitems;  // FwdItem as 2 x 16 bytes
@@ -297,7 +298,7 @@ __device__ __forceinline__ void solve_P(const SimDev &S, auto b, auto T, auto Y,
     // of G_s (row-major copy: the items of a wavefront read consecutive addresses)
     for (int l = S.n_levels - 1; l >= 0; --l) {
         if (pos0 >= 0) announce(S.fwd_pos, S.fwd_epoch, pos0 + 2 * S.n_levels - 1 - l);
-        const int tl = G(S.lvl_team)[2 * l + 1];
+        const int tl = team_of[2 * l + 1];
         const int team = threadIdx.x / tl, lane = threadIdx.x % tl, nteams = (int)blockDim.x / tl;
         const int c0 = G(S.lvl_bwd_ptr)[l], c1 = G(S.lvl_bwd_ptr)[l + 1];
         const auto bit = (GLOBAL const v4i *)S.bitems;  // BwdItem as 2 x 16 bytes
@@ -1046,7 +1047,7 @@ __global__ __launch_bounds__(kBlock) void k_forward(const SimDev *__restrict__ s
             if (converge)
                 for (int i = threadIdx.x; i < 3 * m; i += (int)blockDim.x) Vprev[i] = A[i];
             __syncthreads();
-            solve_P(S, B, B, A, B, U, it_run * 2 * S.n_levels);
+            solve_P(S, G(S.lvl_team), B, B, A, B, U, it_run * 2 * S.n_levels);
             ++it_run;
             double dmax = 0.0;
             for (int i = threadIdx.x; i < m; i += (int)blockDim.x) fwd_contact_node<km>(S, i, B, XN, Vprev, converge, dmax);
@@ -1593,7 +1594,7 @@ __device__ __forceinline__ int gmres_solve(const SimDev &S, auto mode, auto prt,
         apply_adjoint_operator<MIXED>(S, mode, prt, zeta, G(S.rhs));
         for (int i = threadIdx.x; i < n3; i += (int)blockDim.x) G(S.rhs)[i] = gbar[i] - G(S.rhs)[i];
         __syncthreads();
-        solve_P(S, G(S.rhs), T, Y, V, U);
+        solve_P(S, G(S.lvl_team_adj), G(S.rhs), T, Y, V, U);
         double ss = 0.0;
         for (int i = threadIdx.x; i < n3; i += (int)blockDim.x) ss += V[i] * V[i];
         const double beta = sqrt(block_sum(ss, red));
@@ -1610,7 +1611,7 @@ __device__ __forceinline__ int gmres_solve(const SimDev &S, auto mode, auto prt,
         for (int j = 0; j < S.kry_m; ++j) {
             auto w = V + (j + 1) * ld;
             apply_adjoint_operator<MIXED>(S, mode, prt, V + j * ld, G(S.rhs));
-            solve_P(S, G(S.rhs), T, Y, w, U);
+            solve_P(S, G(S.lvl_team_adj), G(S.rhs), T, Y, w, U);
             // classical Gram-Schmidt; a second pass only when the first one
             // cancelled most of w (|w| dropped below 0.7 of its norm)
             double ws = 0.0;
@@ -2478,7 +2479,7 @@ __global__ __launch_bounds__(kBlockAdj) void k_backward(const SimDev *__restrict
             __syncthreads();
             adjoint_rhs<MIXED>(S, gbar, G(S.wp), zeta, G(S.zt), T);
             __syncthreads();
-            solve_P(S, T, T, Y, zeta1, U);
+            solve_P(S, G(S.lvl_team_adj), T, T, Y, zeta1, U);
             double dmax = 0.0, zmax = 0.0;
             for (int i = threadIdx.x; i < 3 * m; i += (int)blockDim.x) {
                 dmax = fmax(dmax, fabs(zeta1[i] - zeta[i]));

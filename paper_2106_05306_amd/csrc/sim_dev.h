@@ -162,6 +162,7 @@ struct SimDev {
     const int32_t *root_rows;         //   writes x_s into Y, copied to x at the end (3 i each)
     const int32_t *lvl_items_ptr;     // [n_levels+1] into fwd items
     const int32_t *lvl_team;          // [2*n_levels] lanes per item: forward, backward
+    const int32_t *lvl_team_adj;      // the same for the adjoint's solves with P (one workgroup's choice)
     const RowItem *rows;
     const FwdItem *fitems;
     const BwdItem *bitems;
