@@ -615,7 +615,8 @@ def bench_serve(args):
         "poisson": {"arrival_rate_per_s": lam, "batched": out.get("bat_poisson"),
                     "sequential": out.get("seq_poisson")},
         "server": dict(srv.stats),
-        "gradient_nonfinite_requests": srv.stats.get("nonfinite", 0),
+        # per phase, from each request's own gradient status (3 = SIM_WADJ_NONFINITE)
+        "gradient_nonfinite_requests": {k: v["gradient_status"].get("3", 0) for k, v in out.items()},
     }
     srv.close()
     print(json.dumps(result), flush=True)
