@@ -110,12 +110,15 @@ namespace {
 
 int hip_err(hipError_t e) { return e == hipSuccess ? SIM_OK : SIM_EHIP; }
 
-// Nested-dissection leaf size (nodes per leaf supernode).  DIFFCLOTH_LEAF
+// Nested-dissection leaf size (nodes per leaf supernode) of a mesh of m
+// nodes: 128 where the multi-workgroup forward runs by default (its solves
+// pay per level: at 40 x 40, leaves of 32 / 64 / 128 nodes give 5 / 4 / 3
+// levels and 641 / 684 / 744 cloth steps/s), else 32.  DIFFCLOTH_LEAF
 // overrides it for experiments.
-int leaf_size_default() {
+int leaf_size_default(int m) {
     const char *e = std::getenv("DIFFCLOTH_LEAF");
     const int v = e ? std::atoi(e) : 0;
-    return v >= 4 && v <= 256 ? v : 32;
+    return v >= 4 && v <= 256 ? v : (m >= kMwMinNodes ? 128 : 32);
 }
 
 // Largest merged top supernode of P (nodes); DIFFCLOTH_MERGE overrides it for
@@ -1427,7 +1430,7 @@ int sim_plan_create(const sim_mesh_t *mesh, const sim_params_t *params, sim_plan
     if (!pl) return SIM_ENOMEM;
     // the host build allocates (std::map, std::vector): no exception may leave the ABI
     int rc = guarded([&] { return pl->hm.build(mesh, params); });
-    if (rc == SIM_OK) rc = guarded([&] { return pl->hm.order_and_factor(leaf_size_default(), merge_cap_default()); });
+    if (rc == SIM_OK) rc = guarded([&] { return pl->hm.order_and_factor(leaf_size_default(mesh->n_nodes), merge_cap_default()); });
     if (rc != SIM_OK) {
         delete pl;
         return rc;

@@ -84,7 +84,8 @@ def test_headline_mixed_40x40_every_step_from_gpu_state():
     # the benchmark's solver settings (its refinement stops at a backward error of 1e-4)
     sim = Sim.from_scene(sc, device=DEV, precision="mixed", adj_solver="direct", adj_tol=1e-4, adj_max_iters=10)
     st = sim.stats()
-    assert (st["lds_flags_fwd"], st["lds_flags_bwd"]) == (3, 1)    # the benchmark's instantiation
+    # the benchmark's instantiation: the multi-workgroup forward, the adjoint's LDS placement
+    assert st["fwd_workgroups"] > 1 and st["lds_flags_bwd"] == 1
     sim.forward(sc.steps)
     xs, vs = zip(*[sim.state(n) for n in range(sc.steps + 1)])
     xs = [x.cpu().numpy() for x in xs]
